@@ -1,0 +1,838 @@
+/*
+ * gp_oracle.c -- plain, slow, obviously-correct CPU oracle for stack-based
+ * genetic-programming evaluation ("Accelerating Genetic Programming using
+ * GPUs", arXiv 2110.11226).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes
+ * or calls this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark load it.  It shares no header, helper, table or
+ * generator with the GPU library: every constant below is written out here
+ * from the paper (or from the reading of it that the design notes record).
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC
+ * (no FTZ/DAZ, no contraction: every float operation is a single IEEE op).
+ *
+ * What it computes (each function cites the passage it follows):
+ *   - program value of a prefix list on one row, by the right-to-left stack
+ *     scan of Sec. III-A, in float32 and in float64;
+ *   - per-program fitness under the weighted metrics of Sec. III-C3
+ *     (MAE, MSE, RMSE, logistic loss, Pearson);
+ *   - tournament selection with the parsimony penalty, Sec. III-C1,
+ *     Eqs. (parsimony) and (fitness);
+ *   - Philox4x32-10 (the counter-based generator cited in Sec. III-B);
+ *   - the Full / Grow / ramped-half-and-half initialisations of Sec. II-A and
+ *     an exact-length generator (not in the paper);
+ *   - float64 reverse-mode derivatives of fitness with respect to program
+ *     constants (not in the paper).
+ *
+ * Parity status: every function here is pinned by tests/test_oracle_*.py
+ * against closed forms, hand-evaluated programs, brute force or an
+ * independent library routine, except where a comment says "parity unpinned".
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- node encoding (reading: op in bits 0-7, argument in bits 8-31) ---- */
+enum {
+    O_VAR = 0, O_CONST = 1,
+    O_ADD = 2, O_SUB = 3, O_MUL = 4, O_DIV = 5,
+    O_NEG = 6, O_LOG = 7, O_SQRT = 8, O_SIN = 9, O_COS = 10, O_TAN = 11,
+    O_NUM = 12
+};
+#define ORC_STACK 20          /* fixed evaluation stack, Sec. III-B */
+
+static int op_arity(int op)
+{
+    switch (op) {
+    case O_VAR: case O_CONST: return 0;
+    case O_ADD: case O_SUB: case O_MUL: case O_DIV: return 2;
+    case O_NEG: case O_LOG: case O_SQRT: case O_SIN: case O_COS: case O_TAN: return 1;
+    default: return -1;
+    }
+}
+
+/* ---- protected operators (reading: the gplearn convention) ---- */
+static const float ORC_EPS = 0.001f;      /* float nearest 0.001 */
+
+static float pdiv_f(float a, float b) { return fabsf(b) > ORC_EPS ? a / b : 1.0f; }
+static float plog_f(float a) { return fabsf(a) > ORC_EPS ? logf(fabsf(a)) : 0.0f; }
+static float psqrt_f(float a) { return sqrtf(fabsf(a)); }
+
+static double pdiv_d(double a, double b) { return fabs(b) > (double)ORC_EPS ? a / b : 1.0; }
+static double plog_d(double a) { return fabs(a) > (double)ORC_EPS ? log(fabs(a)) : 0.0; }
+static double psqrt_d(double a) { return sqrt(fabs(a)); }
+
+/* ------------------------------------------------------------------------ */
+/* Validation: right-to-left stack-height scan (Sec. III-A: the list is read  */
+/* in reverse; Sec. III-C2: a stack of size m bounds what can be evaluated).  */
+/* Returns 0 if valid; 1 bad opcode; 2 stack underflow / not exactly one      */
+/* result; 3 stack height above ORC_STACK; 4 feature index out of range;      */
+/* 5 constant slot out of range; 6 empty program.                             */
+/* ------------------------------------------------------------------------ */
+int orc_check_program(const uint32_t *nodes, int64_t len, int32_t n_features,
+                      int64_t n_consts, int32_t *max_height)
+{
+    int64_t h = 0, hmax = 0;
+    if (len <= 0) return 6;
+    for (int64_t i = len - 1; i >= 0; --i) {
+        int op = (int)(nodes[i] & 0xffu);
+        uint32_t arg = nodes[i] >> 8;
+        int a = op_arity(op);
+        if (a < 0) return 1;
+        if (op == O_VAR && (int64_t)arg >= n_features) return 4;
+        if (op == O_CONST && (int64_t)arg >= n_consts) return 5;
+        if (h < a) return 2;
+        h = h - a + 1;
+        if (h > hmax) hmax = h;
+        if (h > ORC_STACK) return 3;
+    }
+    if (h != 1) return 2;
+    if (max_height) *max_height = (int32_t)hmax;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Evaluation of one program on one row (Sec. III-A, III-C3 execution step):  */
+/* scan the prefix list from its last node to its first; a terminal pushes   */
+/* its value; a function pops its operands -- the first pop is its first      */
+/* argument, because in prefix order the first child is written first and so */
+/* is evaluated last -- and pushes its result.  The one value left is the     */
+/* program's output.                                                          */
+/* ------------------------------------------------------------------------ */
+static float eval_row_f32(const uint32_t *nodes, int64_t len, const float *c,
+                          const float *X, int64_t ld, int64_t row)
+{
+    float st[ORC_STACK];
+    int h = 0;
+    for (int64_t i = len - 1; i >= 0; --i) {
+        int op = (int)(nodes[i] & 0xffu);
+        uint32_t arg = nodes[i] >> 8;
+        float a, b;
+        switch (op) {
+        case O_VAR:   st[h++] = X[(int64_t)arg * ld + row]; break;
+        case O_CONST: st[h++] = c[arg]; break;
+        case O_ADD: a = st[--h]; b = st[--h]; st[h++] = a + b; break;
+        case O_SUB: a = st[--h]; b = st[--h]; st[h++] = a - b; break;
+        case O_MUL: a = st[--h]; b = st[--h]; st[h++] = a * b; break;
+        case O_DIV: a = st[--h]; b = st[--h]; st[h++] = pdiv_f(a, b); break;
+        case O_NEG:  a = st[--h]; st[h++] = -a; break;
+        case O_LOG:  a = st[--h]; st[h++] = plog_f(a); break;
+        case O_SQRT: a = st[--h]; st[h++] = psqrt_f(a); break;
+        case O_SIN:  a = st[--h]; st[h++] = sinf(a); break;
+        case O_COS:  a = st[--h]; st[h++] = cosf(a); break;
+        case O_TAN:  a = st[--h]; st[h++] = tanf(a); break;
+        default: return NAN;
+        }
+    }
+    return st[0];
+}
+
+static double eval_row_f64(const uint32_t *nodes, int64_t len, const float *c,
+                           const float *X, int64_t ld, int64_t row)
+{
+    double st[ORC_STACK];
+    int h = 0;
+    for (int64_t i = len - 1; i >= 0; --i) {
+        int op = (int)(nodes[i] & 0xffu);
+        uint32_t arg = nodes[i] >> 8;
+        double a, b;
+        switch (op) {
+        case O_VAR:   st[h++] = (double)X[(int64_t)arg * ld + row]; break;
+        case O_CONST: st[h++] = (double)c[arg]; break;
+        case O_ADD: a = st[--h]; b = st[--h]; st[h++] = a + b; break;
+        case O_SUB: a = st[--h]; b = st[--h]; st[h++] = a - b; break;
+        case O_MUL: a = st[--h]; b = st[--h]; st[h++] = a * b; break;
+        case O_DIV: a = st[--h]; b = st[--h]; st[h++] = pdiv_d(a, b); break;
+        case O_NEG:  a = st[--h]; st[h++] = -a; break;
+        case O_LOG:  a = st[--h]; st[h++] = plog_d(a); break;
+        case O_SQRT: a = st[--h]; st[h++] = psqrt_d(a); break;
+        case O_SIN:  a = st[--h]; st[h++] = sin(a); break;
+        case O_COS:  a = st[--h]; st[h++] = cos(a); break;
+        case O_TAN:  a = st[--h]; st[h++] = tan(a); break;
+        default: return NAN;
+        }
+    }
+    return st[0];
+}
+
+/* Float32 and float64 evaluation in lock-step, reporting whether any
+ * protected predicate (|v| > 0.001) came out differently in the two
+ * precisions on this row.  Used to mark rows whose float32 value is decided
+ * by rounding rather than by the program. */
+static int pred_flip_row(const uint32_t *nodes, int64_t len, const float *c,
+                         const float *X, int64_t ld, int64_t row)
+{
+    float sf[ORC_STACK];
+    double sd[ORC_STACK];
+    int h = 0, flip = 0;
+    for (int64_t i = len - 1; i >= 0; --i) {
+        int op = (int)(nodes[i] & 0xffu);
+        uint32_t arg = nodes[i] >> 8;
+        float af, bf;
+        double ad, bd;
+        switch (op) {
+        case O_VAR:
+            sf[h] = X[(int64_t)arg * ld + row]; sd[h] = (double)sf[h]; h++; break;
+        case O_CONST:
+            sf[h] = c[arg]; sd[h] = (double)c[arg]; h++; break;
+        case O_ADD: case O_SUB: case O_MUL: case O_DIV:
+            h--; af = sf[h]; ad = sd[h];
+            h--; bf = sf[h]; bd = sd[h];
+            if (op == O_ADD) { sf[h] = af + bf; sd[h] = ad + bd; }
+            else if (op == O_SUB) { sf[h] = af - bf; sd[h] = ad - bd; }
+            else if (op == O_MUL) { sf[h] = af * bf; sd[h] = ad * bd; }
+            else {
+                if ((fabsf(bf) > ORC_EPS) != (fabs(bd) > (double)ORC_EPS)) flip = 1;
+                sf[h] = pdiv_f(af, bf); sd[h] = pdiv_d(ad, bd);
+            }
+            h++;
+            break;
+        default:
+            h--; af = sf[h]; ad = sd[h];
+            switch (op) {
+            case O_NEG: sf[h] = -af; sd[h] = -ad; break;
+            case O_LOG:
+                if ((fabsf(af) > ORC_EPS) != (fabs(ad) > (double)ORC_EPS)) flip = 1;
+                sf[h] = plog_f(af); sd[h] = plog_d(ad); break;
+            case O_SQRT: sf[h] = psqrt_f(af); sd[h] = psqrt_d(ad); break;
+            case O_SIN: sf[h] = sinf(af); sd[h] = sin(ad); break;
+            case O_COS: sf[h] = cosf(af); sd[h] = cos(ad); break;
+            case O_TAN: sf[h] = tanf(af); sd[h] = tan(ad); break;
+            default: return 1;
+            }
+            h++;
+        }
+    }
+    return flip;
+}
+
+/* Per-row program outputs out[p*n_rows + r] for rows [0, n_rows) of a
+ * feature-major dataset X[f*ld + r] (Sec. III: column-major data resident in
+ * memory).  Programs are stored flat: program p is nodes[prog_off[p] ..
+ * prog_off[p+1]) with constants consts[const_off[p] ..). */
+void orc_evaluate_f32(const uint32_t *nodes, const int64_t *prog_off,
+                      const float *consts, const int64_t *const_off, int32_t n_programs,
+                      const float *X, int64_t ld, int64_t n_rows, float *out, int n_threads)
+{
+    (void)n_threads;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads > 0 ? n_threads : 1)
+    for (int32_t p = 0; p < n_programs; ++p) {
+        const uint32_t *pn = nodes + prog_off[p];
+        int64_t len = prog_off[p + 1] - prog_off[p];
+        const float *pc = consts + const_off[p];
+        for (int64_t r = 0; r < n_rows; ++r)
+            out[(int64_t)p * n_rows + r] = eval_row_f32(pn, len, pc, X, ld, r);
+    }
+}
+
+void orc_evaluate_f64(const uint32_t *nodes, const int64_t *prog_off,
+                      const float *consts, const int64_t *const_off, int32_t n_programs,
+                      const float *X, int64_t ld, int64_t n_rows, double *out, int n_threads)
+{
+    (void)n_threads;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads > 0 ? n_threads : 1)
+    for (int32_t p = 0; p < n_programs; ++p) {
+        const uint32_t *pn = nodes + prog_off[p];
+        int64_t len = prog_off[p + 1] - prog_off[p];
+        const float *pc = consts + const_off[p];
+        for (int64_t r = 0; r < n_rows; ++r)
+            out[(int64_t)p * n_rows + r] = eval_row_f64(pn, len, pc, X, ld, r);
+    }
+}
+
+/* Evaluate a subset of (program, row) pairs: out32[i], out64[i], flip[i] for
+ * pair (prog[i], row[i]).  Used for sampled parity at full dataset sizes. */
+void orc_evaluate_pairs(const uint32_t *nodes, const int64_t *prog_off,
+                        const float *consts, const int64_t *const_off,
+                        const float *X, int64_t ld,
+                        const int32_t *prog, const int64_t *row, int64_t n_pairs,
+                        float *out32, double *out64, uint8_t *flip, int n_threads)
+{
+    (void)n_threads;
+#pragma omp parallel for schedule(static) num_threads(n_threads > 0 ? n_threads : 1)
+    for (int64_t i = 0; i < n_pairs; ++i) {
+        int32_t p = prog[i];
+        const uint32_t *pn = nodes + prog_off[p];
+        int64_t len = prog_off[p + 1] - prog_off[p];
+        const float *pc = consts + const_off[p];
+        out32[i] = eval_row_f32(pn, len, pc, X, ld, row[i]);
+        out64[i] = eval_row_f64(pn, len, pc, X, ld, row[i]);
+        flip[i] = (uint8_t)pred_flip_row(pn, len, pc, X, ld, row[i]);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Fitness (Sec. III-C3, the fitness metric computation step: a row-wise loss */
+/* against the broadcast target, then a weighted sum per program).  Metrics:  */
+/*   0 MAE  = sum w|yhat-y| / sum w                                           */
+/*   1 MSE  = sum w (yhat-y)^2 / sum w                                        */
+/*   2 RMSE = sqrt(MSE)                                                       */
+/*   3 logistic loss (binary): yhat is a logit, l = log(1+e^yhat) - y*yhat,   */
+/*     written in the overflow-free form max(z,0) - y z + log1p(e^-|z|)       */
+/*   4 Pearson: |r| of the weighted correlation of yhat and y (0 when either  */
+/*     weighted variance is zero or not finite)                               */
+/* w == NULL means unit weights.                                              */
+/*                                                                            */
+/* Precision (reading): the program output yhat is the float32 stack value;   */
+/* the row loss of MAE/MSE/RMSE/Pearson is formed in float64 from the float32 */
+/* yhat, y, w; the logistic row loss is formed in float32 (it needs exp and   */
+/* log1p); every sum over rows is accumulated in float64.  fit_f32path gets   */
+/* this value; fit_f64 gets the same metric with yhat from the float64 stack  */
+/* evaluation and every step in float64 (error reporting only).               */
+/* ------------------------------------------------------------------------ */
+static double metric_from_values(int metric, const float *yh32, const double *yh64,
+                                 const float *y, const float *w, int64_t n)
+{
+    double sw = 0.0, s = 0.0;
+    if (metric == 4) {
+        double ma = 0.0, mb = 0.0;
+        for (int64_t r = 0; r < n; ++r) {
+            double wr = w ? (double)w[r] : 1.0;
+            double a = yh32 ? (double)yh32[r] : yh64[r];
+            sw += wr; ma += wr * a; mb += wr * (double)y[r];
+        }
+        ma /= sw; mb /= sw;
+        double va = 0.0, vb = 0.0, cab = 0.0;
+        for (int64_t r = 0; r < n; ++r) {
+            double wr = w ? (double)w[r] : 1.0;
+            double a = (yh32 ? (double)yh32[r] : yh64[r]) - ma;
+            double b = (double)y[r] - mb;
+            va += wr * a * a; vb += wr * b * b; cab += wr * a * b;
+        }
+        if (!(va > 0.0) || !(vb > 0.0) || !isfinite(va) || !isfinite(vb)) return 0.0;
+        return fabs(cab / sqrt(va * vb));
+    }
+    for (int64_t r = 0; r < n; ++r) {
+        double wr = w ? (double)w[r] : 1.0;
+        double l;
+        if (metric == 3) {
+            if (yh32) {
+                float z = yh32[r], yr = y[r];
+                float t1 = fmaxf(z, 0.0f);
+                float t2 = yr * z;
+                float t3 = t1 - t2;
+                float t5 = log1pf(expf(-fabsf(z)));
+                l = (double)(t3 + t5);
+            } else {
+                double z = yh64[r], yr = (double)y[r];
+                l = fmax(z, 0.0) - yr * z + log1p(exp(-fabs(z)));
+            }
+        } else {
+            double d = (yh32 ? (double)yh32[r] : yh64[r]) - (double)y[r];
+            l = (metric == 0) ? fabs(d) : d * d;
+        }
+        sw += wr;
+        s += wr * l;
+    }
+    double m = s / sw;
+    if (metric == 2) m = sqrt(m);
+    return m;
+}
+
+void orc_fitness(const uint32_t *nodes, const int64_t *prog_off,
+                 const float *consts, const int64_t *const_off, int32_t n_programs,
+                 const float *X, int64_t ld, int64_t n_rows,
+                 const float *y, const float *w, int32_t metric,
+                 double *fit_f32path, double *fit_f64, int n_threads)
+{
+    (void)n_threads;
+#pragma omp parallel num_threads(n_threads > 0 ? n_threads : 1)
+    {
+        float *yh32 = (float *)malloc((size_t)(n_rows > 0 ? n_rows : 1) * sizeof(float));
+        double *yh64 = fit_f64 ? (double *)malloc((size_t)(n_rows > 0 ? n_rows : 1) * sizeof(double)) : NULL;
+#pragma omp for schedule(dynamic, 1)
+        for (int32_t p = 0; p < n_programs; ++p) {
+            const uint32_t *pn = nodes + prog_off[p];
+            int64_t len = prog_off[p + 1] - prog_off[p];
+            const float *pc = consts + const_off[p];
+            for (int64_t r = 0; r < n_rows; ++r)
+                yh32[r] = eval_row_f32(pn, len, pc, X, ld, r);
+            fit_f32path[p] = metric_from_values(metric, yh32, NULL, y, w, n_rows);
+            if (fit_f64) {
+                for (int64_t r = 0; r < n_rows; ++r)
+                    yh64[r] = eval_row_f64(pn, len, pc, X, ld, r);
+                fit_f64[p] = metric_from_values(metric, NULL, yh64, y, w, n_rows);
+            }
+        }
+        free(yh32);
+        free(yh64);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), the counter-based       */
+/* generator the paper uses for tournament draws (Sec. III-B).  Round:        */
+/* (hi0,lo0) = M0*x0, (hi1,lo1) = M1*x2; out = (hi1^x1^k0, lo1, hi0^x3^k1,     */
+/* lo0); the key is bumped by the Weyl constants between rounds.              */
+/* ------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr_in[0], x1 = ctr_in[1], x2 = ctr_in[2], x3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ x1 ^ k0;
+        uint32_t n2 = hi0 ^ x3 ^ k1;
+        x0 = n0; x1 = lo1; x2 = n2; x3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Stream map (reading): key = (seed low word, seed high word); counter =
+ * (block j, item i, generation g, stream tag s).  Draw d of an item is word
+ * (d mod 4) of block floor(d/4).  Stream tags: 0 tournament, 1 init. */
+typedef struct { uint64_t seed; uint32_t item, gen, tag; uint32_t d; uint32_t buf[4]; uint32_t have_block; } orc_rng;
+
+static void rng_init(orc_rng *g, uint64_t seed, uint32_t item, uint32_t gen, uint32_t tag)
+{
+    g->seed = seed; g->item = item; g->gen = gen; g->tag = tag; g->d = 0; g->have_block = 0xffffffffu;
+}
+
+static uint32_t rng_word(orc_rng *g)
+{
+    uint32_t block = g->d / 4u, lane = g->d % 4u;
+    if (g->have_block != block) {
+        uint32_t ctr[4] = {block, g->item, g->gen, g->tag};
+        uint32_t key[2] = {(uint32_t)(g->seed & 0xffffffffu), (uint32_t)(g->seed >> 32)};
+        orc_philox4x32_10(ctr, key, g->buf);
+        g->have_block = block;
+    }
+    g->d++;
+    return g->buf[lane];
+}
+
+/* uniform integer in [0, n): floor(w * n / 2^32) */
+static uint32_t word_below(uint32_t w, uint32_t n) { return (uint32_t)(((uint64_t)w * (uint64_t)n) >> 32); }
+/* uniform float in [0, 1): top 24 bits of the word times 2^-24 */
+static float word_unit(uint32_t w) { return (float)(w >> 8) * (1.0f / 16777216.0f); }
+
+/* Raw draw access for tests: words d0 .. d0+n-1 of (seed, item, gen, tag). */
+void orc_philox_words(uint64_t seed, uint32_t item, uint32_t gen, uint32_t tag,
+                      uint32_t d0, uint32_t n, uint32_t *out)
+{
+    orc_rng g;
+    rng_init(&g, seed, item, gen, tag);
+    g.d = d0;
+    for (uint32_t i = 0; i < n; ++i) out[i] = rng_word(&g);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tournament selection (Sec. III-C1): tournament t draws k program indices,  */
+/* with replacement, and keeps the one with the best adjusted fitness         */
+/*   fitness = raw + c*len  (criterion favouring smaller values, Eqs.         */
+/*   (parsimony), (fitness)); for a criterion favouring larger values the     */
+/*   penalty is subtracted and the largest wins.                              */
+/* Readings: float32 arithmetic, each op rounded (no fused multiply-add);     */
+/* strict comparison so the earliest draw wins ties; NaN ranks worst.         */
+/* ------------------------------------------------------------------------ */
+void orc_tournament(const float *fitness, const int32_t *len, int32_t n_programs,
+                    int32_t larger_is_better, float parsimony, int32_t k,
+                    int32_t n_tournaments, uint64_t seed, uint64_t generation,
+                    int32_t *winners)
+{
+    for (int32_t t = 0; t < n_tournaments; ++t) {
+        orc_rng g;
+        rng_init(&g, seed, (uint32_t)t, (uint32_t)generation, 0u);
+        int32_t best = -1;
+        float best_adj = 0.0f;
+        for (int32_t d = 0; d < k; ++d) {
+            int32_t idx = (int32_t)word_below(rng_word(&g), (uint32_t)n_programs);
+            volatile float pen = parsimony * (float)len[idx];
+            float adj = larger_is_better ? fitness[idx] - pen : fitness[idx] + pen;
+            int take;
+            if (best < 0) take = 1;
+            else if (isnan(adj)) take = 0;
+            else if (isnan(best_adj)) take = 1;
+            else take = larger_is_better ? (adj > best_adj) : (adj < best_adj);
+            if (take) { best = idx; best_adj = adj; }
+        }
+        winners[t] = best;
+    }
+}
+
+/* Indices drawn by tournament t, for tests (draw d -> index). */
+void orc_tournament_draws(int32_t n_programs, int32_t k, int32_t t, uint64_t seed,
+                          uint64_t generation, int32_t *idx_out)
+{
+    orc_rng g;
+    rng_init(&g, seed, (uint32_t)t, (uint32_t)generation, 0u);
+    for (int32_t d = 0; d < k; ++d)
+        idx_out[d] = (int32_t)word_below(rng_word(&g), (uint32_t)n_programs);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Program generation (Sec. II-A: Full, Grow, ramped half-and-half; Sec.      */
+/* III-A: prefix lists are produced directly).  Readings, all draws from the  */
+/* init stream (tag 1), item = program index, generation 0, one word per      */
+/* decision taken in prefix (pre-)order:                                      */
+/*  RHH: word -> Grow if unit < 0.5 else Full; word -> depth d in            */
+/*       [min_depth, max_depth].  Node at depth k: k == d -> terminal;        */
+/*       k == 0 < d -> function; 0 < k < d -> Full: function, Grow: one of    */
+/*       (functions, features, constant) uniformly.  Terminal: one of         */
+/*       (features, constant) uniformly.  A constant takes one more word:      */
+/*       lo + (hi-lo)*unit in float32.  Constants are unavailable when        */
+/*       lo > hi or once max_consts (> 0) of them are used.                   */
+/*  EXACT_LEN: word -> L in [min_len, max_len]; positions L-1 .. 0 are filled */
+/*       right to left with stack height h; allowed at position i:            */
+/*       terminal if h+1 <= 20 and h <= i; unary if h >= 1 and h-1 <= i;      */
+/*       binary if h >= 2 and h-2 <= i; (plus a parity rule when there is no  */
+/*       unary function).  One word picks uniformly among the allowed items,  */
+/*       listed as features, constant, unary ops, binary ops.                 */
+/* Function set: bit (1 << opcode) of fmask for opcodes 2..11.                */
+/* Constant slots are numbered 0,1,.. in prefix order.                        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    uint32_t *nodes; int64_t n, cap;
+    float *consts; int64_t nc, ccap;
+    int overflow;
+} orc_buf;
+
+static void put_node(orc_buf *b, uint32_t w)
+{
+    if (b->nodes && b->n < b->cap) b->nodes[b->n] = w; else if (b->nodes) b->overflow = 1;
+    b->n++;
+}
+static void put_const(orc_buf *b, float v)
+{
+    if (b->consts && b->nc < b->ccap) b->consts[b->nc] = v; else if (b->consts) b->overflow = 1;
+    b->nc++;
+}
+
+typedef struct {
+    int n_features;
+    int funcs[O_NUM]; int n_funcs;      /* enabled functions in opcode order */
+    int un[O_NUM]; int n_un;
+    int bin[O_NUM]; int n_bin;
+    float lo, hi; int consts_on; int max_consts;
+} orc_gen_cfg;
+
+static float draw_const(orc_rng *g, const orc_gen_cfg *cfg)
+{
+    float u = word_unit(rng_word(g));
+    float span = cfg->hi - cfg->lo;
+    float t = span * u;
+    return cfg->lo + t;
+}
+
+/* recursive pre-order builder for Full / Grow */
+static void grow_node(orc_rng *g, const orc_gen_cfg *cfg, orc_buf *b, int depth, int target,
+                      int full, int64_t *n_consts_used)
+{
+    int const_ok = cfg->consts_on && (cfg->max_consts <= 0 || *n_consts_used < cfg->max_consts);
+    int n_term = cfg->n_features + (const_ok ? 1 : 0);
+    int is_func;
+    int pick;
+    if (depth == target) {
+        is_func = 0;
+        pick = (int)word_below(rng_word(g), (uint32_t)n_term);
+    } else if (depth == 0 || full) {
+        is_func = 1;
+        pick = (int)word_below(rng_word(g), (uint32_t)cfg->n_funcs);
+    } else {
+        pick = (int)word_below(rng_word(g), (uint32_t)(cfg->n_funcs + n_term));
+        if (pick < cfg->n_funcs) is_func = 1;
+        else { is_func = 0; pick -= cfg->n_funcs; }
+    }
+    if (is_func) {
+        int op = cfg->funcs[pick];
+        put_node(b, (uint32_t)op);
+        for (int a = 0; a < op_arity(op); ++a)
+            grow_node(g, cfg, b, depth + 1, target, full, n_consts_used);
+    } else if (pick < cfg->n_features) {
+        put_node(b, (uint32_t)O_VAR | ((uint32_t)pick << 8));
+    } else {
+        put_node(b, (uint32_t)O_CONST | ((uint32_t)(*n_consts_used) << 8));
+        put_const(b, draw_const(g, cfg));
+        (*n_consts_used)++;
+    }
+}
+
+static int gen_exact(orc_rng *g, const orc_gen_cfg *cfg, orc_buf *b, int min_len, int max_len)
+{
+    int L = min_len + (int)word_below(rng_word(g), (uint32_t)(max_len - min_len + 1));
+    if (cfg->n_un == 0 && (L % 2) == 0) {
+        if (L - 1 >= min_len && L - 1 >= 1) L -= 1; else L += 1;
+    }
+    uint32_t *tmp = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)L);
+    float *cv = (float *)malloc(sizeof(float) * (size_t)L);
+    int nconst = 0;
+    int h = 0;
+    for (int i = L - 1; i >= 0; --i) {
+        int const_ok = cfg->consts_on && (cfg->max_consts <= 0 || nconst < cfg->max_consts);
+        int n_term = cfg->n_features + (const_ok ? 1 : 0);
+        int t_ok = (h + 1 <= ORC_STACK) && (h <= i);
+        int u_ok = (cfg->n_un > 0) && (h >= 1) && (h - 1 <= i);
+        int b_ok = (cfg->n_bin > 0) && (h >= 2) && (h - 2 <= i);
+        if (cfg->n_un == 0) {
+            /* with only +1 / -1 steps, the height after this position and the
+             * number of positions left must have opposite parity (end at 1) */
+            if (t_ok && (((h + 1) - 1 + i) % 2 != 0)) t_ok = 0;
+            if (b_ok && (((h - 1) - 1 + i) % 2 != 0)) b_ok = 0;
+        }
+        int nt = t_ok ? n_term : 0, nu = u_ok ? cfg->n_un : 0, nb = b_ok ? cfg->n_bin : 0;
+        int tot = nt + nu + nb;
+        if (tot == 0) { free(tmp); free(cv); return -1; }
+        int pick = (int)word_below(rng_word(g), (uint32_t)tot);
+        if (pick < nt) {
+            if (pick < cfg->n_features) tmp[i] = (uint32_t)O_VAR | ((uint32_t)pick << 8);
+            else { tmp[i] = (uint32_t)O_CONST; cv[i] = draw_const(g, cfg); nconst++; }
+            h += 1;
+        } else if (pick < nt + nu) {
+            tmp[i] = (uint32_t)cfg->un[pick - nt];
+        } else {
+            tmp[i] = (uint32_t)cfg->bin[pick - nt - nu];
+            h -= 1;
+        }
+    }
+    int slot = 0;
+    for (int i = 0; i < L; ++i) {
+        if ((tmp[i] & 0xffu) == O_CONST) {
+            put_node(b, (uint32_t)O_CONST | ((uint32_t)slot << 8));
+            put_const(b, cv[i]);
+            slot++;
+        } else {
+            put_node(b, tmp[i]);
+        }
+    }
+    free(tmp);
+    free(cv);
+    return 0;
+}
+
+/* method: 0 RHH, 1 FULL, 2 GROW, 3 EXACT_LEN.  Buffers may be NULL (sizes
+ * only).  Returns 0 on success, -1 bad arguments, -2 a buffer is too small. */
+int orc_build_population(int32_t n_programs, int32_t n_features, int32_t method,
+                         int32_t min_depth, int32_t max_depth, int32_t min_len, int32_t max_len,
+                         uint32_t fmask, float const_lo, float const_hi, int32_t max_consts,
+                         uint64_t seed,
+                         uint32_t *nodes, int64_t nodes_cap, int64_t *prog_off,
+                         float *consts, int64_t consts_cap, int64_t *const_off, int32_t *len,
+                         int64_t *total_nodes, int64_t *total_consts)
+{
+    orc_gen_cfg cfg;
+    memset(&cfg, 0, sizeof cfg);
+    if (n_programs < 0 || n_features < 1) return -1;
+    cfg.n_features = n_features;
+    for (int op = O_ADD; op < O_NUM; ++op) {
+        if (fmask & (1u << op)) {
+            cfg.funcs[cfg.n_funcs++] = op;
+            if (op_arity(op) == 1) cfg.un[cfg.n_un++] = op; else cfg.bin[cfg.n_bin++] = op;
+        }
+    }
+    if (fmask & ~(((1u << O_NUM) - 1u) & ~3u)) return -1;
+    if (cfg.n_funcs == 0) return -1;
+    cfg.lo = const_lo; cfg.hi = const_hi;
+    cfg.consts_on = !(const_lo > const_hi);
+    cfg.max_consts = max_consts;
+    if (method == 3) {
+        if (min_len < 1 || max_len < min_len) return -1;
+        if (cfg.n_bin == 0 && max_len > 1) return -1;
+    } else if (method >= 0 && method <= 2) {
+        if (min_depth < 0 || max_depth < min_depth || max_depth > ORC_STACK - 1) return -1;
+    } else {
+        return -1;
+    }
+    orc_buf b;
+    b.nodes = nodes; b.n = 0; b.cap = nodes_cap;
+    b.consts = consts; b.nc = 0; b.ccap = consts_cap; b.overflow = 0;
+    for (int32_t p = 0; p < n_programs; ++p) {
+        orc_rng g;
+        rng_init(&g, seed, (uint32_t)p, 0u, 1u);
+        int64_t n0 = b.n, c0 = b.nc;
+        if (prog_off && nodes) prog_off[p] = n0;
+        if (const_off && nodes) const_off[p] = c0;
+        if (method == 3) {
+            if (gen_exact(&g, &cfg, &b, min_len, max_len) != 0) return -1;
+        } else {
+            int full, depth;
+            if (method == 0) {
+                full = !(word_unit(rng_word(&g)) < 0.5f);
+                depth = min_depth + (int)word_below(rng_word(&g), (uint32_t)(max_depth - min_depth + 1));
+            } else {
+                full = (method == 1);
+                depth = min_depth + (int)word_below(rng_word(&g), (uint32_t)(max_depth - min_depth + 1));
+            }
+            int64_t used = 0;
+            grow_node(&g, &cfg, &b, 0, depth, full, &used);
+        }
+        if (len && nodes) len[p] = (int32_t)(b.n - n0);
+    }
+    if (prog_off && nodes) prog_off[n_programs] = b.n;
+    if (const_off && nodes) const_off[n_programs] = b.nc;
+    if (total_nodes) *total_nodes = b.n;
+    if (total_consts) *total_consts = b.nc;
+    return b.overflow ? -2 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Reverse-mode derivative of fitness with respect to every program constant, */
+/* in float64 (not in the paper).  For each row the program is evaluated in   */
+/* float64 keeping every node's value; the adjoint of the root is the         */
+/* derivative of the metric with respect to that row's output; nodes are then */
+/* visited parent-before-child (prefix order), handing each child its share    */
+/* by the local partial derivatives (readings):                               */
+/*   add (1,1); sub (1,-1); mul (b,a); pdiv (1/b, -a/b^2) if |b|>eps else 0;  */
+/*   plog 1/a if |a|>eps else 0; psqrt sign(a)/(2 sqrt|a|), 0 at a = 0;       */
+/*   sin cos a; cos -sin a; tan 1 + tan^2 a; neg -1.                          */
+/* Seeds: MSE 2w(yh-y)/W; MAE w sign(yh-y)/W; RMSE dMSE/(2 RMSE) (0 if RMSE   */
+/* is 0); logistic w(sigmoid(yh)-y)/W; Pearson d|r|/dyh.                      */
+/* grad[const_off[p] + s] receives gscale[p] * d fitness_p / d c_s.           */
+/* ------------------------------------------------------------------------ */
+static double local_partial(int op, int which, double a, double b, double out)
+{
+    switch (op) {
+    case O_ADD: return 1.0;
+    case O_SUB: return which == 0 ? 1.0 : -1.0;
+    case O_MUL: return which == 0 ? b : a;
+    case O_DIV:
+        if (!(fabs(b) > (double)ORC_EPS)) return 0.0;
+        return which == 0 ? 1.0 / b : -a / (b * b);
+    case O_NEG: return -1.0;
+    case O_LOG: return fabs(a) > (double)ORC_EPS ? 1.0 / a : 0.0;
+    case O_SQRT:
+        if (a == 0.0) return 0.0;
+        return (a > 0.0 ? 1.0 : -1.0) / (2.0 * sqrt(fabs(a)));
+    case O_SIN: return cos(a);
+    case O_COS: return -sin(a);
+    case O_TAN: return 1.0 + out * out;
+    default: return 0.0;
+    }
+}
+
+void orc_grad_consts(const uint32_t *nodes, const int64_t *prog_off,
+                     const float *consts, const int64_t *const_off, int32_t n_programs,
+                     const float *X, int64_t ld, int64_t n_rows,
+                     const float *y, const float *w, int32_t metric,
+                     const double *gscale, double *grad, double *fit_out, int n_threads)
+{
+    (void)n_threads;
+#pragma omp parallel num_threads(n_threads > 0 ? n_threads : 1)
+    {
+        double *yh = (double *)malloc(sizeof(double) * (size_t)(n_rows > 0 ? n_rows : 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int32_t p = 0; p < n_programs; ++p) {
+            const uint32_t *pn = nodes + prog_off[p];
+            int64_t L = prog_off[p + 1] - prog_off[p];
+            const float *pc = consts + const_off[p];
+            int64_t nc = const_off[p + 1] - const_off[p];
+            double *gp = grad + const_off[p];
+            for (int64_t s = 0; s < nc; ++s) gp[s] = 0.0;
+            /* forward pass for the metric's global statistics */
+            double W = 0.0, S = 0.0;
+            for (int64_t r = 0; r < n_rows; ++r) yh[r] = eval_row_f64(pn, L, pc, X, ld, r);
+            double ma = 0.0, mb = 0.0, va = 0.0, vb = 0.0, cab = 0.0, rr = 0.0;
+            for (int64_t r = 0; r < n_rows; ++r) {
+                double wr = w ? (double)w[r] : 1.0;
+                W += wr;
+                if (metric == 0) S += wr * fabs(yh[r] - (double)y[r]);
+                else if (metric == 1 || metric == 2) S += wr * (yh[r] - (double)y[r]) * (yh[r] - (double)y[r]);
+                else if (metric == 3) {
+                    double z = yh[r];
+                    S += wr * (fmax(z, 0.0) - (double)y[r] * z + log1p(exp(-fabs(z))));
+                }
+                ma += wr * yh[r]; mb += wr * (double)y[r];
+            }
+            double fit;
+            if (metric == 4) {
+                ma /= W; mb /= W;
+                for (int64_t r = 0; r < n_rows; ++r) {
+                    double wr = w ? (double)w[r] : 1.0;
+                    double a = yh[r] - ma, b = (double)y[r] - mb;
+                    va += wr * a * a; vb += wr * b * b; cab += wr * a * b;
+                }
+                int ok = (va > 0.0) && (vb > 0.0) && isfinite(va) && isfinite(vb);
+                rr = ok ? cab / sqrt(va * vb) : 0.0;
+                fit = fabs(rr);
+                if (!ok) { if (fit_out) fit_out[p] = 0.0; continue; }
+            } else {
+                fit = S / W;
+                if (metric == 2) fit = sqrt(fit);
+            }
+            if (fit_out) fit_out[p] = fit;
+            double gs = gscale ? gscale[p] : 1.0;
+            if (nc == 0) continue;
+            /* per-row reverse sweep */
+            double val[4096];
+            int64_t endi[4096];
+            double adj[4096];
+            if (L > 4096) continue;       /* longer programs are not supported here */
+            for (int64_t r = 0; r < n_rows; ++r) {
+                double wr = w ? (double)w[r] : 1.0;
+                double d = yh[r] - (double)y[r];
+                double seed;
+                switch (metric) {
+                case 0: seed = wr * (d > 0 ? 1.0 : (d < 0 ? -1.0 : 0.0)) / W; break;
+                case 1: seed = 2.0 * wr * d / W; break;
+                case 2: seed = fit > 0.0 ? (2.0 * wr * d / W) / (2.0 * fit) : 0.0; break;
+                case 3: seed = wr * (1.0 / (1.0 + exp(-yh[r])) - (double)y[r]) / W; break;
+                default: {
+                    double a = yh[r] - ma, b = (double)y[r] - mb;
+                    double dr = wr * (b / sqrt(va * vb) - rr * a / va);
+                    seed = (rr >= 0.0 ? 1.0 : -1.0) * dr;
+                }
+                }
+                seed *= gs;
+                /* forward with per-node values and subtree extents */
+                double st[ORC_STACK];
+                int h = 0;
+                for (int64_t i = L - 1; i >= 0; --i) {
+                    int op = (int)(pn[i] & 0xffu);
+                    uint32_t arg = pn[i] >> 8;
+                    int ar = op_arity(op);
+                    double v;
+                    if (ar == 0) {
+                        v = (op == O_VAR) ? (double)X[(int64_t)arg * ld + r] : (double)pc[arg];
+                        endi[i] = i + 1;
+                    } else if (ar == 1) {
+                        double a = st[--h];
+                        switch (op) {
+                        case O_NEG: v = -a; break;
+                        case O_LOG: v = plog_d(a); break;
+                        case O_SQRT: v = psqrt_d(a); break;
+                        case O_SIN: v = sin(a); break;
+                        case O_COS: v = cos(a); break;
+                        default: v = tan(a); break;
+                        }
+                        endi[i] = endi[i + 1];
+                    } else {
+                        double a = st[--h];
+                        double b = st[--h];
+                        switch (op) {
+                        case O_ADD: v = a + b; break;
+                        case O_SUB: v = a - b; break;
+                        case O_MUL: v = a * b; break;
+                        default: v = pdiv_d(a, b); break;
+                        }
+                        endi[i] = endi[endi[i + 1]];
+                    }
+                    val[i] = v;
+                    st[h++] = v;
+                }
+                for (int64_t i = 0; i < L; ++i) adj[i] = 0.0;
+                adj[0] = seed;
+                for (int64_t i = 0; i < L; ++i) {
+                    int op = (int)(pn[i] & 0xffu);
+                    int ar = op_arity(op);
+                    if (op == O_CONST) { gp[pn[i] >> 8] += adj[i]; continue; }
+                    if (ar == 0 || adj[i] == 0.0) continue;
+                    int64_t ia = i + 1;
+                    if (ar == 1) {
+                        adj[ia] += adj[i] * local_partial(op, 0, val[ia], 0.0, val[i]);
+                    } else {
+                        int64_t ib = endi[ia];
+                        adj[ia] += adj[i] * local_partial(op, 0, val[ia], val[ib], val[i]);
+                        adj[ib] += adj[i] * local_partial(op, 1, val[ia], val[ib], val[i]);
+                    }
+                }
+            }
+        }
+        free(yh);
+    }
+}

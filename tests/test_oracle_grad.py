@@ -1,0 +1,107 @@
+"""Pins of the oracle's float64 reverse-mode constant gradients: a closed
+form, and central finite differences (an independent method) on random
+programs for every metric."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import MUL, SIN, ADD, VAR, CONST, node
+
+import synth
+
+
+def test_closed_form_mul_c_x0():
+    rng = np.random.default_rng(0)
+    n = 4000
+    x = rng.uniform(-3, 3, size=n).astype(np.float32)
+    X = x[None, :]
+    y = (2.0 * x).astype(np.float32)
+    w = rng.uniform(0.5, 1.5, size=n).astype(np.float32)
+    c = np.float32(0.7)
+    pop = oracle.from_programs([([node(MUL), node(CONST, 0), node(VAR, 0)], [c])])
+    g, f = oracle.grad_consts(pop, X, y, w, "mse")
+    wd, xd = w.astype(np.float64), x.astype(np.float64)
+    expect = 2.0 * (float(c) - 2.0) * np.sum(wd * xd * xd) / np.sum(wd)
+    assert abs(g[0] - expect) <= 1e-12 * abs(expect)
+
+
+def test_closed_form_sin_cx():
+    # d/dc mean (sin(c x) - y)^2 = mean 2 (sin(c x) - y) cos(c x) x
+    rng = np.random.default_rng(1)
+    n = 3000
+    x = rng.uniform(-2, 2, size=n).astype(np.float32)
+    y = rng.normal(size=n).astype(np.float32)
+    c = np.float32(1.3)
+    pop = oracle.from_programs([([node(SIN), node(MUL), node(CONST, 0), node(VAR, 0)], [c])])
+    g, _ = oracle.grad_consts(pop, x[None, :], y, None, "mse")
+    xd, yd = x.astype(np.float64), y.astype(np.float64)
+    cx = float(c) * xd
+    expect = np.mean(2 * (np.sin(cx) - yd) * np.cos(cx) * xd)
+    assert abs(g[0] - expect) <= 1e-12 * abs(expect)
+
+
+def _fd1(pop, X, y, w, metric, h):
+    """Central differences of the float64 fitness, one constant at a time."""
+    out = np.zeros(pop.consts.shape[0])
+    for p in range(pop.n_programs):
+        for k in range(int(pop.const_off[p]), int(pop.const_off[p + 1])):
+            c0 = pop.consts[k]
+            cp, cm = np.float32(c0 + h), np.float32(c0 - h)
+            pop.consts[k] = cp
+            fp = oracle.fitness(pop, X, y, w, metric)[1][p]
+            pop.consts[k] = cm
+            fm = oracle.fitness(pop, X, y, w, metric)[1][p]
+            pop.consts[k] = c0
+            out[k] = (fp - fm) / (float(cp) - float(cm))
+    return out
+
+
+def _fd(pop, X, y, w, metric, h=1e-3):
+    """Central differences at h and h/2 combined by Richardson extrapolation
+    (truncation error O(h^4) instead of O(h^2))."""
+    d1 = _fd1(pop, X, y, w, metric, h)
+    d2 = _fd1(pop, X, y, w, metric, h / 2)
+    return (4.0 * d2 - d1) / 3.0
+
+
+SMOOTH = sum(1 << o for o in (oracle.ADD, oracle.SUB, oracle.MUL, oracle.NEG, oracle.SIN,
+                              oracle.COS))
+
+
+@pytest.mark.parametrize("metric", ["mse", "rmse", "logloss", "pearson", "mae"])
+def test_reverse_mode_matches_central_differences(metric):
+    n = 512
+    X, y = synth.diff_target(n, seed=3)
+    if metric == "logloss":
+        y = (y > np.median(y)).astype(np.float32)
+    w = synth.weights(n, seed=4)
+    pop = oracle.build_population(24, 8, "exact_len", min_len=3, max_len=40, fmask=SMOOTH,
+                                  max_consts=16, seed=5)
+    g, f = oracle.grad_consts(pop, X, y, w, metric)
+    fd = _fd(pop, X, y, w, metric)
+    checked = 0
+    for p in range(pop.n_programs):
+        a, b = int(pop.const_off[p]), int(pop.const_off[p + 1])
+        if a == b:
+            continue
+        scale = max(np.max(np.abs(g[a:b])), 1e-3 * max(abs(f[p]), 1e-6))
+        err = np.max(np.abs(g[a:b] - fd[a:b])) / scale
+        if metric == "mae":
+            # |.| has kinks where a row's residual crosses 0; FD straddling one
+            # differs by O(w/n): accept that size
+            assert err < 2e-2, (p, err)
+        else:
+            assert err < 1e-5, (p, err)
+        checked += 1
+    assert checked >= 10
+
+
+def test_gradient_scale_and_const_free_programs():
+    X, y = synth.diff_target(256, seed=6)
+    progs = [([node(ADD), node(VAR, 0), node(VAR, 1)], []),
+             ([node(MUL), node(CONST, 0), node(VAR, 2)], [0.5])]
+    pop = oracle.from_programs(progs)
+    g1, _ = oracle.grad_consts(pop, X, y, None, "mse")
+    g2, _ = oracle.grad_consts(pop, X, y, None, "mse", gscale=np.array([1.0, -3.0]))
+    assert g1.shape == (1,)
+    assert abs(g2[0] + 3.0 * g1[0]) <= 1e-12 * abs(g1[0])
