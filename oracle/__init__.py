@@ -31,6 +31,9 @@ LARGER_IS_BETTER = {0: 0, 1: 0, 2: 0, 3: 0, 4: 1}
 INIT = {"rhh": 0, "full": 1, "grow": 2, "exact_len": 3}
 # the nine-function set used by the Pagie / classification workloads
 DEFAULT_FMASK = sum(1 << op for op in (ADD, SUB, MUL, DIV, NEG, LOG, SQRT, SIN, COS))
+# relative allowance for a sin/cos/tan/log result in the conditioning bound:
+# 4 float32 ulps (an ulp of v is at most 2^-23 |v|)
+ULP_ALLOWANCE = 4.0 * 2.0 ** -23
 
 
 def build(force: bool = True) -> str:
@@ -60,8 +63,10 @@ def lib():
         L.orc_check_program.restype = ctypes.c_int
         L.orc_evaluate_f32.argtypes = [P, P, P, P, i32, P, i64, i64, P, ctypes.c_int]
         L.orc_evaluate_f64.argtypes = [P, P, P, P, i32, P, i64, i64, P, ctypes.c_int]
-        L.orc_evaluate_pairs.argtypes = [P, P, P, P, P, i64, P, P, i64, P, P, P, ctypes.c_int]
-        L.orc_fitness.argtypes = [P, P, P, P, i32, P, i64, i64, P, P, i32, P, P, ctypes.c_int]
+        L.orc_evaluate_pairs.argtypes = [P, P, P, P, P, i64, P, P, i64, ctypes.c_double, P, P, P, P,
+                                         ctypes.c_int]
+        L.orc_fitness.argtypes = [P, P, P, P, i32, P, i64, i64, P, P, i32, P, P, ctypes.c_double, P, P,
+                                  ctypes.c_int]
         L.orc_philox4x32_10.argtypes = [P, P, P]
         L.orc_philox_words.argtypes = [u64, u32, u32, u32, u32, u32, P]
         L.orc_tournament.argtypes = [P, P, i32, i32, f32, i32, i32, u64, u64, P]
@@ -156,35 +161,53 @@ def evaluate_f64(pop: Population, X, n_threads=None):
     return out
 
 
-def evaluate_pairs(pop: Population, X, prog, row, n_threads=None):
-    """Float32 value, float64 value and protected-predicate flip flag of each
-    (prog[i], row[i]) pair."""
+@dataclass
+class RowAnalysis:
+    v32: np.ndarray      # float32 stack value
+    v64: np.ndarray      # float64 stack value
+    bound: np.ndarray    # first-order bound on the float32 value's sensitivity
+    flip: np.ndarray     # a protected predicate differs between float32 and float64
+    near: np.ndarray     # a protected predicate lies within its bound of the threshold
+
+
+def evaluate_pairs(pop: Population, X, prog, row, n_threads=None, u=ULP_ALLOWANCE) -> RowAnalysis:
+    """Float32 and float64 values and the conditioning analysis of each
+    (prog[i], row[i]) pair (see row_analysis in gp_oracle.c)."""
     X, N = _ds(X)
     prog = np.ascontiguousarray(prog, dtype=np.int32)
     row = np.ascontiguousarray(row, dtype=np.int64)
     n = prog.shape[0]
     o32 = np.empty(n, np.float32)
     o64 = np.empty(n, np.float64)
-    flip = np.empty(n, np.uint8)
+    eb = np.empty(n, np.float64)
+    fl = np.empty(n, np.uint8)
     lib().orc_evaluate_pairs(_p(pop.nodes), _p(pop.prog_off), _p(pop.consts),
-                             _p(pop.const_off), _p(X), N, _p(prog), _p(row), n,
-                             _p(o32), _p(o64), _p(flip), _threads(n_threads))
-    return o32, o64, flip.astype(bool)
+                             _p(pop.const_off), _p(X), N, _p(prog), _p(row), n, float(u),
+                             _p(o32), _p(o64), _p(eb), _p(fl), _threads(n_threads))
+    return RowAnalysis(o32, o64, eb, (fl & 1).astype(bool), (fl & 2).astype(bool))
 
 
-def fitness(pop: Population, X, y, w=None, metric="mse", n_threads=None, with_f64=True):
+def fitness(pop: Population, X, y, w=None, metric="mse", n_threads=None, with_f64=True,
+            with_bound=False, u=ULP_ALLOWANCE):
     """(fitness from the float32 program values, fitness with every step in
-    float64).  Both returned as float64 arrays; the float32 result the library
-    must match is the first one rounded to float32."""
+    float64), as float64 arrays; the float32 result the library must match is
+    the first one rounded to float32.  With with_bound=True also returns the
+    first-order bound on the float32-path fitness's sensitivity and, per
+    program, the number of rows with a protected predicate near its
+    threshold."""
     X, N = _ds(X)
     y = np.ascontiguousarray(y, dtype=np.float32)
     w = None if w is None else np.ascontiguousarray(w, dtype=np.float32)
     m = METRICS[metric] if isinstance(metric, str) else int(metric)
     f32p = np.empty(pop.n_programs, np.float64)
-    f64 = np.empty(pop.n_programs, np.float64) if with_f64 else None
+    f64 = np.empty(pop.n_programs, np.float64) if (with_f64 or with_bound) else None
+    fb = np.empty(pop.n_programs, np.float64) if with_bound else None
+    fn = np.empty(pop.n_programs, np.int32) if with_bound else None
     lib().orc_fitness(_p(pop.nodes), _p(pop.prog_off), _p(pop.consts), _p(pop.const_off),
-                      pop.n_programs, _p(X), N, N, _p(y), _p(w), m, _p(f32p), _p(f64),
-                      _threads(n_threads))
+                      pop.n_programs, _p(X), N, N, _p(y), _p(w), m, _p(f32p), _p(f64), float(u),
+                      _p(fb), _p(fn), _threads(n_threads))
+    if with_bound:
+        return f32p, f64, fb, fn
     return f32p, f64
 
 

@@ -157,55 +157,81 @@ static double eval_row_f64(const uint32_t *nodes, int64_t len, const float *c,
     return st[0];
 }
 
-/* Float32 and float64 evaluation in lock-step, reporting whether any
- * protected predicate (|v| > 0.001) came out differently in the two
- * precisions on this row.  Used to mark rows whose float32 value is decided
- * by rounding rather than by the program. */
-static int pred_flip_row(const uint32_t *nodes, int64_t len, const float *c,
-                         const float *X, int64_t ld, int64_t row)
+/* Conditioning analysis of one row (test infrastructure for the tolerance
+ * policy).  Evaluates the program in float32 and float64 in lock-step and
+ * carries, in float64, a first-order bound E on how far a float32 evaluation
+ * can move when every sin / cos / tan / log result is allowed to differ from
+ * the correctly rounded one by `u` relative (two correct library
+ * implementations of these functions are a few ulp apart; add, sub, mul,
+ * div, neg and sqrt are correctly rounded everywhere and contribute nothing):
+ *   terminal 0;  a+b, a-b: Ea+Eb;  a*b: |b|Ea+|a|Eb;  a/b: Ea/|b|+|a|Eb/b^2
+ *   (0 on the protected arm);  -a: Ea;  sqrt|a|: Ea/(2 sqrt|a|);
+ *   f(a) for f in sin, cos, tan, log: |f'(a)| Ea + u |f(a)|.
+ * Outputs: *v32, *v64 the two values, *E the bound on the output, *flip if
+ * a protected predicate came out differently in float32 and float64, *near if
+ * a protected predicate's float32 operand lies within its own bound of the
+ * 0.001 threshold (so two float32 evaluations may take different arms). */
+static double mul0(double x, double y) { return (x == 0.0 || y == 0.0) ? 0.0 : x * y; }
+
+static void row_analysis(const uint32_t *nodes, int64_t len, const float *c,
+                         const float *X, int64_t ld, int64_t row, double u,
+                         float *v32, double *v64, double *Eout, int *flip_out, int *near_out)
 {
     float sf[ORC_STACK];
-    double sd[ORC_STACK];
-    int h = 0, flip = 0;
+    double sd[ORC_STACK], se[ORC_STACK];
+    int h = 0, flip = 0, near = 0;
+    const double eps = (double)ORC_EPS;
     for (int64_t i = len - 1; i >= 0; --i) {
         int op = (int)(nodes[i] & 0xffu);
         uint32_t arg = nodes[i] >> 8;
         float af, bf;
-        double ad, bd;
+        double ad, bd, ea, eb;
         switch (op) {
         case O_VAR:
-            sf[h] = X[(int64_t)arg * ld + row]; sd[h] = (double)sf[h]; h++; break;
+            sf[h] = X[(int64_t)arg * ld + row]; sd[h] = (double)sf[h]; se[h] = 0.0; h++; break;
         case O_CONST:
-            sf[h] = c[arg]; sd[h] = (double)c[arg]; h++; break;
+            sf[h] = c[arg]; sd[h] = (double)c[arg]; se[h] = 0.0; h++; break;
         case O_ADD: case O_SUB: case O_MUL: case O_DIV:
-            h--; af = sf[h]; ad = sd[h];
-            h--; bf = sf[h]; bd = sd[h];
-            if (op == O_ADD) { sf[h] = af + bf; sd[h] = ad + bd; }
-            else if (op == O_SUB) { sf[h] = af - bf; sd[h] = ad - bd; }
-            else if (op == O_MUL) { sf[h] = af * bf; sd[h] = ad * bd; }
-            else {
-                if ((fabsf(bf) > ORC_EPS) != (fabs(bd) > (double)ORC_EPS)) flip = 1;
+            h--; af = sf[h]; ad = sd[h]; ea = se[h];
+            h--; bf = sf[h]; bd = sd[h]; eb = se[h];
+            if (op == O_ADD) { sf[h] = af + bf; sd[h] = ad + bd; se[h] = ea + eb; }
+            else if (op == O_SUB) { sf[h] = af - bf; sd[h] = ad - bd; se[h] = ea + eb; }
+            else if (op == O_MUL) {
+                sf[h] = af * bf; sd[h] = ad * bd; se[h] = mul0(fabs(bd), ea) + mul0(fabs(ad), eb);
+            } else {
+                if ((fabsf(bf) > ORC_EPS) != (fabs(bd) > eps)) flip = 1;
+                if (eb > 0.0 && fabs(fabs((double)bf) - eps) <= eb) near = 1;
                 sf[h] = pdiv_f(af, bf); sd[h] = pdiv_d(ad, bd);
+                se[h] = fabs(bd) > eps ? mul0(ea, 1.0 / fabs(bd)) + mul0(eb, fabs(ad) / (bd * bd)) : 0.0;
             }
             h++;
             break;
         default:
-            h--; af = sf[h]; ad = sd[h];
+            h--; af = sf[h]; ad = sd[h]; ea = se[h];
             switch (op) {
-            case O_NEG: sf[h] = -af; sd[h] = -ad; break;
+            case O_NEG: sf[h] = -af; sd[h] = -ad; se[h] = ea; break;
             case O_LOG:
-                if ((fabsf(af) > ORC_EPS) != (fabs(ad) > (double)ORC_EPS)) flip = 1;
-                sf[h] = plog_f(af); sd[h] = plog_d(ad); break;
-            case O_SQRT: sf[h] = psqrt_f(af); sd[h] = psqrt_d(ad); break;
-            case O_SIN: sf[h] = sinf(af); sd[h] = sin(ad); break;
-            case O_COS: sf[h] = cosf(af); sd[h] = cos(ad); break;
-            case O_TAN: sf[h] = tanf(af); sd[h] = tan(ad); break;
-            default: return 1;
+                if ((fabsf(af) > ORC_EPS) != (fabs(ad) > eps)) flip = 1;
+                if (ea > 0.0 && fabs(fabs((double)af) - eps) <= ea) near = 1;
+                sf[h] = plog_f(af); sd[h] = plog_d(ad);
+                se[h] = fabs(ad) > eps ? mul0(ea, 1.0 / fabs(ad)) + u * fabs(sd[h]) : 0.0;
+                break;
+            case O_SQRT:
+                sf[h] = psqrt_f(af); sd[h] = psqrt_d(ad);
+                se[h] = ea == 0.0 ? 0.0 : (ad != 0.0 ? ea / (2.0 * sqrt(fabs(ad))) : INFINITY);
+                break;
+            case O_SIN: sf[h] = sinf(af); sd[h] = sin(ad);
+                se[h] = mul0(fabs(cos(ad)), ea) + u * fabs(sd[h]); break;
+            case O_COS: sf[h] = cosf(af); sd[h] = cos(ad);
+                se[h] = mul0(fabs(sin(ad)), ea) + u * fabs(sd[h]); break;
+            case O_TAN: sf[h] = tanf(af); sd[h] = tan(ad);
+                se[h] = mul0(1.0 + sd[h] * sd[h], ea) + u * fabs(sd[h]); break;
+            default: *v32 = NAN; *v64 = NAN; *Eout = INFINITY; *flip_out = 1; *near_out = 1; return;
             }
             h++;
         }
     }
-    return flip;
+    *v32 = sf[0]; *v64 = sd[0]; *Eout = se[0]; *flip_out = flip; *near_out = near;
 }
 
 /* Per-row program outputs out[p*n_rows + r] for rows [0, n_rows) of a
@@ -242,13 +268,15 @@ void orc_evaluate_f64(const uint32_t *nodes, const int64_t *prog_off,
     }
 }
 
-/* Evaluate a subset of (program, row) pairs: out32[i], out64[i], flip[i] for
- * pair (prog[i], row[i]).  Used for sampled parity at full dataset sizes. */
+/* Evaluate a subset of (program, row) pairs: out32[i], out64[i], the
+ * conditioning bound ebound[i] (row_analysis with allowance u) and flags
+ * flags[i] (bit 0: float32/float64 predicate flip, bit 1: predicate within
+ * its bound of the threshold) for pair (prog[i], row[i]). */
 void orc_evaluate_pairs(const uint32_t *nodes, const int64_t *prog_off,
                         const float *consts, const int64_t *const_off,
                         const float *X, int64_t ld,
-                        const int32_t *prog, const int64_t *row, int64_t n_pairs,
-                        float *out32, double *out64, uint8_t *flip, int n_threads)
+                        const int32_t *prog, const int64_t *row, int64_t n_pairs, double u,
+                        float *out32, double *out64, double *ebound, uint8_t *flags, int n_threads)
 {
     (void)n_threads;
 #pragma omp parallel for schedule(static) num_threads(n_threads > 0 ? n_threads : 1)
@@ -257,9 +285,9 @@ void orc_evaluate_pairs(const uint32_t *nodes, const int64_t *prog_off,
         const uint32_t *pn = nodes + prog_off[p];
         int64_t len = prog_off[p + 1] - prog_off[p];
         const float *pc = consts + const_off[p];
-        out32[i] = eval_row_f32(pn, len, pc, X, ld, row[i]);
-        out64[i] = eval_row_f64(pn, len, pc, X, ld, row[i]);
-        flip[i] = (uint8_t)pred_flip_row(pn, len, pc, X, ld, row[i]);
+        int flip, near;
+        row_analysis(pn, len, pc, X, ld, row[i], u, &out32[i], &out64[i], &ebound[i], &flip, &near);
+        flags[i] = (uint8_t)(flip | (near << 1));
     }
 }
 
@@ -295,12 +323,24 @@ static double metric_from_values(int metric, const float *yh32, const double *yh
         }
         ma /= sw; mb /= sw;
         double va = 0.0, vb = 0.0, cab = 0.0;
+        /* a column that takes one value on every weighted row has variance 0
+         * exactly, whatever rounding does to its computed mean */
+        int const_a = 1, const_b = 1, seen = 0;
+        double a0 = 0.0, b0 = 0.0;
         for (int64_t r = 0; r < n; ++r) {
             double wr = w ? (double)w[r] : 1.0;
-            double a = (yh32 ? (double)yh32[r] : yh64[r]) - ma;
-            double b = (double)y[r] - mb;
+            double av = yh32 ? (double)yh32[r] : yh64[r];
+            double bv = (double)y[r];
+            if (wr != 0.0) {
+                if (!seen) { a0 = av; b0 = bv; seen = 1; }
+                if (!(av == a0)) const_a = 0;
+                if (!(bv == b0)) const_b = 0;
+            }
+            double a = av - ma;
+            double b = bv - mb;
             va += wr * a * a; vb += wr * b * b; cab += wr * a * b;
         }
+        if (const_a || const_b) return 0.0;
         if (!(va > 0.0) || !(vb > 0.0) || !isfinite(va) || !isfinite(vb)) return 0.0;
         return fabs(cab / sqrt(va * vb));
     }
@@ -331,33 +371,90 @@ static double metric_from_values(int metric, const float *yh32, const double *yh
     return m;
 }
 
+/* First-order bound on how far the float32-path fitness can move when each
+ * row's float32 output moves by at most its row_analysis bound E[r]:
+ * sum_r |d fitness / d yhat_r| E[r] (plus the second-order term of MSE). */
+static double fitness_bound(int metric, const float *yh, const double *E, const float *y,
+                            const float *w, int64_t n, double fit)
+{
+    double W = 0.0;
+    for (int64_t r = 0; r < n; ++r) W += w ? (double)w[r] : 1.0;
+    double B = 0.0;
+    if (metric == 4) {
+        double ma = 0.0, mb = 0.0, va = 0.0, vb = 0.0, cab = 0.0;
+        for (int64_t r = 0; r < n; ++r) {
+            double wr = w ? (double)w[r] : 1.0;
+            ma += wr * (double)yh[r]; mb += wr * (double)y[r];
+        }
+        ma /= W; mb /= W;
+        for (int64_t r = 0; r < n; ++r) {
+            double wr = w ? (double)w[r] : 1.0;
+            double a = (double)yh[r] - ma, b = (double)y[r] - mb;
+            va += wr * a * a; vb += wr * b * b; cab += wr * a * b;
+        }
+        if (!(va > 0.0) || !(vb > 0.0)) return 0.0;
+        double rr = cab / sqrt(va * vb);
+        for (int64_t r = 0; r < n; ++r) {
+            double wr = w ? (double)w[r] : 1.0;
+            double a = (double)yh[r] - ma, b = (double)y[r] - mb;
+            B += mul0(wr * fabs(b / sqrt(va * vb) - rr * a / va), E[r]);
+        }
+        return B;
+    }
+    for (int64_t r = 0; r < n; ++r) {
+        double wr = w ? (double)w[r] : 1.0;
+        double d = (double)yh[r] - (double)y[r];
+        if (metric == 0 || metric == 3) B += mul0(wr, E[r]);
+        else B += mul0(2.0 * wr * fabs(d), E[r]) + mul0(wr, E[r] * E[r]);
+    }
+    B /= W;
+    if (metric == 2) B = fit > 0.0 ? B / (2.0 * fit) : sqrt(B);
+    return B;
+}
+
 void orc_fitness(const uint32_t *nodes, const int64_t *prog_off,
                  const float *consts, const int64_t *const_off, int32_t n_programs,
                  const float *X, int64_t ld, int64_t n_rows,
                  const float *y, const float *w, int32_t metric,
-                 double *fit_f32path, double *fit_f64, int n_threads)
+                 double *fit_f32path, double *fit_f64, double u, double *fbound, int32_t *fnear,
+                 int n_threads)
 {
     (void)n_threads;
 #pragma omp parallel num_threads(n_threads > 0 ? n_threads : 1)
     {
-        float *yh32 = (float *)malloc((size_t)(n_rows > 0 ? n_rows : 1) * sizeof(float));
-        double *yh64 = fit_f64 ? (double *)malloc((size_t)(n_rows > 0 ? n_rows : 1) * sizeof(double)) : NULL;
+        size_t nn = (size_t)(n_rows > 0 ? n_rows : 1);
+        float *yh32 = (float *)malloc(nn * sizeof(float));
+        double *yh64 = (fit_f64 || fbound) ? (double *)malloc(nn * sizeof(double)) : NULL;
+        double *E = fbound ? (double *)malloc(nn * sizeof(double)) : NULL;
 #pragma omp for schedule(dynamic, 1)
         for (int32_t p = 0; p < n_programs; ++p) {
             const uint32_t *pn = nodes + prog_off[p];
             int64_t len = prog_off[p + 1] - prog_off[p];
             const float *pc = consts + const_off[p];
-            for (int64_t r = 0; r < n_rows; ++r)
-                yh32[r] = eval_row_f32(pn, len, pc, X, ld, r);
-            fit_f32path[p] = metric_from_values(metric, yh32, NULL, y, w, n_rows);
-            if (fit_f64) {
+            int32_t nnear = 0;
+            if (fbound) {
+                for (int64_t r = 0; r < n_rows; ++r) {
+                    int flip, near;
+                    row_analysis(pn, len, pc, X, ld, r, u, &yh32[r], &yh64[r], &E[r], &flip, &near);
+                    nnear += near;
+                }
+            } else {
                 for (int64_t r = 0; r < n_rows; ++r)
-                    yh64[r] = eval_row_f64(pn, len, pc, X, ld, r);
-                fit_f64[p] = metric_from_values(metric, NULL, yh64, y, w, n_rows);
+                    yh32[r] = eval_row_f32(pn, len, pc, X, ld, r);
+                if (fit_f64)
+                    for (int64_t r = 0; r < n_rows; ++r)
+                        yh64[r] = eval_row_f64(pn, len, pc, X, ld, r);
+            }
+            fit_f32path[p] = metric_from_values(metric, yh32, NULL, y, w, n_rows);
+            if (fit_f64) fit_f64[p] = metric_from_values(metric, NULL, yh64, y, w, n_rows);
+            if (fbound) {
+                fbound[p] = fitness_bound(metric, yh32, E, y, w, n_rows, fit_f32path[p]);
+                if (fnear) fnear[p] = nnear;
             }
         }
         free(yh32);
         free(yh64);
+        free(E);
     }
 }
 

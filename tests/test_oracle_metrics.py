@@ -133,3 +133,16 @@ def test_nonfinite_propagates():
     assert np.isnan(fit([x0_prog()], X2, y, None, "mae")[0][0])
     # Pearson with a non-finite variance reads as 0 (no correlation)
     assert fit([x0_prog()], X2, np.array([1, 2, 3], np.float32), None, "pearson")[0][0] == 0.0
+
+
+def test_pearson_constant_program_is_exactly_zero_with_weights():
+    # a constant column has zero weighted variance in exact arithmetic, so
+    # r = 0 exactly however the float64 mean rounds
+    rng = np.random.default_rng(8)
+    n = 20013
+    X = rng.normal(size=(1, n)).astype(np.float32)
+    y = rng.normal(size=n).astype(np.float32)
+    w = rng.uniform(0.5, 1.5, size=n).astype(np.float32)
+    for c in (0.1, 1.0 / 3.0, 123.456, -7.25e-3):
+        f32p, f64 = fit([const_prog(c)], X, y, w, "pearson")
+        assert f32p[0] == 0.0 and f64[0] == 0.0
