@@ -1,0 +1,300 @@
+/*
+ * gp.h -- C ABI of the MI355X (gfx950) GP population-evaluation library.
+ *
+ * The library implements the data-parallel hot path of stack-based
+ * generational genetic programming as described in "Accelerating Genetic
+ * Programming using GPUs" (arXiv 2110.11226): evaluate every program of a
+ * population of prefix lists on every row of a dataset resident in device
+ * memory (Sec. III intro, Sec. III-C3 execution step), reduce each program's
+ * row losses to its fitness (Sec. III-C3, fitness metric computation step) and
+ * select parents by tournament with a parsimony penalty (Sec. III-C1).  It
+ * also generates initial populations (Sec. II-A) and, beyond the paper, gives
+ * the derivative of fitness with respect to every program constant.
+ *
+ * Conventions for every entry point:
+ *   - Plain C types only.  Pointers documented "device" must point to device
+ *     memory on the current HIP device; "host" pointers to host memory.
+ *   - Device entry points are asynchronous on `stream` (a hipStream_t passed
+ *     as void*, NULL = the null stream).  Arguments are checked on the host
+ *     before anything is launched; a non-OK status means nothing was
+ *     launched.  Faults inside kernels surface as GP_ERR_DEVICE on a later
+ *     call or at the caller's synchronisation.
+ *   - The caller owns every buffer it passes.  Scratch space (partial sums,
+ *     work counters, orderings) is owned by the library, kept per device and
+ *     grown on demand; gp_shutdown() releases it.  Calls that share a device
+ *     share this scratch: issue them on one stream (or serialise them).
+ *   - No C++ exception crosses this boundary.  On failure the status is
+ *     returned and gp_last_error() holds a thread-local description.
+ */
+#ifndef GP_H
+#define GP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ */
+/* Program encoding (Sec. III-A: a program is its expression tree in   */
+/* Polish (prefix) order; functions have arity at most 2, Sec. III).   */
+/* A node is one uint32: opcode in bits 0-7, argument in bits 8-31.    */
+/* GP_OP_VAR's argument is a feature index; GP_OP_CONST's argument is  */
+/* a slot in the program's own constant table.                         */
+/* ------------------------------------------------------------------ */
+enum {
+    GP_OP_VAR = 0,   /* terminal: feature value X[arg][row]                       */
+    GP_OP_CONST = 1, /* terminal: constant consts[const_off[p] + arg]             */
+    GP_OP_ADD = 2,   /* a + b                                                      */
+    GP_OP_SUB = 3,   /* a - b   (a is the first argument, b the second)           */
+    GP_OP_MUL = 4,   /* a * b                                                      */
+    GP_OP_DIV = 5,   /* protected: |b| > 0.001f ? a / b : 1                        */
+    GP_OP_NEG = 6,   /* -a                                                         */
+    GP_OP_LOG = 7,   /* protected: |a| > 0.001f ? log|a| : 0                       */
+    GP_OP_SQRT = 8,  /* protected: sqrt|a|                                         */
+    GP_OP_SIN = 9,   /* sin a                                                      */
+    GP_OP_COS = 10,  /* cos a                                                      */
+    GP_OP_TAN = 11,  /* tan a                                                      */
+    GP_OP_COUNT = 12
+};
+#define GP_NODE(op, arg) ((uint32_t)(op) | ((uint32_t)(arg) << 8))
+#define GP_NODE_OP(w) ((uint32_t)(w) & 0xffu)
+#define GP_NODE_ARG(w) ((uint32_t)(w) >> 8)
+
+/* Evaluation stack depth (Sec. III-B fixed-size device stack; the paper's
+ * stack of m slots evaluates trees of depth m-1, Sec. III-C2).  A program is
+ * valid iff its right-to-left stack height never exceeds this. */
+#define GP_MAX_STACK 20
+/* Threshold of the protected operators (the float nearest 0.001). */
+#define GP_PROTECT_EPS 0.001f
+/* The nine-function set {add, sub, mul, div, neg, log, sqrt, sin, cos}. */
+#define GP_FUNCS_DEFAULT 0x7FCu
+
+/* ------------------------------------------------------------------ */
+/* Status                                                              */
+/* ------------------------------------------------------------------ */
+typedef enum {
+    GP_OK = 0,
+    GP_ERR_INVALID_ARG = -1,      /* a null pointer, a size out of range, ...      */
+    GP_ERR_INVALID_PROGRAM = -2,  /* bad opcode / feature / constant slot / arity  */
+    GP_ERR_STACK_OVERFLOW = -3,   /* stack height above GP_MAX_STACK               */
+    GP_ERR_OUT_OF_MEMORY = -4,    /* scratch allocation failed                     */
+    GP_ERR_DEVICE = -5,           /* a HIP runtime error                           */
+    GP_ERR_UNSUPPORTED = -6,      /* e.g. a metric this entry point does not have  */
+    GP_ERR_BUFFER_TOO_SMALL = -7  /* a caller buffer below the size it needs       */
+} gp_status;
+
+/* Thread-local text for the last non-OK status returned on this thread. */
+const char* gp_last_error(void);
+/* Library version string. */
+const char* gp_version(void);
+/* Release the per-device scratch of every device.  Safe to call twice. */
+void gp_shutdown(void);
+
+/* ------------------------------------------------------------------ */
+/* Fitness metrics (Sec. III-C3: weighted MAE, MSE, RMSE, logistic     */
+/* loss, Pearson and Spearman correlation).  Weights w == NULL mean 1. */
+/*   MAE  = sum w|yh-y| / sum w           (smaller is better)          */
+/*   MSE  = sum w(yh-y)^2 / sum w         (smaller is better)          */
+/*   RMSE = sqrt(MSE)                     (smaller is better)          */
+/*   LOGLOSS: yh is a logit, row loss max(yh,0) - y yh + log1p(e^-|yh|)*/
+/*            with y in {0,1}, weighted mean (smaller is better)       */
+/*   PEARSON: |weighted correlation of yh and y|, 0 when a variance is */
+/*            zero or not finite (larger is better)                    */
+/*   SPEARMAN: not provided by this version (GP_ERR_UNSUPPORTED).      */
+/* Row losses of MAE/MSE/RMSE/PEARSON are formed in float64 from the   */
+/* float32 program value; LOGLOSS's in float32; all row sums in        */
+/* float64; the result is rounded to float32.                          */
+/* ------------------------------------------------------------------ */
+typedef enum {
+    GP_METRIC_MAE = 0,
+    GP_METRIC_MSE = 1,
+    GP_METRIC_RMSE = 2,
+    GP_METRIC_LOGLOSS = 3,
+    GP_METRIC_PEARSON = 4,
+    GP_METRIC_SPEARMAN = 5
+} gp_metric;
+
+/* 1 if a larger value of the metric is better (Sec. III-C1: the criterion
+ * may favour smaller or larger values), 0 if smaller is better, -1 if the
+ * metric is unknown. */
+int gp_metric_larger_is_better(gp_metric metric);
+
+/* ------------------------------------------------------------------ */
+/* Population generation (Sec. II-A: Full, Grow, ramped half-and-half; */
+/* prefix lists are generated directly, Sec. III-A), plus an exact-    */
+/* length generator.  Host-only.  Draws come from Philox4x32-10        */
+/* (Sec. III-B) with key = seed and counter = (block, program index,   */
+/* 0, 1); one 32-bit word per decision, taken in prefix order:         */
+/*  RHH: Grow if unit(word) < 0.5 else Full; depth in                  */
+/*   [min_depth, max_depth].  Node at depth k of a tree of depth d:    */
+/*   k == d -> terminal; k == 0 < d -> function; otherwise Full ->     */
+/*   function, Grow -> uniform over (functions, features, constant).   */
+/*  EXACT_LEN: length in [min_len, max_len]; positions filled right to */
+/*   left under the stack-height rule so the program is valid; uniform */
+/*   over the allowed (features, constant, unary ops, binary ops).     */
+/* A constant is const_lo + (const_hi - const_lo) * unit(word) in      */
+/* float32.  Constants are off when const_lo > const_hi or once        */
+/* max_consts (> 0) are used.  unit(word) = (word >> 8) * 2^-24;       */
+/* a choice among n uses floor(word * n / 2^32).  Constant slots are   */
+/* numbered 0, 1, ... in prefix order.                                 */
+/* ------------------------------------------------------------------ */
+typedef enum {
+    GP_INIT_RHH = 0,
+    GP_INIT_FULL = 1,
+    GP_INIT_GROW = 2,
+    GP_INIT_EXACT_LEN = 3
+} gp_init;
+
+typedef struct {
+    int32_t n_programs;       /* >= 0                                             */
+    int32_t n_features;       /* >= 1                                             */
+    int32_t method;           /* gp_init                                          */
+    int32_t min_depth;        /* RHH / FULL / GROW: 0 <= min <= max <= 19          */
+    int32_t max_depth;
+    int32_t min_len;          /* EXACT_LEN: 1 <= min <= max <= 1<<20               */
+    int32_t max_len;
+    uint32_t function_mask;   /* bit (1 << opcode) for each enabled function      */
+    float const_lo;           /* constants ~ U[lo, hi); lo > hi disables them      */
+    float const_hi;
+    int32_t max_consts;       /* 0 = unlimited                                     */
+    uint64_t seed;
+} gp_init_params;
+
+/* Generate a population into caller-owned HOST buffers.
+ * Two-call idiom: with nodes == NULL only *total_nodes / *total_consts are
+ * written.  Otherwise nodes[nodes_cap], prog_off[n_programs+1],
+ * consts[consts_cap], const_off[n_programs+1] and len[n_programs] receive the
+ * flat population; GP_ERR_BUFFER_TOO_SMALL if a capacity is short. */
+gp_status gp_build_population(const gp_init_params* params,
+                              uint32_t* nodes, int64_t nodes_cap, int64_t* prog_off,
+                              float* consts, int64_t consts_cap, int64_t* const_off,
+                              int32_t* len, int64_t* total_nodes, int64_t* total_consts);
+
+/* Check a HOST population: every opcode known, every feature index below
+ * n_features, every constant slot below that program's constant count,
+ * exactly one value left and stack height <= GP_MAX_STACK on the
+ * right-to-left scan (Sec. III-A, III-C2).  max_height[n_programs]
+ * (nullable) receives each program's peak stack height.  On failure
+ * *bad_program (nullable) receives the first offending program. */
+gp_status gp_validate_population(const uint32_t* nodes, const int64_t* prog_off,
+                                 const int64_t* const_off, int32_t n_programs,
+                                 int32_t n_features, int32_t* max_height,
+                                 int32_t* bad_program);
+
+/* ------------------------------------------------------------------ */
+/* Device views                                                        */
+/* ------------------------------------------------------------------ */
+/* A flat population in DEVICE memory (Sec. III-A program struct, laid out
+ * as one structure of arrays instead of the paper's array of structs with
+ * nested pointers, Sec. III-D2).  Program p is nodes[prog_off[p] ..
+ * prog_off[p]+len[p]) with constants consts[const_off[p] ..).  Programs must
+ * be valid (gp_validate_population); device code does not re-check. */
+typedef struct {
+    const uint32_t* nodes;
+    const int64_t* prog_off;   /* [n_programs + 1] */
+    const float* consts;
+    const int64_t* const_off;  /* [n_programs + 1] */
+    const int32_t* len;        /* [n_programs], len[p] = prog_off[p+1]-prog_off[p] */
+    int32_t n_programs;
+    int64_t total_nodes;
+    int32_t max_len;           /* an upper bound on every len[p] (host-known) */
+} gp_population_dev;
+
+/* A dataset in DEVICE memory, feature-major (the paper's column-major
+ * layout, Sec. III intro): feature f of row r is X[f * ld + r]. */
+typedef struct {
+    const float* X;
+    int64_t ld;                /* >= n_rows */
+    int32_t n_features;
+    int64_t n_rows;            /* >= 1 */
+    const float* y;            /* [n_rows] target / binary label */
+    const float* w;            /* [n_rows] sample weights, or NULL for 1 */
+} gp_dataset_dev;
+
+/* ------------------------------------------------------------------ */
+/* Hot path                                                            */
+/* ------------------------------------------------------------------ */
+/* Program outputs (Sec. III-C3 execution step): out[p * n_rows + r] =
+ * float32 value of program p on row r (right-to-left stack evaluation,
+ * Sec. III-A).  out is DEVICE memory of n_programs * n_rows floats. */
+gp_status gp_evaluate(const gp_population_dev* pop, const gp_dataset_dev* data,
+                      float* out, void* stream);
+
+/* Fitness of every program (Sec. III-C3: execution, row loss against the
+ * broadcast target, weighted reduction per program), fused so that per-row
+ * outputs never reach memory.  fitness is DEVICE memory [n_programs]. */
+gp_status gp_fitness(const gp_population_dev* pop, const gp_dataset_dev* data,
+                     gp_metric metric, float* fitness, void* stream);
+
+/* Tournament selection (Sec. III-C1): tournament t draws tournament_size
+ * program indices with replacement, draw d being floor(word * n / 2^32) for
+ * word d%4 of Philox4x32-10(key = seed, counter = (d/4, t, generation, 0)),
+ * and keeps the one with the best adjusted fitness
+ *   raw + parsimony * len   (metric favouring smaller values), or
+ *   raw - parsimony * len   (favouring larger values)  -- Eqs. (parsimony),
+ * (fitness); float32 arithmetic with each operation rounded, the earliest draw
+ * winning ties, NaN ranked worst.  fitness, len and winners are DEVICE
+ * memory; winners[t] receives the winning program index. */
+gp_status gp_tournament(const float* fitness, const int32_t* len, int32_t n_programs,
+                        gp_metric metric, float parsimony, int32_t tournament_size,
+                        int32_t n_tournaments, uint64_t seed, uint64_t generation,
+                        int32_t* winners, void* stream);
+
+/* Derivative of fitness with respect to every program constant (not in the
+ * paper): grad_consts[const_off[p] + s] = g_p * d fitness_p / d consts[s],
+ * with g_p = grad_fitness[p] (NULL: 1).  Reverse mode over each prefix list
+ * per row, recomputing the forward values per row tile.  Local derivatives:
+ * add (1,1), sub (1,-1), mul (b,a), div (1/b, -a/b^2) where |b| > 0.001 else 0,
+ * log 1/a where |a| > 0.001 else 0, sqrt sign(a)/(2 sqrt|a|) (0 at a = 0),
+ * sin cos a, cos -sin a, tan 1 + tan^2 a, neg -1.  Metrics MAE, MSE, RMSE,
+ * LOGLOSS, PEARSON.  fitness_out [n_programs] (nullable) receives the
+ * fitness as gp_fitness would.  All pointers DEVICE memory. */
+gp_status gp_fitness_backward(const gp_population_dev* pop, const gp_dataset_dev* data,
+                              gp_metric metric, const float* grad_fitness,
+                              float* fitness_out, float* grad_consts, void* stream);
+
+/* ------------------------------------------------------------------ */
+/* Launch configuration of the evaluation kernels (gp_evaluate,        */
+/* gp_fitness).  A work item is one program on one chunk of rows; a    */
+/* wavefront evaluates 64*rows_per_lane rows per pass ("tile").        */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int32_t rows_per_lane;    /* 1, 2 or 4                                         */
+    int32_t feature_regs;     /* 0 (features read from memory), 2 or 8 (features
+                                 held in registers; needs n_features <= it)        */
+    int32_t tiles_per_chunk;  /* >= 1: rows per work item = 64*rows_per_lane*this  */
+} gp_launch_config;
+
+/* The configuration gp_evaluate / gp_fitness would use for this shape on the
+ * current device (the forced one if set, else the tuned one if cached, else
+ * the built-in heuristic). */
+gp_status gp_get_launch_config(int32_t n_features, int64_t n_rows, int32_t n_programs,
+                               gp_launch_config* out);
+
+/* Force the configuration of every later gp_evaluate / gp_fitness call in this
+ * process (all shapes); NULL returns to automatic selection.  Invalid values
+ * give GP_ERR_INVALID_ARG; a feature_regs below a dataset's n_features makes
+ * those calls fail with GP_ERR_INVALID_ARG. */
+gp_status gp_set_launch_config(const gp_launch_config* cfg);
+
+/* ------------------------------------------------------------------ */
+/* Kernel timing.  While enabled, the library brackets every launch of */
+/* its evaluation kernel (the dominant kernel of gp_evaluate and       */
+/* gp_fitness) with HIP events on the caller's stream.                 */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int64_t launches;         /* evaluation-kernel launches since enabled   */
+    double total_ms;          /* their summed event-measured duration (ms)  */
+    int64_t node_rows;        /* sum over launches of sum(len) * n_rows     */
+} gp_profile;
+
+/* enable != 0 starts (and resets) the record; 0 stops it. */
+gp_status gp_profile_enable(int enable);
+/* Waits for the recorded events, then fills *out. */
+gp_status gp_profile_read(gp_profile* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GP_H */

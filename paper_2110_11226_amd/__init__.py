@@ -1,0 +1,13 @@
+"""MI355X (gfx950) GP population evaluation: the data-parallel hot path of
+stack-based generational genetic programming (arXiv 2110.11226).
+
+The work happens in ``libgp.so`` (HIP kernels + host C++ behind the C ABI of
+``include/gp.h``); this package binds it.  Importing it without the built
+library raises ImportError.
+"""
+from ._binding import (  # noqa: F401
+    DeviceDataset, DevicePopulation, GPError, HostPopulation, build_population, evaluate,
+    fitness, fitness_backward, larger_is_better, metric_id, shutdown, tournament,
+    validate_population, version, get_launch_config, set_launch_config,
+    profile_enable, profile_read, FUNCS_DEFAULT, MAX_STACK, METRICS, LIB_PATH,
+)

@@ -1,0 +1,310 @@
+"""ctypes binding of libgp.so -- argument marshalling only.
+
+Every computation runs inside the library (host C++ for generation and
+validation, HIP kernels for evaluation, fitness, selection and gradients).
+PyTorch supplies device memory and the current stream.  If the library is
+missing this module raises at import: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgp.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'` "
+        "or `python -m paper_2110_11226_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---- constants mirrored from include/gp.h ----
+OP_VAR, OP_CONST, OP_ADD, OP_SUB, OP_MUL, OP_DIV, OP_NEG, OP_LOG, OP_SQRT, OP_SIN, OP_COS, OP_TAN = range(12)
+MAX_STACK = 20
+FUNCS_DEFAULT = 0x7FC
+METRICS = {"mae": 0, "mse": 1, "rmse": 2, "logloss": 3, "pearson": 4, "spearman": 5}
+INIT = {"rhh": 0, "full": 1, "grow": 2, "exact_len": 3}
+STATUS = {0: "GP_OK", -1: "GP_ERR_INVALID_ARG", -2: "GP_ERR_INVALID_PROGRAM",
+          -3: "GP_ERR_STACK_OVERFLOW", -4: "GP_ERR_OUT_OF_MEMORY", -5: "GP_ERR_DEVICE",
+          -6: "GP_ERR_UNSUPPORTED", -7: "GP_ERR_BUFFER_TOO_SMALL"}
+
+_vp = ctypes.c_void_p
+_i32, _i64, _u32, _u64, _f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_float
+
+
+class InitParams(ctypes.Structure):
+    _fields_ = [("n_programs", _i32), ("n_features", _i32), ("method", _i32),
+                ("min_depth", _i32), ("max_depth", _i32), ("min_len", _i32), ("max_len", _i32),
+                ("function_mask", _u32), ("const_lo", _f32), ("const_hi", _f32),
+                ("max_consts", _i32), ("seed", _u64)]
+
+
+class PopulationDev(ctypes.Structure):
+    _fields_ = [("nodes", _vp), ("prog_off", _vp), ("consts", _vp), ("const_off", _vp),
+                ("len", _vp), ("n_programs", _i32), ("total_nodes", _i64), ("max_len", _i32)]
+
+
+class DatasetDev(ctypes.Structure):
+    _fields_ = [("X", _vp), ("ld", _i64), ("n_features", _i32), ("n_rows", _i64),
+                ("y", _vp), ("w", _vp)]
+
+
+def _sig(name, args, res=ctypes.c_int):
+    f = getattr(_lib, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+_last_error = _sig("gp_last_error", [], ctypes.c_char_p)
+_version = _sig("gp_version", [], ctypes.c_char_p)
+_shutdown = _sig("gp_shutdown", [], None)
+_larger = _sig("gp_metric_larger_is_better", [ctypes.c_int])
+_build_pop = _sig("gp_build_population", [ctypes.POINTER(InitParams), _vp, _i64, _vp, _vp, _i64, _vp,
+                                          _vp, _vp, _vp])
+_validate = _sig("gp_validate_population", [_vp, _vp, _vp, _i32, _i32, _vp, _vp])
+_evaluate = _sig("gp_evaluate", [ctypes.POINTER(PopulationDev), ctypes.POINTER(DatasetDev), _vp, _vp])
+_fitness = _sig("gp_fitness", [ctypes.POINTER(PopulationDev), ctypes.POINTER(DatasetDev), ctypes.c_int,
+                               _vp, _vp])
+_tournament = _sig("gp_tournament", [_vp, _vp, _i32, ctypes.c_int, _f32, _i32, _i32, _u64, _u64, _vp, _vp])
+class LaunchConfig(ctypes.Structure):
+    _fields_ = [("rows_per_lane", _i32), ("feature_regs", _i32), ("tiles_per_chunk", _i32)]
+
+
+_get_cfg = _sig("gp_get_launch_config", [_i32, _i64, _i32, ctypes.POINTER(LaunchConfig)])
+_set_cfg = _sig("gp_set_launch_config", [ctypes.POINTER(LaunchConfig)])
+class Profile(ctypes.Structure):
+    _fields_ = [("launches", _i64), ("total_ms", ctypes.c_double), ("node_rows", _i64)]
+
+
+_prof_enable = _sig("gp_profile_enable", [ctypes.c_int])
+_prof_read = _sig("gp_profile_read", [ctypes.POINTER(Profile)])
+_backward = _sig("gp_fitness_backward", [ctypes.POINTER(PopulationDev), ctypes.POINTER(DatasetDev),
+                                         ctypes.c_int, _vp, _vp, _vp, _vp])
+
+EXPORTED = ["gp_last_error", "gp_version", "gp_shutdown", "gp_metric_larger_is_better",
+            "gp_build_population", "gp_validate_population", "gp_evaluate", "gp_fitness",
+            "gp_tournament", "gp_fitness_backward", "gp_get_launch_config", "gp_set_launch_config",
+            "gp_profile_enable", "gp_profile_read"]
+
+
+def profile_enable(on=True):
+    _check(_prof_enable(1 if on else 0), "gp_profile_enable")
+
+
+def profile_read():
+    """(launches, total_ms, node_rows) of the evaluation kernel since enabled."""
+    p = Profile()
+    _check(_prof_read(ctypes.byref(p)), "gp_profile_read")
+    return int(p.launches), float(p.total_ms), int(p.node_rows)
+
+
+def get_launch_config(n_features, n_rows, n_programs):
+    c = LaunchConfig()
+    _check(_get_cfg(n_features, n_rows, n_programs, ctypes.byref(c)), "gp_get_launch_config")
+    return (c.rows_per_lane, c.feature_regs, c.tiles_per_chunk)
+
+
+def set_launch_config(cfg=None):
+    """cfg = (rows_per_lane, feature_regs, tiles_per_chunk) or None for automatic."""
+    if cfg is None:
+        _check(_set_cfg(None), "gp_set_launch_config")
+    else:
+        c = LaunchConfig(*[int(v) for v in cfg])
+        _check(_set_cfg(ctypes.byref(c)), "gp_set_launch_config")
+
+
+class GPError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise GPError(rc, where)
+
+
+def version() -> str:
+    return _version().decode()
+
+
+def shutdown():
+    _shutdown()
+
+
+def metric_id(metric) -> int:
+    return METRICS[metric] if isinstance(metric, str) else int(metric)
+
+
+def larger_is_better(metric) -> bool:
+    return bool(_larger(metric_id(metric)))
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data_as(_vp)
+
+
+# ---------------------------------------------------------------------------
+# Host population
+# ---------------------------------------------------------------------------
+@dataclass
+class HostPopulation:
+    nodes: np.ndarray      # uint32
+    prog_off: np.ndarray   # int64 [P+1]
+    consts: np.ndarray     # float32
+    const_off: np.ndarray  # int64 [P+1]
+    length: np.ndarray     # int32 [P]
+
+    @property
+    def n_programs(self) -> int:
+        return int(self.length.shape[0])
+
+
+def build_population(n_programs, n_features, method="rhh", min_depth=2, max_depth=6, min_len=1,
+                     max_len=200, function_mask=FUNCS_DEFAULT, const_lo=-1.0, const_hi=1.0,
+                     max_consts=0, seed=0) -> HostPopulation:
+    prm = InitParams(n_programs, n_features, INIT[method] if isinstance(method, str) else int(method),
+                     min_depth, max_depth, min_len, max_len, function_mask, const_lo, const_hi,
+                     max_consts, seed)
+    tn = np.zeros(1, np.int64)
+    tc = np.zeros(1, np.int64)
+    _check(_build_pop(ctypes.byref(prm), None, 0, None, None, 0, None, None, _np_ptr(tn), _np_ptr(tc)),
+           "gp_build_population")
+    nodes = np.zeros(max(int(tn[0]), 1), np.uint32)
+    consts = np.zeros(max(int(tc[0]), 1), np.float32)
+    po = np.zeros(n_programs + 1, np.int64)
+    co = np.zeros(n_programs + 1, np.int64)
+    ln = np.zeros(max(n_programs, 1), np.int32)
+    _check(_build_pop(ctypes.byref(prm), _np_ptr(nodes), nodes.shape[0], _np_ptr(po), _np_ptr(consts),
+                      consts.shape[0], _np_ptr(co), _np_ptr(ln), _np_ptr(tn), _np_ptr(tc)),
+           "gp_build_population")
+    return HostPopulation(nodes[:int(tn[0])], po, consts[:int(tc[0])], co, ln[:n_programs])
+
+
+def validate_population(pop: HostPopulation, n_features: int):
+    """Returns per-program peak stack heights; raises GPError if invalid."""
+    P = pop.n_programs
+    h = np.zeros(max(P, 1), np.int32)
+    bad = np.full(1, -1, np.int32)
+    nodes = np.ascontiguousarray(pop.nodes, np.uint32)
+    rc = _validate(_np_ptr(nodes), _np_ptr(np.ascontiguousarray(pop.prog_off, np.int64)),
+                   _np_ptr(np.ascontiguousarray(pop.const_off, np.int64)), P, n_features,
+                   _np_ptr(h), _np_ptr(bad))
+    _check(rc, "gp_validate_population")
+    return h[:P]
+
+
+# ---------------------------------------------------------------------------
+# Device views (torch tensors on the current HIP device)
+# ---------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _tptr(t):
+    return None if t is None else _vp(t.data_ptr())
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return _vp(s.cuda_stream)
+
+
+class DevicePopulation:
+    """A flat population resident on the device (one contiguous upload)."""
+
+    def __init__(self, host: HostPopulation, device="cuda", validate=True, n_features=None):
+        torch = _torch()
+        if validate:
+            if n_features is None:
+                raise ValueError("n_features is needed to validate")
+            validate_population(host, n_features)
+        self.host = host
+        self.nodes = torch.from_numpy(np.ascontiguousarray(host.nodes, np.uint32).view(np.int32)).to(device)
+        self.prog_off = torch.from_numpy(np.ascontiguousarray(host.prog_off, np.int64)).to(device)
+        c = host.consts if host.consts.shape[0] else np.zeros(1, np.float32)
+        self.consts = torch.from_numpy(np.ascontiguousarray(c, np.float32)).to(device)
+        self.const_off = torch.from_numpy(np.ascontiguousarray(host.const_off, np.int64)).to(device)
+        self.length = torch.from_numpy(np.ascontiguousarray(host.length, np.int32)).to(device)
+        self.n_programs = host.n_programs
+        self.n_consts = int(host.consts.shape[0])
+        self.max_len = int(host.length.max()) if self.n_programs else 0
+        self.view = self.make_view(self.consts)
+
+    def make_view(self, consts):
+        return PopulationDev(self.nodes.data_ptr(), self.prog_off.data_ptr(), consts.data_ptr(),
+                             self.const_off.data_ptr(), self.length.data_ptr(), self.n_programs,
+                             int(self.host.nodes.shape[0]), self.max_len)
+
+
+class DeviceDataset:
+    """Feature-major X[f, r], target y[r], optional weights w[r] on the device."""
+
+    def __init__(self, X, y=None, w=None, device="cuda"):
+        torch = _torch()
+
+        def dev(a):
+            if a is None:
+                return None
+            t = a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(a, np.float32))
+            return t.to(device=device, dtype=torch.float32).contiguous()
+
+        self.X = dev(X)
+        self.y = dev(y)
+        self.w = dev(w)
+        self.n_features, self.n_rows = int(self.X.shape[0]), int(self.X.shape[1])
+        self.view = DatasetDev(self.X.data_ptr(), self.n_rows, self.n_features, self.n_rows,
+                               self.y.data_ptr() if self.y is not None else None,
+                               self.w.data_ptr() if self.w is not None else None)
+
+
+def evaluate(pop: DevicePopulation, data: DeviceDataset, out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty((pop.n_programs, data.n_rows), dtype=torch.float32, device=data.X.device)
+    _check(_evaluate(ctypes.byref(pop.view), ctypes.byref(data.view), _tptr(out), _stream(stream)),
+           "gp_evaluate")
+    return out
+
+
+def fitness(pop: DevicePopulation, data: DeviceDataset, metric="mse", out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(pop.n_programs, dtype=torch.float32, device=data.X.device)
+    _check(_fitness(ctypes.byref(pop.view), ctypes.byref(data.view), metric_id(metric), _tptr(out),
+                    _stream(stream)), "gp_fitness")
+    return out
+
+
+def tournament(fit, length, metric="mse", parsimony=0.0, tournament_size=20, n_tournaments=None,
+               seed=0, generation=0, out=None, stream=None):
+    torch = _torch()
+    P = int(fit.shape[0])
+    T = P if n_tournaments is None else int(n_tournaments)
+    if out is None:
+        out = torch.empty(max(T, 1), dtype=torch.int32, device=fit.device)
+    _check(_tournament(_tptr(fit), _tptr(length), P, metric_id(metric), float(parsimony),
+                       int(tournament_size), T, int(seed), int(generation), _tptr(out), _stream(stream)),
+           "gp_tournament")
+    return out[:T]
+
+
+def fitness_backward(pop: DevicePopulation, data: DeviceDataset, metric="mse", grad_fitness=None,
+                     consts=None, fitness_out=None, grad_out=None, stream=None):
+    torch = _torch()
+    c = pop.consts if consts is None else consts
+    view = pop.view if consts is None else pop.make_view(c)
+    if grad_out is None:
+        grad_out = torch.zeros(max(pop.n_consts, 1), dtype=torch.float32, device=data.X.device)
+    _check(_backward(ctypes.byref(view), ctypes.byref(data.view), metric_id(metric), _tptr(grad_fitness),
+                     _tptr(fitness_out), _tptr(grad_out), _stream(stream)), "gp_fitness_backward")
+    return grad_out[:pop.n_consts]

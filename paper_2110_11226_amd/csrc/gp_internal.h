@@ -1,0 +1,66 @@
+// gp_internal.h -- declarations shared by the library's host and device
+// translation units (not part of the public ABI).
+#pragma once
+
+#include <cstdint>
+#include <string>
+
+#include "gp.h"
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define GP_HD __host__ __device__ __forceinline__
+#else
+#define GP_HD inline
+#endif
+
+namespace gp {
+
+// Arity of every opcode (Sec. III: functions of arity at most two); -1 for an
+// unknown opcode.
+GP_HD int arity(uint32_t op) {
+    return op <= GP_OP_CONST ? 0 : (op <= GP_OP_DIV ? 2 : (op < GP_OP_COUNT ? 1 : -1));
+}
+
+// Philox4x32-10 (Salmon et al., SC'11), the counter-based generator of
+// Sec. III-B.  One call maps a 128-bit counter and a 64-bit key to four
+// 32-bit words through ten rounds of two 32x32->64 multiplies, with the key
+// advanced by the golden-ratio Weyl increments between rounds.
+struct Philox4 {
+    uint32_t v[4];
+};
+
+GP_HD Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint64_t seed) {
+    uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t m0 = static_cast<uint64_t>(0xD2511F53u) * c0;
+        const uint64_t m1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+        const uint32_t n0 = static_cast<uint32_t>(m1 >> 32) ^ c1 ^ k0;
+        const uint32_t n1 = static_cast<uint32_t>(m1);
+        const uint32_t n2 = static_cast<uint32_t>(m0 >> 32) ^ c3 ^ k1;
+        const uint32_t n3 = static_cast<uint32_t>(m0);
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Philox4{{c0, c1, c2, c3}};
+}
+
+// Stream tags of the counter's fourth word.
+enum : uint32_t { kStreamTournament = 0, kStreamInit = 1, kStreamMutation = 2 };
+
+// floor(word * n / 2^32): a draw in [0, n).
+GP_HD uint32_t below(uint32_t word, uint32_t n) {
+    return static_cast<uint32_t>((static_cast<uint64_t>(word) * n) >> 32);
+}
+// (word >> 8) * 2^-24: a float in [0, 1).
+GP_HD float unit(uint32_t word) {
+    return static_cast<float>(word >> 8) * (1.0f / 16777216.0f);
+}
+
+// Thread-local error text behind gp_last_error().
+gp_status fail(gp_status st, const std::string& msg);
+gp_status ok();
+
+}  // namespace gp

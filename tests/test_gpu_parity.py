@@ -1,0 +1,288 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Shapes follow the paper's workloads: the Pagie polynomial on x, y ~ U[-5,5]
+(Sec. IV-A), ramped-half-and-half and exact-length populations, a 28-feature
+classification set (the Higgs column count, Sec. IV-B).  Sizes span several
+tiles and chunks with ragged tails; full-size cases are checked on sampled
+programs and rows.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from _parity import check_fitness, check_rows, to_oracle
+
+pytestmark = pytest.mark.gpu
+
+NT = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def gp():
+    import torch
+    import paper_2110_11226_amd as gp
+    torch.cuda.set_device(0)
+    yield gp
+    gp.set_launch_config(None)
+
+
+def run_eval(gp, host, X, F, cfg=None):
+    import torch
+    gp.set_launch_config(cfg)
+    try:
+        pop = gp.DevicePopulation(host, n_features=F)
+        data = gp.DeviceDataset(X)
+        out = gp.evaluate(pop, data)
+        torch.cuda.synchronize()
+        return out.cpu().numpy()
+    finally:
+        gp.set_launch_config(None)
+
+
+def all_pairs(P, N):
+    prog = np.repeat(np.arange(P, dtype=np.int32), N)
+    row = np.tile(np.arange(N, dtype=np.int64), P)
+    return prog, row
+
+
+CONFIGS = [None, (1, 0, 1), (1, 2, 3), (2, 2, 2), (2, 8, 1), (4, 0, 5), (4, 2, 1), (4, 8, 2)]
+
+
+@pytest.mark.parametrize("cfg", CONFIGS)
+def test_evaluate_pagie_rhh_all_launch_configs(gp, cfg):
+    N = 4096 + 77                                   # ragged tail
+    X, _ = synth.pagie(N, seed=11227)
+    host = gp.build_population(256, 2, "rhh", min_depth=2, max_depth=6, seed=2111)
+    got = run_eval(gp, host, X, 2, cfg)
+    ra = oracle.evaluate_pairs(to_oracle(host), X, *all_pairs(256, N), n_threads=NT)
+    n_ok, n_ill = check_rows(got, ra, f"rhh cfg={cfg}")
+    print(f"cfg={cfg}: {n_ok} rows checked, {n_ill} ill-conditioned")
+    assert n_ok > 0.9 * got.size
+
+
+@pytest.mark.parametrize("cfg", [None, (1, 2, 1), (4, 2, 3), (4, 0, 2)])
+def test_evaluate_exact_length_up_to_200(gp, cfg):
+    N = 3000
+    X, _ = synth.pagie(N, seed=5)
+    host = gp.build_population(96, 2, "exact_len", min_len=1, max_len=200, seed=2113)
+    got = run_eval(gp, host, X, 2, cfg)
+    ra = oracle.evaluate_pairs(to_oracle(host), X, *all_pairs(96, N), n_threads=NT)
+    n_ok, n_ill = check_rows(got, ra, f"exact cfg={cfg}")
+    print(f"cfg={cfg}: {n_ok} checked, {n_ill} ill-conditioned")
+
+
+def test_evaluate_correctly_rounded_ops_bit_exact(gp):
+    # add, sub, mul, protected div, neg, protected sqrt are correctly rounded
+    # on both sides: every row must be bit-identical, none excluded
+    fmask = sum(1 << o for o in (oracle.ADD, oracle.SUB, oracle.MUL, oracle.DIV, oracle.NEG,
+                                 oracle.SQRT))
+    N = 5000
+    X, _ = synth.diff_target(N, seed=9)
+    host = gp.build_population(128, 8, "exact_len", min_len=1, max_len=200, function_mask=fmask,
+                               seed=77)
+    for cfg in (None, (1, 8, 2), (4, 0, 1), (2, 8, 7)):
+        got = run_eval(gp, host, X, 8, cfg)
+        ref = oracle.evaluate_f32(to_oracle(host), X, n_threads=NT)
+        same = (got.view(np.uint32) == ref.view(np.uint32)) | (np.isnan(got) & np.isnan(ref))
+        assert same.all(), (cfg, int((~same).sum()))
+
+
+def test_evaluate_28_features(gp):
+    N = 2500
+    X, _ = synth.higgs_like(N, seed=3)
+    host = gp.build_population(64, 28, "exact_len", min_len=1, max_len=200, seed=2114)
+    got = run_eval(gp, host, X, 28, None)
+    ra = oracle.evaluate_pairs(to_oracle(host), X, *all_pairs(64, N), n_threads=NT)
+    check_rows(got, ra, "F=28")
+    with pytest.raises(gp.GPError, match="INVALID_ARG"):
+        run_eval(gp, host, X, 28, (4, 8, 1))    # 28 features do not fit 8 registers
+
+
+def test_evaluate_edge_shapes(gp):
+    N_list = [1, 2, 63, 64, 65, 255, 257, 1025]
+    progs = [([oracle.node(oracle.VAR, 1)], []), ([oracle.node(oracle.CONST, 0)], [0.375]),
+             ([oracle.node(oracle.ADD)] * 19 + [oracle.node(oracle.VAR, 0)] * 20, []),   # stack 20
+             ([oracle.node(oracle.NEG), oracle.node(oracle.SIN), oracle.node(oracle.VAR, 0)], [])]
+    op = oracle.from_programs(progs)
+    host = gp.HostPopulation(op.nodes, op.prog_off, op.consts, op.const_off, op.length)
+    for N in N_list:
+        X, _ = synth.pagie(N, seed=N)
+        X[0, 0] = np.nan
+        if N > 2:
+            X[1, 1] = np.inf
+        for cfg in (None, (1, 2, 1), (4, 0, 1)):
+            got = run_eval(gp, host, X, 2, cfg)
+            ra = oracle.evaluate_pairs(op, X, *all_pairs(4, N))
+            check_rows(got, ra, f"N={N} cfg={cfg}")
+
+
+def _fitness_case(gp, host, X, y, w, metric, F, cfg=None):
+    import torch
+    gp.set_launch_config(cfg)
+    try:
+        pop = gp.DevicePopulation(host, n_features=F)
+        data = gp.DeviceDataset(X, y, w)
+        fit = gp.fitness(pop, data, metric)
+        torch.cuda.synchronize()
+        got = fit.cpu().numpy()
+    finally:
+        gp.set_launch_config(None)
+    ref = oracle.fitness(to_oracle(host), X, y, w, metric, n_threads=NT, with_bound=True)
+    return (got,) + tuple(ref)
+
+
+@pytest.mark.parametrize("metric", ["mae", "mse", "rmse", "logloss", "pearson"])
+@pytest.mark.parametrize("weighted", [False, True])
+def test_fitness_all_metrics(gp, metric, weighted):
+    N = 20000 + 13
+    if metric == "logloss":
+        X, y = synth.higgs_like(N, seed=4)
+        X = np.ascontiguousarray(X[:8])
+        F = 8
+    else:
+        X, y = synth.pagie(N, seed=11228)
+        F = 2
+    w = synth.weights(N) if weighted else None
+    host = gp.build_population(200, F, "exact_len", min_len=1, max_len=200, seed=31)
+    for cfg in (None, (1, 8, 4), (4, 0, 3)):
+        got, *ref = _fitness_case(gp, host, X, y, w, metric, F, cfg)
+        n_ok, n_ill, e64 = check_fitness(got, *ref, f"{metric} w={weighted} cfg={cfg}")
+        print(f"{metric} weighted={weighted} cfg={cfg}: {n_ok} ok, {n_ill} ill, max rel err vs f64 {e64:.2e}")
+        assert n_ok >= 150
+
+
+def test_fitness_rhh_pagie_small_config(gp):
+    N = 4096
+    X, y = synth.pagie(N, seed=11227)
+    host = gp.build_population(256, 2, "rhh", min_depth=2, max_depth=6, seed=2111)
+    got, *ref = _fitness_case(gp, host, X, y, None, "mse", 2)
+    n_ok, n_ill, e64 = check_fitness(got, *ref, "pagie-4k")
+    assert n_ill <= 5
+
+
+def test_fitness_edge_cases(gp):
+    # single row, single program, constant programs, zero weights on half
+    progs = [([oracle.node(oracle.CONST, 0)], [0.5]), ([oracle.node(oracle.VAR, 0)], []),
+             ([oracle.node(oracle.SUB), oracle.node(oracle.VAR, 0), oracle.node(oracle.VAR, 0)], [])]
+    op = oracle.from_programs(progs)
+    host = gp.HostPopulation(op.nodes, op.prog_off, op.consts, op.const_off, op.length)
+    for N in (1, 3, 300):
+        X, y = synth.pagie(N, seed=N + 100)
+        w = synth.weights(N)
+        w[::2] = 0.0
+        if N == 1:
+            w[0] = 1.0
+        for metric in ("mse", "mae", "pearson", "rmse"):
+            got, *ref = _fitness_case(gp, host, X, y, w, metric, 2)
+            check_fitness(got, *ref, f"edge N={N} {metric}")
+
+
+def test_fitness_nonfinite_propagates(gp):
+    N = 1000
+    X, y = synth.pagie(N, seed=1)
+    X[0, 10] = np.inf
+    X[1, 20] = np.nan
+    progs = [([oracle.node(oracle.VAR, 0)], []), ([oracle.node(oracle.VAR, 1)], []),
+             ([oracle.node(oracle.SIN), oracle.node(oracle.VAR, 0)], [])]
+    op = oracle.from_programs(progs)
+    host = gp.HostPopulation(op.nodes, op.prog_off, op.consts, op.const_off, op.length)
+    for metric in ("mse", "mae", "pearson"):
+        got, *ref = _fitness_case(gp, host, X, y, None, metric, 2)
+        check_fitness(got, *ref, f"nonfinite {metric}")
+    got, *_ = _fitness_case(gp, host, X, y, None, "mse", 2)
+    assert np.isinf(got[0]) and np.isnan(got[1]) and np.isnan(got[2])
+
+
+@pytest.mark.parametrize("metric,parsimony", [("mse", 0.0), ("mse", 1e-3), ("mse", 1e-2),
+                                              ("pearson", 1e-2), ("logloss", 1e-3)])
+def test_tournament_bit_exact(gp, metric, parsimony):
+    import torch
+    P = 1000
+    rng = np.random.default_rng(3)
+    fit = np.round(rng.normal(size=P), 2).astype(np.float32)     # many ties
+    fit[rng.integers(0, P, 20)] = np.nan
+    fit[rng.integers(0, P, 5)] = np.inf
+    ln = rng.integers(1, 201, size=P).astype(np.int32)
+    T = 1713
+    for seed, gen in ((7, 0), (7, 1), (123456789012345, 19)):
+        w = gp.tournament(torch.from_numpy(fit).cuda(), torch.from_numpy(ln).cuda(), metric,
+                          parsimony, 20, T, seed, gen)
+        ref = oracle.tournament(fit, ln, gp.larger_is_better(metric), parsimony, 20, T, seed, gen)
+        assert np.array_equal(w.cpu().numpy(), ref)
+    for k in (1, 2, 3, 4, 5, 64):
+        w = gp.tournament(torch.from_numpy(fit).cuda(), torch.from_numpy(ln).cuda(), metric,
+                          parsimony, k, 333, 5, 2)
+        ref = oracle.tournament(fit, ln, gp.larger_is_better(metric), parsimony, k, 333, 5, 2)
+        assert np.array_equal(w.cpu().numpy(), ref)
+
+
+def test_tournament_on_gpu_fitness(gp):
+    import torch
+    N = 4096
+    X, y = synth.pagie(N, seed=11227)
+    host = gp.build_population(256, 2, "rhh", min_depth=2, max_depth=6, seed=2111)
+    pop = gp.DevicePopulation(host, n_features=2)
+    data = gp.DeviceDataset(X, y)
+    fit = gp.fitness(pop, data, "mse")
+    win = gp.tournament(fit, pop.length, "mse", 0.01, 20, 256, 99, 0)
+    torch.cuda.synchronize()
+    ref = oracle.tournament(fit.cpu().numpy(), host.length, False, 0.01, 20, 256, 99, 0)
+    assert np.array_equal(win.cpu().numpy(), ref)
+
+
+def test_full_size_pagie_16m_sampled(gp):
+    """The 16,777,216-row Pagie workload, 4096 exact-length programs, at the
+    launch configuration the benchmark uses: fitness of sampled programs over
+    every row, and sampled per-row outputs."""
+    import torch
+    N = 16_777_216
+    X, y = synth.pagie(N, seed=11229)
+    host = gp.build_population(4096, 2, "exact_len", min_len=1, max_len=200, seed=2113)
+    pop = gp.DevicePopulation(host, n_features=2)
+    data = gp.DeviceDataset(X, y)
+    fit = gp.fitness(pop, data, "mse")
+    torch.cuda.synchronize()
+    got = fit.cpu().numpy()
+    assert got.shape == (4096,)
+    rng = np.random.default_rng(0)
+    order = np.argsort(-host.length, kind="stable")
+    sample = np.unique(np.concatenate([order[:2], order[-2:], rng.integers(0, 4096, 2)]))
+    sub = [(host.nodes[host.prog_off[p]:host.prog_off[p + 1]],
+            host.consts[host.const_off[p]:host.const_off[p + 1]]) for p in sample]
+    osub = oracle.from_programs(sub)
+    ref = oracle.fitness(osub, X, y, None, "mse", n_threads=NT, with_bound=True)
+    n_ok, n_ill, _ = check_fitness(got[sample], *ref, "pagie-16M sampled")
+    print(f"pagie-16M: {n_ok} sampled programs checked, {n_ill} ill-conditioned")
+    # per-row outputs of the sampled programs on sampled rows
+    hsub = gp.HostPopulation(osub.nodes, osub.prog_off, osub.consts, osub.const_off, osub.length)
+    dsub = gp.DevicePopulation(hsub, n_features=2)
+    out = gp.evaluate(dsub, gp.DeviceDataset(data.X))
+    torch.cuda.synchronize()
+    rows = np.unique(np.concatenate([rng.integers(0, N, 4000), [0, N - 1]])).astype(np.int64)
+    prog = np.repeat(np.arange(len(sample), dtype=np.int32), len(rows))
+    rr = np.tile(rows, len(sample))
+    ra = oracle.evaluate_pairs(osub, X, prog, rr, n_threads=NT)
+    check_rows(out.cpu().numpy()[prog, rr], ra, "pagie-16M rows")
+
+
+def test_full_size_higgs_like_logloss_sampled(gp):
+    import torch
+    N = 11_000_000
+    X, y = synth.higgs_like(N, seed=11230)
+    host = gp.build_population(2000, 28, "exact_len", min_len=1, max_len=200, seed=2114)
+    pop = gp.DevicePopulation(host, n_features=28)
+    data = gp.DeviceDataset(X, y)
+    fit = gp.fitness(pop, data, "logloss")
+    torch.cuda.synchronize()
+    got = fit.cpu().numpy()
+    rng = np.random.default_rng(1)
+    sample = np.unique(rng.integers(0, 2000, 4))
+    sub = [(host.nodes[host.prog_off[p]:host.prog_off[p + 1]],
+            host.consts[host.const_off[p]:host.const_off[p + 1]]) for p in sample]
+    ref = oracle.fitness(oracle.from_programs(sub), X, y, None, "logloss", n_threads=NT,
+                         with_bound=True)
+    n_ok, n_ill, _ = check_fitness(got[sample], *ref, "higgs-like sampled")
+    print(f"higgs-like: {n_ok} sampled programs checked, {n_ill} ill-conditioned")

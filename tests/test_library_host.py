@@ -1,0 +1,143 @@
+"""CPU tests of the library's host side: the C ABI loads and exports every
+symbol include/gp.h declares, population generation is bit-exact with the
+oracle's, validation agrees with the oracle's scan, and host-checked argument
+errors are reported before anything reaches the GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def gp():
+    import paper_2110_11226_amd as gp
+    return gp
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "gp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(gp_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol(gp):
+    lib = ctypes.CDLL(gp.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert gp.version().startswith("gp-mi355x")
+
+
+CASES = [
+    dict(method="rhh", min_depth=2, max_depth=6),
+    dict(method="rhh", min_depth=0, max_depth=3),
+    dict(method="full", min_depth=1, max_depth=8),
+    dict(method="grow", min_depth=2, max_depth=10),
+    dict(method="exact_len", min_len=1, max_len=200),
+    dict(method="exact_len", min_len=1, max_len=200, max_consts=16),
+    dict(method="exact_len", min_len=5, max_len=60,
+         fmask=sum(1 << o for o in (oracle.ADD, oracle.SUB, oracle.MUL))),
+    dict(method="rhh", min_depth=2, max_depth=5, const_lo=1.0, const_hi=0.0),
+    dict(method="exact_len", min_len=30, max_len=30,
+         fmask=sum(1 << o for o in (oracle.ADD, oracle.MUL, oracle.SIN, oracle.TAN))),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("n_features", [1, 2, 28])
+def test_build_population_bit_exact_with_oracle(gp, case, n_features):
+    kw = dict(case)
+    fmask = kw.pop("fmask", oracle.DEFAULT_FMASK)
+    a = gp.build_population(300, n_features, function_mask=fmask, seed=2024, **kw)
+    b = oracle.build_population(300, n_features, fmask=fmask, seed=2024, **kw)
+    assert np.array_equal(a.nodes, b.nodes)
+    assert np.array_equal(a.consts.view(np.uint32), b.consts.view(np.uint32))
+    assert np.array_equal(a.prog_off, b.prog_off)
+    assert np.array_equal(a.const_off, b.const_off)
+    assert np.array_equal(a.length, b.length)
+
+
+def test_build_population_errors(gp):
+    with pytest.raises(gp.GPError, match="INVALID_ARG"):
+        gp.build_population(10, 2, "rhh", min_depth=3, max_depth=2)
+    with pytest.raises(gp.GPError, match="INVALID_ARG"):
+        gp.build_population(10, 2, "exact_len", min_len=0)
+    with pytest.raises(gp.GPError, match="INVALID_ARG"):
+        gp.build_population(10, 0, "rhh")
+    with pytest.raises(gp.GPError, match="INVALID_ARG"):
+        gp.build_population(10, 2, "rhh", function_mask=1 << 13)
+
+
+def test_validate_matches_oracle_on_mutated_programs(gp):
+    rng = np.random.default_rng(0)
+    base = gp.build_population(400, 3, "exact_len", min_len=1, max_len=60, max_consts=4, seed=5)
+    nodes = base.nodes.copy()
+    # corrupt one node in about half the programs
+    for p in range(base.n_programs):
+        if rng.random() < 0.5:
+            i = int(base.prog_off[p] + rng.integers(0, base.length[p]))
+            op = int(rng.integers(0, 13))
+            arg = int(rng.integers(0, 6))
+            nodes[i] = op | (arg << 8)
+    expected_codes = {1: -2, 2: -2, 3: -3, 4: -2, 5: -2, 6: -2}
+    for p in range(base.n_programs):
+        a, b = int(base.prog_off[p]), int(base.prog_off[p + 1])
+        one = gp.HostPopulation(nodes[a:b], np.array([0, b - a], np.int64),
+                                base.consts[base.const_off[p]:base.const_off[p + 1]],
+                                np.array([0, base.const_off[p + 1] - base.const_off[p]], np.int64),
+                                np.array([b - a], np.int32))
+        rc, h = oracle.check_program(nodes[a:b], 3, int(base.const_off[p + 1] - base.const_off[p]))
+        if rc == 0:
+            assert gp.validate_population(one, 3)[0] == h
+        else:
+            with pytest.raises(gp.GPError) as ei:
+                gp.validate_population(one, 3)
+            assert ei.value.status == expected_codes[rc]
+
+
+def test_validate_stack_limit(gp):
+    def prog(nodes):
+        n = len(nodes)
+        return gp.HostPopulation(np.array(nodes, np.uint32), np.array([0, n], np.int64),
+                                 np.zeros(0, np.float32), np.array([0, 0], np.int64),
+                                 np.array([n], np.int32))
+    ok = [oracle.node(oracle.ADD)] * 19 + [oracle.node(oracle.VAR, 0)] * 20
+    assert gp.validate_population(prog(ok), 1)[0] == 20
+    over = [oracle.node(oracle.ADD)] * 20 + [oracle.node(oracle.VAR, 0)] * 21
+    with pytest.raises(gp.GPError, match="STACK_OVERFLOW"):
+        gp.validate_population(prog(over), 1)
+
+
+def test_device_entry_points_reject_bad_arguments_before_launch(gp):
+    from paper_2110_11226_amd import _binding as B
+    # NULL population / dataset / outputs are rejected on the host
+    assert B._fitness(None, None, 1, None, None) == -1
+    assert B._evaluate(None, None, None, None) == -1
+    pv = B.PopulationDev(None, None, None, None, None, 3, 10, 5)
+    dv = B.DatasetDev(None, 0, 2, 0, None, None)
+    assert B._fitness(ctypes.byref(pv), ctypes.byref(dv), 1, None, None) == -1
+    # tournament argument checks
+    assert B._tournament(None, None, 0, 1, 0.0, 20, 10, 0, 0, None, None) == -1
+    assert B._tournament(None, None, 10, 1, 0.0, 0, 10, 0, 0, None, None) == -1
+    assert B._tournament(None, None, 10, 9, 0.0, 2, 10, 0, 0, None, None) == -1
+    assert B._tournament(None, None, 10, 1, 0.0, 2, 10, 0, 2 ** 33, None, None) == -1
+    # unsupported metric
+    assert B._fitness(ctypes.byref(pv), ctypes.byref(dv), 5, None, None) == -1
+    with pytest.raises(gp.GPError, match="INVALID_ARG"):
+        gp.set_launch_config((3, 0, 1))
+    with pytest.raises(gp.GPError, match="INVALID_ARG"):
+        gp.set_launch_config((4, 5, 1))
+    gp.set_launch_config(None)
+
+
+def test_metric_direction(gp):
+    assert [gp.larger_is_better(m) for m in ("mae", "mse", "rmse", "logloss", "pearson", "spearman")] == \
+        [False, False, False, False, True, True]
