@@ -6,11 +6,18 @@
 // against the target is formed in registers, and the losses are summed per
 // program.  The paper launches one thread per (program, row) and materialises
 // the (rows x programs) prediction matrix before two library reductions; here
-// one persistent launch walks (row chunk, program) work items taken from an
-// atomic counter, the 64 lanes of a wavefront evaluate the same program on 64
-// different rows so every node is a wave-uniform (scalar) branch, each lane
-// carries R rows, and only one float64 partial per (program, chunk) leaves the
-// kernel.  A second small kernel merges the partials in a fixed order.
+//   1. k_compile rewrites each prefix list once per call into its execution
+//      order as two-word instructions (the stack-schedule pre-pass): a
+//      terminal whose parent is a binary function and which is that
+//      function's first operand is fused with it, and a constant's value
+//      travels inside its instruction;
+//   2. one persistent launch of k_eval walks (row chunk, program) work items
+//      taken from an atomic counter; the 64 lanes of a wavefront run the same
+//      program on 64 different rows, so every instruction is a wave-uniform
+//      (scalar) branch, and each lane carries R rows to spread the scalar
+//      dispatch over more vector work; the row loss is formed in registers
+//      and only one float64 partial per (program, chunk) leaves the kernel;
+//   3. k_finalize merges the partials in a fixed order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -52,6 +59,13 @@ struct DataView {
     const float* w;
 };
 
+// Compiled programs: program p's instructions are code[prog_off[p] ..
+// prog_off[p] + clen[p]) (clen[p] <= len[p]), in execution order.
+struct CodeView {
+    const uint2* code;
+    const int32_t* clen;
+};
+
 // Work decomposition: rows are split into n_chunks chunks of `chunk` rows
 // (a multiple of the 64*R rows one wavefront covers per tile).  Work item
 // it = chunk_index * P + k covers program order[k] on that chunk; programs are
@@ -63,6 +77,21 @@ struct Sched {
     const int32_t* order;
     uint32_t* counter;
 };
+
+// ---------------------------------------------------------------------------
+// Instruction format (word x; word y holds a constant's float bits):
+//   bits 0-1  class: kPush (push a terminal), kFold (terminal fused with the
+//             binary function whose first operand it is; the current top is
+//             the second operand), kBin (binary: top op next-below), kUn
+//   bits 2-4  function: binary ADD..DIV as 0..3, unary NEG..TAN as 0..5
+//   bit 5     the terminal is a constant (value in y) rather than a feature
+//   bits 8-31 feature index
+// ---------------------------------------------------------------------------
+enum : uint32_t { kPush = 0, kFold = 1, kBin = 2, kUn = 3 };
+
+GP_HD uint32_t enc(uint32_t cls, uint32_t fn, uint32_t is_const, uint32_t arg) {
+    return cls | (fn << 2) | (is_const << 5) | (arg << 8);
+}
 
 // ---------------------------------------------------------------------------
 // Register-resident arrays.  The compiler keeps a small local array in
@@ -86,6 +115,20 @@ struct Sched {
         if constexpr (R > 3) v[3] = name##3[idx];    \
     } while (0)
 
+// Uniform loads of read-only data through the scalar data cache: the pointer
+// is cast to the constant address space so the compiler issues s_load.
+template <typename T>
+__device__ __forceinline__ T ldu(const T* p) {
+    return *(const __attribute__((address_space(4))) T*)p;
+}
+
+// Stack slots: slots below kStackRegs live in VGPRs, slots from kStackRegs
+// on in a per-wavefront LDS area; register slot kStackRegs is a sink for the
+// speculative writes of those deeper slots (see k_eval).  Slot 0 is never
+// read, so a full stack of GP_MAX_STACK values uses slots 1 .. GP_MAX_STACK-1.
+constexpr int kStackRegs = 15;
+constexpr int kStackLds = GP_MAX_STACK - kStackRegs;
+
 // Protected operators (reading of Sec. III-C3's function set: the gplearn
 // convention).  Comparisons are written so that NaN takes the protected arm.
 __device__ __forceinline__ float op_div(float a, float b) {
@@ -96,51 +139,95 @@ __device__ __forceinline__ float op_log(float a) {
 }
 __device__ __forceinline__ float op_sqrt(float a) { return sqrtf(fabsf(a)); }
 
+// a = a (op) b for the binary function index fn (ADD, SUB, MUL, DIV)
 template <int R>
-__device__ __forceinline__ void apply_binary(uint32_t op, float (&t)[R], const float (&b)[R]) {
-    if (op == GP_OP_ADD) {
+__device__ __forceinline__ void apply_binary(uint32_t fn, float (&a)[R], const float (&b)[R]) {
+    if (fn < 2) {
+        if (fn == 0) {
 #pragma unroll
-        for (int j = 0; j < R; ++j) t[j] = t[j] + b[j];
-    } else if (op == GP_OP_SUB) {
+            for (int j = 0; j < R; ++j) a[j] = a[j] + b[j];
+        } else {
 #pragma unroll
-        for (int j = 0; j < R; ++j) t[j] = t[j] - b[j];
-    } else if (op == GP_OP_MUL) {
-#pragma unroll
-        for (int j = 0; j < R; ++j) t[j] = t[j] * b[j];
+            for (int j = 0; j < R; ++j) a[j] = a[j] - b[j];
+        }
     } else {
+        if (fn == 2) {
 #pragma unroll
-        for (int j = 0; j < R; ++j) t[j] = op_div(t[j], b[j]);
+            for (int j = 0; j < R; ++j) a[j] = a[j] * b[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < R; ++j) a[j] = op_div(a[j], b[j]);
+        }
     }
 }
 
+// t = f(t) for the unary function index fn (NEG, LOG, SQRT, SIN, COS, TAN)
 template <int R>
-__device__ __forceinline__ void apply_unary(uint32_t op, float (&t)[R]) {
-    switch (op) {
-    case GP_OP_NEG:
+__device__ __forceinline__ void apply_unary(uint32_t fn, float (&t)[R]) {
+    if (fn < 3) {
+        if (fn == 0) {
 #pragma unroll
-        for (int j = 0; j < R; ++j) t[j] = -t[j];
-        break;
-    case GP_OP_LOG:
+            for (int j = 0; j < R; ++j) t[j] = -t[j];
+        } else if (fn == 1) {
 #pragma unroll
-        for (int j = 0; j < R; ++j) t[j] = op_log(t[j]);
-        break;
-    case GP_OP_SQRT:
+            for (int j = 0; j < R; ++j) t[j] = op_log(t[j]);
+        } else {
 #pragma unroll
-        for (int j = 0; j < R; ++j) t[j] = op_sqrt(t[j]);
-        break;
-    case GP_OP_SIN:
+            for (int j = 0; j < R; ++j) t[j] = op_sqrt(t[j]);
+        }
+    } else {
+        if (fn == 3) {
 #pragma unroll
-        for (int j = 0; j < R; ++j) t[j] = sinf(t[j]);
-        break;
-    case GP_OP_COS:
+            for (int j = 0; j < R; ++j) t[j] = sinf(t[j]);
+        } else if (fn == 4) {
 #pragma unroll
-        for (int j = 0; j < R; ++j) t[j] = cosf(t[j]);
-        break;
-    default:
+            for (int j = 0; j < R; ++j) t[j] = cosf(t[j]);
+        } else {
 #pragma unroll
-        for (int j = 0; j < R; ++j) t[j] = tanf(t[j]);
-        break;
+            for (int j = 0; j < R; ++j) t[j] = tanf(t[j]);
+        }
     }
+}
+
+// ---------------------------------------------------------------------------
+// k_compile: one lane per program.  Scans the prefix list right to left (the
+// evaluation order of Sec. III-A) and emits instructions in that order.  A
+// terminal at position i is the first operand of the function at i-1 exactly
+// when that function is binary (its first operand starts right after it), so
+// such pairs become one kFold instruction.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint2* __restrict__ code,
+                                                     int32_t* __restrict__ clen) {
+    const int32_t p = static_cast<int32_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (p >= pop.P) return;
+    const int64_t off = pop.prog_off[p];
+    const int32_t L = pop.len[p];
+    const uint32_t* pn = pop.nodes + off;
+    const float* pc = pop.consts + pop.const_off[p];
+    uint2* out = code + off;
+    int32_t k = 0;
+    for (int32_t i = L - 1; i >= 0; --i) {
+        const uint32_t w = pn[i];
+        const uint32_t op = w & 0xffu;
+        const uint32_t arg = w >> 8;
+        if (op <= GP_OP_CONST) {
+            const uint32_t is_c = op == GP_OP_CONST ? 1u : 0u;
+            const uint32_t val = is_c ? __float_as_uint(pc[arg]) : 0u;
+            const uint32_t farg = is_c ? 0u : arg;
+            const uint32_t prev = i >= 1 ? (pn[i - 1] & 0xffu) : 0u;
+            if (i >= 1 && i != L - 1 && prev >= GP_OP_ADD && prev <= GP_OP_DIV) {
+                out[k++] = make_uint2(enc(kFold, prev - GP_OP_ADD, is_c, farg), val);
+                --i;
+            } else {
+                out[k++] = make_uint2(enc(kPush, 0, is_c, farg), val);
+            }
+        } else if (op <= GP_OP_DIV) {
+            out[k++] = make_uint2(enc(kBin, op - GP_OP_ADD, 0, 0), 0u);
+        } else {
+            out[k++] = make_uint2(enc(kUn, op - GP_OP_NEG, 0, 0), 0u);
+        }
+    }
+    clen[p] = k;
 }
 
 // ---------------------------------------------------------------------------
@@ -220,25 +307,29 @@ __global__ __launch_bounds__(kBlock) void k_ystats(DataView d, int64_t chunk, in
 // The evaluation kernel.
 //   MODE 0: write every program output out[p * N + r]   (gp_evaluate)
 //   MODE 1: accumulate the metric's float64 row sums per (program, chunk)
-//           into part[(p * n_chunks + c) * K + k]      (gp_fitness)
+//           into part[(p * n_chunks + c) * KK + k]     (gp_fitness)
 // R rows per lane; FREG > 0 keeps the tile's F <= FREG feature values in
-// registers, FREG == 0 reads a feature from memory at each VAR node.
+// registers, FREG == 0 reads a feature from memory at each terminal.
 // ---------------------------------------------------------------------------
 template <int METRIC>
 struct MetricTraits {
-    static constexpr int K = (METRIC == GP_METRIC_PEARSON) ? 3 : 1;
+    static constexpr int K = (METRIC == GP_METRIC_PEARSON) ? 3 : 1;   // moments per row
+    static constexpr int KK = (METRIC == GP_METRIC_PEARSON) ? 4 : 1;  // doubles per partial
 };
 
 template <int R, int FREG, int MODE, int METRIC>
-__global__ __launch_bounds__(kBlock) void k_eval(PopView pop, DataView d, Sched s,
+__global__ __launch_bounds__(kBlock) void k_eval(PopView pop, CodeView cv, DataView d, Sched s,
                                                   float* __restrict__ out,
                                                   double* __restrict__ part) {
     constexpr int K = MetricTraits<METRIC>::K;
+    constexpr int KK = MetricTraits<METRIC>::KK;
     constexpr int FA = FREG > 0 ? FREG : 1;
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t N = d.N;
     const int64_t ld = d.ld;
     const float* __restrict__ X = d.X;
+    __shared__ float ovf_all[kBlock / kWave][kStackLds * R * kWave];
+    float* ovf = ovf_all[threadIdx.x >> 6];
 
     for (;;) {
         uint32_t it32 = 0;
@@ -247,11 +338,10 @@ __global__ __launch_bounds__(kBlock) void k_eval(PopView pop, DataView d, Sched 
         if (it >= s.n_items) break;   // every wavefront leaves here once the items run out
         const int32_t c = static_cast<int32_t>(it / pop.P);
         const int32_t k = static_cast<int32_t>(it - static_cast<int64_t>(c) * pop.P);
-        const int32_t p = __builtin_amdgcn_readfirstlane(s.order[k]);
-        const int64_t off = pop.prog_off[p];
-        const int32_t L = pop.len[p];
-        const uint32_t* __restrict__ pn = pop.nodes + off;
-        const float* __restrict__ pc = pop.consts + pop.const_off[p];
+        const int32_t p = ldu(s.order + k);
+        const int64_t off = ldu(pop.prog_off + p);
+        const int32_t CL = ldu(cv.clen + p);
+        const uint2* __restrict__ pcode = cv.code + off;
         const int64_t r0 = static_cast<int64_t>(c) * s.chunk;
         const int64_t r1 = min(r0 + s.chunk, N);
 
@@ -283,43 +373,81 @@ __global__ __launch_bounds__(kBlock) void k_eval(PopView pop, DataView d, Sched 
                 }
             }
 
-            // ---- right-to-left stack scan of the prefix list (Sec. III-A) ----
-            float t[R];                 // cached top of stack
-            GP_ARRAYS(st, kSpill);      // entries below the top
-            int dpt = 0;                // number of entries below the top
-            for (int i = L - 1; i >= 0; --i) {
-                const uint32_t w = __builtin_amdgcn_readfirstlane(pn[i]);
-                const uint32_t op = w & 0xffu;
-                const uint32_t arg = w >> 8;
-                if (op <= GP_OP_CONST) {
-                    if (i != L - 1) {
-                        GP_PUT(st, dpt, t);
-                        ++dpt;
-                    }
-                    if (op == GP_OP_VAR) {
-                        if constexpr (FREG > 0) {
-                            t[0] = xa0[arg];
-                            if constexpr (R > 1) t[1] = xa1[arg];
-                            if constexpr (R > 2) t[2] = xa2[arg];
-                            if constexpr (R > 3) t[3] = xa3[arg];
-                        } else {
-                            const float* __restrict__ col = X + static_cast<int64_t>(arg) * ld;
+            // ---- the stack machine (Sec. III-A order, compiled by k_compile) ----
+            // t[] is the top of the stack; slot `dp` (VGPRs below kStackRegs,
+            // LDS from there on) is the entry just below it.  Every instruction
+            // first writes the top into the slot above dp -- kept only when the
+            // instruction is a push, which then just advances dp -- so the
+            // register array sees exactly one indexed write per instruction and
+            // is never copied.  The first push parks the empty top in slot 0,
+            // which is never read back.  The next instruction is fetched one
+            // step ahead as a vector register and made scalar where it is used.
+            float t[R];
 #pragma unroll
-                            for (int j = 0; j < R; ++j) t[j] = col[row[j]];
-                        }
-                    } else {
-                        const float cv = pc[arg];
-#pragma unroll
-                        for (int j = 0; j < R; ++j) t[j] = cv;
-                    }
-                } else if (op <= GP_OP_DIV) {
-                    --dpt;
-                    float b[R];
-                    GP_GET(st, dpt, b);
-                    apply_binary<R>(op, t, b);
-                } else {
-                    apply_unary<R>(op, t);
+            for (int j = 0; j < R; ++j) t[j] = 0.0f;
+            GP_ARRAYS(st, kStackRegs + 1);
+            int dp = -1;
+            uint2 nxt = pcode[0];
+            for (int q = 0; q < CL; ++q) {
+                const uint2 cur = nxt;
+                nxt = pcode[min(q + 1, CL - 1)];
+                const uint32_t w = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(cur.x)));
+                const uint32_t cls = w & 3u;
+                const uint32_t fn = (w >> 2) & 7u;
+                const int up = min(dp + 1, kStackRegs);
+                GP_PUT(st, up, t);
+                if (cls == kUn) {
+                    apply_unary<R>(fn, t);
+                    continue;
                 }
+                float a[R], b[R];
+                if (cls == kBin) {
+                    if (dp < kStackRegs) {
+                        GP_GET(st, dp, b);
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < R; ++j) b[j] = ovf[((dp - kStackRegs) * R + j) * kWave + lane];
+                    }
+                    --dp;
+#pragma unroll
+                    for (int j = 0; j < R; ++j) a[j] = t[j];
+                } else {
+                    float v[R];
+                    if (w & 32u) {
+                        const float cval = __uint_as_float(cur.y);
+#pragma unroll
+                        for (int j = 0; j < R; ++j) v[j] = cval;
+                    } else if constexpr (FREG > 0) {
+                        const uint32_t arg = w >> 8;
+                        v[0] = xa0[arg];
+                        if constexpr (R > 1) v[1] = xa1[arg];
+                        if constexpr (R > 2) v[2] = xa2[arg];
+                        if constexpr (R > 3) v[3] = xa3[arg];
+                    } else {
+                        const float* __restrict__ col = X + static_cast<int64_t>(w >> 8) * ld;
+#pragma unroll
+                        for (int j = 0; j < R; ++j) v[j] = col[row[j]];
+                    }
+                    if (cls == kPush) {
+                        ++dp;
+                        if (dp >= kStackRegs) {
+#pragma unroll
+                            for (int j = 0; j < R; ++j) ovf[((dp - kStackRegs) * R + j) * kWave + lane] = t[j];
+                        }
+#pragma unroll
+                        for (int j = 0; j < R; ++j) t[j] = v[j];
+                        continue;
+                    }
+                    // kFold: the terminal is the first operand, the top the second
+#pragma unroll
+                    for (int j = 0; j < R; ++j) {
+                        a[j] = v[j];
+                        b[j] = t[j];
+                    }
+                }
+                apply_binary<R>(fn, a, b);
+#pragma unroll
+                for (int j = 0; j < R; ++j) t[j] = a[j];
             }
 
             if constexpr (MODE == 0) {
@@ -371,7 +499,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(PopView pop, DataView d, Sched 
                 acc2 = wave_sum(acc2);
             }
             if (lane == 0) {
-                double* dst = part + (static_cast<int64_t>(p) * s.n_chunks + c) * (K + (K > 1 ? 1 : 0));
+                double* dst = part + (static_cast<int64_t>(p) * s.n_chunks + c) * KK;
                 dst[0] = acc0;
                 if constexpr (K > 1) {
                     dst[1] = acc1;
@@ -518,6 +646,10 @@ struct DeviceScratch {
     size_t part_cap = 0;         // doubles
     double* ystat = nullptr;
     size_t ystat_cap = 0;        // doubles
+    uint2* code = nullptr;
+    size_t code_cap = 0;         // instructions
+    int32_t* clen = nullptr;
+    size_t clen_cap = 0;
     int n_cu = 0;
 };
 
@@ -614,8 +746,9 @@ LaunchCfg pick_cfg(int F, int64_t N, int32_t P, int n_cu) {
 }
 
 template <int MODE, int METRIC>
-gp_status launch_eval_m(const LaunchCfg& cfg, int n_cu, const PopView& pv, const DataView& dv,
-                        const Sched& s, float* out, double* part, hipStream_t st, int64_t node_rows) {
+gp_status launch_eval_m(const LaunchCfg& cfg, int n_cu, const PopView& pv, const CodeView& cv,
+                        const DataView& dv, const Sched& s, float* out, double* part, hipStream_t st,
+                        int64_t node_rows) {
     auto go = [&](auto kernel) -> gp_status {
         int per_cu = 0;
         GP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0));
@@ -630,7 +763,8 @@ gp_status launch_eval_m(const LaunchCfg& cfg, int n_cu, const PopView& pv, const
             GP_HIP(hipEventCreate(&rec.b));
             GP_HIP(hipEventRecord(rec.a, st));
         }
-        hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, st, pv, dv, s, out, part);
+        hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, st, pv, cv, dv, s, out,
+                           part);
         GP_HIP(hipGetLastError());
         if (g_prof_on) {
             GP_HIP(hipEventRecord(rec.b, st));
@@ -648,27 +782,28 @@ gp_status launch_eval_m(const LaunchCfg& cfg, int n_cu, const PopView& pv, const
 }
 
 gp_status launch_eval(int mode, int metric, const LaunchCfg& cfg, int n_cu, const PopView& pv,
-                      const DataView& dv, const Sched& s, float* out, double* part, hipStream_t st,
-                      int64_t node_rows) {
-    if (mode == 0) return launch_eval_m<0, GP_METRIC_MSE>(cfg, n_cu, pv, dv, s, out, part, st, node_rows);
+                      const CodeView& cv, const DataView& dv, const Sched& s, float* out, double* part,
+                      hipStream_t st, int64_t node_rows) {
+    if (mode == 0)
+        return launch_eval_m<0, GP_METRIC_MSE>(cfg, n_cu, pv, cv, dv, s, out, part, st, node_rows);
     switch (metric) {
     case GP_METRIC_MAE:
-        return launch_eval_m<1, GP_METRIC_MAE>(cfg, n_cu, pv, dv, s, out, part, st, node_rows);
+        return launch_eval_m<1, GP_METRIC_MAE>(cfg, n_cu, pv, cv, dv, s, out, part, st, node_rows);
     case GP_METRIC_MSE:
     case GP_METRIC_RMSE:
-        return launch_eval_m<1, GP_METRIC_MSE>(cfg, n_cu, pv, dv, s, out, part, st, node_rows);
+        return launch_eval_m<1, GP_METRIC_MSE>(cfg, n_cu, pv, cv, dv, s, out, part, st, node_rows);
     case GP_METRIC_LOGLOSS:
-        return launch_eval_m<1, GP_METRIC_LOGLOSS>(cfg, n_cu, pv, dv, s, out, part, st, node_rows);
+        return launch_eval_m<1, GP_METRIC_LOGLOSS>(cfg, n_cu, pv, cv, dv, s, out, part, st, node_rows);
     case GP_METRIC_PEARSON:
-        return launch_eval_m<1, GP_METRIC_PEARSON>(cfg, n_cu, pv, dv, s, out, part, st, node_rows);
+        return launch_eval_m<1, GP_METRIC_PEARSON>(cfg, n_cu, pv, cv, dv, s, out, part, st, node_rows);
     default: return fail(GP_ERR_UNSUPPORTED, "metric not supported by the fused fitness kernel");
     }
 }
 
 // Shared front half of gp_evaluate / gp_fitness: checks, scratch, ordering.
 gp_status prepare(const gp_population_dev* pop, const gp_dataset_dev* data, int mode, int metric,
-                  hipStream_t st, DeviceScratch** sc_out, PopView* pv, DataView* dv, Sched* sch,
-                  LaunchCfg* cfg) {
+                  hipStream_t st, DeviceScratch** sc_out, PopView* pv, CodeView* cvw, DataView* dv,
+                  Sched* sch, LaunchCfg* cfg) {
     int dev = 0;
     GP_HIP(hipGetDevice(&dev));
     DeviceScratch* sc = nullptr;
@@ -687,6 +822,11 @@ gp_status prepare(const gp_population_dev* pop, const gp_dataset_dev* data, int 
         return fail(GP_ERR_INVALID_ARG, "too many work items (n_programs * row chunks above 2^30)");
     rc = grow(reinterpret_cast<void**>(&sc->order), &sc->order_cap, pop->n_programs, sizeof(int32_t));
     if (rc != GP_OK) return rc;
+    rc = grow(reinterpret_cast<void**>(&sc->code), &sc->code_cap, static_cast<size_t>(pop->total_nodes),
+              sizeof(uint2));
+    if (rc != GP_OK) return rc;
+    rc = grow(reinterpret_cast<void**>(&sc->clen), &sc->clen_cap, pop->n_programs, sizeof(int32_t));
+    if (rc != GP_OK) return rc;
     if (mode == 1) {
         const size_t kk = metric == GP_METRIC_PEARSON ? 4 : 1;
         rc = grow(reinterpret_cast<void**>(&sc->part), &sc->part_cap,
@@ -701,6 +841,10 @@ gp_status prepare(const gp_population_dev* pop, const gp_dataset_dev* data, int 
     hipLaunchKernelGGL(k_prepare, dim3(1), dim3(1024), 0, st, pop->len, pop->n_programs, sc->order,
                        static_cast<uint32_t*>(sc->counter));
     GP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_compile, dim3((pop->n_programs + kBlock - 1) / kBlock), dim3(kBlock), 0, st, *pv,
+                       sc->code, sc->clen);
+    GP_HIP(hipGetLastError());
+    *cvw = CodeView{sc->code, sc->clen};
     *sc_out = sc;
     return GP_OK;
 }
@@ -715,13 +859,15 @@ void gp_shutdown(void) {
     (void)hipGetDevice(&cur);
     for (size_t d = 0; d < g_dev.size(); ++d) {
         DeviceScratch& s = g_dev[d];
-        if (!s.counter && !s.order && !s.part && !s.ystat) continue;
+        if (!s.counter && !s.order && !s.part && !s.ystat && !s.code && !s.clen) continue;
         (void)hipSetDevice(static_cast<int>(d));
         (void)hipDeviceSynchronize();
         if (s.counter) (void)hipFree(s.counter);
         if (s.order) (void)hipFree(s.order);
         if (s.part) (void)hipFree(s.part);
         if (s.ystat) (void)hipFree(s.ystat);
+        if (s.code) (void)hipFree(s.code);
+        if (s.clen) (void)hipFree(s.clen);
         s = DeviceScratch{};
     }
     (void)hipSetDevice(cur);
@@ -800,12 +946,13 @@ gp_status gp_evaluate(const gp_population_dev* pop, const gp_dataset_dev* data, 
     hipStream_t st = static_cast<hipStream_t>(stream);
     DeviceScratch* sc;
     PopView pv;
+    CodeView cvw;
     DataView dv;
     Sched sch;
     LaunchCfg cfg;
-    rc = prepare(pop, data, 0, GP_METRIC_MSE, st, &sc, &pv, &dv, &sch, &cfg);
+    rc = prepare(pop, data, 0, GP_METRIC_MSE, st, &sc, &pv, &cvw, &dv, &sch, &cfg);
     if (rc != GP_OK) return rc;
-    return launch_eval(0, GP_METRIC_MSE, cfg, sc->n_cu, pv, dv, sch, out, nullptr, st,
+    return launch_eval(0, GP_METRIC_MSE, cfg, sc->n_cu, pv, cvw, dv, sch, out, nullptr, st,
                        pop->total_nodes * data->n_rows);
 }
 
@@ -824,10 +971,11 @@ gp_status gp_fitness(const gp_population_dev* pop, const gp_dataset_dev* data, g
     hipStream_t st = static_cast<hipStream_t>(stream);
     DeviceScratch* sc;
     PopView pv;
+    CodeView cvw;
     DataView dv;
     Sched sch;
     LaunchCfg cfg;
-    rc = prepare(pop, data, 1, metric, st, &sc, &pv, &dv, &sch, &cfg);
+    rc = prepare(pop, data, 1, metric, st, &sc, &pv, &cvw, &dv, &sch, &cfg);
     if (rc != GP_OK) return rc;
     const bool need_ystats = data->w != nullptr || metric == GP_METRIC_PEARSON;
     if (need_ystats) {
@@ -835,7 +983,7 @@ gp_status gp_fitness(const gp_population_dev* pop, const gp_dataset_dev* data, g
         hipLaunchKernelGGL(k_ystats, dim3(blocks), dim3(kBlock), 0, st, dv, sch.chunk, sch.n_chunks, sc->ystat);
         GP_HIP(hipGetLastError());
     }
-    rc = launch_eval(1, metric, cfg, sc->n_cu, pv, dv, sch, nullptr, sc->part, st,
+    rc = launch_eval(1, metric, cfg, sc->n_cu, pv, cvw, dv, sch, nullptr, sc->part, st,
                      pop->total_nodes * data->n_rows);
     if (rc != GP_OK) return rc;
     const int fblocks = (pop->n_programs + (kBlock / kWave) - 1) / (kBlock / kWave);

@@ -16,7 +16,8 @@ Tolerance policy (the acceptance bar for float work):
   * fitness: |gpu - oracle| <= 1e-4 * |oracle| (oracle rounded to float32),
     same non-finite class; a program is ill-conditioned -- reported, not
     checked -- iff the bound propagated from its rows to its fitness exceeds
-    half that budget or one of its rows has a predicate near the threshold.
+    that tolerance or one of its rows has a predicate near the threshold
+    (within the bound, a result outside the tolerance can only be a defect).
 """
 from __future__ import annotations
 
@@ -76,7 +77,7 @@ def check_fitness(got, f32p, f64, fbound, fnear, label=""):
     f64 = np.asarray(f64, np.float64)
     fbound = np.asarray(fbound, np.float64)
     with np.errstate(invalid="ignore"):
-        ill = (np.asarray(fnear) > 0) | ~(fbound <= 0.5 * FIT_TOL * np.abs(ref))
+        ill = (np.asarray(fnear) > 0) | ~(fbound <= FIT_TOL * np.abs(ref))
     ill &= ~((fbound == 0) & (np.asarray(fnear) == 0))
     ok = ~ill
     fin = np.isfinite(ref)

@@ -134,24 +134,63 @@ def _fitness_case(gp, host, X, y, w, metric, F, cfg=None):
     return (got,) + tuple(ref)
 
 
+CR_FMASK = sum(1 << o for o in (oracle.ADD, oracle.SUB, oracle.MUL, oracle.DIV, oracle.NEG,
+                                oracle.SQRT))
+
+
+def _metric_data(metric, N, seed):
+    if metric == "logloss":
+        X, y = synth.higgs_like(N, seed=seed)
+        return np.ascontiguousarray(X[:8]), y, 8
+    X, y = synth.pagie(N, seed=seed)
+    return X, y, 2
+
+
 @pytest.mark.parametrize("metric", ["mae", "mse", "rmse", "logloss", "pearson"])
 @pytest.mark.parametrize("weighted", [False, True])
-def test_fitness_all_metrics(gp, metric, weighted):
+def test_fitness_all_metrics_rhh(gp, metric, weighted):
+    """Ramped half-and-half programs (depth 2-8) over the nine-function set."""
     N = 20000 + 13
-    if metric == "logloss":
-        X, y = synth.higgs_like(N, seed=4)
-        X = np.ascontiguousarray(X[:8])
-        F = 8
-    else:
-        X, y = synth.pagie(N, seed=11228)
-        F = 2
+    X, y, F = _metric_data(metric, N, 11228)
     w = synth.weights(N) if weighted else None
-    host = gp.build_population(200, F, "exact_len", min_len=1, max_len=200, seed=31)
+    host = gp.build_population(300, F, "rhh", min_depth=2, max_depth=8, seed=31)
     for cfg in (None, (1, 8, 4), (4, 0, 3)):
         got, *ref = _fitness_case(gp, host, X, y, w, metric, F, cfg)
         n_ok, n_ill, e64 = check_fitness(got, *ref, f"{metric} w={weighted} cfg={cfg}")
-        print(f"{metric} weighted={weighted} cfg={cfg}: {n_ok} ok, {n_ill} ill, max rel err vs f64 {e64:.2e}")
-        assert n_ok >= 150
+        print(f"rhh {metric} weighted={weighted} cfg={cfg}: {n_ok} ok, {n_ill} ill, "
+              f"max rel err vs f64 {e64:.2e}")
+        # a small |r| is relatively sensitive to every row, so fewer Pearson
+        # programs clear the conditioning bar than loss-type metrics
+        assert n_ok >= (0.65 if metric == "pearson" else 0.8) * 300
+
+
+@pytest.mark.parametrize("metric", ["mae", "mse", "rmse", "logloss", "pearson"])
+@pytest.mark.parametrize("weighted", [False, True])
+def test_fitness_all_metrics_long_correctly_rounded(gp, metric, weighted):
+    """Programs of 1-200 nodes over the correctly rounded functions: no row is
+    ill-conditioned, so every program must meet the bar."""
+    N = 20000 + 13
+    X, y, F = _metric_data(metric, N, 11229)
+    w = synth.weights(N) if weighted else None
+    host = gp.build_population(200, F, "exact_len", min_len=1, max_len=200, function_mask=CR_FMASK,
+                               seed=32)
+    for cfg in (None, (2, 8, 4), (4, 0, 3)):
+        got, *ref = _fitness_case(gp, host, X, y, w, metric, F, cfg)
+        n_ok, n_ill, e64 = check_fitness(got, *ref, f"{metric} w={weighted} cfg={cfg}")
+        assert n_ill == 0 and n_ok == 200
+
+
+@pytest.mark.parametrize("metric", ["mse", "logloss", "pearson"])
+def test_fitness_long_nine_function_programs(gp, metric):
+    """Programs of 1-200 nodes over the nine-function set: many are chaotic in
+    float32; the well-conditioned ones must meet the bar."""
+    N = 20000 + 13
+    X, y, F = _metric_data(metric, N, 11230)
+    host = gp.build_population(200, F, "exact_len", min_len=1, max_len=200, seed=33)
+    got, *ref = _fitness_case(gp, host, X, y, None, metric, F)
+    n_ok, n_ill, e64 = check_fitness(got, *ref, f"{metric} long")
+    print(f"long {metric}: {n_ok} ok, {n_ill} ill, max rel err vs f64 {e64:.2e}")
+    assert n_ok >= 20
 
 
 def test_fitness_rhh_pagie_small_config(gp):
@@ -233,6 +272,25 @@ def test_tournament_on_gpu_fitness(gp):
     assert np.array_equal(win.cpu().numpy(), ref)
 
 
+def well_conditioned_sample(host, X, y, metric, rng, k):
+    """k programs, half the longest well-conditioned candidates and half at
+    random among well-conditioned ones, judged by the oracle's fitness bound on
+    an evenly spaced 32768-row subsample."""
+    cand = np.unique(np.concatenate([np.argsort(-host.length, kind="stable")[:48],
+                                     rng.integers(0, host.n_programs, 48)]))
+    idx = np.linspace(0, X.shape[1] - 1, 32768).astype(np.int64)
+    Xs, ys = np.ascontiguousarray(X[:, idx]), np.ascontiguousarray(y[idx])
+    sub = oracle.from_programs([(host.nodes[host.prog_off[p]:host.prog_off[p + 1]],
+                                 host.consts[host.const_off[p]:host.const_off[p + 1]]) for p in cand])
+    f32p, _, fb, fn = oracle.fitness(sub, Xs, ys, None, metric, n_threads=NT, with_bound=True)
+    good = cand[(fn == 0) & (fb <= 0.05 * 1e-4 * np.abs(f32p))]
+    assert len(good) >= k, len(good)
+    longest = good[np.argsort(-host.length[good], kind="stable")[:k // 2]]
+    rest = np.setdiff1d(good, longest)
+    pick = rng.choice(rest, size=k - len(longest), replace=False)
+    return np.sort(np.concatenate([longest, pick]))
+
+
 def test_full_size_pagie_16m_sampled(gp):
     """The 16,777,216-row Pagie workload, 4096 exact-length programs, at the
     launch configuration the benchmark uses: fitness of sampled programs over
@@ -248,14 +306,15 @@ def test_full_size_pagie_16m_sampled(gp):
     got = fit.cpu().numpy()
     assert got.shape == (4096,)
     rng = np.random.default_rng(0)
-    order = np.argsort(-host.length, kind="stable")
-    sample = np.unique(np.concatenate([order[:2], order[-2:], rng.integers(0, 4096, 2)]))
+    sample = well_conditioned_sample(host, X, y, "mse", rng, 6)
     sub = [(host.nodes[host.prog_off[p]:host.prog_off[p + 1]],
             host.consts[host.const_off[p]:host.const_off[p + 1]]) for p in sample]
     osub = oracle.from_programs(sub)
     ref = oracle.fitness(osub, X, y, None, "mse", n_threads=NT, with_bound=True)
     n_ok, n_ill, _ = check_fitness(got[sample], *ref, "pagie-16M sampled")
-    print(f"pagie-16M: {n_ok} sampled programs checked, {n_ill} ill-conditioned")
+    print(f"pagie-16M: {n_ok} sampled programs checked, {n_ill} ill-conditioned, "
+          f"lengths {host.length[sample].tolist()}")
+    assert n_ok >= 4
     # per-row outputs of the sampled programs on sampled rows
     hsub = gp.HostPopulation(osub.nodes, osub.prog_off, osub.consts, osub.const_off, osub.length)
     dsub = gp.DevicePopulation(hsub, n_features=2)
@@ -279,10 +338,12 @@ def test_full_size_higgs_like_logloss_sampled(gp):
     torch.cuda.synchronize()
     got = fit.cpu().numpy()
     rng = np.random.default_rng(1)
-    sample = np.unique(rng.integers(0, 2000, 4))
+    sample = well_conditioned_sample(host, X, y, "logloss", rng, 4)
     sub = [(host.nodes[host.prog_off[p]:host.prog_off[p + 1]],
             host.consts[host.const_off[p]:host.const_off[p + 1]]) for p in sample]
     ref = oracle.fitness(oracle.from_programs(sub), X, y, None, "logloss", n_threads=NT,
                          with_bound=True)
     n_ok, n_ill, _ = check_fitness(got[sample], *ref, "higgs-like sampled")
-    print(f"higgs-like: {n_ok} sampled programs checked, {n_ill} ill-conditioned")
+    print(f"higgs-like: {n_ok} sampled programs checked, {n_ill} ill-conditioned, "
+          f"lengths {host.length[sample].tolist()}")
+    assert n_ok >= 3
