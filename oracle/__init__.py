@@ -75,7 +75,7 @@ def lib():
                                            i32, u64, P, i64, P, P, i64, P, P, P, P]
         L.orc_build_population.restype = ctypes.c_int
         L.orc_grad_consts.argtypes = [P, P, P, P, i32, P, i64, i64, P, P, i32, P, P, P,
-                                      ctypes.c_int]
+                                      ctypes.c_double, u64, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -266,8 +266,13 @@ def build_population(n_programs, n_features, method="rhh", min_depth=2, max_dept
                       const_off=co, length=ln)
 
 
-def grad_consts(pop: Population, X, y, w=None, metric="mse", gscale=None, n_threads=None):
-    """(d fitness / d consts for every constant, fitness) in float64."""
+def grad_consts(pop: Population, X, y, w=None, metric="mse", gscale=None, n_threads=None,
+                mc_u=0.0, mc_seed=0):
+    """(d fitness / d consts for every constant, fitness) in float64.
+
+    mc_u > 0 perturbs every operation's result by a relative +-mc_u (Monte
+    Carlo arithmetic, signs from SplitMix64 keyed by mc_seed): the spread of
+    the results over a few seeds estimates their float32 conditioning."""
     X, N = _ds(X)
     y = np.ascontiguousarray(y, dtype=np.float32)
     w = None if w is None else np.ascontiguousarray(w, dtype=np.float32)
@@ -277,5 +282,5 @@ def grad_consts(pop: Population, X, y, w=None, metric="mse", gscale=None, n_thre
     fit = np.zeros(pop.n_programs, np.float64)
     lib().orc_grad_consts(_p(pop.nodes), _p(pop.prog_off), _p(pop.consts), _p(pop.const_off),
                           pop.n_programs, _p(X), N, N, _p(y), _p(w), m, _p(gs), _p(g), _p(fit),
-                          _threads(n_threads))
+                          float(mc_u), int(mc_seed), _threads(n_threads))
     return g[:pop.consts.shape[0]], fit

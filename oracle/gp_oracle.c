@@ -781,6 +781,7 @@ int orc_build_population(int32_t n_programs, int32_t n_features, int32_t method,
 /* Seeds: MSE 2w(yh-y)/W; MAE w sign(yh-y)/W; RMSE dMSE/(2 RMSE) (0 if RMSE   */
 /* is 0); logistic w(sigmoid(yh)-y)/W; Pearson d|r|/dyh.                      */
 /* grad[const_off[p] + s] receives gscale[p] * d fitness_p / d c_s.           */
+/* Programs longer than 4096 nodes get NaN fitness and derivatives.          */
 /* ------------------------------------------------------------------------ */
 static double local_partial(int op, int which, double a, double b, double out)
 {
@@ -803,16 +804,84 @@ static double local_partial(int op, int which, double a, double b, double out)
     }
 }
 
+/* ---- Monte Carlo arithmetic (Parker, 1997), for conditioning estimates ---- */
+/* With u > 0 every operation's result v is replaced by v (1 + s u), s = +-1,  */
+/* the sign taken from SplitMix64 (Steele, Lea and Flood, 2014) of the         */
+/* (seed, row, node, role) counter.  The spread of the derivatives over a few  */
+/* seeds estimates how far float32 rounding (relative error u per operation)   */
+/* can move them.  With u = 0 nothing is perturbed.                            */
+static double mc_factor(double u, uint64_t seed, int64_t r, int64_t i, int role)
+{
+    if (u == 0.0) return 1.0;
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull *
+                 (1ull + (uint64_t)r * 16384ull + (uint64_t)i * 4ull + (uint64_t)role);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (z >> 63) ? 1.0 - u : 1.0 + u;
+}
+
+/* float64 forward pass of one row keeping every node's value val[i] and the  */
+/* end (one past) of its subtree endi[i]; returns the program value.          */
+static double forward_row(const uint32_t *pn, int64_t L, const float *pc, const float *X,
+                          int64_t ld, int64_t r, double u, uint64_t seed,
+                          double *val, int64_t *endi)
+{
+    double st[ORC_STACK];
+    int h = 0;
+    for (int64_t i = L - 1; i >= 0; --i) {
+        int op = (int)(pn[i] & 0xffu);
+        uint32_t arg = pn[i] >> 8;
+        int ar = op_arity(op);
+        double v;
+        if (ar == 0) {
+            v = (op == O_VAR) ? (double)X[(int64_t)arg * ld + r] : (double)pc[arg];
+            endi[i] = i + 1;
+        } else if (ar == 1) {
+            double a = st[--h];
+            switch (op) {
+            case O_NEG: v = -a; break;
+            case O_LOG: v = plog_d(a); break;
+            case O_SQRT: v = psqrt_d(a); break;
+            case O_SIN: v = sin(a); break;
+            case O_COS: v = cos(a); break;
+            default: v = tan(a); break;
+            }
+            v *= mc_factor(u, seed, r, i, 0);
+            endi[i] = endi[i + 1];
+        } else {
+            double a = st[--h];
+            double b = st[--h];
+            switch (op) {
+            case O_ADD: v = a + b; break;
+            case O_SUB: v = a - b; break;
+            case O_MUL: v = a * b; break;
+            default: v = pdiv_d(a, b); break;
+            }
+            v *= mc_factor(u, seed, r, i, 0);
+            endi[i] = endi[endi[i + 1]];
+        }
+        val[i] = v;
+        st[h++] = v;
+    }
+    return val[0];
+}
+
+#define ORC_GRAD_MAX_LEN 4096
+
 void orc_grad_consts(const uint32_t *nodes, const int64_t *prog_off,
                      const float *consts, const int64_t *const_off, int32_t n_programs,
                      const float *X, int64_t ld, int64_t n_rows,
                      const float *y, const float *w, int32_t metric,
-                     const double *gscale, double *grad, double *fit_out, int n_threads)
+                     const double *gscale, double *grad, double *fit_out,
+                     double mc_u, uint64_t mc_seed, int n_threads)
 {
-    (void)n_threads;
 #pragma omp parallel num_threads(n_threads > 0 ? n_threads : 1)
     {
         double *yh = (double *)malloc(sizeof(double) * (size_t)(n_rows > 0 ? n_rows : 1));
+        double *val = (double *)malloc(sizeof(double) * ORC_GRAD_MAX_LEN);
+        double *adj = (double *)malloc(sizeof(double) * ORC_GRAD_MAX_LEN);
+        int64_t *endi = (int64_t *)malloc(sizeof(int64_t) * ORC_GRAD_MAX_LEN);
 #pragma omp for schedule(dynamic, 1)
         for (int32_t p = 0; p < n_programs; ++p) {
             const uint32_t *pn = nodes + prog_off[p];
@@ -821,9 +890,16 @@ void orc_grad_consts(const uint32_t *nodes, const int64_t *prog_off,
             int64_t nc = const_off[p + 1] - const_off[p];
             double *gp = grad + const_off[p];
             for (int64_t s = 0; s < nc; ++s) gp[s] = 0.0;
+            if (L > ORC_GRAD_MAX_LEN) {      /* longer programs are not supported here */
+                if (fit_out) fit_out[p] = NAN;
+                for (int64_t s = 0; s < nc; ++s) gp[s] = NAN;
+                continue;
+            }
             /* forward pass for the metric's global statistics */
             double W = 0.0, S = 0.0;
-            for (int64_t r = 0; r < n_rows; ++r) yh[r] = eval_row_f64(pn, L, pc, X, ld, r);
+            for (int64_t r = 0; r < n_rows; ++r)
+                yh[r] = mc_u == 0.0 ? eval_row_f64(pn, L, pc, X, ld, r)
+                                    : forward_row(pn, L, pc, X, ld, r, mc_u, mc_seed, val, endi);
             double ma = 0.0, mb = 0.0, va = 0.0, vb = 0.0, cab = 0.0, rr = 0.0;
             for (int64_t r = 0; r < n_rows; ++r) {
                 double wr = w ? (double)w[r] : 1.0;
@@ -856,10 +932,6 @@ void orc_grad_consts(const uint32_t *nodes, const int64_t *prog_off,
             double gs = gscale ? gscale[p] : 1.0;
             if (nc == 0) continue;
             /* per-row reverse sweep */
-            double val[4096];
-            int64_t endi[4096];
-            double adj[4096];
-            if (L > 4096) continue;       /* longer programs are not supported here */
             for (int64_t r = 0; r < n_rows; ++r) {
                 double wr = w ? (double)w[r] : 1.0;
                 double d = yh[r] - (double)y[r];
@@ -875,43 +947,8 @@ void orc_grad_consts(const uint32_t *nodes, const int64_t *prog_off,
                     seed = (rr >= 0.0 ? 1.0 : -1.0) * dr;
                 }
                 }
-                seed *= gs;
-                /* forward with per-node values and subtree extents */
-                double st[ORC_STACK];
-                int h = 0;
-                for (int64_t i = L - 1; i >= 0; --i) {
-                    int op = (int)(pn[i] & 0xffu);
-                    uint32_t arg = pn[i] >> 8;
-                    int ar = op_arity(op);
-                    double v;
-                    if (ar == 0) {
-                        v = (op == O_VAR) ? (double)X[(int64_t)arg * ld + r] : (double)pc[arg];
-                        endi[i] = i + 1;
-                    } else if (ar == 1) {
-                        double a = st[--h];
-                        switch (op) {
-                        case O_NEG: v = -a; break;
-                        case O_LOG: v = plog_d(a); break;
-                        case O_SQRT: v = psqrt_d(a); break;
-                        case O_SIN: v = sin(a); break;
-                        case O_COS: v = cos(a); break;
-                        default: v = tan(a); break;
-                        }
-                        endi[i] = endi[i + 1];
-                    } else {
-                        double a = st[--h];
-                        double b = st[--h];
-                        switch (op) {
-                        case O_ADD: v = a + b; break;
-                        case O_SUB: v = a - b; break;
-                        case O_MUL: v = a * b; break;
-                        default: v = pdiv_d(a, b); break;
-                        }
-                        endi[i] = endi[endi[i + 1]];
-                    }
-                    val[i] = v;
-                    st[h++] = v;
-                }
+                seed *= gs * mc_factor(mc_u, mc_seed, r, 0, 3);
+                forward_row(pn, L, pc, X, ld, r, mc_u, mc_seed, val, endi);
                 for (int64_t i = 0; i < L; ++i) adj[i] = 0.0;
                 adj[0] = seed;
                 for (int64_t i = 0; i < L; ++i) {
@@ -921,15 +958,21 @@ void orc_grad_consts(const uint32_t *nodes, const int64_t *prog_off,
                     if (ar == 0 || adj[i] == 0.0) continue;
                     int64_t ia = i + 1;
                     if (ar == 1) {
-                        adj[ia] += adj[i] * local_partial(op, 0, val[ia], 0.0, val[i]);
+                        adj[ia] += adj[i] * local_partial(op, 0, val[ia], 0.0, val[i])
+                                   * mc_factor(mc_u, mc_seed, r, i, 1);
                     } else {
                         int64_t ib = endi[ia];
-                        adj[ia] += adj[i] * local_partial(op, 0, val[ia], val[ib], val[i]);
-                        adj[ib] += adj[i] * local_partial(op, 1, val[ia], val[ib], val[i]);
+                        adj[ia] += adj[i] * local_partial(op, 0, val[ia], val[ib], val[i])
+                                   * mc_factor(mc_u, mc_seed, r, i, 1);
+                        adj[ib] += adj[i] * local_partial(op, 1, val[ia], val[ib], val[i])
+                                   * mc_factor(mc_u, mc_seed, r, i, 2);
                     }
                 }
             }
         }
+        free(endi);
+        free(adj);
+        free(val);
         free(yh);
     }
 }

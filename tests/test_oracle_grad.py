@@ -105,3 +105,50 @@ def test_gradient_scale_and_const_free_programs():
     g2, _ = oracle.grad_consts(pop, X, y, None, "mse", gscale=np.array([1.0, -3.0]))
     assert g1.shape == (1,)
     assert abs(g2[0] + 3.0 * g1[0]) <= 1e-12 * abs(g1[0])
+
+
+def test_monte_carlo_spread_matches_first_order_sensitivity():
+    """Monte Carlo arithmetic estimate of float32 conditioning.
+
+    One row of x1 / cos(c0 / x3) with y = 0 under MSE: the derivative is
+    G = 2 x1^2 sin(t) / (x3 cos(t)^3), t = c0 / x3.  A relative error d on
+    t moves it by (cot t + 3 tan t) t d to first order, which near a zero
+    of cos dominates the few-u moves the other operations add.  Each
+    perturbed run must show that move (in size) and the signs must vary."""
+    from oracle import DIV, COS
+    u = 2.0 ** -22
+    c0 = np.float32(0.5)
+    x3 = np.float32(0.5 / (np.pi / 2 - 2e-3))   # cos(t) near 2e-3, above the 0.001 guard
+    X = np.array([[0.0], [1.0], [0.0], [x3]], dtype=np.float32)
+    y = np.zeros(1, np.float32)
+    prog = [node(DIV), node(VAR, 1), node(COS), node(DIV), node(CONST, 0), node(VAR, 3)]
+    pop = oracle.from_programs([(prog, [c0])])
+    g0, _ = oracle.grad_consts(pop, X, y, None, "mse")
+    t = float(c0) / float(x3)
+    closed = 2.0 * np.sin(t) / (float(x3) * np.cos(t) ** 3)
+    assert abs(g0[0] - closed) <= 1e-12 * abs(closed)
+    main = abs((1.0 / np.tan(t) + 3.0 * np.tan(t)) * t) * u
+    assert main > 1000 * u
+    signs = set()
+    for seed in range(16):
+        g, _ = oracle.grad_consts(pop, X, y, None, "mse", mc_u=u, mc_seed=seed)
+        rel = (g[0] - g0[0]) / g0[0]
+        assert abs(abs(rel) - main) <= 10 * u + 0.01 * main, (seed, rel, main)
+        signs.add(rel > 0)
+    assert signs == {True, False}
+    # u = 0 perturbs nothing
+    gz, _ = oracle.grad_consts(pop, X, y, None, "mse", mc_u=0.0, mc_seed=7)
+    assert gz[0] == g0[0]
+
+
+def test_monte_carlo_spread_small_when_well_conditioned():
+    """c x0 against y = 2 x0: every row's term moves by a few u at most."""
+    rng = np.random.default_rng(3)
+    x = rng.uniform(1, 2, size=500).astype(np.float32)
+    y = (2.0 * x).astype(np.float32)
+    pop = oracle.from_programs([([node(MUL), node(CONST, 0), node(VAR, 0)], [0.7])])
+    g0, _ = oracle.grad_consts(pop, x[None, :], y, None, "mse")
+    u = 2.0 ** -22
+    for seed in range(4):
+        g, _ = oracle.grad_consts(pop, x[None, :], y, None, "mse", mc_u=u, mc_seed=seed)
+        assert 0 < abs(g[0] - g0[0]) <= 8 * u * abs(g0[0])
