@@ -76,6 +76,13 @@ def lib():
         L.orc_build_population.restype = ctypes.c_int
         L.orc_grad_consts.argtypes = [P, P, P, P, i32, P, i64, i64, P, P, i32, P, P, P,
                                       ctypes.c_double, u64, ctypes.c_int]
+        L.orc_plan_generation.argtypes = [f32, f32, f32, f32, u64, i32, u64, P, P, P]
+        L.orc_plan_generation.restype = ctypes.c_int
+        L.orc_mutate.argtypes = [f32, f32, f32, f32, f32, i32, u64,
+                                 i32, i32, i32, i32, i32, i32, u32, f32, f32, i32,
+                                 P, P, P, P, P, P, P, i32, u64,
+                                 P, i64, P, P, i64, P, P, P, P]
+        L.orc_mutate.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -284,3 +291,69 @@ def grad_consts(pop: Population, X, y, w=None, metric="mse", gscale=None, n_thre
                           pop.n_programs, _p(X), N, N, _p(y), _p(w), m, _p(gs), _p(g), _p(fit),
                           float(mc_u), int(mc_seed), _threads(n_threads))
     return g[:pop.consts.shape[0]], fit
+
+
+@dataclass
+class EvolveParams:
+    """Genetic-operation probabilities (reproduction takes the rest), the
+    per-node point replacement probability, the crossover length bound and
+    the seed of the mutation streams."""
+    p_crossover: float = 0.7
+    p_subtree: float = 0.1
+    p_hoist: float = 0.05
+    p_point: float = 0.1
+    p_point_replace: float = 0.05
+    max_len: int = 4096
+    seed: int = 0
+
+
+@dataclass
+class InitParams:
+    """The initialisation settings donors of subtree mutation follow."""
+    n_features: int
+    method: str = "rhh"
+    min_depth: int = 2
+    max_depth: int = 6
+    min_len: int = 1
+    max_len: int = 200
+    fmask: int = DEFAULT_FMASK
+    const_lo: float = -1.0
+    const_hi: float = 1.0
+    max_consts: int = 0
+
+
+def plan_generation(ev: EvolveParams, n_offspring, generation):
+    """(ops, first_tournament, n_tournaments) of the pre-draw."""
+    ops = np.zeros(max(n_offspring, 1), np.int32)
+    ft = np.zeros(max(n_offspring, 1), np.int32)
+    nt = np.zeros(1, np.int32)
+    lib().orc_plan_generation(ev.p_crossover, ev.p_subtree, ev.p_hoist, ev.p_point, int(ev.seed),
+                              int(n_offspring), int(generation), _p(ops), _p(ft), _p(nt))
+    return ops[:n_offspring], ft[:n_offspring], int(nt[0])
+
+
+def mutate(ev: EvolveParams, init: InitParams, parents: Population, ops, first_t, winners, generation):
+    """The offspring population (one per entry of ops)."""
+    n_off = int(len(ops))
+    ops = np.ascontiguousarray(ops, np.int32)
+    first_t = np.ascontiguousarray(first_t, np.int32)
+    winners = np.ascontiguousarray(winners, np.int32)
+    cap = max(n_off * max(int(ev.max_len), int(parents.length.max(initial=1)), 256) * 2, 1)
+    nodes = np.zeros(cap, np.uint32)
+    consts = np.zeros(cap, np.float32)
+    po = np.zeros(n_off + 1, np.int64)
+    co = np.zeros(n_off + 1, np.int64)
+    ln = np.zeros(max(n_off, 1), np.int32)
+    tn = np.zeros(1, np.int64)
+    tc = np.zeros(1, np.int64)
+    pc = parents.consts if parents.consts.shape[0] else np.zeros(1, np.float32)
+    rc = lib().orc_mutate(ev.p_crossover, ev.p_subtree, ev.p_hoist, ev.p_point, ev.p_point_replace,
+                          int(ev.max_len), int(ev.seed), INIT[init.method], init.n_features, init.min_depth,
+                          init.max_depth, init.min_len, init.max_len, init.fmask, init.const_lo,
+                          init.const_hi, init.max_consts, _p(parents.nodes), _p(parents.prog_off), _p(pc),
+                          _p(parents.const_off), _p(ops), _p(first_t), _p(winners), n_off, int(generation),
+                          _p(nodes), cap, _p(po), _p(consts), cap, _p(co), _p(ln), _p(tn), _p(tc))
+    if rc != 0:
+        raise RuntimeError(f"orc_mutate failed ({rc})")
+    return Population(nodes[:int(tn[0])].copy(), po, consts[:int(tc[0])].copy(), co, ln[:n_off].copy())
+

@@ -703,6 +703,40 @@ static int gen_exact(orc_rng *g, const orc_gen_cfg *cfg, orc_buf *b, int min_len
     return 0;
 }
 
+/* one program by the method: 0 RHH, 1 FULL, 2 GROW, 3 EXACT_LEN */
+static int gen_one(orc_rng *g, const orc_gen_cfg *cfg, orc_buf *b, int method, int min_depth,
+                   int max_depth, int min_len, int max_len)
+{
+    if (method == 3) return gen_exact(g, cfg, b, min_len, max_len);
+    int full;
+    if (method == 0) full = !(word_unit(rng_word(g)) < 0.5f);
+    else full = (method == 1);
+    int depth = min_depth + (int)word_below(rng_word(g), (uint32_t)(max_depth - min_depth + 1));
+    int64_t used = 0;
+    grow_node(g, cfg, b, 0, depth, full, &used);
+    return 0;
+}
+
+static int fill_cfg(orc_gen_cfg *cfg, int32_t n_features, uint32_t fmask, float const_lo,
+                    float const_hi, int32_t max_consts)
+{
+    memset(cfg, 0, sizeof *cfg);
+    if (n_features < 1) return -1;
+    if (fmask & ~(((1u << O_NUM) - 1u) & ~3u)) return -1;
+    cfg->n_features = n_features;
+    for (int op = O_ADD; op < O_NUM; ++op) {
+        if (fmask & (1u << op)) {
+            cfg->funcs[cfg->n_funcs++] = op;
+            if (op_arity(op) == 1) cfg->un[cfg->n_un++] = op; else cfg->bin[cfg->n_bin++] = op;
+        }
+    }
+    if (cfg->n_funcs == 0) return -1;
+    cfg->lo = const_lo; cfg->hi = const_hi;
+    cfg->consts_on = !(const_lo > const_hi);
+    cfg->max_consts = max_consts;
+    return 0;
+}
+
 /* method: 0 RHH, 1 FULL, 2 GROW, 3 EXACT_LEN.  Buffers may be NULL (sizes
  * only).  Returns 0 on success, -1 bad arguments, -2 a buffer is too small. */
 int orc_build_population(int32_t n_programs, int32_t n_features, int32_t method,
@@ -745,20 +779,7 @@ int orc_build_population(int32_t n_programs, int32_t n_features, int32_t method,
         int64_t n0 = b.n, c0 = b.nc;
         if (prog_off && nodes) prog_off[p] = n0;
         if (const_off && nodes) const_off[p] = c0;
-        if (method == 3) {
-            if (gen_exact(&g, &cfg, &b, min_len, max_len) != 0) return -1;
-        } else {
-            int full, depth;
-            if (method == 0) {
-                full = !(word_unit(rng_word(&g)) < 0.5f);
-                depth = min_depth + (int)word_below(rng_word(&g), (uint32_t)(max_depth - min_depth + 1));
-            } else {
-                full = (method == 1);
-                depth = min_depth + (int)word_below(rng_word(&g), (uint32_t)(max_depth - min_depth + 1));
-            }
-            int64_t used = 0;
-            grow_node(&g, &cfg, &b, 0, depth, full, &used);
-        }
+        if (gen_one(&g, &cfg, &b, method, min_depth, max_depth, min_len, max_len) != 0) return -1;
         if (len && nodes) len[p] = (int32_t)(b.n - n0);
     }
     if (prog_off && nodes) prog_off[n_programs] = b.n;
@@ -976,3 +997,250 @@ void orc_grad_consts(const uint32_t *nodes, const int64_t *prog_off,
         free(yh);
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Genetic operations (Sec. II-A lists reproduction, point, hoist, subtree  */
+/* and crossover; Sec. III-C pre-draws each offspring's operation so the    */
+/* number of tournaments is known; Sec. III-C2 hoists the donor subtree     */
+/* until the child fits the stack).  Readings:                              */
+/*  - stream tag 2, item = offspring index i, generation g; draw 0 picks    */
+/*    the operation: u < pc crossover, < pc+ps subtree, < ..+ph hoist,      */
+/*    < ..+pp point, else reproduction (running sums in float32);           */
+/*  - crossover takes two tournaments (parent, then donor), every other     */
+/*    operation one; offspring i's tournaments start at the prefix sum;     */
+/*  - a random subtree is the one rooted at a uniformly drawn position;     */
+/*  - crossover: parent subtree (draw 1) replaced by donor subtree (draw    */
+/*    2); while the child's stack height exceeds 20 or its length max_len,  */
+/*    the donor subtree becomes the one rooted at a uniformly drawn         */
+/*    position strictly inside it (one draw each; it stops at a terminal);  */
+/*  - subtree mutation: as crossover, the donor a program generated by the  */
+/*    initialisation method on stream tag 3 (item i, generation g);         */
+/*  - hoist: subtree (draw 1) replaced by the subtree rooted at a position  */
+/*    drawn uniformly within it (draw 2, possibly its own root);            */
+/*  - point: per node in prefix order one draw u; if u < p_replace the node */
+/*    is replaced -- a function by one of the same arity (one draw over     */
+/*    that arity's functions), a terminal by one of (features, constant)    */
+/*    (one draw; a constant is allowed while the program's other constants  */
+/*    number below max_consts, and takes one more draw for its value);     */
+/*  - constants keep their values; slots are renumbered in prefix order.    */
+/* ------------------------------------------------------------------------ */
+static int draw_genetic_op(orc_rng *g, float pc, float ps, float ph, float pp)
+{
+    float t1 = pc;
+    float t2 = t1 + ps;
+    float t3 = t2 + ph;
+    float t4 = t3 + pp;
+    float u = word_unit(rng_word(g));
+    if (u < t1) return 0;
+    if (u < t2) return 1;
+    if (u < t3) return 2;
+    if (u < t4) return 3;
+    return 4;
+}
+
+int orc_plan_generation(float pc, float ps, float ph, float pp, uint64_t seed, int32_t n_offspring,
+                        uint64_t generation, int32_t *ops, int32_t *first_t, int32_t *n_t)
+{
+    int64_t t = 0;
+    for (int32_t i = 0; i < n_offspring; ++i) {
+        orc_rng g;
+        rng_init(&g, seed, (uint32_t)i, (uint32_t)generation, 2u);
+        ops[i] = draw_genetic_op(&g, pc, ps, ph, pp);
+        first_t[i] = (int32_t)t;
+        t += ops[i] == 0 ? 2 : 1;
+    }
+    *n_t = (int32_t)t;
+    return 0;
+}
+
+/* a program as node words plus the value of each node's constant */
+typedef struct { uint32_t *w; float *v; int64_t n; } orc_prog;
+
+static orc_prog prog_alloc(int64_t n)
+{
+    orc_prog p;
+    p.w = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    p.v = (float *)malloc(sizeof(float) * (size_t)(n > 0 ? n : 1));
+    p.n = n;
+    return p;
+}
+static void prog_free(orc_prog *p) { free(p->w); free(p->v); p->w = NULL; p->v = NULL; p->n = 0; }
+
+/* end (one past) of the subtree rooted at s, by recursion on the arities */
+static int64_t sub_end(const uint32_t *w, int64_t s)
+{
+    int ar = op_arity((int)(w[s] & 0xffu));
+    int64_t e = s + 1;
+    for (int a = 0; a < ar; ++a) e = sub_end(w, e);
+    return e;
+}
+
+/* peak height of the right-to-left stack scan */
+static int stack_peak(const uint32_t *w, int64_t n)
+{
+    int h = 0, m = 0;
+    for (int64_t i = n - 1; i >= 0; --i) {
+        h += 1 - op_arity((int)(w[i] & 0xffu));
+        if (h > m) m = h;
+    }
+    return m;
+}
+
+static orc_prog prog_from(const uint32_t *nodes, const int64_t *prog_off, const float *consts,
+                          const int64_t *const_off, int32_t p)
+{
+    int64_t a = prog_off[p], n = prog_off[p + 1] - a;
+    orc_prog r = prog_alloc(n);
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t w = nodes[a + i];
+        r.w[i] = w;
+        r.v[i] = ((w & 0xffu) == O_CONST) ? consts[const_off[p] + (w >> 8)] : 0.0f;
+    }
+    return r;
+}
+
+/* parent with [s, e) replaced by donor [ds, de) */
+static orc_prog replace_subtree(const orc_prog *par, int64_t s, int64_t e, const orc_prog *don,
+                                int64_t ds, int64_t de)
+{
+    int64_t n = s + (de - ds) + (par->n - e), k = 0;
+    orc_prog c = prog_alloc(n);
+    for (int64_t i = 0; i < s; ++i, ++k) { c.w[k] = par->w[i]; c.v[k] = par->v[i]; }
+    for (int64_t i = ds; i < de; ++i, ++k) { c.w[k] = don->w[i]; c.v[k] = don->v[i]; }
+    for (int64_t i = e; i < par->n; ++i, ++k) { c.w[k] = par->w[i]; c.v[k] = par->v[i]; }
+    return c;
+}
+
+static orc_prog hoisted_crossover(const orc_prog *par, const orc_prog *don, orc_rng *g, int32_t max_len)
+{
+    int64_t s = (int64_t)word_below(rng_word(g), (uint32_t)par->n);
+    int64_t e = sub_end(par->w, s);
+    int64_t ds = (int64_t)word_below(rng_word(g), (uint32_t)don->n);
+    int64_t de = sub_end(don->w, ds);
+    for (;;) {
+        orc_prog c = replace_subtree(par, s, e, don, ds, de);
+        if ((stack_peak(c.w, c.n) <= ORC_STACK && c.n <= max_len) || de - ds == 1) return c;
+        prog_free(&c);
+        ds = ds + 1 + (int64_t)word_below(rng_word(g), (uint32_t)(de - ds - 1));
+        de = sub_end(don->w, ds);
+    }
+}
+
+int orc_mutate(float pc, float ps, float ph, float pp, float p_replace, int32_t max_len, uint64_t seed,
+               int32_t method, int32_t n_features, int32_t min_depth, int32_t max_depth,
+               int32_t min_len, int32_t init_max_len, uint32_t fmask, float const_lo,
+               float const_hi, int32_t max_consts,
+               const uint32_t *nodes, const int64_t *prog_off, const float *consts,
+               const int64_t *const_off, const int32_t *ops, const int32_t *first_t,
+               const int32_t *winners, int32_t n_offspring, uint64_t generation,
+               uint32_t *out_nodes, int64_t nodes_cap, int64_t *out_prog_off, float *out_consts,
+               int64_t consts_cap, int64_t *out_const_off, int32_t *out_len,
+               int64_t *total_nodes, int64_t *total_consts)
+{
+    (void)pc; (void)ps; (void)ph; (void)pp;
+    orc_gen_cfg cfg;
+    if (fill_cfg(&cfg, n_features, fmask, const_lo, const_hi, max_consts) != 0) return -1;
+    int64_t nn = 0, ncs = 0;
+    int overflow = 0;
+    for (int32_t i = 0; i < n_offspring; ++i) {
+        orc_rng g;
+        rng_init(&g, seed, (uint32_t)i, (uint32_t)generation, 2u);
+        (void)rng_word(&g);               /* the operation draw */
+        orc_prog par = prog_from(nodes, prog_off, consts, const_off, winners[first_t[i]]);
+        orc_prog child;
+        if (ops[i] == 0) {
+            orc_prog don = prog_from(nodes, prog_off, consts, const_off, winners[first_t[i] + 1]);
+            child = hoisted_crossover(&par, &don, &g, max_len);
+            prog_free(&don);
+        } else if (ops[i] == 1) {
+            /* the donor: a fresh program on the donor stream */
+            orc_rng gd;
+            rng_init(&gd, seed, (uint32_t)i, (uint32_t)generation, 3u);
+            orc_buf b;
+            b.nodes = NULL; b.consts = NULL;
+            b.n = 0; b.nc = 0; b.cap = 0; b.ccap = 0; b.overflow = 0;
+            orc_rng probe = gd;                              /* size pass */
+            if (gen_one(&probe, &cfg, &b, method, min_depth, max_depth, min_len, init_max_len) != 0) return -1;
+            int64_t dn = b.n, dc = b.nc;
+            uint32_t *dw = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(dn > 0 ? dn : 1));
+            float *dv = (float *)malloc(sizeof(float) * (size_t)(dc > 0 ? dc : 1));
+            b.nodes = dw; b.cap = dn; b.consts = dv; b.ccap = dc; b.n = 0; b.nc = 0;
+            gen_one(&gd, &cfg, &b, method, min_depth, max_depth, min_len, init_max_len);
+            orc_prog don = prog_alloc(dn);
+            for (int64_t k = 0; k < dn; ++k) {
+                don.w[k] = dw[k];
+                don.v[k] = ((dw[k] & 0xffu) == O_CONST) ? dv[dw[k] >> 8] : 0.0f;
+            }
+            free(dw); free(dv);
+            child = hoisted_crossover(&par, &don, &g, max_len);
+            prog_free(&don);
+        } else if (ops[i] == 2) {
+            int64_t s = (int64_t)word_below(rng_word(&g), (uint32_t)par.n);
+            int64_t e = sub_end(par.w, s);
+            int64_t s2 = s + (int64_t)word_below(rng_word(&g), (uint32_t)(e - s));
+            int64_t e2 = sub_end(par.w, s2);
+            child = replace_subtree(&par, s, e, &par, s2, e2);
+        } else if (ops[i] == 3) {
+            child = prog_alloc(par.n);
+            int nconst = 0;
+            for (int64_t k = 0; k < par.n; ++k) {
+                child.w[k] = par.w[k]; child.v[k] = par.v[k];
+                if ((par.w[k] & 0xffu) == O_CONST) nconst++;
+            }
+            for (int64_t k = 0; k < child.n; ++k) {
+                float u = word_unit(rng_word(&g));
+                if (!(u < p_replace)) continue;
+                int op = (int)(child.w[k] & 0xffu);
+                int ar = op_arity(op);
+                if (ar == 1) {
+                    if (cfg.n_un == 0) continue;
+                    child.w[k] = (uint32_t)cfg.un[word_below(rng_word(&g), (uint32_t)cfg.n_un)];
+                } else if (ar == 2) {
+                    if (cfg.n_bin == 0) continue;
+                    child.w[k] = (uint32_t)cfg.bin[word_below(rng_word(&g), (uint32_t)cfg.n_bin)];
+                } else {
+                    int others = nconst - (op == O_CONST ? 1 : 0);
+                    int c_ok = cfg.consts_on && (cfg.max_consts <= 0 || others < cfg.max_consts);
+                    int pick = (int)word_below(rng_word(&g), (uint32_t)(cfg.n_features + (c_ok ? 1 : 0)));
+                    if (pick < cfg.n_features) {
+                        child.w[k] = (uint32_t)O_VAR | ((uint32_t)pick << 8);
+                        child.v[k] = 0.0f;
+                        nconst = others;
+                    } else {
+                        child.w[k] = (uint32_t)O_CONST;
+                        child.v[k] = draw_const(&g, &cfg);
+                        nconst = others + 1;
+                    }
+                }
+            }
+        } else {
+            child = prog_alloc(par.n);
+            for (int64_t k = 0; k < par.n; ++k) { child.w[k] = par.w[k]; child.v[k] = par.v[k]; }
+        }
+        prog_free(&par);
+        /* emit with constants renumbered in prefix order */
+        if (out_prog_off) out_prog_off[i] = nn;
+        if (out_const_off) out_const_off[i] = ncs;
+        if (out_len) out_len[i] = (int32_t)child.n;
+        int64_t slot = 0;
+        for (int64_t k = 0; k < child.n; ++k) {
+            uint32_t w = child.w[k];
+            if ((w & 0xffu) == O_CONST) {
+                if (out_consts && ncs + slot < consts_cap) out_consts[ncs + slot] = child.v[k];
+                else overflow = 1;
+                w = (uint32_t)O_CONST | ((uint32_t)slot << 8);
+                slot++;
+            }
+            if (out_nodes && nn + k < nodes_cap) out_nodes[nn + k] = w; else overflow = 1;
+        }
+        nn += child.n;
+        ncs += slot;
+        prog_free(&child);
+    }
+    if (out_prog_off) out_prog_off[n_offspring] = nn;
+    if (out_const_off) out_const_off[n_offspring] = ncs;
+    *total_nodes = nn;
+    *total_consts = ncs;
+    return overflow ? -2 : 0;
+}
+

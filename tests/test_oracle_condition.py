@@ -122,3 +122,59 @@ def test_near_threshold_flag():
     assert ra.near[0]
     X2 = np.array([[0.1], [0.0]], dtype=np.float32)
     assert not oracle.evaluate_pairs(pop, X2, [0], [0]).near[0]
+
+
+def _metric64(metric, v, y, w):
+    W = np.sum(w)
+    if metric == "mae":
+        return np.sum(w * np.abs(v - y)) / W
+    if metric in ("mse", "rmse"):
+        m = np.sum(w * (v - y) ** 2) / W
+        return np.sqrt(m) if metric == "rmse" else m
+    if metric == "logloss":
+        return np.sum(w * (np.maximum(v, 0) - y * v + np.log1p(np.exp(-np.abs(v))))) / W
+    a = v - np.sum(w * v) / W
+    b = y - np.sum(w * y) / W
+    return abs(np.sum(w * a * b) / np.sqrt(np.sum(w * a * a) * np.sum(w * b * b)))
+
+
+@pytest.mark.parametrize("metric", ["mae", "mse", "rmse", "logloss", "pearson"])
+def test_fitness_bound_dominates_row_displacements(metric):
+    """The fitness-level bound is the metric's propagation of the row bounds:
+    moving every row's value anywhere within its (pinned) bound moves the
+    fitness by at most the fitness bound, and the worst-case signs reach it."""
+    N = 400
+    X, y = synth.pagie(N, seed=3)
+    if metric == "logloss":
+        y = (y > np.median(y)).astype(np.float32)
+    w = synth.weights(N, seed=4)
+    fmask = oracle.DEFAULT_FMASK | (1 << TAN)
+    pop = oracle.build_population(30, 2, "exact_len", min_len=3, max_len=40, fmask=fmask, seed=77)
+    u = 1e-7
+    f32p, f64, fb, fn = oracle.fitness(pop, X, y, w, metric, with_bound=True, u=u)
+    rng = np.random.default_rng(5)
+    yd, wd = y.astype(np.float64), w.astype(np.float64)
+    checked = 0
+    for p in range(pop.n_programs):
+        ra = oracle.evaluate_pairs(pop, X, np.full(N, p, np.int32), np.arange(N), u=u)
+        v, E = ra.v32.astype(np.float64), ra.bound
+        if fn[p] or not (np.all(np.isfinite(v)) and np.all(np.isfinite(E))) or not np.isfinite(fb[p]):
+            continue
+        if fb[p] == 0.0 or fb[p] > 1e-3 * max(abs(f32p[p]), 1e-30):
+            continue   # constant programs; or outside the first-order regime
+        F0 = _metric64(metric, v, yd, wd)
+        for _ in range(10):
+            s = rng.choice([-1.0, 1.0], size=N)
+            F1 = _metric64(metric, v + s * E, yd, wd)
+            assert abs(F1 - F0) <= fb[p] * (1 + 1e-3) + 1e-12 * abs(F0), (metric, p)
+        checked += 1
+        if metric == "logloss":
+            # bounded with the loss's Lipschitz constant 1 while its slope
+            # |sigmoid(v) - y| may be far smaller: domination only
+            continue
+        # worst-case signs: along the derivative of the metric
+        h = 1e-6 * np.maximum(np.abs(v), 1.0)
+        g = np.array([(_metric64(metric, v + h * (np.arange(N) == r), yd, wd) - F0) for r in range(0, N, 1)])
+        F2 = _metric64(metric, v + np.sign(g) * E, yd, wd)
+        assert abs(F2 - F0) >= 0.5 * fb[p], (metric, p, abs(F2 - F0), fb[p])
+    assert checked >= 5
