@@ -183,6 +183,71 @@ gp_status gp_validate_population(const uint32_t* nodes, const int64_t* prog_off,
                                  int32_t* bad_program);
 
 /* ------------------------------------------------------------------ */
+/* Genetic operations on the host (Sec. II-A mutation list; Sec. III-C */
+/* pre-draw of operation types; Sec. III-C2 hoisted crossover).  Draws */
+/* come from Philox4x32-10 with key seed and counter (block, offspring */
+/* i, generation, 2), consumed in order; donor programs of subtree     */
+/* mutation from counter (block, i, generation, 3).                    */
+/* ------------------------------------------------------------------ */
+typedef enum {
+    GP_GENOP_CROSSOVER = 0,     /* 2 tournaments: parent, donor                    */
+    GP_GENOP_SUBTREE = 1,       /* crossover with a freshly generated donor        */
+    GP_GENOP_HOIST = 2,
+    GP_GENOP_POINT = 3,
+    GP_GENOP_REPRODUCTION = 4
+} gp_genetic_op;
+
+typedef struct {
+    float p_crossover;        /* operation probabilities, each in [0, 1]; the     */
+    float p_subtree;          /* float32 running sums crossover, subtree, hoist,  */
+    float p_hoist;            /* point must stay <= 1; reproduction takes the     */
+    float p_point;            /* rest                                              */
+    float p_point_replace;    /* per-node replacement probability (point)          */
+    int32_t max_len;          /* length bound of crossover children (>= 1)         */
+    uint64_t seed;
+} gp_evolve_params;
+
+/* The operation of every offspring (draw 0 of its stream: the first k with
+ * u < running sum k, else reproduction) and where its tournaments start in
+ * the winners array: first_tournament is the prefix sum of the tournaments
+ * each operation needs (crossover 2, others 1), *n_tournaments the total.
+ * ops and first_tournament are HOST arrays [n_offspring]. */
+gp_status gp_plan_generation(const gp_evolve_params* params, int32_t n_offspring, uint64_t generation,
+                             int32_t* ops, int32_t* first_tournament, int32_t* n_tournaments);
+
+/* Offspring i from parent winners[first_tournament[i]] (and, for crossover,
+ * donor winners[first_tournament[i] + 1]) of the HOST parent population:
+ *   crossover: a uniformly chosen subtree of the parent is replaced by a
+ *     uniformly chosen subtree of the donor (draws 1, 2); while the child's
+ *     stack height exceeds GP_MAX_STACK or its length max_len, the donor
+ *     subtree is replaced by a uniformly chosen proper subtree of itself (one
+ *     draw each) -- the hoisted crossover;
+ *   subtree: the same with a donor program generated by `init`'s method,
+ *     function set, depths or lengths and constants;
+ *   hoist: a uniformly chosen subtree is replaced by a uniformly chosen
+ *     subtree of itself (draws 1, 2);
+ *   point: each node in prefix order is replaced when its draw u <
+ *     p_point_replace: a function by one of the same arity (one draw), a
+ *     terminal by a variable or a new constant (one draw, and one for the
+ *     value; constants only while the program's others number below
+ *     init->max_consts);
+ *   reproduction: a copy.
+ * "Uniformly chosen subtree" means a uniformly chosen node position.
+ * Constants keep their values and are renumbered in prefix order.  Parents
+ * are validated first.  The offspring population goes to caller-owned HOST
+ * buffers with capacities nodes_cap / consts_cap (GP_ERR_BUFFER_TOO_SMALL
+ * with *total_nodes / *total_consts set if short); out_prog_off and
+ * out_const_off [n_offspring + 1], out_len [n_offspring]. */
+gp_status gp_mutate(const gp_evolve_params* params, const gp_init_params* init,
+                    const uint32_t* nodes, const int64_t* prog_off, const float* consts,
+                    const int64_t* const_off, int32_t n_parents, const int32_t* ops,
+                    const int32_t* first_tournament, const int32_t* winners, int32_t n_winners,
+                    int32_t n_offspring, uint64_t generation, uint32_t* out_nodes, int64_t nodes_cap,
+                    int64_t* out_prog_off, float* out_consts, int64_t consts_cap,
+                    int64_t* out_const_off, int32_t* out_len, int64_t* total_nodes,
+                    int64_t* total_consts);
+
+/* ------------------------------------------------------------------ */
 /* Device views                                                        */
 /* ------------------------------------------------------------------ */
 /* A flat population in DEVICE memory (Sec. III-A program struct, laid out
@@ -198,7 +263,8 @@ typedef struct {
     const int32_t* len;        /* [n_programs], len[p] = prog_off[p+1]-prog_off[p] */
     int32_t n_programs;
     int64_t total_nodes;
-    int32_t max_len;           /* an upper bound on every len[p] (host-known) */
+    int32_t max_len;           /* an upper bound on every len[p] (host-known)   */
+    int64_t total_consts;      /* const_off[n_programs] (host-known)            */
 } gp_population_dev;
 
 /* A dataset in DEVICE memory, feature-major (the paper's column-major
@@ -249,7 +315,11 @@ gp_status gp_tournament(const float* fitness, const int32_t* len, int32_t n_prog
  * log 1/a where |a| > 0.001 else 0, sqrt sign(a)/(2 sqrt|a|) (0 at a = 0),
  * sin cos a, cos -sin a, tan 1 + tan^2 a, neg -1.  Metrics MAE, MSE, RMSE,
  * LOGLOSS, PEARSON.  fitness_out [n_programs] (nullable) receives the
- * fitness as gp_fitness would.  All pointers DEVICE memory. */
+ * fitness as gp_fitness would.  All pointers DEVICE memory.  The population
+ * view must carry max_len and total_consts.  A program's constants in slots
+ * below 16 are summed in a fixed order (bit-reproducible); further slots are
+ * summed with float64 atomics.  Scratch grows with 2*max_len tape entries per
+ * wavefront (64 floats each). */
 gp_status gp_fitness_backward(const gp_population_dev* pop, const gp_dataset_dev* data,
                               gp_metric metric, const float* grad_fitness,
                               float* fitness_out, float* grad_consts, void* stream);
@@ -266,17 +336,99 @@ typedef struct {
     int32_t tiles_per_chunk;  /* >= 1: rows per work item = 64*rows_per_lane*this  */
 } gp_launch_config;
 
-/* The configuration gp_evaluate / gp_fitness would use for this shape on the
- * current device (the forced one if set, else the tuned one if cached, else
- * the built-in heuristic). */
+/* The configuration gp_fitness would use for this shape and metric on the
+ * current device: the forced one if set, else the tuned one if the autotuner
+ * has an entry for exactly (device, n_features, n_rows, n_programs, metric's
+ * kernel), else the built-in heuristic. */
 gp_status gp_get_launch_config(int32_t n_features, int64_t n_rows, int32_t n_programs,
-                               gp_launch_config* out);
+                               gp_metric metric, gp_launch_config* out);
 
 /* Force the configuration of every later gp_evaluate / gp_fitness call in this
  * process (all shapes); NULL returns to automatic selection.  Invalid values
  * give GP_ERR_INVALID_ARG; a feature_regs below a dataset's n_features makes
  * those calls fail with GP_ERR_INVALID_ARG. */
 gp_status gp_set_launch_config(const gp_launch_config* cfg);
+
+/* Autotuner (batching of uneven programs; not in the paper).  Times the
+ * fitness computation of this population under each candidate configuration
+ * -- rows_per_lane 1, 2, 4; feature registers that fit n_features, and 0;
+ * rows per work item from 1/4 to 2 times the heuristic's -- on the first
+ * min(n_rows, 2^20) rows, `repeats` timed runs after one warm-up each, and
+ * keeps the fastest for the full shape (device, n_features, n_rows,
+ * n_programs, metric's kernel), which gp_fitness and gp_generation_run then
+ * use unless a configuration is forced.  *best and *best_ms (nullable)
+ * receive the choice and its time on the row prefix.  Synchronizes `stream`
+ * and may allocate: not for use under stream capture.  Results are
+ * unchanged by the choice except for the float64 summation order across row
+ * chunks. */
+gp_status gp_autotune(const gp_population_dev* pop, const gp_dataset_dev* data,
+                      gp_metric metric, int32_t repeats, gp_launch_config* best,
+                      double* best_ms, void* stream);
+
+/* The tuned entries as JSON lines (one object per shape, keys arch, n_cu,
+ * n_features, n_rows, n_programs, kernel, rows_per_lane, feature_regs,
+ * tiles_per_chunk, ms); load merges a file written by save (a malformed line
+ * gives GP_ERR_INVALID_ARG and loads nothing); clear forgets every entry. */
+gp_status gp_autotune_save(const char* path);
+gp_status gp_autotune_load(const char* path);
+gp_status gp_autotune_clear(void);
+
+/* ------------------------------------------------------------------ */
+/* One generation as a HIP graph (batching; the paper's future-work    */
+/* item of fewer transfers, Sec. V).  The graph holds: one upload of   */
+/* the whole population from pinned host memory (instead of copies per */
+/* program, Sec. III-D2), the fitness computation of gp_fitness, the   */
+/* tournaments of gp_tournament (Sec. III-C1) and the download of      */
+/* fitness and winners.  It is captured on the first run, after the    */
+/* autotuner if asked, at the capacities given here, and replayed for  */
+/* every later generation; the generation number the tournaments use   */
+/* travels with the population.                                        */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_programs;        /* population size, fixed across generations (>= 1) */
+    int64_t node_capacity;     /* bound on sum(len) of any generation              */
+    int64_t const_capacity;    /* bound on the constants of any generation         */
+    int32_t metric;            /* gp_metric (not SPEARMAN)                          */
+    float parsimony;
+    int32_t tournament_size;   /* >= 1                                              */
+    int32_t n_tournaments;     /* winners per generation (>= 0)                     */
+    uint64_t seed;             /* Philox key of the tournaments                     */
+    int32_t autotune;          /* 1: tune on the first population (unless forced)  */
+    int32_t time_kernel;       /* 1: time the evaluation kernel inside the graph
+                                  (device wall clock read just before and after it) */
+} gp_generation_params;
+
+typedef struct gp_generation_s gp_generation;
+
+/* Allocates the pinned staging and result buffers (about node_capacity*4 +
+ * const_capacity*4 + 20*n_programs bytes on host and device), a stream of
+ * its own and a private scratch arena.  The dataset (DEVICE memory) must
+ * outlive the object. */
+gp_status gp_generation_create(const gp_generation_params* params, const gp_dataset_dev* data,
+                               gp_generation** out);
+
+/* Runs one generation on the HOST population given (same flat layout as
+ * gp_build_population, n_programs programs): validates it
+ * (gp_validate_population; GP_ERR_BUFFER_TOO_SMALL beyond the capacities),
+ * stages it, launches the graph, waits, and copies fitness[n_programs] and
+ * winners[n_tournaments] (HOST, nullable) out.  Winners equal those of
+ * gp_tournament(seed, generation) on the same fitness.  Calls on one object
+ * must not overlap; the device current at creation must be current. */
+gp_status gp_generation_run(gp_generation* gen, const uint32_t* nodes, const int64_t* prog_off,
+                            const float* consts, const int64_t* const_off, const int32_t* len,
+                            uint64_t generation, float* fitness, int32_t* winners);
+
+/* The launch configuration captured; the evaluation kernel's duration in the
+ * last run (ms, -1 unless time_kernel) measured by HIP event-record nodes
+ * placed around it in the graph (*timed_by_events = 1), or by the device
+ * clock if HIP refused those nodes (*timed_by_events = 0); the clock-stamp
+ * duration itself; and the autotuner's best time (ms on the row prefix, -1
+ * if not tuned).  Each output is nullable. */
+gp_status gp_generation_info(const gp_generation* gen, gp_launch_config* cfg, float* kernel_ms,
+                             float* clock_ms, int32_t* timed_by_events, double* tuned_ms);
+
+/* Waits for the object's work and frees it (NULL is ignored). */
+void gp_generation_destroy(gp_generation* gen);
 
 /* ------------------------------------------------------------------ */
 /* Kernel timing.  While enabled, the library brackets every launch of */

@@ -9,5 +9,9 @@ from ._binding import (  # noqa: F401
     DeviceDataset, DevicePopulation, GPError, HostPopulation, build_population, evaluate,
     fitness, fitness_backward, larger_is_better, metric_id, shutdown, tournament,
     validate_population, version, get_launch_config, set_launch_config,
-    profile_enable, profile_read, FUNCS_DEFAULT, MAX_STACK, METRICS, LIB_PATH,
+    profile_enable, profile_read, autotune, autotune_save, autotune_load, autotune_clear, Generation,
+    plan_generation, mutate, GENOPS,
+    FUNCS_DEFAULT, MAX_STACK, METRICS, LIB_PATH,
 )
+from .autograd import GPFitness, refine_constants  # noqa: F401,E402
+from .loop import run_generations, RunResult, GenerationLog  # noqa: F401,E402

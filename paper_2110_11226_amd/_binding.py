@@ -46,7 +46,8 @@ class InitParams(ctypes.Structure):
 
 class PopulationDev(ctypes.Structure):
     _fields_ = [("nodes", _vp), ("prog_off", _vp), ("consts", _vp), ("const_off", _vp),
-                ("len", _vp), ("n_programs", _i32), ("total_nodes", _i64), ("max_len", _i32)]
+                ("len", _vp), ("n_programs", _i32), ("total_nodes", _i64), ("max_len", _i32),
+                ("total_consts", _i64)]
 
 
 class DatasetDev(ctypes.Structure):
@@ -76,8 +77,38 @@ class LaunchConfig(ctypes.Structure):
     _fields_ = [("rows_per_lane", _i32), ("feature_regs", _i32), ("tiles_per_chunk", _i32)]
 
 
-_get_cfg = _sig("gp_get_launch_config", [_i32, _i64, _i32, ctypes.POINTER(LaunchConfig)])
+_get_cfg = _sig("gp_get_launch_config", [_i32, _i64, _i32, ctypes.c_int, ctypes.POINTER(LaunchConfig)])
 _set_cfg = _sig("gp_set_launch_config", [ctypes.POINTER(LaunchConfig)])
+_autotune = _sig("gp_autotune", [ctypes.POINTER(PopulationDev), ctypes.POINTER(DatasetDev), ctypes.c_int, _i32,
+                                  ctypes.POINTER(LaunchConfig), ctypes.POINTER(ctypes.c_double), _vp])
+_tune_save = _sig("gp_autotune_save", [ctypes.c_char_p])
+_tune_load = _sig("gp_autotune_load", [ctypes.c_char_p])
+_tune_clear = _sig("gp_autotune_clear", [])
+
+
+class GenerationParams(ctypes.Structure):
+    _fields_ = [("n_programs", _i32), ("node_capacity", _i64), ("const_capacity", _i64), ("metric", _i32),
+                ("parsimony", _f32), ("tournament_size", _i32), ("n_tournaments", _i32), ("seed", _u64),
+                ("autotune", _i32), ("time_kernel", _i32)]
+
+
+_gen_create = _sig("gp_generation_create", [ctypes.POINTER(GenerationParams), ctypes.POINTER(DatasetDev),
+                                            ctypes.POINTER(_vp)])
+_gen_run = _sig("gp_generation_run", [_vp, _vp, _vp, _vp, _vp, _vp, _u64, _vp, _vp])
+_gen_info = _sig("gp_generation_info", [_vp, ctypes.POINTER(LaunchConfig), ctypes.POINTER(_f32),
+                                        ctypes.POINTER(_f32), ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double)])
+_gen_destroy = _sig("gp_generation_destroy", [_vp], None)
+
+
+class EvolveParams(ctypes.Structure):
+    _fields_ = [("p_crossover", _f32), ("p_subtree", _f32), ("p_hoist", _f32), ("p_point", _f32),
+                ("p_point_replace", _f32), ("max_len", _i32), ("seed", _u64)]
+
+
+_plan = _sig("gp_plan_generation", [ctypes.POINTER(EvolveParams), _i32, _u64, _vp, _vp, _vp])
+_mutate = _sig("gp_mutate", [ctypes.POINTER(EvolveParams), ctypes.POINTER(InitParams), _vp, _vp, _vp, _vp, _i32,
+                             _vp, _vp, _vp, _i32, _i32, _u64, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp])
+GENOPS = {"crossover": 0, "subtree": 1, "hoist": 2, "point": 3, "reproduction": 4}
 class Profile(ctypes.Structure):
     _fields_ = [("launches", _i64), ("total_ms", ctypes.c_double), ("node_rows", _i64)]
 
@@ -90,7 +121,9 @@ _backward = _sig("gp_fitness_backward", [ctypes.POINTER(PopulationDev), ctypes.P
 EXPORTED = ["gp_last_error", "gp_version", "gp_shutdown", "gp_metric_larger_is_better",
             "gp_build_population", "gp_validate_population", "gp_evaluate", "gp_fitness",
             "gp_tournament", "gp_fitness_backward", "gp_get_launch_config", "gp_set_launch_config",
-            "gp_profile_enable", "gp_profile_read"]
+            "gp_profile_enable", "gp_profile_read", "gp_autotune", "gp_autotune_save", "gp_autotune_load",
+            "gp_autotune_clear", "gp_generation_create", "gp_generation_run", "gp_generation_info",
+            "gp_generation_destroy", "gp_plan_generation", "gp_mutate"]
 
 
 def profile_enable(on=True):
@@ -104,10 +137,32 @@ def profile_read():
     return int(p.launches), float(p.total_ms), int(p.node_rows)
 
 
-def get_launch_config(n_features, n_rows, n_programs):
+def get_launch_config(n_features, n_rows, n_programs, metric="mse"):
     c = LaunchConfig()
-    _check(_get_cfg(n_features, n_rows, n_programs, ctypes.byref(c)), "gp_get_launch_config")
+    _check(_get_cfg(n_features, n_rows, n_programs, metric_id(metric), ctypes.byref(c)), "gp_get_launch_config")
     return (c.rows_per_lane, c.feature_regs, c.tiles_per_chunk)
+
+
+def autotune(pop, data, metric="mse", repeats=2, stream=None):
+    """Times candidate launch configurations (see gp_autotune); returns
+    ((rows_per_lane, feature_regs, tiles_per_chunk), best_ms)."""
+    c = LaunchConfig()
+    ms = ctypes.c_double(-1.0)
+    _check(_autotune(ctypes.byref(pop.view), ctypes.byref(data.view), metric_id(metric), int(repeats),
+                     ctypes.byref(c), ctypes.byref(ms), _stream(stream)), "gp_autotune")
+    return (c.rows_per_lane, c.feature_regs, c.tiles_per_chunk), float(ms.value)
+
+
+def autotune_save(path):
+    _check(_tune_save(os.fsencode(path)), "gp_autotune_save")
+
+
+def autotune_load(path):
+    _check(_tune_load(os.fsencode(path)), "gp_autotune_load")
+
+
+def autotune_clear():
+    _check(_tune_clear(), "gp_autotune_clear")
 
 
 def set_launch_config(cfg=None):
@@ -243,7 +298,7 @@ class DevicePopulation:
     def make_view(self, consts):
         return PopulationDev(self.nodes.data_ptr(), self.prog_off.data_ptr(), consts.data_ptr(),
                              self.const_off.data_ptr(), self.length.data_ptr(), self.n_programs,
-                             int(self.host.nodes.shape[0]), self.max_len)
+                             int(self.host.nodes.shape[0]), self.max_len, self.n_consts)
 
 
 class DeviceDataset:
@@ -276,11 +331,12 @@ def evaluate(pop: DevicePopulation, data: DeviceDataset, out=None, stream=None):
     return out
 
 
-def fitness(pop: DevicePopulation, data: DeviceDataset, metric="mse", out=None, stream=None):
+def fitness(pop: DevicePopulation, data: DeviceDataset, metric="mse", out=None, stream=None, consts=None):
     torch = _torch()
     if out is None:
         out = torch.empty(pop.n_programs, dtype=torch.float32, device=data.X.device)
-    _check(_fitness(ctypes.byref(pop.view), ctypes.byref(data.view), metric_id(metric), _tptr(out),
+    view = pop.view if consts is None else pop.make_view(consts)
+    _check(_fitness(ctypes.byref(view), ctypes.byref(data.view), metric_id(metric), _tptr(out),
                     _stream(stream)), "gp_fitness")
     return out
 
@@ -308,3 +364,126 @@ def fitness_backward(pop: DevicePopulation, data: DeviceDataset, metric="mse", g
     _check(_backward(ctypes.byref(view), ctypes.byref(data.view), metric_id(metric), _tptr(grad_fitness),
                      _tptr(fitness_out), _tptr(grad_out), _stream(stream)), "gp_fitness_backward")
     return grad_out[:pop.n_consts]
+
+
+class Generation:
+    """One generation as a captured HIP graph (gp_generation_*): upload of the
+    host population, fitness, tournaments, download of fitness and winners."""
+
+    def __init__(self, data: DeviceDataset, n_programs, node_capacity, const_capacity, metric="mse",
+                 parsimony=0.0, tournament_size=20, n_tournaments=None, seed=0, autotune=False,
+                 time_kernel=False):
+        self.data = data          # the dataset must outlive the graph
+        self.n_programs = int(n_programs)
+        self.n_tournaments = self.n_programs if n_tournaments is None else int(n_tournaments)
+        prm = GenerationParams(self.n_programs, int(node_capacity), int(const_capacity), metric_id(metric),
+                               float(parsimony), int(tournament_size), self.n_tournaments, int(seed),
+                               1 if autotune else 0, 1 if time_kernel else 0)
+        h = _vp()
+        _check(_gen_create(ctypes.byref(prm), ctypes.byref(data.view), ctypes.byref(h)), "gp_generation_create")
+        self._h = h
+
+    def run(self, pop: HostPopulation, generation):
+        """(fitness float32 [P], winners int32 [T]) as numpy arrays."""
+        if pop.n_programs != self.n_programs:
+            raise ValueError("population size differs from the one the graph was built for")
+        nodes = np.ascontiguousarray(pop.nodes, np.uint32)
+        po = np.ascontiguousarray(pop.prog_off, np.int64)
+        c = np.ascontiguousarray(pop.consts, np.float32)
+        co = np.ascontiguousarray(pop.const_off, np.int64)
+        ln = np.ascontiguousarray(pop.length, np.int32)
+        fit = np.empty(self.n_programs, np.float32)
+        win = np.empty(max(self.n_tournaments, 1), np.int32)
+        _check(_gen_run(self._h, _np_ptr(nodes), _np_ptr(po), _np_ptr(c) if c.shape[0] else None, _np_ptr(co),
+                        _np_ptr(ln), int(generation), _np_ptr(fit), _np_ptr(win)), "gp_generation_run")
+        return fit, win[:self.n_tournaments]
+
+    def info(self):
+        """((rows_per_lane, feature_regs, tiles_per_chunk), kernel_ms of the last run, tuned_ms)."""
+        d = self.timing()
+        return d["launch"], d["kernel_ms"], d["tuned_ms"]
+
+    def timing(self):
+        """Launch configuration, the evaluation kernel's last duration (HIP
+        event nodes if the graph holds them, else the device clock), the
+        clock-stamp duration, which method timed it, and the tuned time."""
+        c = LaunchConfig()
+        k = _f32(-1.0)
+        ck = _f32(-1.0)
+        ev = _i32(0)
+        t = ctypes.c_double(-1.0)
+        _check(_gen_info(self._h, ctypes.byref(c), ctypes.byref(k), ctypes.byref(ck), ctypes.byref(ev),
+                         ctypes.byref(t)), "gp_generation_info")
+        return {"launch": (c.rows_per_lane, c.feature_regs, c.tiles_per_chunk), "kernel_ms": float(k.value),
+                "clock_ms": float(ck.value), "timed_by": "hip_events" if ev.value else "device_clock",
+                "tuned_ms": float(t.value)}
+
+    def close(self):
+        if self._h:
+            _gen_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _evolve_struct(p_crossover=0.7, p_subtree=0.1, p_hoist=0.05, p_point=0.1, p_point_replace=0.05,
+                   max_len=4096, seed=0):
+    return EvolveParams(p_crossover, p_subtree, p_hoist, p_point, p_point_replace, max_len, seed)
+
+
+def _init_struct(n_features, method="rhh", min_depth=2, max_depth=6, min_len=1, max_len=200,
+                 function_mask=FUNCS_DEFAULT, const_lo=-1.0, const_hi=1.0, max_consts=0, seed=0):
+    return InitParams(0, n_features, INIT[method] if isinstance(method, str) else int(method), min_depth,
+                      max_depth, min_len, max_len, function_mask, const_lo, const_hi, max_consts, seed)
+
+
+def plan_generation(n_offspring, generation, **evolve):
+    """(ops, first_tournament, n_tournaments): the operation of every
+    offspring and where its tournaments start (gp_plan_generation)."""
+    ev = _evolve_struct(**evolve)
+    ops = np.zeros(max(n_offspring, 1), np.int32)
+    ft = np.zeros(max(n_offspring, 1), np.int32)
+    nt = np.zeros(1, np.int32)
+    _check(_plan(ctypes.byref(ev), int(n_offspring), int(generation), _np_ptr(ops), _np_ptr(ft), _np_ptr(nt)),
+           "gp_plan_generation")
+    return ops[:n_offspring], ft[:n_offspring], int(nt[0])
+
+
+def mutate(parents: HostPopulation, ops, first_tournament, winners, generation, init: dict, **evolve):
+    """The offspring population (gp_mutate).  init: the initialisation
+    settings (n_features, method, depths/lengths, function_mask, constants)
+    that donors of subtree mutation follow."""
+    ev = _evolve_struct(**evolve)
+    ip = _init_struct(**init)
+    n_off = int(len(ops))
+    ops = np.ascontiguousarray(ops, np.int32)
+    ft = np.ascontiguousarray(first_tournament, np.int32)
+    win = np.ascontiguousarray(winners, np.int32)
+    longest = int(parents.length.max(initial=1))
+    cap = max(n_off * max(int(ev.max_len), longest, 1), 1)
+    nodes = np.zeros(cap, np.uint32)
+    consts = np.zeros(cap, np.float32)
+    po = np.zeros(n_off + 1, np.int64)
+    co = np.zeros(n_off + 1, np.int64)
+    ln = np.zeros(max(n_off, 1), np.int32)
+    tn = np.zeros(1, np.int64)
+    tc = np.zeros(1, np.int64)
+    pn = np.ascontiguousarray(parents.nodes, np.uint32)
+    pc = np.ascontiguousarray(parents.consts if parents.consts.shape[0] else np.zeros(1, np.float32), np.float32)
+    args = [ctypes.byref(ev), ctypes.byref(ip), _np_ptr(pn), _np_ptr(np.ascontiguousarray(parents.prog_off, np.int64)),
+            _np_ptr(pc), _np_ptr(np.ascontiguousarray(parents.const_off, np.int64)), parents.n_programs,
+            _np_ptr(ops), _np_ptr(ft), _np_ptr(win), int(win.shape[0]), n_off, int(generation)]
+    rc = _mutate(*args, _np_ptr(nodes), cap, _np_ptr(po), _np_ptr(consts), cap, _np_ptr(co), _np_ptr(ln),
+                 _np_ptr(tn), _np_ptr(tc))
+    if rc == -7:   # GP_ERR_BUFFER_TOO_SMALL: retry at the reported size
+        nodes = np.zeros(max(int(tn[0]), 1), np.uint32)
+        consts = np.zeros(max(int(tc[0]), 1), np.float32)
+        rc = _mutate(*args, _np_ptr(nodes), nodes.shape[0], _np_ptr(po), _np_ptr(consts), consts.shape[0],
+                     _np_ptr(co), _np_ptr(ln), _np_ptr(tn), _np_ptr(tc))
+    _check(rc, "gp_mutate")
+    return HostPopulation(nodes[:int(tn[0])].copy(), po, consts[:int(tc[0])].copy(), co, ln[:n_off].copy())
+

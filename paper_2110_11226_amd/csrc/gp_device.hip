@@ -24,7 +24,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <new>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -85,7 +88,7 @@ struct Sched {
 //             the second operand), kBin (binary: top op next-below), kUn
 //   bits 2-4  function: binary ADD..DIV as 0..3, unary NEG..TAN as 0..5
 //   bit 5     the terminal is a constant (value in y) rather than a feature
-//   bits 8-31 feature index
+//   bits 8-31 feature index, or the constant's slot
 // ---------------------------------------------------------------------------
 enum : uint32_t { kPush = 0, kFold = 1, kBin = 2, kUn = 3 };
 
@@ -213,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint2* __restri
         if (op <= GP_OP_CONST) {
             const uint32_t is_c = op == GP_OP_CONST ? 1u : 0u;
             const uint32_t val = is_c ? __float_as_uint(pc[arg]) : 0u;
-            const uint32_t farg = is_c ? 0u : arg;
+            const uint32_t farg = arg;   // feature index, or constant slot (used by the adjoint)
             const uint32_t prev = i >= 1 ? (pn[i - 1] & 0xffu) : 0u;
             if (i >= 1 && i != L - 1 && prev >= GP_OP_ADD && prev <= GP_OP_DIV) {
                 out[k++] = make_uint2(enc(kFold, prev - GP_OP_ADD, is_c, farg), val);
@@ -547,11 +550,18 @@ __device__ __forceinline__ Moments shfl_moments(const Moments& m, int src) {
     return r;
 }
 
+// stats (nullable) receives per program: [0] sum of weights W, [1] mean of
+// yhat, [2] mean of y, [3] sum w (yhat - mean)^2, [4] sum w (y - mean)^2,
+// [5] sum w (yhat - mean)(y - mean), [6] the metric in float64 (Pearson: the
+// signed r), [7] unused.
+constexpr int kStats = 8;
+
 template <int METRIC>
 __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ part,
                                                       const double* __restrict__ ystat,
                                                       int32_t n_chunks, int32_t P, int64_t N,
-                                                      int has_w, float* __restrict__ fitness) {
+                                                      int has_w, float* __restrict__ fitness,
+                                                      double* __restrict__ stats) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t p = static_cast<int64_t>(blockIdx.x) * (kBlock / kWave) + (threadIdx.x >> 6);
     if (p >= P) return;
@@ -576,8 +586,13 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
         if (lane == 0) {
             const double va = m.Maa, vb = m.Mbb;
             double r = 0.0;
-            if (va > 0.0 && vb > 0.0 && isfinite(va) && isfinite(vb)) r = fabs(m.Mab / sqrt(va * vb));
-            fitness[p] = static_cast<float>(r);
+            if (va > 0.0 && vb > 0.0 && isfinite(va) && isfinite(vb)) r = m.Mab / sqrt(va * vb);
+            fitness[p] = static_cast<float>(fabs(r));
+            if (stats) {
+                double* o = stats + p * kStats;
+                o[0] = m.W; o[1] = m.ma; o[2] = m.mb; o[3] = m.Maa; o[4] = m.Mbb; o[5] = m.Mab;
+                o[6] = r; o[7] = 0.0;
+            }
         }
     } else {
         double s = 0.0, sw = 0.0;
@@ -591,8 +606,392 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
             double v = s / sw;
             if constexpr (METRIC == GP_METRIC_RMSE) v = sqrt(v);
             fitness[p] = static_cast<float>(v);
+            if (stats) {
+                double* o = stats + p * kStats;
+                o[0] = sw; o[1] = o[2] = o[3] = o[4] = o[5] = 0.0; o[6] = v; o[7] = 0.0;
+            }
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// k_adjoint: derivative of every program's fitness with respect to each of
+// its constants (not in the paper), by reverse mode over the compiled
+// instructions, one wavefront per (row chunk, program) work item.
+//
+// Per tile of 64*R rows: a forward pass runs the stack machine and records
+// on a tape the operands that the local derivatives need (both operands of a
+// product or quotient; the input of log, sqrt, sin, cos, tan); the seed is
+// d fitness / d yhat of each row; a reverse pass walks the instructions back
+// with an adjoint stack that mirrors the value stack and, at each constant,
+// adds its adjoint into a per-lane float64 accumulator in LDS.  The tape is
+// the only per-row data written to memory: a per-wavefront area that is
+// written once and read back once, in reverse, mostly from L2 (the forward
+// values are recomputed per tile, not kept).  Local derivatives (reading): add (1,1),
+// sub (1,-1), mul (b,a), div (1/b, -a/b^2) if |b| > 0.001 else (0,0),
+// log 1/a if |a| > 0.001 else 0, sqrt sign(a)/(2 sqrt|a|) (0 at a = 0),
+// sin cos a, cos -sin a, tan 1 + tan^2 a, neg -1.
+// ---------------------------------------------------------------------------
+constexpr int kGradLds = 16;   // constants per program accumulated in LDS
+
+// tape entries an instruction records (0, 1 or 2)
+__device__ __forceinline__ int tape_entries(uint32_t cls, uint32_t fn) {
+    if (cls == kPush) return 0;
+    if (cls == kUn) return fn == 0 ? 0 : 1;           // neg needs nothing
+    return fn >= 2 ? 2 : 0;                           // mul / div need both operands
+}
+
+template <int R, int FREG, int METRIC>
+__global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, DataView d, Sched s,
+                                                    const double* __restrict__ stats,
+                                                    const double* __restrict__ wsum,
+                                                    const float* __restrict__ gscale,
+                                                    double* __restrict__ part,
+                                                    double* __restrict__ gpart,
+                                                    double* __restrict__ gextra,
+                                                    float* __restrict__ tape_ovf,
+                                                    int64_t ovf_entries) {
+    constexpr int FA = FREG > 0 ? FREG : 1;
+    const int lane = threadIdx.x;
+    const int64_t N = d.N;
+    const int64_t ld = d.ld;
+    const float* __restrict__ X = d.X;
+    __shared__ double gl[kGradLds * kWave];
+    __shared__ float ovf[kStackLds * R * kWave];
+    __shared__ float aovf[kStackLds * R * kWave];
+    // this wavefront's tape: entry e of row slot j at tape[(e * R + j) * 64 + lane]
+    float* __restrict__ tape = tape_ovf + static_cast<int64_t>(blockIdx.x) * ovf_entries * R * kWave;
+    const double W = *wsum;
+
+    for (;;) {
+        uint32_t it32 = 0;
+        if (lane == 0) it32 = atomicAdd(s.counter, 1u);
+        const int64_t it = static_cast<int64_t>(__builtin_amdgcn_readlane(static_cast<int>(it32), 0));
+        if (it >= s.n_items) break;
+        const int32_t c = static_cast<int32_t>(it / pop.P);
+        const int32_t k = static_cast<int32_t>(it - static_cast<int64_t>(c) * pop.P);
+        const int32_t p = ldu(s.order + k);
+        const int64_t off = ldu(pop.prog_off + p);
+        const int32_t CL = ldu(cv.clen + p);
+        const int64_t cbase = ldu(pop.const_off + p);
+        const int32_t nconst = static_cast<int32_t>(ldu(pop.const_off + p + 1) - cbase);
+        const uint2* __restrict__ pcode = cv.code + off;
+        const int64_t r0 = static_cast<int64_t>(c) * s.chunk;
+        const int64_t r1 = min(r0 + s.chunk, N);
+        const float gsc = gscale ? ldu(gscale + p) : 1.0f;
+        double sm0 = 0.0, sm1 = 0.0, sm2 = 0.0, sm3 = 0.0, sm4 = 0.0, sm5 = 0.0, sm6 = 0.0;
+        if (stats) {
+            sm0 = stats[p * kStats + 0]; sm1 = stats[p * kStats + 1]; sm2 = stats[p * kStats + 2];
+            sm3 = stats[p * kStats + 3]; sm4 = stats[p * kStats + 4]; sm5 = stats[p * kStats + 5];
+            sm6 = stats[p * kStats + 6];
+        }
+        (void)sm0; (void)sm5;
+        const int nlds = min(nconst, kGradLds);
+        for (int q = 0; q < nlds; ++q) gl[q * kWave + lane] = 0.0;
+        double lacc = 0.0;
+
+        for (int64_t base = r0; base < r1; base += kWave * R) {
+            int64_t row[R];
+            bool valid[R];
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int64_t r = base + j * kWave + lane;
+                valid[j] = r < r1;
+                row[j] = valid[j] ? r : r1 - 1;
+            }
+            GP_ARRAYS(xa, FA);
+            if constexpr (FREG > 0) {
+#pragma unroll
+                for (int f = 0; f < FREG; ++f) {
+                    if (f < d.F) {
+                        xa0[f] = X[f * ld + row[0]];
+                        if constexpr (R > 1) xa1[f] = X[f * ld + row[1]];
+                    }
+                }
+            }
+            // ---------------- forward pass, recording the tape ----------------
+            float t[R];
+#pragma unroll
+            for (int j = 0; j < R; ++j) t[j] = 0.0f;
+            GP_ARRAYS(st, kStackRegs + 1);
+            int dp = -1;
+            int ntape = 0;
+            uint2 nxt = pcode[0];
+            for (int q = 0; q < CL; ++q) {
+                const uint2 cur = nxt;
+                nxt = pcode[min(q + 1, CL - 1)];
+                const uint32_t w = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(cur.x)));
+                const uint32_t cls = w & 3u;
+                const uint32_t fn = (w >> 2) & 7u;
+                GP_PUT(st, min(dp + 1, kStackRegs), t);
+                float a[R], b[R];
+                if (cls == kUn) {
+#pragma unroll
+                    for (int j = 0; j < R; ++j) a[j] = b[j] = t[j];
+                } else if (cls == kBin) {
+                    if (dp < kStackRegs) {
+                        GP_GET(st, dp, b);
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < R; ++j) b[j] = ovf[((dp - kStackRegs) * R + j) * kWave + lane];
+                    }
+                    --dp;
+#pragma unroll
+                    for (int j = 0; j < R; ++j) a[j] = t[j];
+                } else {
+                    float v[R];
+                    if (w & 32u) {
+                        const float cval = __uint_as_float(cur.y);
+#pragma unroll
+                        for (int j = 0; j < R; ++j) v[j] = cval;
+                    } else if constexpr (FREG > 0) {
+                        const uint32_t arg = w >> 8;
+                        v[0] = xa0[arg];
+                        if constexpr (R > 1) v[1] = xa1[arg];
+                    } else {
+                        const float* __restrict__ col = X + static_cast<int64_t>(w >> 8) * ld;
+#pragma unroll
+                        for (int j = 0; j < R; ++j) v[j] = col[row[j]];
+                    }
+                    if (cls == kPush) {
+                        ++dp;
+                        if (dp >= kStackRegs) {
+#pragma unroll
+                            for (int j = 0; j < R; ++j) ovf[((dp - kStackRegs) * R + j) * kWave + lane] = t[j];
+                        }
+#pragma unroll
+                        for (int j = 0; j < R; ++j) t[j] = v[j];
+                        continue;
+                    }
+#pragma unroll
+                    for (int j = 0; j < R; ++j) {
+                        a[j] = v[j];
+                        b[j] = t[j];
+                    }
+                }
+                // record: entry ntape = a, entry ntape+1 = b (as needed)
+                const int ne = tape_entries(cls, fn);
+                if (ne > 0) {
+#pragma unroll
+                    for (int j = 0; j < R; ++j) tape[(ntape * R + j) * kWave + lane] = a[j];
+                    if (ne == 2) {
+#pragma unroll
+                        for (int j = 0; j < R; ++j) tape[((ntape + 1) * R + j) * kWave + lane] = b[j];
+                    }
+                }
+                ntape += ne;
+                if (cls == kUn) {
+                    apply_unary<R>(fn, t);
+                } else {
+                    apply_binary<R>(fn, a, b);
+#pragma unroll
+                    for (int j = 0; j < R; ++j) t[j] = a[j];
+                }
+            }
+
+            // ---------------- seeds: d fitness / d yhat per row ----------------
+            float g[R];
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const double yh = static_cast<double>(t[j]);
+                const double yv = static_cast<double>(d.y[row[j]]);
+                const double wv = d.w ? static_cast<double>(d.w[row[j]]) : 1.0;
+                double sd;
+                if constexpr (METRIC == GP_METRIC_MSE) {
+                    const double e = yh - yv;
+                    sd = 2.0 * wv * e / W;
+                    lacc += valid[j] ? wv * (e * e) : 0.0;
+                } else if constexpr (METRIC == GP_METRIC_RMSE) {
+                    const double e = yh - yv;
+                    sd = sm6 > 0.0 ? (wv * e / W) / sm6 : 0.0;
+                } else if constexpr (METRIC == GP_METRIC_MAE) {
+                    const double e = yh - yv;
+                    sd = wv * (e > 0.0 ? 1.0 : (e < 0.0 ? -1.0 : 0.0)) / W;
+                    lacc += valid[j] ? wv * fabs(e) : 0.0;
+                } else if constexpr (METRIC == GP_METRIC_LOGLOSS) {
+                    const float z = t[j];
+                    const float yf = d.y[row[j]];
+                    const float t1 = fmaxf(z, 0.0f);
+                    const float t2 = yf * z;
+                    const float t3 = t1 - t2;
+                    const float t5 = log1pf(expf(-fabsf(z)));
+                    lacc += valid[j] ? wv * static_cast<double>(t3 + t5) : 0.0;
+                    sd = wv * (1.0 / (1.0 + exp(-yh)) - yv) / W;
+                } else {  // PEARSON: d|r|/dyhat
+                    const double va = sm3, vb = sm4, rr = sm6;
+                    if (va > 0.0 && vb > 0.0 && isfinite(va) && isfinite(vb)) {
+                        const double dr = wv * ((yv - sm2) / sqrt(va * vb) - rr * (yh - sm1) / va);
+                        sd = rr >= 0.0 ? dr : -dr;
+                    } else {
+                        sd = 0.0;
+                    }
+                }
+                g[j] = valid[j] ? static_cast<float>(sd) * gsc : 0.0f;
+            }
+
+            // ---------------- reverse pass ----------------
+            GP_ARRAYS(as, kStackRegs + 1);   // adjoints of the entries below the top
+            int ad = dp;                     // mirrors the value stack (dp == 0 here)
+            int q = CL - 1;
+            uint2 prv = pcode[q];
+            for (; q >= 0; --q) {
+                const uint2 cur = prv;
+                prv = pcode[max(q - 1, 0)];
+                const uint32_t w = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(cur.x)));
+                const uint32_t cls = w & 3u;
+                const uint32_t fn = (w >> 2) & 7u;
+                const int ne = tape_entries(cls, fn);
+                ntape -= ne;
+                float a[R], b[R];
+#pragma unroll
+                for (int j = 0; j < R; ++j) a[j] = b[j] = 0.0f;
+                if (ne > 0) {
+#pragma unroll
+                    for (int j = 0; j < R; ++j) a[j] = tape[(ntape * R + j) * kWave + lane];
+                    if (ne == 2) {
+#pragma unroll
+                        for (int j = 0; j < R; ++j) b[j] = tape[((ntape + 1) * R + j) * kWave + lane];
+                    }
+                }
+                float gb[R];   // adjoint handed to the entry below the top (binary only)
+#pragma unroll
+                for (int j = 0; j < R; ++j) gb[j] = 0.0f;
+                float gc[R];   // adjoint of the terminal (push / fold)
+#pragma unroll
+                for (int j = 0; j < R; ++j) gc[j] = 0.0f;
+                if (cls == kUn) {
+#pragma unroll
+                    for (int j = 0; j < R; ++j) {
+                        const float x = a[j];
+                        float dfx;
+                        switch (fn) {
+                        case 0: dfx = -1.0f; break;
+                        case 1: dfx = fabsf(x) > GP_PROTECT_EPS ? 1.0f / x : 0.0f; break;
+                        case 2: dfx = x == 0.0f ? 0.0f : copysignf(1.0f, x) / (2.0f * sqrtf(fabsf(x))); break;
+                        case 3: dfx = cosf(x); break;
+                        case 4: dfx = -sinf(x); break;
+                        default: { const float tx = tanf(x); dfx = 1.0f + tx * tx; } break;
+                        }
+                        g[j] = g[j] * dfx;
+                    }
+                } else if (cls == kPush) {
+#pragma unroll
+                    for (int j = 0; j < R; ++j) gc[j] = g[j];
+                } else {
+                    // binary: operands (a, b); fold: a is the terminal, b the old top
+                    float ga[R];
+#pragma unroll
+                    for (int j = 0; j < R; ++j) {
+                        float da, db;
+                        switch (fn) {
+                        case 0: da = 1.0f; db = 1.0f; break;
+                        case 1: da = 1.0f; db = -1.0f; break;
+                        case 2: da = b[j]; db = a[j]; break;
+                        default:
+                            if (fabsf(b[j]) > GP_PROTECT_EPS) {
+                                const float inv = 1.0f / b[j];
+                                da = inv;
+                                db = -a[j] * inv * inv;
+                            } else {
+                                da = 0.0f;
+                                db = 0.0f;
+                            }
+                            break;
+                        }
+                        ga[j] = g[j] * da;
+                        gb[j] = g[j] * db;
+                    }
+                    if (cls == kBin) {
+#pragma unroll
+                        for (int j = 0; j < R; ++j) g[j] = ga[j];
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < R; ++j) {
+                            gc[j] = ga[j];
+                            g[j] = gb[j];
+                        }
+                    }
+                }
+                // adjoint stack: a binary hands gb to the (restored) entry below
+                GP_PUT(as, min(ad + 1, kStackRegs), gb);
+                if (cls == kBin) {
+                    ++ad;
+                    if (ad >= kStackRegs) {
+#pragma unroll
+                        for (int j = 0; j < R; ++j) aovf[((ad - kStackRegs) * R + j) * kWave + lane] = gb[j];
+                    }
+                }
+                // a constant terminal collects its adjoint
+                if (cls <= kFold && (w & 32u)) {
+                    const int slot = static_cast<int>(w >> 8);
+                    double sum = 0.0;
+#pragma unroll
+                    for (int j = 0; j < R; ++j) sum += valid[j] ? static_cast<double>(gc[j]) : 0.0;
+                    if (slot < kGradLds) {
+                        gl[slot * kWave + lane] += sum;
+                    } else {
+                        const double tot = wave_sum(sum);
+                        if (lane == 0) atomicAdd(gextra + cbase + slot, tot);
+                    }
+                }
+                // a push is undone: the entry below becomes the top again
+                if (cls == kPush) {
+                    if (ad >= 0) {
+                        if (ad < kStackRegs) {
+                            GP_GET(as, ad, g);
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < R; ++j) g[j] = aovf[((ad - kStackRegs) * R + j) * kWave + lane];
+                        }
+                    }
+                    --ad;
+                }
+            }
+        }
+        // ---------------- per-item reductions ----------------
+        for (int q = 0; q < nlds; ++q) {
+            const double v = wave_sum(gl[q * kWave + lane]);
+            if (lane == 0) gpart[(cbase + q) * s.n_chunks + c] = v;
+        }
+        if (part) {
+            lacc = wave_sum(lacc);
+            if (lane == 0) part[static_cast<int64_t>(p) * s.n_chunks + c] = lacc;
+        }
+    }
+}
+
+// grad[i] = sum over chunks of gpart[i * n_chunks + c] (fixed order) plus
+// gextra[i]; one lane per constant.
+__global__ __launch_bounds__(kBlock) void k_finalize_grad(const double* __restrict__ gpart,
+                                                           const double* __restrict__ gextra,
+                                                           const int64_t* __restrict__ const_off,
+                                                           int32_t P, int32_t n_chunks,
+                                                           float* __restrict__ grad) {
+    const int32_t p = static_cast<int32_t>(blockIdx.x) * (kBlock / kWave) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & (kWave - 1);
+    if (p >= P) return;
+    const int64_t c0 = const_off[p], c1 = const_off[p + 1];
+    for (int64_t i = c0 + lane; i < c1; i += kWave) {
+        double sum = gextra[i];
+        if (i - c0 < kGradLds)
+            for (int c = 0; c < n_chunks; ++c) sum += gpart[i * n_chunks + c];
+        grad[i] = static_cast<float>(sum);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero(double* __restrict__ p, int64_t n) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+// sum of weights over all rows (float64), from the per-chunk statistics
+__global__ __launch_bounds__(kWave) void k_wsum(const double* __restrict__ ystat, int32_t n_chunks,
+                                                 int has_w, int64_t N, double* __restrict__ out) {
+    double s = 0.0;
+    if (has_w)
+        for (int c = threadIdx.x; c < n_chunks; c += kWave) s += ystat[static_cast<int64_t>(c) * 4];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) *out = has_w ? s : static_cast<double>(N);
 }
 
 // ---------------------------------------------------------------------------
@@ -601,10 +1000,13 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
 __global__ __launch_bounds__(kBlock) void k_tournament(const float* __restrict__ fit,
                                                         const int32_t* __restrict__ len,
                                                         int32_t P, int larger, float c, int32_t k,
-                                                        int32_t T, uint64_t seed, uint32_t gen,
+                                                        int32_t T, uint64_t seed, uint32_t gen_value,
+                                                        const uint32_t* __restrict__ gen_dev,
                                                         int32_t* __restrict__ winners) {
     const int32_t t = static_cast<int32_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (t >= T) return;
+    // a captured generation graph reads the generation number from memory
+    const uint32_t gen = gen_dev ? *gen_dev : gen_value;
     int32_t best = -1;
     float best_adj = 0.0f;
     Philox4 blk{};
@@ -626,6 +1028,12 @@ __global__ __launch_bounds__(kBlock) void k_tournament(const float* __restrict__
         }
     }
     winners[t] = best;
+}
+
+// k_stamp: one lane records the device's constant-rate clock (kernel timing
+// inside a captured graph, where event records are not available).
+__global__ __launch_bounds__(kWave) void k_stamp(uint64_t* __restrict__ out) {
+    if (threadIdx.x == 0) out[0] = wall_clock64();
 }
 
 // ---------------------------------------------------------------------------
@@ -650,11 +1058,23 @@ struct DeviceScratch {
     size_t code_cap = 0;         // instructions
     int32_t* clen = nullptr;
     size_t clen_cap = 0;
+    double* stats = nullptr;     // per-program statistics (kStats doubles each)
+    size_t stats_cap = 0;
+    double* gpart = nullptr;     // gradient partials
+    size_t gpart_cap = 0;
+    double* gextra = nullptr;    // gradient sums of constants beyond kGradLds
+    size_t gextra_cap = 0;
+    float* tape = nullptr;       // adjoint tape overflow
+    size_t tape_cap = 0;
+    float* fit_tmp = nullptr;
+    size_t fit_tmp_cap = 0;
     int n_cu = 0;
+    int dev = -1;
+    std::string arch;
 };
 
 std::mutex g_mu;
-std::vector<DeviceScratch> g_dev;
+std::vector<DeviceScratch> g_dev;   // per-device arena of the plain entry points
 
 // kernel timing (gp_profile_enable / gp_profile_read)
 struct ProfRec {
@@ -684,17 +1104,43 @@ gp_status grow(void** ptr, size_t* cap, size_t need_elems, size_t elem) {
     return GP_OK;
 }
 
-gp_status scratch_for(int dev, DeviceScratch** out) {
+gp_status scratch_init(DeviceScratch& s, int dev) {
+    if (s.counter) return GP_OK;
+    GP_HIP(hipMalloc(&s.counter, 256));
+    GP_HIP(hipMemset(s.counter, 0, 256));
+    hipDeviceProp_t prop;
+    GP_HIP(hipGetDeviceProperties(&prop, dev));
+    s.n_cu = prop.multiProcessorCount;
+    s.dev = dev;
+    s.arch = prop.gcnArchName;
+    const size_t colon = s.arch.find(':');
+    if (colon != std::string::npos) s.arch.resize(colon);
+    return GP_OK;
+}
+
+bool scratch_empty(const DeviceScratch& s) {
+    return !s.counter && !s.order && !s.part && !s.ystat && !s.code && !s.clen && !s.stats && !s.gpart &&
+           !s.gextra && !s.tape && !s.fit_tmp;
+}
+
+// Frees every buffer of s (the caller has made its device current and idle).
+void scratch_free(DeviceScratch& s) {
+    for (void* q : {s.counter, static_cast<void*>(s.order), static_cast<void*>(s.part),
+                    static_cast<void*>(s.ystat), static_cast<void*>(s.code), static_cast<void*>(s.clen),
+                    static_cast<void*>(s.stats), static_cast<void*>(s.gpart), static_cast<void*>(s.gextra),
+                    static_cast<void*>(s.tape), static_cast<void*>(s.fit_tmp)})
+        if (q) (void)hipFree(q);
+    s = DeviceScratch{};
+}
+
+// The shared arena of the current device.
+gp_status arena(DeviceScratch** out) {
+    int dev = 0;
+    GP_HIP(hipGetDevice(&dev));
     if (static_cast<int>(g_dev.size()) <= dev) g_dev.resize(dev + 1);
-    DeviceScratch& s = g_dev[dev];
-    if (!s.counter) {
-        GP_HIP(hipMalloc(&s.counter, 256));
-        GP_HIP(hipMemset(s.counter, 0, 256));
-        hipDeviceProp_t prop;
-        GP_HIP(hipGetDeviceProperties(&prop, dev));
-        s.n_cu = prop.multiProcessorCount;
-    }
-    *out = &s;
+    gp_status rc = scratch_init(g_dev[dev], dev);
+    if (rc != GP_OK) return rc;
+    *out = &g_dev[dev];
     return GP_OK;
 }
 
@@ -718,18 +1164,61 @@ gp_status check_data(const gp_dataset_dev* d, const char* who, bool need_y) {
     return GP_OK;
 }
 
-// Launch configuration of the evaluation kernel.
+gp_status check_fitness_metric(int metric, const char* who) {
+    if (metric == GP_METRIC_SPEARMAN)
+        return fail(GP_ERR_UNSUPPORTED, std::string(who) + ": Spearman is not provided by this version");
+    if (gp_metric_larger_is_better(static_cast<gp_metric>(metric)) < 0)
+        return fail(GP_ERR_INVALID_ARG, std::string(who) + ": unknown metric");
+    return GP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Launch configuration of the evaluation kernel: forced > tuned > heuristic.
+// ---------------------------------------------------------------------------
 struct LaunchCfg {
     int R;        // rows per lane: 1, 2 or 4
     int freg;     // features held in registers: 0, 2 or 8
     int tiles;    // tiles of 64*R rows per chunk
 };
 
+bool cfg_valid(const LaunchCfg& c) {
+    return (c.R == 1 || c.R == 2 || c.R == 4) && (c.freg == 0 || c.freg == 2 || c.freg == 8) && c.tiles >= 1 &&
+           c.tiles <= (1 << 20);
+}
+
 bool g_forced = false;
 LaunchCfg g_forced_cfg{4, 0, 1};
 
-LaunchCfg pick_cfg(int F, int64_t N, int32_t P, int n_cu) {
-    if (g_forced) return g_forced_cfg;
+// Evaluation kernels differ by metric; each class is tuned on its own.
+int kernel_class(int mode, int metric) {
+    if (mode == 0) return 0;
+    switch (metric) {
+    case GP_METRIC_MSE:
+    case GP_METRIC_RMSE: return 1;
+    case GP_METRIC_MAE: return 2;
+    case GP_METRIC_LOGLOSS: return 3;
+    default: return 4;
+    }
+}
+
+struct TuneKey {
+    std::string arch;
+    int n_cu;
+    int F;
+    int64_t N;
+    int32_t P;
+    int kclass;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(arch, n_cu, F, N, P, kclass) < std::tie(o.arch, o.n_cu, o.F, o.N, o.P, o.kclass);
+    }
+};
+struct TuneVal {
+    LaunchCfg cfg;
+    double ms;
+};
+std::map<TuneKey, TuneVal> g_tuned;
+
+LaunchCfg heuristic_cfg(int F, int64_t N, int32_t P, int n_cu) {
     LaunchCfg c;
     c.R = 4;
     c.freg = F <= 2 ? 2 : (F <= 8 ? 8 : 0);
@@ -745,10 +1234,26 @@ LaunchCfg pick_cfg(int F, int64_t N, int32_t P, int n_cu) {
     return c;
 }
 
+LaunchCfg pick_cfg(const DeviceScratch& sc, int F, int64_t N, int32_t P, int kclass) {
+    if (g_forced) return g_forced_cfg;
+    auto it = g_tuned.find(TuneKey{sc.arch, sc.n_cu, F, N, P, kclass});
+    if (it != g_tuned.end()) return it->second.cfg;
+    return heuristic_cfg(F, N, P, sc.n_cu);
+}
+
+// How a launch of the evaluation kernel is timed: by the process-wide profile
+// (plain entry points), by a pair of events recorded as graph nodes (captured
+// generations), or not at all (autotuning, capture without timing).
+struct Timing {
+    bool profile = false;
+    uint64_t* stamp = nullptr;   // device [2]: clock before and after the kernel
+    const void** launched = nullptr;   // receives the evaluation kernel launched
+};
+
 template <int MODE, int METRIC>
 gp_status launch_eval_m(const LaunchCfg& cfg, int n_cu, const PopView& pv, const CodeView& cv,
                         const DataView& dv, const Sched& s, float* out, double* part, hipStream_t st,
-                        int64_t node_rows) {
+                        int64_t node_rows, const Timing& tm) {
     auto go = [&](auto kernel) -> gp_status {
         int per_cu = 0;
         GP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0));
@@ -757,16 +1262,23 @@ gp_status launch_eval_m(const LaunchCfg& cfg, int n_cu, const PopView& pv, const
         int64_t blocks = static_cast<int64_t>(per_cu) * n_cu;
         blocks = std::min<int64_t>(blocks, (waves_needed + (kBlock / kWave) - 1) / (kBlock / kWave));
         blocks = std::max<int64_t>(blocks, 1);
+        const bool prof = tm.profile && g_prof_on;
         ProfRec rec{nullptr, nullptr, node_rows};
-        if (g_prof_on) {
+        if (prof) {
             GP_HIP(hipEventCreate(&rec.a));
             GP_HIP(hipEventCreate(&rec.b));
             GP_HIP(hipEventRecord(rec.a, st));
         }
+        if (tm.launched) *tm.launched = reinterpret_cast<const void*>(kernel);
+        if (tm.stamp) hipLaunchKernelGGL(k_stamp, dim3(1), dim3(kWave), 0, st, tm.stamp);
         hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, st, pv, cv, dv, s, out,
                            part);
         GP_HIP(hipGetLastError());
-        if (g_prof_on) {
+        if (tm.stamp) {
+            hipLaunchKernelGGL(k_stamp, dim3(1), dim3(kWave), 0, st, tm.stamp + 1);
+            GP_HIP(hipGetLastError());
+        }
+        if (prof) {
             GP_HIP(hipEventRecord(rec.b, st));
             g_prof_pending.push_back(rec);
         }
@@ -783,60 +1295,73 @@ gp_status launch_eval_m(const LaunchCfg& cfg, int n_cu, const PopView& pv, const
 
 gp_status launch_eval(int mode, int metric, const LaunchCfg& cfg, int n_cu, const PopView& pv,
                       const CodeView& cv, const DataView& dv, const Sched& s, float* out, double* part,
-                      hipStream_t st, int64_t node_rows) {
+                      hipStream_t st, int64_t node_rows, const Timing& tm) {
     if (mode == 0)
-        return launch_eval_m<0, GP_METRIC_MSE>(cfg, n_cu, pv, cv, dv, s, out, part, st, node_rows);
+        return launch_eval_m<0, GP_METRIC_MSE>(cfg, n_cu, pv, cv, dv, s, out, part, st, node_rows, tm);
     switch (metric) {
     case GP_METRIC_MAE:
-        return launch_eval_m<1, GP_METRIC_MAE>(cfg, n_cu, pv, cv, dv, s, out, part, st, node_rows);
+        return launch_eval_m<1, GP_METRIC_MAE>(cfg, n_cu, pv, cv, dv, s, out, part, st, node_rows, tm);
     case GP_METRIC_MSE:
     case GP_METRIC_RMSE:
-        return launch_eval_m<1, GP_METRIC_MSE>(cfg, n_cu, pv, cv, dv, s, out, part, st, node_rows);
+        return launch_eval_m<1, GP_METRIC_MSE>(cfg, n_cu, pv, cv, dv, s, out, part, st, node_rows, tm);
     case GP_METRIC_LOGLOSS:
-        return launch_eval_m<1, GP_METRIC_LOGLOSS>(cfg, n_cu, pv, cv, dv, s, out, part, st, node_rows);
+        return launch_eval_m<1, GP_METRIC_LOGLOSS>(cfg, n_cu, pv, cv, dv, s, out, part, st, node_rows, tm);
     case GP_METRIC_PEARSON:
-        return launch_eval_m<1, GP_METRIC_PEARSON>(cfg, n_cu, pv, cv, dv, s, out, part, st, node_rows);
+        return launch_eval_m<1, GP_METRIC_PEARSON>(cfg, n_cu, pv, cv, dv, s, out, part, st, node_rows, tm);
     default: return fail(GP_ERR_UNSUPPORTED, "metric not supported by the fused fitness kernel");
     }
 }
 
-// Shared front half of gp_evaluate / gp_fitness: checks, scratch, ordering.
-gp_status prepare(const gp_population_dev* pop, const gp_dataset_dev* data, int mode, int metric,
-                  hipStream_t st, DeviceScratch** sc_out, PopView* pv, CodeView* cvw, DataView* dv,
-                  Sched* sch, LaunchCfg* cfg) {
-    int dev = 0;
-    GP_HIP(hipGetDevice(&dev));
-    DeviceScratch* sc = nullptr;
-    gp_status rc = scratch_for(dev, &sc);
+// Scratch sizes one evaluation needs; grows sc's buffers to them.  Called
+// outside any stream capture (it may allocate).
+gp_status reserve(DeviceScratch* sc, int32_t P, int64_t total_nodes, int64_t n_chunks, int mode, int metric) {
+    gp_status rc = grow(reinterpret_cast<void**>(&sc->order), &sc->order_cap, P, sizeof(int32_t));
     if (rc != GP_OK) return rc;
-    *pv = PopView{pop->nodes, pop->prog_off, pop->consts, pop->const_off, pop->len, pop->n_programs};
-    *dv = DataView{data->X, data->ld, data->n_features, data->n_rows, data->y, data->w};
-    *cfg = pick_cfg(data->n_features, data->n_rows, pop->n_programs, sc->n_cu);
-    if (cfg->freg > 0 && data->n_features > cfg->freg)
-        return fail(GP_ERR_INVALID_ARG, "launch configuration holds fewer feature registers than n_features");
-    const int64_t chunk = static_cast<int64_t>(cfg->tiles) * kWave * cfg->R;
-    const int64_t n_chunks = (data->n_rows + chunk - 1) / chunk;
-    const int64_t n_items = n_chunks * pop->n_programs;
-    // the 32-bit work counter overshoots n_items by at most one per wavefront
-    if (n_items > (int64_t{1} << 30))
-        return fail(GP_ERR_INVALID_ARG, "too many work items (n_programs * row chunks above 2^30)");
-    rc = grow(reinterpret_cast<void**>(&sc->order), &sc->order_cap, pop->n_programs, sizeof(int32_t));
+    rc = grow(reinterpret_cast<void**>(&sc->code), &sc->code_cap, static_cast<size_t>(total_nodes), sizeof(uint2));
     if (rc != GP_OK) return rc;
-    rc = grow(reinterpret_cast<void**>(&sc->code), &sc->code_cap, static_cast<size_t>(pop->total_nodes),
-              sizeof(uint2));
-    if (rc != GP_OK) return rc;
-    rc = grow(reinterpret_cast<void**>(&sc->clen), &sc->clen_cap, pop->n_programs, sizeof(int32_t));
+    rc = grow(reinterpret_cast<void**>(&sc->clen), &sc->clen_cap, P, sizeof(int32_t));
     if (rc != GP_OK) return rc;
     if (mode == 1) {
         const size_t kk = metric == GP_METRIC_PEARSON ? 4 : 1;
-        rc = grow(reinterpret_cast<void**>(&sc->part), &sc->part_cap,
-                  static_cast<size_t>(pop->n_programs) * n_chunks * kk, sizeof(double));
+        rc = grow(reinterpret_cast<void**>(&sc->part), &sc->part_cap, static_cast<size_t>(P) * n_chunks * kk,
+                  sizeof(double));
         if (rc != GP_OK) return rc;
         rc = grow(reinterpret_cast<void**>(&sc->ystat), &sc->ystat_cap, static_cast<size_t>(n_chunks) * 4,
                   sizeof(double));
         if (rc != GP_OK) return rc;
     }
-    *sch = Sched{chunk, static_cast<int32_t>(n_chunks), n_items, sc->order,
+    return GP_OK;
+}
+
+gp_status chunking(const gp_population_dev* pop, const gp_dataset_dev* data, const LaunchCfg& cfg,
+                   int64_t* chunk, int64_t* n_chunks) {
+    if (!cfg_valid(cfg)) return fail(GP_ERR_INVALID_ARG, "invalid launch configuration");
+    if (cfg.freg > 0 && data->n_features > cfg.freg)
+        return fail(GP_ERR_INVALID_ARG, "launch configuration holds fewer feature registers than n_features");
+    *chunk = static_cast<int64_t>(cfg.tiles) * kWave * cfg.R;
+    *n_chunks = (data->n_rows + *chunk - 1) / *chunk;
+    // the 32-bit work counter overshoots n_items by at most one per wavefront
+    if (*n_chunks * pop->n_programs > (int64_t{1} << 30))
+        return fail(GP_ERR_INVALID_ARG, "too many work items (n_programs * row chunks above 2^30)");
+    return GP_OK;
+}
+
+// Shared front half of the evaluation paths: configuration, scratch, the
+// length ordering and the instruction stream.  `force` (nullable) overrides
+// the configuration choice.
+gp_status prepare(DeviceScratch* sc, const gp_population_dev* pop, const gp_dataset_dev* data, int mode,
+                  int metric, hipStream_t st, const LaunchCfg* force, PopView* pv, CodeView* cvw, DataView* dv,
+                  Sched* sch, LaunchCfg* cfg) {
+    *pv = PopView{pop->nodes, pop->prog_off, pop->consts, pop->const_off, pop->len, pop->n_programs};
+    *dv = DataView{data->X, data->ld, data->n_features, data->n_rows, data->y, data->w};
+    *cfg = force ? *force
+                 : pick_cfg(*sc, data->n_features, data->n_rows, pop->n_programs, kernel_class(mode, metric));
+    int64_t chunk = 0, n_chunks = 0;
+    gp_status rc = chunking(pop, data, *cfg, &chunk, &n_chunks);
+    if (rc != GP_OK) return rc;
+    rc = reserve(sc, pop->n_programs, pop->total_nodes, n_chunks, mode, metric);
+    if (rc != GP_OK) return rc;
+    *sch = Sched{chunk, static_cast<int32_t>(n_chunks), n_chunks * pop->n_programs, sc->order,
                  static_cast<uint32_t*>(sc->counter)};
     hipLaunchKernelGGL(k_prepare, dim3(1), dim3(1024), 0, st, pop->len, pop->n_programs, sc->order,
                        static_cast<uint32_t*>(sc->counter));
@@ -845,8 +1370,262 @@ gp_status prepare(const gp_population_dev* pop, const gp_dataset_dev* data, int 
                        sc->code, sc->clen);
     GP_HIP(hipGetLastError());
     *cvw = CodeView{sc->code, sc->clen};
-    *sc_out = sc;
     return GP_OK;
+}
+
+// Fitness of every program into `fitness` (device), on scratch sc.
+gp_status fitness_impl(DeviceScratch* sc, const gp_population_dev* pop, const gp_dataset_dev* data, int metric,
+                       float* fitness, hipStream_t st, const LaunchCfg* force, const Timing& tm) {
+    PopView pv;
+    CodeView cvw;
+    DataView dv;
+    Sched sch;
+    LaunchCfg cfg;
+    gp_status rc = prepare(sc, pop, data, 1, metric, st, force, &pv, &cvw, &dv, &sch, &cfg);
+    if (rc != GP_OK) return rc;
+    const bool need_ystats = data->w != nullptr || metric == GP_METRIC_PEARSON;
+    if (need_ystats) {
+        const int blocks = (sch.n_chunks + (kBlock / kWave) - 1) / (kBlock / kWave);
+        hipLaunchKernelGGL(k_ystats, dim3(blocks), dim3(kBlock), 0, st, dv, sch.chunk, sch.n_chunks, sc->ystat);
+        GP_HIP(hipGetLastError());
+    }
+    rc = launch_eval(1, metric, cfg, sc->n_cu, pv, cvw, dv, sch, nullptr, sc->part, st,
+                     pop->total_nodes * data->n_rows, tm);
+    if (rc != GP_OK) return rc;
+    const int fblocks = (pop->n_programs + (kBlock / kWave) - 1) / (kBlock / kWave);
+    const int has_w = data->w != nullptr;
+#define GP_FIN(M)                                                                                  \
+    hipLaunchKernelGGL(k_finalize<M>, dim3(fblocks), dim3(kBlock), 0, st, sc->part, sc->ystat,   \
+                       sch.n_chunks, pop->n_programs, data->n_rows, has_w, fitness, nullptr)
+    switch (metric) {
+    case GP_METRIC_MAE: GP_FIN(GP_METRIC_MAE); break;
+    case GP_METRIC_MSE: GP_FIN(GP_METRIC_MSE); break;
+    case GP_METRIC_RMSE: GP_FIN(GP_METRIC_RMSE); break;
+    case GP_METRIC_LOGLOSS: GP_FIN(GP_METRIC_LOGLOSS); break;
+    default: GP_FIN(GP_METRIC_PEARSON); break;
+    }
+#undef GP_FIN
+    GP_HIP(hipGetLastError());
+    return GP_OK;
+}
+
+gp_status tournament_impl(const float* fitness, const int32_t* len, int32_t P, int larger, float parsimony,
+                          int32_t k, int32_t T, uint64_t seed, uint32_t gen, const uint32_t* gen_dev,
+                          int32_t* winners, hipStream_t st) {
+    if (T == 0) return GP_OK;
+    const int blocks = (T + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_tournament, dim3(blocks), dim3(kBlock), 0, st, fitness, len, P, larger, parsimony, k, T,
+                       seed, gen, gen_dev, winners);
+    GP_HIP(hipGetLastError());
+    return GP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: times candidate configurations of the fitness kernel on a prefix
+// of at most kTuneRows rows and keeps the fastest for the full shape.
+// ---------------------------------------------------------------------------
+constexpr int64_t kTuneRows = int64_t{1} << 20;
+
+gp_status autotune_impl(DeviceScratch* sc, const gp_population_dev* pop, const gp_dataset_dev* data, int metric,
+                        int repeats, hipStream_t st, LaunchCfg* best_out, double* best_ms_out) {
+    gp_dataset_dev sub = *data;
+    sub.n_rows = std::min(data->n_rows, kTuneRows);
+    gp_status rc = grow(reinterpret_cast<void**>(&sc->fit_tmp), &sc->fit_tmp_cap,
+                        static_cast<size_t>(std::max(pop->n_programs, 1)), sizeof(float));
+    if (rc != GP_OK) return rc;
+    const LaunchCfg h = heuristic_cfg(data->n_features, data->n_rows, pop->n_programs, sc->n_cu);
+    std::vector<int> fregs;
+    if (data->n_features <= 2) fregs.push_back(2);
+    if (data->n_features <= 8) fregs.push_back(8);
+    fregs.push_back(0);
+    std::vector<int> tiles;
+    for (int t : {h.tiles / 4, h.tiles / 2, h.tiles, h.tiles * 2})
+        if (t >= 1 && std::find(tiles.begin(), tiles.end(), t) == tiles.end()) tiles.push_back(t);
+    hipEvent_t a = nullptr, b = nullptr;
+    GP_HIP(hipEventCreate(&a));
+    GP_HIP(hipEventCreate(&b));
+    LaunchCfg best = h;
+    double best_ms = -1.0;
+    for (int R : {1, 2, 4})
+        for (int fr : fregs)
+            for (int t : tiles) {
+                // keep the rows per work item of the heuristic within a factor of 4
+                const LaunchCfg c{R, fr, std::max(1, t * 4 / R)};
+                int64_t chunk = 0, n_chunks = 0;
+                if (chunking(pop, data, c, &chunk, &n_chunks) != GP_OK) continue;
+                double ms_min = -1.0;
+                for (int rep = 0; rep <= repeats && rc == GP_OK; ++rep) {
+                    rc = hipEventRecord(a, st) == hipSuccess ? GP_OK : GP_ERR_DEVICE;
+                    if (rc == GP_OK) rc = fitness_impl(sc, pop, &sub, metric, sc->fit_tmp, st, &c, Timing{});
+                    if (rc == GP_OK) rc = hipEventRecord(b, st) == hipSuccess ? GP_OK : GP_ERR_DEVICE;
+                    if (rc == GP_OK) rc = hipEventSynchronize(b) == hipSuccess ? GP_OK : GP_ERR_DEVICE;
+                    float ms = 0.0f;
+                    if (rc == GP_OK) rc = hipEventElapsedTime(&ms, a, b) == hipSuccess ? GP_OK : GP_ERR_DEVICE;
+                    if (rc == GP_OK && rep > 0 && (ms_min < 0.0 || ms < ms_min)) ms_min = ms;  // rep 0 warms up
+                }
+                if (rc != GP_OK) break;
+                if (ms_min >= 0.0 && (best_ms < 0.0 || ms_min < best_ms)) {
+                    best_ms = ms_min;
+                    best = c;
+                }
+            }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc != GP_OK) return rc == GP_ERR_DEVICE ? fail(GP_ERR_DEVICE, "autotune: a timed launch failed") : rc;
+    if (best_ms < 0.0) return fail(GP_ERR_INVALID_ARG, "autotune: no launch configuration fits this shape");
+    g_tuned[TuneKey{sc->arch, sc->n_cu, data->n_features, data->n_rows, pop->n_programs, kernel_class(1, metric)}] =
+        TuneVal{best, best_ms};
+    *best_out = best;
+    if (best_ms_out) *best_ms_out = best_ms;
+    return GP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// One generation as a HIP graph.
+// ---------------------------------------------------------------------------
+size_t align_up(size_t v) { return (v + 255) & ~size_t{255}; }
+
+struct StageLayout {
+    size_t gen, len, prog_off, const_off, nodes, consts, bytes;
+};
+
+StageLayout stage_layout(int32_t P, int64_t node_cap, int64_t const_cap) {
+    StageLayout l;
+    l.gen = 0;
+    l.len = 256;
+    l.prog_off = align_up(l.len + sizeof(int32_t) * static_cast<size_t>(P));
+    l.const_off = align_up(l.prog_off + sizeof(int64_t) * (static_cast<size_t>(P) + 1));
+    l.nodes = align_up(l.const_off + sizeof(int64_t) * (static_cast<size_t>(P) + 1));
+    l.consts = align_up(l.nodes + sizeof(uint32_t) * static_cast<size_t>(node_cap));
+    l.bytes = align_up(l.consts + sizeof(float) * static_cast<size_t>(std::max<int64_t>(const_cap, 1)));
+    return l;
+}
+
+}  // namespace
+
+struct gp_generation_s {
+    gp_generation_params prm{};
+    gp_dataset_dev data{};
+    int dev = 0;
+    hipStream_t stream = nullptr;
+    DeviceScratch sc;
+    StageLayout lay{};
+    char* h_stage = nullptr;     // pinned: the population of the next generation
+    char* d_stage = nullptr;
+    float* d_fit = nullptr;
+    int32_t* d_win = nullptr;
+    float* h_fit = nullptr;      // pinned outputs
+    int32_t* h_win = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t* d_stamp = nullptr;  // evaluation-kernel clock stamps (time_kernel)
+    uint64_t* h_stamp = nullptr;
+    int clock_khz = 0;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;   // event nodes around the evaluation kernel
+    bool events = false;
+    const void* eval_kernel = nullptr;
+    LaunchCfg cfg{4, 0, 1};
+    bool captured = false;
+    double tuned_ms = -1.0;
+    float kernel_ms = -1.0f;    // HIP events if inserted, else the clock stamps
+    float clock_ms = -1.0f;     // clock stamps
+};
+
+namespace {
+
+gp_population_dev stage_view(const gp_generation_s* g, int64_t total_nodes, int64_t total_consts) {
+    gp_population_dev v{};
+    v.nodes = reinterpret_cast<const uint32_t*>(g->d_stage + g->lay.nodes);
+    v.prog_off = reinterpret_cast<const int64_t*>(g->d_stage + g->lay.prog_off);
+    v.consts = reinterpret_cast<const float*>(g->d_stage + g->lay.consts);
+    v.const_off = reinterpret_cast<const int64_t*>(g->d_stage + g->lay.const_off);
+    v.len = reinterpret_cast<const int32_t*>(g->d_stage + g->lay.len);
+    v.n_programs = g->prm.n_programs;
+    v.total_nodes = total_nodes;
+    v.max_len = 0;
+    v.total_consts = total_consts;
+    return v;
+}
+
+void generation_release(gp_generation_s* g) {
+    if (g->stream) (void)hipStreamSynchronize(g->stream);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->ev_a) (void)hipEventDestroy(g->ev_a);
+    if (g->ev_b) (void)hipEventDestroy(g->ev_b);
+    if (g->d_stamp) (void)hipFree(g->d_stamp);
+    if (g->h_stamp) (void)hipHostFree(g->h_stamp);
+    if (g->h_stage) (void)hipHostFree(g->h_stage);
+    if (g->h_fit) (void)hipHostFree(g->h_fit);
+    if (g->h_win) (void)hipHostFree(g->h_win);
+    if (g->d_stage) (void)hipFree(g->d_stage);
+    if (g->d_fit) (void)hipFree(g->d_fit);
+    if (g->d_win) (void)hipFree(g->d_win);
+    scratch_free(g->sc);
+    if (g->stream) (void)hipStreamDestroy(g->stream);
+}
+
+// Records the generation into g->stream: population upload, fitness,
+// tournament, result download.  Run under capture.
+gp_status record_generation(gp_generation_s* g) {
+    const gp_generation_params& p = g->prm;
+    GP_HIP(hipMemcpyAsync(g->d_stage, g->h_stage, g->lay.bytes, hipMemcpyHostToDevice, g->stream));
+    const gp_population_dev view = stage_view(g, p.node_capacity, p.const_capacity);
+    Timing tm;
+    tm.stamp = g->d_stamp;
+    tm.launched = &g->eval_kernel;
+    gp_status rc = fitness_impl(&g->sc, &view, &g->data, p.metric, g->d_fit, g->stream, &g->cfg, tm);
+    if (rc != GP_OK) return rc;
+    rc = tournament_impl(g->d_fit, view.len, p.n_programs, gp_metric_larger_is_better(static_cast<gp_metric>(p.metric)), p.parsimony,
+                         p.tournament_size, p.n_tournaments, p.seed, 0,
+                         reinterpret_cast<const uint32_t*>(g->d_stage + g->lay.gen), g->d_win, g->stream);
+    if (rc != GP_OK) return rc;
+    GP_HIP(hipMemcpyAsync(g->h_fit, g->d_fit, sizeof(float) * p.n_programs, hipMemcpyDeviceToHost, g->stream));
+    if (p.n_tournaments > 0)
+        GP_HIP(hipMemcpyAsync(g->h_win, g->d_win, sizeof(int32_t) * p.n_tournaments, hipMemcpyDeviceToHost,
+                              g->stream));
+    if (g->d_stamp)
+        GP_HIP(hipMemcpyAsync(g->h_stamp, g->d_stamp, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, g->stream));
+    return GP_OK;
+}
+
+// Puts event-record nodes right before and right after the evaluation-kernel
+// node of a captured graph, so that the graph's launches record ev_a / ev_b
+// around that kernel.  Returns false (graph unchanged or not) if HIP refuses;
+// the caller then relies on the clock stamps.
+bool insert_event_nodes(hipGraph_t graph, const void* func, hipEvent_t ev_a, hipEvent_t ev_b) {
+    size_t n = 0;
+    if (hipGraphGetNodes(graph, nullptr, &n) != hipSuccess || n == 0) return false;
+    std::vector<hipGraphNode_t> nodes(n);
+    if (hipGraphGetNodes(graph, nodes.data(), &n) != hipSuccess) return false;
+    hipGraphNode_t K = nullptr;
+    for (hipGraphNode_t nd : nodes) {
+        hipGraphNodeType t;
+        if (hipGraphNodeGetType(nd, &t) != hipSuccess || t != hipGraphNodeTypeKernel) continue;
+        hipKernelNodeParams kp{};
+        if (hipGraphKernelNodeGetParams(nd, &kp) != hipSuccess) continue;
+        if (kp.func == func) {
+            if (K) return false;   // not unique
+            K = nd;
+        }
+    }
+    if (!K) return false;
+    size_t nd_in = 0, nd_out = 0;
+    if (hipGraphNodeGetDependencies(K, nullptr, &nd_in) != hipSuccess) return false;
+    if (hipGraphNodeGetDependentNodes(K, nullptr, &nd_out) != hipSuccess) return false;
+    std::vector<hipGraphNode_t> pred(nd_in), succ(nd_out);
+    if (nd_in && hipGraphNodeGetDependencies(K, pred.data(), &nd_in) != hipSuccess) return false;
+    if (nd_out && hipGraphNodeGetDependentNodes(K, succ.data(), &nd_out) != hipSuccess) return false;
+    std::vector<hipGraphNode_t> Ks_in(nd_in, K), Ks_out(nd_out, K);
+    hipGraphNode_t A = nullptr, B = nullptr;
+    if (nd_in && hipGraphRemoveDependencies(graph, pred.data(), Ks_in.data(), nd_in) != hipSuccess) return false;
+    if (hipGraphAddEventRecordNode(&A, graph, pred.data(), nd_in, ev_a) != hipSuccess) return false;
+    if (hipGraphAddDependencies(graph, &A, &K, 1) != hipSuccess) return false;
+    if (nd_out && hipGraphRemoveDependencies(graph, Ks_out.data(), succ.data(), nd_out) != hipSuccess) return false;
+    if (hipGraphAddEventRecordNode(&B, graph, &K, 1, ev_b) != hipSuccess) return false;
+    std::vector<hipGraphNode_t> Bs(nd_out, B);
+    if (nd_out && hipGraphAddDependencies(graph, Bs.data(), succ.data(), nd_out) != hipSuccess) return false;
+    return true;
 }
 
 }  // namespace
@@ -859,31 +1638,25 @@ void gp_shutdown(void) {
     (void)hipGetDevice(&cur);
     for (size_t d = 0; d < g_dev.size(); ++d) {
         DeviceScratch& s = g_dev[d];
-        if (!s.counter && !s.order && !s.part && !s.ystat && !s.code && !s.clen) continue;
+        if (scratch_empty(s)) continue;
         (void)hipSetDevice(static_cast<int>(d));
         (void)hipDeviceSynchronize();
-        if (s.counter) (void)hipFree(s.counter);
-        if (s.order) (void)hipFree(s.order);
-        if (s.part) (void)hipFree(s.part);
-        if (s.ystat) (void)hipFree(s.ystat);
-        if (s.code) (void)hipFree(s.code);
-        if (s.clen) (void)hipFree(s.clen);
-        s = DeviceScratch{};
+        scratch_free(s);
     }
     (void)hipSetDevice(cur);
 }
 
-gp_status gp_get_launch_config(int32_t n_features, int64_t n_rows, int32_t n_programs,
+gp_status gp_get_launch_config(int32_t n_features, int64_t n_rows, int32_t n_programs, gp_metric metric,
                                gp_launch_config* out) {
     std::lock_guard<std::mutex> lk(g_mu);
     if (!out || n_features < 1 || n_rows < 1 || n_programs < 0)
         return fail(GP_ERR_INVALID_ARG, "gp_get_launch_config: bad arguments");
-    int dev = 0;
-    GP_HIP(hipGetDevice(&dev));
-    DeviceScratch* sc = nullptr;
-    gp_status rc = scratch_for(dev, &sc);
+    gp_status rc = check_fitness_metric(metric, "gp_get_launch_config");
     if (rc != GP_OK) return rc;
-    const LaunchCfg c = pick_cfg(n_features, n_rows, n_programs, sc->n_cu);
+    DeviceScratch* sc = nullptr;
+    rc = arena(&sc);
+    if (rc != GP_OK) return rc;
+    const LaunchCfg c = pick_cfg(*sc, n_features, n_rows, n_programs, kernel_class(1, metric));
     *out = gp_launch_config{c.R, c.freg, c.tiles};
     return GP_OK;
 }
@@ -894,13 +1667,95 @@ gp_status gp_set_launch_config(const gp_launch_config* cfg) {
         g_forced = false;
         return GP_OK;
     }
-    const bool r_ok = cfg->rows_per_lane == 1 || cfg->rows_per_lane == 2 || cfg->rows_per_lane == 4;
-    const bool f_ok = cfg->feature_regs == 0 || cfg->feature_regs == 2 || cfg->feature_regs == 8;
-    if (!r_ok || !f_ok || cfg->tiles_per_chunk < 1 || cfg->tiles_per_chunk > (1 << 20))
+    const LaunchCfg c{cfg->rows_per_lane, cfg->feature_regs, cfg->tiles_per_chunk};
+    if (!cfg_valid(c))
         return fail(GP_ERR_INVALID_ARG, "gp_set_launch_config: rows_per_lane in {1,2,4}, feature_regs in {0,2,8}, "
                                         "tiles_per_chunk in [1, 2^20]");
-    g_forced_cfg = LaunchCfg{cfg->rows_per_lane, cfg->feature_regs, cfg->tiles_per_chunk};
+    g_forced_cfg = c;
     g_forced = true;
+    return GP_OK;
+}
+
+gp_status gp_autotune(const gp_population_dev* pop, const gp_dataset_dev* data, gp_metric metric,
+                      int32_t repeats, gp_launch_config* best, double* best_ms, void* stream) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    gp_status rc = check_pop(pop, "gp_autotune");
+    if (rc != GP_OK) return rc;
+    rc = check_data(data, "gp_autotune", true);
+    if (rc != GP_OK) return rc;
+    rc = check_fitness_metric(metric, "gp_autotune");
+    if (rc != GP_OK) return rc;
+    if (pop->n_programs < 1) return fail(GP_ERR_INVALID_ARG, "gp_autotune: empty population");
+    if (repeats < 1 || repeats > 100) return fail(GP_ERR_INVALID_ARG, "gp_autotune: repeats in [1, 100]");
+    DeviceScratch* sc = nullptr;
+    rc = arena(&sc);
+    if (rc != GP_OK) return rc;
+    LaunchCfg c{};
+    rc = autotune_impl(sc, pop, data, metric, repeats, static_cast<hipStream_t>(stream), &c, best_ms);
+    if (rc != GP_OK) return rc;
+    if (best) *best = gp_launch_config{c.R, c.freg, c.tiles};
+    return GP_OK;
+}
+
+gp_status gp_autotune_save(const char* path) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!path) return fail(GP_ERR_INVALID_ARG, "gp_autotune_save: path is NULL");
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(GP_ERR_INVALID_ARG, std::string("gp_autotune_save: cannot open ") + path);
+    for (const auto& kv : g_tuned) {
+        const TuneKey& k = kv.first;
+        const TuneVal& v = kv.second;
+        std::fprintf(f,
+                     "{\"arch\": \"%s\", \"n_cu\": %d, \"n_features\": %d, \"n_rows\": %lld, \"n_programs\": %d, "
+                     "\"kernel\": %d, \"rows_per_lane\": %d, \"feature_regs\": %d, \"tiles_per_chunk\": %d, "
+                     "\"ms\": %.6f}\n",
+                     k.arch.c_str(), k.n_cu, k.F, static_cast<long long>(k.N), k.P, k.kclass, v.cfg.R, v.cfg.freg,
+                     v.cfg.tiles, v.ms);
+    }
+    const bool ok = std::fclose(f) == 0;
+    return ok ? GP_OK : fail(GP_ERR_INVALID_ARG, "gp_autotune_save: write failed");
+}
+
+gp_status gp_autotune_load(const char* path) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!path) return fail(GP_ERR_INVALID_ARG, "gp_autotune_load: path is NULL");
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(GP_ERR_INVALID_ARG, std::string("gp_autotune_load: cannot open ") + path);
+    std::vector<std::pair<TuneKey, TuneVal>> got;
+    char line[1024];
+    int lineno = 0;
+    bool bad = false;
+    while (std::fgets(line, sizeof line, f)) {
+        ++lineno;
+        if (line[0] == '\n' || line[0] == '\0') continue;
+        char arch[64] = {0};
+        int n_cu = 0, F = 0, P = 0, kc = 0, R = 0, fr = 0, t = 0;
+        long long N = 0;
+        double ms = 0.0;
+        const int n = std::sscanf(line,
+                                  "{\"arch\": \"%63[^\"]\", \"n_cu\": %d, \"n_features\": %d, \"n_rows\": %lld, "
+                                  "\"n_programs\": %d, \"kernel\": %d, \"rows_per_lane\": %d, \"feature_regs\": %d, "
+                                  "\"tiles_per_chunk\": %d, \"ms\": %lf}",
+                                  arch, &n_cu, &F, &N, &P, &kc, &R, &fr, &t, &ms);
+        const LaunchCfg c{R, fr, t};
+        if (n != 10 || !cfg_valid(c) || F < 1 || N < 1 || P < 0 || kc < 0 || kc > 4 ||
+            (c.freg > 0 && F > c.freg)) {
+            bad = true;
+            break;
+        }
+        got.push_back({TuneKey{arch, n_cu, F, static_cast<int64_t>(N), P, kc}, TuneVal{c, ms}});
+    }
+    std::fclose(f);
+    if (bad)
+        return fail(GP_ERR_INVALID_ARG,
+                    std::string("gp_autotune_load: malformed entry at line ") + std::to_string(lineno));
+    for (auto& kv : got) g_tuned[kv.first] = kv.second;
+    return GP_OK;
+}
+
+gp_status gp_autotune_clear(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tuned.clear();
     return GP_OK;
 }
 
@@ -945,15 +1800,19 @@ gp_status gp_evaluate(const gp_population_dev* pop, const gp_dataset_dev* data, 
     if (pop->n_programs == 0) return GP_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
     DeviceScratch* sc;
+    rc = arena(&sc);
+    if (rc != GP_OK) return rc;
     PopView pv;
     CodeView cvw;
     DataView dv;
     Sched sch;
     LaunchCfg cfg;
-    rc = prepare(pop, data, 0, GP_METRIC_MSE, st, &sc, &pv, &cvw, &dv, &sch, &cfg);
+    rc = prepare(sc, pop, data, 0, GP_METRIC_MSE, st, nullptr, &pv, &cvw, &dv, &sch, &cfg);
     if (rc != GP_OK) return rc;
+    Timing tm;
+    tm.profile = true;
     return launch_eval(0, GP_METRIC_MSE, cfg, sc->n_cu, pv, cvw, dv, sch, out, nullptr, st,
-                       pop->total_nodes * data->n_rows);
+                       pop->total_nodes * data->n_rows, tm);
 }
 
 gp_status gp_fitness(const gp_population_dev* pop, const gp_dataset_dev* data, gp_metric metric,
@@ -964,43 +1823,15 @@ gp_status gp_fitness(const gp_population_dev* pop, const gp_dataset_dev* data, g
     rc = check_data(data, "gp_fitness", true);
     if (rc != GP_OK) return rc;
     if (!fitness) return fail(GP_ERR_INVALID_ARG, "gp_fitness: fitness is NULL");
-    if (metric == GP_METRIC_SPEARMAN)
-        return fail(GP_ERR_UNSUPPORTED, "gp_fitness: Spearman is not provided by this version");
-    if (gp_metric_larger_is_better(metric) < 0) return fail(GP_ERR_INVALID_ARG, "gp_fitness: unknown metric");
+    rc = check_fitness_metric(metric, "gp_fitness");
+    if (rc != GP_OK) return rc;
     if (pop->n_programs == 0) return GP_OK;
-    hipStream_t st = static_cast<hipStream_t>(stream);
     DeviceScratch* sc;
-    PopView pv;
-    CodeView cvw;
-    DataView dv;
-    Sched sch;
-    LaunchCfg cfg;
-    rc = prepare(pop, data, 1, metric, st, &sc, &pv, &cvw, &dv, &sch, &cfg);
+    rc = arena(&sc);
     if (rc != GP_OK) return rc;
-    const bool need_ystats = data->w != nullptr || metric == GP_METRIC_PEARSON;
-    if (need_ystats) {
-        const int blocks = (sch.n_chunks + (kBlock / kWave) - 1) / (kBlock / kWave);
-        hipLaunchKernelGGL(k_ystats, dim3(blocks), dim3(kBlock), 0, st, dv, sch.chunk, sch.n_chunks, sc->ystat);
-        GP_HIP(hipGetLastError());
-    }
-    rc = launch_eval(1, metric, cfg, sc->n_cu, pv, cvw, dv, sch, nullptr, sc->part, st,
-                     pop->total_nodes * data->n_rows);
-    if (rc != GP_OK) return rc;
-    const int fblocks = (pop->n_programs + (kBlock / kWave) - 1) / (kBlock / kWave);
-    const int has_w = data->w != nullptr;
-#define GP_FIN(M)                                                                                  \
-    hipLaunchKernelGGL(k_finalize<M>, dim3(fblocks), dim3(kBlock), 0, st, sc->part, sc->ystat,   \
-                       sch.n_chunks, pop->n_programs, data->n_rows, has_w, fitness)
-    switch (metric) {
-    case GP_METRIC_MAE: GP_FIN(GP_METRIC_MAE); break;
-    case GP_METRIC_MSE: GP_FIN(GP_METRIC_MSE); break;
-    case GP_METRIC_RMSE: GP_FIN(GP_METRIC_RMSE); break;
-    case GP_METRIC_LOGLOSS: GP_FIN(GP_METRIC_LOGLOSS); break;
-    default: GP_FIN(GP_METRIC_PEARSON); break;
-    }
-#undef GP_FIN
-    GP_HIP(hipGetLastError());
-    return GP_OK;
+    Timing tm;
+    tm.profile = true;
+    return fitness_impl(sc, pop, data, metric, fitness, static_cast<hipStream_t>(stream), nullptr, tm);
 }
 
 gp_status gp_tournament(const float* fitness, const int32_t* len, int32_t n_programs, gp_metric metric,
@@ -1014,20 +1845,311 @@ gp_status gp_tournament(const float* fitness, const int32_t* len, int32_t n_prog
     if (larger < 0) return fail(GP_ERR_INVALID_ARG, "gp_tournament: unknown metric");
     if (n_tournaments == 0) return GP_OK;
     if (!fitness || !len || !winners) return fail(GP_ERR_INVALID_ARG, "gp_tournament: NULL pointer");
-    const int blocks = (n_tournaments + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_tournament, dim3(blocks), dim3(kBlock), 0, static_cast<hipStream_t>(stream), fitness,
-                       len, n_programs, larger, parsimony, tournament_size, n_tournaments, seed,
-                       static_cast<uint32_t>(generation), winners);
-    GP_HIP(hipGetLastError());
+    return tournament_impl(fitness, len, n_programs, larger, parsimony, tournament_size, n_tournaments, seed,
+                           static_cast<uint32_t>(generation), nullptr, winners, static_cast<hipStream_t>(stream));
+}
+
+gp_status gp_generation_create(const gp_generation_params* prm, const gp_dataset_dev* data, gp_generation** out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!prm || !out) return fail(GP_ERR_INVALID_ARG, "gp_generation_create: NULL argument");
+    *out = nullptr;
+    gp_status rc = check_data(data, "gp_generation_create", true);
+    if (rc != GP_OK) return rc;
+    rc = check_fitness_metric(prm->metric, "gp_generation_create");
+    if (rc != GP_OK) return rc;
+    if (prm->n_programs < 1 || prm->node_capacity < prm->n_programs || prm->const_capacity < 0 ||
+        prm->tournament_size < 1 || prm->n_tournaments < 0 || prm->autotune < 0 || prm->time_kernel < 0)
+        return fail(GP_ERR_INVALID_ARG, "gp_generation_create: bad sizes (n_programs >= 1, node_capacity >= "
+                                        "n_programs, const_capacity >= 0, tournament_size >= 1, n_tournaments >= 0)");
+    if (prm->node_capacity > (int64_t{1} << 32))
+        return fail(GP_ERR_INVALID_ARG, "gp_generation_create: node_capacity above 2^32");
+    auto* g = new (std::nothrow) gp_generation_s();
+    if (!g) return fail(GP_ERR_OUT_OF_MEMORY, "gp_generation_create: out of host memory");
+    g->prm = *prm;
+    g->data = *data;
+    g->lay = stage_layout(prm->n_programs, prm->node_capacity, prm->const_capacity);
+    auto bail = [&](gp_status r) {
+        generation_release(g);
+        delete g;
+        return r;
+    };
+    auto hip = [&](hipError_t e, const char* what) -> gp_status {
+        return e == hipSuccess ? GP_OK : fail(GP_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    };
+    if ((rc = hip(hipGetDevice(&g->dev), "hipGetDevice")) != GP_OK) return bail(rc);
+    if ((rc = scratch_init(g->sc, g->dev)) != GP_OK) return bail(rc);
+    if ((rc = hip(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking), "hipStreamCreate")) != GP_OK)
+        return bail(rc);
+    if ((rc = hip(hipHostMalloc(reinterpret_cast<void**>(&g->h_stage), g->lay.bytes, hipHostMallocDefault),
+                  "hipHostMalloc")) != GP_OK)
+        return bail(rc);
+    std::memset(g->h_stage, 0, g->lay.bytes);
+    if ((rc = hip(hipHostMalloc(reinterpret_cast<void**>(&g->h_fit), sizeof(float) * prm->n_programs,
+                                hipHostMallocDefault), "hipHostMalloc")) != GP_OK)
+        return bail(rc);
+    if ((rc = hip(hipHostMalloc(reinterpret_cast<void**>(&g->h_win),
+                                sizeof(int32_t) * std::max(prm->n_tournaments, 1), hipHostMallocDefault),
+                  "hipHostMalloc")) != GP_OK)
+        return bail(rc);
+    if ((rc = hip(hipMalloc(reinterpret_cast<void**>(&g->d_stage), g->lay.bytes), "hipMalloc")) != GP_OK)
+        return bail(rc == GP_ERR_DEVICE ? GP_ERR_OUT_OF_MEMORY : rc);
+    if ((rc = hip(hipMalloc(reinterpret_cast<void**>(&g->d_fit), sizeof(float) * prm->n_programs), "hipMalloc")) !=
+        GP_OK)
+        return bail(rc);
+    if ((rc = hip(hipMalloc(reinterpret_cast<void**>(&g->d_win), sizeof(int32_t) * std::max(prm->n_tournaments, 1)),
+                  "hipMalloc")) != GP_OK)
+        return bail(rc);
+    if (prm->time_kernel) {
+        if ((rc = hip(hipMalloc(reinterpret_cast<void**>(&g->d_stamp), 2 * sizeof(uint64_t)), "hipMalloc")) != GP_OK)
+            return bail(rc);
+        if ((rc = hip(hipHostMalloc(reinterpret_cast<void**>(&g->h_stamp), 2 * sizeof(uint64_t),
+                                    hipHostMallocDefault), "hipHostMalloc")) != GP_OK)
+            return bail(rc);
+        if ((rc = hip(hipDeviceGetAttribute(&g->clock_khz, hipDeviceAttributeWallClockRate, g->dev),
+                      "hipDeviceGetAttribute")) != GP_OK)
+            return bail(rc);
+        if (g->clock_khz <= 0) return bail(fail(GP_ERR_DEVICE, "gp_generation_create: no device wall clock rate"));
+    }
+    *out = g;
     return GP_OK;
+}
+
+gp_status gp_generation_run(gp_generation* g, const uint32_t* nodes, const int64_t* prog_off, const float* consts,
+                            const int64_t* const_off, const int32_t* len, uint64_t generation, float* fitness_out,
+                            int32_t* winners_out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g || !nodes || !prog_off || !const_off || !len)
+        return fail(GP_ERR_INVALID_ARG, "gp_generation_run: NULL argument");
+    const gp_generation_params& p = g->prm;
+    const int32_t P = p.n_programs;
+    if (generation > 0xffffffffull) return fail(GP_ERR_INVALID_ARG, "gp_generation_run: generation above 2^32-1");
+    if (prog_off[0] != 0 || const_off[0] != 0)
+        return fail(GP_ERR_INVALID_ARG, "gp_generation_run: offsets must start at 0");
+    const int64_t total_nodes = prog_off[P];
+    const int64_t total_consts = const_off[P];
+    if (total_nodes > p.node_capacity || total_consts > p.const_capacity)
+        return fail(GP_ERR_BUFFER_TOO_SMALL, "gp_generation_run: population exceeds the capacity given at creation");
+    if (total_consts > 0 && !consts) return fail(GP_ERR_INVALID_ARG, "gp_generation_run: consts is NULL");
+    for (int32_t q = 0; q < P; ++q)
+        if (len[q] != prog_off[q + 1] - prog_off[q] || len[q] < 1 || const_off[q + 1] < const_off[q])
+            return fail(GP_ERR_INVALID_ARG, "gp_generation_run: len / offsets are inconsistent at program " +
+                                                std::to_string(q));
+    // the device code assumes valid programs
+    int32_t bad = -1;
+    gp_status rc = gp_validate_population(nodes, prog_off, const_off, P, g->data.n_features, nullptr, &bad);
+    if (rc != GP_OK) return rc;
+    int cur = 0;
+    GP_HIP(hipGetDevice(&cur));
+    if (cur != g->dev) return fail(GP_ERR_INVALID_ARG, "gp_generation_run: another device is current");
+    GP_HIP(hipStreamSynchronize(g->stream));
+    // stage the population in pinned memory (one upload per generation)
+    const uint32_t gen32 = static_cast<uint32_t>(generation);
+    std::memcpy(g->h_stage + g->lay.gen, &gen32, sizeof gen32);
+    std::memcpy(g->h_stage + g->lay.len, len, sizeof(int32_t) * P);
+    std::memcpy(g->h_stage + g->lay.prog_off, prog_off, sizeof(int64_t) * (P + 1));
+    std::memcpy(g->h_stage + g->lay.const_off, const_off, sizeof(int64_t) * (P + 1));
+    std::memcpy(g->h_stage + g->lay.nodes, nodes, sizeof(uint32_t) * total_nodes);
+    if (total_consts > 0) std::memcpy(g->h_stage + g->lay.consts, consts, sizeof(float) * total_consts);
+    if (!g->captured) {
+        // configuration: forced, tuned on this first population, or cached/heuristic
+        g->cfg = pick_cfg(g->sc, g->data.n_features, g->data.n_rows, P, kernel_class(1, p.metric));
+        if (p.autotune && !g_forced) {
+            GP_HIP(hipMemcpyAsync(g->d_stage, g->h_stage, g->lay.bytes, hipMemcpyHostToDevice, g->stream));
+            const gp_population_dev cur_view = stage_view(g, total_nodes, total_consts);
+            rc = autotune_impl(&g->sc, &cur_view, &g->data, p.metric, 2, g->stream, &g->cfg, &g->tuned_ms);
+            if (rc != GP_OK) return rc;
+        }
+        // every buffer the graph touches exists before capture
+        int64_t chunk = 0, n_chunks = 0;
+        const gp_population_dev cap_view = stage_view(g, p.node_capacity, p.const_capacity);
+        rc = chunking(&cap_view, &g->data, g->cfg, &chunk, &n_chunks);
+        if (rc != GP_OK) return rc;
+        rc = reserve(&g->sc, P, p.node_capacity, n_chunks, 1, p.metric);
+        if (rc != GP_OK) return rc;
+        GP_HIP(hipStreamSynchronize(g->stream));
+        GP_HIP(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
+        rc = record_generation(g);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(g->stream, &graph);
+        if (rc != GP_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(GP_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        g->graph = graph;
+        if (p.time_kernel) {
+            GP_HIP(hipEventCreate(&g->ev_a));
+            GP_HIP(hipEventCreate(&g->ev_b));
+            g->events = insert_event_nodes(g->graph, g->eval_kernel, g->ev_a, g->ev_b);
+            if (!g->events) {
+                // a half-edited graph is not used: capture it again, stamps only
+                (void)hipGraphDestroy(g->graph);
+                g->graph = nullptr;
+                GP_HIP(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
+                rc = record_generation(g);
+                const hipError_t e2 = hipStreamEndCapture(g->stream, &graph);
+                if (rc != GP_OK) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    return rc;
+                }
+                if (e2 != hipSuccess)
+                    return fail(GP_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
+                g->graph = graph;
+            }
+        }
+        GP_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+        g->captured = true;
+    }
+    GP_HIP(hipGraphLaunch(g->exec, g->stream));
+    GP_HIP(hipStreamSynchronize(g->stream));
+    if (p.time_kernel) {
+        g->clock_ms = static_cast<float>(static_cast<double>(g->h_stamp[1] - g->h_stamp[0]) / g->clock_khz);
+        g->kernel_ms = g->clock_ms;
+        if (g->events) GP_HIP(hipEventElapsedTime(&g->kernel_ms, g->ev_a, g->ev_b));
+    }
+    if (fitness_out) std::memcpy(fitness_out, g->h_fit, sizeof(float) * P);
+    if (winners_out && p.n_tournaments > 0) std::memcpy(winners_out, g->h_win, sizeof(int32_t) * p.n_tournaments);
+    return GP_OK;
+}
+
+gp_status gp_generation_info(const gp_generation* g, gp_launch_config* cfg, float* kernel_ms, float* clock_ms,
+                             int32_t* timed_by_events, double* tuned_ms) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g) return fail(GP_ERR_INVALID_ARG, "gp_generation_info: NULL generation");
+    if (cfg) *cfg = gp_launch_config{g->cfg.R, g->cfg.freg, g->cfg.tiles};
+    if (kernel_ms) *kernel_ms = g->kernel_ms;
+    if (clock_ms) *clock_ms = g->clock_ms;
+    if (timed_by_events) *timed_by_events = g->events ? 1 : 0;
+    if (tuned_ms) *tuned_ms = g->tuned_ms;
+    return GP_OK;
+}
+
+void gp_generation_destroy(gp_generation* g) {
+    if (!g) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(g->dev);
+    generation_release(g);
+    (void)hipSetDevice(cur);
+    delete g;
 }
 
 gp_status gp_fitness_backward(const gp_population_dev* pop, const gp_dataset_dev* data, gp_metric metric,
                               const float* grad_fitness, float* fitness_out, float* grad_consts,
                               void* stream) {
-    (void)pop; (void)data; (void)metric; (void)grad_fitness; (void)fitness_out; (void)grad_consts;
-    (void)stream;
-    return fail(GP_ERR_UNSUPPORTED, "gp_fitness_backward: not built yet");
+    std::lock_guard<std::mutex> lk(g_mu);
+    gp_status rc = check_pop(pop, "gp_fitness_backward");
+    if (rc != GP_OK) return rc;
+    rc = check_data(data, "gp_fitness_backward", true);
+    if (rc != GP_OK) return rc;
+    rc = check_fitness_metric(metric, "gp_fitness_backward");
+    if (rc != GP_OK) return rc;
+    if (pop->n_programs == 0) return GP_OK;
+    if (pop->total_consts < 0 || (pop->total_consts > 0 && (!grad_consts || !pop->consts)))
+        return fail(GP_ERR_INVALID_ARG, "gp_fitness_backward: grad_consts and consts are needed");
+    if (pop->max_len < 1)
+        return fail(GP_ERR_INVALID_ARG, "gp_fitness_backward: max_len must bound the program lengths");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    DeviceScratch* sc;
+    rc = arena(&sc);
+    if (rc != GP_OK) return rc;
+    PopView pv;
+    CodeView cvw;
+    DataView dv;
+    Sched sch;
+    LaunchCfg cfg;
+    rc = prepare(sc, pop, data, 1, metric, st, nullptr, &pv, &cvw, &dv, &sch, &cfg);
+    if (rc != GP_OK) return rc;
+    const int32_t P = pop->n_programs;
+    const int64_t nc = std::max<int64_t>(pop->total_consts, 1);
+    constexpr int RA = 1;
+    const int64_t ovf_entries = 2 * static_cast<int64_t>(pop->max_len) + 2;   // tape entries per wavefront
+    rc = grow(reinterpret_cast<void**>(&sc->stats), &sc->stats_cap, static_cast<size_t>(P) * kStats + 1,
+              sizeof(double));
+    if (rc != GP_OK) return rc;
+    rc = grow(reinterpret_cast<void**>(&sc->gpart), &sc->gpart_cap, static_cast<size_t>(nc) * sch.n_chunks,
+              sizeof(double));
+    if (rc != GP_OK) return rc;
+    rc = grow(reinterpret_cast<void**>(&sc->gextra), &sc->gextra_cap, static_cast<size_t>(nc), sizeof(double));
+    if (rc != GP_OK) return rc;
+    rc = grow(reinterpret_cast<void**>(&sc->fit_tmp), &sc->fit_tmp_cap, static_cast<size_t>(P), sizeof(float));
+    if (rc != GP_OK) return rc;
+    double* wsum = sc->stats + static_cast<size_t>(P) * kStats;
+    const int has_w = data->w != nullptr;
+    const int ys_blocks = (sch.n_chunks + (kBlock / kWave) - 1) / (kBlock / kWave);
+    hipLaunchKernelGGL(k_ystats, dim3(ys_blocks), dim3(kBlock), 0, st, dv, sch.chunk, sch.n_chunks, sc->ystat);
+    GP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_wsum, dim3(1), dim3(kWave), 0, st, sc->ystat, sch.n_chunks, has_w, data->n_rows, wsum);
+    GP_HIP(hipGetLastError());
+    const int fblocks = (P + (kBlock / kWave) - 1) / (kBlock / kWave);
+    float* fit = fitness_out ? fitness_out : sc->fit_tmp;
+    const bool needs_forward = metric == GP_METRIC_RMSE || metric == GP_METRIC_PEARSON;
+    if (needs_forward) {
+        rc = launch_eval(1, metric, cfg, sc->n_cu, pv, cvw, dv, sch, nullptr, sc->part, st,
+                         pop->total_nodes * data->n_rows, Timing{});
+        if (rc != GP_OK) return rc;
+        if (metric == GP_METRIC_RMSE)
+            hipLaunchKernelGGL(k_finalize<GP_METRIC_RMSE>, dim3(fblocks), dim3(kBlock), 0, st, sc->part, sc->ystat,
+                               sch.n_chunks, P, data->n_rows, has_w, fit, sc->stats);
+        else
+            hipLaunchKernelGGL(k_finalize<GP_METRIC_PEARSON>, dim3(fblocks), dim3(kBlock), 0, st, sc->part,
+                               sc->ystat, sch.n_chunks, P, data->n_rows, has_w, fit, sc->stats);
+        GP_HIP(hipGetLastError());
+        // the forward pass consumed the work counter: reset it (and reorder)
+        hipLaunchKernelGGL(k_prepare, dim3(1), dim3(1024), 0, st, pop->len, P, sc->order,
+                           static_cast<uint32_t*>(sc->counter));
+        GP_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_zero, dim3(static_cast<unsigned>((nc + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                       sc->gextra, nc);
+    GP_HIP(hipGetLastError());
+    const int freg = cfg.freg > 0 && data->n_features <= 2 ? 2 : (data->n_features <= 8 ? 8 : 0);
+    double* lossp = needs_forward ? nullptr : sc->part;
+    auto go = [&](auto kernel) -> gp_status {
+        int per_cu = 0;
+        GP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWave, 0));
+        per_cu = std::max(per_cu, 1);
+        int64_t blocks = std::min<int64_t>(static_cast<int64_t>(per_cu) * sc->n_cu, sch.n_items);
+        blocks = std::max<int64_t>(blocks, 1);
+        gp_status r2 = grow(reinterpret_cast<void**>(&sc->tape), &sc->tape_cap,
+                            static_cast<size_t>(blocks) * ovf_entries * RA * kWave, sizeof(float));
+        if (r2 != GP_OK) return r2;
+        hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(blocks)), dim3(kWave), 0, st, pv, cvw, dv, sch,
+                           needs_forward ? sc->stats : nullptr, wsum, grad_fitness, lossp, sc->gpart, sc->gextra,
+                           sc->tape, ovf_entries);
+        GP_HIP(hipGetLastError());
+        return GP_OK;
+    };
+#define GP_ADJ(M)                                                          \
+    (freg == 2 ? go(k_adjoint<RA, 2, M>) : freg == 8 ? go(k_adjoint<RA, 8, M>) : go(k_adjoint<RA, 0, M>))
+    switch (metric) {
+    case GP_METRIC_MAE: rc = GP_ADJ(GP_METRIC_MAE); break;
+    case GP_METRIC_MSE: rc = GP_ADJ(GP_METRIC_MSE); break;
+    case GP_METRIC_RMSE: rc = GP_ADJ(GP_METRIC_RMSE); break;
+    case GP_METRIC_LOGLOSS: rc = GP_ADJ(GP_METRIC_LOGLOSS); break;
+    default: rc = GP_ADJ(GP_METRIC_PEARSON); break;
+    }
+#undef GP_ADJ
+    if (rc != GP_OK) return rc;
+    if (!needs_forward && fitness_out) {
+        if (metric == GP_METRIC_MAE)
+            hipLaunchKernelGGL(k_finalize<GP_METRIC_MAE>, dim3(fblocks), dim3(kBlock), 0, st, sc->part, sc->ystat,
+                               sch.n_chunks, P, data->n_rows, has_w, fitness_out, nullptr);
+        else if (metric == GP_METRIC_MSE)
+            hipLaunchKernelGGL(k_finalize<GP_METRIC_MSE>, dim3(fblocks), dim3(kBlock), 0, st, sc->part, sc->ystat,
+                               sch.n_chunks, P, data->n_rows, has_w, fitness_out, nullptr);
+        else
+            hipLaunchKernelGGL(k_finalize<GP_METRIC_LOGLOSS>, dim3(fblocks), dim3(kBlock), 0, st, sc->part,
+                               sc->ystat, sch.n_chunks, P, data->n_rows, has_w, fitness_out, nullptr);
+        GP_HIP(hipGetLastError());
+    }
+    if (pop->total_consts > 0) {
+        hipLaunchKernelGGL(k_finalize_grad, dim3(fblocks), dim3(kBlock), 0, st, sc->gpart, sc->gextra,
+                           pop->const_off, P, sch.n_chunks, grad_consts);
+        GP_HIP(hipGetLastError());
+    }
+    return GP_OK;
 }
 
 }  // extern "C"

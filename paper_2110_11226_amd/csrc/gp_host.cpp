@@ -1,5 +1,6 @@
 // gp_host.cpp -- host side of the library: status text, population
 // generation (Sec. II-A, Sec. III-A) and population validation.
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -161,7 +162,205 @@ struct Gen {
             }
         }
     }
+
+    // One program by the configured method (Sec. II-A): ramped half-and-half
+    // draws Grow or Full and then the depth; exact length draws the length.
+    void program(Draws& dr) {
+        nodes.clear();
+        consts.clear();
+        if (prm.method == GP_INIT_EXACT_LEN) {
+            exact(dr);
+            return;
+        }
+        bool full;
+        if (prm.method == GP_INIT_RHH) full = !(unit(dr.next()) < 0.5f);
+        else full = (prm.method == GP_INIT_FULL);
+        const int depth = prm.min_depth +
+                          static_cast<int>(below(dr.next(), static_cast<uint32_t>(prm.max_depth - prm.min_depth + 1)));
+        tree(dr, depth, full);
+    }
 };
+
+gp_status check_init(const gp_init_params& p, const char* who) {
+    if (p.n_programs < 0 || p.n_features < 1)
+        return fail(GP_ERR_INVALID_ARG, std::string(who) + ": need n_programs >= 0 and n_features >= 1");
+    const uint32_t allowed = ((1u << GP_OP_COUNT) - 1u) & ~3u;
+    if (p.function_mask == 0 || (p.function_mask & ~allowed))
+        return fail(GP_ERR_INVALID_ARG, std::string(who) + ": function_mask must select functions (bits 2..11) only");
+    if (p.method == GP_INIT_EXACT_LEN) {
+        if (p.min_len < 1 || p.max_len < p.min_len || p.max_len > (1 << 20))
+            return fail(GP_ERR_INVALID_ARG, std::string(who) + ": need 1 <= min_len <= max_len <= 2^20");
+        bool has_binary = false;
+        for (uint32_t op = GP_OP_ADD; op <= GP_OP_DIV; ++op) has_binary |= (p.function_mask >> op) & 1u;
+        if (!has_binary && p.max_len > 1)
+            return fail(GP_ERR_INVALID_ARG, std::string(who) + ": exact lengths above 1 need a binary function");
+    } else if (p.method >= GP_INIT_RHH && p.method <= GP_INIT_GROW) {
+        if (p.min_depth < 0 || p.max_depth < p.min_depth || p.max_depth > GP_MAX_STACK - 1)
+            return fail(GP_ERR_INVALID_ARG, std::string(who) + ": need 0 <= min_depth <= max_depth <= 19");
+    } else {
+        return fail(GP_ERR_INVALID_ARG, std::string(who) + ": unknown method");
+    }
+    return GP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Genetic operations (Sec. II-A, Sec. III-C2), applied on the host.
+// ---------------------------------------------------------------------------
+// A program being assembled: node words, with each constant's value carried
+// beside its node; slots are renumbered in prefix order when it is emitted.
+struct Prog {
+    std::vector<uint32_t> w;
+    std::vector<float> val;
+};
+
+Prog load_prog(const uint32_t* nodes, const int64_t* prog_off, const float* consts, const int64_t* const_off,
+               int32_t p) {
+    Prog g;
+    const float* pc = consts ? consts + const_off[p] : nullptr;
+    for (int64_t i = prog_off[p]; i < prog_off[p + 1]; ++i) {
+        const uint32_t w = nodes[i];
+        g.w.push_back(w);
+        g.val.push_back(GP_NODE_OP(w) == GP_OP_CONST ? pc[GP_NODE_ARG(w)] : 0.0f);
+    }
+    return g;
+}
+
+Prog from_gen(const Gen& gen) {
+    Prog g;
+    for (uint32_t w : gen.nodes) {
+        g.w.push_back(w);
+        g.val.push_back(GP_NODE_OP(w) == GP_OP_CONST ? gen.consts[GP_NODE_ARG(w)] : 0.0f);
+    }
+    return g;
+}
+
+// One past the last node of the subtree whose root is at position s.
+size_t subtree_end(const std::vector<uint32_t>& w, size_t s) {
+    int open = 1;
+    size_t i = s;
+    while (open > 0) {
+        open += arity(GP_NODE_OP(w[i])) - 1;
+        ++i;
+    }
+    return i;
+}
+
+// Peak stack height of the right-to-left scan of a valid program.
+int peak_height(const std::vector<uint32_t>& w) {
+    int h = 0, hmax = 0;
+    for (size_t i = w.size(); i-- > 0;) {
+        h += 1 - arity(GP_NODE_OP(w[i]));
+        hmax = std::max(hmax, h);
+    }
+    return hmax;
+}
+
+// parent[0:s) + donor[ds:de) + parent[e:)
+Prog splice(const Prog& p, size_t s, size_t e, const Prog& d, size_t ds, size_t de) {
+    Prog c;
+    c.w.assign(p.w.begin(), p.w.begin() + s);
+    c.val.assign(p.val.begin(), p.val.begin() + s);
+    c.w.insert(c.w.end(), d.w.begin() + ds, d.w.begin() + de);
+    c.val.insert(c.val.end(), d.val.begin() + ds, d.val.begin() + de);
+    c.w.insert(c.w.end(), p.w.begin() + e, p.w.end());
+    c.val.insert(c.val.end(), p.val.begin() + e, p.val.end());
+    return c;
+}
+
+// Crossover with hoisting (Sec. III-C2): a uniformly chosen subtree of the
+// parent is replaced by a uniformly chosen subtree of the donor; while the
+// child's stack would exceed GP_MAX_STACK or its length max_len, the donor
+// subtree is replaced by a uniformly chosen proper subtree of itself.
+Prog crossover(const Prog& parent, const Prog& donor, Draws& dr, int32_t max_len) {
+    const size_t s = below(dr.next(), static_cast<uint32_t>(parent.w.size()));
+    const size_t e = subtree_end(parent.w, s);
+    size_t ds = below(dr.next(), static_cast<uint32_t>(donor.w.size()));
+    size_t de = subtree_end(donor.w, ds);
+    for (;;) {
+        Prog c = splice(parent, s, e, donor, ds, de);
+        const bool fits = peak_height(c.w) <= GP_MAX_STACK && static_cast<int64_t>(c.w.size()) <= max_len;
+        if (fits || de - ds == 1) return c;
+        ds = ds + 1 + below(dr.next(), static_cast<uint32_t>(de - ds - 1));
+        de = subtree_end(donor.w, ds);
+    }
+}
+
+// Hoist mutation: a uniformly chosen subtree is replaced by a uniformly
+// chosen subtree of itself (possibly itself).
+Prog hoist(const Prog& parent, Draws& dr) {
+    const size_t s = below(dr.next(), static_cast<uint32_t>(parent.w.size()));
+    const size_t e = subtree_end(parent.w, s);
+    const size_t s2 = s + below(dr.next(), static_cast<uint32_t>(e - s));
+    const size_t e2 = subtree_end(parent.w, s2);
+    return splice(parent, s, e, parent, s2, e2);
+}
+
+// Point mutation: each node, in prefix order, is replaced with probability
+// p_replace -- a function by one of the same arity from the function set, a
+// terminal by a variable or (if constants are enabled and the program's
+// other constants number below max_consts) a new constant.
+Prog point(const Prog& parent, const Gen& gen, float p_replace, Draws& dr) {
+    Prog c = parent;
+    int n_const = 0;
+    for (uint32_t w : c.w) n_const += GP_NODE_OP(w) == GP_OP_CONST;
+    const int nf = gen.prm.n_features;
+    for (size_t j = 0; j < c.w.size(); ++j) {
+        if (!(unit(dr.next()) < p_replace)) continue;
+        const uint32_t op = GP_NODE_OP(c.w[j]);
+        const int ar = arity(op);
+        if (ar > 0) {
+            const std::vector<uint32_t>& set = ar == 1 ? gen.fs.unary : gen.fs.binary;
+            if (set.empty()) continue;
+            c.w[j] = GP_NODE(set[below(dr.next(), static_cast<uint32_t>(set.size()))], 0);
+            continue;
+        }
+        const int others = n_const - (op == GP_OP_CONST ? 1 : 0);
+        const int n_term = nf + (gen.const_available(others) ? 1 : 0);
+        const int pick = static_cast<int>(below(dr.next(), static_cast<uint32_t>(n_term)));
+        if (pick < nf) {
+            c.w[j] = GP_NODE(GP_OP_VAR, pick);
+            c.val[j] = 0.0f;
+            n_const = others;
+        } else {
+            c.w[j] = GP_NODE(GP_OP_CONST, 0);
+            c.val[j] = gen.draw_const(dr);
+            n_const = others + 1;
+        }
+    }
+    return c;
+}
+
+// float32 cumulative thresholds of the operation draw
+struct OpThresholds {
+    float t[4];
+};
+OpThresholds thresholds(const gp_evolve_params& e) {
+    OpThresholds o;
+    o.t[0] = e.p_crossover;
+    o.t[1] = o.t[0] + e.p_subtree;
+    o.t[2] = o.t[1] + e.p_hoist;
+    o.t[3] = o.t[2] + e.p_point;
+    return o;
+}
+
+int32_t draw_op(const OpThresholds& th, Draws& dr) {
+    const float u = unit(dr.next());
+    for (int32_t k = 0; k < 4; ++k)
+        if (u < th.t[k]) return k;
+    return GP_GENOP_REPRODUCTION;
+}
+
+gp_status check_evolve(const gp_evolve_params* e, const char* who) {
+    if (!e) return fail(GP_ERR_INVALID_ARG, std::string(who) + ": params is NULL");
+    const float ps[5] = {e->p_crossover, e->p_subtree, e->p_hoist, e->p_point, e->p_point_replace};
+    for (float v : ps)
+        if (!(v >= 0.0f && v <= 1.0f))
+            return fail(GP_ERR_INVALID_ARG, std::string(who) + ": probabilities must lie in [0, 1]");
+    if (!(thresholds(*e).t[3] <= 1.0f))
+        return fail(GP_ERR_INVALID_ARG, std::string(who) + ": operation probabilities sum above 1");
+    if (e->max_len < 1) return fail(GP_ERR_INVALID_ARG, std::string(who) + ": max_len must be >= 1");
+    return GP_OK;
+}
 
 }  // namespace
 }  // namespace gp
@@ -191,24 +390,8 @@ gp_status gp_build_population(const gp_init_params* prm, uint32_t* nodes, int64_
                               int64_t* total_consts) {
     if (!prm) return fail(GP_ERR_INVALID_ARG, "gp_build_population: params is NULL");
     const gp_init_params& p = *prm;
-    if (p.n_programs < 0 || p.n_features < 1)
-        return fail(GP_ERR_INVALID_ARG, "gp_build_population: need n_programs >= 0 and n_features >= 1");
-    const uint32_t allowed = ((1u << GP_OP_COUNT) - 1u) & ~3u;
-    if (p.function_mask == 0 || (p.function_mask & ~allowed))
-        return fail(GP_ERR_INVALID_ARG, "gp_build_population: function_mask must select functions (bits 2..11) only");
-    if (p.method == GP_INIT_EXACT_LEN) {
-        if (p.min_len < 1 || p.max_len < p.min_len || p.max_len > (1 << 20))
-            return fail(GP_ERR_INVALID_ARG, "gp_build_population: need 1 <= min_len <= max_len <= 2^20");
-        bool has_binary = false;
-        for (uint32_t op = GP_OP_ADD; op <= GP_OP_DIV; ++op) has_binary |= (p.function_mask >> op) & 1u;
-        if (!has_binary && p.max_len > 1)
-            return fail(GP_ERR_INVALID_ARG, "gp_build_population: exact lengths above 1 need a binary function");
-    } else if (p.method >= GP_INIT_RHH && p.method <= GP_INIT_GROW) {
-        if (p.min_depth < 0 || p.max_depth < p.min_depth || p.max_depth > GP_MAX_STACK - 1)
-            return fail(GP_ERR_INVALID_ARG, "gp_build_population: need 0 <= min_depth <= max_depth <= 19");
-    } else {
-        return fail(GP_ERR_INVALID_ARG, "gp_build_population: unknown method");
-    }
+    gp_status rc = check_init(p, "gp_build_population");
+    if (rc != GP_OK) return rc;
     if (nodes && (!prog_off || !const_off || !len || (consts_cap > 0 && !consts)))
         return fail(GP_ERR_INVALID_ARG, "gp_build_population: output arrays must be given with nodes");
 
@@ -217,18 +400,7 @@ gp_status gp_build_population(const gp_init_params* prm, uint32_t* nodes, int64_
     bool short_buf = false;
     for (int32_t prog = 0; prog < p.n_programs; ++prog) {
         Draws dr(p.seed, static_cast<uint32_t>(prog), 0u, kStreamInit);
-        gen.nodes.clear();
-        gen.consts.clear();
-        if (p.method == GP_INIT_EXACT_LEN) {
-            gen.exact(dr);
-        } else {
-            bool full;
-            if (p.method == GP_INIT_RHH) full = !(unit(dr.next()) < 0.5f);
-            else full = (p.method == GP_INIT_FULL);
-            const int depth = p.min_depth +
-                              static_cast<int>(below(dr.next(), static_cast<uint32_t>(p.max_depth - p.min_depth + 1)));
-            gen.tree(dr, depth, full);
-        }
+        gen.program(dr);
         if (nodes) {
             prog_off[prog] = n_nodes;
             const_off[prog] = n_consts;
@@ -290,6 +462,111 @@ gp_status gp_validate_population(const uint32_t* nodes, const int64_t* prog_off,
         if (h != 1) return bad(GP_ERR_INVALID_PROGRAM, "more than one value left on the stack");
         if (max_height) max_height[p] = hmax;
     }
+    return ok();
+}
+
+gp_status gp_plan_generation(const gp_evolve_params* params, int32_t n_offspring, uint64_t generation,
+                             int32_t* ops, int32_t* first_tournament, int32_t* n_tournaments) {
+    gp_status rc = check_evolve(params, "gp_plan_generation");
+    if (rc != GP_OK) return rc;
+    if (n_offspring < 0 || generation > 0xffffffffull || !n_tournaments || (n_offspring > 0 && (!ops || !first_tournament)))
+        return fail(GP_ERR_INVALID_ARG, "gp_plan_generation: bad arguments");
+    const OpThresholds th = thresholds(*params);
+    int64_t t = 0;
+    for (int32_t i = 0; i < n_offspring; ++i) {
+        Draws dr(params->seed, static_cast<uint32_t>(i), static_cast<uint32_t>(generation), kStreamMutation);
+        ops[i] = draw_op(th, dr);
+        first_tournament[i] = static_cast<int32_t>(t);
+        t += ops[i] == GP_GENOP_CROSSOVER ? 2 : 1;
+        if (t > 0x7fffffff) return fail(GP_ERR_INVALID_ARG, "gp_plan_generation: too many tournaments");
+    }
+    *n_tournaments = static_cast<int32_t>(t);
+    return ok();
+}
+
+gp_status gp_mutate(const gp_evolve_params* params, const gp_init_params* init, const uint32_t* nodes,
+                    const int64_t* prog_off, const float* consts, const int64_t* const_off, int32_t n_parents,
+                    const int32_t* ops, const int32_t* first_tournament, const int32_t* winners, int32_t n_winners,
+                    int32_t n_offspring, uint64_t generation, uint32_t* out_nodes, int64_t nodes_cap,
+                    int64_t* out_prog_off, float* out_consts, int64_t consts_cap, int64_t* out_const_off,
+                    int32_t* out_len, int64_t* total_nodes, int64_t* total_consts) {
+    gp_status rc = check_evolve(params, "gp_mutate");
+    if (rc != GP_OK) return rc;
+    if (!init) return fail(GP_ERR_INVALID_ARG, "gp_mutate: init params are NULL");
+    rc = check_init(*init, "gp_mutate");
+    if (rc != GP_OK) return rc;
+    if (n_parents < 1 || n_offspring < 0 || n_winners < 0 || generation > 0xffffffffull || !total_nodes ||
+        !total_consts || !out_prog_off || !out_const_off || (n_offspring > 0 && (!ops || !first_tournament || !out_len)) ||
+        (n_winners > 0 && !winners))
+        return fail(GP_ERR_INVALID_ARG, "gp_mutate: bad arguments");
+    // the parents must be valid programs over init->n_features
+    rc = gp_validate_population(nodes, prog_off, const_off, n_parents, init->n_features, nullptr, nullptr);
+    if (rc != GP_OK) return rc;
+    if (const_off[n_parents] > 0 && !consts) return fail(GP_ERR_INVALID_ARG, "gp_mutate: consts is NULL");
+    for (int32_t i = 0; i < n_offspring; ++i) {
+        const int32_t need = ops[i] == GP_GENOP_CROSSOVER ? 2 : 1;
+        if (ops[i] < 0 || ops[i] > GP_GENOP_REPRODUCTION || first_tournament[i] < 0 ||
+            static_cast<int64_t>(first_tournament[i]) + need > n_winners)
+            return fail(GP_ERR_INVALID_ARG, "gp_mutate: operation or tournament index out of range at offspring " +
+                                                std::to_string(i));
+        for (int32_t k = 0; k < need; ++k) {
+            const int32_t wv = winners[first_tournament[i] + k];
+            if (wv < 0 || wv >= n_parents)
+                return fail(GP_ERR_INVALID_ARG, "gp_mutate: winner index out of range at offspring " + std::to_string(i));
+        }
+    }
+    const Gen gen(*init);
+    Gen donor_gen(*init);
+    int64_t n_nodes = 0, n_consts = 0;
+    bool short_buf = false;
+    for (int32_t i = 0; i < n_offspring; ++i) {
+        Draws dr(params->seed, static_cast<uint32_t>(i), static_cast<uint32_t>(generation), kStreamMutation);
+        (void)dr.next();   // the operation draw (gp_plan_generation)
+        const Prog parent = load_prog(nodes, prog_off, consts, const_off, winners[first_tournament[i]]);
+        Prog child;
+        switch (ops[i]) {
+        case GP_GENOP_CROSSOVER: {
+            const Prog donor = load_prog(nodes, prog_off, consts, const_off, winners[first_tournament[i] + 1]);
+            child = crossover(parent, donor, dr, params->max_len);
+            break;
+        }
+        case GP_GENOP_SUBTREE: {
+            Draws ddr(params->seed, static_cast<uint32_t>(i), static_cast<uint32_t>(generation), kStreamDonor);
+            donor_gen.program(ddr);
+            child = crossover(parent, from_gen(donor_gen), dr, params->max_len);
+            break;
+        }
+        case GP_GENOP_HOIST: child = hoist(parent, dr); break;
+        case GP_GENOP_POINT: child = point(parent, gen, params->p_point_replace, dr); break;
+        default: child = parent; break;
+        }
+        out_prog_off[i] = n_nodes;
+        out_const_off[i] = n_consts;
+        out_len[i] = static_cast<int32_t>(child.w.size());
+        int64_t nc = 0;
+        for (uint32_t w : child.w) nc += GP_NODE_OP(w) == GP_OP_CONST;
+        if (n_nodes + static_cast<int64_t>(child.w.size()) > nodes_cap || n_consts + nc > consts_cap || !out_nodes ||
+            (nc > 0 && !out_consts)) {
+            short_buf = true;
+        } else {
+            uint32_t slot = 0;
+            for (size_t j = 0; j < child.w.size(); ++j) {
+                uint32_t w = child.w[j];
+                if (GP_NODE_OP(w) == GP_OP_CONST) {
+                    out_consts[n_consts + slot] = child.val[j];
+                    w = GP_NODE(GP_OP_CONST, slot++);
+                }
+                out_nodes[n_nodes + static_cast<int64_t>(j)] = w;
+            }
+        }
+        n_nodes += static_cast<int64_t>(child.w.size());
+        n_consts += nc;
+    }
+    out_prog_off[n_offspring] = n_nodes;
+    out_const_off[n_offspring] = n_consts;
+    *total_nodes = n_nodes;
+    *total_consts = n_consts;
+    if (short_buf) return fail(GP_ERR_BUFFER_TOO_SMALL, "gp_mutate: nodes_cap or consts_cap too small");
     return ok();
 }
 

@@ -48,7 +48,7 @@ GP_HD Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, 
 }
 
 // Stream tags of the counter's fourth word.
-enum : uint32_t { kStreamTournament = 0, kStreamInit = 1, kStreamMutation = 2 };
+enum : uint32_t { kStreamTournament = 0, kStreamInit = 1, kStreamMutation = 2, kStreamDonor = 3 };
 
 // floor(word * n / 2^32): a draw in [0, n).
 GP_HD uint32_t below(uint32_t word, uint32_t n) {

@@ -1,0 +1,100 @@
+"""The generational loop (Alg. 1 of the paper, with the Sec. III-C order:
+pre-draw the genetic operations, select by tournament on the device,
+mutate on the host, evaluate on the device).
+
+Each generation is one replay of a captured graph (population upload,
+fitness, tournaments, result download: ``Generation``), then the host pre-draw
+(``plan_generation``) and genetic operations (``mutate``).  The graph always
+runs the largest number of tournaments a generation can need (two per
+offspring); a generation uses the first ones, which are the same as if only
+those had been run (the draws are counter-based).  With ``use_graph=False``
+the same steps run as plain calls (fitness, tournament), which gives the same
+results bit for bit.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import _binding as B
+
+
+@dataclass
+class GenerationLog:
+    generation: int
+    best: float
+    best_program: int
+    mean: float
+    median: float
+    total_nodes: int
+    kernel_ms: float
+
+
+@dataclass
+class RunResult:
+    population: B.HostPopulation     # the last generation's programs
+    fitness: np.ndarray              # their fitness
+    history: list = field(default_factory=list)
+    launch_config: tuple | None = None
+
+
+def _log(g, fit, pop, larger, kernel_ms):
+    finite = np.where(np.isfinite(fit), fit, -np.inf if larger else np.inf)
+    best = int(np.argmax(finite) if larger else np.argmin(finite))
+    ok = fit[np.isfinite(fit)]
+    return GenerationLog(g, float(fit[best]), best, float(ok.mean()) if ok.size else float("nan"),
+                         float(np.median(ok)) if ok.size else float("nan"), int(pop.nodes.shape[0]), kernel_ms)
+
+
+def run_generations(data: B.DeviceDataset, n_generations: int, n_programs: int, init: dict,
+                    metric="mse", tournament_size=20, parsimony=0.0, evolve: dict | None = None,
+                    seed=0, use_graph=True, autotune=False, time_kernel=False, callback=None) -> RunResult:
+    """Evolves `n_programs` programs for `n_generations` generations.
+
+    init: initialisation settings (n_features, method, min_depth, max_depth,
+    min_len, max_len, function_mask, const_lo, const_hi, max_consts, seed).
+    evolve: genetic-operation settings (p_crossover, p_subtree, p_hoist,
+    p_point, p_point_replace, max_len, seed); defaults are those of the
+    paper's large-scale runs (crossover 0.7, subtree 0.1, hoist 0.05, point
+    0.1, reproduction 0.05)."""
+    evolve = dict(evolve or {})
+    evolve.setdefault("max_len", 1024)
+    evolve.setdefault("seed", seed)
+    init = dict(init)
+    init_seed = init.pop("seed", seed)
+    larger = B.larger_is_better(metric)
+    gen_kw = {k: init[k] for k in ("min_depth", "max_depth", "min_len", "max_len", "function_mask", "const_lo",
+                                   "const_hi", "max_consts") if k in init}
+    pop = B.build_population(n_programs, init["n_features"], init.get("method", "rhh"), seed=init_seed, **gen_kw)
+    longest = int(pop.length.max(initial=1))
+    cap = n_programs * max(int(evolve["max_len"]), longest)
+    T_max = 2 * n_programs
+    graph = None
+    if use_graph:
+        graph = B.Generation(data, n_programs, cap, cap, metric, parsimony, tournament_size, T_max, seed,
+                             autotune=autotune, time_kernel=time_kernel)
+    history = []
+    try:
+        for g in range(n_generations + 1):
+            if graph is not None:
+                fit, win = graph.run(pop, g)
+                kernel_ms = graph.info()[1]
+            else:
+                dpop = B.DevicePopulation(pop, validate=True, n_features=init["n_features"])
+                fit_d = B.fitness(dpop, data, metric)
+                win_d = B.tournament(fit_d, dpop.length, metric, parsimony, tournament_size, T_max, seed, g)
+                fit, win = fit_d.cpu().numpy(), win_d.cpu().numpy()
+                kernel_ms = -1.0
+            history.append(_log(g, fit, pop, larger, kernel_ms))
+            if callback is not None:
+                callback(history[-1], pop, fit)
+            if g == n_generations:
+                break
+            ops, ft, T = B.plan_generation(n_programs, g, **evolve)
+            pop = B.mutate(pop, ops, ft, win[:T], g, init, **evolve)
+        cfg = graph.info()[0] if graph is not None else None
+        return RunResult(pop, fit, history, cfg)
+    finally:
+        if graph is not None:
+            graph.close()

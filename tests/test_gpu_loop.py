@@ -1,0 +1,102 @@
+"""GPU tests of the generational loop (Alg. 1; Sec. III-C order): the
+graph-captured loop against the loop of plain calls (bit-identical fitness
+sequences and populations), and every generation against the oracle given
+the GPU's fitness arrays (tournament winners and offspring bit-exact,
+fitness within the parity tolerance)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from _parity import to_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gp():
+    import torch
+    import paper_2110_11226_amd as gp
+    torch.cuda.set_device(0)
+    gp.set_launch_config(None)
+    return gp
+
+
+def record(store):
+    def cb(log, pop, fit):
+        store.append((log, gp_copy(pop), fit.copy()))
+    return cb
+
+
+def gp_copy(pop):
+    import paper_2110_11226_amd as gp
+    return gp.HostPopulation(pop.nodes.copy(), pop.prog_off.copy(), pop.consts.copy(), pop.const_off.copy(),
+                             pop.length.copy())
+
+
+INIT = dict(n_features=2, method="rhh", min_depth=2, max_depth=6, seed=2111)
+EVOLVE = dict(p_crossover=0.7, p_subtree=0.1, p_hoist=0.05, p_point=0.1, p_point_replace=0.05, max_len=256)
+
+
+def test_graph_loop_equals_plain_loop(gp):
+    X, y = synth.pagie(65_536, seed=11228)
+    data = gp.DeviceDataset(X, y)
+    a, b = [], []
+    ra = gp.run_generations(data, 4, 200, INIT, "mse", 20, 0.01, EVOLVE, seed=7, use_graph=True, callback=record(a))
+    rb = gp.run_generations(data, 4, 200, INIT, "mse", 20, 0.01, EVOLVE, seed=7, use_graph=False,
+                            callback=record(b))
+    assert len(a) == len(b) == 5
+    for (la, pa, fa), (lb, pb, fb) in zip(a, b):
+        assert np.array_equal(fa.view(np.uint32), fb.view(np.uint32)), la.generation
+        assert np.array_equal(pa.nodes, pb.nodes) and np.array_equal(pa.consts.view(np.uint32),
+                                                                      pb.consts.view(np.uint32))
+    assert np.array_equal(ra.fitness.view(np.uint32), rb.fitness.view(np.uint32))
+
+
+def test_loop_against_oracle_each_generation(gp):
+    N, P, G = 4096, 64, 3
+    X, y = synth.pagie(N, seed=11227)
+    data = gp.DeviceDataset(X, y)
+    steps = []
+    seed = 11
+    gp.run_generations(data, G, P, INIT, "mse", 20, 0.01, EVOLVE, seed=seed, callback=record(steps))
+    init = dict(INIT)
+    init.pop("seed")
+    ev = oracle.EvolveParams(**EVOLVE, seed=seed)
+    oi = oracle.InitParams(n_features=2, method="rhh", min_depth=2, max_depth=6)
+    # generation 0 is the initial population
+    o0 = oracle.build_population(P, 2, "rhh", min_depth=2, max_depth=6, seed=2111)
+    assert np.array_equal(steps[0][1].nodes, o0.nodes)
+    for g in range(G):
+        _, pop, fit = steps[g]
+        opop = to_oracle(pop)
+        f32p, f64 = oracle.fitness(opop, X, y, None, "mse", n_threads=8)
+        ok = np.isfinite(f64) & (np.abs(f32p - f64) <= 1e-6 * np.abs(f64))
+        assert np.allclose(fit[ok], f32p[ok], rtol=1e-4, atol=0), g
+        assert np.array_equal(np.isfinite(fit), np.isfinite(f32p))
+        ops, ft, T = oracle.plan_generation(ev, P, g)
+        win = oracle.tournament(fit, pop.length, False, 0.01, 20, T, seed, g)
+        kids = oracle.mutate(ev, oi, opop, ops, ft, win, g)
+        nxt = steps[g + 1][1]
+        assert np.array_equal(kids.nodes, nxt.nodes), g
+        assert np.array_equal(kids.consts.view(np.uint32), nxt.consts.view(np.uint32)), g
+        assert np.array_equal(kids.length, nxt.length), g
+
+
+def test_pagie_one_million_rows_twenty_generations(gp):
+    """The 1,048,576-row loop shape: population 1000, RHH depth 2-8, twenty
+    generations of crossover / subtree / hoist / point mutation."""
+    import time
+    X, y = synth.pagie(1_048_576, seed=11228)
+    data = gp.DeviceDataset(X, y)
+    init = dict(n_features=2, method="rhh", min_depth=2, max_depth=8, seed=2112)
+    t0 = time.time()
+    res = gp.run_generations(data, 20, 1000, init, "mse", 20, 0.01, EVOLVE, seed=2112, time_kernel=True)
+    wall = time.time() - t0
+    assert len(res.history) == 21
+    gp.validate_population(res.population, 2)
+    assert np.isfinite(min(h.best for h in res.history))
+    assert all(h.kernel_ms > 0 for h in res.history)
+    print(f"1M-row loop: 20 generations in {wall:.2f} s; best MSE {res.history[0].best:.4g} -> "
+          f"{min(h.best for h in res.history):.4g}; kernel ms/gen "
+          f"{np.mean([h.kernel_ms for h in res.history]):.2f}")

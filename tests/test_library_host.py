@@ -121,7 +121,7 @@ def test_device_entry_points_reject_bad_arguments_before_launch(gp):
     # NULL population / dataset / outputs are rejected on the host
     assert B._fitness(None, None, 1, None, None) == -1
     assert B._evaluate(None, None, None, None) == -1
-    pv = B.PopulationDev(None, None, None, None, None, 3, 10, 5)
+    pv = B.PopulationDev(None, None, None, None, None, 3, 10, 5, 0)
     dv = B.DatasetDev(None, 0, 2, 0, None, None)
     assert B._fitness(ctypes.byref(pv), ctypes.byref(dv), 1, None, None) == -1
     # tournament argument checks
@@ -141,3 +141,60 @@ def test_device_entry_points_reject_bad_arguments_before_launch(gp):
 def test_metric_direction(gp):
     assert [gp.larger_is_better(m) for m in ("mae", "mse", "rmse", "logloss", "pearson", "spearman")] == \
         [False, False, False, False, True, True]
+
+
+MUT_CASES = [
+    dict(F=1, method="rhh", max_consts=0, p_point_replace=0.05, max_len=4096),
+    dict(F=2, method="exact_len", max_consts=4, p_point_replace=0.5, max_len=40),
+    dict(F=8, method="grow", max_consts=16, p_point_replace=1.0, max_len=8),
+    dict(F=3, method="full", max_consts=0, p_point_replace=0.2, max_len=64),
+]
+
+
+@pytest.mark.parametrize("case", MUT_CASES)
+@pytest.mark.parametrize("generation", [0, 7])
+def test_genetic_operations_bit_exact_with_oracle(gp, case, generation):
+    F, meth = case["F"], case["method"]
+    init = dict(n_features=F, method=meth, min_depth=1, max_depth=7, min_len=1, max_len=80,
+                max_consts=case["max_consts"])
+    parents = gp.build_population(96, F, meth, min_depth=1, max_depth=7, min_len=1, max_len=80,
+                                  max_consts=case["max_consts"], seed=generation + 11)
+    ev = dict(p_crossover=0.4, p_subtree=0.2, p_hoist=0.15, p_point=0.15,
+              p_point_replace=case["p_point_replace"], max_len=case["max_len"], seed=4242)
+    ops, ft, T = gp.plan_generation(96, generation, **ev)
+    o_ops, o_ft, o_T = oracle.plan_generation(oracle.EvolveParams(**ev), 96, generation)
+    assert np.array_equal(ops, o_ops) and np.array_equal(ft, o_ft) and T == o_T
+    win = np.random.default_rng(generation).integers(0, 96, size=T).astype(np.int32)
+    a = gp.mutate(parents, ops, ft, win, generation, init, **ev)
+    b = oracle.mutate(oracle.EvolveParams(**ev), oracle.InitParams(**init),
+                      oracle.Population(parents.nodes, parents.prog_off, parents.consts, parents.const_off,
+                                        parents.length), ops, ft, win, generation)
+    assert np.array_equal(a.nodes, b.nodes)
+    assert np.array_equal(a.consts.view(np.uint32), b.consts.view(np.uint32))
+    assert np.array_equal(a.prog_off, b.prog_off) and np.array_equal(a.const_off, b.const_off)
+    assert np.array_equal(a.length, b.length)
+    gp.validate_population(a, F)
+
+
+def test_genetic_operation_errors(gp):
+    parents = gp.build_population(10, 2, "rhh", seed=1)
+    init = dict(n_features=2)
+    with pytest.raises(gp.GPError, match="INVALID_ARG"):
+        gp.plan_generation(10, 0, p_crossover=0.8, p_subtree=0.3)     # sums above 1
+    with pytest.raises(gp.GPError, match="INVALID_ARG"):
+        gp.plan_generation(10, 0, p_hoist=-0.1)
+    with pytest.raises(gp.GPError, match="INVALID_ARG"):
+        gp.plan_generation(10, 0, max_len=0)
+    ops, ft, T = gp.plan_generation(10, 0)
+    win = np.zeros(T, np.int32)
+    bad = win.copy()
+    bad[-1] = 10                                                        # not a parent index
+    with pytest.raises(gp.GPError, match="INVALID_ARG"):
+        gp.mutate(parents, ops, ft, bad, 0, init)
+    with pytest.raises(gp.GPError, match="INVALID_ARG"):
+        gp.mutate(parents, ops, ft, win[:-1], 0, init)                  # too few winners
+    broken = gp.HostPopulation(parents.nodes.copy(), parents.prog_off, parents.consts, parents.const_off,
+                               parents.length)
+    broken.nodes[int(parents.prog_off[1]) - 1] = oracle.node(oracle.ADD)
+    with pytest.raises(gp.GPError, match="INVALID_PROGRAM"):
+        gp.mutate(broken, ops, ft, win, 0, init)
