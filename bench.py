@@ -1,18 +1,27 @@
 """Throughput of the GP hot path on one MI355X.
 
-One step = one generation's pass over the hot path on the 16,777,216-row
-Pagie workload: upload the population (one async copy per array from pinned
-host memory), evaluate every program on every row with the fused MSE fitness
-(gp_fitness), and run the tournament selection (gp_tournament).  The dataset
-is resident in HBM before timing starts.
+One step = one generation of the 16,777,216-row Pagie workload (4096
+programs of 1-200 nodes), replayed from a captured HIP graph: the host
+validates and stages the population in pinned memory, and the graph uploads
+it in one copy, runs the instruction pre-pass, the fused MSE fitness (one
+persistent launch of the evaluation kernel over every (row chunk, program)
+work item, launch configuration from the autotuner), the tournaments, and
+downloads fitness and winners.  The dataset is resident in HBM before
+timing starts.
 
-Prints one JSON line (metric GPops/s = sum(len) * rows / time per step).
+Prints one JSON line: GPops/s = sum(len) * rows / time per step; the
+evaluation kernel's roofline (its duration from HIP event nodes recorded
+around it inside the graph); the adjoint/forward time ratio on the
+differentiation workload (1,048,576 rows x 8 features, 2048 programs with
+up to 16 constants); and the CPU oracle on a row sample.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -22,9 +31,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_VALU = 157.3e12     # MI355X dense FP32 vector, FLOP/s (packed FMA = 4 flops/lane/clk)
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2110_11226_amd", "csrc", "gp_device.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_eval_pagie-16M_traffic.md")
 
 WORKLOADS = {
-    # name: (rows, programs, init kwargs, metric, features)
     "pagie-16M": dict(rows=16_777_216, programs=4096, features=2, metric="mse", data_seed=11229,
                       pop=dict(method="exact_len", min_len=1, max_len=200, seed=2113)),
     "pagie-4K": dict(rows=4096, programs=256, features=2, metric="mse", data_seed=11227,
@@ -32,6 +42,8 @@ WORKLOADS = {
     "higgs-11M": dict(rows=11_000_000, programs=2000, features=28, metric="logloss", data_seed=11230,
                       pop=dict(method="exact_len", min_len=1, max_len=200, seed=2114)),
 }
+DIFF = dict(rows=1_048_576, programs=2048, features=8, data_seed=11231,
+            pop=dict(method="exact_len", min_len=1, max_len=200, max_consts=16, seed=2115))
 
 
 def log(msg):
@@ -43,6 +55,24 @@ def make_data(wl):
     if wl["features"] == 28:
         return synth.higgs_like(wl["rows"], seed=wl["data_seed"])
     return synth.pagie(wl["rows"], seed=wl["data_seed"])
+
+
+def source_sha():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def committed_traffic():
+    """HBM bytes per launch of the evaluation kernel from the committed PMC
+    summary, if it was taken from the kernel source as it is now."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    text = open(TRAFFIC_SUMMARY).read()
+    sha = re.search(r"kernel source sha256:\s*([0-9a-f]{64})", text)
+    val = re.search(r"traffic bytes per launch:\s*([0-9.eE+]+)", text)
+    if not sha or not val or sha.group(1) != source_sha():
+        return None
+    return float(val.group(1))
 
 
 def cpu_baseline(host, X, y, metric, budget_rows):
@@ -62,7 +92,37 @@ def cpu_baseline(host, X, y, metric, budget_rows):
     gops = float(host.length.astype(np.int64).sum()) * len(idx) / dt
     return {"value": gops, "unit": "GPops/s", "cores": cores, "kind": "oracle",
             "sample": f"all {host.n_programs} programs x {len(idx)} rows (every {stride}th row), "
-                      f"float32 path, {dt:.1f} s"}
+                      f"float32 path, {dt:.1f} s on {cores} threads"}
+
+
+def adjoint_ratio(gp, torch, reps=5):
+    """gp_fitness_backward time / gp_fitness time on the differentiation
+    workload (medians of `reps` event-timed calls each)."""
+    import synth
+    X, y = synth.diff_target(DIFF["rows"], seed=DIFF["data_seed"])
+    host = gp.build_population(DIFF["programs"], DIFF["features"], **DIFF["pop"])
+    pop = gp.DevicePopulation(host, n_features=DIFF["features"])
+    data = gp.DeviceDataset(X, y)
+    fit = torch.empty(host.n_programs, dtype=torch.float32, device="cuda")
+    grad = torch.empty(max(pop.n_consts, 1), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        out = []
+        for _ in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            b.synchronize()
+            out.append(a.elapsed_time(b))
+        return float(np.median(out[1:]))
+
+    fwd = timed(lambda: gp.fitness(pop, data, "mse", out=fit))
+    bwd = timed(lambda: gp.fitness_backward(pop, data, "mse", grad_out=grad))
+    return {"workload": f"diff-1M: {DIFF['rows']} rows x {DIFF['features']} features, {DIFF['programs']} "
+                        f"programs of 1-200 nodes with <= 16 constants, MSE",
+            "forward_ms": fwd, "backward_ms": bwd, "ratio": bwd / fwd, "target": 3.0}
 
 
 def main():
@@ -72,11 +132,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="pagie-16M", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=65536)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=196_608)
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache (JSON lines): loaded if present, written after tuning")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the path shards by programs or rows, see DESIGN.md)", file=sys.stderr)
+              "(the path would shard by programs or rows; one GPU's share is what runs here)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -84,62 +151,68 @@ def main():
 
     wl = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.copy_calibration_mib} MiB done")
+        del src, dst
     log(f"[bench] building {args.workload}: {wl['rows']} rows x {wl['programs']} programs")
     X, y = make_data(wl)
     host = gp.build_population(wl["programs"], wl["features"], **wl["pop"])
-    gp.validate_population(host, wl["features"])
     sum_len = int(host.length.astype(np.int64).sum())
     data = gp.DeviceDataset(X, y)
-    pop = gp.DevicePopulation(host, n_features=wl["features"], validate=False)
-    # pinned staging copies of the population: the per-generation upload
-    pinned = {k: torch.from_numpy(np.ascontiguousarray(v)).pin_memory()
-              for k, v in (("nodes", host.nodes.view(np.int32)), ("prog_off", host.prog_off),
-                           ("consts", host.consts if host.consts.size else np.zeros(1, np.float32)),
-                           ("const_off", host.const_off), ("length", host.length))}
-    dev = {"nodes": pop.nodes, "prog_off": pop.prog_off, "consts": pop.consts,
-           "const_off": pop.const_off, "length": pop.length}
-    fit = torch.empty(host.n_programs, dtype=torch.float32, device="cuda")
-    T = host.n_programs
-    win = torch.empty(T, dtype=torch.int32, device="cuda")
     metric = wl["metric"]
-    stream = torch.cuda.current_stream()
-
-    def step(g):
-        for k in dev:
-            dev[k].copy_(pinned[k], non_blocking=True)
-        gp.fitness(pop, data, metric, out=fit)
-        gp.tournament(fit, pop.length, metric, 0.0, 20, T, seed=2025, generation=g, out=win)
-
-    for i in range(args.warmup):
-        step(i)
+    T = host.n_programs
+    loaded = bool(args.tune_cache and os.path.exists(args.tune_cache))
+    if loaded:
+        gp.autotune_load(args.tune_cache)
+        log(f"[bench] autotuner cache loaded from {args.tune_cache}")
+    gen = gp.Generation(data, host.n_programs, host.nodes.shape[0], max(host.consts.shape[0], 1), metric,
+                        parsimony=0.0, tournament_size=20, n_tournaments=T, seed=2025,
+                        autotune=not args.no_autotune and not loaded,
+                        time_kernel=True)
+    try:
+        for i in range(args.warmup):
+            gen.run(host, i)
+            log(f"[bench] warmup {i + 1}/{args.warmup} done (graph captured; launch {gen.timing()['launch']})")
+        kernel_ms = []
         torch.cuda.synchronize()
-        log(f"[bench] warmup {i + 1}/{args.warmup} done")
-
-    gp.profile_enable(True)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for i in range(args.steps):
-        step(args.warmup + i)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    launches, kern_ms, node_rows = gp.profile_read()
-    gp.profile_enable(False)
-    ms_step = ev0.elapsed_time(ev1) / args.steps
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            gen.run(host, args.warmup + i)
+            kernel_ms.append(gen.timing()["kernel_ms"])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        tm = gen.timing()
+        if args.tune_cache and tm["tuned_ms"] > 0:
+            gp.autotune_save(args.tune_cache)
+    finally:
+        gen.close()
+    ms_step = wall * 1e3 / args.steps
     gops = sum_len * wl["rows"] / (ms_step / 1e3)
-    kern_avg_ms = kern_ms / max(launches, 1)
-    achieved = (node_rows / max(launches, 1)) / (kern_avg_ms / 1e3)
-    log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step (wall {wall:.2f} s), eval kernel "
-        f"{kern_avg_ms:.3f} ms avg over {launches} launches")
+    kern_avg_ms = float(np.mean(kernel_ms))
+    ops_launch = float(sum_len) * wl["rows"]
+    achieved = ops_launch / (kern_avg_ms / 1e3)
+    log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step, evaluation kernel {kern_avg_ms:.3f} ms avg "
+        f"({tm['timed_by']}; device clock {tm['clock_ms']:.3f} ms)")
+
+    adj = None
+    if not args.no_adjoint:
+        log("[bench] adjoint / forward ratio on the differentiation workload")
+        adj = adjoint_ratio(gp, torch)
+        log(f"[bench] forward {adj['forward_ms']:.2f} ms, backward {adj['backward_ms']:.2f} ms, "
+            f"ratio {adj['ratio']:.2f}")
 
     base = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a row subsample")
         base = cpu_baseline(host, X, y, metric, args.cpu_rows)
 
-    cfg = gp.get_launch_config(wl["features"], wl["rows"], wl["programs"])
+    traffic = committed_traffic() if args.workload == "pagie-16M" else None
     line = {
         "metric": "GPops/s (program-node evals/sec) for population fitness",
         "value": gops,
@@ -155,14 +228,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n_rows": wl["rows"], "n_programs": wl["programs"],
                    "n_features": wl["features"], "population": wl["pop"], "sum_len": sum_len,
-                   "metric": metric, "tournament_size": 20,
-                   "step": "H2D population + fused fitness + tournament",
-                   "launch": {"rows_per_lane": cfg[0], "feature_regs": cfg[1], "tiles_per_chunk": cfg[2]}},
+                   "metric": metric, "tournament_size": 20, "n_tournaments": T,
+                   "step": "validate+stage (host), one HIP graph: population upload, instruction pre-pass, "
+                           "fused fitness, tournaments, result download",
+                   "launch": {"rows_per_lane": tm["launch"][0], "feature_regs": tm["launch"][1],
+                              "tiles_per_chunk": tm["launch"][2],
+                              "source": ("autotuner" if tm["tuned_ms"] > 0 else
+                                         "autotuner cache" if loaded else "heuristic"),
+                              "tuned_ms_row_prefix": tm["tuned_ms"]}},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None,
-                     "kernel": "k_eval (fused evaluation + MSE row loss + wave reduction)",
-                     "kernel_avg_ms": kern_avg_ms, "ops_per_launch": node_rows / max(launches, 1),
-                     "op": "one program node evaluated on one row"},
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU,
+                     "traffic": traffic,
+                     "kernel": "k_eval (persistent fused evaluation + MSE row loss + wave reduction)",
+                     "kernel_avg_ms": kern_avg_ms, "kernel_timed_by": tm["timed_by"],
+                     "ops_per_launch": ops_launch, "op": "one program node evaluated on one row"},
+        "adjoint": adj,
         "cpu_baseline": base,
     }
     print(json.dumps(line), flush=True)
