@@ -82,15 +82,20 @@ struct Sched {
 };
 
 // ---------------------------------------------------------------------------
-// Instruction format (word x; word y holds a constant's float bits):
+// Instruction format (word x; word y):
 //   bits 0-1  class: kPush (push a terminal), kFold (terminal fused with the
 //             binary function whose first operand it is; the current top is
 //             the second operand), kBin (binary: top op next-below), kUn
 //   bits 2-4  function: binary ADD..DIV as 0..3, unary NEG..TAN as 0..5
 //   bit 5     the terminal is a constant (value in y) rather than a feature
+//   bit 6     "active": the subtree this instruction completes holds a
+//             constant (only such instructions carry derivatives back)
 //   bits 8-31 feature index, or the constant's slot
+//   y         a constant's float bits; for an inactive instruction, the
+//             index of the first instruction of the subtree it completes
 // ---------------------------------------------------------------------------
 enum : uint32_t { kPush = 0, kFold = 1, kBin = 2, kUn = 3 };
+constexpr uint32_t kActive = 64u;
 
 GP_HD uint32_t enc(uint32_t cls, uint32_t fn, uint32_t is_const, uint32_t arg) {
     return cls | (fn << 2) | (is_const << 5) | (arg << 8);
@@ -197,10 +202,14 @@ __device__ __forceinline__ void apply_unary(uint32_t fn, float (&t)[R]) {
 // evaluation order of Sec. III-A) and emits instructions in that order.  A
 // terminal at position i is the first operand of the function at i-1 exactly
 // when that function is binary (its first operand starts right after it), so
-// such pairs become one kFold instruction.
+// such pairs become one kFold instruction.  A shadow stack (in LDS, one
+// column per lane) tracks, for each value on the evaluation stack, the first
+// instruction of the subtree that produced it and whether that subtree holds
+// a constant; each instruction records both (bit kActive, word y).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint2* __restrict__ code,
                                                      int32_t* __restrict__ clen) {
+    __shared__ uint32_t shadow[GP_MAX_STACK][kBlock];   // start | active << 31
     const int32_t p = static_cast<int32_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (p >= pop.P) return;
     const int64_t off = pop.prog_off[p];
@@ -208,27 +217,57 @@ __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint2* __restri
     const uint32_t* pn = pop.nodes + off;
     const float* pc = pop.consts + pop.const_off[p];
     uint2* out = code + off;
+    uint32_t* sh = &shadow[0][threadIdx.x];   // entry h at sh[h * kBlock]
+    int h = 0;                                // shadow stack height
     int32_t k = 0;
     for (int32_t i = L - 1; i >= 0; --i) {
         const uint32_t w = pn[i];
         const uint32_t op = w & 0xffu;
         const uint32_t arg = w >> 8;
+        uint32_t x, start, active;
         if (op <= GP_OP_CONST) {
             const uint32_t is_c = op == GP_OP_CONST ? 1u : 0u;
-            const uint32_t val = is_c ? __float_as_uint(pc[arg]) : 0u;
             const uint32_t farg = arg;   // feature index, or constant slot (used by the adjoint)
             const uint32_t prev = i >= 1 ? (pn[i - 1] & 0xffu) : 0u;
             if (i >= 1 && i != L - 1 && prev >= GP_OP_ADD && prev <= GP_OP_DIV) {
-                out[k++] = make_uint2(enc(kFold, prev - GP_OP_ADD, is_c, farg), val);
+                const uint32_t top = sh[max(h - 1, 0) * kBlock];    // the second operand
+                x = enc(kFold, prev - GP_OP_ADD, is_c, farg);
+                start = top & 0x7fffffffu;
+                active = is_c | (top >> 31);
+                --h;
                 --i;
             } else {
-                out[k++] = make_uint2(enc(kPush, 0, is_c, farg), val);
+                x = enc(kPush, 0, is_c, farg);
+                start = static_cast<uint32_t>(k);
+                active = is_c;
+            }
+            if (is_c) {
+                out[k] = make_uint2(x | kActive, __float_as_uint(pc[arg]));
+            } else {
+                out[k] = make_uint2(x | (active ? kActive : 0u), start);
             }
         } else if (op <= GP_OP_DIV) {
-            out[k++] = make_uint2(enc(kBin, op - GP_OP_ADD, 0, 0), 0u);
+            const uint32_t first = sh[max(h - 1, 0) * kBlock];     // top: the first operand
+            const uint32_t second = sh[max(h - 2, 0) * kBlock];    // evaluated before it
+            x = enc(kBin, op - GP_OP_ADD, 0, 0);
+            start = second & 0x7fffffffu;
+            active = (first >> 31) | (second >> 31);
+            h -= 2;
+            out[k] = make_uint2(x | (active ? kActive : 0u), start);
         } else {
-            out[k++] = make_uint2(enc(kUn, op - GP_OP_NEG, 0, 0), 0u);
+            const uint32_t top = sh[max(h - 1, 0) * kBlock];
+            x = enc(kUn, op - GP_OP_NEG, 0, 0);
+            start = top & 0x7fffffffu;
+            active = top >> 31;
+            --h;
+            out[k] = make_uint2(x | (active ? kActive : 0u), start);
         }
+        // (valid programs keep 1 <= h <= GP_MAX_STACK; the clamps only keep an
+        // invalid one inside this array)
+        h = max(h, 0);
+        sh[min(h, GP_MAX_STACK - 1) * kBlock] = start | (active << 31);
+        ++h;
+        ++k;
     }
     clen[p] = k;
 }
@@ -620,25 +659,38 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
 // instructions, one wavefront per (row chunk, program) work item.
 //
 // Per tile of 64*R rows: a forward pass runs the stack machine and records
-// on a tape the operands that the local derivatives need (both operands of a
-// product or quotient; the input of log, sqrt, sin, cos, tan); the seed is
-// d fitness / d yhat of each row; a reverse pass walks the instructions back
-// with an adjoint stack that mirrors the value stack and, at each constant,
-// adds its adjoint into a per-lane float64 accumulator in LDS.  The tape is
-// the only per-row data written to memory: a per-wavefront area that is
-// written once and read back once, in reverse, mostly from L2 (the forward
-// values are recomputed per tile, not kept).  Local derivatives (reading): add (1,1),
+// on a tape the local derivatives each instruction will need (both partials
+// of a product or quotient; the derivative of log, sqrt, sin, cos, tan at
+// its input); the seed is d fitness / d yhat of each row; a reverse pass
+// walks the instructions back with an adjoint stack that mirrors the value
+// stack, multiplying by the taped partials, and at each constant reduces its
+// adjoint over the wavefront into a per-program float64 sum.  Only
+// instructions whose subtree holds a constant (kActive) record partials, and
+// the reverse pass jumps over every subtree without one.  The first
+// kTapeLdsBytes of each wavefront's tape live in LDS, the rest (long
+// programs) in a per-wavefront global area; the forward values are
+// recomputed per tile, never kept.  Local derivatives (reading): add (1,1),
 // sub (1,-1), mul (b,a), div (1/b, -a/b^2) if |b| > 0.001 else (0,0),
 // log 1/a if |a| > 0.001 else 0, sqrt sign(a)/(2 sqrt|a|) (0 at a = 0),
 // sin cos a, cos -sin a, tan 1 + tan^2 a, neg -1.
 // ---------------------------------------------------------------------------
-constexpr int kGradLds = 16;   // constants per program accumulated in LDS
+constexpr int kGradLds = 16;            // constants per program summed in a fixed order
+constexpr int kTapeLdsBytes = 12288;    // per-wavefront tape held in LDS
 
 // tape entries an instruction records (0, 1 or 2)
 __device__ __forceinline__ int tape_entries(uint32_t cls, uint32_t fn) {
     if (cls == kPush) return 0;
-    if (cls == kUn) return fn == 0 ? 0 : 1;           // neg needs nothing
-    return fn >= 2 ? 2 : 0;                           // mul / div need both operands
+    if (cls == kUn) return fn == 0 ? 0 : 1;           // neg: the constant -1
+    return fn >= 2 ? 2 : 0;                           // mul / div: both partials
+}
+
+// floats of a wavefront's global area: value- and adjoint-stack overflow, then
+// the tape entries beyond those in LDS
+template <int R>
+constexpr int64_t adjoint_wave_floats(int64_t tape_entries_max) {
+    const int64_t lds_entries = kTapeLdsBytes / (R * kWave * 4);
+    const int64_t beyond = tape_entries_max > lds_entries ? tape_entries_max - lds_entries : 0;
+    return (2 * kStackLds + beyond) * R * kWave;
 }
 
 template <int R, int FREG, int METRIC>
@@ -649,19 +701,41 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                                                     double* __restrict__ part,
                                                     double* __restrict__ gpart,
                                                     double* __restrict__ gextra,
-                                                    float* __restrict__ tape_ovf,
-                                                    int64_t ovf_entries) {
+                                                    float* __restrict__ gmem,
+                                                    int64_t wave_floats) {
     constexpr int FA = FREG > 0 ? FREG : 1;
+    constexpr int kTapeLds = kTapeLdsBytes / (R * kWave * 4);
     const int lane = threadIdx.x;
     const int64_t N = d.N;
     const int64_t ld = d.ld;
     const float* __restrict__ X = d.X;
-    __shared__ double gl[kGradLds * kWave];
-    __shared__ float ovf[kStackLds * R * kWave];
-    __shared__ float aovf[kStackLds * R * kWave];
-    // this wavefront's tape: entry e of row slot j at tape[(e * R + j) * 64 + lane]
-    float* __restrict__ tape = tape_ovf + static_cast<int64_t>(blockIdx.x) * ovf_entries * R * kWave;
+    __shared__ float ltape[kTapeLds * R * kWave];
+    __shared__ double gw[kGradLds];
+    float* __restrict__ wmem = gmem + static_cast<int64_t>(blockIdx.x) * wave_floats;
+    float* __restrict__ ovf = wmem;                                 // value stack beyond registers
+    float* __restrict__ aovf = wmem + kStackLds * R * kWave;        // adjoint stack beyond registers
+    float* __restrict__ gtape = wmem + 2 * kStackLds * R * kWave;   // tape entries beyond LDS
     const double W = *wsum;
+
+    // entry e of row slot j: LDS for e < kTapeLds, the global area beyond
+    auto tape_put = [&](int e, const float (&v)[R]) {
+        if (e < kTapeLds) {
+#pragma unroll
+            for (int j = 0; j < R; ++j) ltape[(e * R + j) * kWave + lane] = v[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < R; ++j) gtape[((e - kTapeLds) * R + j) * kWave + lane] = v[j];
+        }
+    };
+    auto tape_get = [&](int e, float (&v)[R]) {
+        if (e < kTapeLds) {
+#pragma unroll
+            for (int j = 0; j < R; ++j) v[j] = ltape[(e * R + j) * kWave + lane];
+        } else {
+#pragma unroll
+            for (int j = 0; j < R; ++j) v[j] = gtape[((e - kTapeLds) * R + j) * kWave + lane];
+        }
+    };
 
     for (;;) {
         uint32_t it32 = 0;
@@ -687,10 +761,13 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
         }
         (void)sm0; (void)sm5;
         const int nlds = min(nconst, kGradLds);
-        for (int q = 0; q < nlds; ++q) gl[q * kWave + lane] = 0.0;
+        if (lane < nlds) gw[lane] = 0.0;
+        __syncthreads();
         double lacc = 0.0;
+        // a program without constants needs only its loss, and only when asked
+        const int64_t r_end = (nconst == 0 && !part) ? r0 : r1;
 
-        for (int64_t base = r0; base < r1; base += kWave * R) {
+        for (int64_t base = r0; base < r_end; base += kWave * R) {
             int64_t row[R];
             bool valid[R];
 #pragma unroll
@@ -706,6 +783,8 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                     if (f < d.F) {
                         xa0[f] = X[f * ld + row[0]];
                         if constexpr (R > 1) xa1[f] = X[f * ld + row[1]];
+                        if constexpr (R > 2) xa2[f] = X[f * ld + row[2]];
+                        if constexpr (R > 3) xa3[f] = X[f * ld + row[3]];
                     }
                 }
             }
@@ -724,11 +803,30 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                 const uint32_t cls = w & 3u;
                 const uint32_t fn = (w >> 2) & 7u;
                 GP_PUT(st, min(dp + 1, kStackRegs), t);
-                float a[R], b[R];
                 if (cls == kUn) {
+                    float x[R];
 #pragma unroll
-                    for (int j = 0; j < R; ++j) a[j] = b[j] = t[j];
-                } else if (cls == kBin) {
+                    for (int j = 0; j < R; ++j) x[j] = t[j];
+                    apply_unary<R>(fn, t);
+                    if (fn != 0 && (w & kActive)) {
+                        float dv[R];
+#pragma unroll
+                        for (int j = 0; j < R; ++j) {
+                            switch (fn) {
+                            case 1: dv[j] = fabsf(x[j]) > GP_PROTECT_EPS ? 1.0f / x[j] : 0.0f; break;
+                            case 2: dv[j] = x[j] == 0.0f ? 0.0f : copysignf(1.0f, x[j]) / (2.0f * t[j]); break;
+                            case 3: dv[j] = cosf(x[j]); break;
+                            case 4: dv[j] = -sinf(x[j]); break;
+                            default: dv[j] = 1.0f + t[j] * t[j]; break;
+                            }
+                        }
+                        tape_put(ntape, dv);
+                        ++ntape;
+                    }
+                    continue;
+                }
+                float a[R], b[R];
+                if (cls == kBin) {
                     if (dp < kStackRegs) {
                         GP_GET(st, dp, b);
                     } else {
@@ -748,6 +846,8 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                         const uint32_t arg = w >> 8;
                         v[0] = xa0[arg];
                         if constexpr (R > 1) v[1] = xa1[arg];
+                        if constexpr (R > 2) v[2] = xa2[arg];
+                        if constexpr (R > 3) v[3] = xa3[arg];
                     } else {
                         const float* __restrict__ col = X + static_cast<int64_t>(w >> 8) * ld;
 #pragma unroll
@@ -769,24 +869,29 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                         b[j] = t[j];
                     }
                 }
-                // record: entry ntape = a, entry ntape+1 = b (as needed)
-                const int ne = tape_entries(cls, fn);
-                if (ne > 0) {
+                if (fn >= 2 && (w & kActive)) {   // mul / div: both partials
+                    float da[R], db[R];
 #pragma unroll
-                    for (int j = 0; j < R; ++j) tape[(ntape * R + j) * kWave + lane] = a[j];
-                    if (ne == 2) {
-#pragma unroll
-                        for (int j = 0; j < R; ++j) tape[((ntape + 1) * R + j) * kWave + lane] = b[j];
+                    for (int j = 0; j < R; ++j) {
+                        if (fn == 2) {
+                            da[j] = b[j];
+                            db[j] = a[j];
+                        } else if (fabsf(b[j]) > GP_PROTECT_EPS) {
+                            const float inv = 1.0f / b[j];
+                            da[j] = inv;
+                            db[j] = -a[j] * inv * inv;
+                        } else {
+                            da[j] = 0.0f;
+                            db[j] = 0.0f;
+                        }
                     }
+                    tape_put(ntape, da);
+                    tape_put(ntape + 1, db);
+                    ntape += 2;
                 }
-                ntape += ne;
-                if (cls == kUn) {
-                    apply_unary<R>(fn, t);
-                } else {
-                    apply_binary<R>(fn, a, b);
+                apply_binary<R>(fn, a, b);
 #pragma unroll
-                    for (int j = 0; j < R; ++j) t[j] = a[j];
-                }
+                for (int j = 0; j < R; ++j) t[j] = a[j];
             }
 
             // ---------------- seeds: d fitness / d yhat per row ----------------
@@ -829,6 +934,7 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                 g[j] = valid[j] ? static_cast<float>(sd) * gsc : 0.0f;
             }
 
+            if (nconst == 0) continue;   // no constant: nothing to carry back
             // ---------------- reverse pass ----------------
             GP_ARRAYS(as, kStackRegs + 1);   // adjoints of the entries below the top
             int ad = dp;                     // mirrors the value stack (dp == 0 here)
@@ -838,21 +944,27 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                 const uint2 cur = prv;
                 prv = pcode[max(q - 1, 0)];
                 const uint32_t w = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(cur.x)));
+                if (!(w & kActive)) {
+                    // no constant below: the whole subtree carries nothing back
+                    // and, as one value on the stack, is undone like a push
+                    const int start = __builtin_amdgcn_readfirstlane(static_cast<int>(cur.y));
+                    q = start;
+                    prv = pcode[max(start - 1, 0)];
+                    if (ad >= 0) {
+                        if (ad < kStackRegs) {
+                            GP_GET(as, ad, g);
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < R; ++j) g[j] = aovf[((ad - kStackRegs) * R + j) * kWave + lane];
+                        }
+                    }
+                    --ad;
+                    continue;
+                }
                 const uint32_t cls = w & 3u;
                 const uint32_t fn = (w >> 2) & 7u;
                 const int ne = tape_entries(cls, fn);
                 ntape -= ne;
-                float a[R], b[R];
-#pragma unroll
-                for (int j = 0; j < R; ++j) a[j] = b[j] = 0.0f;
-                if (ne > 0) {
-#pragma unroll
-                    for (int j = 0; j < R; ++j) a[j] = tape[(ntape * R + j) * kWave + lane];
-                    if (ne == 2) {
-#pragma unroll
-                        for (int j = 0; j < R; ++j) b[j] = tape[((ntape + 1) * R + j) * kWave + lane];
-                    }
-                }
                 float gb[R];   // adjoint handed to the entry below the top (binary only)
 #pragma unroll
                 for (int j = 0; j < R; ++j) gb[j] = 0.0f;
@@ -860,19 +972,14 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
 #pragma unroll
                 for (int j = 0; j < R; ++j) gc[j] = 0.0f;
                 if (cls == kUn) {
+                    if (ne == 0) {
 #pragma unroll
-                    for (int j = 0; j < R; ++j) {
-                        const float x = a[j];
-                        float dfx;
-                        switch (fn) {
-                        case 0: dfx = -1.0f; break;
-                        case 1: dfx = fabsf(x) > GP_PROTECT_EPS ? 1.0f / x : 0.0f; break;
-                        case 2: dfx = x == 0.0f ? 0.0f : copysignf(1.0f, x) / (2.0f * sqrtf(fabsf(x))); break;
-                        case 3: dfx = cosf(x); break;
-                        case 4: dfx = -sinf(x); break;
-                        default: { const float tx = tanf(x); dfx = 1.0f + tx * tx; } break;
-                        }
-                        g[j] = g[j] * dfx;
+                        for (int j = 0; j < R; ++j) g[j] = -g[j];
+                    } else {
+                        float dv[R];
+                        tape_get(ntape, dv);
+#pragma unroll
+                        for (int j = 0; j < R; ++j) g[j] = g[j] * dv[j];
                     }
                 } else if (cls == kPush) {
 #pragma unroll
@@ -880,26 +987,21 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                 } else {
                     // binary: operands (a, b); fold: a is the terminal, b the old top
                     float ga[R];
+                    if (ne == 0) {
 #pragma unroll
-                    for (int j = 0; j < R; ++j) {
-                        float da, db;
-                        switch (fn) {
-                        case 0: da = 1.0f; db = 1.0f; break;
-                        case 1: da = 1.0f; db = -1.0f; break;
-                        case 2: da = b[j]; db = a[j]; break;
-                        default:
-                            if (fabsf(b[j]) > GP_PROTECT_EPS) {
-                                const float inv = 1.0f / b[j];
-                                da = inv;
-                                db = -a[j] * inv * inv;
-                            } else {
-                                da = 0.0f;
-                                db = 0.0f;
-                            }
-                            break;
+                        for (int j = 0; j < R; ++j) {
+                            ga[j] = g[j];
+                            gb[j] = fn == 0 ? g[j] : -g[j];
                         }
-                        ga[j] = g[j] * da;
-                        gb[j] = g[j] * db;
+                    } else {
+                        float da[R], db[R];
+                        tape_get(ntape, da);
+                        tape_get(ntape + 1, db);
+#pragma unroll
+                        for (int j = 0; j < R; ++j) {
+                            ga[j] = g[j] * da[j];
+                            gb[j] = g[j] * db[j];
+                        }
                     }
                     if (cls == kBin) {
 #pragma unroll
@@ -921,17 +1023,16 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                         for (int j = 0; j < R; ++j) aovf[((ad - kStackRegs) * R + j) * kWave + lane] = gb[j];
                     }
                 }
-                // a constant terminal collects its adjoint
+                // a constant terminal: its adjoint summed over the wavefront's rows
                 if (cls <= kFold && (w & 32u)) {
                     const int slot = static_cast<int>(w >> 8);
                     double sum = 0.0;
 #pragma unroll
                     for (int j = 0; j < R; ++j) sum += valid[j] ? static_cast<double>(gc[j]) : 0.0;
-                    if (slot < kGradLds) {
-                        gl[slot * kWave + lane] += sum;
-                    } else {
-                        const double tot = wave_sum(sum);
-                        if (lane == 0) atomicAdd(gextra + cbase + slot, tot);
+                    const double tot = wave_sum(sum);
+                    if (lane == 0) {
+                        if (slot < kGradLds) gw[slot] += tot;
+                        else atomicAdd(gextra + cbase + slot, tot);
                     }
                 }
                 // a push is undone: the entry below becomes the top again
@@ -948,15 +1049,14 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                 }
             }
         }
-        // ---------------- per-item reductions ----------------
-        for (int q = 0; q < nlds; ++q) {
-            const double v = wave_sum(gl[q * kWave + lane]);
-            if (lane == 0) gpart[(cbase + q) * s.n_chunks + c] = v;
-        }
+        // ---------------- per-item results ----------------
+        __syncthreads();
+        if (lane < nlds) gpart[(cbase + lane) * s.n_chunks + c] = gw[lane];
         if (part) {
             lacc = wave_sum(lacc);
             if (lane == 0) part[static_cast<int64_t>(p) * s.n_chunks + c] = lacc;
         }
+        __syncthreads();
     }
 }
 
@@ -2063,8 +2163,9 @@ gp_status gp_fitness_backward(const gp_population_dev* pop, const gp_dataset_dev
     if (rc != GP_OK) return rc;
     const int32_t P = pop->n_programs;
     const int64_t nc = std::max<int64_t>(pop->total_consts, 1);
-    constexpr int RA = 1;
-    const int64_t ovf_entries = 2 * static_cast<int64_t>(pop->max_len) + 2;   // tape entries per wavefront
+    // rows per lane of the adjoint: a forced configuration's, else 2
+    const int RA = g_forced ? g_forced_cfg.R : 2;
+    const int64_t tape_max = 2 * static_cast<int64_t>(pop->max_len) + 2;   // tape entries per wavefront
     rc = grow(reinterpret_cast<void**>(&sc->stats), &sc->stats_cap, static_cast<size_t>(P) * kStats + 1,
               sizeof(double));
     if (rc != GP_OK) return rc;
@@ -2106,23 +2207,26 @@ gp_status gp_fitness_backward(const gp_population_dev* pop, const gp_dataset_dev
     GP_HIP(hipGetLastError());
     const int freg = cfg.freg > 0 && data->n_features <= 2 ? 2 : (data->n_features <= 8 ? 8 : 0);
     double* lossp = needs_forward ? nullptr : sc->part;
-    auto go = [&](auto kernel) -> gp_status {
+    auto go = [&](auto kernel, int64_t wave_floats) -> gp_status {
         int per_cu = 0;
         GP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kWave, 0));
         per_cu = std::max(per_cu, 1);
         int64_t blocks = std::min<int64_t>(static_cast<int64_t>(per_cu) * sc->n_cu, sch.n_items);
         blocks = std::max<int64_t>(blocks, 1);
         gp_status r2 = grow(reinterpret_cast<void**>(&sc->tape), &sc->tape_cap,
-                            static_cast<size_t>(blocks) * ovf_entries * RA * kWave, sizeof(float));
+                            static_cast<size_t>(blocks) * static_cast<size_t>(wave_floats), sizeof(float));
         if (r2 != GP_OK) return r2;
         hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(blocks)), dim3(kWave), 0, st, pv, cvw, dv, sch,
                            needs_forward ? sc->stats : nullptr, wsum, grad_fitness, lossp, sc->gpart, sc->gextra,
-                           sc->tape, ovf_entries);
+                           sc->tape, wave_floats);
         GP_HIP(hipGetLastError());
         return GP_OK;
     };
-#define GP_ADJ(M)                                                          \
-    (freg == 2 ? go(k_adjoint<RA, 2, M>) : freg == 8 ? go(k_adjoint<RA, 8, M>) : go(k_adjoint<RA, 0, M>))
+#define GP_ADJ_R(RR, M)                                                                        \
+    (freg == 2   ? go(k_adjoint<RR, 2, M>, adjoint_wave_floats<RR>(tape_max))                  \
+     : freg == 8 ? go(k_adjoint<RR, 8, M>, adjoint_wave_floats<RR>(tape_max))                  \
+                 : go(k_adjoint<RR, 0, M>, adjoint_wave_floats<RR>(tape_max)))
+#define GP_ADJ(M) (RA == 1 ? GP_ADJ_R(1, M) : RA == 2 ? GP_ADJ_R(2, M) : GP_ADJ_R(4, M))
     switch (metric) {
     case GP_METRIC_MAE: rc = GP_ADJ(GP_METRIC_MAE); break;
     case GP_METRIC_MSE: rc = GP_ADJ(GP_METRIC_MSE); break;
@@ -2131,6 +2235,7 @@ gp_status gp_fitness_backward(const gp_population_dev* pop, const gp_dataset_dev
     default: rc = GP_ADJ(GP_METRIC_PEARSON); break;
     }
 #undef GP_ADJ
+#undef GP_ADJ_R
     if (rc != GP_OK) return rc;
     if (!needs_forward && fitness_out) {
         if (metric == GP_METRIC_MAE)
