@@ -26,7 +26,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 VAR, CONST, ADD, SUB, MUL, DIV, NEG, LOG, SQRT, SIN, COS, TAN = range(12)
 ARITY = {VAR: 0, CONST: 0, ADD: 2, SUB: 2, MUL: 2, DIV: 2,
          NEG: 1, LOG: 1, SQRT: 1, SIN: 1, COS: 1, TAN: 1}
-METRICS = {"mae": 0, "mse": 1, "rmse": 2, "logloss": 3, "pearson": 4}
+METRICS = {"mae": 0, "mse": 1, "rmse": 2, "logloss": 3, "pearson": 4, "spearman": 5}
 LARGER_IS_BETTER = {0: 0, 1: 0, 2: 0, 3: 0, 4: 1}
 INIT = {"rhh": 0, "full": 1, "grow": 2, "exact_len": 3}
 # the nine-function set used by the Pagie / classification workloads

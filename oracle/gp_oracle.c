@@ -16,7 +16,7 @@
  *   - program value of a prefix list on one row, by the right-to-left stack
  *     scan of Sec. III-A, in float32 and in float64;
  *   - per-program fitness under the weighted metrics of Sec. III-C3
- *     (MAE, MSE, RMSE, logistic loss, Pearson);
+ *     (MAE, MSE, RMSE, logistic loss, Pearson, Spearman);
  *   - tournament selection with the parsimony penalty, Sec. III-C1,
  *     Eqs. (parsimony) and (fitness);
  *   - Philox4x32-10 (the counter-based generator cited in Sec. III-B);
@@ -310,10 +310,103 @@ void orc_evaluate_pairs(const uint32_t *nodes, const int64_t *prog_off,
 /* this value; fit_f64 gets the same metric with yhat from the float64 stack  */
 /* evaluation and every step in float64 (error reporting only).               */
 /* ------------------------------------------------------------------------ */
+/* ---- Spearman (Sec. III-C3): Pearson correlation of the rank vectors ---- */
+/* Readings: rank 1 is the smallest value; tied values share the mean of the  */
+/* ranks they span (the standard definition); ranks ignore the weights, and   */
+/* the correlation of the ranks is the weighted Pearson of metric 4 (|r|,     */
+/* 0 for a constant rank vector); a NaN value makes the fitness NaN.          */
+static void merge_sort_idx(const double *v, int64_t *idx, int64_t *tmp, int64_t n)
+{
+    /* bottom-up merge sort of the indices by value (stable) */
+    for (int64_t width = 1; width < n; width *= 2) {
+        for (int64_t lo = 0; lo < n; lo += 2 * width) {
+            int64_t mid = lo + width < n ? lo + width : n;
+            int64_t hi = lo + 2 * width < n ? lo + 2 * width : n;
+            int64_t i = lo, j = mid, k = lo;
+            while (i < mid && j < hi) tmp[k++] = (v[idx[j]] < v[idx[i]]) ? idx[j++] : idx[i++];
+            while (i < mid) tmp[k++] = idx[i++];
+            while (j < hi) tmp[k++] = idx[j++];
+        }
+        memcpy(idx, tmp, sizeof(int64_t) * (size_t)n);
+    }
+}
+
+/* average ranks (1-based) of v[0..n) into rank[]; idx receives the sort order */
+static void average_ranks(const double *v, int64_t n, double *rank, int64_t *idx)
+{
+    int64_t *tmp = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t r = 0; r < n; ++r) idx[r] = r;
+    merge_sort_idx(v, idx, tmp, n);
+    free(tmp);
+    int64_t i = 0;
+    while (i < n) {
+        int64_t j = i + 1;
+        while (j < n && v[idx[j]] == v[idx[i]]) ++j;
+        double avg = 0.5 * ((double)(i + 1) + (double)j);   /* mean of ranks i+1 .. j */
+        for (int64_t k = i; k < j; ++k) rank[idx[k]] = avg;
+        i = j;
+    }
+}
+
+/* |weighted Pearson| of two float64 columns (0 for a constant column) */
+static double pearson_abs(const double *av_in, const double *bv_in, const float *w, int64_t n)
+{
+    double sw = 0.0, ma = 0.0, mb = 0.0;
+    for (int64_t r = 0; r < n; ++r) {
+        double wr = w ? (double)w[r] : 1.0;
+        sw += wr; ma += wr * av_in[r]; mb += wr * bv_in[r];
+    }
+    ma /= sw; mb /= sw;
+    double va = 0.0, vb = 0.0, cab = 0.0;
+    /* a column that takes one value on every weighted row has variance 0
+     * exactly, whatever rounding does to its computed mean */
+    int const_a = 1, const_b = 1, seen = 0;
+    double a0 = 0.0, b0 = 0.0;
+    for (int64_t r = 0; r < n; ++r) {
+        double wr = w ? (double)w[r] : 1.0;
+        double av = av_in[r], bv = bv_in[r];
+        if (wr != 0.0) {
+            if (!seen) { a0 = av; b0 = bv; seen = 1; }
+            if (!(av == a0)) const_a = 0;
+            if (!(bv == b0)) const_b = 0;
+        }
+        double a = av - ma;
+        double b = bv - mb;
+        va += wr * a * a; vb += wr * b * b; cab += wr * a * b;
+    }
+    if (const_a || const_b) return 0.0;
+    if (!(va > 0.0) || !(vb > 0.0) || !isfinite(va) || !isfinite(vb)) return 0.0;
+    return fabs(cab / sqrt(va * vb));
+}
+
+static double spearman_abs(const float *yh32, const double *yh64, const float *y, const float *w, int64_t n)
+{
+    double *a = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    double *b = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    double *ra = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *rb = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int has_nan = 0;
+    for (int64_t r = 0; r < n; ++r) {
+        a[r] = yh32 ? (double)yh32[r] : yh64[r];
+        b[r] = (double)y[r];
+        if (isnan(a[r])) has_nan = 1;
+    }
+    double out = NAN;
+    if (!has_nan) {
+        average_ranks(a, n, ra, idx);
+        average_ranks(b, n, rb, idx);
+        out = pearson_abs(ra, rb, w, n);
+    }
+    free(a); free(b); free(ra); free(rb); free(idx);
+    return out;
+}
+
 static double metric_from_values(int metric, const float *yh32, const double *yh64,
                                  const float *y, const float *w, int64_t n)
 {
     double sw = 0.0, s = 0.0;
+    if (metric == 5) return spearman_abs(yh32, yh64, y, w, n);
     if (metric == 4) {
         double ma = 0.0, mb = 0.0;
         for (int64_t r = 0; r < n; ++r) {
@@ -374,9 +467,76 @@ static double metric_from_values(int metric, const float *yh32, const double *yh
 /* First-order bound on how far the float32-path fitness can move when each
  * row's float32 output moves by at most its row_analysis bound E[r]:
  * sum_r |d fitness / d yhat_r| E[r] (plus the second-order term of MSE). */
+/* Spearman's sensitivity.  Every value may sit anywhere in [v - E, v + E]  */
+/* on the other side; rows whose intervals form one connected component of    */
+/* the (strict) overlap graph may be reordered or tied among themselves,      */
+/* while different components keep their order, so a row of a component of   */
+/* m rows changes rank by at most d = m - 1.  With a, b the centred value and */
+/* target ranks: the cross term moves by at most sum w |b| d exactly (b sums  */
+/* to zero under w), and the value ranks' weighted norm by at most            */
+/* D = sqrt(sum w d'^2), d' = d + (sum w d) / W (the shift of their mean);    */
+/* |rho| then lies in [(|c| - DC) / ((sa + D) sb), (|c| + DC) / ((sa - D) sb)]. */
+static double spearman_bound(const float *yh, const double *E, const float *y, const float *w, int64_t n,
+                             double rho)
+{
+    double *v = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *lo = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *ra = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *rb = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *d = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t r = 0; r < n; ++r) {
+        v[r] = (double)yh[r];
+        lo[r] = v[r] - E[r];
+    }
+    average_ranks(lo, n, ra, idx);          /* idx: rows by ascending lower end */
+    int64_t i = 0;
+    while (i < n) {
+        double hi = v[idx[i]] + E[idx[i]];
+        int64_t j = i + 1;
+        while (j < n && lo[idx[j]] < hi) {
+            double h2 = v[idx[j]] + E[idx[j]];
+            if (h2 > hi) hi = h2;
+            ++j;
+        }
+        for (int64_t k = i; k < j; ++k) d[idx[k]] = (double)(j - i - 1);
+        i = j;
+    }
+    average_ranks(v, n, ra, idx);
+    for (int64_t r = 0; r < n; ++r) lo[r] = (double)y[r];
+    average_ranks(lo, n, rb, idx);
+    double W = 0.0, ma = 0.0, mb = 0.0, shift = 0.0;
+    for (int64_t r = 0; r < n; ++r) {
+        double wr = w ? (double)w[r] : 1.0;
+        W += wr; ma += wr * ra[r]; mb += wr * rb[r]; shift += wr * d[r];
+    }
+    ma /= W; mb /= W; shift /= W;
+    double va = 0.0, vb = 0.0, cab = 0.0, dc = 0.0, dn = 0.0;
+    for (int64_t r = 0; r < n; ++r) {
+        double wr = w ? (double)w[r] : 1.0;
+        double a = ra[r] - ma, b = rb[r] - mb, dd = d[r] + shift;
+        va += wr * a * a; vb += wr * b * b; cab += wr * a * b;
+        dc += wr * fabs(b) * d[r];
+        dn += wr * dd * dd;
+    }
+    free(v); free(lo); free(ra); free(rb); free(d); free(idx);
+    (void)rho;
+    if (!(vb > 0.0)) return 0.0;                      /* constant target: 0 on both sides */
+    if (shift == 0.0) return 0.0;                     /* no component can reorder */
+    double sa = sqrt(va), sb = sqrt(vb), D = sqrt(dn);
+    double r0 = va > 0.0 ? fabs(cab) / (sa * sb) : 0.0;
+    double rmax = (sa - D > 0.0) ? (fabs(cab) + dc) / ((sa - D) * sb) : 1.0;
+    double rmin = (fabs(cab) - dc) / ((sa + D) * sb);
+    if (rmax > 1.0) rmax = 1.0;
+    if (rmin < 0.0) rmin = 0.0;
+    double up = rmax - r0, down = r0 - rmin;
+    return up > down ? up : down;
+}
+
 static double fitness_bound(int metric, const float *yh, const double *E, const float *y,
                             const float *w, int64_t n, double fit)
 {
+    if (metric == 5) return spearman_bound(yh, E, y, w, n, fit);
     double W = 0.0;
     for (int64_t r = 0; r < n; ++r) W += w ? (double)w[r] : 1.0;
     double B = 0.0;

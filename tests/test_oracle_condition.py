@@ -178,3 +178,41 @@ def test_fitness_bound_dominates_row_displacements(metric):
         F2 = _metric64(metric, v + np.sign(g) * E, yd, wd)
         assert abs(F2 - F0) >= 0.5 * fb[p], (metric, p, abs(F2 - F0), fb[p])
     assert checked >= 5
+
+
+def test_spearman_bound_dominates_rank_changes():
+    """Displacing every row within its bound reorders only rows whose
+    intervals chain-overlap; the change of Spearman's |rho| stays inside the
+    bound (recomputed with scipy's average ranks and numpy)."""
+    from scipy.stats import rankdata
+    N = 300
+    X, y = synth.pagie(N, seed=8)
+    w = synth.weights(N, seed=9)
+    fmask = oracle.DEFAULT_FMASK | (1 << TAN)
+    pop = oracle.build_population(30, 2, "exact_len", min_len=3, max_len=30, fmask=fmask, seed=81)
+    u = 1e-5        # large: many near ties
+    f32p, f64, fb, fn = oracle.fitness(pop, X, y, w, "spearman", with_bound=True, u=u)
+    rng = np.random.default_rng(2)
+    wd = w.astype(np.float64)
+    rb = rankdata(y.astype(np.float64))
+
+    def rho(v):
+        ra = rankdata(v)
+        ma, mb = np.sum(wd * ra) / wd.sum(), np.sum(wd * rb) / wd.sum()
+        va, vb = np.sum(wd * (ra - ma) ** 2), np.sum(wd * (rb - mb) ** 2)
+        return 0.0 if va == 0 or vb == 0 else abs(np.sum(wd * (ra - ma) * (rb - mb)) / np.sqrt(va * vb))
+    nonzero = 0
+    for p in range(pop.n_programs):
+        ra_ = oracle.evaluate_pairs(pop, X, np.full(N, p, np.int32), np.arange(N), u=u)
+        v, E = ra_.v32.astype(np.float64), ra_.bound
+        if fn[p] or not (np.all(np.isfinite(v)) and np.all(np.isfinite(E))):
+            continue
+        R0 = rho(v)
+        assert abs(R0 - f32p[p]) <= 1e-12
+        for _ in range(20):
+            R1 = rho(v + rng.uniform(-1, 1, size=N) * E)
+            assert abs(R1 - R0) <= fb[p] * 1.05 + 1e-12, (p, abs(R1 - R0), fb[p])
+        nonzero += fb[p] > 0
+        if np.all(E == 0):
+            assert fb[p] == 0.0       # exact values: ranks cannot differ
+    assert nonzero >= 5

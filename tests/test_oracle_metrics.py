@@ -146,3 +146,69 @@ def test_pearson_constant_program_is_exactly_zero_with_weights():
     for c in (0.1, 1.0 / 3.0, 123.456, -7.25e-3):
         f32p, f64 = fit([const_prog(c)], X, y, w, "pearson")
         assert f32p[0] == 0.0 and f64[0] == 0.0
+
+
+# ---- Spearman: Pearson of the average-rank vectors (Sec. III-C3) ----
+
+def _spearman_progs():
+    from oracle import ADD, MUL, SIN, SQRT, NEG
+    return [
+        ([node(VAR, 0)], []),
+        ([node(MUL), node(MUL), node(VAR, 0), node(VAR, 0), node(VAR, 0)], []),       # x0^3: monotone
+        ([node(SIN), node(VAR, 1)], []),
+        ([node(ADD), node(SQRT), node(VAR, 0), node(NEG), node(VAR, 1)], []),
+        ([node(CONST, 0)], [0.5]),                                                       # constant
+    ]
+
+
+def test_spearman_matches_scipy_without_weights():
+    from scipy.stats import spearmanr
+    rng = np.random.default_rng(11)
+    n = 3001
+    X = rng.uniform(-2, 2, size=(2, n)).astype(np.float32)
+    # y with ties (rounded to a coarse grid)
+    y = np.round(rng.normal(size=n) * 4).astype(np.float32)
+    pop = oracle.from_programs(_spearman_progs())
+    f32p, f64 = oracle.fitness(pop, X, y, None, "spearman")
+    for p in range(pop.n_programs - 1):
+        v = oracle.evaluate_f64(pop, X)[p]
+        expect = abs(spearmanr(v, y.astype(np.float64)).correlation)
+        assert abs(f64[p] - expect) <= 1e-12, p
+    assert f64[-1] == 0.0 and f32p[-1] == 0.0                                          # constant program
+
+
+def test_spearman_invariant_under_monotone_maps_and_weight_scale():
+    rng = np.random.default_rng(12)
+    n = 2000
+    X = rng.uniform(0.1, 3, size=(2, n)).astype(np.float32)
+    y = rng.normal(size=n).astype(np.float32)
+    pop = oracle.from_programs(_spearman_progs()[:2])                                 # x0 and x0^3
+    _, f = oracle.fitness(pop, X, y, None, "spearman")
+    assert f[0] == f[1]
+    w = rng.uniform(0.5, 1.5, size=n).astype(np.float32)
+    _, fa = oracle.fitness(pop, X, y, w, "spearman")
+    _, fb = oracle.fitness(pop, X, y, (w * 4).astype(np.float32), "spearman")
+    assert np.allclose(fa, fb, rtol=1e-12, atol=0)
+
+
+def test_spearman_weighted_hand_example_with_ties():
+    # values (1, 2, 2, 5) -> ranks (1, 2.5, 2.5, 4); y (10, 30, 20, 40) -> (1, 3, 2, 4)
+    X = np.array([[1, 2, 2, 5]], dtype=np.float32)
+    y = np.array([10, 30, 20, 40], dtype=np.float32)
+    w = np.array([1, 2, 1, 2], dtype=np.float32)
+    pop = oracle.from_programs([([node(VAR, 0)], [])])
+    _, f = oracle.fitness(pop, X, y, w, "spearman")
+    a = np.array([1, 2.5, 2.5, 4.0])
+    b = np.array([1, 3, 2, 4.0])
+    wd = w.astype(np.float64)
+    ma, mb = np.sum(wd * a) / wd.sum(), np.sum(wd * b) / wd.sum()
+    r = np.sum(wd * (a - ma) * (b - mb)) / np.sqrt(np.sum(wd * (a - ma) ** 2) * np.sum(wd * (b - mb) ** 2))
+    assert abs(f[0] - abs(r)) <= 1e-15
+
+
+def test_spearman_nan_is_nan():
+    X = np.array([[1.0, np.nan, 3.0]], dtype=np.float32)
+    y = np.array([1.0, 2.0, 3.0], dtype=np.float32)
+    pop = oracle.from_programs([([node(VAR, 0)], [])])
+    f32p, f64 = oracle.fitness(pop, X, y, None, "spearman")
+    assert np.isnan(f32p[0]) and np.isnan(f64[0])
