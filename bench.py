@@ -232,7 +232,7 @@ def main():
                    "step": "validate+stage (host), one HIP graph: population upload, instruction pre-pass, "
                            "fused fitness, tournaments, result download",
                    "launch": {"rows_per_lane": tm["launch"][0], "feature_regs": tm["launch"][1],
-                              "tiles_per_chunk": tm["launch"][2],
+                              "tiles_per_chunk": tm["launch"][2], "waves_per_block": tm["launch"][3],
                               "source": ("autotuner" if tm["tuned_ms"] > 0 else
                                          "autotuner cache" if loaded else "heuristic"),
                               "tuned_ms_row_prefix": tm["tuned_ms"]}},

@@ -334,6 +334,7 @@ typedef struct {
     int32_t feature_regs;     /* 0 (features read from memory), 2 or 8 (features
                                  held in registers; needs n_features <= it)        */
     int32_t tiles_per_chunk;  /* >= 1: rows per work item = 64*rows_per_lane*this  */
+    int32_t waves_per_block;  /* 1, 2 or 4: block size 64, 128 or 256 threads     */
 } gp_launch_config;
 
 /* The configuration gp_fitness would use for this shape and metric on the
@@ -352,7 +353,8 @@ gp_status gp_set_launch_config(const gp_launch_config* cfg);
 /* Autotuner (batching of uneven programs; not in the paper).  Times the
  * fitness computation of this population under each candidate configuration
  * -- rows_per_lane 1, 2, 4; feature registers that fit n_features, and 0;
- * rows per work item from 1/4 to 2 times the heuristic's -- on the first
+ * rows per work item from 1/4 to 2 times the heuristic's, at 4 waves per
+ * block; then 1 and 2 waves per block for the best of those -- on the first
  * min(n_rows, 2^20) rows, `repeats` timed runs after one warm-up each, and
  * keeps the fastest for the full shape (device, n_features, n_rows,
  * n_programs, metric's kernel), which gp_fitness and gp_generation_run then
@@ -367,7 +369,7 @@ gp_status gp_autotune(const gp_population_dev* pop, const gp_dataset_dev* data,
 
 /* The tuned entries as JSON lines (one object per shape, keys arch, n_cu,
  * n_features, n_rows, n_programs, kernel, rows_per_lane, feature_regs,
- * tiles_per_chunk, ms); load merges a file written by save (a malformed line
+ * tiles_per_chunk, waves_per_block, ms); load merges a file written by save (a malformed line
  * gives GP_ERR_INVALID_ARG and loads nothing); clear forgets every entry. */
 gp_status gp_autotune_save(const char* path);
 gp_status gp_autotune_load(const char* path);

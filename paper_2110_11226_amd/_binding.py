@@ -74,7 +74,8 @@ _fitness = _sig("gp_fitness", [ctypes.POINTER(PopulationDev), ctypes.POINTER(Dat
                                _vp, _vp])
 _tournament = _sig("gp_tournament", [_vp, _vp, _i32, ctypes.c_int, _f32, _i32, _i32, _u64, _u64, _vp, _vp])
 class LaunchConfig(ctypes.Structure):
-    _fields_ = [("rows_per_lane", _i32), ("feature_regs", _i32), ("tiles_per_chunk", _i32)]
+    _fields_ = [("rows_per_lane", _i32), ("feature_regs", _i32), ("tiles_per_chunk", _i32),
+                ("waves_per_block", _i32)]
 
 
 _get_cfg = _sig("gp_get_launch_config", [_i32, _i64, _i32, ctypes.c_int, ctypes.POINTER(LaunchConfig)])
@@ -140,7 +141,7 @@ def profile_read():
 def get_launch_config(n_features, n_rows, n_programs, metric="mse"):
     c = LaunchConfig()
     _check(_get_cfg(n_features, n_rows, n_programs, metric_id(metric), ctypes.byref(c)), "gp_get_launch_config")
-    return (c.rows_per_lane, c.feature_regs, c.tiles_per_chunk)
+    return (c.rows_per_lane, c.feature_regs, c.tiles_per_chunk, c.waves_per_block)
 
 
 def autotune(pop, data, metric="mse", repeats=2, stream=None):
@@ -150,7 +151,7 @@ def autotune(pop, data, metric="mse", repeats=2, stream=None):
     ms = ctypes.c_double(-1.0)
     _check(_autotune(ctypes.byref(pop.view), ctypes.byref(data.view), metric_id(metric), int(repeats),
                      ctypes.byref(c), ctypes.byref(ms), _stream(stream)), "gp_autotune")
-    return (c.rows_per_lane, c.feature_regs, c.tiles_per_chunk), float(ms.value)
+    return (c.rows_per_lane, c.feature_regs, c.tiles_per_chunk, c.waves_per_block), float(ms.value)
 
 
 def autotune_save(path):
@@ -166,11 +167,15 @@ def autotune_clear():
 
 
 def set_launch_config(cfg=None):
-    """cfg = (rows_per_lane, feature_regs, tiles_per_chunk) or None for automatic."""
+    """cfg = (rows_per_lane, feature_regs, tiles_per_chunk[, waves_per_block
+    = 4]) or None for automatic."""
     if cfg is None:
         _check(_set_cfg(None), "gp_set_launch_config")
     else:
-        c = LaunchConfig(*[int(v) for v in cfg])
+        v = [int(x) for x in cfg]
+        if len(v) == 3:
+            v.append(4)
+        c = LaunchConfig(*v)
         _check(_set_cfg(ctypes.byref(c)), "gp_set_launch_config")
 
 
@@ -399,7 +404,7 @@ class Generation:
         return fit, win[:self.n_tournaments]
 
     def info(self):
-        """((rows_per_lane, feature_regs, tiles_per_chunk), kernel_ms of the last run, tuned_ms)."""
+        """(launch configuration, kernel_ms of the last run, tuned_ms)."""
         d = self.timing()
         return d["launch"], d["kernel_ms"], d["tuned_ms"]
 
@@ -414,7 +419,8 @@ class Generation:
         t = ctypes.c_double(-1.0)
         _check(_gen_info(self._h, ctypes.byref(c), ctypes.byref(k), ctypes.byref(ck), ctypes.byref(ev),
                          ctypes.byref(t)), "gp_generation_info")
-        return {"launch": (c.rows_per_lane, c.feature_regs, c.tiles_per_chunk), "kernel_ms": float(k.value),
+        return {"launch": (c.rows_per_lane, c.feature_regs, c.tiles_per_chunk, c.waves_per_block),
+                "kernel_ms": float(k.value),
                 "clock_ms": float(ck.value), "timed_by": "hip_events" if ev.value else "device_clock",
                 "tuned_ms": float(t.value)}
 

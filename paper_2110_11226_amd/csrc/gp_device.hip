@@ -65,7 +65,7 @@ struct DataView {
 // Compiled programs: program p's instructions are code[prog_off[p] ..
 // prog_off[p] + clen[p]) (clen[p] <= len[p]), in execution order.
 struct CodeView {
-    const uint2* code;
+    const uint4* code;
     const int32_t* clen;
 };
 
@@ -93,6 +93,10 @@ struct Sched {
 //   bits 8-31 feature index, or the constant's slot
 //   y         a constant's float bits; for an inactive instruction, the
 //             index of the first instruction of the subtree it completes
+//   z         up to 8 unary functions applied, in order, to the result of
+//             the instruction (4 bits each from the lowest: unary function
+//             + 1; 0 ends the chain), so that a unary function costs no
+//             dispatch of its own
 // ---------------------------------------------------------------------------
 enum : uint32_t { kPush = 0, kFold = 1, kBin = 2, kUn = 3 };
 constexpr uint32_t kActive = 64u;
@@ -207,7 +211,7 @@ __device__ __forceinline__ void apply_unary(uint32_t fn, float (&t)[R]) {
 // instruction of the subtree that produced it and whether that subtree holds
 // a constant; each instruction records both (bit kActive, word y).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint2* __restrict__ code,
+__global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint4* __restrict__ code,
                                                      int32_t* __restrict__ clen) {
     __shared__ uint32_t shadow[GP_MAX_STACK][kBlock];   // start | active << 31
     const int32_t p = static_cast<int32_t>(blockIdx.x) * kBlock + threadIdx.x;
@@ -216,15 +220,25 @@ __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint2* __restri
     const int32_t L = pop.len[p];
     const uint32_t* pn = pop.nodes + off;
     const float* pc = pop.consts + pop.const_off[p];
-    uint2* out = code + off;
+    uint4* out = code + off;
     uint32_t* sh = &shadow[0][threadIdx.x];   // entry h at sh[h * kBlock]
     int h = 0;                                // shadow stack height
-    int32_t k = 0;
+    int32_t k = 0;                            // instructions emitted
+    uint4 pend = make_uint4(0u, 0u, 0u, 0u);  // the last instruction, still open for a unary chain
+    int chain = -1;                           // unary functions chained on it (-1: none pending)
     for (int32_t i = L - 1; i >= 0; --i) {
         const uint32_t w = pn[i];
         const uint32_t op = w & 0xffu;
         const uint32_t arg = w >> 8;
+        if (op > GP_OP_DIV && chain >= 0 && chain < 8) {
+            // a unary function applied to the pending instruction's result:
+            // same subtree start and activity as its operand
+            pend.z |= (op - GP_OP_NEG + 1u) << (4 * chain);
+            ++chain;
+            continue;
+        }
         uint32_t x, start, active;
+        uint2 xy;
         if (op <= GP_OP_CONST) {
             const uint32_t is_c = op == GP_OP_CONST ? 1u : 0u;
             const uint32_t farg = arg;   // feature index, or constant slot (used by the adjoint)
@@ -241,11 +255,8 @@ __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint2* __restri
                 start = static_cast<uint32_t>(k);
                 active = is_c;
             }
-            if (is_c) {
-                out[k] = make_uint2(x | kActive, __float_as_uint(pc[arg]));
-            } else {
-                out[k] = make_uint2(x | (active ? kActive : 0u), start);
-            }
+            xy = is_c ? make_uint2(x | kActive, __float_as_uint(pc[arg]))
+                      : make_uint2(x | (active ? kActive : 0u), start);
         } else if (op <= GP_OP_DIV) {
             const uint32_t first = sh[max(h - 1, 0) * kBlock];     // top: the first operand
             const uint32_t second = sh[max(h - 2, 0) * kBlock];    // evaluated before it
@@ -253,15 +264,19 @@ __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint2* __restri
             start = second & 0x7fffffffu;
             active = (first >> 31) | (second >> 31);
             h -= 2;
-            out[k] = make_uint2(x | (active ? kActive : 0u), start);
+            xy = make_uint2(x | (active ? kActive : 0u), start);
         } else {
+            // a unary function with a full chain before it: its own instruction
             const uint32_t top = sh[max(h - 1, 0) * kBlock];
             x = enc(kUn, op - GP_OP_NEG, 0, 0);
             start = top & 0x7fffffffu;
             active = top >> 31;
             --h;
-            out[k] = make_uint2(x | (active ? kActive : 0u), start);
+            xy = make_uint2(x | (active ? kActive : 0u), start);
         }
+        if (chain >= 0) out[k - 1] = pend;
+        pend = make_uint4(xy.x, xy.y, 0u, 0u);
+        chain = 0;
         // (valid programs keep 1 <= h <= GP_MAX_STACK; the clamps only keep an
         // invalid one inside this array)
         h = max(h, 0);
@@ -269,6 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint2* __restri
         ++h;
         ++k;
     }
+    if (chain >= 0) out[k - 1] = pend;
     clen[p] = k;
 }
 
@@ -370,8 +386,10 @@ __global__ __launch_bounds__(kBlock) void k_eval(PopView pop, CodeView cv, DataV
     const int64_t N = d.N;
     const int64_t ld = d.ld;
     const float* __restrict__ X = d.X;
-    __shared__ float ovf_all[kBlock / kWave][kStackLds * R * kWave];
-    float* ovf = ovf_all[threadIdx.x >> 6];
+    // stack entries beyond the registers: kStackLds * R * 64 floats per wavefront
+    // of the block (dynamic LDS, sized at launch for the block's wavefronts)
+    extern __shared__ float ovf_all[];
+    float* ovf = ovf_all + (threadIdx.x >> 6) * (kStackLds * R * kWave);
 
     for (;;) {
         uint32_t it32 = 0;
@@ -383,7 +401,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(PopView pop, CodeView cv, DataV
         const int32_t p = ldu(s.order + k);
         const int64_t off = ldu(pop.prog_off + p);
         const int32_t CL = ldu(cv.clen + p);
-        const uint2* __restrict__ pcode = cv.code + off;
+        const uint4* __restrict__ pcode = cv.code + off;
         const int64_t r0 = static_cast<int64_t>(c) * s.chunk;
         const int64_t r1 = min(r0 + s.chunk, N);
 
@@ -429,21 +447,20 @@ __global__ __launch_bounds__(kBlock) void k_eval(PopView pop, CodeView cv, DataV
             for (int j = 0; j < R; ++j) t[j] = 0.0f;
             GP_ARRAYS(st, kStackRegs + 1);
             int dp = -1;
-            uint2 nxt = pcode[0];
+            uint4 nxt = pcode[0];
             for (int q = 0; q < CL; ++q) {
-                const uint2 cur = nxt;
+                const uint4 cur = nxt;
                 nxt = pcode[min(q + 1, CL - 1)];
                 const uint32_t w = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(cur.x)));
                 const uint32_t cls = w & 3u;
                 const uint32_t fn = (w >> 2) & 7u;
                 const int up = min(dp + 1, kStackRegs);
                 GP_PUT(st, up, t);
+                float a[R], b[R];
+                bool binary = false;
                 if (cls == kUn) {
                     apply_unary<R>(fn, t);
-                    continue;
-                }
-                float a[R], b[R];
-                if (cls == kBin) {
+                } else if (cls == kBin) {
                     if (dp < kStackRegs) {
                         GP_GET(st, dp, b);
                     } else {
@@ -453,6 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(PopView pop, CodeView cv, DataV
                     --dp;
 #pragma unroll
                     for (int j = 0; j < R; ++j) a[j] = t[j];
+                    binary = true;
                 } else {
                     float v[R];
                     if (w & 32u) {
@@ -478,18 +496,25 @@ __global__ __launch_bounds__(kBlock) void k_eval(PopView pop, CodeView cv, DataV
                         }
 #pragma unroll
                         for (int j = 0; j < R; ++j) t[j] = v[j];
-                        continue;
-                    }
-                    // kFold: the terminal is the first operand, the top the second
+                    } else {
+                        // kFold: the terminal is the first operand, the top the second
 #pragma unroll
-                    for (int j = 0; j < R; ++j) {
-                        a[j] = v[j];
-                        b[j] = t[j];
+                        for (int j = 0; j < R; ++j) {
+                            a[j] = v[j];
+                            b[j] = t[j];
+                        }
+                        binary = true;
                     }
                 }
-                apply_binary<R>(fn, a, b);
+                if (binary) {
+                    apply_binary<R>(fn, a, b);
 #pragma unroll
-                for (int j = 0; j < R; ++j) t[j] = a[j];
+                    for (int j = 0; j < R; ++j) t[j] = a[j];
+                }
+                // the unary functions chained on this instruction
+                for (uint32_t ch = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(cur.z)));
+                     ch != 0u; ch >>= 4)
+                    apply_unary<R>((ch & 15u) - 1u, t);
             }
 
             if constexpr (MODE == 0) {
@@ -693,6 +718,23 @@ constexpr int64_t adjoint_wave_floats(int64_t tape_entries_max) {
     return (2 * kStackLds + beyond) * R * kWave;
 }
 
+// derivative of unary function fn (1..5: log, sqrt, sin, cos, tan) at input
+// x, whose result is y (reading above)
+template <int R>
+__device__ __forceinline__ void unary_derivative(uint32_t fn, const float (&x)[R], const float (&y)[R],
+                                                 float (&dv)[R]) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        switch (fn) {
+        case 1: dv[j] = fabsf(x[j]) > GP_PROTECT_EPS ? 1.0f / x[j] : 0.0f; break;
+        case 2: dv[j] = x[j] == 0.0f ? 0.0f : copysignf(1.0f, x[j]) / (2.0f * y[j]); break;
+        case 3: dv[j] = cosf(x[j]); break;
+        case 4: dv[j] = -sinf(x[j]); break;
+        default: dv[j] = 1.0f + y[j] * y[j]; break;
+        }
+    }
+}
+
 template <int R, int FREG, int METRIC>
 __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, DataView d, Sched s,
                                                     const double* __restrict__ stats,
@@ -749,7 +791,7 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
         const int32_t CL = ldu(cv.clen + p);
         const int64_t cbase = ldu(pop.const_off + p);
         const int32_t nconst = static_cast<int32_t>(ldu(pop.const_off + p + 1) - cbase);
-        const uint2* __restrict__ pcode = cv.code + off;
+        const uint4* __restrict__ pcode = cv.code + off;
         const int64_t r0 = static_cast<int64_t>(c) * s.chunk;
         const int64_t r1 = min(r0 + s.chunk, N);
         const float gsc = gscale ? ldu(gscale + p) : 1.0f;
@@ -795,38 +837,29 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
             GP_ARRAYS(st, kStackRegs + 1);
             int dp = -1;
             int ntape = 0;
-            uint2 nxt = pcode[0];
+            uint4 nxt = pcode[0];
             for (int q = 0; q < CL; ++q) {
-                const uint2 cur = nxt;
+                const uint4 cur = nxt;
                 nxt = pcode[min(q + 1, CL - 1)];
                 const uint32_t w = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(cur.x)));
                 const uint32_t cls = w & 3u;
                 const uint32_t fn = (w >> 2) & 7u;
+                const bool act = (w & kActive) != 0u;
                 GP_PUT(st, min(dp + 1, kStackRegs), t);
+                float a[R], b[R];
+                bool binary = false;
                 if (cls == kUn) {
                     float x[R];
 #pragma unroll
                     for (int j = 0; j < R; ++j) x[j] = t[j];
                     apply_unary<R>(fn, t);
-                    if (fn != 0 && (w & kActive)) {
+                    if (fn != 0 && act) {
                         float dv[R];
-#pragma unroll
-                        for (int j = 0; j < R; ++j) {
-                            switch (fn) {
-                            case 1: dv[j] = fabsf(x[j]) > GP_PROTECT_EPS ? 1.0f / x[j] : 0.0f; break;
-                            case 2: dv[j] = x[j] == 0.0f ? 0.0f : copysignf(1.0f, x[j]) / (2.0f * t[j]); break;
-                            case 3: dv[j] = cosf(x[j]); break;
-                            case 4: dv[j] = -sinf(x[j]); break;
-                            default: dv[j] = 1.0f + t[j] * t[j]; break;
-                            }
-                        }
+                        unary_derivative<R>(fn, x, t, dv);
                         tape_put(ntape, dv);
                         ++ntape;
                     }
-                    continue;
-                }
-                float a[R], b[R];
-                if (cls == kBin) {
+                } else if (cls == kBin) {
                     if (dp < kStackRegs) {
                         GP_GET(st, dp, b);
                     } else {
@@ -836,6 +869,7 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                     --dp;
 #pragma unroll
                     for (int j = 0; j < R; ++j) a[j] = t[j];
+                    binary = true;
                 } else {
                     float v[R];
                     if (w & 32u) {
@@ -861,37 +895,55 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                         }
 #pragma unroll
                         for (int j = 0; j < R; ++j) t[j] = v[j];
-                        continue;
-                    }
+                    } else {
 #pragma unroll
-                    for (int j = 0; j < R; ++j) {
-                        a[j] = v[j];
-                        b[j] = t[j];
-                    }
-                }
-                if (fn >= 2 && (w & kActive)) {   // mul / div: both partials
-                    float da[R], db[R];
-#pragma unroll
-                    for (int j = 0; j < R; ++j) {
-                        if (fn == 2) {
-                            da[j] = b[j];
-                            db[j] = a[j];
-                        } else if (fabsf(b[j]) > GP_PROTECT_EPS) {
-                            const float inv = 1.0f / b[j];
-                            da[j] = inv;
-                            db[j] = -a[j] * inv * inv;
-                        } else {
-                            da[j] = 0.0f;
-                            db[j] = 0.0f;
+                        for (int j = 0; j < R; ++j) {
+                            a[j] = v[j];
+                            b[j] = t[j];
                         }
+                        binary = true;
                     }
-                    tape_put(ntape, da);
-                    tape_put(ntape + 1, db);
-                    ntape += 2;
                 }
-                apply_binary<R>(fn, a, b);
+                if (binary) {
+                    if (fn >= 2 && act) {   // mul / div: both partials
+                        float da[R], db[R];
 #pragma unroll
-                for (int j = 0; j < R; ++j) t[j] = a[j];
+                        for (int j = 0; j < R; ++j) {
+                            if (fn == 2) {
+                                da[j] = b[j];
+                                db[j] = a[j];
+                            } else if (fabsf(b[j]) > GP_PROTECT_EPS) {
+                                const float inv = 1.0f / b[j];
+                                da[j] = inv;
+                                db[j] = -a[j] * inv * inv;
+                            } else {
+                                da[j] = 0.0f;
+                                db[j] = 0.0f;
+                            }
+                        }
+                        tape_put(ntape, da);
+                        tape_put(ntape + 1, db);
+                        ntape += 2;
+                    }
+                    apply_binary<R>(fn, a, b);
+#pragma unroll
+                    for (int j = 0; j < R; ++j) t[j] = a[j];
+                }
+                // the chained unary functions, each taping its derivative
+                for (uint32_t ch = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(cur.z)));
+                     ch != 0u; ch >>= 4) {
+                    const uint32_t u = (ch & 15u) - 1u;
+                    float x[R];
+#pragma unroll
+                    for (int j = 0; j < R; ++j) x[j] = t[j];
+                    apply_unary<R>(u, t);
+                    if (u != 0 && act) {
+                        float dv[R];
+                        unary_derivative<R>(u, x, t, dv);
+                        tape_put(ntape, dv);
+                        ++ntape;
+                    }
+                }
             }
 
             // ---------------- seeds: d fitness / d yhat per row ----------------
@@ -939,9 +991,9 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
             GP_ARRAYS(as, kStackRegs + 1);   // adjoints of the entries below the top
             int ad = dp;                     // mirrors the value stack (dp == 0 here)
             int q = CL - 1;
-            uint2 prv = pcode[q];
+            uint4 prv = pcode[q];
             for (; q >= 0; --q) {
-                const uint2 cur = prv;
+                const uint4 cur = prv;
                 prv = pcode[max(q - 1, 0)];
                 const uint32_t w = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(cur.x)));
                 if (!(w & kActive)) {
@@ -963,6 +1015,24 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                 }
                 const uint32_t cls = w & 3u;
                 const uint32_t fn = (w >> 2) & 7u;
+                // the chained unary functions first, the last one first
+                const uint32_t chain = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(cur.z)));
+                if (chain != 0u) {
+                    const int nch = (32 - __clz(static_cast<int>(chain)) + 3) >> 2;
+                    for (int kq = nch - 1; kq >= 0; --kq) {
+                        const uint32_t u = ((chain >> (4 * kq)) & 15u) - 1u;
+                        if (u == 0u) {
+#pragma unroll
+                            for (int j = 0; j < R; ++j) g[j] = -g[j];
+                        } else {
+                            --ntape;
+                            float dv[R];
+                            tape_get(ntape, dv);
+#pragma unroll
+                            for (int j = 0; j < R; ++j) g[j] = g[j] * dv[j];
+                        }
+                    }
+                }
                 const int ne = tape_entries(cls, fn);
                 ntape -= ne;
                 float gb[R];   // adjoint handed to the entry below the top (binary only)
@@ -1130,6 +1200,244 @@ __global__ __launch_bounds__(kBlock) void k_tournament(const float* __restrict__
     winners[t] = best;
 }
 
+// ---------------------------------------------------------------------------
+// Spearman (Sec. III-C3 ranks each program's outputs with a sort): the outputs
+// of a batch of programs are turned into order-preserving 32-bit keys, each
+// program's N keys are sorted with their row indices by a segmented LSD radix
+// sort (four passes of 8 bits: per-tile digit counts, a per-segment scan,
+// a stable scatter), and one workgroup per program walks its sorted keys,
+// giving tied values the mean of their ranks, and forms the float64 moments
+// of the (value rank, target rank) pairs.
+// ---------------------------------------------------------------------------
+constexpr int kRsBlock = 256;                  // threads of the sort kernels
+constexpr int kRsItems = 16;                   // keys per thread
+constexpr int kRsTile = kRsBlock * kRsItems;   // keys per tile
+constexpr int kRsRadix = 256;
+
+// float -> uint32 with the same order; -0 and +0 map to one key
+__device__ __forceinline__ uint32_t order_key(float v) {
+    uint32_t b = __float_as_uint(v == 0.0f ? 0.0f : v);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// keys[s*N + r] = order_key(out[s*N + r]), idx = r; nan[s] = 1 if any NaN
+__global__ __launch_bounds__(kRsBlock) void k_spear_keys(const float* __restrict__ out, int64_t N, int32_t B,
+                                                          uint32_t* __restrict__ keys, uint32_t* __restrict__ idx,
+                                                          int32_t* __restrict__ nan_flag) {
+    const int64_t total = N * B;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kRsBlock + threadIdx.x; i < total;
+         i += static_cast<int64_t>(gridDim.x) * kRsBlock) {
+        const float v = out[i];
+        const int64_t seg = i / N;
+        if (isnan(v)) nan_flag[seg] = 1;
+        keys[i] = order_key(v);
+        idx[i] = static_cast<uint32_t>(i - seg * N);
+    }
+}
+
+// counts[(seg * 256 + digit) * T + tile] for one pass
+__global__ __launch_bounds__(kRsBlock) void k_rs_count(const uint32_t* __restrict__ keys, int64_t N, int32_t T,
+                                                        int shift, uint32_t* __restrict__ counts) {
+    __shared__ uint32_t hist[kRsRadix];
+    const int32_t tile = blockIdx.x, seg = blockIdx.y;
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = static_cast<int64_t>(seg) * N;
+    const int64_t t0 = static_cast<int64_t>(tile) * kRsTile;
+    for (int k = 0; k < kRsItems; ++k) {
+        const int64_t i = t0 + k * kRsBlock + threadIdx.x;
+        if (i < N) atomicAdd(&hist[(keys[base + i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    counts[(static_cast<int64_t>(seg) * kRsRadix + threadIdx.x) * T + tile] = hist[threadIdx.x];
+}
+
+// exclusive scan of one segment's 256*T counts, digit-major (in place)
+__global__ __launch_bounds__(1024) void k_rs_scan(uint32_t* __restrict__ counts, int32_t T) {
+    __shared__ uint32_t part[1024];
+    const int64_t n = static_cast<int64_t>(kRsRadix) * T;
+    uint32_t* c = counts + static_cast<int64_t>(blockIdx.x) * n;
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t a = min(n, per * threadIdx.x), b = min(n, a + per);
+    uint32_t sum = 0;
+    for (int64_t i = a; i < b; ++i) sum += c[i];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {   // inclusive Hillis-Steele scan
+        const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[threadIdx.x] - sum;     // exclusive prefix of this thread's range
+    for (int64_t i = a; i < b; ++i) {
+        const uint32_t v = c[i];
+        c[i] = run;
+        run += v;
+    }
+}
+
+// stable scatter of one tile: keys are taken in index order, 256 at a time;
+// within a round, equal digits are ranked by lane (wave ballots) and by wave
+__global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint32_t* __restrict__ kin,
+                                                          const uint32_t* __restrict__ vin,
+                                                          uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                          int64_t N, int32_t T, int shift,
+                                                          const uint32_t* __restrict__ offsets) {
+    __shared__ uint32_t base_off[kRsRadix];           // global start of each digit for this tile
+    __shared__ uint32_t wcnt[kRsBlock / kWave][kRsRadix];
+    const int32_t tile = blockIdx.x, seg = blockIdx.y;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+    base_off[threadIdx.x] = offsets[(static_cast<int64_t>(seg) * kRsRadix + threadIdx.x) * T + tile];
+    const int64_t sbase = static_cast<int64_t>(seg) * N;
+    const int64_t t0 = static_cast<int64_t>(tile) * kRsTile;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int k = 0; k < kRsItems; ++k) {
+        const int64_t i = t0 + k * kRsBlock + threadIdx.x;
+        const bool valid = i < N;
+        const uint32_t key = valid ? kin[sbase + i] : 0u;
+        const uint32_t val = valid ? vin[sbase + i] : 0u;
+        const uint32_t d = (key >> shift) & 255u;
+        for (int w = 0; w < kRsBlock / kWave; ++w) wcnt[w][threadIdx.x] = 0;
+        __syncthreads();
+        // lanes of this wave holding a valid key with the same digit
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const uint64_t bal = __ballot((d >> bit) & 1u);
+            peers &= ((d >> bit) & 1u) ? bal : ~bal;
+        }
+        const uint32_t rank_w = static_cast<uint32_t>(__popcll(peers & lt_mask));
+        if (valid && rank_w == 0) wcnt[wave][d] = static_cast<uint32_t>(__popcll(peers));
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+        for (int w = 0; w < kRsBlock / kWave; ++w) {
+            const uint32_t c = wcnt[w][d];
+            before += w < wave ? c : 0u;
+            total += c;
+        }
+        if (valid) {
+            const uint32_t pos = base_off[d] + before + rank_w;
+            kout[sbase + pos] = key;
+            vout[sbase + pos] = val;
+        }
+        __syncthreads();
+        // the first holder of each digit in this round advances its start
+        if (valid && rank_w == 0 && before == 0) base_off[d] += total;
+        __syncthreads();
+    }
+}
+
+// Walks one segment's sorted keys (one workgroup): tied runs share the mean
+// of their ranks; twice that rank is used so that it stays an integer.
+// MODE 0 writes rank2[idx] (the target's ranks); MODE 1 accumulates the
+// weighted moments of (value rank, target rank), both centred on (N+1)/2,
+// and writes |r| (0 for a constant rank vector, NaN if the outputs held a NaN).
+template <int MODE>
+__global__ __launch_bounds__(1024) void k_spear_ranks(const uint32_t* __restrict__ keys,
+                                                       const uint32_t* __restrict__ idx, int64_t N,
+                                                       uint32_t* __restrict__ run_start,
+                                                       uint32_t* __restrict__ rank2_out,
+                                                       const uint32_t* __restrict__ rank2_y,
+                                                       const float* __restrict__ w,
+                                                       const int32_t* __restrict__ nan_flag,
+                                                       float* __restrict__ fitness, int32_t prog0) {
+    __shared__ uint32_t sc[1024];
+    __shared__ double red[6][1024 / kWave];
+    const int32_t seg = blockIdx.x;
+    const int tid = threadIdx.x;
+    const uint32_t* k = keys + static_cast<int64_t>(seg) * N;
+    const uint32_t* ix = idx + static_cast<int64_t>(seg) * N;
+    uint32_t* rs = run_start + static_cast<int64_t>(seg) * N;
+    // pass A, ascending chunks: start of the run holding position i (max-scan)
+    uint32_t carry = 0;
+    for (int64_t c0 = 0; c0 < N; c0 += 1024) {
+        const int64_t i = c0 + tid;
+        uint32_t v = 0;
+        if (i < N) v = (i == 0 || k[i] != k[i - 1]) ? static_cast<uint32_t>(i) : 0u;
+        sc[tid] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const uint32_t o = tid >= off ? sc[tid - off] : 0u;
+            __syncthreads();
+            sc[tid] = max(sc[tid], o);
+            __syncthreads();
+        }
+        const uint32_t st = max(sc[tid], carry);
+        if (i < N) rs[i] = st;
+        const uint32_t last = max(sc[1023], carry);
+        __syncthreads();
+        carry = last;
+    }
+    // pass B, descending chunks: end of the run (min-scan from the right)
+    double s_w = 0.0, s_a = 0.0, s_aa = 0.0, s_ab = 0.0, s_b = 0.0, s_bb = 0.0;
+    const double mid = 0.5 * (static_cast<double>(N) + 1.0);
+    uint32_t carry_end = static_cast<uint32_t>(N);
+    for (int64_t c1 = ((N + 1023) / 1024) * 1024; c1 > 0; c1 -= 1024) {
+        const int64_t i = c1 - 1024 + tid;
+        uint32_t v = 0xffffffffu;
+        if (i < N) v = (i == N - 1 || k[i] != k[i + 1]) ? static_cast<uint32_t>(i + 1) : 0xffffffffu;
+        sc[tid] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const uint32_t o = tid + off < 1024 ? sc[tid + off] : 0xffffffffu;
+            __syncthreads();
+            sc[tid] = min(sc[tid], o);
+            __syncthreads();
+        }
+        const uint32_t en = min(sc[tid], carry_end);
+        const uint32_t first = min(sc[0], carry_end);
+        if (i < N) {
+            const uint32_t r2 = rs[i] + 1u + en;        // twice the mean rank of the run
+            const uint32_t row = ix[i];
+            if constexpr (MODE == 0) {
+                rank2_out[row] = r2;
+            } else {
+                const double a = 0.5 * static_cast<double>(r2) - mid;
+                const double b = 0.5 * static_cast<double>(rank2_y[row]) - mid;
+                const double wv = w ? static_cast<double>(w[row]) : 1.0;
+                s_w += wv;
+                s_a += wv * a;
+                s_aa += wv * a * a;
+                s_ab += wv * a * b;
+                s_b += wv * b;
+                s_bb += wv * b * b;
+            }
+        }
+        __syncthreads();
+        carry_end = first;
+    }
+    if constexpr (MODE == 1) {
+        double v[6] = {s_w, s_a, s_aa, s_ab, s_b, s_bb};
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const double t = wave_sum(v[q]);
+            if ((tid & (kWave - 1)) == 0) red[q][tid >> 6] = t;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double tot[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                double acc = 0.0;
+                for (int j = 0; j < 1024 / kWave; ++j) acc += red[q][j];
+                tot[q] = acc;
+            }
+            const double W = tot[0];
+            const double va = tot[2] - tot[1] * tot[1] / W;
+            const double vb = tot[5] - tot[4] * tot[4] / W;
+            const double cab = tot[3] - tot[1] * tot[4] / W;
+            // one run of equal values: a constant rank vector
+            const bool constant = rs[N - 1] == 0u;
+            float f;
+            if (nan_flag[seg]) f = __builtin_nanf("");
+            else if (constant || !(va > 0.0) || !(vb > 0.0) || !isfinite(va) || !isfinite(vb)) f = 0.0f;
+            else f = static_cast<float>(fabs(cab / sqrt(va * vb)));
+            fitness[prog0 + seg] = f;
+        }
+    }
+}
+
 // k_stamp: one lane records the device's constant-rate clock (kernel timing
 // inside a captured graph, where event records are not available).
 __global__ __launch_bounds__(kWave) void k_stamp(uint64_t* __restrict__ out) {
@@ -1154,7 +1462,7 @@ struct DeviceScratch {
     size_t part_cap = 0;         // doubles
     double* ystat = nullptr;
     size_t ystat_cap = 0;        // doubles
-    uint2* code = nullptr;
+    uint4* code = nullptr;
     size_t code_cap = 0;         // instructions
     int32_t* clen = nullptr;
     size_t clen_cap = 0;
@@ -1168,6 +1476,26 @@ struct DeviceScratch {
     size_t tape_cap = 0;
     float* fit_tmp = nullptr;
     size_t fit_tmp_cap = 0;
+    // Spearman: program outputs, sort keys and indices (double-buffered), run
+    // starts, digit counts, the target's ranks, NaN flags
+    float* sp_out = nullptr;
+    size_t sp_out_cap = 0;
+    uint32_t* sp_k0 = nullptr;
+    size_t sp_k0_cap = 0;
+    uint32_t* sp_k1 = nullptr;
+    size_t sp_k1_cap = 0;
+    uint32_t* sp_v0 = nullptr;
+    size_t sp_v0_cap = 0;
+    uint32_t* sp_v1 = nullptr;
+    size_t sp_v1_cap = 0;
+    uint32_t* sp_rs = nullptr;
+    size_t sp_rs_cap = 0;
+    uint32_t* sp_cnt = nullptr;
+    size_t sp_cnt_cap = 0;
+    uint32_t* sp_r2y = nullptr;
+    size_t sp_r2y_cap = 0;
+    int32_t* sp_nan = nullptr;
+    size_t sp_nan_cap = 0;
     int n_cu = 0;
     int dev = -1;
     std::string arch;
@@ -1220,7 +1548,8 @@ gp_status scratch_init(DeviceScratch& s, int dev) {
 
 bool scratch_empty(const DeviceScratch& s) {
     return !s.counter && !s.order && !s.part && !s.ystat && !s.code && !s.clen && !s.stats && !s.gpart &&
-           !s.gextra && !s.tape && !s.fit_tmp;
+           !s.gextra && !s.tape && !s.fit_tmp && !s.sp_out && !s.sp_k0 && !s.sp_k1 && !s.sp_v0 && !s.sp_v1 &&
+           !s.sp_rs && !s.sp_cnt && !s.sp_r2y && !s.sp_nan;
 }
 
 // Frees every buffer of s (the caller has made its device current and idle).
@@ -1228,7 +1557,10 @@ void scratch_free(DeviceScratch& s) {
     for (void* q : {s.counter, static_cast<void*>(s.order), static_cast<void*>(s.part),
                     static_cast<void*>(s.ystat), static_cast<void*>(s.code), static_cast<void*>(s.clen),
                     static_cast<void*>(s.stats), static_cast<void*>(s.gpart), static_cast<void*>(s.gextra),
-                    static_cast<void*>(s.tape), static_cast<void*>(s.fit_tmp)})
+                    static_cast<void*>(s.tape), static_cast<void*>(s.fit_tmp), static_cast<void*>(s.sp_out),
+                    static_cast<void*>(s.sp_k0), static_cast<void*>(s.sp_k1), static_cast<void*>(s.sp_v0),
+                    static_cast<void*>(s.sp_v1), static_cast<void*>(s.sp_rs), static_cast<void*>(s.sp_cnt),
+                    static_cast<void*>(s.sp_r2y), static_cast<void*>(s.sp_nan)})
         if (q) (void)hipFree(q);
     s = DeviceScratch{};
 }
@@ -1264,11 +1596,11 @@ gp_status check_data(const gp_dataset_dev* d, const char* who, bool need_y) {
     return GP_OK;
 }
 
-gp_status check_fitness_metric(int metric, const char* who) {
-    if (metric == GP_METRIC_SPEARMAN)
-        return fail(GP_ERR_UNSUPPORTED, std::string(who) + ": Spearman is not provided by this version");
+gp_status check_fitness_metric(int metric, const char* who, bool spearman_ok = false) {
     if (gp_metric_larger_is_better(static_cast<gp_metric>(metric)) < 0)
         return fail(GP_ERR_INVALID_ARG, std::string(who) + ": unknown metric");
+    if (metric == GP_METRIC_SPEARMAN && !spearman_ok)
+        return fail(GP_ERR_UNSUPPORTED, std::string(who) + ": Spearman is available through gp_fitness only");
     return GP_OK;
 }
 
@@ -1279,15 +1611,16 @@ struct LaunchCfg {
     int R;        // rows per lane: 1, 2 or 4
     int freg;     // features held in registers: 0, 2 or 8
     int tiles;    // tiles of 64*R rows per chunk
+    int wpb;      // wavefronts per block: 1, 2 or 4
 };
 
 bool cfg_valid(const LaunchCfg& c) {
     return (c.R == 1 || c.R == 2 || c.R == 4) && (c.freg == 0 || c.freg == 2 || c.freg == 8) && c.tiles >= 1 &&
-           c.tiles <= (1 << 20);
+           c.tiles <= (1 << 20) && (c.wpb == 1 || c.wpb == 2 || c.wpb == 4);
 }
 
 bool g_forced = false;
-LaunchCfg g_forced_cfg{4, 0, 1};
+LaunchCfg g_forced_cfg{4, 0, 1, 4};
 
 // Evaluation kernels differ by metric; each class is tuned on its own.
 int kernel_class(int mode, int metric) {
@@ -1321,6 +1654,7 @@ std::map<TuneKey, TuneVal> g_tuned;
 LaunchCfg heuristic_cfg(int F, int64_t N, int32_t P, int n_cu) {
     LaunchCfg c;
     c.R = 4;
+    c.wpb = 4;
     c.freg = F <= 2 ? 2 : (F <= 8 ? 8 : 0);
     const int64_t tile_rows = static_cast<int64_t>(kWave) * c.R;
     const int64_t n_tiles = (N + tile_rows - 1) / tile_rows;
@@ -1354,13 +1688,15 @@ template <int MODE, int METRIC>
 gp_status launch_eval_m(const LaunchCfg& cfg, int n_cu, const PopView& pv, const CodeView& cv,
                         const DataView& dv, const Sched& s, float* out, double* part, hipStream_t st,
                         int64_t node_rows, const Timing& tm) {
+    const int block = cfg.wpb * kWave;
+    const size_t lds = static_cast<size_t>(cfg.wpb) * kStackLds * cfg.R * kWave * sizeof(float);
     auto go = [&](auto kernel) -> gp_status {
         int per_cu = 0;
-        GP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0));
+        GP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds));
         per_cu = std::max(per_cu, 1);
         const int64_t waves_needed = s.n_items;
         int64_t blocks = static_cast<int64_t>(per_cu) * n_cu;
-        blocks = std::min<int64_t>(blocks, (waves_needed + (kBlock / kWave) - 1) / (kBlock / kWave));
+        blocks = std::min<int64_t>(blocks, (waves_needed + cfg.wpb - 1) / cfg.wpb);
         blocks = std::max<int64_t>(blocks, 1);
         const bool prof = tm.profile && g_prof_on;
         ProfRec rec{nullptr, nullptr, node_rows};
@@ -1371,7 +1707,7 @@ gp_status launch_eval_m(const LaunchCfg& cfg, int n_cu, const PopView& pv, const
         }
         if (tm.launched) *tm.launched = reinterpret_cast<const void*>(kernel);
         if (tm.stamp) hipLaunchKernelGGL(k_stamp, dim3(1), dim3(kWave), 0, st, tm.stamp);
-        hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, st, pv, cv, dv, s, out,
+        hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(blocks)), dim3(block), lds, st, pv, cv, dv, s, out,
                            part);
         GP_HIP(hipGetLastError());
         if (tm.stamp) {
@@ -1417,7 +1753,7 @@ gp_status launch_eval(int mode, int metric, const LaunchCfg& cfg, int n_cu, cons
 gp_status reserve(DeviceScratch* sc, int32_t P, int64_t total_nodes, int64_t n_chunks, int mode, int metric) {
     gp_status rc = grow(reinterpret_cast<void**>(&sc->order), &sc->order_cap, P, sizeof(int32_t));
     if (rc != GP_OK) return rc;
-    rc = grow(reinterpret_cast<void**>(&sc->code), &sc->code_cap, static_cast<size_t>(total_nodes), sizeof(uint2));
+    rc = grow(reinterpret_cast<void**>(&sc->code), &sc->code_cap, static_cast<size_t>(total_nodes), sizeof(uint4));
     if (rc != GP_OK) return rc;
     rc = grow(reinterpret_cast<void**>(&sc->clen), &sc->clen_cap, P, sizeof(int32_t));
     if (rc != GP_OK) return rc;
@@ -1520,6 +1856,104 @@ gp_status tournament_impl(const float* fitness, const int32_t* len, int32_t P, i
     return GP_OK;
 }
 
+__global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Sorts the B segments of N keys (with their indices) held in k0 / v0; the
+// result is back in k0 / v0 after the four passes.
+gp_status radix_sort_segments(DeviceScratch* sc, int64_t N, int32_t B, hipStream_t st) {
+    const int32_t T = static_cast<int32_t>((N + kRsTile - 1) / kRsTile);
+    uint32_t *kin = sc->sp_k0, *vin = sc->sp_v0, *kout = sc->sp_k1, *vout = sc->sp_v1;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 8 * pass;
+        hipLaunchKernelGGL(k_rs_count, dim3(T, B), dim3(kRsBlock), 0, st, kin, N, T, shift, sc->sp_cnt);
+        GP_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_rs_scan, dim3(B), dim3(1024), 0, st, sc->sp_cnt, T);
+        GP_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_rs_scatter, dim3(T, B), dim3(kRsBlock), 0, st, kin, vin, kout, vout, N, T, shift,
+                           sc->sp_cnt);
+        GP_HIP(hipGetLastError());
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+    }
+    return GP_OK;
+}
+
+// Spearman fitness (Sec. III-C3): programs in batches of B are evaluated,
+// ranked by a sort, and correlated with the target's ranks.
+gp_status spearman_impl(DeviceScratch* sc, const gp_population_dev* pop, const gp_dataset_dev* data,
+                        float* fitness, hipStream_t st) {
+    const int64_t N = data->n_rows;
+    const int32_t P = pop->n_programs;
+    if (N >= (int64_t{1} << 31)) return fail(GP_ERR_INVALID_ARG, "gp_fitness: Spearman needs n_rows below 2^31");
+    const int32_t T = static_cast<int32_t>((N + kRsTile - 1) / kRsTile);
+    // working set per program: outputs, keys and indices twice, run starts
+    const int64_t budget = int64_t{4} << 30;
+    const int32_t B = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(P, budget / (24 * N))));
+    const size_t BN = static_cast<size_t>(B) * static_cast<size_t>(N);
+    gp_status rc = GP_OK;
+    auto need = [&](void** ptr, size_t* cap, size_t n, size_t elem) {
+        if (rc == GP_OK) rc = grow(ptr, cap, n, elem);
+    };
+    need(reinterpret_cast<void**>(&sc->sp_out), &sc->sp_out_cap, BN, sizeof(float));
+    need(reinterpret_cast<void**>(&sc->sp_k0), &sc->sp_k0_cap, BN, sizeof(uint32_t));
+    need(reinterpret_cast<void**>(&sc->sp_k1), &sc->sp_k1_cap, BN, sizeof(uint32_t));
+    need(reinterpret_cast<void**>(&sc->sp_v0), &sc->sp_v0_cap, BN, sizeof(uint32_t));
+    need(reinterpret_cast<void**>(&sc->sp_v1), &sc->sp_v1_cap, BN, sizeof(uint32_t));
+    need(reinterpret_cast<void**>(&sc->sp_rs), &sc->sp_rs_cap, BN, sizeof(uint32_t));
+    need(reinterpret_cast<void**>(&sc->sp_cnt), &sc->sp_cnt_cap, static_cast<size_t>(B) * kRsRadix * T,
+         sizeof(uint32_t));
+    need(reinterpret_cast<void**>(&sc->sp_r2y), &sc->sp_r2y_cap, static_cast<size_t>(N), sizeof(uint32_t));
+    need(reinterpret_cast<void**>(&sc->sp_nan), &sc->sp_nan_cap, static_cast<size_t>(B), sizeof(int32_t));
+    if (rc != GP_OK) return rc;
+    auto fill_nan_flags = [&](int32_t n) -> gp_status {
+        hipLaunchKernelGGL(k_fill_i32, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, sc->sp_nan,
+                           static_cast<int64_t>(n), 0);
+        GP_HIP(hipGetLastError());
+        return GP_OK;
+    };
+    const int key_blocks = static_cast<int>(std::min<int64_t>((static_cast<int64_t>(BN) + kRsBlock - 1) / kRsBlock,
+                                                              int64_t{1} << 16));
+    // the target's ranks (twice the mean rank of each row)
+    if ((rc = fill_nan_flags(1)) != GP_OK) return rc;
+    hipLaunchKernelGGL(k_spear_keys, dim3(static_cast<unsigned>(std::min<int64_t>((N + kRsBlock - 1) / kRsBlock,
+                                                                                  int64_t{1} << 16))),
+                       dim3(kRsBlock), 0, st, data->y, N, 1, sc->sp_k0, sc->sp_v0, sc->sp_nan);
+    GP_HIP(hipGetLastError());
+    if ((rc = radix_sort_segments(sc, N, 1, st)) != GP_OK) return rc;
+    hipLaunchKernelGGL(k_spear_ranks<0>, dim3(1), dim3(1024), 0, st, sc->sp_k0, sc->sp_v0, N, sc->sp_rs,
+                       sc->sp_r2y, nullptr, nullptr, nullptr, nullptr, 0);
+    GP_HIP(hipGetLastError());
+    for (int32_t p0 = 0; p0 < P; p0 += B) {
+        const int32_t b = std::min(B, P - p0);
+        gp_population_dev view = *pop;
+        view.prog_off = pop->prog_off + p0;
+        view.const_off = pop->const_off + p0;
+        view.len = pop->len + p0;
+        view.n_programs = b;
+        PopView pv;
+        CodeView cvw;
+        DataView dv;
+        Sched sch;
+        LaunchCfg cfg;
+        rc = prepare(sc, &view, data, 0, GP_METRIC_MSE, st, nullptr, &pv, &cvw, &dv, &sch, &cfg);
+        if (rc != GP_OK) return rc;
+        rc = launch_eval(0, GP_METRIC_MSE, cfg, sc->n_cu, pv, cvw, dv, sch, sc->sp_out, nullptr, st, 0, Timing{});
+        if (rc != GP_OK) return rc;
+        if ((rc = fill_nan_flags(b)) != GP_OK) return rc;
+        hipLaunchKernelGGL(k_spear_keys, dim3(key_blocks), dim3(kRsBlock), 0, st, sc->sp_out, N, b, sc->sp_k0,
+                           sc->sp_v0, sc->sp_nan);
+        GP_HIP(hipGetLastError());
+        if ((rc = radix_sort_segments(sc, N, b, st)) != GP_OK) return rc;
+        hipLaunchKernelGGL(k_spear_ranks<1>, dim3(b), dim3(1024), 0, st, sc->sp_k0, sc->sp_v0, N, sc->sp_rs,
+                           nullptr, sc->sp_r2y, data->w, sc->sp_nan, fitness, p0);
+        GP_HIP(hipGetLastError());
+    }
+    return GP_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Autotuner: times candidate configurations of the fitness kernel on a prefix
 // of at most kTuneRows rows and keeps the fastest for the full shape.
@@ -1546,29 +1980,34 @@ gp_status autotune_impl(DeviceScratch* sc, const gp_population_dev* pop, const g
     GP_HIP(hipEventCreate(&b));
     LaunchCfg best = h;
     double best_ms = -1.0;
+    auto trial = [&](const LaunchCfg& c) {
+        int64_t chunk = 0, n_chunks = 0;
+        if (chunking(pop, data, c, &chunk, &n_chunks) != GP_OK) return;   // does not fit this shape
+        double ms_min = -1.0;
+        for (int rep = 0; rep <= repeats && rc == GP_OK; ++rep) {
+            rc = hipEventRecord(a, st) == hipSuccess ? GP_OK : GP_ERR_DEVICE;
+            if (rc == GP_OK) rc = fitness_impl(sc, pop, &sub, metric, sc->fit_tmp, st, &c, Timing{});
+            if (rc == GP_OK) rc = hipEventRecord(b, st) == hipSuccess ? GP_OK : GP_ERR_DEVICE;
+            if (rc == GP_OK) rc = hipEventSynchronize(b) == hipSuccess ? GP_OK : GP_ERR_DEVICE;
+            float ms = 0.0f;
+            if (rc == GP_OK) rc = hipEventElapsedTime(&ms, a, b) == hipSuccess ? GP_OK : GP_ERR_DEVICE;
+            if (rc == GP_OK && rep > 0 && (ms_min < 0.0 || ms < ms_min)) ms_min = ms;  // rep 0 warms up
+        }
+        if (rc == GP_OK && ms_min >= 0.0 && (best_ms < 0.0 || ms_min < best_ms)) {
+            best_ms = ms_min;
+            best = c;
+        }
+    };
+    // stage 1: rows per lane, feature registers, rows per work item (keeping
+    // the heuristic's rows per item within a factor of 4), 4 waves per block
     for (int R : {1, 2, 4})
         for (int fr : fregs)
-            for (int t : tiles) {
-                // keep the rows per work item of the heuristic within a factor of 4
-                const LaunchCfg c{R, fr, std::max(1, t * 4 / R)};
-                int64_t chunk = 0, n_chunks = 0;
-                if (chunking(pop, data, c, &chunk, &n_chunks) != GP_OK) continue;
-                double ms_min = -1.0;
-                for (int rep = 0; rep <= repeats && rc == GP_OK; ++rep) {
-                    rc = hipEventRecord(a, st) == hipSuccess ? GP_OK : GP_ERR_DEVICE;
-                    if (rc == GP_OK) rc = fitness_impl(sc, pop, &sub, metric, sc->fit_tmp, st, &c, Timing{});
-                    if (rc == GP_OK) rc = hipEventRecord(b, st) == hipSuccess ? GP_OK : GP_ERR_DEVICE;
-                    if (rc == GP_OK) rc = hipEventSynchronize(b) == hipSuccess ? GP_OK : GP_ERR_DEVICE;
-                    float ms = 0.0f;
-                    if (rc == GP_OK) rc = hipEventElapsedTime(&ms, a, b) == hipSuccess ? GP_OK : GP_ERR_DEVICE;
-                    if (rc == GP_OK && rep > 0 && (ms_min < 0.0 || ms < ms_min)) ms_min = ms;  // rep 0 warms up
-                }
-                if (rc != GP_OK) break;
-                if (ms_min >= 0.0 && (best_ms < 0.0 || ms_min < best_ms)) {
-                    best_ms = ms_min;
-                    best = c;
-                }
-            }
+            for (int t : tiles)
+                if (rc == GP_OK) trial(LaunchCfg{R, fr, std::max(1, t * 4 / R), 4});
+    // stage 2: the block size for the best of stage 1
+    const LaunchCfg s1 = best;
+    for (int wpb : {1, 2})
+        if (rc == GP_OK) trial(LaunchCfg{s1.R, s1.freg, s1.tiles, wpb});
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     if (rc != GP_OK) return rc == GP_ERR_DEVICE ? fail(GP_ERR_DEVICE, "autotune: a timed launch failed") : rc;
@@ -1757,7 +2196,7 @@ gp_status gp_get_launch_config(int32_t n_features, int64_t n_rows, int32_t n_pro
     rc = arena(&sc);
     if (rc != GP_OK) return rc;
     const LaunchCfg c = pick_cfg(*sc, n_features, n_rows, n_programs, kernel_class(1, metric));
-    *out = gp_launch_config{c.R, c.freg, c.tiles};
+    *out = gp_launch_config{c.R, c.freg, c.tiles, c.wpb};
     return GP_OK;
 }
 
@@ -1767,10 +2206,10 @@ gp_status gp_set_launch_config(const gp_launch_config* cfg) {
         g_forced = false;
         return GP_OK;
     }
-    const LaunchCfg c{cfg->rows_per_lane, cfg->feature_regs, cfg->tiles_per_chunk};
+    const LaunchCfg c{cfg->rows_per_lane, cfg->feature_regs, cfg->tiles_per_chunk, cfg->waves_per_block};
     if (!cfg_valid(c))
         return fail(GP_ERR_INVALID_ARG, "gp_set_launch_config: rows_per_lane in {1,2,4}, feature_regs in {0,2,8}, "
-                                        "tiles_per_chunk in [1, 2^20]");
+                                        "tiles_per_chunk in [1, 2^20], waves_per_block in {1,2,4}");
     g_forced_cfg = c;
     g_forced = true;
     return GP_OK;
@@ -1793,7 +2232,7 @@ gp_status gp_autotune(const gp_population_dev* pop, const gp_dataset_dev* data, 
     LaunchCfg c{};
     rc = autotune_impl(sc, pop, data, metric, repeats, static_cast<hipStream_t>(stream), &c, best_ms);
     if (rc != GP_OK) return rc;
-    if (best) *best = gp_launch_config{c.R, c.freg, c.tiles};
+    if (best) *best = gp_launch_config{c.R, c.freg, c.tiles, c.wpb};
     return GP_OK;
 }
 
@@ -1808,9 +2247,9 @@ gp_status gp_autotune_save(const char* path) {
         std::fprintf(f,
                      "{\"arch\": \"%s\", \"n_cu\": %d, \"n_features\": %d, \"n_rows\": %lld, \"n_programs\": %d, "
                      "\"kernel\": %d, \"rows_per_lane\": %d, \"feature_regs\": %d, \"tiles_per_chunk\": %d, "
-                     "\"ms\": %.6f}\n",
+                     "\"waves_per_block\": %d, \"ms\": %.6f}\n",
                      k.arch.c_str(), k.n_cu, k.F, static_cast<long long>(k.N), k.P, k.kclass, v.cfg.R, v.cfg.freg,
-                     v.cfg.tiles, v.ms);
+                     v.cfg.tiles, v.cfg.wpb, v.ms);
     }
     const bool ok = std::fclose(f) == 0;
     return ok ? GP_OK : fail(GP_ERR_INVALID_ARG, "gp_autotune_save: write failed");
@@ -1829,16 +2268,16 @@ gp_status gp_autotune_load(const char* path) {
         ++lineno;
         if (line[0] == '\n' || line[0] == '\0') continue;
         char arch[64] = {0};
-        int n_cu = 0, F = 0, P = 0, kc = 0, R = 0, fr = 0, t = 0;
+        int n_cu = 0, F = 0, P = 0, kc = 0, R = 0, fr = 0, t = 0, wpb = 0;
         long long N = 0;
         double ms = 0.0;
         const int n = std::sscanf(line,
                                   "{\"arch\": \"%63[^\"]\", \"n_cu\": %d, \"n_features\": %d, \"n_rows\": %lld, "
                                   "\"n_programs\": %d, \"kernel\": %d, \"rows_per_lane\": %d, \"feature_regs\": %d, "
-                                  "\"tiles_per_chunk\": %d, \"ms\": %lf}",
-                                  arch, &n_cu, &F, &N, &P, &kc, &R, &fr, &t, &ms);
-        const LaunchCfg c{R, fr, t};
-        if (n != 10 || !cfg_valid(c) || F < 1 || N < 1 || P < 0 || kc < 0 || kc > 4 ||
+                                  "\"tiles_per_chunk\": %d, \"waves_per_block\": %d, \"ms\": %lf}",
+                                  arch, &n_cu, &F, &N, &P, &kc, &R, &fr, &t, &wpb, &ms);
+        const LaunchCfg c{R, fr, t, wpb};
+        if (n != 11 || !cfg_valid(c) || F < 1 || N < 1 || P < 0 || kc < 0 || kc > 4 ||
             (c.freg > 0 && F > c.freg)) {
             bad = true;
             break;
@@ -1923,12 +2362,14 @@ gp_status gp_fitness(const gp_population_dev* pop, const gp_dataset_dev* data, g
     rc = check_data(data, "gp_fitness", true);
     if (rc != GP_OK) return rc;
     if (!fitness) return fail(GP_ERR_INVALID_ARG, "gp_fitness: fitness is NULL");
-    rc = check_fitness_metric(metric, "gp_fitness");
+    rc = check_fitness_metric(metric, "gp_fitness", true);
     if (rc != GP_OK) return rc;
     if (pop->n_programs == 0) return GP_OK;
     DeviceScratch* sc;
     rc = arena(&sc);
     if (rc != GP_OK) return rc;
+    if (metric == GP_METRIC_SPEARMAN)
+        return spearman_impl(sc, pop, data, fitness, static_cast<hipStream_t>(stream));
     Timing tm;
     tm.profile = true;
     return fitness_impl(sc, pop, data, metric, fitness, static_cast<hipStream_t>(stream), nullptr, tm);
@@ -2116,7 +2557,7 @@ gp_status gp_generation_info(const gp_generation* g, gp_launch_config* cfg, floa
                              int32_t* timed_by_events, double* tuned_ms) {
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g) return fail(GP_ERR_INVALID_ARG, "gp_generation_info: NULL generation");
-    if (cfg) *cfg = gp_launch_config{g->cfg.R, g->cfg.freg, g->cfg.tiles};
+    if (cfg) *cfg = gp_launch_config{g->cfg.R, g->cfg.freg, g->cfg.tiles, g->cfg.wpb};
     if (kernel_ms) *kernel_ms = g->kernel_ms;
     if (clock_ms) *clock_ms = g->clock_ms;
     if (timed_by_events) *timed_by_events = g->events ? 1 : 0;

@@ -48,7 +48,8 @@ def all_pairs(P, N):
     return prog, row
 
 
-CONFIGS = [None, (1, 0, 1), (1, 2, 3), (2, 2, 2), (2, 8, 1), (4, 0, 5), (4, 2, 1), (4, 8, 2)]
+CONFIGS = [None, (1, 0, 1), (1, 2, 3), (2, 2, 2), (2, 8, 1), (4, 0, 5), (4, 2, 1), (4, 8, 2),
+           (1, 2, 3, 1), (2, 0, 2, 2), (4, 8, 3, 1)]   # last: waves per block
 
 
 @pytest.mark.parametrize("cfg", CONFIGS)

@@ -1,0 +1,111 @@
+"""GPU parity of Spearman fitness (Sec. III-C3: the rank correlation whose
+ranks come from a sort) against the oracle's Spearman.
+
+The two sides rank their own float32 outputs, which may differ by a few
+ulps wherever a transcendental sits in the program; rows whose values are
+that close may then be ordered (or tied) differently.  The oracle bounds the
+effect (the components of rows whose value intervals overlap); a program's
+fitness must agree within 1e-6 relative plus that bound.  Programs of
+correctly rounded operations have a zero bound and must agree to float32
+rounding of the same float64 result."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from _parity import to_oracle
+
+pytestmark = pytest.mark.gpu
+NT = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def gp():
+    import torch
+    import paper_2110_11226_amd as gp
+    torch.cuda.set_device(0)
+    return gp
+
+
+def gpu_spearman(gp, host, X, y, w, F):
+    import torch
+    pop = gp.DevicePopulation(host, n_features=F)
+    data = gp.DeviceDataset(X, y, w)
+    f = gp.fitness(pop, data, "spearman")
+    torch.cuda.synchronize()
+    return f.cpu().numpy().astype(np.float64)
+
+
+def check(got, f32p, fb, fn, label):
+    tight = 0
+    for p in range(len(got)):
+        if fn[p]:
+            continue            # a protected predicate near its threshold
+        if np.isnan(f32p[p]):
+            assert np.isnan(got[p]), (label, p)
+            continue
+        tol = 1e-6 * abs(f32p[p]) + 1e-7 + fb[p]
+        assert abs(got[p] - f32p[p]) <= tol, (label, p, got[p], f32p[p], fb[p])
+        tight += fb[p] == 0.0
+    return tight
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_spearman_rhh_population(gp, weighted):
+    N = 4096 + 77
+    X, y = synth.pagie(N, seed=11227)
+    w = synth.weights(N, seed=3) if weighted else None
+    host = gp.build_population(256, 2, "rhh", min_depth=2, max_depth=6, seed=2111)
+    got = gpu_spearman(gp, host, X, y, w, 2)
+    f32p, f64, fb, fn = oracle.fitness(to_oracle(host), X, y, w, "spearman", n_threads=NT, with_bound=True)
+    tight = check(got, f32p, fb, fn, f"rhh w={weighted}")
+    print(f"spearman rhh weighted={weighted}: {tight} programs with a zero bound")
+    assert tight >= 40
+
+
+def test_spearman_ties_everywhere(gp):
+    # integer features and a coarse target: most values tie on both sides
+    rng = np.random.default_rng(5)
+    N = 3000
+    X = rng.integers(-4, 5, size=(2, N)).astype(np.float32)
+    y = np.round(rng.normal(size=N) * 2).astype(np.float32)
+    fmask = sum(1 << o for o in (oracle.ADD, oracle.SUB, oracle.MUL, oracle.NEG))
+    host = gp.build_population(200, 2, "exact_len", min_len=1, max_len=40, function_mask=fmask, seed=9)
+    got = gpu_spearman(gp, host, X, y, None, 2)
+    f32p, f64, fb, fn = oracle.fitness(to_oracle(host), X, y, None, "spearman", n_threads=NT, with_bound=True)
+    # exact arithmetic on small integers: identical values, ranks and ties on both sides
+    assert np.all(fb == 0.0)
+    assert np.allclose(got, f32p, rtol=1e-6, atol=1e-7)
+    assert np.sum(f32p == 0.0) >= 1            # constant programs exist
+
+
+def test_spearman_nan_and_constant_programs(gp):
+    N = 1000
+    X, y = synth.pagie(N, seed=4)
+    X = X.copy()
+    X[0, 17] = np.nan
+    progs = [([oracle.node(oracle.VAR, 0)], []), ([oracle.node(oracle.VAR, 1)], []),
+             ([oracle.node(oracle.CONST, 0)], [2.0]),
+             ([oracle.node(oracle.MUL), oracle.node(oracle.VAR, 1), oracle.node(oracle.VAR, 1)], [])]
+    op = oracle.from_programs(progs)
+    host = gp.HostPopulation(op.nodes, op.prog_off, op.consts, op.const_off, op.length)
+    got = gpu_spearman(gp, host, X, y, None, 2)
+    f32p, _ = oracle.fitness(op, X, y, None, "spearman")
+    assert np.isnan(got[0]) and np.isnan(f32p[0])
+    assert got[2] == 0.0 and f32p[2] == 0.0
+    assert np.allclose(got[[1, 3]], f32p[[1, 3]], rtol=1e-6)
+
+
+@pytest.mark.parametrize("N", [1, 2, 63, 4097, 1_500_000])
+def test_spearman_sizes_and_batches(gp, N):
+    """Ragged tiles, tiny inputs and, at 1.5M rows, several program batches
+    (the sort works on at most 4 GiB of outputs and keys at a time)."""
+    X, y = synth.pagie(N, seed=N)
+    fmask = sum(1 << o for o in (oracle.ADD, oracle.SUB, oracle.MUL, oracle.DIV, oracle.NEG, oracle.SQRT))
+    P = 160 if N > 100_000 else 48
+    host = gp.build_population(P, 2, "rhh", min_depth=1, max_depth=5, function_mask=fmask, seed=7)
+    got = gpu_spearman(gp, host, X, y, None, 2)
+    f32p, f64, fb, fn = oracle.fitness(to_oracle(host), X, y, None, "spearman", n_threads=NT, with_bound=True)
+    check(got, f32p, fb, fn, f"N={N}")
