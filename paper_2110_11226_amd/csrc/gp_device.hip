@@ -206,14 +206,21 @@ __device__ __forceinline__ void apply_unary(uint32_t fn, float (&t)[R]) {
 // evaluation order of Sec. III-A) and emits instructions in that order.  A
 // terminal at position i is the first operand of the function at i-1 exactly
 // when that function is binary (its first operand starts right after it), so
-// such pairs become one kFold instruction.  A shadow stack (in LDS, one
-// column per lane) tracks, for each value on the evaluation stack, the first
-// instruction of the subtree that produced it and whether that subtree holds
-// a constant; each instruction records both (bit kActive, word y).
+// such pairs become one kFold instruction; a unary function is chained onto
+// the instruction before it.  A shadow stack (in LDS, one column per lane)
+// tracks, for each value on the evaluation stack, the first instruction of
+// the subtree that produced it, whether that subtree holds a constant, and
+// whether it holds nothing but constants.  With `fold`, a subtree of
+// constants only is evaluated here, once, by the same float32 functions the
+// evaluation kernel applies per row (so every row would get these very
+// bits), and its instructions are replaced by one push of the result.
 // ---------------------------------------------------------------------------
+constexpr uint32_t kShStartMask = 0x3fffffffu;   // shadow entry: start | const-only << 30 | active << 31
+
 __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint4* __restrict__ code,
-                                                     int32_t* __restrict__ clen) {
-    __shared__ uint32_t shadow[GP_MAX_STACK][kBlock];   // start | active << 31
+                                                     int32_t* __restrict__ clen, int fold) {
+    __shared__ uint32_t shadow[GP_MAX_STACK][kBlock];
+    __shared__ float shadow_v[GP_MAX_STACK][kBlock];   // value of a const-only entry
     const int32_t p = static_cast<int32_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (p >= pop.P) return;
     const int64_t off = pop.prog_off[p];
@@ -222,6 +229,7 @@ __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint4* __restri
     const float* pc = pop.consts + pop.const_off[p];
     uint4* out = code + off;
     uint32_t* sh = &shadow[0][threadIdx.x];   // entry h at sh[h * kBlock]
+    float* shv = &shadow_v[0][threadIdx.x];
     int h = 0;                                // shadow stack height
     int32_t k = 0;                            // instructions emitted
     uint4 pend = make_uint4(0u, 0u, 0u, 0u);  // the last instruction, still open for a unary chain
@@ -230,6 +238,15 @@ __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint4* __restri
         const uint32_t w = pn[i];
         const uint32_t op = w & 0xffu;
         const uint32_t arg = w >> 8;
+        const int top_i = min(max(h - 1, 0), GP_MAX_STACK - 1);
+        if (op > GP_OP_DIV && fold && h >= 1 && ((sh[top_i * kBlock] >> 30) & 1u)) {
+            // unary of a constant: the pending instruction is that constant's push
+            float t[1] = {shv[top_i * kBlock]};
+            apply_unary<1>(op - GP_OP_NEG, t);
+            shv[top_i * kBlock] = t[0];
+            pend.y = __float_as_uint(t[0]);
+            continue;
+        }
         if (op > GP_OP_DIV && chain >= 0 && chain < 8) {
             // a unary function applied to the pending instruction's result:
             // same subtree start and activity as its operand
@@ -237,39 +254,69 @@ __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint4* __restri
             ++chain;
             continue;
         }
-        uint32_t x, start, active;
+        uint32_t x, start, active, konst = 0u;
+        float kval = 0.0f;
         uint2 xy;
         if (op <= GP_OP_CONST) {
             const uint32_t is_c = op == GP_OP_CONST ? 1u : 0u;
             const uint32_t farg = arg;   // feature index, or constant slot (used by the adjoint)
             const uint32_t prev = i >= 1 ? (pn[i - 1] & 0xffu) : 0u;
             if (i >= 1 && i != L - 1 && prev >= GP_OP_ADD && prev <= GP_OP_DIV) {
-                const uint32_t top = sh[max(h - 1, 0) * kBlock];    // the second operand
-                x = enc(kFold, prev - GP_OP_ADD, is_c, farg);
-                start = top & 0x7fffffffu;
-                active = is_c | (top >> 31);
+                const uint32_t top = sh[top_i * kBlock];    // the second operand
+                start = top & kShStartMask;
+                if (fold && is_c && ((top >> 30) & 1u)) {
+                    // constant op constant: evaluated here
+                    float a[1] = {pc[arg]};
+                    const float b[1] = {shv[top_i * kBlock]};
+                    apply_binary<1>(prev - GP_OP_ADD, a, b);
+                    x = enc(kPush, 0, 1u, 0u);
+                    active = 1u;
+                    konst = 1u;
+                    kval = a[0];
+                    k = static_cast<int32_t>(start);   // drop the operand's instructions
+                    chain = -1;
+                } else {
+                    x = enc(kFold, prev - GP_OP_ADD, is_c, farg);
+                    active = is_c | (top >> 31);
+                }
                 --h;
                 --i;
             } else {
                 x = enc(kPush, 0, is_c, farg);
                 start = static_cast<uint32_t>(k);
                 active = is_c;
+                konst = is_c;
+                kval = is_c ? pc[arg] : 0.0f;
             }
-            xy = is_c ? make_uint2(x | kActive, __float_as_uint(pc[arg]))
-                      : make_uint2(x | (active ? kActive : 0u), start);
+            xy = (is_c || konst) ? make_uint2(x | kActive, __float_as_uint(konst ? kval : pc[arg]))
+                                 : make_uint2(x | (active ? kActive : 0u), start);
         } else if (op <= GP_OP_DIV) {
-            const uint32_t first = sh[max(h - 1, 0) * kBlock];     // top: the first operand
-            const uint32_t second = sh[max(h - 2, 0) * kBlock];    // evaluated before it
-            x = enc(kBin, op - GP_OP_ADD, 0, 0);
-            start = second & 0x7fffffffu;
-            active = (first >> 31) | (second >> 31);
+            const int i1 = min(max(h - 1, 0), GP_MAX_STACK - 1), i2 = min(max(h - 2, 0), GP_MAX_STACK - 1);
+            const uint32_t first = sh[i1 * kBlock];      // top: the first operand
+            const uint32_t second = sh[i2 * kBlock];     // evaluated before it
+            start = second & kShStartMask;
             h -= 2;
-            xy = make_uint2(x | (active ? kActive : 0u), start);
+            if (fold && ((first >> 30) & 1u) && ((second >> 30) & 1u)) {
+                float a[1] = {shv[i1 * kBlock]};
+                const float b[1] = {shv[i2 * kBlock]};
+                apply_binary<1>(op - GP_OP_ADD, a, b);
+                x = enc(kPush, 0, 1u, 0u);
+                active = 1u;
+                konst = 1u;
+                kval = a[0];
+                k = static_cast<int32_t>(start);
+                chain = -1;
+                xy = make_uint2(x | kActive, __float_as_uint(kval));
+            } else {
+                x = enc(kBin, op - GP_OP_ADD, 0, 0);
+                active = (first >> 31) | (second >> 31);
+                xy = make_uint2(x | (active ? kActive : 0u), start);
+            }
         } else {
             // a unary function with a full chain before it: its own instruction
-            const uint32_t top = sh[max(h - 1, 0) * kBlock];
+            const uint32_t top = sh[top_i * kBlock];
             x = enc(kUn, op - GP_OP_NEG, 0, 0);
-            start = top & 0x7fffffffu;
+            start = top & kShStartMask;
             active = top >> 31;
             --h;
             xy = make_uint2(x | (active ? kActive : 0u), start);
@@ -280,7 +327,9 @@ __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint4* __restri
         // (valid programs keep 1 <= h <= GP_MAX_STACK; the clamps only keep an
         // invalid one inside this array)
         h = max(h, 0);
-        sh[min(h, GP_MAX_STACK - 1) * kBlock] = start | (active << 31);
+        const int hi = min(h, GP_MAX_STACK - 1);
+        sh[hi * kBlock] = start | (konst << 30) | (active << 31);
+        shv[hi * kBlock] = kval;
         ++h;
         ++k;
     }
@@ -1787,7 +1836,7 @@ gp_status chunking(const gp_population_dev* pop, const gp_dataset_dev* data, con
 // the configuration choice.
 gp_status prepare(DeviceScratch* sc, const gp_population_dev* pop, const gp_dataset_dev* data, int mode,
                   int metric, hipStream_t st, const LaunchCfg* force, PopView* pv, CodeView* cvw, DataView* dv,
-                  Sched* sch, LaunchCfg* cfg) {
+                  Sched* sch, LaunchCfg* cfg, bool fold = true) {
     *pv = PopView{pop->nodes, pop->prog_off, pop->consts, pop->const_off, pop->len, pop->n_programs};
     *dv = DataView{data->X, data->ld, data->n_features, data->n_rows, data->y, data->w};
     *cfg = force ? *force
@@ -1803,7 +1852,7 @@ gp_status prepare(DeviceScratch* sc, const gp_population_dev* pop, const gp_data
                        static_cast<uint32_t*>(sc->counter));
     GP_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_compile, dim3((pop->n_programs + kBlock - 1) / kBlock), dim3(kBlock), 0, st, *pv,
-                       sc->code, sc->clen);
+                       sc->code, sc->clen, fold ? 1 : 0);
     GP_HIP(hipGetLastError());
     *cvw = CodeView{sc->code, sc->clen};
     return GP_OK;
@@ -2600,7 +2649,8 @@ gp_status gp_fitness_backward(const gp_population_dev* pop, const gp_dataset_dev
     DataView dv;
     Sched sch;
     LaunchCfg cfg;
-    rc = prepare(sc, pop, data, 1, metric, st, nullptr, &pv, &cvw, &dv, &sch, &cfg);
+    // no constant folding: every constant carries its own derivative
+    rc = prepare(sc, pop, data, 1, metric, st, nullptr, &pv, &cvw, &dv, &sch, &cfg, false);
     if (rc != GP_OK) return rc;
     const int32_t P = pop->n_programs;
     const int64_t nc = std::max<int64_t>(pop->total_consts, 1);
