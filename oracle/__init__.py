@@ -24,16 +24,26 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 # opcodes as the oracle reads them (op in bits 0-7, argument in bits 8-31)
 VAR, CONST, ADD, SUB, MUL, DIV, NEG, LOG, SQRT, SIN, COS, TAN = range(12)
+MAX, MIN, ATAN2 = 12, 13, 14
+ABS, EXP, INV, SQ, CUBE, TANH, ATAN, CBRT = range(15, 23)
 ARITY = {VAR: 0, CONST: 0, ADD: 2, SUB: 2, MUL: 2, DIV: 2,
-         NEG: 1, LOG: 1, SQRT: 1, SIN: 1, COS: 1, TAN: 1}
+         NEG: 1, LOG: 1, SQRT: 1, SIN: 1, COS: 1, TAN: 1,
+         MAX: 2, MIN: 2, ATAN2: 2,
+         ABS: 1, EXP: 1, INV: 1, SQ: 1, CUBE: 1, TANH: 1, ATAN: 1, CBRT: 1}
+# every function: the nine of the benchmark configurations, tan, and the wider set
+ALL_FMASK = sum(1 << op for op, a in ARITY.items() if a > 0)
 METRICS = {"mae": 0, "mse": 1, "rmse": 2, "logloss": 3, "pearson": 4, "spearman": 5}
 LARGER_IS_BETTER = {0: 0, 1: 0, 2: 0, 3: 0, 4: 1}
 INIT = {"rhh": 0, "full": 1, "grow": 2, "exact_len": 3}
 # the nine-function set used by the Pagie / classification workloads
 DEFAULT_FMASK = sum(1 << op for op in (ADD, SUB, MUL, DIV, NEG, LOG, SQRT, SIN, COS))
-# relative allowance for a sin/cos/tan/log result in the conditioning bound:
+# relative allowance for a library-function result in the conditioning bound:
 # 4 float32 ulps (an ulp of v is at most 2^-23 |v|)
 ULP_ALLOWANCE = 4.0 * 2.0 ** -23
+# the spacing of float32 relative to |v| (at most): a correctly rounded
+# operation whose operands differ between two evaluations may round to
+# neighbouring floats, one spacing apart
+ROUND_FLIP = 2.0 ** -23
 
 
 def build(force: bool = True) -> str:
@@ -53,7 +63,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        if not os.path.exists(_LIB) or os.path.getmtime(_SRC) > os.path.getmtime(_LIB):
             build(force=True)
         L = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
@@ -63,10 +73,10 @@ def lib():
         L.orc_check_program.restype = ctypes.c_int
         L.orc_evaluate_f32.argtypes = [P, P, P, P, i32, P, i64, i64, P, ctypes.c_int]
         L.orc_evaluate_f64.argtypes = [P, P, P, P, i32, P, i64, i64, P, ctypes.c_int]
-        L.orc_evaluate_pairs.argtypes = [P, P, P, P, P, i64, P, P, i64, ctypes.c_double, P, P, P, P,
-                                         ctypes.c_int]
-        L.orc_fitness.argtypes = [P, P, P, P, i32, P, i64, i64, P, P, i32, P, P, ctypes.c_double, P, P,
-                                  ctypes.c_int]
+        L.orc_evaluate_pairs.argtypes = [P, P, P, P, P, i64, P, P, i64, ctypes.c_double, ctypes.c_double,
+                                         P, P, P, P, ctypes.c_int]
+        L.orc_fitness.argtypes = [P, P, P, P, i32, P, i64, i64, P, P, i32, P, P, ctypes.c_double,
+                                  ctypes.c_double, P, P, ctypes.c_int]
         L.orc_philox4x32_10.argtypes = [P, P, P]
         L.orc_philox_words.argtypes = [u64, u32, u32, u32, u32, u32, P]
         L.orc_tournament.argtypes = [P, P, i32, i32, f32, i32, i32, u64, u64, P]
@@ -177,7 +187,8 @@ class RowAnalysis:
     near: np.ndarray     # a protected predicate lies within its bound of the threshold
 
 
-def evaluate_pairs(pop: Population, X, prog, row, n_threads=None, u=ULP_ALLOWANCE) -> RowAnalysis:
+def evaluate_pairs(pop: Population, X, prog, row, n_threads=None, u=ULP_ALLOWANCE,
+                   rf=ROUND_FLIP) -> RowAnalysis:
     """Float32 and float64 values and the conditioning analysis of each
     (prog[i], row[i]) pair (see row_analysis in gp_oracle.c)."""
     X, N = _ds(X)
@@ -189,13 +200,13 @@ def evaluate_pairs(pop: Population, X, prog, row, n_threads=None, u=ULP_ALLOWANC
     eb = np.empty(n, np.float64)
     fl = np.empty(n, np.uint8)
     lib().orc_evaluate_pairs(_p(pop.nodes), _p(pop.prog_off), _p(pop.consts),
-                             _p(pop.const_off), _p(X), N, _p(prog), _p(row), n, float(u),
+                             _p(pop.const_off), _p(X), N, _p(prog), _p(row), n, float(u), float(rf),
                              _p(o32), _p(o64), _p(eb), _p(fl), _threads(n_threads))
     return RowAnalysis(o32, o64, eb, (fl & 1).astype(bool), (fl & 2).astype(bool))
 
 
 def fitness(pop: Population, X, y, w=None, metric="mse", n_threads=None, with_f64=True,
-            with_bound=False, u=ULP_ALLOWANCE):
+            with_bound=False, u=ULP_ALLOWANCE, rf=ROUND_FLIP):
     """(fitness from the float32 program values, fitness with every step in
     float64), as float64 arrays; the float32 result the library must match is
     the first one rounded to float32.  With with_bound=True also returns the
@@ -212,7 +223,7 @@ def fitness(pop: Population, X, y, w=None, metric="mse", n_threads=None, with_f6
     fn = np.empty(pop.n_programs, np.int32) if with_bound else None
     lib().orc_fitness(_p(pop.nodes), _p(pop.prog_off), _p(pop.consts), _p(pop.const_off),
                       pop.n_programs, _p(X), N, N, _p(y), _p(w), m, _p(f32p), _p(f64), float(u),
-                      _p(fb), _p(fn), _threads(n_threads))
+                      float(rf), _p(fb), _p(fn), _threads(n_threads))
     if with_bound:
         return f32p, f64, fb, fn
     return f32p, f64

@@ -14,7 +14,10 @@
  *
  * What it computes (each function cites the passage it follows):
  *   - program value of a prefix list on one row, by the right-to-left stack
- *     scan of Sec. III-A, in float32 and in float64;
+ *     scan of Sec. III-A, in float32 and in float64, over 21 functions (the
+ *     paper's experiments use +, -, *, protected /, sin, cos, tan; Sec. III-D1
+ *     counts 33 without listing them; the others here follow gplearn, the
+ *     library the paper compares against);
  *   - per-program fitness under the weighted metrics of Sec. III-C3
  *     (MAE, MSE, RMSE, logistic loss, Pearson, Spearman);
  *   - tournament selection with the parsimony penalty, Sec. III-C1,
@@ -29,6 +32,7 @@
  * against closed forms, hand-evaluated programs, brute force or an
  * independent library routine, except where a comment says "parity unpinned".
  */
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -39,7 +43,9 @@ enum {
     O_VAR = 0, O_CONST = 1,
     O_ADD = 2, O_SUB = 3, O_MUL = 4, O_DIV = 5,
     O_NEG = 6, O_LOG = 7, O_SQRT = 8, O_SIN = 9, O_COS = 10, O_TAN = 11,
-    O_NUM = 12
+    O_MAX = 12, O_MIN = 13, O_ATAN2 = 14,
+    O_ABS = 15, O_EXP = 16, O_INV = 17, O_SQ = 18, O_CUBE = 19, O_TANH = 20, O_ATAN = 21, O_CBRT = 22,
+    O_NUM = 23
 };
 #define ORC_STACK 20          /* fixed evaluation stack, Sec. III-B */
 
@@ -47,8 +53,10 @@ static int op_arity(int op)
 {
     switch (op) {
     case O_VAR: case O_CONST: return 0;
-    case O_ADD: case O_SUB: case O_MUL: case O_DIV: return 2;
-    case O_NEG: case O_LOG: case O_SQRT: case O_SIN: case O_COS: case O_TAN: return 1;
+    case O_ADD: case O_SUB: case O_MUL: case O_DIV: case O_MAX: case O_MIN: case O_ATAN2: return 2;
+    case O_NEG: case O_LOG: case O_SQRT: case O_SIN: case O_COS: case O_TAN:
+    case O_ABS: case O_EXP: case O_INV: case O_SQ: case O_CUBE: case O_TANH: case O_ATAN: case O_CBRT:
+        return 1;
     default: return -1;
     }
 }
@@ -63,6 +71,108 @@ static float psqrt_f(float a) { return sqrtf(fabsf(a)); }
 static double pdiv_d(double a, double b) { return fabs(b) > (double)ORC_EPS ? a / b : 1.0; }
 static double plog_d(double a) { return fabs(a) > (double)ORC_EPS ? log(fabs(a)) : 0.0; }
 static double psqrt_d(double a) { return sqrt(fabs(a)); }
+
+/* ---- the wider function set (reading: the paper counts its functions,
+ * Sec. III-D1, without listing them).  max / min follow IEEE maxNum /
+ * minNum (fmax / fmin: a NaN operand yields the other); atan2 takes the
+ * first operand as y; inv is protected like division (0 where |a| <=
+ * 0.001, gplearn's convention); sq is a*a and cube (a*a)*a, rounded after
+ * each product; exp, tanh, atan, cbrt are the library functions. ---- */
+static float pinv_f(float a) { return fabsf(a) > ORC_EPS ? 1.0f / a : 0.0f; }
+static double pinv_d(double a) { return fabs(a) > (double)ORC_EPS ? 1.0 / a : 0.0; }
+
+/* result of function `op` on its first operand a and (binary) second b */
+/* max / min as IEEE 754-2019 maximumNumber / minimumNumber: a NaN operand
+ * is ignored and -0 orders below +0 (C's fmax leaves the sign of a zero
+ * result open, and atan2 can see it) */
+static float max_f(float a, float b)
+{
+    if (isnan(a)) return b;
+    if (isnan(b)) return a;
+    if (a > b) return a;
+    if (b > a) return b;
+    return signbit(a) ? b : a;
+}
+static float min_f(float a, float b)
+{
+    if (isnan(a)) return b;
+    if (isnan(b)) return a;
+    if (a < b) return a;
+    if (b < a) return b;
+    return signbit(a) ? a : b;
+}
+static double max_d(double a, double b)
+{
+    if (isnan(a)) return b;
+    if (isnan(b)) return a;
+    if (a > b) return a;
+    if (b > a) return b;
+    return signbit(a) ? b : a;
+}
+static double min_d(double a, double b)
+{
+    if (isnan(a)) return b;
+    if (isnan(b)) return a;
+    if (a < b) return a;
+    if (b < a) return b;
+    return signbit(a) ? a : b;
+}
+
+static float op_f32(int op, float a, float b)
+{
+    switch (op) {
+    case O_ADD: return a + b;
+    case O_SUB: return a - b;
+    case O_MUL: return a * b;
+    case O_DIV: return pdiv_f(a, b);
+    case O_MAX: return max_f(a, b);
+    case O_MIN: return min_f(a, b);
+    case O_ATAN2: return atan2f(a, b);
+    case O_NEG: return -a;
+    case O_LOG: return plog_f(a);
+    case O_SQRT: return psqrt_f(a);
+    case O_SIN: return sinf(a);
+    case O_COS: return cosf(a);
+    case O_TAN: return tanf(a);
+    case O_ABS: return fabsf(a);
+    case O_EXP: return expf(a);
+    case O_INV: return pinv_f(a);
+    case O_SQ: return a * a;
+    case O_CUBE: { float q = a * a; return q * a; }
+    case O_TANH: return tanhf(a);
+    case O_ATAN: return atanf(a);
+    case O_CBRT: return cbrtf(a);
+    default: return NAN;
+    }
+}
+
+static double op_f64(int op, double a, double b)
+{
+    switch (op) {
+    case O_ADD: return a + b;
+    case O_SUB: return a - b;
+    case O_MUL: return a * b;
+    case O_DIV: return pdiv_d(a, b);
+    case O_MAX: return max_d(a, b);
+    case O_MIN: return min_d(a, b);
+    case O_ATAN2: return atan2(a, b);
+    case O_NEG: return -a;
+    case O_LOG: return plog_d(a);
+    case O_SQRT: return psqrt_d(a);
+    case O_SIN: return sin(a);
+    case O_COS: return cos(a);
+    case O_TAN: return tan(a);
+    case O_ABS: return fabs(a);
+    case O_EXP: return exp(a);
+    case O_INV: return pinv_d(a);
+    case O_SQ: return a * a;
+    case O_CUBE: return a * a * a;
+    case O_TANH: return tanh(a);
+    case O_ATAN: return atan(a);
+    case O_CBRT: return cbrt(a);
+    default: return NAN;
+    }
+}
 
 /* ------------------------------------------------------------------------ */
 /* Validation: right-to-left stack-height scan (Sec. III-A: the list is read  */
@@ -109,22 +219,13 @@ static float eval_row_f32(const uint32_t *nodes, int64_t len, const float *c,
     for (int64_t i = len - 1; i >= 0; --i) {
         int op = (int)(nodes[i] & 0xffu);
         uint32_t arg = nodes[i] >> 8;
-        float a, b;
-        switch (op) {
-        case O_VAR:   st[h++] = X[(int64_t)arg * ld + row]; break;
-        case O_CONST: st[h++] = c[arg]; break;
-        case O_ADD: a = st[--h]; b = st[--h]; st[h++] = a + b; break;
-        case O_SUB: a = st[--h]; b = st[--h]; st[h++] = a - b; break;
-        case O_MUL: a = st[--h]; b = st[--h]; st[h++] = a * b; break;
-        case O_DIV: a = st[--h]; b = st[--h]; st[h++] = pdiv_f(a, b); break;
-        case O_NEG:  a = st[--h]; st[h++] = -a; break;
-        case O_LOG:  a = st[--h]; st[h++] = plog_f(a); break;
-        case O_SQRT: a = st[--h]; st[h++] = psqrt_f(a); break;
-        case O_SIN:  a = st[--h]; st[h++] = sinf(a); break;
-        case O_COS:  a = st[--h]; st[h++] = cosf(a); break;
-        case O_TAN:  a = st[--h]; st[h++] = tanf(a); break;
-        default: return NAN;
-        }
+        int ar = op_arity(op);
+        if (op == O_VAR) { st[h++] = X[(int64_t)arg * ld + row]; continue; }
+        if (op == O_CONST) { st[h++] = c[arg]; continue; }
+        if (ar < 0) return NAN;
+        float a = st[--h];
+        float b = ar == 2 ? st[--h] : 0.0f;
+        st[h++] = op_f32(op, a, b);
     }
     return st[0];
 }
@@ -137,44 +238,100 @@ static double eval_row_f64(const uint32_t *nodes, int64_t len, const float *c,
     for (int64_t i = len - 1; i >= 0; --i) {
         int op = (int)(nodes[i] & 0xffu);
         uint32_t arg = nodes[i] >> 8;
-        double a, b;
-        switch (op) {
-        case O_VAR:   st[h++] = (double)X[(int64_t)arg * ld + row]; break;
-        case O_CONST: st[h++] = (double)c[arg]; break;
-        case O_ADD: a = st[--h]; b = st[--h]; st[h++] = a + b; break;
-        case O_SUB: a = st[--h]; b = st[--h]; st[h++] = a - b; break;
-        case O_MUL: a = st[--h]; b = st[--h]; st[h++] = a * b; break;
-        case O_DIV: a = st[--h]; b = st[--h]; st[h++] = pdiv_d(a, b); break;
-        case O_NEG:  a = st[--h]; st[h++] = -a; break;
-        case O_LOG:  a = st[--h]; st[h++] = plog_d(a); break;
-        case O_SQRT: a = st[--h]; st[h++] = psqrt_d(a); break;
-        case O_SIN:  a = st[--h]; st[h++] = sin(a); break;
-        case O_COS:  a = st[--h]; st[h++] = cos(a); break;
-        case O_TAN:  a = st[--h]; st[h++] = tan(a); break;
-        default: return NAN;
-        }
+        int ar = op_arity(op);
+        if (op == O_VAR) { st[h++] = (double)X[(int64_t)arg * ld + row]; continue; }
+        if (op == O_CONST) { st[h++] = (double)c[arg]; continue; }
+        if (ar < 0) return NAN;
+        double a = st[--h];
+        double b = ar == 2 ? st[--h] : 0.0;
+        st[h++] = op_f64(op, a, b);
     }
     return st[0];
 }
 
 /* Conditioning analysis of one row (test infrastructure for the tolerance
  * policy).  Evaluates the program in float32 and float64 in lock-step and
- * carries, in float64, a first-order bound E on how far a float32 evaluation
- * can move when every sin / cos / tan / log result is allowed to differ from
- * the correctly rounded one by `u` relative (two correct library
- * implementations of these functions are a few ulp apart; add, sub, mul,
- * div, neg and sqrt are correctly rounded everywhere and contribute nothing):
- *   terminal 0;  a+b, a-b: Ea+Eb;  a*b: |b|Ea+|a|Eb;  a/b: Ea/|b|+|a|Eb/b^2
- *   (0 on the protected arm);  -a: Ea;  sqrt|a|: Ea/(2 sqrt|a|);
- *   f(a) for f in sin, cos, tan, log: |f'(a)| Ea + u |f(a)|.
+ * carries, in float64, a bound E on how far a float32 evaluation can move
+ * when every library-function result (sin, cos, tan, log, exp, tanh, atan,
+ * cbrt, atan2) is allowed to differ from the correctly rounded one by `u`
+ * relative: two correct library implementations of these functions are a
+ * few ulp apart, while add, sub, mul, div, neg, abs, sqrt, max, min, inv, sq
+ * and cube are correctly rounded everywhere and contribute nothing of their
+ * own.  Operands carry bounds Ea, Eb; each node's bound is the largest
+ * change of its value over the whole box [a - Ea, a + Ea] x [b - Eb, b + Eb]
+ * (mean value theorem with the supremum of |f'| over the interval, or the
+ * exact remainder of a polynomial), not the first-order |f'(a)| Ea, so that
+ * it stays a bound where a large Ea meets a saturating function:
+ *   terminal 0;  a+b, a-b: Ea+Eb;  a*b: |b|Ea + |a|Eb + Ea Eb;
+ *   a/b: (Ea|b| + |a|Eb) / (|b|(|b|-Eb)) (0 on the protected arm);
+ *   -a, |a|: Ea;  max, min: max(Ea, Eb) (1-Lipschitz in each operand);
+ *   sqrt|a|: min(Ea / (2 sqrt(|a|-Ea)), sqrt(Ea));  inv: Ea/(|a|-Ea)^2;
+ *   a^2: 2|a|Ea + Ea^2;  a^3: 3a^2 Ea + 3|a|Ea^2 + Ea^3;
+ *   f(a) for the library functions: D (1+u) + u |f(a)| with D = Ea sup|f'|
+ *   (cbrt also min'd with its Hoelder bound 2^(2/3) Ea^(1/3));
+ *   atan2(a, b): D = ((|b|+Eb) Ea + (|a|+Ea) Eb) / rmin^2, rmin the distance
+ *   of the box from the origin, and a possible jump of 2 pi (near) when
+ *   b < 0 and a lies within Ea of 0.
+ * A bound that cannot be given (the interval reaches a pole or the origin)
+ * is infinite, which excludes the row.
  * Outputs: *v32, *v64 the two values, *E the bound on the output, *flip if
- * a protected predicate came out differently in float32 and float64, *near if
- * a protected predicate's float32 operand lies within its own bound of the
- * 0.001 threshold (so two float32 evaluations may take different arms). */
+ * a protected predicate or a sign that selects a branch of atan2 came out
+ * differently in float32 and float64, *near if a protected predicate's
+ * operand lies within its own bound of the 0.001 threshold, or a value
+ * within its bound of float32 overflow (so two float32 evaluations may take
+ * different arms). */
 static double mul0(double x, double y) { return (x == 0.0 || y == 0.0) ? 0.0 : x * y; }
 
+static const double ORC_PI = 3.14159265358979323846;
+
+/* does [lo, hi] contain off + k pi for some integer k? */
+static int has_point(double lo, double hi, double off)
+{
+    if (!(hi - lo < ORC_PI)) return 1;
+    double k = ceil((lo - off) / ORC_PI);
+    return off + k * ORC_PI <= hi;
+}
+
+/* sup |f'(t)| over t in [a - e, a + e], e > 0, for the library functions */
+static double sup_deriv(int op, double a, double e)
+{
+    double lo = a - e, hi = a + e, m = fabs(a) - e;
+    double nearest = (lo <= 0.0 && hi >= 0.0) ? 0.0 : fmin(fabs(lo), fabs(hi));
+    switch (op) {
+    case O_SIN: return has_point(lo, hi, 0.0) ? 1.0 : fmax(fabs(cos(lo)), fabs(cos(hi)));
+    case O_COS: return has_point(lo, hi, ORC_PI / 2) ? 1.0 : fmax(fabs(sin(lo)), fabs(sin(hi)));
+    case O_TAN: {
+        if (has_point(lo, hi, ORC_PI / 2)) return INFINITY;
+        double tl = tan(lo), th = tan(hi);
+        return fmax(1.0 + tl * tl, 1.0 + th * th);
+    }
+    case O_LOG: return m > 0.0 ? 1.0 / m : INFINITY;
+    case O_EXP: return exp(hi);
+    case O_TANH: { double t = tanh(nearest); return 1.0 - t * t; }
+    case O_ATAN: return 1.0 / (1.0 + nearest * nearest);
+    case O_CBRT: return m > 0.0 ? 1.0 / (3.0 * cbrt(m) * cbrt(m)) : INFINITY;
+    default: return INFINITY;
+    }
+}
+
+/* A correctly rounded operation whose operands differ between the two
+ * sides (bound e > 0) may also round them to neighbouring floats: one
+ * spacing of the result, at most rf (|v| + e) with rf = 2^-23 for float32,
+ * per rounding.  Operands known exactly on both sides round identically. */
+static double round_flip(double v, double e, int n_round, double rf)
+{
+    return e > 0.0 ? n_round * rf * (fabs(v) + e) : 0.0;
+}
+
+/* the sign bit as 0 / 1 (signbit() returns an unspecified nonzero value,
+ * which may differ between a float and a double argument) */
+static int neg_bit(double x) { return signbit(x) ? 1 : 0; }
+
+/* bound of a library function's result: D (1 + u) + u |v| */
+static double lib_bound(double D, double v, double u) { return D * (1.0 + u) + u * fabs(v); }
+
 static void row_analysis(const uint32_t *nodes, int64_t len, const float *c,
-                         const float *X, int64_t ld, int64_t row, double u,
+                         const float *X, int64_t ld, int64_t row, double u, double rf,
                          float *v32, double *v64, double *Eout, int *flip_out, int *near_out)
 {
     float sf[ORC_STACK];
@@ -191,45 +348,94 @@ static void row_analysis(const uint32_t *nodes, int64_t len, const float *c,
             sf[h] = X[(int64_t)arg * ld + row]; sd[h] = (double)sf[h]; se[h] = 0.0; h++; break;
         case O_CONST:
             sf[h] = c[arg]; sd[h] = (double)c[arg]; se[h] = 0.0; h++; break;
-        case O_ADD: case O_SUB: case O_MUL: case O_DIV:
+        case O_ADD: case O_SUB: case O_MUL: case O_DIV: case O_MAX: case O_MIN: case O_ATAN2:
             h--; af = sf[h]; ad = sd[h]; ea = se[h];
             h--; bf = sf[h]; bd = sd[h]; eb = se[h];
-            if (op == O_ADD) { sf[h] = af + bf; sd[h] = ad + bd; se[h] = ea + eb; }
-            else if (op == O_SUB) { sf[h] = af - bf; sd[h] = ad - bd; se[h] = ea + eb; }
-            else if (op == O_MUL) {
-                sf[h] = af * bf; sd[h] = ad * bd; se[h] = mul0(fabs(bd), ea) + mul0(fabs(ad), eb);
+            sf[h] = op_f32(op, af, bf); sd[h] = op_f64(op, ad, bd);
+            if (op == O_MAX || op == O_MIN) {
+                se[h] = ea > eb ? ea : eb;
+            } else if (op == O_ATAN2) {
+                /* the branch cut on the negative x axis: a sign of the first
+                 * operand that differs between the two paths, or lies within
+                 * its bound of zero, moves the result by about 2 pi */
+                if ((neg_bit(bf) || neg_bit(bd)) && neg_bit(af) != neg_bit(ad)) flip = 1;
+                if (af == 0.0f && ad == 0.0 && neg_bit(bf) != neg_bit(bd)) flip = 1;
+                if (bd < 0.0 && fabs(ad) <= ea) near = 1;
+                if (ea == 0.0 && eb == 0.0) {
+                    se[h] = u * fabs(sd[h]);
+                } else {
+                    double ra = fmax(fabs(ad) - ea, 0.0), rb = fmax(fabs(bd) - eb, 0.0);
+                    double r2 = ra * ra + rb * rb;
+                    if (!(r2 > 0.0)) { near = 1; se[h] = INFINITY; }
+                    else se[h] = lib_bound((mul0(fabs(bd) + eb, ea) + mul0(fabs(ad) + ea, eb)) / r2,
+                                           sd[h], u);
+                }
+            } else if (op == O_ADD || op == O_SUB) {
+                se[h] = ea + eb;
+                se[h] += round_flip(sd[h], se[h], 1, rf);
+            } else if (op == O_MUL) {
+                se[h] = mul0(fabs(bd), ea) + mul0(fabs(ad), eb) + mul0(ea, eb);
+                se[h] += round_flip(sd[h], se[h], 1, rf);
             } else {
                 if ((fabsf(bf) > ORC_EPS) != (fabs(bd) > eps)) flip = 1;
                 if (eb > 0.0 && fabs(fabs((double)bf) - eps) <= eb) near = 1;
-                sf[h] = pdiv_f(af, bf); sd[h] = pdiv_d(ad, bd);
-                se[h] = fabs(bd) > eps ? mul0(ea, 1.0 / fabs(bd)) + mul0(eb, fabs(ad) / (bd * bd)) : 0.0;
+                if (!(fabs(bd) > eps)) se[h] = 0.0;
+                else if (eb >= fabs(bd)) se[h] = INFINITY;
+                else se[h] = (mul0(ea, fabs(bd)) + mul0(fabs(ad), eb)) / (fabs(bd) * (fabs(bd) - eb));
+                se[h] += round_flip(sd[h], se[h], 1, rf);
             }
             h++;
             break;
         default:
             h--; af = sf[h]; ad = sd[h]; ea = se[h];
+            if (op < 0 || op >= O_NUM || op_arity(op) != 1) {
+                *v32 = NAN; *v64 = NAN; *Eout = INFINITY; *flip_out = 1; *near_out = 1; return;
+            }
+            sf[h] = op_f32(op, af, 0.0f); sd[h] = op_f64(op, ad, 0.0);
             switch (op) {
-            case O_NEG: sf[h] = -af; sd[h] = -ad; se[h] = ea; break;
-            case O_LOG:
+            case O_NEG: case O_ABS: se[h] = ea; break;
+            case O_LOG: case O_INV:
                 if ((fabsf(af) > ORC_EPS) != (fabs(ad) > eps)) flip = 1;
                 if (ea > 0.0 && fabs(fabs((double)af) - eps) <= ea) near = 1;
-                sf[h] = plog_f(af); sd[h] = plog_d(ad);
-                se[h] = fabs(ad) > eps ? mul0(ea, 1.0 / fabs(ad)) + u * fabs(sd[h]) : 0.0;
+                if (!(fabs(ad) > eps)) se[h] = 0.0;            /* the protected arm: a constant */
+                else if (op == O_INV) {
+                    double m = fabs(ad) - ea;
+                    se[h] = ea == 0.0 ? 0.0 : (m > 0.0 ? ea / (m * m) : INFINITY);
+                    se[h] += round_flip(sd[h], se[h], 1, rf);
+                } else {
+                    se[h] = lib_bound(ea == 0.0 ? 0.0 : ea * sup_deriv(O_LOG, ad, ea), sd[h], u);
+                }
                 break;
-            case O_SQRT:
-                sf[h] = psqrt_f(af); sd[h] = psqrt_d(ad);
-                se[h] = ea == 0.0 ? 0.0 : (ad != 0.0 ? ea / (2.0 * sqrt(fabs(ad))) : INFINITY);
+            case O_SQRT: {
+                double m = fabs(ad) - ea;
+                se[h] = ea == 0.0 ? 0.0 : fmin(m > 0.0 ? ea / (2.0 * sqrt(m)) : INFINITY, sqrt(ea));
+                se[h] += round_flip(sd[h], se[h], 1, rf);
                 break;
-            case O_SIN: sf[h] = sinf(af); sd[h] = sin(ad);
-                se[h] = mul0(fabs(cos(ad)), ea) + u * fabs(sd[h]); break;
-            case O_COS: sf[h] = cosf(af); sd[h] = cos(ad);
-                se[h] = mul0(fabs(sin(ad)), ea) + u * fabs(sd[h]); break;
-            case O_TAN: sf[h] = tanf(af); sd[h] = tan(ad);
-                se[h] = mul0(1.0 + sd[h] * sd[h], ea) + u * fabs(sd[h]); break;
-            default: *v32 = NAN; *v64 = NAN; *Eout = INFINITY; *flip_out = 1; *near_out = 1; return;
+            }
+            case O_SQ:
+                se[h] = mul0(2.0 * fabs(ad), ea) + mul0(ea, ea);
+                se[h] += round_flip(sd[h], se[h], 1, rf);
+                break;
+            case O_CUBE:   /* two roundings: (a*a)*a */
+                se[h] = mul0(3.0 * ad * ad, ea) + mul0(3.0 * fabs(ad), mul0(ea, ea)) + mul0(ea, mul0(ea, ea));
+                se[h] += round_flip(sd[h], se[h], 2, rf);
+                break;
+            case O_CBRT: {
+                double D = ea == 0.0 ? 0.0 : fmin(ea * sup_deriv(O_CBRT, ad, ea), 1.5874010519681994 * cbrt(ea));
+                se[h] = lib_bound(D, sd[h], u);
+                break;
+            }
+            default:   /* sin, cos, tan, exp, tanh, atan */
+                se[h] = lib_bound(ea == 0.0 ? 0.0 : ea * sup_deriv(op, ad, ea), sd[h], u);
+                break;
             }
             h++;
         }
+        /* float32 overflow is a threshold too: a value whose bound reaches
+         * FLT_MAX may be infinite on one side and finite on the other */
+        if (h > 0 && se[h - 1] > 0.0 && fabs(sd[h - 1]) + se[h - 1] >= (double)FLT_MAX
+            && fabs(sd[h - 1]) - se[h - 1] <= (double)FLT_MAX)
+            near = 1;
     }
     *v32 = sf[0]; *v64 = sd[0]; *Eout = se[0]; *flip_out = flip; *near_out = near;
 }
@@ -275,7 +481,7 @@ void orc_evaluate_f64(const uint32_t *nodes, const int64_t *prog_off,
 void orc_evaluate_pairs(const uint32_t *nodes, const int64_t *prog_off,
                         const float *consts, const int64_t *const_off,
                         const float *X, int64_t ld,
-                        const int32_t *prog, const int64_t *row, int64_t n_pairs, double u,
+                        const int32_t *prog, const int64_t *row, int64_t n_pairs, double u, double rf,
                         float *out32, double *out64, double *ebound, uint8_t *flags, int n_threads)
 {
     (void)n_threads;
@@ -286,7 +492,7 @@ void orc_evaluate_pairs(const uint32_t *nodes, const int64_t *prog_off,
         int64_t len = prog_off[p + 1] - prog_off[p];
         const float *pc = consts + const_off[p];
         int flip, near;
-        row_analysis(pn, len, pc, X, ld, row[i], u, &out32[i], &out64[i], &ebound[i], &flip, &near);
+        row_analysis(pn, len, pc, X, ld, row[i], u, rf, &out32[i], &out64[i], &ebound[i], &flip, &near);
         flags[i] = (uint8_t)(flip | (near << 1));
     }
 }
@@ -541,7 +747,18 @@ static double fitness_bound(int metric, const float *yh, const double *E, const 
     for (int64_t r = 0; r < n; ++r) W += w ? (double)w[r] : 1.0;
     double B = 0.0;
     if (metric == 4) {
-        double ma = 0.0, mb = 0.0, va = 0.0, vb = 0.0, cab = 0.0;
+        /* r = c / (sa sb) with c = sum w a b, sa^2 = sum w a^2 over the
+         * centred columns.  Rows moving by d_r, |d_r| <= E_r, give (b is
+         * centred, so d's mean drops out of c)
+         *   r' - r = (1/sa') sum w d (b/sb - k r a) - r |d_c|^2 / ((sa' + sa) sa'),
+         * k = 2 / (sa' + sa), an identity; and sa'^2 = sa^2 + 2 sum w a d +
+         * |d_c|^2 lies within [sa^2 - 2A, sa^2 + 2A + dn], A = sum w |a| E,
+         * dn = sum w E^2.  Bounding sa' below by sa_lo and taking k at both
+         * ends of its range row by row gives a bound on |r' - r| that tends
+         * to the first-order sum w E |b/(sa sb) - r a/sa^2| as E -> 0.  A
+         * column that may become constant (sa_lo = 0) may take any |r|: the
+         * bound is then 1. */
+        double ma = 0.0, mb = 0.0, va = 0.0, vb = 0.0, cab = 0.0, dn = 0.0, A = 0.0;
         for (int64_t r = 0; r < n; ++r) {
             double wr = w ? (double)w[r] : 1.0;
             ma += wr * (double)yh[r]; mb += wr * (double)y[r];
@@ -551,15 +768,26 @@ static double fitness_bound(int metric, const float *yh, const double *E, const 
             double wr = w ? (double)w[r] : 1.0;
             double a = (double)yh[r] - ma, b = (double)y[r] - mb;
             va += wr * a * a; vb += wr * b * b; cab += wr * a * b;
+            dn += mul0(wr, E[r] * E[r]);
+            A += mul0(wr * fabs(a), E[r]);
         }
-        if (!(va > 0.0) || !(vb > 0.0)) return 0.0;
-        double rr = cab / sqrt(va * vb);
+        if (!(vb > 0.0)) return 0.0;                 /* constant target: 0 on both sides */
+        if (!(dn > 0.0)) return 0.0;                 /* no row can move */
+        if (!isfinite(va) || !isfinite(dn) || !isfinite(A)) return INFINITY;
+        double lo2 = va - 2.0 * A;
+        if (!(lo2 > 0.0)) return 1.0;
+        double sa = sqrt(va), sb = sqrt(vb), sa_lo = sqrt(lo2), sa_hi = sqrt(va + 2.0 * A + dn);
+        double rr = cab / (sa * sb);
+        double k1 = 2.0 / (sa + sa_hi), k2 = 2.0 / (sa + sa_lo);
+        double S = 0.0;
         for (int64_t r = 0; r < n; ++r) {
             double wr = w ? (double)w[r] : 1.0;
             double a = (double)yh[r] - ma, b = (double)y[r] - mb;
-            B += mul0(wr * fabs(b / sqrt(va * vb) - rr * a / va), E[r]);
+            double g1 = fabs(b / sb - k1 * rr * a), g2 = fabs(b / sb - k2 * rr * a);
+            S += mul0(wr * (g1 > g2 ? g1 : g2), E[r]);
         }
-        return B;
+        double bound = S / sa_lo + fabs(rr) * dn / ((sa_lo + sa) * sa_lo);
+        return bound < 1.0 ? bound : 1.0;
     }
     for (int64_t r = 0; r < n; ++r) {
         double wr = w ? (double)w[r] : 1.0;
@@ -576,8 +804,8 @@ void orc_fitness(const uint32_t *nodes, const int64_t *prog_off,
                  const float *consts, const int64_t *const_off, int32_t n_programs,
                  const float *X, int64_t ld, int64_t n_rows,
                  const float *y, const float *w, int32_t metric,
-                 double *fit_f32path, double *fit_f64, double u, double *fbound, int32_t *fnear,
-                 int n_threads)
+                 double *fit_f32path, double *fit_f64, double u, double rf, double *fbound,
+                 int32_t *fnear, int n_threads)
 {
     (void)n_threads;
 #pragma omp parallel num_threads(n_threads > 0 ? n_threads : 1)
@@ -595,7 +823,7 @@ void orc_fitness(const uint32_t *nodes, const int64_t *prog_off,
             if (fbound) {
                 for (int64_t r = 0; r < n_rows; ++r) {
                     int flip, near;
-                    row_analysis(pn, len, pc, X, ld, r, u, &yh32[r], &yh64[r], &E[r], &flip, &near);
+                    row_analysis(pn, len, pc, X, ld, r, u, rf, &yh32[r], &yh64[r], &E[r], &flip, &near);
                     nnear += near;
                 }
             } else {
@@ -958,7 +1186,11 @@ int orc_build_population(int32_t n_programs, int32_t n_features, int32_t method,
 /* by the local partial derivatives (readings):                               */
 /*   add (1,1); sub (1,-1); mul (b,a); pdiv (1/b, -a/b^2) if |b|>eps else 0;  */
 /*   plog 1/a if |a|>eps else 0; psqrt sign(a)/(2 sqrt|a|), 0 at a = 0;       */
-/*   sin cos a; cos -sin a; tan 1 + tan^2 a; neg -1.                          */
+/*   sin cos a; cos -sin a; tan 1 + tan^2 a; neg -1; max / min 1 for the      */
+/*   operand selected (the first on ties), 0 for the other; atan2(a, b)       */
+/*   (b, -a)/(a^2+b^2), 0 at the origin; abs sign(a) (0 at 0); exp exp(a);    */
+/*   inv -1/a^2 if |a|>eps else 0; sq 2a; cube 3a^2; tanh 1 - tanh^2 a;       */
+/*   atan 1/(1+a^2); cbrt 1/(3 cbrt(a)^2), 0 at a = 0.                        */
 /* Seeds: MSE 2w(yh-y)/W; MAE w sign(yh-y)/W; RMSE dMSE/(2 RMSE) (0 if RMSE   */
 /* is 0); logistic w(sigmoid(yh)-y)/W; Pearson d|r|/dyh.                      */
 /* grad[const_off[p] + s] receives gscale[p] * d fitness_p / d c_s.           */
@@ -981,6 +1213,27 @@ static double local_partial(int op, int which, double a, double b, double out)
     case O_SIN: return cos(a);
     case O_COS: return -sin(a);
     case O_TAN: return 1.0 + out * out;
+    case O_MAX: {   /* the selected operand carries the derivative */
+        int first = (a >= b) || isnan(b);
+        return which == 0 ? (first ? 1.0 : 0.0) : (first ? 0.0 : 1.0);
+    }
+    case O_MIN: {
+        int first = (a <= b) || isnan(b);
+        return which == 0 ? (first ? 1.0 : 0.0) : (first ? 0.0 : 1.0);
+    }
+    case O_ATAN2: {
+        double r2 = a * a + b * b;
+        if (!(r2 > 0.0)) return 0.0;
+        return which == 0 ? b / r2 : -a / r2;
+    }
+    case O_ABS: return a > 0.0 ? 1.0 : (a < 0.0 ? -1.0 : 0.0);
+    case O_EXP: return out;
+    case O_INV: return fabs(a) > (double)ORC_EPS ? -out * out : 0.0;
+    case O_SQ: return 2.0 * a;
+    case O_CUBE: return 3.0 * a * a;
+    case O_TANH: return 1.0 - out * out;
+    case O_ATAN: return 1.0 / (1.0 + a * a);
+    case O_CBRT: return out != 0.0 ? 1.0 / (3.0 * out * out) : 0.0;
     default: return 0.0;
     }
 }
@@ -1020,26 +1273,12 @@ static double forward_row(const uint32_t *pn, int64_t L, const float *pc, const 
             endi[i] = i + 1;
         } else if (ar == 1) {
             double a = st[--h];
-            switch (op) {
-            case O_NEG: v = -a; break;
-            case O_LOG: v = plog_d(a); break;
-            case O_SQRT: v = psqrt_d(a); break;
-            case O_SIN: v = sin(a); break;
-            case O_COS: v = cos(a); break;
-            default: v = tan(a); break;
-            }
-            v *= mc_factor(u, seed, r, i, 0);
+            v = op_f64(op, a, 0.0) * mc_factor(u, seed, r, i, 0);
             endi[i] = endi[i + 1];
         } else {
             double a = st[--h];
             double b = st[--h];
-            switch (op) {
-            case O_ADD: v = a + b; break;
-            case O_SUB: v = a - b; break;
-            case O_MUL: v = a * b; break;
-            default: v = pdiv_d(a, b); break;
-            }
-            v *= mc_factor(u, seed, r, i, 0);
+            v = op_f64(op, a, b) * mc_factor(u, seed, r, i, 0);
             endi[i] = endi[endi[i + 1]];
         }
         val[i] = v;

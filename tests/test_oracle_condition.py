@@ -10,10 +10,17 @@ import pytest
 
 import oracle
 from oracle import ARITY, CONST, VAR, ADD, SUB, MUL, DIV, NEG, LOG, SQRT, SIN, COS, TAN
+from oracle import MAX, MIN, ATAN2, ABS, EXP, INV, SQ, CUBE, TANH, ATAN, CBRT
 
 import synth
 
-TRANS = (LOG, SIN, COS, TAN)
+# the library functions, whose results differ by a few ulps between sides
+TRANS = (LOG, SIN, COS, TAN, EXP, TANH, ATAN, CBRT, ATAN2)
+_EPS = 0.0010000000474974513
+
+
+def _cbrt(a):
+    return math.copysign(abs(a) ** (1.0 / 3.0), a)
 
 
 def perturbed_value(nodes, consts, xs, signs, u):
@@ -28,18 +35,13 @@ def perturbed_value(nodes, consts, xs, signs, u):
             return float(consts[arg]), i + 1
         a, j = rec(i + 1)
         if ARITY[op] == 1:
-            if op == NEG:
-                v = -a
-            elif op == SQRT:
-                v = math.sqrt(abs(a))
-            elif op == LOG:
-                v = math.log(abs(a)) if abs(a) > 0.0010000000474974513 else 0.0
-            elif op == SIN:
-                v = math.sin(a)
-            elif op == COS:
-                v = math.cos(a)
-            else:
-                v = math.tan(a)
+            v = {NEG: lambda: -a, SQRT: lambda: math.sqrt(abs(a)),
+                 LOG: lambda: math.log(abs(a)) if abs(a) > _EPS else 0.0,
+                 SIN: lambda: math.sin(a), COS: lambda: math.cos(a), TAN: lambda: math.tan(a),
+                 ABS: lambda: abs(a), EXP: lambda: math.exp(a) if a < 700 else math.inf,
+                 INV: lambda: 1.0 / a if abs(a) > _EPS else 0.0, SQ: lambda: a * a,
+                 CUBE: lambda: a * a * a, TANH: lambda: math.tanh(a), ATAN: lambda: math.atan(a),
+                 CBRT: lambda: _cbrt(a)}[op]()
             if op in TRANS:
                 v *= 1.0 + signs[i] * u
             return v, j
@@ -50,7 +52,13 @@ def perturbed_value(nodes, consts, xs, signs, u):
             return a - b, j
         if op == MUL:
             return a * b, j
-        return (a / b if abs(b) > 0.0010000000474974513 else 1.0), j
+        if op == MAX:
+            return max(a, b), j
+        if op == MIN:
+            return min(a, b), j
+        if op == ATAN2:
+            return math.atan2(a, b) * (1.0 + signs[i] * u), j
+        return (a / b if abs(b) > _EPS else 1.0), j
 
     return rec(0)[0]
 
@@ -62,14 +70,15 @@ def test_single_transcendental_bound_is_tight():
     pop = oracle.from_programs([(nodes, [3.0])])
     X, _ = synth.pagie(200, seed=1)
     u = 1e-9
-    ra = oracle.evaluate_pairs(pop, X, np.zeros(200, np.int32), np.arange(200), u=u)
+    ra = oracle.evaluate_pairs(pop, X, np.zeros(200, np.int32), np.arange(200), u=u, rf=0.0)
     expect = u * np.abs(3.0 * np.sin(X[0].astype(np.float64)))
     assert np.allclose(ra.bound, expect, rtol=1e-12, atol=0)
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2])
-def test_bound_dominates_perturbation_experiment(seed):
-    fmask = oracle.DEFAULT_FMASK | (1 << TAN)
+@pytest.mark.parametrize("seed,fset", [(0, "paper"), (1, "paper"), (2, "paper"),
+                                       (3, "wide"), (4, "wide"), (5, "wide")])
+def test_bound_dominates_perturbation_experiment(seed, fset):
+    fmask = oracle.DEFAULT_FMASK | (1 << TAN) if fset == "paper" else oracle.ALL_FMASK
     pop = oracle.build_population(40, 2, "exact_len", min_len=2, max_len=60, fmask=fmask,
                                   seed=100 + seed)
     X, _ = synth.pagie(30, seed=seed)
@@ -79,7 +88,7 @@ def test_bound_dominates_perturbation_experiment(seed):
     checked = 0
     for p in range(pop.n_programs):
         nodes, consts = pop.program(p)
-        ra = oracle.evaluate_pairs(pop, X, np.full(30, p, np.int32), np.arange(30), u=u)
+        ra = oracle.evaluate_pairs(pop, X, np.full(30, p, np.int32), np.arange(30), u=u, rf=0.0)
         for r in range(30):
             if ra.near[r] or ra.flip[r] or not np.isfinite(ra.bound[r]) or not np.isfinite(ra.v64[r]):
                 continue
@@ -151,12 +160,12 @@ def test_fitness_bound_dominates_row_displacements(metric):
     fmask = oracle.DEFAULT_FMASK | (1 << TAN)
     pop = oracle.build_population(30, 2, "exact_len", min_len=3, max_len=40, fmask=fmask, seed=77)
     u = 1e-7
-    f32p, f64, fb, fn = oracle.fitness(pop, X, y, w, metric, with_bound=True, u=u)
+    f32p, f64, fb, fn = oracle.fitness(pop, X, y, w, metric, with_bound=True, u=u, rf=0.0)
     rng = np.random.default_rng(5)
     yd, wd = y.astype(np.float64), w.astype(np.float64)
     checked = 0
     for p in range(pop.n_programs):
-        ra = oracle.evaluate_pairs(pop, X, np.full(N, p, np.int32), np.arange(N), u=u)
+        ra = oracle.evaluate_pairs(pop, X, np.full(N, p, np.int32), np.arange(N), u=u, rf=0.0)
         v, E = ra.v32.astype(np.float64), ra.bound
         if fn[p] or not (np.all(np.isfinite(v)) and np.all(np.isfinite(E))) or not np.isfinite(fb[p]):
             continue
@@ -191,7 +200,7 @@ def test_spearman_bound_dominates_rank_changes():
     fmask = oracle.DEFAULT_FMASK | (1 << TAN)
     pop = oracle.build_population(30, 2, "exact_len", min_len=3, max_len=30, fmask=fmask, seed=81)
     u = 1e-5        # large: many near ties
-    f32p, f64, fb, fn = oracle.fitness(pop, X, y, w, "spearman", with_bound=True, u=u)
+    f32p, f64, fb, fn = oracle.fitness(pop, X, y, w, "spearman", with_bound=True, u=u, rf=0.0)
     rng = np.random.default_rng(2)
     wd = w.astype(np.float64)
     rb = rankdata(y.astype(np.float64))
@@ -203,7 +212,7 @@ def test_spearman_bound_dominates_rank_changes():
         return 0.0 if va == 0 or vb == 0 else abs(np.sum(wd * (ra - ma) * (rb - mb)) / np.sqrt(va * vb))
     nonzero = 0
     for p in range(pop.n_programs):
-        ra_ = oracle.evaluate_pairs(pop, X, np.full(N, p, np.int32), np.arange(N), u=u)
+        ra_ = oracle.evaluate_pairs(pop, X, np.full(N, p, np.int32), np.arange(N), u=u, rf=0.0)
         v, E = ra_.v32.astype(np.float64), ra_.bound
         if fn[p] or not (np.all(np.isfinite(v)) and np.all(np.isfinite(E))):
             continue
@@ -216,3 +225,136 @@ def test_spearman_bound_dominates_rank_changes():
         if np.all(E == 0):
             assert fb[p] == 0.0       # exact values: ranks cannot differ
     assert nonzero >= 5
+
+
+# ---- the whole tolerance policy against a float32 experiment ----
+def _f32_lib(op, a, b=None):
+    """A library function evaluated in float64 and rounded to float32 (the
+    correctly rounded result, up to double rounding)."""
+    with np.errstate(all="ignore"):
+        if op == ATAN2:
+            return np.float32(math.atan2(float(a), float(b)))
+        fa = float(a)
+        v = {LOG: lambda: math.log(abs(fa)), SIN: lambda: math.sin(fa), COS: lambda: math.cos(fa),
+             TAN: lambda: math.tan(fa), EXP: lambda: math.exp(fa) if fa < 700 else math.inf,
+             TANH: lambda: math.tanh(fa), ATAN: lambda: math.atan(fa), CBRT: lambda: _cbrt(fa)}[op]()
+        return np.float32(v)
+
+
+def _shift(v, k):
+    """v moved by k float32 ulps (k may be negative); zero and subnormal
+    results stay exact (the allowance is relative: 4 ulps of a normal |v|)."""
+    if not abs(v) >= np.finfo(np.float32).tiny or not np.isfinite(v):
+        return v
+    for _ in range(abs(k)):
+        v = np.nextafter(v, np.float32(np.inf if k > 0 else -np.inf))
+    return v
+
+
+def value32_shifted(nodes, consts, xs, shifts):
+    """Recursive float32 evaluation (numpy float32 arithmetic, correctly
+    rounded) in which library function i returns its correctly rounded value
+    moved by shifts[i] ulps: a stand-in for another correct float32 library."""
+    f = np.float32
+    eps = f(0.001)
+
+    def rec(i):
+        w = int(nodes[i])
+        op, arg = w & 0xFF, w >> 8
+        if op == VAR:
+            return f(xs[arg]), i + 1
+        if op == CONST:
+            return f(consts[arg]), i + 1
+        a, j = rec(i + 1)
+        with np.errstate(all="ignore"):
+            if ARITY[op] == 1:
+                if op == NEG:
+                    return f(-a), j
+                if op == ABS:
+                    return f(abs(a)), j
+                if op == SQRT:
+                    return f(np.sqrt(f(abs(a)))), j
+                if op == INV:
+                    return (f(f(1) / a) if abs(a) > eps else f(0)), j
+                if op == SQ:
+                    return f(a * a), j
+                if op == CUBE:
+                    return f(f(a * a) * a), j
+                if op == LOG and not abs(a) > eps:
+                    return f(0), j
+                return _shift(_f32_lib(op, a), shifts[i]), j
+            b, j = rec(j)
+            if op == ADD:
+                return f(a + b), j
+            if op == SUB:
+                return f(a - b), j
+            if op == MUL:
+                return f(a * b), j
+            if op == DIV:
+                return (f(a / b) if abs(b) > eps else f(1)), j
+            if op in (MAX, MIN):
+                if np.isnan(a):
+                    return b, j
+                if np.isnan(b):
+                    return a, j
+                if a == b:
+                    na = np.signbit(a)
+                    return ((b if na else a) if op == MAX else (a if na else b)), j
+                return (max(a, b) if op == MAX else min(a, b)), j
+            return _shift(_f32_lib(ATAN2, a, b), shifts[i]), j
+
+    return rec(0)[0]
+
+
+@pytest.mark.parametrize("seed,fset", [(0, "paper"), (1, "paper"), (2, "wide"), (3, "wide")])
+def test_policy_bound_dominates_float32_experiment(seed, fset):
+    """On every row the tolerance policy keeps (no predicate near or across
+    its threshold, bound within the row tolerance), a float32 evaluation with
+    each library result up to 2 ulps from its correctly rounded value -- so
+    within 4 ulps of the oracle's C library -- stays within the bound of the
+    oracle's float32 value.  This includes the neighbouring-float rounding
+    of every correctly rounded operation downstream (rf); with rf = 0 the
+    same experiment breaks the bound on some rows."""
+    fmask = oracle.DEFAULT_FMASK | (1 << TAN) if fset == "paper" else oracle.ALL_FMASK
+    pop = oracle.build_population(60, 2, "rhh", min_depth=3, max_depth=6, fmask=fmask, seed=300 + seed)
+    X, _ = synth.pagie(40, seed=seed)
+    rng = np.random.default_rng(seed)
+    checked = broken_without_rf = 0
+    for p in range(pop.n_programs):
+        nodes, consts = pop.program(p)
+        idx = np.full(40, p, np.int32)
+        ra = oracle.evaluate_pairs(pop, X, idx, np.arange(40))
+        ra0 = oracle.evaluate_pairs(pop, X, idx, np.arange(40), rf=0.0)
+        for r in range(40):
+            v = float(ra.v32[r])
+            if ra.near[r] or ra.flip[r] or not np.isfinite(v) or not ra.bound[r] <= 1e-5 * max(1.0, abs(v)):
+                continue
+            worst = 0.0
+            for _ in range(6):
+                sh = rng.integers(-2, 3, size=len(nodes))
+                g = value32_shifted(nodes, consts, X[:, r], sh)
+                worst = max(worst, abs(float(g) - v))
+            assert worst <= ra.bound[r], (p, r, worst, ra.bound[r])
+            checked += 1
+            broken_without_rf += worst > ra0.bound[r]
+    assert checked > 600
+    print(f"{fset}: {checked} rows, {broken_without_rf} beyond the bound without rf")
+    assert broken_without_rf >= 1       # the experiment can see the rounding term
+
+
+def test_pearson_bound_of_a_constant_column():
+    """A program constant in float32 whose rows can move (a library function
+    upstream) may have any |r| on the other side: bound 1.  Constant from
+    exact operations only: bound 0.  (sin(tanh(-(tan(atan2(x1, x1)) / c^2))):
+    atan2(x1, x1) is +-pi/4 or -3pi/4, and tan of those lands on one float32
+    value, but another library's tan need not.)"""
+    n = oracle.node
+    X, y = synth.pagie(500, seed=4)
+    prog = [n(SIN), n(TANH), n(NEG), n(DIV), n(TAN), n(ATAN2), n(VAR, 1), n(VAR, 1), n(SQ), n(CONST, 0)]
+    pop = oracle.from_programs([(prog, [0.8781998]),
+                                ([n(MUL), n(CONST, 0), n(CONST, 1)], [0.5, 3.0])])
+    f32p, f64, fb, fn = oracle.fitness(pop, X, y, None, "pearson", with_bound=True)
+    v = oracle.evaluate_f32(pop, X)
+    assert np.unique(v[0]).size == 1 and np.unique(v[1]).size == 1
+    assert f32p[0] == 0.0 and fb[0] == 1.0
+    assert f32p[1] == 0.0 and fb[1] == 0.0

@@ -138,3 +138,28 @@ def test_bad_arguments_rejected():
         oracle.build_population(10, 2, "exact_len", min_len=0)
     with pytest.raises(ValueError):
         oracle.build_population(10, 2, "rhh", fmask=0)
+
+
+@pytest.mark.parametrize("method", ["rhh", "exact_len"])
+def test_every_enabled_function_is_drawn_uniformly(method):
+    """With every function enabled the generators draw each of the 21 about
+    equally often among function nodes (the draw is uniform over the enabled
+    set), and never one that is not enabled."""
+    pop = oracle.build_population(2000, 3, method, min_depth=2, max_depth=6, min_len=1,
+                                  max_len=60, fmask=oracle.ALL_FMASK, max_consts=4, seed=77)
+    check_valid(pop, 3, max_consts=4)
+    ops = pop.nodes & 0xFF
+    funcs = [o for o, a in ARITY.items() if a > 0]
+    assert len(funcs) == 21
+    counts = np.array([(ops == o).sum() for o in funcs], np.float64)
+    assert counts.min() > 0
+    # exact_len chooses unary vs binary by the length budget, so compare
+    # within each arity class
+    for ar in (1, 2):
+        c = np.array([counts[i] for i, o in enumerate(funcs) if ARITY[o] == ar])
+        assert c.max() / c.min() < 1.15, (ar, c)
+    only = sum(1 << o for o in (oracle.ATAN2, oracle.CBRT))
+    pop2 = oracle.build_population(300, 2, method, min_depth=2, max_depth=5, min_len=1, max_len=40,
+                                   fmask=only, seed=78)
+    ops2 = set(np.unique(pop2.nodes & 0xFF).tolist())
+    assert ops2 <= {VAR, CONST, oracle.ATAN2, oracle.CBRT} and {oracle.ATAN2, oracle.CBRT} <= ops2

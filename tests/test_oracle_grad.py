@@ -152,3 +152,43 @@ def test_monte_carlo_spread_small_when_well_conditioned():
     for seed in range(4):
         g, _ = oracle.grad_consts(pop, x[None, :], y, None, "mse", mc_u=u, mc_seed=seed)
         assert 0 < abs(g[0] - g0[0]) <= 8 * u * abs(g0[0])
+
+
+# the wider function set: smooth everywhere (exp, tanh, atan, sq, cube) and
+# smooth away from a measure-zero set (atan2 off the origin and branch cut,
+# cbrt off 0, inv off its threshold, max / min / abs off their kinks)
+SMOOTH_WIDE = sum(1 << o for o in (oracle.ADD, oracle.SUB, oracle.MUL, oracle.EXP, oracle.TANH,
+                                   oracle.ATAN, oracle.SQ, oracle.CUBE))
+KINKED_WIDE = sum(1 << o for o in (oracle.ADD, oracle.MUL, oracle.SIN, oracle.ATAN2, oracle.CBRT,
+                                   oracle.INV, oracle.MAX, oracle.MIN, oracle.ABS))
+
+
+@pytest.mark.parametrize("fmask,seed", [(SMOOTH_WIDE, 7), (KINKED_WIDE, 8)])
+def test_reverse_mode_matches_central_differences_wider_set(fmask, seed):
+    """Every partial of the wider set against Richardson central differences
+    of the float64 fitness (MSE).  Where a program's rows cross a kink inside
+    the difference stencil, the two disagree by the size of that row's share;
+    such programs are allowed, but must stay a small minority."""
+    n = 384
+    X, y = synth.diff_target(n, seed=seed)
+    w = synth.weights(n, seed=seed + 1)
+    pop = oracle.build_population(48, 8, "exact_len", min_len=3, max_len=24, fmask=fmask,
+                                  max_consts=16, seed=seed + 2)
+    g, f = oracle.grad_consts(pop, X, y, w, "mse")
+    fd = _fd(pop, X, y, w, "mse")
+    checked = agree = 0
+    for p in range(pop.n_programs):
+        a, b = int(pop.const_off[p]), int(pop.const_off[p + 1])
+        if a == b or not np.isfinite(f[p]) or not np.all(np.isfinite(g[a:b])) \
+                or not np.all(np.isfinite(fd[a:b])):
+            continue
+        scale = max(np.max(np.abs(g[a:b])), 1e-3 * max(abs(f[p]), 1e-6))
+        err = np.max(np.abs(g[a:b] - fd[a:b])) / scale
+        checked += 1
+        if err < 1e-5:
+            agree += 1
+        elif fmask == SMOOTH_WIDE:
+            raise AssertionError((p, err))
+    assert checked >= 12
+    print(f"checked {checked}, agree {agree}")
+    assert agree >= 0.8 * checked, (agree, checked)
