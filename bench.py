@@ -11,7 +11,9 @@ timing starts.
 
 Prints one JSON line: GPops/s = sum(len) * rows / time per step; the
 evaluation kernel's roofline (its duration from HIP event nodes recorded
-around it inside the graph); the adjoint/forward time ratio on the
+around it inside the graph); the same rows with an add/sub/mul-only
+population (every node one vector operation); the adjoint/forward time
+ratio on the
 differentiation workload (1,048,576 rows x 8 features, 2048 programs with
 up to 16 constants); and the CPU oracle on a row sample.
 """
@@ -95,6 +97,31 @@ def cpu_baseline(host, X, y, metric, budget_rows):
                       f"float32 path, {dt:.1f} s on {cores} threads"}
 
 
+def arith_only(gp, data, wl, steps):
+    """The same rows with a population over add, sub and mul only (lengths
+    1-200, same seed): the function set where every node is one vector
+    operation, timed like the main step."""
+    mask = sum(1 << op for op in (2, 3, 4))
+    host = gp.build_population(wl["programs"], wl["features"], function_mask=mask, **wl["pop"])
+    sum_len = int(host.length.astype(np.int64).sum())
+    gen = gp.Generation(data, host.n_programs, host.nodes.shape[0], max(host.consts.shape[0], 1), wl["metric"],
+                        tournament_size=20, seed=2025, autotune=True, time_kernel=True)
+    try:
+        gen.run(host, 0)
+        ms = []
+        for i in range(steps):
+            gen.run(host, 1 + i)
+            ms.append(gen.timing()["kernel_ms"])
+        launch = gen.timing()["launch"]
+    finally:
+        gen.close()
+    k = float(np.mean(ms))
+    gops = sum_len * wl["rows"] / (k / 1e3)
+    return {"population": "exact_len 1-200 over {add, sub, mul}, seed 2113", "sum_len": sum_len,
+            "kernel_avg_ms": k, "value": gops, "unit": "GPops/s", "frac": gops / PEAK_FP32_VALU,
+            "launch": list(launch)}
+
+
 def adjoint_ratio(gp, torch, reps=5):
     """gp_fitness_backward time / gp_fitness time on the differentiation
     workload (medians of `reps` event-timed calls each)."""
@@ -134,6 +161,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-arith", action="store_true", help="skip the add/sub/mul-only population")
     ap.add_argument("--cpu-rows", type=int, default=196_608)
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache (JSON lines): loaded if present, written after tuning")
@@ -200,6 +228,13 @@ def main():
     log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step, evaluation kernel {kern_avg_ms:.3f} ms avg "
         f"({tm['timed_by']}; device clock {tm['clock_ms']:.3f} ms)")
 
+    arith = None
+    if not args.no_arith and args.workload == "pagie-16M":
+        log("[bench] add/sub/mul-only population on the same rows")
+        arith = arith_only(gp, data, wl, 3)
+        log(f"[bench] add/sub/mul only: {arith['kernel_avg_ms']:.1f} ms, {arith['value']:.3g} GPops/s "
+            f"({100 * arith['frac']:.2f}% of peak)")
+
     adj = None
     if not args.no_adjoint:
         log("[bench] adjoint / forward ratio on the differentiation workload")
@@ -242,6 +277,7 @@ def main():
                      "kernel": "k_eval (persistent fused evaluation + MSE row loss + wave reduction)",
                      "kernel_avg_ms": kern_avg_ms, "kernel_timed_by": tm["timed_by"],
                      "ops_per_launch": ops_launch, "op": "one program node evaluated on one row"},
+        "arith_only": arith,
         "adjoint": adj,
         "cpu_baseline": base,
     }

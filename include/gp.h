@@ -55,7 +55,19 @@ enum {
     GP_OP_SIN = 9,   /* sin a                                                      */
     GP_OP_COS = 10,  /* cos a                                                      */
     GP_OP_TAN = 11,  /* tan a                                                      */
-    GP_OP_COUNT = 12
+    /* the wider set (the paper counts its functions without listing them) */
+    GP_OP_MAX = 12,   /* fmaxf(a, b): IEEE maxNum, a NaN operand yields the other */
+    GP_OP_MIN = 13,   /* fminf(a, b)                                              */
+    GP_OP_ATAN2 = 14, /* atan2f(a, b): a is y, b is x                             */
+    GP_OP_ABS = 15,   /* |a|                                                      */
+    GP_OP_EXP = 16,   /* exp a                                                    */
+    GP_OP_INV = 17,   /* protected: |a| > 0.001f ? 1 / a : 0                      */
+    GP_OP_SQ = 18,    /* a * a                                                    */
+    GP_OP_CUBE = 19,  /* (a * a) * a                                              */
+    GP_OP_TANH = 20,  /* tanh a                                                   */
+    GP_OP_ATAN = 21,  /* atan a                                                   */
+    GP_OP_CBRT = 22,  /* cube root of a                                           */
+    GP_OP_COUNT = 23
 };
 #define GP_NODE(op, arg) ((uint32_t)(op) | ((uint32_t)(arg) << 8))
 #define GP_NODE_OP(w) ((uint32_t)(w) & 0xffu)
@@ -313,7 +325,11 @@ gp_status gp_tournament(const float* fitness, const int32_t* len, int32_t n_prog
  * per row, recomputing the forward values per row tile.  Local derivatives:
  * add (1,1), sub (1,-1), mul (b,a), div (1/b, -a/b^2) where |b| > 0.001 else 0,
  * log 1/a where |a| > 0.001 else 0, sqrt sign(a)/(2 sqrt|a|) (0 at a = 0),
- * sin cos a, cos -sin a, tan 1 + tan^2 a, neg -1.  Metrics MAE, MSE, RMSE,
+ * sin cos a, cos -sin a, tan 1 + tan^2 a, neg -1; max / min (1,0) to the
+ * selected operand (the first on ties or when the second is NaN), atan2
+ * (b, -a)/(a^2+b^2) (0 at the origin), abs sign(a) (0 at 0), exp e^a, inv
+ * -1/a^2 where |a| > 0.001 else 0, sq 2a, cube 3a^2, tanh 1 - tanh^2 a, atan
+ * 1/(1+a^2), cbrt 1/(3 cbrt(a)^2) (0 at 0).  Metrics MAE, MSE, RMSE,
  * LOGLOSS, PEARSON.  fitness_out [n_programs] (nullable) receives the
  * fitness as gp_fitness would.  All pointers DEVICE memory.  The population
  * view must carry max_len and total_consts.  A program's constants in slots
@@ -323,6 +339,48 @@ gp_status gp_tournament(const float* fitness, const int32_t* len, int32_t n_prog
 gp_status gp_fitness_backward(const gp_population_dev* pop, const gp_dataset_dev* data,
                               gp_metric metric, const float* grad_fitness,
                               float* fitness_out, float* grad_consts, void* stream);
+
+/* ------------------------------------------------------------------ */
+/* Genetic operations on the DEVICE.  The same draws, choices and      */
+/* output layout as gp_plan_generation / gp_mutate (Sec. II-A, Sec.    */
+/* III-C2; the paper mutates on the CPU): offspring agree with the     */
+/* host functions bit for bit, with no host round trip.  Both calls    */
+/* are asynchronous on `stream`, allocate nothing after their first    */
+/* use at a size, and have fixed launch shapes (graph-capturable).     */
+/* ------------------------------------------------------------------ */
+/* An offspring population written by the device, in DEVICE memory. */
+typedef struct {
+    uint32_t* nodes;           /* [node_capacity]                                 */
+    int64_t* prog_off;         /* [n_offspring + 1]                               */
+    float* consts;             /* [const_capacity]                                */
+    int64_t* const_off;        /* [n_offspring + 1]                               */
+    int32_t* len;              /* [n_offspring]                                   */
+    int64_t node_capacity;
+    int64_t const_capacity;
+} gp_population_out_dev;
+
+/* gp_plan_generation with DEVICE outputs: ops and first_tournament
+ * [n_offspring], n_tournaments [1]. */
+gp_status gp_plan_generation_device(const gp_evolve_params* params, int32_t n_offspring,
+                                    uint64_t generation, int32_t* ops, int32_t* first_tournament,
+                                    int32_t* n_tournaments, void* stream);
+
+/* gp_mutate on a DEVICE parent population (valid programs over
+ * init->n_features, as gp_validate_population accepts; not re-checked) with
+ * DEVICE ops, first_tournament [n_offspring] and winners [n_winners].  The
+ * offspring go to `out`; info is DEVICE int64[4]: info[0], info[1] the total
+ * nodes and constants; info[2] status bits -- 1: a capacity of `out` is
+ * short, nothing was written; 2: an operation, tournament or winner index
+ * was out of range, those offspring are the one-node program x0; 4: the
+ * donors overflowed the library's bound (not reachable with settings that
+ * pass the checks).  Subtree-mutation donors are bounded by 2^(max_depth+1)-1
+ * nodes (tree methods) or max_len + 1 (exact length) each; settings whose
+ * bound times n_offspring exceeds 2^25 nodes give GP_ERR_INVALID_ARG. */
+gp_status gp_mutate_device(const gp_evolve_params* params, const gp_init_params* init,
+                           const gp_population_dev* parents, const int32_t* ops,
+                           const int32_t* first_tournament, const int32_t* winners, int32_t n_winners,
+                           int32_t n_offspring, uint64_t generation, const gp_population_out_dev* out,
+                           int64_t* info, void* stream);
 
 /* ------------------------------------------------------------------ */
 /* Launch configuration of the evaluation kernels (gp_evaluate,        */
@@ -431,6 +489,79 @@ gp_status gp_generation_info(const gp_generation* gen, gp_launch_config* cfg, fl
 
 /* Waits for the object's work and frees it (NULL is ignored). */
 void gp_generation_destroy(gp_generation* gen);
+
+/* ------------------------------------------------------------------ */
+/* A device-resident generational loop (Alg. 1 with the Sec. III-C     */
+/* order; the paper mutates on the CPU, here nothing leaves the        */
+/* device).  Two populations alternate as parents and offspring.  Each */
+/* generation is one replay of a captured graph: fitness of the        */
+/* current population (gp_fitness), the fitness recorded in a device   */
+/* history, 2 * n_programs tournaments (gp_tournament; a generation    */
+/* uses the first ones it needs, which are the same as if only those   */
+/* had run), the operation pre-draw (gp_plan_generation_device) and    */
+/* the genetic operations (gp_mutate_device).  The generation number   */
+/* lives in device memory.  At the same launch configuration every     */
+/* generation equals gp_fitness + gp_tournament + gp_plan_generation + */
+/* gp_mutate on the host, bit for bit.                                 */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_programs;        /* population size (1 .. 2^29)                        */
+    int32_t metric;            /* gp_metric (not SPEARMAN)                            */
+    float parsimony;
+    int32_t tournament_size;   /* >= 1                                                */
+    uint64_t tournament_seed;  /* Philox key of the tournaments                       */
+    gp_evolve_params evolve;
+    gp_init_params init;       /* donors of subtree mutation, point-mutation sets;   */
+                               /* init.n_features must equal the dataset's           */
+    int32_t max_generations;   /* history capacity: generations 0 .. max_generations  */
+    int32_t autotune;          /* 1: tune on the initial population (unless forced)  */
+    int32_t time_kernel;       /* 1: HIP event nodes around the evaluation kernel     */
+} gp_evolution_params;
+
+typedef struct gp_evolution_s gp_evolution;
+
+/* Uploads the HOST initial population (validated; every program at most
+ * max(evolve.max_len, its longest program) nodes is what the offspring
+ * buffers hold: each population is allocated at n_programs times that).
+ * The dataset (DEVICE memory) must outlive the object. */
+gp_status gp_evolution_create(const gp_evolution_params* params, const gp_dataset_dev* data,
+                              const uint32_t* nodes, const int64_t* prog_off, const float* consts,
+                              const int64_t* const_off, const int32_t* len, gp_evolution** out);
+
+/* Runs generations g .. g + n - 1 (g = the generations run so far): for each,
+ * the current population's fitness is recorded as entry g of the history and
+ * its offspring become the current population.  Waits for the device;
+ * GP_ERR_DEVICE if a mutation status bit was raised (see gp_mutate_device),
+ * GP_ERR_INVALID_ARG beyond max_generations. */
+gp_status gp_evolution_run(gp_evolution* evo, int32_t n_generations);
+
+/* Fitness of the current population, recorded as history entry g, without
+ * selection or mutation (the loop's last step).  Waits for the device. */
+gp_status gp_evolution_evaluate(gp_evolution* evo);
+
+/* The history: *n_recorded entries; fitness_history [n_recorded *
+ * n_programs] (entry g's fitness in row g) and nodes_history [n_recorded]
+ * (sum of lengths of generation g), HOST, nullable, at most `capacity`
+ * entries copied. */
+gp_status gp_evolution_history(const gp_evolution* evo, int32_t capacity, int32_t* n_recorded,
+                               float* fitness_history, int64_t* nodes_history);
+
+/* The current population to HOST buffers (the gp_mutate layout);
+ * GP_ERR_BUFFER_TOO_SMALL with the totals set if a capacity is short. */
+gp_status gp_evolution_population(const gp_evolution* evo, uint32_t* nodes, int64_t nodes_cap,
+                                  int64_t* prog_off, float* consts, int64_t consts_cap,
+                                  int64_t* const_off, int32_t* len, int64_t* total_nodes,
+                                  int64_t* total_consts);
+
+/* Launch configuration, the evaluation kernel's duration in the last
+ * replay (ms, -1 unless time_kernel and the event nodes were accepted),
+ * the generations run, and the autotuner's best time (-1 if not tuned).
+ * Each output is nullable. */
+gp_status gp_evolution_info(const gp_evolution* evo, gp_launch_config* cfg, float* kernel_ms,
+                            int64_t* generation, double* tuned_ms);
+
+/* Waits for the object's work and frees it (NULL is ignored). */
+void gp_evolution_destroy(gp_evolution* evo);
 
 /* ------------------------------------------------------------------ */
 /* Kernel timing.  While enabled, the library brackets every launch of */

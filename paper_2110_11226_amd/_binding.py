@@ -25,6 +25,9 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 # ---- constants mirrored from include/gp.h ----
 OP_VAR, OP_CONST, OP_ADD, OP_SUB, OP_MUL, OP_DIV, OP_NEG, OP_LOG, OP_SQRT, OP_SIN, OP_COS, OP_TAN = range(12)
+OP_MAX, OP_MIN, OP_ATAN2 = 12, 13, 14
+OP_ABS, OP_EXP, OP_INV, OP_SQ, OP_CUBE, OP_TANH, OP_ATAN, OP_CBRT = range(15, 23)
+FUNCS_ALL = sum(1 << op for op in range(OP_ADD, OP_CBRT + 1))
 MAX_STACK = 20
 FUNCS_DEFAULT = 0x7FC
 METRICS = {"mae": 0, "mse": 1, "rmse": 2, "logloss": 3, "pearson": 4, "spearman": 5}
@@ -107,6 +110,17 @@ class EvolveParams(ctypes.Structure):
 
 
 _plan = _sig("gp_plan_generation", [ctypes.POINTER(EvolveParams), _i32, _u64, _vp, _vp, _vp])
+
+
+class PopulationOutDev(ctypes.Structure):
+    _fields_ = [("nodes", _vp), ("prog_off", _vp), ("consts", _vp), ("const_off", _vp), ("len", _vp),
+                ("node_capacity", _i64), ("const_capacity", _i64)]
+
+
+_plan_dev = _sig("gp_plan_generation_device", [ctypes.POINTER(EvolveParams), _i32, _u64, _vp, _vp, _vp, _vp])
+_mutate_dev = _sig("gp_mutate_device", [ctypes.POINTER(EvolveParams), ctypes.POINTER(InitParams),
+                                        ctypes.POINTER(PopulationDev), _vp, _vp, _vp, _i32, _i32, _u64,
+                                        ctypes.POINTER(PopulationOutDev), _vp, _vp])
 _mutate = _sig("gp_mutate", [ctypes.POINTER(EvolveParams), ctypes.POINTER(InitParams), _vp, _vp, _vp, _vp, _i32,
                              _vp, _vp, _vp, _i32, _i32, _u64, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp])
 GENOPS = {"crossover": 0, "subtree": 1, "hoist": 2, "point": 3, "reproduction": 4}
@@ -303,7 +317,26 @@ class DevicePopulation:
     def make_view(self, consts):
         return PopulationDev(self.nodes.data_ptr(), self.prog_off.data_ptr(), consts.data_ptr(),
                              self.const_off.data_ptr(), self.length.data_ptr(), self.n_programs,
-                             int(self.host.nodes.shape[0]), self.max_len, self.n_consts)
+                             self.total_nodes, self.max_len, self.n_consts)
+
+    @property
+    def total_nodes(self):
+        return int(self.host.nodes.shape[0]) if self.host is not None else self._total_nodes
+
+    @classmethod
+    def from_device(cls, nodes, prog_off, consts, const_off, length, total_nodes, total_consts, max_len):
+        """A view of a population already on the device (offsets and
+        lengths describe valid programs; max_len bounds every length)."""
+        self = cls.__new__(cls)
+        self.host = None
+        self.nodes, self.prog_off, self.consts = nodes, prog_off, consts
+        self.const_off, self.length = const_off, length
+        self.n_programs = int(length.shape[0])
+        self.n_consts = int(total_consts)
+        self._total_nodes = int(total_nodes)
+        self.max_len = int(max_len)
+        self.view = self.make_view(self.consts)
+        return self
 
 
 class DeviceDataset:
@@ -493,3 +526,187 @@ def mutate(parents: HostPopulation, ops, first_tournament, winners, generation, 
     _check(rc, "gp_mutate")
     return HostPopulation(nodes[:int(tn[0])].copy(), po, consts[:int(tc[0])].copy(), co, ln[:n_off].copy())
 
+
+
+def plan_generation_device(n_offspring, generation, stream=None, **evolve):
+    """(ops, first_tournament, n_tournaments) as DEVICE int32 tensors
+    ([n_offspring], [n_offspring], [1]); gp_plan_generation_device."""
+    torch = _torch()
+    ev = _evolve_struct(**evolve)
+    n = int(n_offspring)
+    ops = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    ft = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    nt = torch.empty(1, dtype=torch.int32, device="cuda")
+    _check(_plan_dev(ctypes.byref(ev), n, int(generation), _tptr(ops), _tptr(ft), _tptr(nt), _stream(stream)),
+           "gp_plan_generation_device")
+    return ops[:n], ft[:n], nt
+
+
+MUTATE_STATUS = {1: "a capacity of the output is short; nothing was written",
+                 2: "an operation, tournament or winner index was out of range",
+                 4: "the subtree-mutation donors overflowed the library's bound"}
+
+
+class DeviceOffspring:
+    """An offspring population written on the device by gp_mutate_device."""
+
+    def __init__(self, nodes, prog_off, consts, const_off, length, info, max_len):
+        self.nodes, self.prog_off, self.consts = nodes, prog_off, consts
+        self.const_off, self.length, self.info = const_off, length, info
+        self.max_len = int(max_len)
+
+    def status(self):
+        """(total_nodes, total_consts, status bits) after synchronising."""
+        v = self.info.cpu().numpy()
+        return int(v[0]), int(v[1]), int(v[2])
+
+    def check(self):
+        tn, tc, st = self.status()
+        if st:
+            msgs = [m for b, m in MUTATE_STATUS.items() if st & b]
+            raise GPError(-1, "gp_mutate_device: " + "; ".join(msgs))
+        return tn, tc
+
+    def to_host(self) -> HostPopulation:
+        tn, tc = self.check()
+        return HostPopulation(self.nodes[:tn].cpu().numpy().view(np.uint32).copy(),
+                              self.prog_off.cpu().numpy().copy(), self.consts[:tc].cpu().numpy().copy(),
+                              self.const_off.cpu().numpy().copy(), self.length.cpu().numpy().copy())
+
+    def as_parents(self) -> DevicePopulation:
+        """This population as the next generation's device parents (reads the
+        totals, so it synchronises)."""
+        tn, tc = self.check()
+        return DevicePopulation.from_device(self.nodes, self.prog_off, self.consts, self.const_off, self.length,
+                                            tn, tc, self.max_len)
+
+
+def mutate_device(parents: DevicePopulation, ops, first_tournament, winners, generation, init: dict,
+                  stream=None, node_capacity=None, const_capacity=None, **evolve) -> DeviceOffspring:
+    """The offspring population on the device (gp_mutate_device); ops,
+    first_tournament and winners are device int32 tensors (or arrays,
+    uploaded).  The default capacities hold any outcome: every child is at
+    most max(max_len, the longest parent) nodes long."""
+    torch = _torch()
+    ev = _evolve_struct(**evolve)
+    ip = _init_struct(**init)
+
+    def dev_i32(a):
+        t = a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(a, np.int32))
+        return t.to(device="cuda", dtype=torch.int32).contiguous()
+
+    ops, ft, win = dev_i32(ops), dev_i32(first_tournament), dev_i32(winners)
+    n_off = int(ops.shape[0])
+    longest = max(int(ev.max_len), int(parents.max_len), 1)
+    ncap = int(node_capacity) if node_capacity is not None else max(n_off * longest, 1)
+    ccap = int(const_capacity) if const_capacity is not None else max(n_off * longest, 1)
+    nodes = torch.empty(max(ncap, 1), dtype=torch.int32, device="cuda")
+    consts = torch.empty(max(ccap, 1), dtype=torch.float32, device="cuda")
+    po = torch.empty(n_off + 1, dtype=torch.int64, device="cuda")
+    co = torch.empty(n_off + 1, dtype=torch.int64, device="cuda")
+    ln = torch.empty(max(n_off, 1), dtype=torch.int32, device="cuda")
+    info = torch.empty(4, dtype=torch.int64, device="cuda")
+    out = PopulationOutDev(nodes.data_ptr(), po.data_ptr(), consts.data_ptr(), co.data_ptr(), ln.data_ptr(),
+                           ncap, ccap)
+    _check(_mutate_dev(ctypes.byref(ev), ctypes.byref(ip), ctypes.byref(parents.view), _tptr(ops), _tptr(ft),
+                       _tptr(win), int(win.shape[0]), n_off, int(generation), ctypes.byref(out), _tptr(info),
+                       _stream(stream)), "gp_mutate_device")
+    return DeviceOffspring(nodes, po, consts, co, ln[:n_off], info, longest)
+
+
+class EvolutionParams(ctypes.Structure):
+    _fields_ = [("n_programs", _i32), ("metric", _i32), ("parsimony", _f32), ("tournament_size", _i32),
+                ("tournament_seed", _u64), ("evolve", EvolveParams), ("init", InitParams),
+                ("max_generations", _i32), ("autotune", _i32), ("time_kernel", _i32)]
+
+
+_evo_create = _sig("gp_evolution_create", [ctypes.POINTER(EvolutionParams), ctypes.POINTER(DatasetDev), _vp, _vp,
+                                           _vp, _vp, _vp, ctypes.POINTER(_vp)])
+_evo_run = _sig("gp_evolution_run", [_vp, _i32])
+_evo_eval = _sig("gp_evolution_evaluate", [_vp])
+_evo_hist = _sig("gp_evolution_history", [_vp, _i32, _vp, _vp, _vp])
+_evo_pop = _sig("gp_evolution_population", [_vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp])
+_evo_info = _sig("gp_evolution_info", [_vp, ctypes.POINTER(LaunchConfig), ctypes.POINTER(_f32),
+                                       ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)])
+_evo_destroy = _sig("gp_evolution_destroy", [_vp], None)
+
+
+class Evolution:
+    """The device-resident generational loop (gp_evolution_*): each generation
+    is one graph replay -- fitness, history record, tournaments, operation
+    pre-draw, genetic operations -- with no host round trip."""
+
+    def __init__(self, data: DeviceDataset, pop: HostPopulation, init: dict, evolve: dict | None = None,
+                 metric="mse", parsimony=0.0, tournament_size=20, tournament_seed=0, max_generations=100,
+                 autotune=False, time_kernel=False):
+        self.data = data
+        self.n_programs = pop.n_programs
+        ev = _evolve_struct(**(evolve or {}))
+        ip = _init_struct(**init)
+        prm = EvolutionParams(self.n_programs, metric_id(metric), float(parsimony), int(tournament_size),
+                              int(tournament_seed), ev, ip, int(max_generations), int(bool(autotune)),
+                              int(bool(time_kernel)))
+        c = pop.consts if pop.consts.shape[0] else np.zeros(1, np.float32)
+        self._keep = [np.ascontiguousarray(pop.nodes, np.uint32), np.ascontiguousarray(pop.prog_off, np.int64),
+                      np.ascontiguousarray(c, np.float32), np.ascontiguousarray(pop.const_off, np.int64),
+                      np.ascontiguousarray(pop.length, np.int32)]
+        h = _vp()
+        _check(_evo_create(ctypes.byref(prm), ctypes.byref(data.view), *[_np_ptr(a) for a in self._keep],
+                           ctypes.byref(h)), "gp_evolution_create")
+        self._h = h
+        self._keep = None
+
+    def run(self, n_generations):
+        _check(_evo_run(self._h, int(n_generations)), "gp_evolution_run")
+
+    def evaluate(self):
+        _check(_evo_eval(self._h), "gp_evolution_evaluate")
+
+    def history(self):
+        """(fitness [n_recorded, n_programs], total nodes [n_recorded])."""
+        n = _i32()
+        _check(_evo_hist(self._h, 0, ctypes.byref(n), None, None), "gp_evolution_history")
+        k = int(n.value)
+        fit = np.zeros((max(k, 1), self.n_programs), np.float32)
+        nodes = np.zeros(max(k, 1), np.int64)
+        _check(_evo_hist(self._h, k, ctypes.byref(n), _np_ptr(fit), _np_ptr(nodes)), "gp_evolution_history")
+        return fit[:k], nodes[:k]
+
+    def population(self) -> HostPopulation:
+        P = self.n_programs
+        po = np.zeros(P + 1, np.int64)
+        co = np.zeros(P + 1, np.int64)
+        ln = np.zeros(P, np.int32)
+        tn, tc = _i64(), _i64()
+        rc = _evo_pop(self._h, None, 0, _np_ptr(po), None, 0, _np_ptr(co), _np_ptr(ln), ctypes.byref(tn),
+                      ctypes.byref(tc))
+        if rc not in (0, -7):
+            _check(rc, "gp_evolution_population")
+        nodes = np.zeros(max(tn.value, 1), np.uint32)
+        consts = np.zeros(max(tc.value, 1), np.float32)
+        _check(_evo_pop(self._h, _np_ptr(nodes), nodes.shape[0], _np_ptr(po), _np_ptr(consts), consts.shape[0],
+                        _np_ptr(co), _np_ptr(ln), ctypes.byref(tn), ctypes.byref(tc)), "gp_evolution_population")
+        return HostPopulation(nodes[:tn.value].copy(), po, consts[:tc.value].copy(), co, ln)
+
+    def info(self):
+        """(launch config tuple, evaluation-kernel ms of the last replay (-1
+        if not timed), generations run, autotuner best ms (-1 if not tuned))."""
+        cfg = LaunchConfig()
+        ms = _f32()
+        g = _i64()
+        t = ctypes.c_double()
+        _check(_evo_info(self._h, ctypes.byref(cfg), ctypes.byref(ms), ctypes.byref(g), ctypes.byref(t)),
+               "gp_evolution_info")
+        return ((cfg.rows_per_lane, cfg.feature_regs, cfg.tiles_per_chunk, cfg.waves_per_block), float(ms.value),
+                int(g.value), float(t.value))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _evo_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -15,7 +15,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libgp.so")
-SOURCES = [os.path.join(CSRC, "gp_device.hip"), os.path.join(CSRC, "gp_host.cpp")]
+SOURCES = [os.path.join(CSRC, "gp_device.hip"), os.path.join(CSRC, "gp_mutate.hip"), os.path.join(CSRC, "gp_host.cpp")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

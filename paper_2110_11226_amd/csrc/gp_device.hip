@@ -86,23 +86,25 @@ struct Sched {
 //   bits 0-1  class: kPush (push a terminal), kFold (terminal fused with the
 //             binary function whose first operand it is; the current top is
 //             the second operand), kBin (binary: top op next-below), kUn
-//   bits 2-4  function: binary ADD..DIV as 0..3, unary NEG..TAN as 0..5
-//   bit 5     the terminal is a constant (value in y) rather than a feature
-//   bit 6     "active": the subtree this instruction completes holds a
+//   bits 2-5  function: binary ADD..DIV, MAX..ATAN2 as 0..6; unary NEG..TAN,
+//             ABS..CBRT as 0..13
+//   bit 6     the terminal is a constant (value in y) rather than a feature
+//   bit 7     "active": the subtree this instruction completes holds a
 //             constant (only such instructions carry derivatives back)
 //   bits 8-31 feature index, or the constant's slot
 //   y         a constant's float bits; for an inactive instruction, the
 //             index of the first instruction of the subtree it completes
 //   z         up to 8 unary functions applied, in order, to the result of
 //             the instruction (4 bits each from the lowest: unary function
-//             + 1; 0 ends the chain), so that a unary function costs no
+//             index + 1; 0 ends the chain), so that a unary function costs no
 //             dispatch of its own
 // ---------------------------------------------------------------------------
 enum : uint32_t { kPush = 0, kFold = 1, kBin = 2, kUn = 3 };
-constexpr uint32_t kActive = 64u;
+constexpr uint32_t kConstBit = 64u;
+constexpr uint32_t kActive = 128u;
 
 GP_HD uint32_t enc(uint32_t cls, uint32_t fn, uint32_t is_const, uint32_t arg) {
-    return cls | (fn << 2) | (is_const << 5) | (arg << 8);
+    return cls | (fn << 2) | (is_const << 6) | (arg << 8);
 }
 
 // ---------------------------------------------------------------------------
@@ -150,11 +152,82 @@ __device__ __forceinline__ float op_log(float a) {
     return fabsf(a) > GP_PROTECT_EPS ? logf(fabsf(a)) : 0.0f;
 }
 __device__ __forceinline__ float op_sqrt(float a) { return sqrtf(fabsf(a)); }
+__device__ __forceinline__ float op_inv(float a) {
+    return fabsf(a) > GP_PROTECT_EPS ? 1.0f / a : 0.0f;
+}
 
-// a = a (op) b for the binary function index fn (ADD, SUB, MUL, DIV)
+// a = a (op) b for the wider binary functions (MAX, MIN, ATAN2 as 4..6)
+template <int R>
+__device__ __forceinline__ void apply_binary_wide(uint32_t fn, float (&a)[R], const float (&b)[R]) {
+    // max / min ignore a NaN operand; on equal operands the sign bits are
+    // combined so that -0 orders below +0 whatever order fmaxf takes them in
+    if (fn == 4) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const float m = fmaxf(a[j], b[j]);
+            a[j] = a[j] == b[j] ? __int_as_float(__float_as_int(a[j]) & __float_as_int(b[j])) : m;
+        }
+    } else if (fn == 5) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const float m = fminf(a[j], b[j]);
+            a[j] = a[j] == b[j] ? __int_as_float(__float_as_int(a[j]) | __float_as_int(b[j])) : m;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < R; ++j) a[j] = atan2f(a[j], b[j]);
+    }
+}
+
+// t = f(t) for the wider unary functions (ABS..CBRT as 6..13)
+template <int R>
+__device__ __forceinline__ void apply_unary_wide(uint32_t fn, float (&t)[R]) {
+    switch (fn) {
+    case 6:
+#pragma unroll
+        for (int j = 0; j < R; ++j) t[j] = fabsf(t[j]);
+        break;
+    case 7:
+#pragma unroll
+        for (int j = 0; j < R; ++j) t[j] = expf(t[j]);
+        break;
+    case 8:
+#pragma unroll
+        for (int j = 0; j < R; ++j) t[j] = op_inv(t[j]);
+        break;
+    case 9:
+#pragma unroll
+        for (int j = 0; j < R; ++j) t[j] = t[j] * t[j];
+        break;
+    case 10:
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const float q = t[j] * t[j];
+            t[j] = q * t[j];
+        }
+        break;
+    case 11:
+#pragma unroll
+        for (int j = 0; j < R; ++j) t[j] = tanhf(t[j]);
+        break;
+    case 12:
+#pragma unroll
+        for (int j = 0; j < R; ++j) t[j] = atanf(t[j]);
+        break;
+    default:
+#pragma unroll
+        for (int j = 0; j < R; ++j) t[j] = cbrtf(t[j]);
+        break;
+    }
+}
+
+// a = a (op) b for the binary function index fn (ADD, SUB, MUL, DIV first,
+// then the wider set)
 template <int R>
 __device__ __forceinline__ void apply_binary(uint32_t fn, float (&a)[R], const float (&b)[R]) {
-    if (fn < 2) {
+    if (fn >= 4) {
+        apply_binary_wide<R>(fn, a, b);
+    } else if (fn < 2) {
         if (fn == 0) {
 #pragma unroll
             for (int j = 0; j < R; ++j) a[j] = a[j] + b[j];
@@ -173,10 +246,13 @@ __device__ __forceinline__ void apply_binary(uint32_t fn, float (&a)[R], const f
     }
 }
 
-// t = f(t) for the unary function index fn (NEG, LOG, SQRT, SIN, COS, TAN)
+// t = f(t) for the unary function index fn (NEG, LOG, SQRT, SIN, COS, TAN
+// first, then the wider set)
 template <int R>
 __device__ __forceinline__ void apply_unary(uint32_t fn, float (&t)[R]) {
-    if (fn < 3) {
+    if (fn >= 6) {
+        apply_unary_wide<R>(fn, t);
+    } else if (fn < 3) {
         if (fn == 0) {
 #pragma unroll
             for (int j = 0; j < R; ++j) t[j] = -t[j];
@@ -239,18 +315,19 @@ __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint4* __restri
         const uint32_t op = w & 0xffu;
         const uint32_t arg = w >> 8;
         const int top_i = min(max(h - 1, 0), GP_MAX_STACK - 1);
-        if (op > GP_OP_DIV && fold && h >= 1 && ((sh[top_i * kBlock] >> 30) & 1u)) {
+        const int ar = arity(op);
+        if (ar == 1 && fold && h >= 1 && ((sh[top_i * kBlock] >> 30) & 1u)) {
             // unary of a constant: the pending instruction is that constant's push
             float t[1] = {shv[top_i * kBlock]};
-            apply_unary<1>(op - GP_OP_NEG, t);
+            apply_unary<1>(unary_index(op), t);
             shv[top_i * kBlock] = t[0];
             pend.y = __float_as_uint(t[0]);
             continue;
         }
-        if (op > GP_OP_DIV && chain >= 0 && chain < 8) {
+        if (ar == 1 && chain >= 0 && chain < 8) {
             // a unary function applied to the pending instruction's result:
             // same subtree start and activity as its operand
-            pend.z |= (op - GP_OP_NEG + 1u) << (4 * chain);
+            pend.z |= (unary_index(op) + 1u) << (4 * chain);
             ++chain;
             continue;
         }
@@ -261,14 +338,14 @@ __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint4* __restri
             const uint32_t is_c = op == GP_OP_CONST ? 1u : 0u;
             const uint32_t farg = arg;   // feature index, or constant slot (used by the adjoint)
             const uint32_t prev = i >= 1 ? (pn[i - 1] & 0xffu) : 0u;
-            if (i >= 1 && i != L - 1 && prev >= GP_OP_ADD && prev <= GP_OP_DIV) {
+            if (i >= 1 && i != L - 1 && arity(prev) == 2) {
                 const uint32_t top = sh[top_i * kBlock];    // the second operand
                 start = top & kShStartMask;
                 if (fold && is_c && ((top >> 30) & 1u)) {
                     // constant op constant: evaluated here
                     float a[1] = {pc[arg]};
                     const float b[1] = {shv[top_i * kBlock]};
-                    apply_binary<1>(prev - GP_OP_ADD, a, b);
+                    apply_binary<1>(binary_index(prev), a, b);
                     x = enc(kPush, 0, 1u, 0u);
                     active = 1u;
                     konst = 1u;
@@ -276,7 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint4* __restri
                     k = static_cast<int32_t>(start);   // drop the operand's instructions
                     chain = -1;
                 } else {
-                    x = enc(kFold, prev - GP_OP_ADD, is_c, farg);
+                    x = enc(kFold, binary_index(prev), is_c, farg);
                     active = is_c | (top >> 31);
                 }
                 --h;
@@ -290,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint4* __restri
             }
             xy = (is_c || konst) ? make_uint2(x | kActive, __float_as_uint(konst ? kval : pc[arg]))
                                  : make_uint2(x | (active ? kActive : 0u), start);
-        } else if (op <= GP_OP_DIV) {
+        } else if (ar == 2) {
             const int i1 = min(max(h - 1, 0), GP_MAX_STACK - 1), i2 = min(max(h - 2, 0), GP_MAX_STACK - 1);
             const uint32_t first = sh[i1 * kBlock];      // top: the first operand
             const uint32_t second = sh[i2 * kBlock];     // evaluated before it
@@ -299,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint4* __restri
             if (fold && ((first >> 30) & 1u) && ((second >> 30) & 1u)) {
                 float a[1] = {shv[i1 * kBlock]};
                 const float b[1] = {shv[i2 * kBlock]};
-                apply_binary<1>(op - GP_OP_ADD, a, b);
+                apply_binary<1>(binary_index(op), a, b);
                 x = enc(kPush, 0, 1u, 0u);
                 active = 1u;
                 konst = 1u;
@@ -308,14 +385,14 @@ __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint4* __restri
                 chain = -1;
                 xy = make_uint2(x | kActive, __float_as_uint(kval));
             } else {
-                x = enc(kBin, op - GP_OP_ADD, 0, 0);
+                x = enc(kBin, binary_index(op), 0, 0);
                 active = (first >> 31) | (second >> 31);
                 xy = make_uint2(x | (active ? kActive : 0u), start);
             }
         } else {
             // a unary function with a full chain before it: its own instruction
             const uint32_t top = sh[top_i * kBlock];
-            x = enc(kUn, op - GP_OP_NEG, 0, 0);
+            x = enc(kUn, unary_index(op), 0, 0);
             start = top & kShStartMask;
             active = top >> 31;
             --h;
@@ -502,7 +579,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(PopView pop, CodeView cv, DataV
                 nxt = pcode[min(q + 1, CL - 1)];
                 const uint32_t w = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(cur.x)));
                 const uint32_t cls = w & 3u;
-                const uint32_t fn = (w >> 2) & 7u;
+                const uint32_t fn = (w >> 2) & 15u;
                 const int up = min(dp + 1, kStackRegs);
                 GP_PUT(st, up, t);
                 float a[R], b[R];
@@ -522,7 +599,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(PopView pop, CodeView cv, DataV
                     binary = true;
                 } else {
                     float v[R];
-                    if (w & 32u) {
+                    if (w & kConstBit) {
                         const float cval = __uint_as_float(cur.y);
 #pragma unroll
                         for (int j = 0; j < R; ++j) v[j] = cval;
@@ -767,8 +844,8 @@ constexpr int64_t adjoint_wave_floats(int64_t tape_entries_max) {
     return (2 * kStackLds + beyond) * R * kWave;
 }
 
-// derivative of unary function fn (1..5: log, sqrt, sin, cos, tan) at input
-// x, whose result is y (reading above)
+// derivative of unary function fn (1..5: log, sqrt, sin, cos, tan; 6..13:
+// abs, exp, inv, sq, cube, tanh, atan, cbrt) at input x, whose result is y
 template <int R>
 __device__ __forceinline__ void unary_derivative(uint32_t fn, const float (&x)[R], const float (&y)[R],
                                                  float (&dv)[R]) {
@@ -779,7 +856,15 @@ __device__ __forceinline__ void unary_derivative(uint32_t fn, const float (&x)[R
         case 2: dv[j] = x[j] == 0.0f ? 0.0f : copysignf(1.0f, x[j]) / (2.0f * y[j]); break;
         case 3: dv[j] = cosf(x[j]); break;
         case 4: dv[j] = -sinf(x[j]); break;
-        default: dv[j] = 1.0f + y[j] * y[j]; break;
+        case 5: dv[j] = 1.0f + y[j] * y[j]; break;
+        case 6: dv[j] = x[j] > 0.0f ? 1.0f : (x[j] < 0.0f ? -1.0f : 0.0f); break;
+        case 7: dv[j] = y[j]; break;
+        case 8: dv[j] = fabsf(x[j]) > GP_PROTECT_EPS ? -y[j] * y[j] : 0.0f; break;
+        case 9: dv[j] = 2.0f * x[j]; break;
+        case 10: dv[j] = 3.0f * (x[j] * x[j]); break;
+        case 11: dv[j] = 1.0f - y[j] * y[j]; break;
+        case 12: dv[j] = 1.0f / (1.0f + x[j] * x[j]); break;
+        default: dv[j] = y[j] != 0.0f ? 1.0f / (3.0f * (y[j] * y[j])) : 0.0f; break;
         }
     }
 }
@@ -892,7 +977,7 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                 nxt = pcode[min(q + 1, CL - 1)];
                 const uint32_t w = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(cur.x)));
                 const uint32_t cls = w & 3u;
-                const uint32_t fn = (w >> 2) & 7u;
+                const uint32_t fn = (w >> 2) & 15u;
                 const bool act = (w & kActive) != 0u;
                 GP_PUT(st, min(dp + 1, kStackRegs), t);
                 float a[R], b[R];
@@ -921,7 +1006,7 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                     binary = true;
                 } else {
                     float v[R];
-                    if (w & 32u) {
+                    if (w & kConstBit) {
                         const float cval = __uint_as_float(cur.y);
 #pragma unroll
                         for (int j = 0; j < R; ++j) v[j] = cval;
@@ -954,20 +1039,31 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                     }
                 }
                 if (binary) {
-                    if (fn >= 2 && act) {   // mul / div: both partials
+                    if (fn >= 2 && act) {   // mul, div, max, min, atan2: both partials
                         float da[R], db[R];
 #pragma unroll
                         for (int j = 0; j < R; ++j) {
                             if (fn == 2) {
                                 da[j] = b[j];
                                 db[j] = a[j];
-                            } else if (fabsf(b[j]) > GP_PROTECT_EPS) {
-                                const float inv = 1.0f / b[j];
-                                da[j] = inv;
-                                db[j] = -a[j] * inv * inv;
+                            } else if (fn == 3) {
+                                if (fabsf(b[j]) > GP_PROTECT_EPS) {
+                                    const float inv = 1.0f / b[j];
+                                    da[j] = inv;
+                                    db[j] = -a[j] * inv * inv;
+                                } else {
+                                    da[j] = 0.0f;
+                                    db[j] = 0.0f;
+                                }
+                            } else if (fn == 4 || fn == 5) {
+                                // the selected operand (the first on ties) carries it
+                                const bool first = (fn == 4 ? a[j] >= b[j] : a[j] <= b[j]) || isnan(b[j]);
+                                da[j] = first ? 1.0f : 0.0f;
+                                db[j] = first ? 0.0f : 1.0f;
                             } else {
-                                da[j] = 0.0f;
-                                db[j] = 0.0f;
+                                const float r2 = a[j] * a[j] + b[j] * b[j];
+                                da[j] = r2 > 0.0f ? b[j] / r2 : 0.0f;
+                                db[j] = r2 > 0.0f ? -a[j] / r2 : 0.0f;
                             }
                         }
                         tape_put(ntape, da);
@@ -1063,7 +1159,7 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                     continue;
                 }
                 const uint32_t cls = w & 3u;
-                const uint32_t fn = (w >> 2) & 7u;
+                const uint32_t fn = (w >> 2) & 15u;
                 // the chained unary functions first, the last one first
                 const uint32_t chain = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(cur.z)));
                 if (chain != 0u) {
@@ -1143,7 +1239,7 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                     }
                 }
                 // a constant terminal: its adjoint summed over the wavefront's rows
-                if (cls <= kFold && (w & 32u)) {
+                if (cls <= kFold && (w & kConstBit)) {
                     const int slot = static_cast<int>(w >> 8);
                     double sum = 0.0;
 #pragma unroll
@@ -1496,12 +1592,6 @@ __global__ __launch_bounds__(kWave) void k_stamp(uint64_t* __restrict__ out) {
 // ---------------------------------------------------------------------------
 // Host side: scratch, launch configuration, entry points.
 // ---------------------------------------------------------------------------
-#define GP_HIP(expr)                                                                   \
-    do {                                                                               \
-        hipError_t e_ = (expr);                                                        \
-        if (e_ != hipSuccess)                                                          \
-            return fail(GP_ERR_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
-    } while (0)
 
 struct DeviceScratch {
     void* counter = nullptr;     // 256 bytes: the work counter
@@ -2216,6 +2306,184 @@ bool insert_event_nodes(hipGraph_t graph, const void* func, hipEvent_t ev_a, hip
     return true;
 }
 
+// ---------------------------------------------------------------------------
+// The device-resident loop: two alternating populations, a fitness history,
+// the generation counter in device memory.
+// ---------------------------------------------------------------------------
+// History entry *gen: the fitness of every program and the population's
+// node count (prog_off[P]).
+__global__ void k_evo_record(const float* __restrict__ fit, int32_t P, const uint32_t* __restrict__ gen,
+                             int32_t cap, float* __restrict__ hist, int64_t* __restrict__ hist_nodes,
+                             const int64_t* __restrict__ prog_off) {
+    const uint32_t g = *gen;
+    if (g >= static_cast<uint32_t>(cap)) return;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < P) hist[static_cast<int64_t>(g) * P + i] = fit[i];
+    if (i == 0) hist_nodes[g] = prog_off[P];
+}
+
+// End of a generation: keep the mutation status bits, advance the counter.
+__global__ void k_evo_step(uint32_t* __restrict__ gen, const int64_t* __restrict__ info,
+                           unsigned long long* __restrict__ sticky) {
+    if (threadIdx.x == 0) {
+        *sticky |= static_cast<unsigned long long>(info[2]);
+        *gen += 1u;
+    }
+}
+
+// Sets the counter and the status word (a fill kernel: no memset node).
+__global__ void k_evo_set(uint32_t* __restrict__ gen, uint32_t g, unsigned long long* __restrict__ sticky) {
+    if (threadIdx.x == 0) {
+        *gen = g;
+        *sticky = 0ull;
+    }
+}
+
+}  // namespace
+
+struct EvoPop {
+    uint32_t* nodes = nullptr;
+    int64_t* prog_off = nullptr;
+    float* consts = nullptr;
+    int64_t* const_off = nullptr;
+    int32_t* len = nullptr;
+};
+
+struct gp_evolution_s {
+    gp_evolution_params prm{};
+    gp_dataset_dev data{};
+    int dev = 0;
+    hipStream_t stream = nullptr;
+    DeviceScratch sc;
+    MutateWork mw;
+    EvoPop pop[2];
+    int64_t node_cap = 0, const_cap = 0;
+    int cur = 0;                         // the current population
+    float* d_fit = nullptr;
+    int32_t* d_win = nullptr;            // [2P]
+    int32_t* d_ops = nullptr;
+    int32_t* d_first = nullptr;
+    int32_t* d_nt = nullptr;
+    int64_t* d_info = nullptr;           // [4]
+    uint32_t* d_gen = nullptr;
+    unsigned long long* d_sticky = nullptr;
+    float* d_hist = nullptr;             // [(max_generations + 1) * P]
+    int64_t* d_hist_nodes = nullptr;     // [max_generations + 1]
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
+    bool events = false;
+    const void* eval_kernel = nullptr;
+    LaunchCfg cfg{4, 0, 1};
+    double tuned_ms = -1.0;
+    float kernel_ms = -1.0f;
+    int64_t generation = 0;              // generations run (host mirror of *d_gen)
+    int64_t recorded = 0;                // history entries written
+    bool captured = false;
+};
+
+namespace {
+
+gp_population_dev evo_view(const gp_evolution_s* e, int which) {
+    gp_population_dev v{};
+    const EvoPop& q = e->pop[which];
+    v.nodes = q.nodes;
+    v.prog_off = q.prog_off;
+    v.consts = q.consts;
+    v.const_off = q.const_off;
+    v.len = q.len;
+    v.n_programs = e->prm.n_programs;
+    v.total_nodes = e->node_cap;
+    v.max_len = 0;
+    v.total_consts = e->const_cap;
+    return v;
+}
+
+void evolution_release(gp_evolution_s* e) {
+    if (e->stream) (void)hipStreamSynchronize(e->stream);
+    for (int k = 0; k < 2; ++k) {
+        if (e->exec[k]) (void)hipGraphExecDestroy(e->exec[k]);
+        if (e->graph[k]) (void)hipGraphDestroy(e->graph[k]);
+        EvoPop& q = e->pop[k];
+        for (void* p : {static_cast<void*>(q.nodes), static_cast<void*>(q.prog_off), static_cast<void*>(q.consts),
+                        static_cast<void*>(q.const_off), static_cast<void*>(q.len)})
+            if (p) (void)hipFree(p);
+        q = EvoPop{};
+    }
+    if (e->ev_a) (void)hipEventDestroy(e->ev_a);
+    if (e->ev_b) (void)hipEventDestroy(e->ev_b);
+    for (void* p : {static_cast<void*>(e->d_fit), static_cast<void*>(e->d_win), static_cast<void*>(e->d_ops),
+                    static_cast<void*>(e->d_first), static_cast<void*>(e->d_nt), static_cast<void*>(e->d_info),
+                    static_cast<void*>(e->d_gen), static_cast<void*>(e->d_sticky), static_cast<void*>(e->d_hist),
+                    static_cast<void*>(e->d_hist_nodes)})
+        if (p) (void)hipFree(p);
+    mutate_work_free(&e->mw);
+    scratch_free(e->sc);
+    if (e->stream) (void)hipStreamDestroy(e->stream);
+}
+
+// Fitness of population `which` and its history entry (plain launches or
+// under capture).
+gp_status evo_evaluate(gp_evolution_s* e, int which, bool timed) {
+    const gp_evolution_params& p = e->prm;
+    const gp_population_dev v = evo_view(e, which);
+    Timing tm;
+    if (timed) tm.launched = &e->eval_kernel;
+    gp_status rc = fitness_impl(&e->sc, &v, &e->data, p.metric, e->d_fit, e->stream, &e->cfg, tm);
+    if (rc != GP_OK) return rc;
+    const int32_t P = p.n_programs;
+    hipLaunchKernelGGL(k_evo_record, dim3((P + 255) / 256), dim3(256), 0, e->stream, e->d_fit, P, e->d_gen,
+                       p.max_generations + 1, e->d_hist, e->d_hist_nodes, v.prog_off);
+    GP_HIP(hipGetLastError());
+    return GP_OK;
+}
+
+// One generation from population a to population a ^ 1 (recorded under capture).
+gp_status record_evolution(gp_evolution_s* e, int a) {
+    const gp_evolution_params& p = e->prm;
+    const int32_t P = p.n_programs;
+    gp_status rc = evo_evaluate(e, a, true);
+    if (rc != GP_OK) return rc;
+    const gp_population_dev v = evo_view(e, a);
+    rc = tournament_impl(e->d_fit, v.len, P, gp_metric_larger_is_better(static_cast<gp_metric>(p.metric)),
+                         p.parsimony, p.tournament_size, 2 * P, p.tournament_seed, 0, e->d_gen, e->d_win, e->stream);
+    if (rc != GP_OK) return rc;
+    rc = plan_launch(p.evolve, P, 0, e->d_gen, e->d_ops, e->d_first, e->d_nt, e->stream);
+    if (rc != GP_OK) return rc;
+    const EvoPop& b = e->pop[a ^ 1];
+    const gp_population_out_dev out{b.nodes, b.prog_off, b.consts, b.const_off, b.len, e->node_cap, e->const_cap};
+    rc = mutate_launch(e->mw, p.evolve, p.init, v, e->d_ops, e->d_first, e->d_win, 2 * P, P, 0, e->d_gen, out,
+                       e->d_info, e->stream);
+    if (rc != GP_OK) return rc;
+    hipLaunchKernelGGL(k_evo_step, dim3(1), dim3(64), 0, e->stream, e->d_gen, e->d_info, e->d_sticky);
+    GP_HIP(hipGetLastError());
+    return GP_OK;
+}
+
+gp_status evo_capture(gp_evolution_s* e, int a, bool with_events, bool* got_events) {
+    *got_events = false;
+    GP_HIP(hipStreamSynchronize(e->stream));
+    GP_HIP(hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal));
+    gp_status rc = record_evolution(e, a);
+    hipGraph_t graph = nullptr;
+    const hipError_t err = hipStreamEndCapture(e->stream, &graph);
+    if (rc != GP_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (err != hipSuccess) return fail(GP_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(err));
+    if (with_events) {
+        if (!insert_event_nodes(graph, e->eval_kernel, e->ev_a, e->ev_b)) {
+            // a half-edited graph is not used: capture again without events
+            (void)hipGraphDestroy(graph);
+            return evo_capture(e, a, false, got_events);
+        }
+        *got_events = true;
+    }
+    e->graph[a] = graph;
+    return GP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2623,6 +2891,241 @@ void gp_generation_destroy(gp_generation* g) {
     generation_release(g);
     (void)hipSetDevice(cur);
     delete g;
+}
+
+gp_status gp_evolution_create(const gp_evolution_params* prm, const gp_dataset_dev* data, const uint32_t* nodes,
+                              const int64_t* prog_off, const float* consts, const int64_t* const_off,
+                              const int32_t* len, gp_evolution** out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!prm || !out || !nodes || !prog_off || !const_off || !len)
+        return fail(GP_ERR_INVALID_ARG, "gp_evolution_create: NULL argument");
+    *out = nullptr;
+    gp_status rc = check_data(data, "gp_evolution_create", true);
+    if (rc != GP_OK) return rc;
+    rc = check_fitness_metric(prm->metric, "gp_evolution_create");
+    if (rc != GP_OK) return rc;
+    const int32_t P = prm->n_programs;
+    if (P < 1 || P > (1 << 29) || prm->tournament_size < 1 || prm->max_generations < 1 ||
+        prm->max_generations > (1 << 24) || prm->autotune < 0 || prm->time_kernel < 0)
+        return fail(GP_ERR_INVALID_ARG, "gp_evolution_create: need 1 <= n_programs <= 2^29, tournament_size >= 1, "
+                                        "1 <= max_generations <= 2^24");
+    rc = mutate_check(&prm->evolve, &prm->init, P, "gp_evolution_create");
+    if (rc != GP_OK) return rc;
+    if (prm->init.n_features != data->n_features)
+        return fail(GP_ERR_INVALID_ARG, "gp_evolution_create: init.n_features must equal the dataset's");
+    if (prog_off[0] != 0 || const_off[0] != 0)
+        return fail(GP_ERR_INVALID_ARG, "gp_evolution_create: offsets must start at 0");
+    int32_t longest = 1;
+    for (int32_t q = 0; q < P; ++q) {
+        if (len[q] != prog_off[q + 1] - prog_off[q] || len[q] < 1 || const_off[q + 1] < const_off[q])
+            return fail(GP_ERR_INVALID_ARG, "gp_evolution_create: len / offsets are inconsistent at program " +
+                                                std::to_string(q));
+        longest = std::max(longest, len[q]);
+    }
+    if (const_off[P] > 0 && !consts) return fail(GP_ERR_INVALID_ARG, "gp_evolution_create: consts is NULL");
+    rc = gp_validate_population(nodes, prog_off, const_off, P, data->n_features, nullptr, nullptr);
+    if (rc != GP_OK) return rc;
+    const int64_t lmax = std::max<int64_t>(prm->evolve.max_len, longest);
+    const int64_t cap = static_cast<int64_t>(P) * lmax;
+    if (cap > (int64_t{1} << 32))
+        return fail(GP_ERR_INVALID_ARG, "gp_evolution_create: n_programs * max length above 2^32 nodes");
+    auto* e = new (std::nothrow) gp_evolution_s();
+    if (!e) return fail(GP_ERR_OUT_OF_MEMORY, "gp_evolution_create: out of host memory");
+    e->prm = *prm;
+    e->data = *data;
+    e->node_cap = cap;
+    e->const_cap = cap;
+    auto bail = [&](gp_status r) {
+        evolution_release(e);
+        delete e;
+        return r;
+    };
+    auto hip = [&](hipError_t err, const char* what) -> gp_status {
+        return err == hipSuccess ? GP_OK : fail(GP_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(err));
+    };
+    auto dmalloc = [&](void** ptr, size_t bytes) -> gp_status {
+        return hipMalloc(ptr, std::max<size_t>(bytes, 4)) == hipSuccess
+                   ? GP_OK
+                   : fail(GP_ERR_OUT_OF_MEMORY, "gp_evolution_create: hipMalloc failed");
+    };
+    if ((rc = hip(hipGetDevice(&e->dev), "hipGetDevice")) != GP_OK) return bail(rc);
+    if ((rc = scratch_init(e->sc, e->dev)) != GP_OK) return bail(rc);
+    if ((rc = hip(hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking), "hipStreamCreate")) != GP_OK)
+        return bail(rc);
+    for (int k = 0; k < 2; ++k) {
+        EvoPop& q = e->pop[k];
+        if ((rc = dmalloc(reinterpret_cast<void**>(&q.nodes), sizeof(uint32_t) * cap)) != GP_OK) return bail(rc);
+        if ((rc = dmalloc(reinterpret_cast<void**>(&q.consts), sizeof(float) * cap)) != GP_OK) return bail(rc);
+        if ((rc = dmalloc(reinterpret_cast<void**>(&q.prog_off), sizeof(int64_t) * (P + 1))) != GP_OK) return bail(rc);
+        if ((rc = dmalloc(reinterpret_cast<void**>(&q.const_off), sizeof(int64_t) * (P + 1))) != GP_OK)
+            return bail(rc);
+        if ((rc = dmalloc(reinterpret_cast<void**>(&q.len), sizeof(int32_t) * P)) != GP_OK) return bail(rc);
+    }
+    const size_t hist_n = static_cast<size_t>(prm->max_generations + 1);
+    if ((rc = dmalloc(reinterpret_cast<void**>(&e->d_fit), sizeof(float) * P)) != GP_OK ||
+        (rc = dmalloc(reinterpret_cast<void**>(&e->d_win), sizeof(int32_t) * 2 * P)) != GP_OK ||
+        (rc = dmalloc(reinterpret_cast<void**>(&e->d_ops), sizeof(int32_t) * P)) != GP_OK ||
+        (rc = dmalloc(reinterpret_cast<void**>(&e->d_first), sizeof(int32_t) * P)) != GP_OK ||
+        (rc = dmalloc(reinterpret_cast<void**>(&e->d_nt), sizeof(int32_t))) != GP_OK ||
+        (rc = dmalloc(reinterpret_cast<void**>(&e->d_info), sizeof(int64_t) * 4)) != GP_OK ||
+        (rc = dmalloc(reinterpret_cast<void**>(&e->d_gen), sizeof(uint32_t))) != GP_OK ||
+        (rc = dmalloc(reinterpret_cast<void**>(&e->d_sticky), sizeof(unsigned long long))) != GP_OK ||
+        (rc = dmalloc(reinterpret_cast<void**>(&e->d_hist), sizeof(float) * hist_n * P)) != GP_OK ||
+        (rc = dmalloc(reinterpret_cast<void**>(&e->d_hist_nodes), sizeof(int64_t) * hist_n)) != GP_OK)
+        return bail(rc);
+    if ((rc = mutate_work_reserve(&e->mw, P, prm->init)) != GP_OK) return bail(rc);
+    // the initial population
+    const EvoPop& q0 = e->pop[0];
+    if ((rc = hip(hipMemcpy(q0.nodes, nodes, sizeof(uint32_t) * prog_off[P], hipMemcpyHostToDevice), "hipMemcpy")) !=
+            GP_OK ||
+        (const_off[P] > 0 &&
+         (rc = hip(hipMemcpy(q0.consts, consts, sizeof(float) * const_off[P], hipMemcpyHostToDevice), "hipMemcpy")) !=
+             GP_OK) ||
+        (rc = hip(hipMemcpy(q0.prog_off, prog_off, sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice), "hipMemcpy")) !=
+            GP_OK ||
+        (rc = hip(hipMemcpy(q0.const_off, const_off, sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice),
+                  "hipMemcpy")) != GP_OK ||
+        (rc = hip(hipMemcpy(q0.len, len, sizeof(int32_t) * P, hipMemcpyHostToDevice), "hipMemcpy")) != GP_OK)
+        return bail(rc);
+    hipLaunchKernelGGL(k_evo_set, dim3(1), dim3(64), 0, e->stream, e->d_gen, 0u, e->d_sticky);
+    if ((rc = hip(hipGetLastError(), "k_evo_set")) != GP_OK) return bail(rc);
+    if ((rc = hip(hipStreamSynchronize(e->stream), "hipStreamSynchronize")) != GP_OK) return bail(rc);
+    *out = e;
+    return GP_OK;
+}
+
+namespace {
+gp_status evo_prepare(gp_evolution_s* e) {
+    if (e->captured) return GP_OK;
+    const gp_evolution_params& p = e->prm;
+    const int32_t P = p.n_programs;
+    e->cfg = pick_cfg(e->sc, e->data.n_features, e->data.n_rows, P, kernel_class(1, p.metric));
+    if (p.autotune && !g_forced) {
+        const gp_population_dev v = evo_view(e, e->cur);
+        gp_status rc = autotune_impl(&e->sc, &v, &e->data, p.metric, 2, e->stream, &e->cfg, &e->tuned_ms);
+        if (rc != GP_OK) return rc;
+    }
+    int64_t chunk = 0, n_chunks = 0;
+    const gp_population_dev v = evo_view(e, 0);
+    gp_status rc = chunking(&v, &e->data, e->cfg, &chunk, &n_chunks);
+    if (rc != GP_OK) return rc;
+    rc = reserve(&e->sc, P, e->node_cap, n_chunks, 1, p.metric);
+    if (rc != GP_OK) return rc;
+    if (p.time_kernel) {
+        GP_HIP(hipEventCreate(&e->ev_a));
+        GP_HIP(hipEventCreate(&e->ev_b));
+    }
+    // events count only if both graphs carry them
+    bool events = p.time_kernel != 0;
+    for (int a = 0; a < 2; ++a) {
+        bool got = false;
+        rc = evo_capture(e, a, p.time_kernel != 0, &got);
+        if (rc != GP_OK) return rc;
+        events = events && got;
+        GP_HIP(hipGraphInstantiate(&e->exec[a], e->graph[a], nullptr, nullptr, 0));
+    }
+    e->events = events;
+    e->captured = true;
+    return GP_OK;
+}
+}  // namespace
+
+gp_status gp_evolution_run(gp_evolution* e, int32_t n) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!e || n < 0) return fail(GP_ERR_INVALID_ARG, "gp_evolution_run: bad arguments");
+    if (e->generation + n > e->prm.max_generations)
+        return fail(GP_ERR_INVALID_ARG, "gp_evolution_run: beyond max_generations");
+    int cur_dev = 0;
+    GP_HIP(hipGetDevice(&cur_dev));
+    if (cur_dev != e->dev) return fail(GP_ERR_INVALID_ARG, "gp_evolution_run: another device is current");
+    gp_status rc = evo_prepare(e);
+    if (rc != GP_OK) return rc;
+    for (int32_t k = 0; k < n; ++k) {
+        GP_HIP(hipGraphLaunch(e->exec[e->cur], e->stream));
+        e->cur ^= 1;
+    }
+    GP_HIP(hipStreamSynchronize(e->stream));
+    e->generation += n;
+    e->recorded = std::max(e->recorded, e->generation);
+    unsigned long long sticky = 0;
+    GP_HIP(hipMemcpy(&sticky, e->d_sticky, sizeof sticky, hipMemcpyDeviceToHost));
+    if (n > 0 && e->events) GP_HIP(hipEventElapsedTime(&e->kernel_ms, e->ev_a, e->ev_b));
+    if (sticky)
+        return fail(GP_ERR_DEVICE, "gp_evolution_run: mutation status bits " + std::to_string(sticky) +
+                                       " (1 capacity, 2 index out of range, 4 donor bound)");
+    return GP_OK;
+}
+
+gp_status gp_evolution_evaluate(gp_evolution* e) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!e) return fail(GP_ERR_INVALID_ARG, "gp_evolution_evaluate: NULL");
+    if (e->generation > e->prm.max_generations)
+        return fail(GP_ERR_INVALID_ARG, "gp_evolution_evaluate: beyond max_generations");
+    gp_status rc = evo_prepare(e);
+    if (rc != GP_OK) return rc;
+    rc = evo_evaluate(e, e->cur, false);
+    if (rc != GP_OK) return rc;
+    GP_HIP(hipStreamSynchronize(e->stream));
+    e->recorded = std::max(e->recorded, e->generation + 1);
+    return GP_OK;
+}
+
+gp_status gp_evolution_history(const gp_evolution* e, int32_t capacity, int32_t* n_recorded, float* fitness_history,
+                               int64_t* nodes_history) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!e || capacity < 0) return fail(GP_ERR_INVALID_ARG, "gp_evolution_history: bad arguments");
+    if (n_recorded) *n_recorded = static_cast<int32_t>(e->recorded);
+    const int64_t n = std::min<int64_t>(capacity, e->recorded);
+    const int64_t P = e->prm.n_programs;
+    GP_HIP(hipStreamSynchronize(e->stream));
+    if (fitness_history && n > 0)
+        GP_HIP(hipMemcpy(fitness_history, e->d_hist, sizeof(float) * n * P, hipMemcpyDeviceToHost));
+    if (nodes_history && n > 0)
+        GP_HIP(hipMemcpy(nodes_history, e->d_hist_nodes, sizeof(int64_t) * n, hipMemcpyDeviceToHost));
+    return GP_OK;
+}
+
+gp_status gp_evolution_population(const gp_evolution* e, uint32_t* nodes, int64_t nodes_cap, int64_t* prog_off,
+                                  float* consts, int64_t consts_cap, int64_t* const_off, int32_t* len,
+                                  int64_t* total_nodes, int64_t* total_consts) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!e || !prog_off || !const_off || !len || !total_nodes || !total_consts)
+        return fail(GP_ERR_INVALID_ARG, "gp_evolution_population: NULL argument");
+    const int32_t P = e->prm.n_programs;
+    const EvoPop& q = e->pop[e->cur];
+    GP_HIP(hipStreamSynchronize(e->stream));
+    GP_HIP(hipMemcpy(prog_off, q.prog_off, sizeof(int64_t) * (P + 1), hipMemcpyDeviceToHost));
+    GP_HIP(hipMemcpy(const_off, q.const_off, sizeof(int64_t) * (P + 1), hipMemcpyDeviceToHost));
+    GP_HIP(hipMemcpy(len, q.len, sizeof(int32_t) * P, hipMemcpyDeviceToHost));
+    *total_nodes = prog_off[P];
+    *total_consts = const_off[P];
+    if (*total_nodes > nodes_cap || *total_consts > consts_cap || !nodes || (*total_consts > 0 && !consts))
+        return fail(GP_ERR_BUFFER_TOO_SMALL, "gp_evolution_population: a capacity is short");
+    GP_HIP(hipMemcpy(nodes, q.nodes, sizeof(uint32_t) * *total_nodes, hipMemcpyDeviceToHost));
+    if (*total_consts > 0) GP_HIP(hipMemcpy(consts, q.consts, sizeof(float) * *total_consts, hipMemcpyDeviceToHost));
+    return GP_OK;
+}
+
+gp_status gp_evolution_info(const gp_evolution* e, gp_launch_config* cfg, float* kernel_ms, int64_t* generation,
+                            double* tuned_ms) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!e) return fail(GP_ERR_INVALID_ARG, "gp_evolution_info: NULL");
+    if (cfg) *cfg = gp_launch_config{e->cfg.R, e->cfg.freg, e->cfg.tiles, e->cfg.wpb};
+    if (kernel_ms) *kernel_ms = e->events ? e->kernel_ms : -1.0f;
+    if (generation) *generation = e->generation;
+    if (tuned_ms) *tuned_ms = e->tuned_ms;
+    return GP_OK;
+}
+
+void gp_evolution_destroy(gp_evolution* e) {
+    if (!e) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(e->dev);
+    evolution_release(e);
+    (void)hipSetDevice(cur);
+    delete e;
 }
 
 gp_status gp_fitness_backward(const gp_population_dev* pop, const gp_dataset_dev* data, gp_metric metric,

@@ -186,12 +186,12 @@ gp_status check_init(const gp_init_params& p, const char* who) {
         return fail(GP_ERR_INVALID_ARG, std::string(who) + ": need n_programs >= 0 and n_features >= 1");
     const uint32_t allowed = ((1u << GP_OP_COUNT) - 1u) & ~3u;
     if (p.function_mask == 0 || (p.function_mask & ~allowed))
-        return fail(GP_ERR_INVALID_ARG, std::string(who) + ": function_mask must select functions (bits 2..11) only");
+        return fail(GP_ERR_INVALID_ARG, std::string(who) + ": function_mask must select functions (bits 2..22) only");
     if (p.method == GP_INIT_EXACT_LEN) {
         if (p.min_len < 1 || p.max_len < p.min_len || p.max_len > (1 << 20))
             return fail(GP_ERR_INVALID_ARG, std::string(who) + ": need 1 <= min_len <= max_len <= 2^20");
         bool has_binary = false;
-        for (uint32_t op = GP_OP_ADD; op <= GP_OP_DIV; ++op) has_binary |= (p.function_mask >> op) & 1u;
+        for (uint32_t op = GP_OP_ADD; op < GP_OP_COUNT; ++op) has_binary |= arity(op) == 2 && ((p.function_mask >> op) & 1u);
         if (!has_binary && p.max_len > 1)
             return fail(GP_ERR_INVALID_ARG, std::string(who) + ": exact lengths above 1 need a binary function");
     } else if (p.method >= GP_INIT_RHH && p.method <= GP_INIT_GROW) {

@@ -19,8 +19,15 @@ namespace gp {
 // Arity of every opcode (Sec. III: functions of arity at most two); -1 for an
 // unknown opcode.
 GP_HD int arity(uint32_t op) {
-    return op <= GP_OP_CONST ? 0 : (op <= GP_OP_DIV ? 2 : (op < GP_OP_COUNT ? 1 : -1));
+    if (op <= GP_OP_CONST) return 0;
+    if (op <= GP_OP_DIV || (op >= GP_OP_MAX && op <= GP_OP_ATAN2)) return 2;
+    return op < GP_OP_COUNT ? 1 : -1;
 }
+
+// Index of a binary function among the binary ones (ADD..DIV, MAX..ATAN2 ->
+// 0..6) and of a unary one among the unary ones (NEG..TAN, ABS..CBRT -> 0..13).
+GP_HD uint32_t binary_index(uint32_t op) { return op <= GP_OP_DIV ? op - GP_OP_ADD : op - GP_OP_MAX + 4u; }
+GP_HD uint32_t unary_index(uint32_t op) { return op <= GP_OP_TAN ? op - GP_OP_NEG : op - GP_OP_ABS + 6u; }
 
 // Philox4x32-10 (Salmon et al., SC'11), the counter-based generator of
 // Sec. III-B.  One call maps a 128-bit counter and a 64-bit key to four
@@ -62,5 +69,39 @@ GP_HD float unit(uint32_t word) {
 // Thread-local error text behind gp_last_error().
 gp_status fail(gp_status st, const std::string& msg);
 gp_status ok();
+
+#if defined(__HIPCC__)
+// Returns GP_ERR_DEVICE with the runtime's message when a HIP call fails.
+#define GP_HIP(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(GP_ERR_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+// Device buffers of the mutation pipeline (gp_mutate.hip): donor lengths,
+// constant counts and offsets, offspring plans, lengths and constant
+// counts ([n + 1] each), and the donors themselves.
+struct MutateWork {
+    int64_t *dlen = nullptr, *dnc = nullptr, *doff = nullptr, *dcoff = nullptr, *clen = nullptr, *cnc = nullptr;
+    int64_t dlen_cap = 0, dnc_cap = 0, doff_cap = 0, dcoff_cap = 0, clen_cap = 0, cnc_cap = 0;
+    int4* plan = nullptr;
+    int64_t plan_cap = 0;
+    uint32_t* dnodes = nullptr;
+    float* dconsts = nullptr;
+    int64_t dnodes_cap = 0, dconsts_cap = 0, donor_cap = 0;
+};
+
+gp_status mutate_check(const gp_evolve_params* ev, const gp_init_params* in, int32_t n_offspring, const char* who);
+gp_status mutate_work_reserve(MutateWork* w, int32_t n_offspring, const gp_init_params& in);
+void mutate_work_free(MutateWork* w);
+// The generation number is d_gen[0] when d_gen is not NULL, else gen.
+gp_status plan_launch(const gp_evolve_params& ev, int32_t n_offspring, uint32_t gen, const uint32_t* d_gen,
+                      int32_t* ops, int32_t* first, int32_t* n_tournaments, hipStream_t s);
+gp_status mutate_launch(MutateWork& w, const gp_evolve_params& ev, const gp_init_params& in,
+                        const gp_population_dev& par, const int32_t* ops, const int32_t* first, const int32_t* winners,
+                        int32_t n_winners, int32_t n_offspring, uint32_t gen, const uint32_t* d_gen,
+                        const gp_population_out_dev& out, int64_t* info, hipStream_t s);
+#endif
 
 }  // namespace gp

@@ -39,17 +39,18 @@ class RunResult:
     launch_config: tuple | None = None
 
 
-def _log(g, fit, pop, larger, kernel_ms):
+def _log(g, fit, total_nodes, larger, kernel_ms):
     finite = np.where(np.isfinite(fit), fit, -np.inf if larger else np.inf)
     best = int(np.argmax(finite) if larger else np.argmin(finite))
     ok = fit[np.isfinite(fit)]
     return GenerationLog(g, float(fit[best]), best, float(ok.mean()) if ok.size else float("nan"),
-                         float(np.median(ok)) if ok.size else float("nan"), int(pop.nodes.shape[0]), kernel_ms)
+                         float(np.median(ok)) if ok.size else float("nan"), int(total_nodes), kernel_ms)
 
 
 def run_generations(data: B.DeviceDataset, n_generations: int, n_programs: int, init: dict,
                     metric="mse", tournament_size=20, parsimony=0.0, evolve: dict | None = None,
-                    seed=0, use_graph=True, autotune=False, time_kernel=False, callback=None) -> RunResult:
+                    seed=0, use_graph=True, autotune=False, time_kernel=False, callback=None,
+                    device_loop=False) -> RunResult:
     """Evolves `n_programs` programs for `n_generations` generations.
 
     init: initialisation settings (n_features, method, min_depth, max_depth,
@@ -57,7 +58,13 @@ def run_generations(data: B.DeviceDataset, n_generations: int, n_programs: int, 
     evolve: genetic-operation settings (p_crossover, p_subtree, p_hoist,
     p_point, p_point_replace, max_len, seed); defaults are those of the
     paper's large-scale runs (crossover 0.7, subtree 0.1, hoist 0.05, point
-    0.1, reproduction 0.05)."""
+    0.1, reproduction 0.05).
+
+    device_loop=True keeps every generation on the device (``Evolution``):
+    the same results bit for bit at the same launch configuration, with the
+    history read back once at the end (the callback then runs afterwards,
+    with no population, and kernel_ms is known for the last generation
+    only)."""
     evolve = dict(evolve or {})
     evolve.setdefault("max_len", 1024)
     evolve.setdefault("seed", seed)
@@ -70,6 +77,9 @@ def run_generations(data: B.DeviceDataset, n_generations: int, n_programs: int, 
     longest = int(pop.length.max(initial=1))
     cap = n_programs * max(int(evolve["max_len"]), longest)
     T_max = 2 * n_programs
+    if device_loop:
+        return _run_device(data, n_generations, pop, init, evolve, metric, tournament_size, parsimony, seed,
+                           autotune, time_kernel, callback, larger)
     graph = None
     if use_graph:
         graph = B.Generation(data, n_programs, cap, cap, metric, parsimony, tournament_size, T_max, seed,
@@ -86,7 +96,7 @@ def run_generations(data: B.DeviceDataset, n_generations: int, n_programs: int, 
                 win_d = B.tournament(fit_d, dpop.length, metric, parsimony, tournament_size, T_max, seed, g)
                 fit, win = fit_d.cpu().numpy(), win_d.cpu().numpy()
                 kernel_ms = -1.0
-            history.append(_log(g, fit, pop, larger, kernel_ms))
+            history.append(_log(g, fit, pop.nodes.shape[0], larger, kernel_ms))
             if callback is not None:
                 callback(history[-1], pop, fit)
             if g == n_generations:
@@ -98,3 +108,23 @@ def run_generations(data: B.DeviceDataset, n_generations: int, n_programs: int, 
     finally:
         if graph is not None:
             graph.close()
+
+
+def _run_device(data, n_generations, pop, init, evolve, metric, tournament_size, parsimony, seed, autotune,
+                time_kernel, callback, larger) -> RunResult:
+    evo = B.Evolution(data, pop, init, evolve, metric=metric, parsimony=parsimony, tournament_size=tournament_size,
+                      tournament_seed=seed, max_generations=max(n_generations, 1), autotune=autotune,
+                      time_kernel=time_kernel)
+    try:
+        evo.run(n_generations)
+        evo.evaluate()
+        fit, nodes = evo.history()
+        cfg, kernel_ms, _, _ = evo.info()
+        history = [_log(g, fit[g], nodes[g], larger, kernel_ms if g == n_generations - 1 else -1.0)
+                   for g in range(n_generations + 1)]
+        if callback is not None:
+            for g in range(n_generations + 1):
+                callback(history[g], None, fit[g])
+        return RunResult(evo.population(), fit[n_generations].copy(), history, cfg)
+    finally:
+        evo.close()

@@ -14,7 +14,8 @@ Tolerance, per program, with scale = max_k |g_64[k]|:
   * well-conditioned programs (no protected predicate near its threshold,
     derivative spread at most 2.5e-5 * scale):
         max_k |g_gpu[k] - g_64[k]| <= 1e-4 * scale;
-  * every program with no protected predicate near its threshold:
+  * every program whose fitness is well-conditioned (no protected predicate
+    near its threshold, fitness bound within the fitness tolerance):
         max_k |g_gpu[k] - g_64[k]| <= 1e-4 * scale + 10 * max_k spread[k].
 """
 import os
@@ -77,19 +78,30 @@ def oracle_reference(opop, X, y, w, metric, gscale=None):
 
 
 def check_grads(host, g, ref, spread, cond, label):
-    fnear = cond[3]
+    f32p, _, fbound, fnear = cond
+    # a fitness whose own conditioning bound exceeds the fitness tolerance is
+    # chaotic in float32 (e.g. sin of a cube that reaches 1e10 on some rows):
+    # a few Monte Carlo samples of such a heavy-tailed sum do not bound its
+    # derivative, so only the tight bar's exclusion applies there
+    with np.errstate(invalid="ignore"):
+        fit_ok = (np.asarray(fnear) == 0) & ((np.asarray(fbound) <= 1e-4 * np.abs(f32p))
+                                              | (np.asarray(fbound) == 0))
     checked = ill = 0
     for p in range(host.n_programs):
         a, b = int(host.const_off[p]), int(host.const_off[p + 1])
         if a == b:
             continue
         r, sp = ref[a:b], spread[a:b]
-        if not (np.all(np.isfinite(r)) and np.all(np.isfinite(sp))):
+        # a fitness or derivative beyond the float32 range (nested cubes
+        # reaching 1e49, say) has no float32 value to compare with
+        big = np.finfo(np.float32).max
+        if not (np.all(np.isfinite(r)) and np.all(np.isfinite(sp)) and abs(f32p[p]) <= big
+                and np.all(np.abs(r) <= big)):
             ill += 1
             continue
         scale = np.max(np.abs(r))
         err = np.max(np.abs(g[a:b] - r))
-        if fnear[p] == 0:
+        if fit_ok[p]:
             assert err <= GRAD_TOL * scale + 10.0 * np.max(sp), \
                 (label, p, "beyond the conditioning estimate", err, np.max(sp), g[a:b], r)
         if not (fnear[p] == 0 and np.max(sp) <= SPREAD_TOL * scale):
@@ -172,6 +184,44 @@ def test_correctly_rounded_function_set_all_programs(gp):
     ref, spread, (f32p, f64, fb, fn) = oracle_reference(to_oracle(host), X, y, None, "mse")
     checked, ill = check_grads(host, g, ref, spread, (f32p, f32p, fb, fn), "add/sub/mul/neg")
     assert ill == 0 and checked == sum(int(host.const_off[p + 1] > host.const_off[p]) for p in range(128))
+
+
+@pytest.mark.parametrize("metric", ["mse", "pearson"])
+def test_wider_function_set_float64_reverse_mode(gp, metric):
+    """Ramped half-and-half programs over every function (the wider set's
+    partials: max / min pass the derivative to the selected operand, atan2's
+    two partials, abs, exp, protected inverse, square, cube, tanh, atan,
+    cbrt)."""
+    N = 30_000 + 5
+    X, y = synth.diff_target(N, seed=15)
+    P = 384
+    host = gp.build_population(P, 8, "rhh", min_depth=2, max_depth=6, max_consts=16,
+                               function_mask=oracle.ALL_FMASK, seed=2119)
+    g, fit_out, fwd = run_backward(gp, host, X, y, None, metric, 8)
+    ref, spread, cond = oracle_reference(to_oracle(host), X, y, None, metric)
+    checked, ill = check_grads(host, g, ref, spread, cond, f"wide {metric}")
+    print(f"wide {metric}: {checked} programs checked, {ill} ill-conditioned")
+    assert checked >= (15 if metric == "pearson" else 40)
+    fin = np.isfinite(fwd)
+    assert np.array_equal(fin, np.isfinite(fit_out))
+    assert np.allclose(fit_out[fin], fwd[fin], rtol=1e-6, atol=0)
+
+
+def test_wider_correctly_rounded_set_all_programs(gp):
+    # max, min, abs, square, cube with add / sub / mul / neg: no library
+    # function, so every program is well-conditioned and all are checked
+    fmask = sum(1 << o for o in (oracle.ADD, oracle.SUB, oracle.MUL, oracle.NEG, oracle.MAX,
+                                 oracle.MIN, oracle.ABS, oracle.SQ, oracle.CUBE))
+    N = 20_000
+    X, y = synth.diff_target(N, seed=17)
+    host = gp.build_population(128, 8, "exact_len", min_len=1, max_len=60, max_consts=16,
+                               function_mask=fmask, seed=18)
+    g, _, _ = run_backward(gp, host, X, y, None, "mse", 8)
+    ref, spread, (f32p, f64, fb, fn) = oracle_reference(to_oracle(host), X, y, None, "mse")
+    checked, ill = check_grads(host, g, ref, spread, (f32p, f32p, fb, fn), "wide correctly rounded")
+    print(f"wide correctly rounded: {checked} checked, {ill} ill")
+    n_const = sum(int(host.const_off[p + 1] > host.const_off[p]) for p in range(128))
+    assert checked >= 0.9 * n_const
 
 
 def test_more_than_sixteen_constants_and_edge_rows(gp):

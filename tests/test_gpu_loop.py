@@ -100,3 +100,71 @@ def test_pagie_one_million_rows_twenty_generations(gp):
     print(f"1M-row loop: 20 generations in {wall:.2f} s; best MSE {res.history[0].best:.4g} -> "
           f"{min(h.best for h in res.history):.4g}; kernel ms/gen "
           f"{np.mean([h.kernel_ms for h in res.history]):.2f}")
+
+
+@pytest.mark.parametrize("init,metric", [
+    (INIT, "mse"),
+    (dict(n_features=2, method="exact_len", min_len=1, max_len=60, max_consts=6, function_mask=oracle.ALL_FMASK,
+          seed=33), "pearson"),
+])
+def test_device_loop_equals_host_loop(gp, init, metric):
+    """Every generation on the device (Evolution) against the graph loop with
+    host genetic operations: bit-identical fitness in every generation and
+    the same final population."""
+    X, y = synth.pagie(20_000 + 17, seed=11229)
+    data = gp.DeviceDataset(X, y)
+    host_steps = []
+    ra = gp.run_generations(data, 8, 256, init, metric, 20, 0.01, EVOLVE, seed=5, callback=record(host_steps))
+    dev_fit = []
+    rb = gp.run_generations(data, 8, 256, init, metric, 20, 0.01, EVOLVE, seed=5, device_loop=True,
+                            callback=lambda log, pop, fit: dev_fit.append(fit.copy()))
+    assert len(dev_fit) == len(host_steps) == 9
+    for g, ((_, _, fa), fb) in enumerate(zip(host_steps, dev_fit)):
+        assert np.array_equal(fa.view(np.uint32), fb.view(np.uint32)), g
+    for la, lb in zip(ra.history, rb.history):
+        assert la.total_nodes == lb.total_nodes and la.best_program == lb.best_program
+    pa, pb = ra.population, rb.population
+    assert np.array_equal(pa.nodes, pb.nodes) and np.array_equal(pa.prog_off, pb.prog_off)
+    assert np.array_equal(pa.consts.view(np.uint32), pb.consts.view(np.uint32))
+    assert np.array_equal(pa.const_off, pb.const_off) and np.array_equal(pa.length, pb.length)
+    assert rb.launch_config == ra.launch_config
+
+
+def test_device_loop_pagie_one_million_rows(gp):
+    """The 1,048,576-row shape with the loop on the device: twenty
+    generations, the evolution improving, and its time next to the host loop."""
+    import time
+    X, y = synth.pagie(1_048_576, seed=11228)
+    data = gp.DeviceDataset(X, y)
+    init = dict(n_features=2, method="rhh", min_depth=2, max_depth=8, seed=2112)
+    t0 = time.time()
+    rd = gp.run_generations(data, 20, 1000, init, "mse", 20, 0.01, EVOLVE, seed=2112, device_loop=True,
+                            time_kernel=True)
+    t_dev = time.time() - t0
+    t0 = time.time()
+    rh = gp.run_generations(data, 20, 1000, init, "mse", 20, 0.01, EVOLVE, seed=2112)
+    t_host = time.time() - t0
+    assert [h.best for h in rd.history] == [h.best for h in rh.history]
+    gp.validate_population(rd.population, 2)
+    assert rd.history[-2].kernel_ms > 0
+    print(f"1M-row loop, 20 generations: device loop {t_dev:.3f} s, host-mutation loop {t_host:.3f} s; "
+          f"best MSE {rd.history[0].best:.4g} -> {min(h.best for h in rd.history):.4g}")
+
+
+def test_device_loop_limits(gp):
+    X, y = synth.pagie(2000, seed=3)
+    data = gp.DeviceDataset(X, y)
+    pop = gp.build_population(32, 2, "rhh", seed=1)
+    evo = gp.Evolution(data, pop, dict(n_features=2), dict(EVOLVE, seed=1), max_generations=3)
+    try:
+        evo.run(3)
+        with pytest.raises(gp.GPError, match="INVALID_ARG"):
+            evo.run(1)
+        evo.evaluate()
+        fit, nodes = evo.history()
+        assert fit.shape == (4, 32) and nodes.shape == (4,)
+        assert evo.info()[2] == 3
+    finally:
+        evo.close()
+    with pytest.raises(gp.GPError, match="INVALID_ARG"):
+        gp.Evolution(data, pop, dict(n_features=3), dict(EVOLVE, seed=1))     # init features != data's

@@ -162,7 +162,7 @@ def test_fitness_all_metrics_rhh(gp, metric, weighted):
               f"max rel err vs f64 {e64:.2e}")
         # a small |r| is relatively sensitive to every row, so fewer Pearson
         # programs clear the conditioning bar than loss-type metrics
-        assert n_ok >= (0.65 if metric == "pearson" else 0.8) * 300
+        assert n_ok >= (0.6 if metric == "pearson" else 0.8) * 300
 
 
 @pytest.mark.parametrize("metric", ["mae", "mse", "rmse", "logloss", "pearson"])
@@ -348,3 +348,100 @@ def test_full_size_higgs_like_logloss_sampled(gp):
     print(f"higgs-like: {n_ok} sampled programs checked, {n_ill} ill-conditioned, "
           f"lengths {host.length[sample].tolist()}")
     assert n_ok >= 3
+
+
+# ---- the wider function set (max, min, atan2, abs, exp, inv, sq, cube, tanh,
+# atan, cbrt, next to the nine functions and tan) ----
+WIDE_CR_FMASK = sum(1 << o for o in (oracle.ADD, oracle.SUB, oracle.MUL, oracle.DIV, oracle.NEG,
+                                     oracle.SQRT, oracle.MAX, oracle.MIN, oracle.ABS, oracle.INV,
+                                     oracle.SQ, oracle.CUBE))
+
+
+@pytest.mark.parametrize("cfg", [None, (1, 0, 1), (2, 2, 2), (4, 2, 1), (4, 8, 3, 1), (2, 0, 2, 2)])
+def test_evaluate_wider_set_rhh(gp, cfg):
+    N = 4096 + 77
+    X, _ = synth.pagie(N, seed=11227)
+    host = gp.build_population(256, 2, "rhh", min_depth=2, max_depth=6,
+                               function_mask=oracle.ALL_FMASK, seed=2117)
+    got = run_eval(gp, host, X, 2, cfg)
+    ra = oracle.evaluate_pairs(to_oracle(host), X, *all_pairs(256, N), n_threads=NT)
+    n_ok, n_ill = check_rows(got, ra, f"wide cfg={cfg}")
+    print(f"wide cfg={cfg}: {n_ok} rows checked, {n_ill} ill-conditioned")
+    assert n_ok > 0.85 * got.size
+
+
+def test_evaluate_wider_correctly_rounded_bit_exact(gp):
+    """max, min, abs, protected inverse, square and cube are IEEE operations
+    (cube is two products in the same order on both sides): with the other
+    correctly rounded functions, every row is bit-identical."""
+    N = 5000
+    X, _ = synth.diff_target(N, seed=19)
+    host = gp.build_population(128, 8, "exact_len", min_len=1, max_len=200,
+                               function_mask=WIDE_CR_FMASK, seed=78)
+    for cfg in (None, (1, 8, 2), (4, 0, 1), (2, 8, 7, 2)):
+        got = run_eval(gp, host, X, 8, cfg)
+        ref = oracle.evaluate_f32(to_oracle(host), X, n_threads=NT)
+        same = (got.view(np.uint32) == ref.view(np.uint32)) | (np.isnan(got) & np.isnan(ref))
+        assert same.all(), (cfg, int((~same).sum()))
+
+
+def test_evaluate_wider_set_special_values(gp):
+    """NaN operands of max / min, the sign of a zero max / min seen through
+    atan2, the protected inverse at its threshold, exp overflow: bit for bit
+    (each case is exact or a correctly rounded constant on both sides)."""
+    n = oracle.node
+    V0, V1, C0 = n(oracle.VAR, 0), n(oracle.VAR, 1), n(oracle.CONST, 0)
+    progs = [([n(oracle.MAX), V0, V1], []), ([n(oracle.MIN), V0, V1], []),
+             ([n(oracle.ATAN2), C0, n(oracle.MAX), V0, V1], [0.0]),
+             ([n(oracle.ATAN2), C0, n(oracle.MIN), V0, V1], [0.0]),
+             ([n(oracle.ATAN2), C0, n(oracle.MAX), V1, V0], [0.0]),
+             ([n(oracle.ATAN2), C0, n(oracle.MIN), V1, V0], [0.0]),
+             ([n(oracle.INV), V0], []), ([n(oracle.INV), V1], []), ([n(oracle.ABS), V0], []),
+             ([n(oracle.CUBE), V0], []), ([n(oracle.SQ), V1], [])]
+    op = oracle.from_programs(progs)
+    host = gp.HostPopulation(op.nodes, op.prog_off, op.consts, op.const_off, op.length)
+    eps = np.float32(0.001)
+    vals = np.array([0.0, -0.0, np.nan, 1.0, -1.0, eps, -eps, np.nextafter(eps, np.float32(1)),
+                     np.inf, -np.inf, 3e38], np.float32)
+    a, b = np.meshgrid(vals, vals, indexing="ij")
+    X = np.ascontiguousarray(np.stack([a.ravel(), b.ravel()]))
+    got = run_eval(gp, host, X, 2, None)
+    ref = oracle.evaluate_f32(op, X, n_threads=NT)
+    same = (got.view(np.uint32) == ref.view(np.uint32)) | (np.isnan(got) & np.isnan(ref))
+    bad = np.argwhere(~same)
+    assert same.all(), [(int(p), float(X[0, r]), float(X[1, r]), float(got[p, r]), float(ref[p, r]))
+                        for p, r in bad[:8]]
+    # atan2 on the same grid: exact at zeros and infinities (C's conventions,
+    # correctly rounded multiples of pi / 4), within 4 ulps elsewhere
+    op = oracle.from_programs([([n(oracle.ATAN2), V0, V1], [])])
+    host = gp.HostPopulation(op.nodes, op.prog_off, op.consts, op.const_off, op.length)
+    got = run_eval(gp, host, X, 2, None)[0]
+    ref = oracle.evaluate_f32(op, X, n_threads=NT)[0]
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    special = (X[0] == 0) | (X[1] == 0) | np.isinf(X[0]) | np.isinf(X[1])
+    fin = ~np.isnan(ref)
+    ex = special & fin
+    assert np.array_equal(got[ex].view(np.uint32), ref[ex].view(np.uint32))
+    gen = ~special & fin
+    assert np.all(np.abs(got[gen] - ref[gen]) <= 4 * np.spacing(np.abs(ref[gen])))
+    # exp overflows to +inf and underflows towards 0 like the oracle
+    progs = [([n(oracle.EXP), V0], [])]
+    op = oracle.from_programs(progs)
+    host = gp.HostPopulation(op.nodes, op.prog_off, op.consts, op.const_off, op.length)
+    X = np.ascontiguousarray(np.array([[100.0, 89.0, -100.0, -200.0, 0.0], [0.0] * 5], np.float32))
+    got = run_eval(gp, host, X, 2, None)[0]
+    assert np.isposinf(got[0]) and np.isposinf(got[1]) and got[4] == 1.0
+    assert 0.0 <= got[2] < 1e-43 and got[3] == 0.0
+
+
+@pytest.mark.parametrize("metric", ["mae", "mse", "logloss", "pearson"])
+def test_fitness_wider_set_rhh(gp, metric):
+    N = 20000 + 13
+    X, y, F = _metric_data(metric, N, 5)
+    host = gp.build_population(300, F, "rhh", min_depth=2, max_depth=7,
+                               function_mask=oracle.ALL_FMASK, seed=2118)
+    for cfg in (None, (1, 8, 4), (4, 0, 3, 2)):
+        got, *ref = _fitness_case(gp, host, X, y, None, metric, F, cfg)
+        n_ok, n_ill, e64 = check_fitness(got, *ref, f"wide {metric} cfg={cfg}")
+        print(f"wide {metric} cfg={cfg}: {n_ok} ok, {n_ill} ill, max rel err vs f64 {e64:.2e}")
+        assert n_ok >= (0.6 if metric == "pearson" else 0.8) * 300

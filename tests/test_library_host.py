@@ -48,6 +48,13 @@ CASES = [
     dict(method="rhh", min_depth=2, max_depth=5, const_lo=1.0, const_hi=0.0),
     dict(method="exact_len", min_len=30, max_len=30,
          fmask=sum(1 << o for o in (oracle.ADD, oracle.MUL, oracle.SIN, oracle.TAN))),
+    # every function, and the wider set on its own
+    dict(method="rhh", min_depth=2, max_depth=7, fmask=oracle.ALL_FMASK),
+    dict(method="exact_len", min_len=1, max_len=150, max_consts=8, fmask=oracle.ALL_FMASK),
+    dict(method="grow", min_depth=1, max_depth=9,
+         fmask=sum(1 << o for o in (oracle.MAX, oracle.MIN, oracle.ATAN2, oracle.ABS, oracle.EXP,
+                                    oracle.INV, oracle.SQ, oracle.CUBE, oracle.TANH, oracle.ATAN,
+                                    oracle.CBRT))),
 ]
 
 
@@ -73,7 +80,7 @@ def test_build_population_errors(gp):
     with pytest.raises(gp.GPError, match="INVALID_ARG"):
         gp.build_population(10, 0, "rhh")
     with pytest.raises(gp.GPError, match="INVALID_ARG"):
-        gp.build_population(10, 2, "rhh", function_mask=1 << 13)
+        gp.build_population(10, 2, "rhh", function_mask=1 << 23)
 
 
 def test_validate_matches_oracle_on_mutated_programs(gp):
@@ -84,7 +91,7 @@ def test_validate_matches_oracle_on_mutated_programs(gp):
     for p in range(base.n_programs):
         if rng.random() < 0.5:
             i = int(base.prog_off[p] + rng.integers(0, base.length[p]))
-            op = int(rng.integers(0, 13))
+            op = int(rng.integers(0, 24))
             arg = int(rng.integers(0, 6))
             nodes[i] = op | (arg << 8)
     expected_codes = {1: -2, 2: -2, 3: -3, 4: -2, 5: -2, 6: -2}
@@ -148,6 +155,7 @@ MUT_CASES = [
     dict(F=2, method="exact_len", max_consts=4, p_point_replace=0.5, max_len=40),
     dict(F=8, method="grow", max_consts=16, p_point_replace=1.0, max_len=8),
     dict(F=3, method="full", max_consts=0, p_point_replace=0.2, max_len=64),
+    dict(F=4, method="rhh", max_consts=6, p_point_replace=0.3, max_len=120, fmask=oracle.ALL_FMASK),
 ]
 
 
@@ -155,17 +163,24 @@ MUT_CASES = [
 @pytest.mark.parametrize("generation", [0, 7])
 def test_genetic_operations_bit_exact_with_oracle(gp, case, generation):
     F, meth = case["F"], case["method"]
+    fmask = case.get("fmask", oracle.DEFAULT_FMASK)
     init = dict(n_features=F, method=meth, min_depth=1, max_depth=7, min_len=1, max_len=80,
                 max_consts=case["max_consts"])
+    if "fmask" in case:
+        init["fmask"] = fmask
     parents = gp.build_population(96, F, meth, min_depth=1, max_depth=7, min_len=1, max_len=80,
-                                  max_consts=case["max_consts"], seed=generation + 11)
+                                  max_consts=case["max_consts"], function_mask=fmask,
+                                  seed=generation + 11)
     ev = dict(p_crossover=0.4, p_subtree=0.2, p_hoist=0.15, p_point=0.15,
               p_point_replace=case["p_point_replace"], max_len=case["max_len"], seed=4242)
     ops, ft, T = gp.plan_generation(96, generation, **ev)
     o_ops, o_ft, o_T = oracle.plan_generation(oracle.EvolveParams(**ev), 96, generation)
     assert np.array_equal(ops, o_ops) and np.array_equal(ft, o_ft) and T == o_T
     win = np.random.default_rng(generation).integers(0, 96, size=T).astype(np.int32)
-    a = gp.mutate(parents, ops, ft, win, generation, init, **ev)
+    ginit = dict(init)
+    if "fmask" in ginit:
+        ginit["function_mask"] = ginit.pop("fmask")
+    a = gp.mutate(parents, ops, ft, win, generation, ginit, **ev)
     b = oracle.mutate(oracle.EvolveParams(**ev), oracle.InitParams(**init),
                       oracle.Population(parents.nodes, parents.prog_off, parents.consts, parents.const_off,
                                         parents.length), ops, ft, win, generation)
