@@ -3199,7 +3199,16 @@ gp_status gp_fitness_backward(const gp_population_dev* pop, const gp_dataset_dev
     hipLaunchKernelGGL(k_zero, dim3(static_cast<unsigned>((nc + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
                        sc->gextra, nc);
     GP_HIP(hipGetLastError());
-    const int freg = cfg.freg > 0 && data->n_features <= 2 ? 2 : (data->n_features <= 8 ? 8 : 0);
+    // features in registers when they fit -- unless a forced configuration
+    // says otherwise, or holding them would cost a wavefront of occupancy
+    // against reading them from memory (the choice below, per kernel)
+    const int freg_fit = data->n_features <= 2 ? 2 : (data->n_features <= 8 ? 8 : 0);
+    const int freg = (g_forced && g_forced_cfg.freg == 0) ? 0 : freg_fit;
+    auto occ = [](const void* k) {
+        int n = 0;
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kWave, 0);
+        return n;
+    };
     double* lossp = needs_forward ? nullptr : sc->part;
     auto go = [&](auto kernel, int64_t wave_floats) -> gp_status {
         int per_cu = 0;
@@ -3216,9 +3225,14 @@ gp_status gp_fitness_backward(const gp_population_dev* pop, const gp_dataset_dev
         GP_HIP(hipGetLastError());
         return GP_OK;
     };
+#define GP_ADJ_PICK(RR, F, M)                                                                  \
+    (g_forced || occ(reinterpret_cast<const void*>(k_adjoint<RR, F, M>)) >=                    \
+                     occ(reinterpret_cast<const void*>(k_adjoint<RR, 0, M>))                   \
+         ? go(k_adjoint<RR, F, M>, adjoint_wave_floats<RR>(tape_max))                          \
+         : go(k_adjoint<RR, 0, M>, adjoint_wave_floats<RR>(tape_max)))
 #define GP_ADJ_R(RR, M)                                                                        \
-    (freg == 2   ? go(k_adjoint<RR, 2, M>, adjoint_wave_floats<RR>(tape_max))                  \
-     : freg == 8 ? go(k_adjoint<RR, 8, M>, adjoint_wave_floats<RR>(tape_max))                  \
+    (freg == 2   ? GP_ADJ_PICK(RR, 2, M)                                                       \
+     : freg == 8 ? GP_ADJ_PICK(RR, 8, M)                                                       \
                  : go(k_adjoint<RR, 0, M>, adjoint_wave_floats<RR>(tape_max)))
 #define GP_ADJ(M) (RA == 1 ? GP_ADJ_R(1, M) : RA == 2 ? GP_ADJ_R(2, M) : GP_ADJ_R(4, M))
     switch (metric) {
@@ -3230,6 +3244,7 @@ gp_status gp_fitness_backward(const gp_population_dev* pop, const gp_dataset_dev
     }
 #undef GP_ADJ
 #undef GP_ADJ_R
+#undef GP_ADJ_PICK
     if (rc != GP_OK) return rc;
     if (!needs_forward && fitness_out) {
         if (metric == GP_METRIC_MAE)
