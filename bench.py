@@ -122,6 +122,60 @@ def arith_only(gp, data, wl, steps):
             "launch": list(launch)}
 
 
+def loop_generation_time(gp, torch, n_gen=10):
+    """Wall time per generation of the whole loop (fitness, tournaments,
+    pre-draw, genetic operations) with the genetic operations on the host
+    (captured generation graph + gp_mutate) and on the device (gp_evolution),
+    on 65,536 Pagie rows x 4,096 ramped half-and-half programs: a small-N
+    shape where the mutation step is visible next to the fitness."""
+    import synth
+    X, y = synth.pagie(65_536, seed=11229)
+    data = gp.DeviceDataset(X, y)
+    init = dict(n_features=2, method="rhh", min_depth=2, max_depth=6, seed=2111)
+    ev = dict(p_crossover=0.7, p_subtree=0.1, p_hoist=0.05, p_point=0.1, p_point_replace=0.05, max_len=256)
+    out = {"workload": "pagie, 65536 rows x 4096 programs (RHH depth 2-6), MSE", "generations": n_gen}
+    for key, kw in (("host_mutation_ms_per_generation", {}), ("device_loop_ms_per_generation",
+                                                           {"device_loop": True})):
+        gp.run_generations(data, 1, 4096, init, "mse", 20, 0.01, ev, seed=3, **kw)     # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gp.run_generations(data, n_gen, 4096, init, "mse", 20, 0.01, ev, seed=3, **kw)
+        torch.cuda.synchronize()
+        out[key] = (time.perf_counter() - t0) * 1e3 / n_gen
+    return out
+
+
+def spearman_time(gp, torch, reps=3):
+    """Spearman fitness (evaluate, segmented radix sort of every program's
+    outputs, ranks, rank correlation) on 1,048,576 Pagie rows x 4,096
+    exact-length programs: event-timed median of `reps` calls, with the MSE
+    fitness of the same population beside it."""
+    import synth
+    X, y = synth.pagie(1_048_576, seed=11232)
+    host = gp.build_population(4096, 2, "exact_len", min_len=1, max_len=200, seed=2113)
+    pop = gp.DevicePopulation(host, n_features=2)
+    data = gp.DeviceDataset(X, y)
+    fit = torch.empty(4096, dtype=torch.float32, device="cuda")
+    s = torch.cuda.current_stream()
+
+    def timed(metric):
+        out = []
+        for _ in range(reps + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            gp.fitness(pop, data, metric, out=fit)
+            b.record(s)
+            b.synchronize()
+            out.append(a.elapsed_time(b))
+        return float(np.median(out[1:]))
+
+    ms_sp, ms_mse = timed("spearman"), timed("mse")
+    node_rows = float(host.length.astype(np.int64).sum()) * 1_048_576
+    return {"workload": "pagie, 1048576 rows x 4096 programs (exact length 1-200)", "spearman_ms": ms_sp,
+            "mse_ms": ms_mse, "spearman_gpops": node_rows / (ms_sp / 1e3),
+            "sorted_keys_per_s": 4096 * 1_048_576 / (ms_sp / 1e3)}
+
+
 def adjoint_ratio(gp, torch, reps=5):
     """gp_fitness_backward time / gp_fitness time on the differentiation
     workload (medians of `reps` event-timed calls each)."""
@@ -162,6 +216,10 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-arith", action="store_true", help="skip the add/sub/mul-only population")
+    ap.add_argument("--no-loop", action="store_true", help="skip the generation-loop timing")
+    ap.add_argument("--no-spearman", action="store_true", help="skip the Spearman fitness timing")
+    ap.add_argument("--only-spearman", action="store_true",
+                    help="time only the Spearman fitness (for a kernel trace of it)")
     ap.add_argument("--cpu-rows", type=int, default=196_608)
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache (JSON lines): loaded if present, written after tuning")
@@ -188,6 +246,11 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {args.copy_calibration_mib} MiB done")
         del src, dst
+    if args.only_spearman:
+        spear = spearman_time(gp, torch)
+        log(f"[bench] Spearman {spear['spearman_ms']:.1f} ms vs MSE {spear['mse_ms']:.1f} ms")
+        print(json.dumps({"spearman": spear}))
+        return 0
     log(f"[bench] building {args.workload}: {wl['rows']} rows x {wl['programs']} programs")
     X, y = make_data(wl)
     host = gp.build_population(wl["programs"], wl["features"], **wl["pop"])
@@ -235,6 +298,20 @@ def main():
         log(f"[bench] add/sub/mul only: {arith['kernel_avg_ms']:.1f} ms, {arith['value']:.3g} GPops/s "
             f"({100 * arith['frac']:.2f}% of peak)")
 
+    spear = None
+    if not args.no_spearman and args.workload == "pagie-16M":
+        log("[bench] Spearman fitness")
+        spear = spearman_time(gp, torch)
+        log(f"[bench] Spearman {spear['spearman_ms']:.1f} ms vs MSE {spear['mse_ms']:.1f} ms on "
+            f"1M rows x 4096 programs ({spear['sorted_keys_per_s']:.3g} ranked outputs/s)")
+
+    loop = None
+    if not args.no_loop and args.workload == "pagie-16M":
+        log("[bench] generation loop: host vs device genetic operations")
+        loop = loop_generation_time(gp, torch)
+        log(f"[bench] loop ms/generation: host mutation {loop['host_mutation_ms_per_generation']:.2f}, "
+            f"device loop {loop['device_loop_ms_per_generation']:.2f}")
+
     adj = None
     if not args.no_adjoint:
         log("[bench] adjoint / forward ratio on the differentiation workload")
@@ -278,6 +355,8 @@ def main():
                      "kernel_avg_ms": kern_avg_ms, "kernel_timed_by": tm["timed_by"],
                      "ops_per_launch": ops_launch, "op": "one program node evaluated on one row"},
         "arith_only": arith,
+        "generation_loop": loop,
+        "spearman": spear,
         "adjoint": adj,
         "cpu_baseline": base,
     }

@@ -448,7 +448,7 @@ typedef struct {
     int32_t n_programs;        /* population size, fixed across generations (>= 1) */
     int64_t node_capacity;     /* bound on sum(len) of any generation              */
     int64_t const_capacity;    /* bound on the constants of any generation         */
-    int32_t metric;            /* gp_metric (not SPEARMAN)                          */
+    int32_t metric;            /* gp_metric (SPEARMAN: no autotune, no kernel time) */
     float parsimony;
     int32_t tournament_size;   /* >= 1                                              */
     int32_t n_tournaments;     /* winners per generation (>= 0)                     */
@@ -506,16 +506,19 @@ void gp_generation_destroy(gp_generation* gen);
 /* ------------------------------------------------------------------ */
 typedef struct {
     int32_t n_programs;        /* population size (1 .. 2^29)                        */
-    int32_t metric;            /* gp_metric (not SPEARMAN)                            */
+    int32_t metric;            /* gp_metric (SPEARMAN: no autotune, no kernel time)   */
     float parsimony;
     int32_t tournament_size;   /* >= 1                                                */
     uint64_t tournament_seed;  /* Philox key of the tournaments                       */
     gp_evolve_params evolve;
     gp_init_params init;       /* donors of subtree mutation, point-mutation sets;   */
                                /* init.n_features must equal the dataset's           */
-    int32_t max_generations;   /* history capacity: generations 0 .. max_generations  */
+    int32_t max_generations;   /* history capacity: max_generations + 1 entries        */
     int32_t autotune;          /* 1: tune on the initial population (unless forced)  */
     int32_t time_kernel;       /* 1: HIP event nodes around the evaluation kernel     */
+    uint64_t first_generation; /* generation number of the initial population: a run
+                                  resumed from generation g's population passes g and
+                                  continues exactly (the draws are counter-based)     */
 } gp_evolution_params;
 
 typedef struct gp_evolution_s gp_evolution;
@@ -528,21 +531,22 @@ gp_status gp_evolution_create(const gp_evolution_params* params, const gp_datase
                               const uint32_t* nodes, const int64_t* prog_off, const float* consts,
                               const int64_t* const_off, const int32_t* len, gp_evolution** out);
 
-/* Runs generations g .. g + n - 1 (g = the generations run so far): for each,
- * the current population's fitness is recorded as entry g of the history and
- * its offspring become the current population.  Waits for the device;
+/* Runs generations g .. g + n - 1 (g = first_generation + the generations run
+ * so far): for each, the current population's fitness is recorded as history
+ * entry g - first_generation and its offspring become the current
+ * population.  Waits for the device;
  * GP_ERR_DEVICE if a mutation status bit was raised (see gp_mutate_device),
  * GP_ERR_INVALID_ARG beyond max_generations. */
 gp_status gp_evolution_run(gp_evolution* evo, int32_t n_generations);
 
-/* Fitness of the current population, recorded as history entry g, without
+/* Fitness of the current population, recorded as its history entry, without
  * selection or mutation (the loop's last step).  Waits for the device. */
 gp_status gp_evolution_evaluate(gp_evolution* evo);
 
 /* The history: *n_recorded entries; fitness_history [n_recorded *
- * n_programs] (entry g's fitness in row g) and nodes_history [n_recorded]
- * (sum of lengths of generation g), HOST, nullable, at most `capacity`
- * entries copied. */
+ * n_programs] (generation first_generation + k in row k) and nodes_history
+ * [n_recorded] (the sum of lengths of that generation), HOST, nullable, at
+ * most `capacity` entries copied. */
 gp_status gp_evolution_history(const gp_evolution* evo, int32_t capacity, int32_t* n_recorded,
                                float* fitness_history, int64_t* nodes_history);
 
@@ -555,7 +559,8 @@ gp_status gp_evolution_population(const gp_evolution* evo, uint32_t* nodes, int6
 
 /* Launch configuration, the evaluation kernel's duration in the last
  * replay (ms, -1 unless time_kernel and the event nodes were accepted),
- * the generations run, and the autotuner's best time (-1 if not tuned).
+ * the generations run by this object, and the autotuner's best time (-1 if
+ * not tuned).
  * Each output is nullable. */
 gp_status gp_evolution_info(const gp_evolution* evo, gp_launch_config* cfg, float* kernel_ms,
                             int64_t* generation, double* tuned_ms);

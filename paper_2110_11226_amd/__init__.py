@@ -14,4 +14,5 @@ from ._binding import (  # noqa: F401
     FUNCS_DEFAULT, MAX_STACK, METRICS, LIB_PATH,
 )
 from .autograd import GPFitness, refine_constants  # noqa: F401,E402
-from .loop import run_generations, RunResult, GenerationLog  # noqa: F401,E402
+from .loop import (run_generations, RunResult, GenerationLog, save_checkpoint,  # noqa: F401,E402
+                   load_checkpoint)

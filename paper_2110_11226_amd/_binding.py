@@ -617,7 +617,8 @@ def mutate_device(parents: DevicePopulation, ops, first_tournament, winners, gen
 class EvolutionParams(ctypes.Structure):
     _fields_ = [("n_programs", _i32), ("metric", _i32), ("parsimony", _f32), ("tournament_size", _i32),
                 ("tournament_seed", _u64), ("evolve", EvolveParams), ("init", InitParams),
-                ("max_generations", _i32), ("autotune", _i32), ("time_kernel", _i32)]
+                ("max_generations", _i32), ("autotune", _i32), ("time_kernel", _i32),
+                ("first_generation", _u64)]
 
 
 _evo_create = _sig("gp_evolution_create", [ctypes.POINTER(EvolutionParams), ctypes.POINTER(DatasetDev), _vp, _vp,
@@ -638,14 +639,14 @@ class Evolution:
 
     def __init__(self, data: DeviceDataset, pop: HostPopulation, init: dict, evolve: dict | None = None,
                  metric="mse", parsimony=0.0, tournament_size=20, tournament_seed=0, max_generations=100,
-                 autotune=False, time_kernel=False):
+                 autotune=False, time_kernel=False, first_generation=0):
         self.data = data
         self.n_programs = pop.n_programs
         ev = _evolve_struct(**(evolve or {}))
         ip = _init_struct(**init)
         prm = EvolutionParams(self.n_programs, metric_id(metric), float(parsimony), int(tournament_size),
                               int(tournament_seed), ev, ip, int(max_generations), int(bool(autotune)),
-                              int(bool(time_kernel)))
+                              int(bool(time_kernel)), int(first_generation))
         c = pop.consts if pop.consts.shape[0] else np.zeros(1, np.float32)
         self._keep = [np.ascontiguousarray(pop.nodes, np.uint32), np.ascontiguousarray(pop.prog_off, np.int64),
                       np.ascontiguousarray(c, np.float32), np.ascontiguousarray(pop.const_off, np.int64),

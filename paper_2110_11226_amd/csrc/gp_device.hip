@@ -2243,6 +2243,15 @@ void generation_release(gp_generation_s* g) {
     if (g->stream) (void)hipStreamDestroy(g->stream);
 }
 
+// Fitness step of the generation objects: the fused kernels, or for
+// Spearman the batched evaluate / rank / correlate pipeline (whose buffers
+// must exist before a capture: one eager call grows them).
+gp_status graph_fitness(DeviceScratch* sc, const gp_population_dev* view, const gp_dataset_dev* data, int metric,
+                        float* fit, hipStream_t st, const LaunchCfg* cfg, const Timing& tm) {
+    if (metric == GP_METRIC_SPEARMAN) return spearman_impl(sc, view, data, fit, st);
+    return fitness_impl(sc, view, data, metric, fit, st, cfg, tm);
+}
+
 // Records the generation into g->stream: population upload, fitness,
 // tournament, result download.  Run under capture.
 gp_status record_generation(gp_generation_s* g) {
@@ -2252,7 +2261,7 @@ gp_status record_generation(gp_generation_s* g) {
     Timing tm;
     tm.stamp = g->d_stamp;
     tm.launched = &g->eval_kernel;
-    gp_status rc = fitness_impl(&g->sc, &view, &g->data, p.metric, g->d_fit, g->stream, &g->cfg, tm);
+    gp_status rc = graph_fitness(&g->sc, &view, &g->data, p.metric, g->d_fit, g->stream, &g->cfg, tm);
     if (rc != GP_OK) return rc;
     rc = tournament_impl(g->d_fit, view.len, p.n_programs, gp_metric_larger_is_better(static_cast<gp_metric>(p.metric)), p.parsimony,
                          p.tournament_size, p.n_tournaments, p.seed, 0,
@@ -2310,12 +2319,12 @@ bool insert_event_nodes(hipGraph_t graph, const void* func, hipEvent_t ev_a, hip
 // The device-resident loop: two alternating populations, a fitness history,
 // the generation counter in device memory.
 // ---------------------------------------------------------------------------
-// History entry *gen: the fitness of every program and the population's
-// node count (prog_off[P]).
+// History entry *gen - first: the fitness of every program and the
+// population's node count (prog_off[P]).
 __global__ void k_evo_record(const float* __restrict__ fit, int32_t P, const uint32_t* __restrict__ gen,
-                             int32_t cap, float* __restrict__ hist, int64_t* __restrict__ hist_nodes,
+                             uint32_t first, int32_t cap, float* __restrict__ hist, int64_t* __restrict__ hist_nodes,
                              const int64_t* __restrict__ prog_off) {
-    const uint32_t g = *gen;
+    const uint32_t g = *gen - first;
     if (g >= static_cast<uint32_t>(cap)) return;
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < P) hist[static_cast<int64_t>(g) * P + i] = fit[i];
@@ -2429,11 +2438,12 @@ gp_status evo_evaluate(gp_evolution_s* e, int which, bool timed) {
     const gp_population_dev v = evo_view(e, which);
     Timing tm;
     if (timed) tm.launched = &e->eval_kernel;
-    gp_status rc = fitness_impl(&e->sc, &v, &e->data, p.metric, e->d_fit, e->stream, &e->cfg, tm);
+    gp_status rc = graph_fitness(&e->sc, &v, &e->data, p.metric, e->d_fit, e->stream, &e->cfg, tm);
     if (rc != GP_OK) return rc;
     const int32_t P = p.n_programs;
     hipLaunchKernelGGL(k_evo_record, dim3((P + 255) / 256), dim3(256), 0, e->stream, e->d_fit, P, e->d_gen,
-                       p.max_generations + 1, e->d_hist, e->d_hist_nodes, v.prog_off);
+                       static_cast<uint32_t>(p.first_generation), p.max_generations + 1, e->d_hist,
+                       e->d_hist_nodes, v.prog_off);
     GP_HIP(hipGetLastError());
     return GP_OK;
 }
@@ -2713,7 +2723,7 @@ gp_status gp_generation_create(const gp_generation_params* prm, const gp_dataset
     *out = nullptr;
     gp_status rc = check_data(data, "gp_generation_create", true);
     if (rc != GP_OK) return rc;
-    rc = check_fitness_metric(prm->metric, "gp_generation_create");
+    rc = check_fitness_metric(prm->metric, "gp_generation_create", true);
     if (rc != GP_OK) return rc;
     if (prm->n_programs < 1 || prm->node_capacity < prm->n_programs || prm->const_capacity < 0 ||
         prm->tournament_size < 1 || prm->n_tournaments < 0 || prm->autotune < 0 || prm->time_kernel < 0)
@@ -2810,8 +2820,9 @@ gp_status gp_generation_run(gp_generation* g, const uint32_t* nodes, const int64
     if (total_consts > 0) std::memcpy(g->h_stage + g->lay.consts, consts, sizeof(float) * total_consts);
     if (!g->captured) {
         // configuration: forced, tuned on this first population, or cached/heuristic
-        g->cfg = pick_cfg(g->sc, g->data.n_features, g->data.n_rows, P, kernel_class(1, p.metric));
-        if (p.autotune && !g_forced) {
+        const bool spear = p.metric == GP_METRIC_SPEARMAN;
+        g->cfg = pick_cfg(g->sc, g->data.n_features, g->data.n_rows, P, kernel_class(spear ? 0 : 1, p.metric));
+        if (p.autotune && !g_forced && !spear) {
             GP_HIP(hipMemcpyAsync(g->d_stage, g->h_stage, g->lay.bytes, hipMemcpyHostToDevice, g->stream));
             const gp_population_dev cur_view = stage_view(g, total_nodes, total_consts);
             rc = autotune_impl(&g->sc, &cur_view, &g->data, p.metric, 2, g->stream, &g->cfg, &g->tuned_ms);
@@ -2824,6 +2835,13 @@ gp_status gp_generation_run(gp_generation* g, const uint32_t* nodes, const int64
         if (rc != GP_OK) return rc;
         rc = reserve(&g->sc, P, p.node_capacity, n_chunks, 1, p.metric);
         if (rc != GP_OK) return rc;
+        if (spear) {
+            // grow the Spearman buffers outside the capture (on this population)
+            GP_HIP(hipMemcpyAsync(g->d_stage, g->h_stage, g->lay.bytes, hipMemcpyHostToDevice, g->stream));
+            const gp_population_dev cap_full = stage_view(g, p.node_capacity, p.const_capacity);
+            rc = spearman_impl(&g->sc, &cap_full, &g->data, g->d_fit, g->stream);
+            if (rc != GP_OK) return rc;
+        }
         GP_HIP(hipStreamSynchronize(g->stream));
         GP_HIP(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
         rc = record_generation(g);
@@ -2860,7 +2878,7 @@ gp_status gp_generation_run(gp_generation* g, const uint32_t* nodes, const int64
     }
     GP_HIP(hipGraphLaunch(g->exec, g->stream));
     GP_HIP(hipStreamSynchronize(g->stream));
-    if (p.time_kernel) {
+    if (p.time_kernel && p.metric != GP_METRIC_SPEARMAN) {
         g->clock_ms = static_cast<float>(static_cast<double>(g->h_stamp[1] - g->h_stamp[0]) / g->clock_khz);
         g->kernel_ms = g->clock_ms;
         if (g->events) GP_HIP(hipEventElapsedTime(&g->kernel_ms, g->ev_a, g->ev_b));
@@ -2902,7 +2920,7 @@ gp_status gp_evolution_create(const gp_evolution_params* prm, const gp_dataset_d
     *out = nullptr;
     gp_status rc = check_data(data, "gp_evolution_create", true);
     if (rc != GP_OK) return rc;
-    rc = check_fitness_metric(prm->metric, "gp_evolution_create");
+    rc = check_fitness_metric(prm->metric, "gp_evolution_create", true);
     if (rc != GP_OK) return rc;
     const int32_t P = prm->n_programs;
     if (P < 1 || P > (1 << 29) || prm->tournament_size < 1 || prm->max_generations < 1 ||
@@ -2911,6 +2929,8 @@ gp_status gp_evolution_create(const gp_evolution_params* prm, const gp_dataset_d
                                         "1 <= max_generations <= 2^24");
     rc = mutate_check(&prm->evolve, &prm->init, P, "gp_evolution_create");
     if (rc != GP_OK) return rc;
+    if (prm->first_generation + static_cast<uint64_t>(prm->max_generations) > 0xffffffffull)
+        return fail(GP_ERR_INVALID_ARG, "gp_evolution_create: generation numbers above 2^32-1");
     if (prm->init.n_features != data->n_features)
         return fail(GP_ERR_INVALID_ARG, "gp_evolution_create: init.n_features must equal the dataset's");
     if (prog_off[0] != 0 || const_off[0] != 0)
@@ -2987,7 +3007,8 @@ gp_status gp_evolution_create(const gp_evolution_params* prm, const gp_dataset_d
                   "hipMemcpy")) != GP_OK ||
         (rc = hip(hipMemcpy(q0.len, len, sizeof(int32_t) * P, hipMemcpyHostToDevice), "hipMemcpy")) != GP_OK)
         return bail(rc);
-    hipLaunchKernelGGL(k_evo_set, dim3(1), dim3(64), 0, e->stream, e->d_gen, 0u, e->d_sticky);
+    hipLaunchKernelGGL(k_evo_set, dim3(1), dim3(64), 0, e->stream, e->d_gen,
+                       static_cast<uint32_t>(prm->first_generation), e->d_sticky);
     if ((rc = hip(hipGetLastError(), "k_evo_set")) != GP_OK) return bail(rc);
     if ((rc = hip(hipStreamSynchronize(e->stream), "hipStreamSynchronize")) != GP_OK) return bail(rc);
     *out = e;
@@ -2999,8 +3020,9 @@ gp_status evo_prepare(gp_evolution_s* e) {
     if (e->captured) return GP_OK;
     const gp_evolution_params& p = e->prm;
     const int32_t P = p.n_programs;
-    e->cfg = pick_cfg(e->sc, e->data.n_features, e->data.n_rows, P, kernel_class(1, p.metric));
-    if (p.autotune && !g_forced) {
+    const bool spear = p.metric == GP_METRIC_SPEARMAN;
+    e->cfg = pick_cfg(e->sc, e->data.n_features, e->data.n_rows, P, kernel_class(spear ? 0 : 1, p.metric));
+    if (p.autotune && !g_forced && !spear) {
         const gp_population_dev v = evo_view(e, e->cur);
         gp_status rc = autotune_impl(&e->sc, &v, &e->data, p.metric, 2, e->stream, &e->cfg, &e->tuned_ms);
         if (rc != GP_OK) return rc;
@@ -3011,6 +3033,13 @@ gp_status evo_prepare(gp_evolution_s* e) {
     if (rc != GP_OK) return rc;
     rc = reserve(&e->sc, P, e->node_cap, n_chunks, 1, p.metric);
     if (rc != GP_OK) return rc;
+    if (spear) {
+        // grow the Spearman buffers outside the capture (on the current population)
+        const gp_population_dev vc = evo_view(e, e->cur);
+        rc = spearman_impl(&e->sc, &vc, &e->data, e->d_fit, e->stream);
+        if (rc != GP_OK) return rc;
+        GP_HIP(hipStreamSynchronize(e->stream));
+    }
     if (p.time_kernel) {
         GP_HIP(hipEventCreate(&e->ev_a));
         GP_HIP(hipEventCreate(&e->ev_b));

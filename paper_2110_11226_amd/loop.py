@@ -13,7 +13,8 @@ results bit for bit.
 """
 from __future__ import annotations
 
-from dataclasses import dataclass, field
+import json
+from dataclasses import asdict, dataclass, field
 
 import numpy as np
 
@@ -37,6 +38,32 @@ class RunResult:
     fitness: np.ndarray              # their fitness
     history: list = field(default_factory=list)
     launch_config: tuple | None = None
+    generation: int = 0              # the generation number of `population`
+
+    def write_history(self, path):
+        """One JSON object per generation (generation, best, best_program,
+        mean, median, total_nodes, kernel_ms)."""
+        with open(path, "w") as f:
+            for h in self.history:
+                f.write(json.dumps(asdict(h)) + "\n")
+
+
+def save_checkpoint(path, population: B.HostPopulation, generation: int, **meta):
+    """The loop's whole state: the flat population and its generation
+    number (the draws are counter-based, so no generator state is needed),
+    with any JSON-serialisable settings in `meta`.  numpy .npz, no pickles."""
+    np.savez(path, nodes=np.asarray(population.nodes, np.uint32), prog_off=np.asarray(population.prog_off, np.int64),
+             consts=np.asarray(population.consts, np.float32), const_off=np.asarray(population.const_off, np.int64),
+             length=np.asarray(population.length, np.int32), generation=np.int64(generation),
+             meta=np.array(json.dumps(meta)))
+
+
+def load_checkpoint(path):
+    """(population, generation, meta) written by save_checkpoint."""
+    with np.load(path, allow_pickle=False) as z:
+        pop = B.HostPopulation(z["nodes"].copy(), z["prog_off"].copy(), z["consts"].copy(), z["const_off"].copy(),
+                               z["length"].copy())
+        return pop, int(z["generation"]), json.loads(str(z["meta"]))
 
 
 def _log(g, fit, total_nodes, larger, kernel_ms):
@@ -50,7 +77,8 @@ def _log(g, fit, total_nodes, larger, kernel_ms):
 def run_generations(data: B.DeviceDataset, n_generations: int, n_programs: int, init: dict,
                     metric="mse", tournament_size=20, parsimony=0.0, evolve: dict | None = None,
                     seed=0, use_graph=True, autotune=False, time_kernel=False, callback=None,
-                    device_loop=False) -> RunResult:
+                    device_loop=False, population: B.HostPopulation | None = None,
+                    first_generation: int = 0) -> RunResult:
     """Evolves `n_programs` programs for `n_generations` generations.
 
     init: initialisation settings (n_features, method, min_depth, max_depth,
@@ -64,7 +92,12 @@ def run_generations(data: B.DeviceDataset, n_generations: int, n_programs: int, 
     the same results bit for bit at the same launch configuration, with the
     history read back once at the end (the callback then runs afterwards,
     with no population, and kernel_ms is known for the last generation
-    only)."""
+    only).
+
+    population / first_generation resume a run: the population of
+    generation `first_generation` (e.g. from load_checkpoint) replaces the
+    initial one, and generations are numbered from there, so the run
+    continues exactly as if it had not stopped."""
     evolve = dict(evolve or {})
     evolve.setdefault("max_len", 1024)
     evolve.setdefault("seed", seed)
@@ -73,20 +106,27 @@ def run_generations(data: B.DeviceDataset, n_generations: int, n_programs: int, 
     larger = B.larger_is_better(metric)
     gen_kw = {k: init[k] for k in ("min_depth", "max_depth", "min_len", "max_len", "function_mask", "const_lo",
                                    "const_hi", "max_consts") if k in init}
-    pop = B.build_population(n_programs, init["n_features"], init.get("method", "rhh"), seed=init_seed, **gen_kw)
+    if population is not None:
+        if population.n_programs != n_programs:
+            raise ValueError("the population's size differs from n_programs")
+        pop = population
+    else:
+        pop = B.build_population(n_programs, init["n_features"], init.get("method", "rhh"), seed=init_seed,
+                                 **gen_kw)
+    g0 = int(first_generation)
     longest = int(pop.length.max(initial=1))
     cap = n_programs * max(int(evolve["max_len"]), longest)
     T_max = 2 * n_programs
     if device_loop:
         return _run_device(data, n_generations, pop, init, evolve, metric, tournament_size, parsimony, seed,
-                           autotune, time_kernel, callback, larger)
+                           autotune, time_kernel, callback, larger, g0)
     graph = None
     if use_graph:
         graph = B.Generation(data, n_programs, cap, cap, metric, parsimony, tournament_size, T_max, seed,
                              autotune=autotune, time_kernel=time_kernel)
     history = []
     try:
-        for g in range(n_generations + 1):
+        for g in range(g0, g0 + n_generations + 1):
             if graph is not None:
                 fit, win = graph.run(pop, g)
                 kernel_ms = graph.info()[1]
@@ -99,32 +139,32 @@ def run_generations(data: B.DeviceDataset, n_generations: int, n_programs: int, 
             history.append(_log(g, fit, pop.nodes.shape[0], larger, kernel_ms))
             if callback is not None:
                 callback(history[-1], pop, fit)
-            if g == n_generations:
+            if g == g0 + n_generations:
                 break
             ops, ft, T = B.plan_generation(n_programs, g, **evolve)
             pop = B.mutate(pop, ops, ft, win[:T], g, init, **evolve)
         cfg = graph.info()[0] if graph is not None else None
-        return RunResult(pop, fit, history, cfg)
+        return RunResult(pop, fit, history, cfg, g0 + n_generations)
     finally:
         if graph is not None:
             graph.close()
 
 
 def _run_device(data, n_generations, pop, init, evolve, metric, tournament_size, parsimony, seed, autotune,
-                time_kernel, callback, larger) -> RunResult:
+                time_kernel, callback, larger, g0) -> RunResult:
     evo = B.Evolution(data, pop, init, evolve, metric=metric, parsimony=parsimony, tournament_size=tournament_size,
                       tournament_seed=seed, max_generations=max(n_generations, 1), autotune=autotune,
-                      time_kernel=time_kernel)
+                      time_kernel=time_kernel, first_generation=g0)
     try:
         evo.run(n_generations)
         evo.evaluate()
         fit, nodes = evo.history()
         cfg, kernel_ms, _, _ = evo.info()
-        history = [_log(g, fit[g], nodes[g], larger, kernel_ms if g == n_generations - 1 else -1.0)
-                   for g in range(n_generations + 1)]
+        history = [_log(g0 + k, fit[k], nodes[k], larger, kernel_ms if k == n_generations - 1 else -1.0)
+                   for k in range(n_generations + 1)]
         if callback is not None:
-            for g in range(n_generations + 1):
-                callback(history[g], None, fit[g])
-        return RunResult(evo.population(), fit[n_generations].copy(), history, cfg)
+            for k in range(n_generations + 1):
+                callback(history[k], None, fit[k])
+        return RunResult(evo.population(), fit[n_generations].copy(), history, cfg, g0 + n_generations)
     finally:
         evo.close()

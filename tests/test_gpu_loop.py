@@ -168,3 +168,51 @@ def test_device_loop_limits(gp):
         evo.close()
     with pytest.raises(gp.GPError, match="INVALID_ARG"):
         gp.Evolution(data, pop, dict(n_features=3), dict(EVOLVE, seed=1))     # init features != data's
+
+
+def test_spearman_in_every_loop_form(gp):
+    """Spearman fitness (Sec. III-C3) in the plain loop, the captured
+    generation graph and the device-resident loop: bit-identical fitness in
+    every generation and the same final population."""
+    X, y = synth.pagie(8192 + 5, seed=11230)
+    data = gp.DeviceDataset(X, y)
+    runs = []
+    for kw in (dict(use_graph=False), dict(use_graph=True), dict(device_loop=True)):
+        fits = []
+        r = gp.run_generations(data, 4, 128, INIT, "spearman", 20, 0.01, EVOLVE, seed=21,
+                               callback=lambda log, pop, fit: fits.append(fit.copy()), **kw)
+        runs.append((r, fits))
+    (r0, f0) = runs[0]
+    assert all(np.isfinite(f).any() for f in f0)
+    for r, f in runs[1:]:
+        for g, (a, b) in enumerate(zip(f0, f)):
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), g
+        assert np.array_equal(r.population.nodes, r0.population.nodes)
+        assert np.array_equal(r.population.consts.view(np.uint32), r0.population.consts.view(np.uint32))
+    assert max(h.best for h in r0.history) > r0.history[0].best - 1e-12
+
+
+@pytest.mark.parametrize("device_loop", [False, True])
+def test_resume_from_checkpoint_continues_exactly(gp, device_loop, tmp_path):
+    """Six generations in one run equal three, a checkpoint, and three more
+    resumed from it (counter-based draws: the population and its generation
+    number are the whole state)."""
+    X, y = synth.pagie(16_384 + 3, seed=11231)
+    data = gp.DeviceDataset(X, y)
+    full = gp.run_generations(data, 6, 200, INIT, "mse", 20, 0.01, EVOLVE, seed=9, device_loop=device_loop)
+    part = gp.run_generations(data, 3, 200, INIT, "mse", 20, 0.01, EVOLVE, seed=9, device_loop=device_loop)
+    assert part.generation == 3
+    path = tmp_path / "gen3.npz"
+    gp.save_checkpoint(path, part.population, part.generation)
+    pop, g, _ = gp.load_checkpoint(path)
+    rest = gp.run_generations(data, 3, 200, INIT, "mse", 20, 0.01, EVOLVE, seed=9, device_loop=device_loop,
+                              population=pop, first_generation=g)
+    assert rest.generation == 6 and [h.generation for h in rest.history] == [3, 4, 5, 6]
+    assert [h.best for h in rest.history] == [h.best for h in full.history[3:]]
+    assert np.array_equal(rest.population.nodes, full.population.nodes)
+    assert np.array_equal(rest.population.consts.view(np.uint32), full.population.consts.view(np.uint32))
+    assert np.array_equal(rest.fitness.view(np.uint32), full.fitness.view(np.uint32))
+    rest.write_history(tmp_path / "h.jsonl")
+    import json
+    rows = [json.loads(l) for l in open(tmp_path / "h.jsonl")]
+    assert [r["generation"] for r in rows] == [3, 4, 5, 6]

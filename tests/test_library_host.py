@@ -213,3 +213,18 @@ def test_genetic_operation_errors(gp):
     broken.nodes[int(parents.prog_off[1]) - 1] = oracle.node(oracle.ADD)
     with pytest.raises(gp.GPError, match="INVALID_PROGRAM"):
         gp.mutate(broken, ops, ft, win, 0, init)
+
+
+def test_checkpoint_round_trip(gp, tmp_path):
+    """The loop's state (flat population + generation number + settings)
+    saves to .npz without pickles and loads back bit for bit."""
+    pop = gp.build_population(50, 3, "exact_len", min_len=1, max_len=40, max_consts=4,
+                              function_mask=oracle.ALL_FMASK, seed=9)
+    path = tmp_path / "state.npz"
+    gp.save_checkpoint(path, pop, 17, seed=5, metric="mse")
+    back, g, meta = gp.load_checkpoint(path)
+    assert g == 17 and meta == {"seed": 5, "metric": "mse"}
+    assert np.array_equal(back.nodes, pop.nodes) and np.array_equal(back.prog_off, pop.prog_off)
+    assert np.array_equal(back.consts.view(np.uint32), pop.consts.view(np.uint32))
+    assert np.array_equal(back.const_off, pop.const_off) and np.array_equal(back.length, pop.length)
+    gp.validate_population(back, 3)
