@@ -1487,32 +1487,38 @@ __global__ __launch_bounds__(1024) void k_spear_ranks(const uint32_t* __restrict
                                                        const float* __restrict__ w,
                                                        const int32_t* __restrict__ nan_flag,
                                                        float* __restrict__ fitness, int32_t prog0) {
-    __shared__ uint32_t sc[1024];
-    __shared__ double red[6][1024 / kWave];
+    constexpr int kW = 1024 / kWave;                 // wavefronts in the block
+    __shared__ uint32_t wtot[kW];
+    __shared__ double red[6][kW];
     const int32_t seg = blockIdx.x;
     const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1), wid = tid >> 6;
     const uint32_t* k = keys + static_cast<int64_t>(seg) * N;
     const uint32_t* ix = idx + static_cast<int64_t>(seg) * N;
     uint32_t* rs = run_start + static_cast<int64_t>(seg) * N;
-    // pass A, ascending chunks: start of the run holding position i (max-scan)
+    // pass A, ascending chunks of 1024: start of the run holding position i
+    // (an inclusive max-scan: by shuffles within each wavefront, then across
+    // the block's wavefronts through LDS, then the carry of earlier chunks)
     uint32_t carry = 0;
     for (int64_t c0 = 0; c0 < N; c0 += 1024) {
         const int64_t i = c0 + tid;
         uint32_t v = 0;
         if (i < N) v = (i == 0 || k[i] != k[i - 1]) ? static_cast<uint32_t>(i) : 0u;
-        sc[tid] = v;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            const uint32_t o = tid >= off ? sc[tid - off] : 0u;
-            __syncthreads();
-            sc[tid] = max(sc[tid], o);
-            __syncthreads();
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t o = __shfl_up(v, d, kWave);
+            if (lane >= d) v = max(v, o);
         }
-        const uint32_t st = max(sc[tid], carry);
-        if (i < N) rs[i] = st;
-        const uint32_t last = max(sc[1023], carry);
+        if (lane == kWave - 1) wtot[wid] = v;
         __syncthreads();
-        carry = last;
+        uint32_t pre = carry, all = carry;
+        for (int q = 0; q < kW; ++q) {
+            const uint32_t t = wtot[q];
+            if (q < wid) pre = max(pre, t);
+            all = max(all, t);
+        }
+        if (i < N) rs[i] = max(v, pre);
+        __syncthreads();
+        carry = all;
     }
     // pass B, descending chunks: end of the run (min-scan from the right)
     double s_w = 0.0, s_a = 0.0, s_aa = 0.0, s_ab = 0.0, s_b = 0.0, s_bb = 0.0;
@@ -1522,16 +1528,20 @@ __global__ __launch_bounds__(1024) void k_spear_ranks(const uint32_t* __restrict
         const int64_t i = c1 - 1024 + tid;
         uint32_t v = 0xffffffffu;
         if (i < N) v = (i == N - 1 || k[i] != k[i + 1]) ? static_cast<uint32_t>(i + 1) : 0xffffffffu;
-        sc[tid] = v;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            const uint32_t o = tid + off < 1024 ? sc[tid + off] : 0xffffffffu;
-            __syncthreads();
-            sc[tid] = min(sc[tid], o);
-            __syncthreads();
+        // inclusive min-scan from the right, the mirror of pass A
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t o = __shfl_down(v, d, kWave);
+            if (lane + d < kWave) v = min(v, o);
         }
-        const uint32_t en = min(sc[tid], carry_end);
-        const uint32_t first = min(sc[0], carry_end);
+        if (lane == 0) wtot[wid] = v;
+        __syncthreads();
+        uint32_t suf = carry_end, all = carry_end;
+        for (int q = 0; q < kW; ++q) {
+            const uint32_t t = wtot[q];
+            if (q > wid) suf = min(suf, t);
+            all = min(all, t);
+        }
+        const uint32_t en = min(v, suf);
         if (i < N) {
             const uint32_t r2 = rs[i] + 1u + en;        // twice the mean rank of the run
             const uint32_t row = ix[i];
@@ -1550,7 +1560,7 @@ __global__ __launch_bounds__(1024) void k_spear_ranks(const uint32_t* __restrict
             }
         }
         __syncthreads();
-        carry_end = first;
+        carry_end = all;
     }
     if constexpr (MODE == 1) {
         double v[6] = {s_w, s_a, s_aa, s_ab, s_b, s_bb};
@@ -2029,7 +2039,13 @@ gp_status spearman_impl(DeviceScratch* sc, const gp_population_dev* pop, const g
     if (N >= (int64_t{1} << 31)) return fail(GP_ERR_INVALID_ARG, "gp_fitness: Spearman needs n_rows below 2^31");
     const int32_t T = static_cast<int32_t>((N + kRsTile - 1) / kRsTile);
     // working set per program: outputs, keys and indices twice, run starts
-    const int64_t budget = int64_t{4} << 30;
+    // (24 bytes per row).  Up to 16 GiB of it, at most half the free memory
+    // (large batches fill the chip: the rank kernel runs one workgroup per
+    // program); a program's fitness does not depend on its batch.
+    size_t free_b = 0, total_b = 0;
+    GP_HIP(hipMemGetInfo(&free_b, &total_b));
+    const int64_t budget = std::max<int64_t>(std::min<int64_t>(int64_t{16} << 30, static_cast<int64_t>(free_b / 2)),
+                                             int64_t{256} << 20);
     const int32_t B = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(P, budget / (24 * N))));
     const size_t BN = static_cast<size_t>(B) * static_cast<size_t>(N);
     gp_status rc = GP_OK;
