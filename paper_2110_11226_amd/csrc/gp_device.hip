@@ -1422,28 +1422,57 @@ __global__ __launch_bounds__(1024) void k_rs_scan(uint32_t* __restrict__ counts,
     }
 }
 
-// stable scatter of one tile: keys are taken in index order, 256 at a time;
-// within a round, equal digits are ranked by lane (wave ballots) and by wave
+// stable scatter of one tile, staged through LDS: keys are taken in index
+// order, 256 at a time; within a round, equal digits are ranked by lane (wave
+// ballots) and by wave, which places every key at its digit-sorted position
+// within the tile in LDS.  The tile then goes out run by run: consecutive
+// threads write consecutive addresses of each digit's output range.  The
+// tile's count of digit d is the difference of adjacent scanned offsets
+// (digit-major over tiles, the last one closed by N).
 __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint32_t* __restrict__ kin,
                                                           const uint32_t* __restrict__ vin,
                                                           uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                           int64_t N, int32_t T, int shift,
                                                           const uint32_t* __restrict__ offsets) {
     __shared__ uint32_t base_off[kRsRadix];           // global start of each digit for this tile
+    __shared__ uint32_t loc_off[kRsRadix];            // local start of each digit within the tile
+    __shared__ uint32_t run[kRsRadix];                // keys of each digit placed so far
     __shared__ uint32_t wcnt[kRsBlock / kWave][kRsRadix];
+    __shared__ uint32_t wsum[kRsBlock / kWave];
+    __shared__ uint32_t skey[kRsTile], sval[kRsTile];
     const int32_t tile = blockIdx.x, seg = blockIdx.y;
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
-    base_off[threadIdx.x] = offsets[(static_cast<int64_t>(seg) * kRsRadix + threadIdx.x) * T + tile];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1), wave = tid >> 6;
+    const int64_t cidx = (static_cast<int64_t>(seg) * kRsRadix + tid) * T + tile;
+    const int64_t nidx = static_cast<int64_t>(kRsRadix) * T;     // offsets per segment
+    const uint32_t start = offsets[cidx];
+    const int64_t cnext = (static_cast<int64_t>(tid) * T + tile + 1 < nidx) ? cidx + 1 : -1;
+    const uint32_t cnt = (cnext >= 0 ? offsets[cnext] : static_cast<uint32_t>(N)) - start;
+    base_off[tid] = start;
+    run[tid] = 0;
+    // exclusive scan of the tile's digit counts (shuffles within each wave,
+    // then the waves' totals)
+    uint32_t v = cnt;
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t o = __shfl_up(v, d, kWave);
+        if (lane >= d) v += o;
+    }
+    if (lane == kWave - 1) wsum[wave] = v;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int q = 0; q < wave; ++q) pre += wsum[q];
+    loc_off[tid] = pre + v - cnt;
     const int64_t sbase = static_cast<int64_t>(seg) * N;
     const int64_t t0 = static_cast<int64_t>(tile) * kRsTile;
+    const int tile_len = static_cast<int>(min<int64_t>(kRsTile, N - t0));
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int k = 0; k < kRsItems; ++k) {
-        const int64_t i = t0 + k * kRsBlock + threadIdx.x;
+        const int64_t i = t0 + k * kRsBlock + tid;
         const bool valid = i < N;
         const uint32_t key = valid ? kin[sbase + i] : 0u;
         const uint32_t val = valid ? vin[sbase + i] : 0u;
         const uint32_t d = (key >> shift) & 255u;
-        for (int w = 0; w < kRsBlock / kWave; ++w) wcnt[w][threadIdx.x] = 0;
+        for (int w = 0; w < kRsBlock / kWave; ++w) wcnt[w][tid] = 0;
         __syncthreads();
         // lanes of this wave holding a valid key with the same digit
         uint64_t peers = __ballot(valid);
@@ -1462,14 +1491,26 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint32_t* __restr
             total += c;
         }
         if (valid) {
-            const uint32_t pos = base_off[d] + before + rank_w;
-            kout[sbase + pos] = key;
-            vout[sbase + pos] = val;
+            const uint32_t lp = loc_off[d] + run[d] + before + rank_w;
+            if (lp < static_cast<uint32_t>(kRsTile)) {
+                skey[lp] = key;
+                sval[lp] = val;
+            }
         }
         __syncthreads();
-        // the first holder of each digit in this round advances its start
-        if (valid && rank_w == 0 && before == 0) base_off[d] += total;
+        // the first holder of each digit in this round advances its count
+        if (valid && rank_w == 0 && before == 0) run[d] += total;
         __syncthreads();
+    }
+    // the tile, digit-sorted, to its digits' output ranges
+    for (int j = tid; j < tile_len; j += kRsBlock) {
+        const uint32_t key = skey[j];
+        const uint32_t d = (key >> shift) & 255u;
+        const uint32_t pos = base_off[d] + (static_cast<uint32_t>(j) - loc_off[d]);
+        if (pos < static_cast<uint64_t>(N)) {
+            kout[sbase + pos] = key;
+            vout[sbase + pos] = sval[j];
+        }
     }
 }
 
