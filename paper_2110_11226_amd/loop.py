@@ -78,7 +78,7 @@ def run_generations(data: B.DeviceDataset, n_generations: int, n_programs: int, 
                     metric="mse", tournament_size=20, parsimony=0.0, evolve: dict | None = None,
                     seed=0, use_graph=True, autotune=False, time_kernel=False, callback=None,
                     device_loop=False, population: B.HostPopulation | None = None,
-                    first_generation: int = 0) -> RunResult:
+                    first_generation: int = 0, refine: dict | None = None) -> RunResult:
     """Evolves `n_programs` programs for `n_generations` generations.
 
     init: initialisation settings (n_features, method, min_depth, max_depth,
@@ -97,7 +97,16 @@ def run_generations(data: B.DeviceDataset, n_generations: int, n_programs: int, 
     population / first_generation resume a run: the population of
     generation `first_generation` (e.g. from load_checkpoint) replaces the
     initial one, and generations are numbered from there, so the run
-    continues exactly as if it had not stopped."""
+    continues exactly as if it had not stopped.
+
+    refine = dict(top=0.1, steps=5, lr=1e-2) refines elite constants by
+    gradient (not in the paper): in every generation, after fitness and
+    before selection, the best `top` fraction of the programs that hold
+    constants take `steps` Adam steps on them through gp_fitness_backward;
+    a program keeps its new constants only if its fitness improved, and
+    selection sees the refined fitness.  It runs as plain calls (the
+    refinement sits between fitness and tournament), not in a graph or the
+    device loop."""
     evolve = dict(evolve or {})
     evolve.setdefault("max_len", 1024)
     evolve.setdefault("seed", seed)
@@ -117,11 +126,13 @@ def run_generations(data: B.DeviceDataset, n_generations: int, n_programs: int, 
     longest = int(pop.length.max(initial=1))
     cap = n_programs * max(int(evolve["max_len"]), longest)
     T_max = 2 * n_programs
+    if refine is not None and device_loop:
+        raise ValueError("constant refinement runs with the host loop (device_loop=False)")
     if device_loop:
         return _run_device(data, n_generations, pop, init, evolve, metric, tournament_size, parsimony, seed,
                            autotune, time_kernel, callback, larger, g0)
     graph = None
-    if use_graph:
+    if use_graph and refine is None:
         graph = B.Generation(data, n_programs, cap, cap, metric, parsimony, tournament_size, T_max, seed,
                              autotune=autotune, time_kernel=time_kernel)
     history = []
@@ -133,6 +144,9 @@ def run_generations(data: B.DeviceDataset, n_generations: int, n_programs: int, 
             else:
                 dpop = B.DevicePopulation(pop, validate=True, n_features=init["n_features"])
                 fit_d = B.fitness(dpop, data, metric)
+                if refine is not None:
+                    pop, fit_d = _refine(pop, dpop, data, metric, fit_d, larger, **refine)
+                    dpop = B.DevicePopulation(pop, validate=False)
                 win_d = B.tournament(fit_d, dpop.length, metric, parsimony, tournament_size, T_max, seed, g)
                 fit, win = fit_d.cpu().numpy(), win_d.cpu().numpy()
                 kernel_ms = -1.0
@@ -168,3 +182,20 @@ def _run_device(data, n_generations, pop, init, evolve, metric, tournament_size,
         return RunResult(evo.population(), fit[n_generations].copy(), history, cfg, g0 + n_generations)
     finally:
         evo.close()
+
+
+def _refine(pop, dpop, data, metric, fit_d, larger, top=0.1, steps=5, lr=1e-2):
+    """The elite's constants refined by gradient (see run_generations):
+    (population with the kept constants, fitness after refinement)."""
+    from .autograd import refine_constants
+    fit = fit_d.cpu().numpy()
+    n_const = np.diff(pop.const_off)
+    key = np.where(np.isfinite(fit), fit, -np.inf if larger else np.inf)
+    order = np.argsort(-key if larger else key, kind="stable")
+    k = max(1, int(round(top * pop.n_programs)))
+    elite = [int(p) for p in order[:k] if n_const[p] > 0]
+    if not elite:
+        return pop, fit_d
+    new_c, _, f_after = refine_constants(dpop, data, metric, elite, steps=steps, lr=lr)
+    consts = new_c.detach().cpu().numpy().astype(np.float32)
+    return B.HostPopulation(pop.nodes, pop.prog_off, consts, pop.const_off, pop.length), f_after.contiguous()

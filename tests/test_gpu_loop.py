@@ -216,3 +216,32 @@ def test_resume_from_checkpoint_continues_exactly(gp, device_loop, tmp_path):
     import json
     rows = [json.loads(l) for l in open(tmp_path / "h.jsonl")]
     assert [r["generation"] for r in rows] == [3, 4, 5, 6]
+
+
+def test_loop_with_constant_refinement(gp):
+    """The differentiation workload's loop (8 features, programs with up to
+    16 constants), smaller: in every generation the best 10% take 5 Adam
+    steps on their constants before selection.  At generation 0 (the same
+    programs in both runs) refinement only ever lowers a program's MSE, it
+    lowers some, and the fitness selection sees is that of the constants
+    kept."""
+    X, y = synth.diff_target(65_536, seed=12)
+    data = gp.DeviceDataset(X, y)
+    init = dict(n_features=8, method="exact_len", min_len=1, max_len=40, max_consts=16, seed=2115)
+    ev = dict(EVOLVE, max_len=64)
+    plain, refined = [], []
+    gp.run_generations(data, 3, 256, init, "mse", 20, 0.0, ev, seed=4, use_graph=False, callback=record(plain))
+    res = gp.run_generations(data, 3, 256, init, "mse", 20, 0.0, ev, seed=4,
+                             refine=dict(top=0.1, steps=5, lr=1e-2), callback=record(refined))
+    f_plain, f_ref = plain[0][2], refined[0][2]
+    same_nan = np.isnan(f_plain) == np.isnan(f_ref)
+    assert same_nan.all()
+    ok = ~np.isnan(f_plain)
+    assert np.all(f_ref[ok] <= f_plain[ok])
+    assert int((f_ref[ok] < f_plain[ok]).sum()) >= 5
+    pop0 = refined[0][1]
+    again = gp.fitness(gp.DevicePopulation(pop0, n_features=8), data, "mse").cpu().numpy()
+    assert np.array_equal(again.view(np.uint32), f_ref.view(np.uint32))
+    with pytest.raises(ValueError):
+        gp.run_generations(data, 1, 16, init, "mse", refine=dict(top=0.1), device_loop=True)
+    gp.validate_population(res.population, 8)
