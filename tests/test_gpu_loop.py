@@ -245,3 +245,44 @@ def test_loop_with_constant_refinement(gp):
     with pytest.raises(ValueError):
         gp.run_generations(data, 1, 16, init, "mse", refine=dict(top=0.1), device_loop=True)
     gp.validate_population(res.population, 8)
+
+
+def test_classification_11m_rows_ten_generations_device_loop(gp):
+    """The classification shape at full size: 11,000,000 rows x 28 features
+    (the Higgs column count), 2,000 programs of 1-200 nodes, log-loss
+    fitness, tournament size 20, ten generations on the device."""
+    import time
+    X, y = synth.higgs_like(11_000_000, seed=11230)
+    data = gp.DeviceDataset(X, y)
+    init = dict(n_features=28, method="exact_len", min_len=1, max_len=200, seed=2114)
+    t0 = time.time()
+    res = gp.run_generations(data, 10, 2000, init, "logloss", 20, 0.0, EVOLVE, seed=2114, device_loop=True)
+    wall = time.time() - t0
+    assert len(res.history) == 11 and res.generation == 10
+    gp.validate_population(res.population, 28)
+    best = [h.best for h in res.history]
+    assert np.isfinite(best).all() and min(best[1:]) <= best[0]
+    print(f"11M x 28 log-loss, 2000 programs: 10 generations in {wall:.1f} s; best {best[0]:.4f} -> {min(best):.4f}")
+
+
+def test_differentiation_workload_loop_with_refinement_full_size(gp):
+    """The differentiation shape at full size: 1,048,576 rows x 8 features,
+    2,048 programs with up to 16 constants, MSE, two generations with 5
+    Adam steps of constant refinement on the best 10% in each."""
+    import time
+    X, y = synth.diff_target(1_048_576, seed=11231)
+    data = gp.DeviceDataset(X, y)
+    init = dict(n_features=8, method="exact_len", min_len=1, max_len=200, max_consts=16, seed=2115)
+    t0 = time.time()
+    seen = []
+    res = gp.run_generations(data, 2, 2048, init, "mse", 20, 0.0, EVOLVE, seed=5,
+                             refine=dict(top=0.1, steps=5, lr=1e-2), callback=record(seen))
+    wall = time.time() - t0
+    assert len(res.history) == 3
+    gp.validate_population(res.population, 8)
+    # every logged fitness is that of the constants the population holds
+    pop1, fit1 = seen[1][1], seen[1][2]
+    again = gp.fitness(gp.DevicePopulation(pop1, n_features=8), data, "mse").cpu().numpy()
+    assert np.array_equal(again.view(np.uint32), fit1.view(np.uint32))
+    print(f"diff-1M, 2048 programs, refinement: 2 generations in {wall:.1f} s; best MSE "
+          f"{res.history[0].best:.4g} -> {min(h.best for h in res.history):.4g}")
