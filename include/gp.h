@@ -408,6 +408,15 @@ gp_status gp_get_launch_config(int32_t n_features, int64_t n_rows, int32_t n_pro
  * those calls fail with GP_ERR_INVALID_ARG. */
 gp_status gp_set_launch_config(const gp_launch_config* cfg);
 
+/* Limit on the device memory that Spearman fitness (Sec. III-C3: ranks from
+ * a sort) uses for its batches of programs: 20 bytes per row per program
+ * (outputs; sort keys and row indices, double-buffered), plus the sort's
+ * per-tile counts.  0 (the default) means 16 GiB and at most half the free
+ * memory.  A batch holds at least one program whatever the limit.  Applies
+ * to every later gp_fitness call and captured generation in this process;
+ * results do not depend on it.  A negative value gives GP_ERR_INVALID_ARG. */
+gp_status gp_set_spearman_workset(int64_t max_bytes);
+
 /* Autotuner (batching of uneven programs; not in the paper).  Times the
  * fitness computation of this population under each candidate configuration
  * -- rows_per_lane 1, 2, 4; feature registers that fit n_features, and 0;

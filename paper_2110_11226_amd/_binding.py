@@ -83,6 +83,7 @@ class LaunchConfig(ctypes.Structure):
 
 _get_cfg = _sig("gp_get_launch_config", [_i32, _i64, _i32, ctypes.c_int, ctypes.POINTER(LaunchConfig)])
 _set_cfg = _sig("gp_set_launch_config", [ctypes.POINTER(LaunchConfig)])
+_set_spear_ws = _sig("gp_set_spearman_workset", [_i64])
 _autotune = _sig("gp_autotune", [ctypes.POINTER(PopulationDev), ctypes.POINTER(DatasetDev), ctypes.c_int, _i32,
                                   ctypes.POINTER(LaunchConfig), ctypes.POINTER(ctypes.c_double), _vp])
 _tune_save = _sig("gp_autotune_save", [ctypes.c_char_p])
@@ -191,6 +192,13 @@ def set_launch_config(cfg=None):
             v.append(4)
         c = LaunchConfig(*v)
         _check(_set_cfg(ctypes.byref(c)), "gp_set_launch_config")
+
+
+def set_spearman_workset(max_bytes=0):
+    """Device memory Spearman fitness may use for a batch of programs (20
+    bytes per row per program); 0 returns to the default (16 GiB, at most half
+    the free memory)."""
+    _check(_set_spear_ws(int(max_bytes)), "gp_set_spearman_workset")
 
 
 class GPError(RuntimeError):

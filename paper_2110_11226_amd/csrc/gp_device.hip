@@ -1397,28 +1397,46 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_count(const uint32_t* __restric
     counts[(static_cast<int64_t>(seg) * kRsRadix + threadIdx.x) * T + tile] = hist[threadIdx.x];
 }
 
-// exclusive scan of one segment's 256*T counts, digit-major (in place)
+// exclusive scan of one segment's 256*T counts, digit-major (in place), in
+// chunks of 1,024 consecutive counts (coalesced; four chunks' loads issued
+// together): shuffle scans within each wavefront, the wavefronts' totals
+// through LDS (double-buffered, so one barrier per chunk), then the carry of
+// the earlier chunks.
 __global__ __launch_bounds__(1024) void k_rs_scan(uint32_t* __restrict__ counts, int32_t T) {
-    __shared__ uint32_t part[1024];
+    constexpr int kW = 1024 / kWave, kE = 4;
+    __shared__ uint32_t wtot[2][kW];
     const int64_t n = static_cast<int64_t>(kRsRadix) * T;
     uint32_t* c = counts + static_cast<int64_t>(blockIdx.x) * n;
-    const int64_t per = (n + 1023) / 1024;
-    const int64_t a = min(n, per * threadIdx.x), b = min(n, a + per);
-    uint32_t sum = 0;
-    for (int64_t i = a; i < b; ++i) sum += c[i];
-    part[threadIdx.x] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {   // inclusive Hillis-Steele scan
-        const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
-    }
-    uint32_t run = part[threadIdx.x] - sum;     // exclusive prefix of this thread's range
-    for (int64_t i = a; i < b; ++i) {
-        const uint32_t v = c[i];
-        c[i] = run;
-        run += v;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid >> 6;
+    uint32_t carry = 0;
+    int par = 0;
+    for (int64_t c0 = 0; c0 < n; c0 += 1024 * kE) {
+        uint32_t v[kE];
+#pragma unroll
+        for (int e = 0; e < kE; ++e) {
+            const int64_t i = c0 + e * 1024 + tid;
+            v[e] = i < n ? c[i] : 0u;
+        }
+#pragma unroll
+        for (int e = 0; e < kE; ++e) {
+            uint32_t x = v[e];
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t o = __shfl_up(x, d, kWave);
+                if (lane >= d) x += o;
+            }
+            if (lane == kWave - 1) wtot[par][wid] = x;
+            __syncthreads();
+            uint32_t pre = carry, all = carry;
+            for (int q = 0; q < kW; ++q) {
+                const uint32_t t = wtot[par][q];
+                pre += q < wid ? t : 0u;
+                all += t;
+            }
+            const int64_t i = c0 + e * 1024 + tid;
+            if (i < n) c[i] = pre + x - v[e];
+            carry = all;
+            par ^= 1;
+        }
     }
 }
 
@@ -1466,11 +1484,20 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint32_t* __restr
     const int64_t t0 = static_cast<int64_t>(tile) * kRsTile;
     const int tile_len = static_cast<int>(min<int64_t>(kRsTile, N - t0));
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    // the whole tile's loads are issued before the first round
+    uint32_t pkey[kRsItems], pval[kRsItems];
+#pragma unroll
+    for (int k = 0; k < kRsItems; ++k) {
+        const int64_t i = t0 + k * kRsBlock + tid;
+        pkey[k] = i < N ? kin[sbase + i] : 0u;
+        pval[k] = i < N ? vin[sbase + i] : 0u;
+    }
+#pragma unroll
     for (int k = 0; k < kRsItems; ++k) {
         const int64_t i = t0 + k * kRsBlock + tid;
         const bool valid = i < N;
-        const uint32_t key = valid ? kin[sbase + i] : 0u;
-        const uint32_t val = valid ? vin[sbase + i] : 0u;
+        const uint32_t key = pkey[k];
+        const uint32_t val = pval[k];
         const uint32_t d = (key >> shift) & 255u;
         for (int w = 0; w < kRsBlock / kWave; ++w) wcnt[w][tid] = 0;
         __syncthreads();
@@ -1514,32 +1541,27 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint32_t* __restr
     }
 }
 
-// Walks one segment's sorted keys (one workgroup): tied runs share the mean
-// of their ranks; twice that rank is used so that it stays an integer.
-// MODE 0 writes rank2[idx] (the target's ranks); MODE 1 accumulates the
-// weighted moments of (value rank, target rank), both centred on (N+1)/2,
-// and writes |r| (0 for a constant rank vector, NaN if the outputs held a NaN).
-template <int MODE>
-__global__ __launch_bounds__(1024) void k_spear_ranks(const uint32_t* __restrict__ keys,
-                                                       const uint32_t* __restrict__ idx, int64_t N,
-                                                       uint32_t* __restrict__ run_start,
-                                                       uint32_t* __restrict__ rank2_out,
-                                                       const uint32_t* __restrict__ rank2_y,
-                                                       const float* __restrict__ w,
-                                                       const int32_t* __restrict__ nan_flag,
-                                                       float* __restrict__ fitness, int32_t prog0) {
+// The target's ranks, from its sorted keys (one workgroup): rank2[row] is
+// twice the mean rank of the tied run holding the row, an integer.  Pass A,
+// ascending chunks of 1,024: the start of the run holding position i (an
+// inclusive max-scan: shuffles within each wavefront, the wavefronts' totals
+// through LDS, the carry of earlier chunks), kept in run_start.  Pass B,
+// descending: the end of the run (the mirror min-scan from the right), and
+// the weighted sums (w, w b, w b^2) of the centred ranks b = rank - (N+1)/2,
+// which every program's correlation shares (tsum).
+__global__ __launch_bounds__(1024) void k_spear_rank_target(const uint32_t* __restrict__ keys,
+                                                             const uint32_t* __restrict__ idx, int64_t N,
+                                                             const float* __restrict__ w,
+                                                             uint32_t* __restrict__ run_start,
+                                                             uint32_t* __restrict__ rank2_out,
+                                                             double* __restrict__ tsum) {
     constexpr int kW = 1024 / kWave;                 // wavefronts in the block
     __shared__ uint32_t wtot[kW];
-    __shared__ double red[6][kW];
-    const int32_t seg = blockIdx.x;
+    __shared__ double red[3][kW];
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wid = tid >> 6;
-    const uint32_t* k = keys + static_cast<int64_t>(seg) * N;
-    const uint32_t* ix = idx + static_cast<int64_t>(seg) * N;
-    uint32_t* rs = run_start + static_cast<int64_t>(seg) * N;
-    // pass A, ascending chunks of 1024: start of the run holding position i
-    // (an inclusive max-scan: by shuffles within each wavefront, then across
-    // the block's wavefronts through LDS, then the carry of earlier chunks)
+    const uint32_t* k = keys;
+    uint32_t* rs = run_start;
     uint32_t carry = 0;
     for (int64_t c0 = 0; c0 < N; c0 += 1024) {
         const int64_t i = c0 + tid;
@@ -1561,15 +1583,13 @@ __global__ __launch_bounds__(1024) void k_spear_ranks(const uint32_t* __restrict
         __syncthreads();
         carry = all;
     }
-    // pass B, descending chunks: end of the run (min-scan from the right)
-    double s_w = 0.0, s_a = 0.0, s_aa = 0.0, s_ab = 0.0, s_b = 0.0, s_bb = 0.0;
     const double mid = 0.5 * (static_cast<double>(N) + 1.0);
+    double s_w = 0.0, s_b = 0.0, s_bb = 0.0;
     uint32_t carry_end = static_cast<uint32_t>(N);
     for (int64_t c1 = ((N + 1023) / 1024) * 1024; c1 > 0; c1 -= 1024) {
         const int64_t i = c1 - 1024 + tid;
         uint32_t v = 0xffffffffu;
         if (i < N) v = (i == N - 1 || k[i] != k[i + 1]) ? static_cast<uint32_t>(i + 1) : 0xffffffffu;
-        // inclusive min-scan from the right, the mirror of pass A
         for (int d = 1; d < kWave; d <<= 1) {
             const uint32_t o = __shfl_down(v, d, kWave);
             if (lane + d < kWave) v = min(v, o);
@@ -1582,55 +1602,171 @@ __global__ __launch_bounds__(1024) void k_spear_ranks(const uint32_t* __restrict
             if (q > wid) suf = min(suf, t);
             all = min(all, t);
         }
-        const uint32_t en = min(v, suf);
         if (i < N) {
-            const uint32_t r2 = rs[i] + 1u + en;        // twice the mean rank of the run
-            const uint32_t row = ix[i];
-            if constexpr (MODE == 0) {
-                rank2_out[row] = r2;
-            } else {
-                const double a = 0.5 * static_cast<double>(r2) - mid;
-                const double b = 0.5 * static_cast<double>(rank2_y[row]) - mid;
-                const double wv = w ? static_cast<double>(w[row]) : 1.0;
-                s_w += wv;
-                s_a += wv * a;
-                s_aa += wv * a * a;
-                s_ab += wv * a * b;
-                s_b += wv * b;
-                s_bb += wv * b * b;
-            }
+            const uint32_t row = idx[i];
+            const uint32_t r2 = rs[i] + 1u + min(v, suf);
+            rank2_out[row] = r2;
+            const double wv = w ? static_cast<double>(w[row]) : 1.0;
+            const double b = 0.5 * static_cast<double>(r2) - mid;
+            s_w += wv;
+            s_b += wv * b;
+            s_bb += wv * b * b;
         }
         __syncthreads();
         carry_end = all;
     }
-    if constexpr (MODE == 1) {
-        double v[6] = {s_w, s_a, s_aa, s_ab, s_b, s_bb};
+    double v[3] = {s_w, s_b, s_bb};
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            const double t = wave_sum(v[q]);
-            if ((tid & (kWave - 1)) == 0) red[q][tid >> 6] = t;
+    for (int q = 0; q < 3; ++q) {
+        const double t = wave_sum(v[q]);
+        if (lane == 0) red[q][wid] = t;
+    }
+    __syncthreads();
+    if (tid < 3) {
+        double acc = 0.0;
+        for (int j = 0; j < kW; ++j) acc += red[tid][j];
+        tsum[tid] = acc;
+    }
+}
+
+// Rank correlation of a batch of programs, one workgroup per program and one
+// pass over its sorted keys.  The tied run holding position i spans
+// [start, end) and twice its mean rank is start + 1 + end.  Each block of
+// 1,024 positions finds starts by a max-scan from the left and ends by a
+// min-scan from the right (wavefront shuffles, the wavefronts' totals in
+// double-buffered LDS: one barrier per block of positions).  A run that
+// reaches past the block is still open: each thread sums its rows' weights
+// and weighted target ranks for it, and folds those sums in with the run's
+// mean rank in the block whose first end closes the run (its start is then
+// the carry of the earlier blocks).  With a = rank - (N+1)/2 for the program
+// and b likewise for the target, the weighted sums of a, a^2 and a b and the
+// target's shared sums (tsum) give |r|: 0 for a constant rank vector, NaN if
+// the outputs held a NaN.  Two blocks' loads go out together.
+template <bool WEIGHTED>
+__global__ __launch_bounds__(1024) void k_spear_corr(const uint32_t* __restrict__ keys,
+                                                      const uint32_t* __restrict__ idx, int64_t N,
+                                                      const uint32_t* __restrict__ rank2_y,
+                                                      const float* __restrict__ w,
+                                                      const double* __restrict__ tsum,
+                                                      const int32_t* __restrict__ nan_flag,
+                                                      float* __restrict__ fitness, int32_t prog0) {
+    constexpr int kW = 1024 / kWave, kE = 2;
+    constexpr uint32_t kNone = 0xffffffffu;
+    __shared__ uint32_t wmax[2][kW], wmin[2][kW];
+    __shared__ double red[3][kW];
+    const int32_t seg = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1), wid = tid >> 6;
+    const uint32_t n = static_cast<uint32_t>(N);      // below 2^31
+    const uint32_t* k = keys + static_cast<int64_t>(seg) * N;
+    const uint32_t* ix = idx + static_cast<int64_t>(seg) * N;
+    const double mid = 0.5 * (static_cast<double>(N) + 1.0);
+    double s_a = 0.0, s_aa = 0.0, s_ab = 0.0;
+    double o_w = 0.0, o_wb = 0.0;     // this thread's rows of the open run
+    uint32_t carry = 0;               // start of the last run so far
+    int par = 0;
+    for (uint32_t c0 = 0; c0 < n; c0 += 1024 * kE) {
+        uint32_t kc[kE], ry[kE];
+        float wf[kE];
+#pragma unroll
+        for (int e = 0; e < kE; ++e) {
+            const uint32_t i = c0 + e * 1024 + tid;
+            kc[e] = i < n ? k[i] : 0u;
+            ry[e] = i < n ? ix[i] : 0u;
         }
-        __syncthreads();
-        if (tid == 0) {
-            double tot[6];
 #pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                double acc = 0.0;
-                for (int j = 0; j < 1024 / kWave; ++j) acc += red[q][j];
-                tot[q] = acc;
+        for (int e = 0; e < kE; ++e) {
+            const uint32_t i = c0 + e * 1024 + tid;
+            const uint32_t row = ry[e];
+            ry[e] = i < n ? rank2_y[row] : 0u;
+            wf[e] = (WEIGHTED && i < n) ? w[row] : 1.0f;
+        }
+#pragma unroll
+        for (int e = 0; e < kE; ++e) {
+            const uint32_t i = c0 + e * 1024 + tid;
+            const bool in = i < n;
+            // neighbours by shuffles, loads at the wavefront's edges
+            uint32_t kp = __shfl_up(kc[e], 1, kWave), kn = __shfl_down(kc[e], 1, kWave);
+            if (lane == 0) kp = (in && i > 0) ? k[i - 1] : 0u;
+            if (lane == kWave - 1) kn = (i + 1 < n) ? k[i + 1] : 0u;
+            const bool start = in && (i == 0 || kc[e] != kp);
+            const bool end = in && (i == n - 1 || kc[e] != kn);
+            uint32_t vs = start ? i : 0u;
+            uint32_t ve = end ? i + 1 : kNone;
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t os = __shfl_up(vs, d, kWave);
+                const uint32_t oe = __shfl_down(ve, d, kWave);
+                if (lane >= d) vs = max(vs, os);
+                if (lane + d < kWave) ve = min(ve, oe);
             }
-            const double W = tot[0];
-            const double va = tot[2] - tot[1] * tot[1] / W;
-            const double vb = tot[5] - tot[4] * tot[4] / W;
-            const double cab = tot[3] - tot[1] * tot[4] / W;
-            // one run of equal values: a constant rank vector
-            const bool constant = rs[N - 1] == 0u;
-            float f;
-            if (nan_flag[seg]) f = __builtin_nanf("");
-            else if (constant || !(va > 0.0) || !(vb > 0.0) || !isfinite(va) || !isfinite(vb)) f = 0.0f;
-            else f = static_cast<float>(fabs(cab / sqrt(va * vb)));
-            fitness[prog0 + seg] = f;
+            if (lane == kWave - 1) wmax[par][wid] = vs;
+            if (lane == 0) wmin[par][wid] = ve;
+            __syncthreads();
+            // the wavefronts' totals, lane q holding wavefront q's: a prefix
+            // max and a suffix min over them by shuffles
+            uint32_t tm = lane < kW ? wmax[par][lane] : 0u;
+            uint32_t te = lane < kW ? wmin[par][lane] : kNone;
+            for (int d = 1; d < kW; d <<= 1) {
+                const uint32_t om = __shfl_up(tm, d, kWave);
+                const uint32_t oe = __shfl_down(te, d, kWave);
+                if (lane >= d) tm = max(tm, om);
+                if (lane + d < kWave) te = min(te, oe);
+            }
+            const uint32_t pre = max(carry, wid > 0 ? static_cast<uint32_t>(__shfl(tm, wid - 1, kWave)) : 0u);
+            const uint32_t all = max(carry, static_cast<uint32_t>(__shfl(tm, kW - 1, kWave)));
+            const uint32_t suf = wid < kW - 1 ? static_cast<uint32_t>(__shfl(te, wid + 1, kWave)) : kNone;
+            const uint32_t first_end = __shfl(te, 0, kWave);
+            if (first_end != kNone) {       // the open run (if any) ends here
+                const double a = 0.5 * (static_cast<double>(carry) + 1.0 + static_cast<double>(first_end)) - mid;
+                s_a += a * o_w;
+                s_aa += a * a * o_w;
+                s_ab += a * o_wb;
+                o_w = 0.0;
+                o_wb = 0.0;
+            }
+            if (in) {
+                const double wv = static_cast<double>(wf[e]);
+                const double b = 0.5 * static_cast<double>(ry[e]) - mid;
+                const uint32_t en = min(ve, suf);
+                if (en != kNone) {
+                    const double a = 0.5 * (static_cast<double>(max(vs, pre)) + 1.0 + static_cast<double>(en)) - mid;
+                    s_a += wv * a;
+                    s_aa += wv * a * a;
+                    s_ab += wv * a * b;
+                } else {
+                    o_w += wv;
+                    o_wb += wv * b;
+                }
+            }
+            carry = all;
+            par ^= 1;
         }
+    }
+    double v[3] = {s_a, s_aa, s_ab};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const double t = wave_sum(v[q]);
+        if (lane == 0) red[q][wid] = t;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double tot[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            double acc = 0.0;
+            for (int j = 0; j < kW; ++j) acc += red[q][j];
+            tot[q] = acc;
+        }
+        const double W = tsum[0];
+        const double va = tot[1] - tot[0] * tot[0] / W;
+        const double vb = tsum[2] - tsum[1] * tsum[1] / W;
+        const double cab = tot[2] - tot[0] * tsum[1] / W;
+        const bool constant = k[0] == k[n - 1];    // one run of equal values
+        float f;
+        if (nan_flag[seg]) f = __builtin_nanf("");
+        else if (constant || !(va > 0.0) || !(vb > 0.0) || !isfinite(va) || !isfinite(vb)) f = 0.0f;
+        else f = static_cast<float>(fabs(cab / sqrt(va * vb)));
+        fitness[prog0 + seg] = f;
     }
 }
 
@@ -1666,8 +1802,8 @@ struct DeviceScratch {
     size_t tape_cap = 0;
     float* fit_tmp = nullptr;
     size_t fit_tmp_cap = 0;
-    // Spearman: program outputs, sort keys and indices (double-buffered), run
-    // starts, digit counts, the target's ranks, NaN flags
+    // Spearman: program outputs, sort keys and indices (double-buffered), the
+    // target's run starts, digit counts, the target's ranks, NaN flags
     float* sp_out = nullptr;
     size_t sp_out_cap = 0;
     uint32_t* sp_k0 = nullptr;
@@ -1686,6 +1822,8 @@ struct DeviceScratch {
     size_t sp_r2y_cap = 0;
     int32_t* sp_nan = nullptr;
     size_t sp_nan_cap = 0;
+    double* sp_ty = nullptr;     // the target ranks' weighted sums (w, w b, w b^2)
+    size_t sp_ty_cap = 0;
     int n_cu = 0;
     int dev = -1;
     std::string arch;
@@ -1739,7 +1877,7 @@ gp_status scratch_init(DeviceScratch& s, int dev) {
 bool scratch_empty(const DeviceScratch& s) {
     return !s.counter && !s.order && !s.part && !s.ystat && !s.code && !s.clen && !s.stats && !s.gpart &&
            !s.gextra && !s.tape && !s.fit_tmp && !s.sp_out && !s.sp_k0 && !s.sp_k1 && !s.sp_v0 && !s.sp_v1 &&
-           !s.sp_rs && !s.sp_cnt && !s.sp_r2y && !s.sp_nan;
+           !s.sp_rs && !s.sp_cnt && !s.sp_r2y && !s.sp_nan && !s.sp_ty;
 }
 
 // Frees every buffer of s (the caller has made its device current and idle).
@@ -1750,7 +1888,7 @@ void scratch_free(DeviceScratch& s) {
                     static_cast<void*>(s.tape), static_cast<void*>(s.fit_tmp), static_cast<void*>(s.sp_out),
                     static_cast<void*>(s.sp_k0), static_cast<void*>(s.sp_k1), static_cast<void*>(s.sp_v0),
                     static_cast<void*>(s.sp_v1), static_cast<void*>(s.sp_rs), static_cast<void*>(s.sp_cnt),
-                    static_cast<void*>(s.sp_r2y), static_cast<void*>(s.sp_nan)})
+                    static_cast<void*>(s.sp_r2y), static_cast<void*>(s.sp_nan), static_cast<void*>(s.sp_ty)})
         if (q) (void)hipFree(q);
     s = DeviceScratch{};
 }
@@ -1810,6 +1948,7 @@ bool cfg_valid(const LaunchCfg& c) {
 }
 
 bool g_forced = false;
+int64_t g_spear_workset = 0;       // Spearman batch working-set limit in bytes (0: automatic)
 LaunchCfg g_forced_cfg{4, 0, 1, 4};
 
 // Evaluation kernels differ by metric; each class is tuned on its own.
@@ -2079,15 +2218,26 @@ gp_status spearman_impl(DeviceScratch* sc, const gp_population_dev* pop, const g
     const int32_t P = pop->n_programs;
     if (N >= (int64_t{1} << 31)) return fail(GP_ERR_INVALID_ARG, "gp_fitness: Spearman needs n_rows below 2^31");
     const int32_t T = static_cast<int32_t>((N + kRsTile - 1) / kRsTile);
-    // working set per program: outputs, keys and indices twice, run starts
-    // (24 bytes per row).  Up to 16 GiB of it, at most half the free memory
-    // (large batches fill the chip: the rank kernel runs one workgroup per
-    // program); a program's fitness does not depend on its batch.
-    size_t free_b = 0, total_b = 0;
-    GP_HIP(hipMemGetInfo(&free_b, &total_b));
-    const int64_t budget = std::max<int64_t>(std::min<int64_t>(int64_t{16} << 30, static_cast<int64_t>(free_b / 2)),
-                                             int64_t{256} << 20);
-    const int32_t B = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(P, budget / (24 * N))));
+    // working set per program: outputs, keys and indices twice (20 bytes per
+    // row).  Up to the set limit, else 16 GiB of it and at most half the
+    // free memory; a program's fitness does not depend on its batch.  When
+    // the programs need several batches, a batch is a whole number of rounds
+    // of resident correlation workgroups (one per program).
+    int64_t budget = g_spear_workset;
+    if (budget <= 0) {
+        size_t free_b = 0, total_b = 0;
+        GP_HIP(hipMemGetInfo(&free_b, &total_b));
+        budget = std::max<int64_t>(std::min<int64_t>(int64_t{16} << 30, static_cast<int64_t>(free_b / 2)),
+                                   int64_t{256} << 20);
+    }
+    int64_t Bmax = std::max<int64_t>(1, budget / (20 * N));
+    if (Bmax < P) {
+        int per_cu = 0;
+        GP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spear_corr<false>, 1024, 0));
+        const int64_t round = static_cast<int64_t>(std::max(per_cu, 1)) * sc->n_cu;
+        if (Bmax > round) Bmax = (Bmax / round) * round;
+    }
+    const int32_t B = static_cast<int32_t>(std::min<int64_t>(P, Bmax));
     const size_t BN = static_cast<size_t>(B) * static_cast<size_t>(N);
     gp_status rc = GP_OK;
     auto need = [&](void** ptr, size_t* cap, size_t n, size_t elem) {
@@ -2098,11 +2248,12 @@ gp_status spearman_impl(DeviceScratch* sc, const gp_population_dev* pop, const g
     need(reinterpret_cast<void**>(&sc->sp_k1), &sc->sp_k1_cap, BN, sizeof(uint32_t));
     need(reinterpret_cast<void**>(&sc->sp_v0), &sc->sp_v0_cap, BN, sizeof(uint32_t));
     need(reinterpret_cast<void**>(&sc->sp_v1), &sc->sp_v1_cap, BN, sizeof(uint32_t));
-    need(reinterpret_cast<void**>(&sc->sp_rs), &sc->sp_rs_cap, BN, sizeof(uint32_t));
+    need(reinterpret_cast<void**>(&sc->sp_rs), &sc->sp_rs_cap, static_cast<size_t>(N), sizeof(uint32_t));
     need(reinterpret_cast<void**>(&sc->sp_cnt), &sc->sp_cnt_cap, static_cast<size_t>(B) * kRsRadix * T,
          sizeof(uint32_t));
     need(reinterpret_cast<void**>(&sc->sp_r2y), &sc->sp_r2y_cap, static_cast<size_t>(N), sizeof(uint32_t));
     need(reinterpret_cast<void**>(&sc->sp_nan), &sc->sp_nan_cap, static_cast<size_t>(B), sizeof(int32_t));
+    need(reinterpret_cast<void**>(&sc->sp_ty), &sc->sp_ty_cap, 3, sizeof(double));
     if (rc != GP_OK) return rc;
     auto fill_nan_flags = [&](int32_t n) -> gp_status {
         hipLaunchKernelGGL(k_fill_i32, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, sc->sp_nan,
@@ -2119,8 +2270,8 @@ gp_status spearman_impl(DeviceScratch* sc, const gp_population_dev* pop, const g
                        dim3(kRsBlock), 0, st, data->y, N, 1, sc->sp_k0, sc->sp_v0, sc->sp_nan);
     GP_HIP(hipGetLastError());
     if ((rc = radix_sort_segments(sc, N, 1, st)) != GP_OK) return rc;
-    hipLaunchKernelGGL(k_spear_ranks<0>, dim3(1), dim3(1024), 0, st, sc->sp_k0, sc->sp_v0, N, sc->sp_rs,
-                       sc->sp_r2y, nullptr, nullptr, nullptr, nullptr, 0);
+    hipLaunchKernelGGL(k_spear_rank_target, dim3(1), dim3(1024), 0, st, sc->sp_k0, sc->sp_v0, N, data->w,
+                       sc->sp_rs, sc->sp_r2y, sc->sp_ty);
     GP_HIP(hipGetLastError());
     for (int32_t p0 = 0; p0 < P; p0 += B) {
         const int32_t b = std::min(B, P - p0);
@@ -2143,8 +2294,12 @@ gp_status spearman_impl(DeviceScratch* sc, const gp_population_dev* pop, const g
                            sc->sp_v0, sc->sp_nan);
         GP_HIP(hipGetLastError());
         if ((rc = radix_sort_segments(sc, N, b, st)) != GP_OK) return rc;
-        hipLaunchKernelGGL(k_spear_ranks<1>, dim3(b), dim3(1024), 0, st, sc->sp_k0, sc->sp_v0, N, sc->sp_rs,
-                           nullptr, sc->sp_r2y, data->w, sc->sp_nan, fitness, p0);
+        if (data->w)
+            hipLaunchKernelGGL(k_spear_corr<true>, dim3(b), dim3(1024), 0, st, sc->sp_k0, sc->sp_v0, N, sc->sp_r2y,
+                               data->w, sc->sp_ty, sc->sp_nan, fitness, p0);
+        else
+            hipLaunchKernelGGL(k_spear_corr<false>, dim3(b), dim3(1024), 0, st, sc->sp_k0, sc->sp_v0, N, sc->sp_r2y,
+                               nullptr, sc->sp_ty, sc->sp_nan, fitness, p0);
         GP_HIP(hipGetLastError());
     }
     return GP_OK;
@@ -2596,6 +2751,13 @@ gp_status gp_set_launch_config(const gp_launch_config* cfg) {
                                         "tiles_per_chunk in [1, 2^20], waves_per_block in {1,2,4}");
     g_forced_cfg = c;
     g_forced = true;
+    return GP_OK;
+}
+
+gp_status gp_set_spearman_workset(int64_t max_bytes) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (max_bytes < 0) return fail(GP_ERR_INVALID_ARG, "gp_set_spearman_workset: max_bytes must be >= 0");
+    g_spear_workset = max_bytes;
     return GP_OK;
 }
 

@@ -52,13 +52,13 @@ def populations(gp, P, F, n):
     return out
 
 
-@pytest.mark.parametrize("metric", ["mse", "pearson", "logloss"])
+@pytest.mark.parametrize("metric", ["mse", "pearson", "logloss", "spearman"])
 def test_graph_replays_match_plain_calls(gp, metric):
     P, N, F = 256, 70_001, 2
     X, y = synth.pagie(N, seed=11227)
     if metric == "logloss":
         y = (y > np.median(y)).astype(np.float32)
-    w = synth.weights(N, seed=4) if metric == "pearson" else None
+    w = synth.weights(N, seed=4) if metric in ("pearson", "spearman") else None
     data = gp.DeviceDataset(X, y, w)
     pops = populations(gp, P, F, 5)
     cap_nodes = max(int(p.nodes.shape[0]) for p in pops)
@@ -73,7 +73,7 @@ def test_graph_replays_match_plain_calls(gp, metric):
             assert np.array_equal(fit_g.view(np.uint32), fit_e.view(np.uint32)), (metric, g)
             assert np.array_equal(win_g, win_e), (metric, g)
             # and against the oracle's tournament on the same fitness array
-            ow = oracle.tournament(fit_g, host.length, metric == "pearson", c, k, T, seed, g)
+            ow = oracle.tournament(fit_g, host.length, gp.larger_is_better(metric), c, k, T, seed, g)
             assert np.array_equal(win_g, ow), (metric, g)
         # a population replayed a second time gives the same results
         fit_a, win_a = gen.run(pops[1], 1)

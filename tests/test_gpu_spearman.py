@@ -65,10 +65,12 @@ def test_spearman_rhh_population(gp, weighted):
     assert tight >= 40
 
 
-def test_spearman_ties_everywhere(gp):
-    # integer features and a coarse target: most values tie on both sides
+@pytest.mark.parametrize("N", [3000, 70_000])
+def test_spearman_ties_everywhere(gp, N):
+    """Integer features and a coarse target: most values tie on both sides,
+    and at 70,000 rows tied runs reach across many blocks of positions of the
+    correlation kernel (a constant program is one run of all rows)."""
     rng = np.random.default_rng(5)
-    N = 3000
     X = rng.integers(-4, 5, size=(2, N)).astype(np.float32)
     y = np.round(rng.normal(size=N) * 2).astype(np.float32)
     fmask = sum(1 << o for o in (oracle.ADD, oracle.SUB, oracle.MUL, oracle.NEG))
@@ -98,14 +100,20 @@ def test_spearman_nan_and_constant_programs(gp):
     assert np.allclose(got[[1, 3]], f32p[[1, 3]], rtol=1e-6)
 
 
-@pytest.mark.parametrize("N", [1, 2, 63, 4097, 1_500_000])
-def test_spearman_sizes_and_batches(gp, N):
-    """Ragged tiles, tiny inputs and, at 1.5M rows, several program batches
-    (the sort works on at most 4 GiB of outputs and keys at a time)."""
+@pytest.mark.parametrize("N,workset", [(1, 0), (2, 0), (63, 0), (4097, 0), (1_500_000, 0),
+                                       (1_500_000, 700 << 20)])
+def test_spearman_sizes_and_batches(gp, N, workset):
+    """Ragged tiles, tiny inputs, 1.5M rows in one batch and, with the working
+    set limited to 700 MiB (20 bytes per row per program: 24 programs a
+    batch), in seven batches, the last one short."""
     X, y = synth.pagie(N, seed=N)
     fmask = sum(1 << o for o in (oracle.ADD, oracle.SUB, oracle.MUL, oracle.DIV, oracle.NEG, oracle.SQRT))
     P = 160 if N > 100_000 else 48
     host = gp.build_population(P, 2, "rhh", min_depth=1, max_depth=5, function_mask=fmask, seed=7)
-    got = gpu_spearman(gp, host, X, y, None, 2)
+    gp.set_spearman_workset(workset)
+    try:
+        got = gpu_spearman(gp, host, X, y, None, 2)
+    finally:
+        gp.set_spearman_workset(0)
     f32p, f64, fb, fn = oracle.fitness(to_oracle(host), X, y, None, "spearman", n_threads=NT, with_bound=True)
     check(got, f32p, fb, fn, f"N={N}")

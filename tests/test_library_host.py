@@ -143,6 +143,9 @@ def test_device_entry_points_reject_bad_arguments_before_launch(gp):
     with pytest.raises(gp.GPError, match="INVALID_ARG"):
         gp.set_launch_config((4, 5, 1))
     gp.set_launch_config(None)
+    with pytest.raises(gp.GPError, match="INVALID_ARG"):
+        gp.set_spearman_workset(-1)
+    gp.set_spearman_workset(0)
 
 
 def test_metric_direction(gp):
