@@ -1354,9 +1354,10 @@ __global__ __launch_bounds__(kBlock) void k_tournament(const float* __restrict__
 // giving tied values the mean of their ranks, and forms the float64 moments
 // of the (value rank, target rank) pairs.
 // ---------------------------------------------------------------------------
-constexpr int kRsBlock = 256;                  // threads of the sort kernels
-constexpr int kRsItems = 16;                   // keys per thread
-constexpr int kRsTile = kRsBlock * kRsItems;   // keys per tile
+constexpr int kRsBlock = 256;                  // threads of the key and count kernels
+constexpr int kRsScatterBlock = 512;           // threads of the scatter
+constexpr int kRsItems = 16;                   // keys per scatter thread
+constexpr int kRsTile = kRsScatterBlock * kRsItems;   // keys per tile
 constexpr int kRsRadix = 256;
 
 // float -> uint32 with the same order; -0 and +0 map to one key
@@ -1365,18 +1366,23 @@ __device__ __forceinline__ uint32_t order_key(float v) {
     return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
-// keys[s*N + r] = order_key(out[s*N + r]), idx = r; nan[s] = 1 if any NaN
+// keys[s*N + r] = order_key(out[s*N + r]); the value sorted along with it is
+// the row r, or the row's target rank rank2_y[r] where given (then the sorted
+// values are the target ranks in the program's order, with no gather);
+// nan[s] = 1 if any NaN
 __global__ __launch_bounds__(kRsBlock) void k_spear_keys(const float* __restrict__ out, int64_t N, int32_t B,
-                                                          uint32_t* __restrict__ keys, uint32_t* __restrict__ idx,
+                                                          const uint32_t* __restrict__ rank2_y,
+                                                          uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                                           int32_t* __restrict__ nan_flag) {
     const int64_t total = N * B;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * kRsBlock + threadIdx.x; i < total;
          i += static_cast<int64_t>(gridDim.x) * kRsBlock) {
         const float v = out[i];
         const int64_t seg = i / N;
+        const int64_t r = i - seg * N;
         if (isnan(v)) nan_flag[seg] = 1;
         keys[i] = order_key(v);
-        idx[i] = static_cast<uint32_t>(i - seg * N);
+        vals[i] = rank2_y ? rank2_y[r] : static_cast<uint32_t>(r);
     }
 }
 
@@ -1389,7 +1395,7 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_count(const uint32_t* __restric
     __syncthreads();
     const int64_t base = static_cast<int64_t>(seg) * N;
     const int64_t t0 = static_cast<int64_t>(tile) * kRsTile;
-    for (int k = 0; k < kRsItems; ++k) {
+    for (int k = 0; k < kRsTile / kRsBlock; ++k) {
         const int64_t i = t0 + k * kRsBlock + threadIdx.x;
         if (i < N) atomicAdd(&hist[(keys[base + i] >> shift) & 255u], 1u);
     }
@@ -1440,34 +1446,61 @@ __global__ __launch_bounds__(1024) void k_rs_scan(uint32_t* __restrict__ counts,
     }
 }
 
-// stable scatter of one tile, staged through LDS: keys are taken in index
-// order, 256 at a time; within a round, equal digits are ranked by lane (wave
-// ballots) and by wave, which places every key at its digit-sorted position
-// within the tile in LDS.  The tile then goes out run by run: consecutive
-// threads write consecutive addresses of each digit's output range.  The
-// tile's count of digit d is the difference of adjacent scanned offsets
-// (digit-major over tiles, the last one closed by N).
-__global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint32_t* __restrict__ kin,
+// stable scatter of one tile, staged through LDS.  Wavefront w takes the
+// tile's keys w*1024 ... w*1024+1023 in index order, 64 a round; within a
+// round, lanes holding the same digit find each other by ballots over the
+// digit's bits, and the wavefront's running count of that digit (its own row
+// of LDS counters, updated by the lowest such lane; a wavefront's LDS
+// operations are ordered, so no barrier is needed) gives each key its rank
+// among the wavefront's keys of that digit.  One barrier later, each digit's
+// counts are turned into exclusive prefixes over the wavefronts, which puts
+// every key at its digit-sorted position within the tile in LDS.  The tile
+// then goes out run by run: consecutive threads write consecutive addresses
+// of each digit's output range.  The tile's count of digit d is the
+// difference of adjacent scanned offsets (digit-major over tiles, the last
+// one closed by N).
+__global__ __launch_bounds__(kRsScatterBlock) void k_rs_scatter(const uint32_t* __restrict__ kin,
                                                           const uint32_t* __restrict__ vin,
                                                           uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                           int64_t N, int32_t T, int shift,
                                                           const uint32_t* __restrict__ offsets) {
+    constexpr int kWaves = kRsScatterBlock / kWave;
+    constexpr int kDigitWaves = kRsRadix / kWave;     // the wavefronts that keep one digit per thread
+    constexpr int kPerWave = kRsTile / kWaves;        // keys per wavefront (kRsItems rounds of 64)
     __shared__ uint32_t base_off[kRsRadix];           // global start of each digit for this tile
     __shared__ uint32_t loc_off[kRsRadix];            // local start of each digit within the tile
-    __shared__ uint32_t run[kRsRadix];                // keys of each digit placed so far
-    __shared__ uint32_t wcnt[kRsBlock / kWave][kRsRadix];
-    __shared__ uint32_t wsum[kRsBlock / kWave];
+    __shared__ uint32_t hist[kWaves][kRsRadix];       // per-wavefront digit counts, then their prefixes
+    __shared__ uint32_t wsum[kDigitWaves];
     __shared__ uint32_t skey[kRsTile], sval[kRsTile];
     const int32_t tile = blockIdx.x, seg = blockIdx.y;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wave = tid >> 6;
-    const int64_t cidx = (static_cast<int64_t>(seg) * kRsRadix + tid) * T + tile;
-    const int64_t nidx = static_cast<int64_t>(kRsRadix) * T;     // offsets per segment
-    const uint32_t start = offsets[cidx];
-    const int64_t cnext = (static_cast<int64_t>(tid) * T + tile + 1 < nidx) ? cidx + 1 : -1;
-    const uint32_t cnt = (cnext >= 0 ? offsets[cnext] : static_cast<uint32_t>(N)) - start;
-    base_off[tid] = start;
-    run[tid] = 0;
+    // threads below kRsRadix keep digit tid's offsets
+    const bool digit_thread = tid < kRsRadix;
+    uint32_t start = 0, cnt = 0;
+    if (digit_thread) {
+        const int64_t cidx = (static_cast<int64_t>(seg) * kRsRadix + tid) * T + tile;
+        const int64_t nidx = static_cast<int64_t>(kRsRadix) * T;     // offsets per segment
+        start = offsets[cidx];
+        const int64_t cnext = (static_cast<int64_t>(tid) * T + tile + 1 < nidx) ? cidx + 1 : -1;
+        cnt = (cnext >= 0 ? offsets[cnext] : static_cast<uint32_t>(N)) - start;
+    }
+    const int64_t sbase = static_cast<int64_t>(seg) * N;
+    const int64_t t0 = static_cast<int64_t>(tile) * kRsTile;
+    const int tile_len = static_cast<int>(min<int64_t>(kRsTile, N - t0));
+    // this wavefront's keys, all loads issued before the ranking
+    uint32_t pkey[kRsItems], pval[kRsItems];
+#pragma unroll
+    for (int k = 0; k < kRsItems; ++k) {
+        const int64_t i = t0 + wave * kPerWave + k * kWave + lane;
+        pkey[k] = i < N ? kin[sbase + i] : 0u;
+        pval[k] = i < N ? vin[sbase + i] : 0u;
+    }
+    if (digit_thread) {
+        base_off[tid] = start;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) hist[w][tid] = 0;
+    }
     // exclusive scan of the tile's digit counts (shuffles within each wave,
     // then the waves' totals)
     uint32_t v = cnt;
@@ -1475,32 +1508,20 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint32_t* __restr
         const uint32_t o = __shfl_up(v, d, kWave);
         if (lane >= d) v += o;
     }
-    if (lane == kWave - 1) wsum[wave] = v;
+    if (digit_thread && lane == kWave - 1) wsum[wave] = v;
     __syncthreads();
-    uint32_t pre = 0;
-    for (int q = 0; q < wave; ++q) pre += wsum[q];
-    loc_off[tid] = pre + v - cnt;
-    const int64_t sbase = static_cast<int64_t>(seg) * N;
-    const int64_t t0 = static_cast<int64_t>(tile) * kRsTile;
-    const int tile_len = static_cast<int>(min<int64_t>(kRsTile, N - t0));
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    // the whole tile's loads are issued before the first round
-    uint32_t pkey[kRsItems], pval[kRsItems];
-#pragma unroll
-    for (int k = 0; k < kRsItems; ++k) {
-        const int64_t i = t0 + k * kRsBlock + tid;
-        pkey[k] = i < N ? kin[sbase + i] : 0u;
-        pval[k] = i < N ? vin[sbase + i] : 0u;
+    if (digit_thread) {
+        uint32_t pre = 0;
+        for (int q = 0; q < wave; ++q) pre += wsum[q];
+        loc_off[tid] = pre + v - cnt;
     }
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t prank[kRsItems];
 #pragma unroll
     for (int k = 0; k < kRsItems; ++k) {
-        const int64_t i = t0 + k * kRsBlock + tid;
+        const int64_t i = t0 + wave * kPerWave + k * kWave + lane;
         const bool valid = i < N;
-        const uint32_t key = pkey[k];
-        const uint32_t val = pval[k];
-        const uint32_t d = (key >> shift) & 255u;
-        for (int w = 0; w < kRsBlock / kWave; ++w) wcnt[w][tid] = 0;
-        __syncthreads();
+        const uint32_t d = (pkey[k] >> shift) & 255u;
         // lanes of this wave holding a valid key with the same digit
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -1509,28 +1530,36 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const uint32_t* __restr
             peers &= ((d >> bit) & 1u) ? bal : ~bal;
         }
         const uint32_t rank_w = static_cast<uint32_t>(__popcll(peers & lt_mask));
-        if (valid && rank_w == 0) wcnt[wave][d] = static_cast<uint32_t>(__popcll(peers));
-        __syncthreads();
-        uint32_t before = 0, total = 0;
-        for (int w = 0; w < kRsBlock / kWave; ++w) {
-            const uint32_t c = wcnt[w][d];
-            before += w < wave ? c : 0u;
-            total += c;
+        const uint32_t before = hist[wave][d];
+        prank[k] = before + rank_w;
+        if (valid && rank_w == 0) hist[wave][d] = before + static_cast<uint32_t>(__popcll(peers));
+    }
+    __syncthreads();
+    if (digit_thread) {   // exclusive prefix over the wavefronts of digit tid's counts
+        uint32_t acc = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            const uint32_t c = hist[w][tid];
+            hist[w][tid] = acc;
+            acc += c;
         }
-        if (valid) {
-            const uint32_t lp = loc_off[d] + run[d] + before + rank_w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRsItems; ++k) {
+        const int64_t i = t0 + wave * kPerWave + k * kWave + lane;
+        if (i < N) {
+            const uint32_t d = (pkey[k] >> shift) & 255u;
+            const uint32_t lp = loc_off[d] + hist[wave][d] + prank[k];
             if (lp < static_cast<uint32_t>(kRsTile)) {
-                skey[lp] = key;
-                sval[lp] = val;
+                skey[lp] = pkey[k];
+                sval[lp] = pval[k];
             }
         }
-        __syncthreads();
-        // the first holder of each digit in this round advances its count
-        if (valid && rank_w == 0 && before == 0) run[d] += total;
-        __syncthreads();
     }
+    __syncthreads();
     // the tile, digit-sorted, to its digits' output ranges
-    for (int j = tid; j < tile_len; j += kRsBlock) {
+    for (int j = tid; j < tile_len; j += kRsScatterBlock) {
         const uint32_t key = skey[j];
         const uint32_t d = (key >> shift) & 255u;
         const uint32_t pos = base_off[d] + (static_cast<uint32_t>(j) - loc_off[d]);
@@ -1641,10 +1670,12 @@ __global__ __launch_bounds__(1024) void k_spear_rank_target(const uint32_t* __re
 // the carry of the earlier blocks).  With a = rank - (N+1)/2 for the program
 // and b likewise for the target, the weighted sums of a, a^2 and a b and the
 // target's shared sums (tsum) give |r|: 0 for a constant rank vector, NaN if
-// the outputs held a NaN.  Two blocks' loads go out together.
+// the outputs held a NaN.  Two blocks' loads go out together.  Unweighted,
+// the sorted values are the target ranks themselves; weighted, they are rows,
+// whose target ranks and weights are gathered.
 template <bool WEIGHTED>
 __global__ __launch_bounds__(1024) void k_spear_corr(const uint32_t* __restrict__ keys,
-                                                      const uint32_t* __restrict__ idx, int64_t N,
+                                                      const uint32_t* __restrict__ vals, int64_t N,
                                                       const uint32_t* __restrict__ rank2_y,
                                                       const float* __restrict__ w,
                                                       const double* __restrict__ tsum,
@@ -1659,7 +1690,7 @@ __global__ __launch_bounds__(1024) void k_spear_corr(const uint32_t* __restrict_
     const int lane = tid & (kWave - 1), wid = tid >> 6;
     const uint32_t n = static_cast<uint32_t>(N);      // below 2^31
     const uint32_t* k = keys + static_cast<int64_t>(seg) * N;
-    const uint32_t* ix = idx + static_cast<int64_t>(seg) * N;
+    const uint32_t* ix = vals + static_cast<int64_t>(seg) * N;
     const double mid = 0.5 * (static_cast<double>(N) + 1.0);
     double s_a = 0.0, s_aa = 0.0, s_ab = 0.0;
     double o_w = 0.0, o_wb = 0.0;     // this thread's rows of the open run
@@ -1678,8 +1709,12 @@ __global__ __launch_bounds__(1024) void k_spear_corr(const uint32_t* __restrict_
         for (int e = 0; e < kE; ++e) {
             const uint32_t i = c0 + e * 1024 + tid;
             const uint32_t row = ry[e];
-            ry[e] = i < n ? rank2_y[row] : 0u;
-            wf[e] = (WEIGHTED && i < n) ? w[row] : 1.0f;
+            if constexpr (WEIGHTED) {
+                ry[e] = i < n ? rank2_y[row] : 0u;
+                wf[e] = i < n ? w[row] : 1.0f;
+            } else {
+                wf[e] = 1.0f;
+            }
         }
 #pragma unroll
         for (int e = 0; e < kE; ++e) {
@@ -2201,7 +2236,7 @@ gp_status radix_sort_segments(DeviceScratch* sc, int64_t N, int32_t B, hipStream
         GP_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_rs_scan, dim3(B), dim3(1024), 0, st, sc->sp_cnt, T);
         GP_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_rs_scatter, dim3(T, B), dim3(kRsBlock), 0, st, kin, vin, kout, vout, N, T, shift,
+        hipLaunchKernelGGL(k_rs_scatter, dim3(T, B), dim3(kRsScatterBlock), 0, st, kin, vin, kout, vout, N, T, shift,
                            sc->sp_cnt);
         GP_HIP(hipGetLastError());
         std::swap(kin, kout);
@@ -2267,7 +2302,7 @@ gp_status spearman_impl(DeviceScratch* sc, const gp_population_dev* pop, const g
     if ((rc = fill_nan_flags(1)) != GP_OK) return rc;
     hipLaunchKernelGGL(k_spear_keys, dim3(static_cast<unsigned>(std::min<int64_t>((N + kRsBlock - 1) / kRsBlock,
                                                                                   int64_t{1} << 16))),
-                       dim3(kRsBlock), 0, st, data->y, N, 1, sc->sp_k0, sc->sp_v0, sc->sp_nan);
+                       dim3(kRsBlock), 0, st, data->y, N, 1, nullptr, sc->sp_k0, sc->sp_v0, sc->sp_nan);
     GP_HIP(hipGetLastError());
     if ((rc = radix_sort_segments(sc, N, 1, st)) != GP_OK) return rc;
     hipLaunchKernelGGL(k_spear_rank_target, dim3(1), dim3(1024), 0, st, sc->sp_k0, sc->sp_v0, N, data->w,
@@ -2290,8 +2325,8 @@ gp_status spearman_impl(DeviceScratch* sc, const gp_population_dev* pop, const g
         rc = launch_eval(0, GP_METRIC_MSE, cfg, sc->n_cu, pv, cvw, dv, sch, sc->sp_out, nullptr, st, 0, Timing{});
         if (rc != GP_OK) return rc;
         if ((rc = fill_nan_flags(b)) != GP_OK) return rc;
-        hipLaunchKernelGGL(k_spear_keys, dim3(key_blocks), dim3(kRsBlock), 0, st, sc->sp_out, N, b, sc->sp_k0,
-                           sc->sp_v0, sc->sp_nan);
+        hipLaunchKernelGGL(k_spear_keys, dim3(key_blocks), dim3(kRsBlock), 0, st, sc->sp_out, N, b,
+                           data->w ? nullptr : sc->sp_r2y, sc->sp_k0, sc->sp_v0, sc->sp_nan);
         GP_HIP(hipGetLastError());
         if ((rc = radix_sort_segments(sc, N, b, st)) != GP_OK) return rc;
         if (data->w)
