@@ -33,6 +33,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_VALU = 157.3e12     # MI355X dense FP32 vector, FLOP/s (packed FMA = 4 flops/lane/clk)
+ISSUE_RATE = 39.3e12          # VALU lane-instruction slots per second: 256 CUs x 64 lanes x 2.4 GHz
+# Op-mix ceiling: a fixed cost per node-row in VALU lane-instruction slots,
+# fixed before it was compared with any measurement.  Terminals are free
+# (folded into operand fetch); a packed two-row FP32 operation counts 0.5; a
+# quarter-rate transcendental instruction (rcp, sqrt, log, exp, sin, cos)
+# counts 4, plus 1 for its argument scaling or predicate; IEEE division and
+# square root take their shortest correctly rounded sequences.  Opcodes:
+# VAR CONST ADD SUB MUL DIV NEG LOG SQRT SIN COS TAN MAX MIN ATAN2 ABS EXP INV
+# SQ CUBE TANH ATAN CBRT.
+OP_COST = (0.0, 0.0, 0.5, 0.5, 0.5, 10.0, 0.5, 5.0, 8.0, 5.0, 5.0, 14.0, 1.0, 1.0, 20.0, 0.5, 5.0, 10.0,
+           0.5, 1.0, 10.0, 12.0, 10.0)
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2110_11226_amd", "csrc", "gp_device.hip")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_eval_pagie-16M_traffic.md")
 
@@ -97,6 +108,74 @@ def cpu_baseline(host, X, y, metric, budget_rows):
                       f"float32 path, {dt:.1f} s on {cores} threads"}
 
 
+def op_mix(host, gops):
+    """The population's op-mix ceiling (ISSUE_RATE / mean cost per node-row
+    from OP_COST) and the fraction of it that `gops` reaches."""
+    ops = np.asarray(host.nodes, np.uint32) & 0xFF
+    hist = np.bincount(ops, minlength=len(OP_COST))
+    per = float((hist[:len(OP_COST)] * np.asarray(OP_COST)).sum() / hist.sum())
+    ceiling = ISSUE_RATE / per
+    return {"lane_slots_per_node_row": per, "ceiling": ceiling, "unit": "GPops/s", "frac": gops / ceiling}
+
+
+CONFIGS = [
+    dict(name="C1 pagie-4K", rows=4096, programs=256, features=2, metric="mse", data="pagie", data_seed=11227,
+         pop=dict(method="rhh", min_depth=2, max_depth=6, seed=2111), runs=20),
+    dict(name="C2 pagie-1M", rows=1_048_576, programs=1000, features=2, metric="mse", data="pagie",
+         data_seed=11228, pop=dict(method="rhh", min_depth=2, max_depth=8, seed=2112), runs=20),
+    dict(name="C3 pagie-16M", rows=16_777_216, programs=4096, features=2, metric="mse", data="pagie",
+         data_seed=11229, pop=dict(method="exact_len", min_len=1, max_len=200, seed=2113), runs=5),
+    dict(name="C4 higgs-11M", rows=11_000_000, programs=2000, features=28, metric="logloss", data="higgs",
+         data_seed=11230, pop=dict(method="exact_len", min_len=1, max_len=200, seed=2114), runs=5),
+    dict(name="C5 diff-1M", rows=1_048_576, programs=2048, features=8, metric="mse", data="diff",
+         data_seed=11231, pop=dict(method="exact_len", min_len=1, max_len=200, max_consts=16, seed=2115),
+         runs=20),
+]
+
+
+def config_table(gp, torch, oracle_rows=65_536):
+    """gp_fitness throughput on each workload configuration: autotuned, 3
+    warm-up calls, then the median of `runs` event-timed calls; the literal
+    and op-mix fractions; the oracle on every program over an evenly spaced
+    row sample (all rows when there are fewer)."""
+    import synth
+    out = []
+    for c in CONFIGS:
+        gen = {"pagie": synth.pagie, "higgs": synth.higgs_like, "diff": synth.diff_target}[c["data"]]
+        X, y = gen(c["rows"], seed=c["data_seed"])
+        host = gp.build_population(c["programs"], c["features"], **c["pop"])
+        sum_len = int(host.length.astype(np.int64).sum())
+        pop = gp.DevicePopulation(host, n_features=c["features"])
+        data = gp.DeviceDataset(X, y)
+        fit = torch.empty(host.n_programs, dtype=torch.float32, device="cuda")
+        cfg, _ = gp.autotune(pop, data, c["metric"], repeats=2)
+        s = torch.cuda.current_stream()
+        ms = []
+        for i in range(3 + c["runs"]):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            gp.fitness(pop, data, c["metric"], out=fit)
+            b.record(s)
+            b.synchronize()
+            if i >= 3:
+                ms.append(a.elapsed_time(b))
+        t = float(np.median(ms))
+        gops = sum_len * c["rows"] / (t / 1e3)
+        row = {"config": c["name"], "rows": c["rows"], "programs": c["programs"], "features": c["features"],
+               "metric": c["metric"], "population": c["pop"], "sum_len": sum_len, "launch": list(cfg),
+               "fitness_ms_median": t, "runs": c["runs"], "gpops": gops, "frac_157T": gops / PEAK_FP32_VALU,
+               "op_mix": op_mix(host, gops)}
+        if c["data"] == "diff":
+            row["adjoint"] = adjoint_ratio(gp, torch)
+        log(f"[bench] {c['name']}: {t:.3f} ms, {gops:.3g} GPops/s ({100 * gops / PEAK_FP32_VALU:.2f}% of 157.3 T, "
+            f"{100 * row['op_mix']['frac']:.1f}% of the op-mix ceiling)")
+        row["oracle"] = cpu_baseline(host, X, y, c["metric"], min(oracle_rows, c["rows"]))
+        log(f"[bench] {c['name']} oracle: {row['oracle']['value']:.3g} GPops/s on {row['oracle']['cores']} threads")
+        out.append(row)
+        del pop, data, fit, X, y
+    return out
+
+
 def arith_only(gp, data, wl, steps):
     """The same rows with a population over add, sub and mul only (lengths
     1-200, same seed): the function set where every node is one vector
@@ -119,7 +198,7 @@ def arith_only(gp, data, wl, steps):
     gops = sum_len * wl["rows"] / (k / 1e3)
     return {"population": "exact_len 1-200 over {add, sub, mul}, seed 2113", "sum_len": sum_len,
             "kernel_avg_ms": k, "value": gops, "unit": "GPops/s", "frac": gops / PEAK_FP32_VALU,
-            "launch": list(launch)}
+            "op_mix": op_mix(host, gops), "launch": list(launch)}
 
 
 def loop_generation_time(gp, torch, n_gen=10):
@@ -178,7 +257,8 @@ def spearman_time(gp, torch, reps=3):
 
 def adjoint_ratio(gp, torch, reps=5):
     """gp_fitness_backward time / gp_fitness time on the differentiation
-    workload (medians of `reps` event-timed calls each)."""
+    workload (medians of `reps` event-timed calls each), the forward under
+    the autotuner's launch configuration for this shape."""
     import synth
     X, y = synth.diff_target(DIFF["rows"], seed=DIFF["data_seed"])
     host = gp.build_population(DIFF["programs"], DIFF["features"], **DIFF["pop"])
@@ -199,11 +279,13 @@ def adjoint_ratio(gp, torch, reps=5):
             out.append(a.elapsed_time(b))
         return float(np.median(out[1:]))
 
+    cfg, _ = gp.autotune(pop, data, "mse", repeats=2)
     fwd = timed(lambda: gp.fitness(pop, data, "mse", out=fit))
     bwd = timed(lambda: gp.fitness_backward(pop, data, "mse", grad_out=grad))
     return {"workload": f"diff-1M: {DIFF['rows']} rows x {DIFF['features']} features, {DIFF['programs']} "
                         f"programs of 1-200 nodes with <= 16 constants, MSE",
-            "forward_ms": fwd, "backward_ms": bwd, "ratio": bwd / fwd, "target": 3.0}
+            "forward_ms": fwd, "forward_launch": list(cfg), "backward_ms": bwd, "ratio": bwd / fwd,
+            "target": 3.0}
 
 
 def main():
@@ -220,6 +302,8 @@ def main():
     ap.add_argument("--no-spearman", action="store_true", help="skip the Spearman fitness timing")
     ap.add_argument("--only-spearman", action="store_true",
                     help="time only the Spearman fitness (for a kernel trace of it)")
+    ap.add_argument("--configs", action="store_true",
+                    help="instead of the step, measure gp_fitness on every workload configuration")
     ap.add_argument("--cpu-rows", type=int, default=196_608)
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache (JSON lines): loaded if present, written after tuning")
@@ -246,6 +330,9 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {args.copy_calibration_mib} MiB done")
         del src, dst
+    if args.configs:
+        print(json.dumps({"configs": config_table(gp, torch)}), flush=True)
+        return 0
     if args.only_spearman:
         spear = spearman_time(gp, torch)
         log(f"[bench] Spearman {spear['spearman_ms']:.1f} ms vs MSE {spear['mse_ms']:.1f} ms")
@@ -354,6 +441,7 @@ def main():
                      "kernel": "k_eval (persistent fused evaluation + MSE row loss + wave reduction)",
                      "kernel_avg_ms": kern_avg_ms, "kernel_timed_by": tm["timed_by"],
                      "ops_per_launch": ops_launch, "op": "one program node evaluated on one row"},
+        "op_mix": op_mix(host, achieved),
         "arith_only": arith,
         "generation_loop": loop,
         "spearman": spear,

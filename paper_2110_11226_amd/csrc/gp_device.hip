@@ -98,10 +98,17 @@ struct Sched {
 //             the instruction (4 bits each from the lowest: unary function
 //             index + 1; 0 ends the chain), so that a unary function costs no
 //             dispatch of its own
+//   w         (active instructions, for the adjoint's reverse walk) bits
+//             0..25: index + 1 of the next active instruction the walk
+//             visits (0: none); bits 26..31: the subtrees without a constant
+//             it skips before that one
 // ---------------------------------------------------------------------------
 enum : uint32_t { kPush = 0, kFold = 1, kBin = 2, kUn = 3 };
 constexpr uint32_t kConstBit = 64u;
 constexpr uint32_t kActive = 128u;
+constexpr uint32_t kNextBits = 26u;
+constexpr uint32_t kNextMask = (1u << kNextBits) - 1u;
+constexpr int64_t kMaxAdjointLen = int64_t{1} << 25;   // program length the reverse links can address
 
 GP_HD uint32_t enc(uint32_t cls, uint32_t fn, uint32_t is_const, uint32_t arg) {
     return cls | (fn << 2) | (is_const << 6) | (arg << 8);
@@ -412,6 +419,26 @@ __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint4* __restri
     }
     if (chain >= 0) out[k - 1] = pend;
     clen[p] = k;
+    // the adjoint's reverse walk, from the last instruction down: an inactive
+    // instruction stands for its whole subtree (skipped, one stack entry);
+    // each active one is linked to the next active one and counts the skips
+    // between them.  (Indices stay below 2^26 for programs the adjoint accepts;
+    // skips never exceed the stack depth, below 2^6.)
+    int32_t last = -1;
+    uint32_t skips = 0u;
+    for (int32_t q = k - 1; q >= 0;) {
+        const uint4 ins = out[q];
+        if (!(ins.x & kActive)) {
+            ++skips;
+            q = min(static_cast<int32_t>(ins.y), q) - 1;   // (the clamp only guards a malformed program)
+            continue;
+        }
+        if (last >= 0) out[last].w = (static_cast<uint32_t>(q + 1) & kNextMask) | (min(skips, 63u) << kNextBits);
+        last = q;
+        skips = 0u;
+        --q;
+    }
+    if (last >= 0) out[last].w = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -1135,29 +1162,15 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
             // ---------------- reverse pass ----------------
             GP_ARRAYS(as, kStackRegs + 1);   // adjoints of the entries below the top
             int ad = dp;                     // mirrors the value stack (dp == 0 here)
-            int q = CL - 1;
-            uint4 prv = pcode[q];
-            for (; q >= 0; --q) {
-                const uint4 cur = prv;
-                prv = pcode[max(q - 1, 0)];
+            // the walk visits the active instructions through their links (the
+            // root, the last instruction, is active: the program holds a
+            // constant); the next one is fetched while this one runs
+            uint4 cur = pcode[CL - 1];
+            for (;;) {
+                const uint32_t link = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(cur.w)));
+                const int qn = static_cast<int>(link & kNextMask) - 1;
+                const uint4 nxt_ins = pcode[max(qn, 0)];
                 const uint32_t w = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(cur.x)));
-                if (!(w & kActive)) {
-                    // no constant below: the whole subtree carries nothing back
-                    // and, as one value on the stack, is undone like a push
-                    const int start = __builtin_amdgcn_readfirstlane(static_cast<int>(cur.y));
-                    q = start;
-                    prv = pcode[max(start - 1, 0)];
-                    if (ad >= 0) {
-                        if (ad < kStackRegs) {
-                            GP_GET(as, ad, g);
-                        } else {
-#pragma unroll
-                            for (int j = 0; j < R; ++j) g[j] = aovf[((ad - kStackRegs) * R + j) * kWave + lane];
-                        }
-                    }
-                    --ad;
-                    continue;
-                }
                 const uint32_t cls = w & 3u;
                 const uint32_t fn = (w >> 2) & 15u;
                 // the chained unary functions first, the last one first
@@ -1250,18 +1263,24 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                         else atomicAdd(gextra + cbase + slot, tot);
                     }
                 }
-                // a push is undone: the entry below becomes the top again
-                if (cls == kPush) {
-                    if (ad >= 0) {
-                        if (ad < kStackRegs) {
-                            GP_GET(as, ad, g);
+                // a push is undone, and so is each skipped subtree (one value on
+                // the stack, carrying nothing back): the entry below becomes
+                // the top again
+                const int undo = (cls == kPush ? 1 : 0) + static_cast<int>(link >> kNextBits);
+                if (undo > 0) {
+                    ad -= undo;
+                    const int top = ad + 1;
+                    if (top >= 0) {
+                        if (top < kStackRegs) {
+                            GP_GET(as, top, g);
                         } else {
 #pragma unroll
-                            for (int j = 0; j < R; ++j) g[j] = aovf[((ad - kStackRegs) * R + j) * kWave + lane];
+                            for (int j = 0; j < R; ++j) g[j] = aovf[((top - kStackRegs) * R + j) * kWave + lane];
                         }
                     }
-                    --ad;
                 }
+                if (qn < 0) break;
+                cur = nxt_ins;
             }
         }
         // ---------------- per-item results ----------------
@@ -2019,7 +2038,9 @@ LaunchCfg heuristic_cfg(int F, int64_t N, int32_t P, int n_cu) {
     LaunchCfg c;
     c.R = 4;
     c.wpb = 4;
-    c.freg = F <= 2 ? 2 : (F <= 8 ? 8 : 0);
+    // features in registers only for F <= 2: eight of them cost a wavefront of
+    // occupancy at 4 rows per lane, which measures slower than reading them
+    c.freg = F <= 2 ? 2 : 0;
     const int64_t tile_rows = static_cast<int64_t>(kWave) * c.R;
     const int64_t n_tiles = (N + tile_rows - 1) / tile_rows;
     // aim for >= 32 work items per resident wavefront, chunks of <= 64 tiles
@@ -3426,6 +3447,8 @@ gp_status gp_fitness_backward(const gp_population_dev* pop, const gp_dataset_dev
         return fail(GP_ERR_INVALID_ARG, "gp_fitness_backward: grad_consts and consts are needed");
     if (pop->max_len < 1)
         return fail(GP_ERR_INVALID_ARG, "gp_fitness_backward: max_len must bound the program lengths");
+    if (pop->max_len > kMaxAdjointLen)
+        return fail(GP_ERR_INVALID_ARG, "gp_fitness_backward: programs longer than 2^25 nodes are not supported");
     hipStream_t st = static_cast<hipStream_t>(stream);
     DeviceScratch* sc;
     rc = arena(&sc);
