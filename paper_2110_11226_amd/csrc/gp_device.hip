@@ -3463,8 +3463,9 @@ gp_status gp_fitness_backward(const gp_population_dev* pop, const gp_dataset_dev
     if (rc != GP_OK) return rc;
     const int32_t P = pop->n_programs;
     const int64_t nc = std::max<int64_t>(pop->total_consts, 1);
-    // rows per lane of the adjoint: a forced configuration's, else 2
-    const int RA = g_forced ? g_forced_cfg.R : 2;
+    // rows per lane of the adjoint: a forced configuration's, else the one
+    // (2 or 4) that keeps more rows in flight per CU (below)
+    const int RA = g_forced ? g_forced_cfg.R : 0;
     const int64_t tape_max = 2 * static_cast<int64_t>(pop->max_len) + 2;   // tape entries per wavefront
     rc = grow(reinterpret_cast<void**>(&sc->stats), &sc->stats_cap, static_cast<size_t>(P) * kStats + 1,
               sizeof(double));
@@ -3540,7 +3541,12 @@ gp_status gp_fitness_backward(const gp_population_dev* pop, const gp_dataset_dev
     (freg == 2   ? GP_ADJ_PICK(RR, 2, M)                                                       \
      : freg == 8 ? GP_ADJ_PICK(RR, 8, M)                                                       \
                  : go(k_adjoint<RR, 0, M>, adjoint_wave_floats<RR>(tape_max)))
-#define GP_ADJ(M) (RA == 1 ? GP_ADJ_R(1, M) : RA == 2 ? GP_ADJ_R(2, M) : GP_ADJ_R(4, M))
+#define GP_ADJ_AUTO(M)                                                                         \
+    (4 * occ(reinterpret_cast<const void*>(k_adjoint<4, 0, M>)) >                              \
+             2 * occ(reinterpret_cast<const void*>(k_adjoint<2, 0, M>))                        \
+         ? GP_ADJ_R(4, M)                                                                      \
+         : GP_ADJ_R(2, M))
+#define GP_ADJ(M) (RA == 0 ? GP_ADJ_AUTO(M) : RA == 1 ? GP_ADJ_R(1, M) : RA == 2 ? GP_ADJ_R(2, M) : GP_ADJ_R(4, M))
     switch (metric) {
     case GP_METRIC_MAE: rc = GP_ADJ(GP_METRIC_MAE); break;
     case GP_METRIC_MSE: rc = GP_ADJ(GP_METRIC_MSE); break;
@@ -3549,6 +3555,7 @@ gp_status gp_fitness_backward(const gp_population_dev* pop, const gp_dataset_dev
     default: rc = GP_ADJ(GP_METRIC_PEARSON); break;
     }
 #undef GP_ADJ
+#undef GP_ADJ_AUTO
 #undef GP_ADJ_R
 #undef GP_ADJ_PICK
     if (rc != GP_OK) return rc;

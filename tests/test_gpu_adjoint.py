@@ -159,6 +159,28 @@ def test_matches_float64_reverse_mode(gp, metric, weighted):
     assert np.allclose(fit_out[fin], fwd[fin], rtol=1e-6, atol=0)
 
 
+@pytest.mark.parametrize("cfg", [(1, 0, 3), (2, 0, 2), (2, 8, 1), (4, 0, 5), (4, 2, 1)])
+def test_forced_rows_per_lane(gp, cfg):
+    """Each rows-per-lane variant of the adjoint (the automatic choice takes
+    2 or 4 by occupancy), with features from memory and from registers, and
+    row chunks that do not divide the rows evenly."""
+    N = 20_000 + 3
+    X, y = synth.diff_target(N, seed=15)
+    F = 2 if cfg[1] == 2 else 8
+    X = np.ascontiguousarray(X[:F])
+    host = gp.build_population(192, F, "rhh", min_depth=2, max_depth=6, max_consts=16, seed=2117)
+    gp.set_launch_config(cfg)
+    try:
+        g, fit_out, fwd = run_backward(gp, host, X, y, None, "mse", F)
+    finally:
+        gp.set_launch_config(None)
+    ref, spread, cond = oracle_reference(to_oracle(host), X, y, None, "mse")
+    checked, ill = check_grads(host, g, ref, spread, cond, f"forced {cfg}")
+    assert checked >= 40
+    fin = np.isfinite(fwd)
+    assert np.allclose(fit_out[fin], fwd[fin], rtol=1e-6, atol=0)
+
+
 def test_long_programs_float64_reverse_mode(gp):
     """Programs of 1-200 nodes over the nine-function set (the shape of the
     differentiation workload): many are chaotic in float32; the
