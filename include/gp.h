@@ -113,7 +113,15 @@ void gp_shutdown(void);
 /*            with y in {0,1}, weighted mean (smaller is better)       */
 /*   PEARSON: |weighted correlation of yh and y|, 0 when a variance is */
 /*            zero or not finite (larger is better)                    */
-/*   SPEARMAN: not provided by this version (GP_ERR_UNSUPPORTED).      */
+/*   SPEARMAN: |weighted correlation of the ranks of yh and of y|:     */
+/*            rank 1 the smallest, tied values the mean of their       */
+/*            ranks, ranks unweighted, the weights in the correlation; */
+/*            0 for a constant rank vector, NaN if any yh is NaN       */
+/*            (larger is better).  gp_fitness, the generation graphs   */
+/*            and the evolution loop compute it (batched sort on the   */
+/*            device, n_rows below 2^31); gp_fitness_backward,         */
+/*            gp_autotune and gp_get_launch_config give                */
+/*            GP_ERR_UNSUPPORTED (ranks have no derivative).           */
 /* Row losses of MAE/MSE/RMSE/PEARSON are formed in float64 from the   */
 /* float32 program value; LOGLOSS's in float32; all row sums in        */
 /* float64; the result is rounded to float32.                          */

@@ -1982,7 +1982,8 @@ gp_status check_fitness_metric(int metric, const char* who, bool spearman_ok = f
     if (gp_metric_larger_is_better(static_cast<gp_metric>(metric)) < 0)
         return fail(GP_ERR_INVALID_ARG, std::string(who) + ": unknown metric");
     if (metric == GP_METRIC_SPEARMAN && !spearman_ok)
-        return fail(GP_ERR_UNSUPPORTED, std::string(who) + ": Spearman is available through gp_fitness only");
+        return fail(GP_ERR_UNSUPPORTED, std::string(who) + ": Spearman has no derivative or launch configuration "
+                                                            "(gp_fitness, generations and evolution compute it)");
     return GP_OK;
 }
 
