@@ -98,10 +98,10 @@ struct Sched {
 //             the instruction (4 bits each from the lowest: unary function
 //             index + 1; 0 ends the chain), so that a unary function costs no
 //             dispatch of its own
-//   w         (active instructions, for the adjoint's reverse walk) bits
-//             0..25: index + 1 of the next active instruction the walk
-//             visits (0: none); bits 26..31: the subtrees without a constant
-//             it skips before that one
+//   w         (active instructions, in the adjoint's compile only) bits
+//             0..25: index + 1 of the next active instruction its reverse
+//             walk visits (0: none); bits 26..31: the subtrees without a
+//             constant it skips before that one
 // ---------------------------------------------------------------------------
 enum : uint32_t { kPush = 0, kFold = 1, kBin = 2, kUn = 3 };
 constexpr uint32_t kConstBit = 64u;
@@ -419,11 +419,13 @@ __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint4* __restri
     }
     if (chain >= 0) out[k - 1] = pend;
     clen[p] = k;
-    // the adjoint's reverse walk, from the last instruction down: an inactive
-    // instruction stands for its whole subtree (skipped, one stack entry);
-    // each active one is linked to the next active one and counts the skips
-    // between them.  (Indices stay below 2^26 for programs the adjoint accepts;
-    // skips never exceed the stack depth, below 2^6.)
+    // the adjoint's reverse walk (its compile is the one without folding),
+    // from the last instruction down: an inactive instruction stands for its
+    // whole subtree (skipped, one stack entry); each active one is linked to
+    // the next active one and counts the skips between them.  (Indices stay
+    // below 2^26 for programs the adjoint accepts; skips never exceed the
+    // stack depth, below 2^6.)
+    if (fold) return;
     int32_t last = -1;
     uint32_t skips = 0u;
     for (int32_t q = k - 1; q >= 0;) {
