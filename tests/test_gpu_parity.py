@@ -203,6 +203,21 @@ def test_fitness_rhh_pagie_small_config(gp):
     assert n_ill <= 5
 
 
+def test_full_size_pagie_1m_rhh_all_programs(gp):
+    """The 1,048,576-row Pagie configuration with 1,000 ramped half-and-half
+    programs (depth 2-8) at the automatic launch configuration: every
+    program's fitness over every row against the oracle.  Over a million
+    rows, about a sixth of the programs meet a protected predicate near its
+    threshold on some row and are excluded."""
+    N = 1_048_576
+    X, y = synth.pagie(N, seed=11228)
+    host = gp.build_population(1000, 2, "rhh", min_depth=2, max_depth=8, seed=2112)
+    got, *ref = _fitness_case(gp, host, X, y, None, "mse", 2)
+    n_ok, n_ill, e64 = check_fitness(got, *ref, "pagie-1M")
+    print(f"pagie-1M: {n_ok} programs checked, {n_ill} excluded, max rel err vs f64 {e64:.2e}")
+    assert n_ok >= 750
+
+
 def test_fitness_edge_cases(gp):
     # single row, single program, constant programs, zero weights on half
     progs = [([oracle.node(oracle.CONST, 0)], [0.5]), ([oracle.node(oracle.VAR, 0)], []),
