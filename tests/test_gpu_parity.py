@@ -290,7 +290,7 @@ def test_tournament_on_gpu_fitness(gp):
 
 def well_conditioned_sample(host, X, y, metric, rng, k):
     """k programs, half the longest well-conditioned candidates and half at
-    random among well-conditioned ones, judged by the oracle's fitness bound on
+    random among well-conditioned ones, decided by the oracle's fitness bound on
     an evenly spaced 32768-row subsample."""
     cand = np.unique(np.concatenate([np.argsort(-host.length, kind="stable")[:48],
                                      rng.integers(0, host.n_programs, 48)]))
