@@ -417,9 +417,9 @@ gp_status gp_get_launch_config(int32_t n_features, int64_t n_rows, int32_t n_pro
 gp_status gp_set_launch_config(const gp_launch_config* cfg);
 
 /* Limit on the device memory that Spearman fitness (Sec. III-C3: ranks from
- * a sort) uses for its batches of programs: 20 bytes per row per program
- * (outputs; sort keys and row indices, double-buffered), plus the sort's
- * per-tile counts.  0 (the default) means 16 GiB and at most half the free
+ * a sort) uses for its batches of programs: 16 bytes per row per program
+ * (sort keys and the values they carry, double-buffered; the program
+ * outputs share the first key buffer), plus the sort's per-tile counts.  0 (the default) means 16 GiB and at most half the free
  * memory.  A batch holds at least one program whatever the limit.  Applies
  * to every later gp_fitness call and captured generation in this process;
  * results do not depend on it.  A negative value gives GP_ERR_INVALID_ARG. */

@@ -195,7 +195,7 @@ def set_launch_config(cfg=None):
 
 
 def set_spearman_workset(max_bytes=0):
-    """Device memory Spearman fitness may use for a batch of programs (20
+    """Device memory Spearman fitness may use for a batch of programs (16
     bytes per row per program); 0 returns to the default (16 GiB, at most half
     the free memory)."""
     _check(_set_spear_ws(int(max_bytes)), "gp_set_spearman_workset")

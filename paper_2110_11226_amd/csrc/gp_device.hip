@@ -1368,14 +1368,15 @@ __global__ __launch_bounds__(kBlock) void k_tournament(const float* __restrict__
 
 // ---------------------------------------------------------------------------
 // Spearman (Sec. III-C3 ranks each program's outputs with a sort): the outputs
-// of a batch of programs are turned into order-preserving 32-bit keys, each
-// program's N keys are sorted with their row indices by a segmented LSD radix
-// sort (four passes of 8 bits: per-tile digit counts, a per-segment scan,
-// a stable scatter), and one workgroup per program walks its sorted keys,
-// giving tied values the mean of their ranks, and forms the float64 moments
-// of the (value rank, target rank) pairs.
+// of a batch of programs become order-preserving 32-bit keys in the first
+// pass of a segmented LSD radix sort (four passes of 8 bits: per-tile digit
+// counts, a per-segment scan, a stable scatter), each carrying its row's
+// target rank (or its row, with weights) through the sort, and one workgroup
+// per program walks its sorted keys, giving tied values the mean of their
+// ranks, and forms the float64 moments of the (value rank, target rank)
+// pairs.
 // ---------------------------------------------------------------------------
-constexpr int kRsBlock = 256;                  // threads of the key and count kernels
+constexpr int kRsBlock = 256;                  // threads of the count kernel
 constexpr int kRsScatterBlock = 512;           // threads of the scatter
 constexpr int kRsItems = 16;                   // keys per scatter thread
 constexpr int kRsTile = kRsScatterBlock * kRsItems;   // keys per tile
@@ -1387,29 +1388,13 @@ __device__ __forceinline__ uint32_t order_key(float v) {
     return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
-// keys[s*N + r] = order_key(out[s*N + r]); the value sorted along with it is
-// the row r, or the row's target rank rank2_y[r] where given (then the sorted
-// values are the target ranks in the program's order, with no gather);
-// nan[s] = 1 if any NaN
-__global__ __launch_bounds__(kRsBlock) void k_spear_keys(const float* __restrict__ out, int64_t N, int32_t B,
-                                                          const uint32_t* __restrict__ rank2_y,
-                                                          uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                          int32_t* __restrict__ nan_flag) {
-    const int64_t total = N * B;
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kRsBlock + threadIdx.x; i < total;
-         i += static_cast<int64_t>(gridDim.x) * kRsBlock) {
-        const float v = out[i];
-        const int64_t seg = i / N;
-        const int64_t r = i - seg * N;
-        if (isnan(v)) nan_flag[seg] = 1;
-        keys[i] = order_key(v);
-        vals[i] = rank2_y ? rank2_y[r] : static_cast<uint32_t>(r);
-    }
-}
-
-// counts[(seg * 256 + digit) * T + tile] for one pass
+// counts[(seg * 256 + digit) * T + tile] for one pass.  The first pass reads
+// the float values themselves (their order-preserving keys are formed here)
+// and raises nan[seg] for a NaN.
+template <bool FIRST>
 __global__ __launch_bounds__(kRsBlock) void k_rs_count(const uint32_t* __restrict__ keys, int64_t N, int32_t T,
-                                                        int shift, uint32_t* __restrict__ counts) {
+                                                        int shift, uint32_t* __restrict__ counts,
+                                                        int32_t* __restrict__ nan_flag) {
     __shared__ uint32_t hist[kRsRadix];
     const int32_t tile = blockIdx.x, seg = blockIdx.y;
     hist[threadIdx.x] = 0;
@@ -1418,7 +1403,15 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_count(const uint32_t* __restric
     const int64_t t0 = static_cast<int64_t>(tile) * kRsTile;
     for (int k = 0; k < kRsTile / kRsBlock; ++k) {
         const int64_t i = t0 + k * kRsBlock + threadIdx.x;
-        if (i < N) atomicAdd(&hist[(keys[base + i] >> shift) & 255u], 1u);
+        if (i < N) {
+            uint32_t key = keys[base + i];
+            if constexpr (FIRST) {
+                const float v = __uint_as_float(key);
+                if (isnan(v)) nan_flag[seg] = 1;
+                key = order_key(v);
+            }
+            atomicAdd(&hist[(key >> shift) & 255u], 1u);
+        }
     }
     __syncthreads();
     counts[(static_cast<int64_t>(seg) * kRsRadix + threadIdx.x) * T + tile] = hist[threadIdx.x];
@@ -1479,12 +1472,17 @@ __global__ __launch_bounds__(1024) void k_rs_scan(uint32_t* __restrict__ counts,
 // then goes out run by run: consecutive threads write consecutive addresses
 // of each digit's output range.  The tile's count of digit d is the
 // difference of adjacent scanned offsets (digit-major over tiles, the last
-// one closed by N).
+// one closed by N).  The first pass reads the float values, forms their
+// keys, and gives each the value it carries through the sort: its row's
+// target rank where rank2_y is given (then the sorted values are the target
+// ranks in the program's order), else its row.
+template <bool FIRST>
 __global__ __launch_bounds__(kRsScatterBlock) void k_rs_scatter(const uint32_t* __restrict__ kin,
                                                           const uint32_t* __restrict__ vin,
                                                           uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                           int64_t N, int32_t T, int shift,
-                                                          const uint32_t* __restrict__ offsets) {
+                                                          const uint32_t* __restrict__ offsets,
+                                                          const uint32_t* __restrict__ rank2_y) {
     constexpr int kWaves = kRsScatterBlock / kWave;
     constexpr int kDigitWaves = kRsRadix / kWave;     // the wavefronts that keep one digit per thread
     constexpr int kPerWave = kRsTile / kWaves;        // keys per wavefront (kRsItems rounds of 64)
@@ -1514,8 +1512,13 @@ __global__ __launch_bounds__(kRsScatterBlock) void k_rs_scatter(const uint32_t* 
 #pragma unroll
     for (int k = 0; k < kRsItems; ++k) {
         const int64_t i = t0 + wave * kPerWave + k * kWave + lane;
-        pkey[k] = i < N ? kin[sbase + i] : 0u;
-        pval[k] = i < N ? vin[sbase + i] : 0u;
+        if constexpr (FIRST) {
+            pkey[k] = i < N ? order_key(__uint_as_float(kin[sbase + i])) : 0u;
+            pval[k] = i < N ? (rank2_y ? rank2_y[i] : static_cast<uint32_t>(i)) : 0u;
+        } else {
+            pkey[k] = i < N ? kin[sbase + i] : 0u;
+            pval[k] = i < N ? vin[sbase + i] : 0u;
+        }
     }
     if (digit_thread) {
         base_off[tid] = start;
@@ -1858,10 +1861,9 @@ struct DeviceScratch {
     size_t tape_cap = 0;
     float* fit_tmp = nullptr;
     size_t fit_tmp_cap = 0;
-    // Spearman: program outputs, sort keys and indices (double-buffered), the
-    // target's run starts, digit counts, the target's ranks, NaN flags
-    float* sp_out = nullptr;
-    size_t sp_out_cap = 0;
+    // Spearman: sort keys (the first also takes the program outputs) and
+    // carried values, double-buffered; the target's run starts, digit counts,
+    // the target's ranks, NaN flags
     uint32_t* sp_k0 = nullptr;
     size_t sp_k0_cap = 0;
     uint32_t* sp_k1 = nullptr;
@@ -1932,7 +1934,7 @@ gp_status scratch_init(DeviceScratch& s, int dev) {
 
 bool scratch_empty(const DeviceScratch& s) {
     return !s.counter && !s.order && !s.part && !s.ystat && !s.code && !s.clen && !s.stats && !s.gpart &&
-           !s.gextra && !s.tape && !s.fit_tmp && !s.sp_out && !s.sp_k0 && !s.sp_k1 && !s.sp_v0 && !s.sp_v1 &&
+           !s.gextra && !s.tape && !s.fit_tmp && !s.sp_k0 && !s.sp_k1 && !s.sp_v0 && !s.sp_v1 &&
            !s.sp_rs && !s.sp_cnt && !s.sp_r2y && !s.sp_nan && !s.sp_ty;
 }
 
@@ -1941,7 +1943,7 @@ void scratch_free(DeviceScratch& s) {
     for (void* q : {s.counter, static_cast<void*>(s.order), static_cast<void*>(s.part),
                     static_cast<void*>(s.ystat), static_cast<void*>(s.code), static_cast<void*>(s.clen),
                     static_cast<void*>(s.stats), static_cast<void*>(s.gpart), static_cast<void*>(s.gextra),
-                    static_cast<void*>(s.tape), static_cast<void*>(s.fit_tmp), static_cast<void*>(s.sp_out),
+                    static_cast<void*>(s.tape), static_cast<void*>(s.fit_tmp),
                     static_cast<void*>(s.sp_k0), static_cast<void*>(s.sp_k1), static_cast<void*>(s.sp_v0),
                     static_cast<void*>(s.sp_v1), static_cast<void*>(s.sp_rs), static_cast<void*>(s.sp_cnt),
                     static_cast<void*>(s.sp_r2y), static_cast<void*>(s.sp_nan), static_cast<void*>(s.sp_ty)})
@@ -2249,19 +2251,31 @@ __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t* __restrict__ p, in
     if (i < n) p[i] = v;
 }
 
-// Sorts the B segments of N keys (with their indices) held in k0 / v0; the
-// result is back in k0 / v0 after the four passes.
-gp_status radix_sort_segments(DeviceScratch* sc, int64_t N, int32_t B, hipStream_t st) {
+// Sorts the B segments of N float values at src (keys formed in the first
+// pass, each carrying its row's target rank, or its row when rank2_y is
+// NULL): the sorted keys and values end in k0 / v0.  src may be k0 itself
+// (the first pass writes k1 / v1 only).
+gp_status radix_sort_segments(DeviceScratch* sc, const float* src, const uint32_t* rank2_y, int64_t N, int32_t B,
+                              hipStream_t st) {
     const int32_t T = static_cast<int32_t>((N + kRsTile - 1) / kRsTile);
-    uint32_t *kin = sc->sp_k0, *vin = sc->sp_v0, *kout = sc->sp_k1, *vout = sc->sp_v1;
-    for (int pass = 0; pass < 4; ++pass) {
+    const uint32_t* in0 = reinterpret_cast<const uint32_t*>(src);
+    hipLaunchKernelGGL(k_rs_count<true>, dim3(T, B), dim3(kRsBlock), 0, st, in0, N, T, 0, sc->sp_cnt, sc->sp_nan);
+    GP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_rs_scan, dim3(B), dim3(1024), 0, st, sc->sp_cnt, T);
+    GP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_rs_scatter<true>, dim3(T, B), dim3(kRsScatterBlock), 0, st, in0, nullptr, sc->sp_k1,
+                       sc->sp_v1, N, T, 0, sc->sp_cnt, rank2_y);
+    GP_HIP(hipGetLastError());
+    uint32_t *kin = sc->sp_k1, *vin = sc->sp_v1, *kout = sc->sp_k0, *vout = sc->sp_v0;
+    for (int pass = 1; pass < 4; ++pass) {
         const int shift = 8 * pass;
-        hipLaunchKernelGGL(k_rs_count, dim3(T, B), dim3(kRsBlock), 0, st, kin, N, T, shift, sc->sp_cnt);
+        hipLaunchKernelGGL(k_rs_count<false>, dim3(T, B), dim3(kRsBlock), 0, st, kin, N, T, shift, sc->sp_cnt,
+                           nullptr);
         GP_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_rs_scan, dim3(B), dim3(1024), 0, st, sc->sp_cnt, T);
         GP_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_rs_scatter, dim3(T, B), dim3(kRsScatterBlock), 0, st, kin, vin, kout, vout, N, T, shift,
-                           sc->sp_cnt);
+        hipLaunchKernelGGL(k_rs_scatter<false>, dim3(T, B), dim3(kRsScatterBlock), 0, st, kin, vin, kout, vout, N,
+                           T, shift, sc->sp_cnt, nullptr);
         GP_HIP(hipGetLastError());
         std::swap(kin, kout);
         std::swap(vin, vout);
@@ -2277,8 +2291,9 @@ gp_status spearman_impl(DeviceScratch* sc, const gp_population_dev* pop, const g
     const int32_t P = pop->n_programs;
     if (N >= (int64_t{1} << 31)) return fail(GP_ERR_INVALID_ARG, "gp_fitness: Spearman needs n_rows below 2^31");
     const int32_t T = static_cast<int32_t>((N + kRsTile - 1) / kRsTile);
-    // working set per program: outputs, keys and indices twice (20 bytes per
-    // row).  Up to the set limit, else 16 GiB of it and at most half the
+    // working set per program: keys and carried values twice, the outputs
+    // sharing the first key buffer (16 bytes per row).  Up to the set limit,
+    // else 16 GiB of it and at most half the
     // free memory; a program's fitness does not depend on its batch.  When
     // the programs need several batches, a batch is a whole number of rounds
     // of resident correlation workgroups (one per program).
@@ -2289,7 +2304,7 @@ gp_status spearman_impl(DeviceScratch* sc, const gp_population_dev* pop, const g
         budget = std::max<int64_t>(std::min<int64_t>(int64_t{16} << 30, static_cast<int64_t>(free_b / 2)),
                                    int64_t{256} << 20);
     }
-    int64_t Bmax = std::max<int64_t>(1, budget / (20 * N));
+    int64_t Bmax = std::max<int64_t>(1, budget / (16 * N));
     if (Bmax < P) {
         int per_cu = 0;
         GP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_spear_corr<false>, 1024, 0));
@@ -2302,7 +2317,6 @@ gp_status spearman_impl(DeviceScratch* sc, const gp_population_dev* pop, const g
     auto need = [&](void** ptr, size_t* cap, size_t n, size_t elem) {
         if (rc == GP_OK) rc = grow(ptr, cap, n, elem);
     };
-    need(reinterpret_cast<void**>(&sc->sp_out), &sc->sp_out_cap, BN, sizeof(float));
     need(reinterpret_cast<void**>(&sc->sp_k0), &sc->sp_k0_cap, BN, sizeof(uint32_t));
     need(reinterpret_cast<void**>(&sc->sp_k1), &sc->sp_k1_cap, BN, sizeof(uint32_t));
     need(reinterpret_cast<void**>(&sc->sp_v0), &sc->sp_v0_cap, BN, sizeof(uint32_t));
@@ -2320,15 +2334,9 @@ gp_status spearman_impl(DeviceScratch* sc, const gp_population_dev* pop, const g
         GP_HIP(hipGetLastError());
         return GP_OK;
     };
-    const int key_blocks = static_cast<int>(std::min<int64_t>((static_cast<int64_t>(BN) + kRsBlock - 1) / kRsBlock,
-                                                              int64_t{1} << 16));
     // the target's ranks (twice the mean rank of each row)
     if ((rc = fill_nan_flags(1)) != GP_OK) return rc;
-    hipLaunchKernelGGL(k_spear_keys, dim3(static_cast<unsigned>(std::min<int64_t>((N + kRsBlock - 1) / kRsBlock,
-                                                                                  int64_t{1} << 16))),
-                       dim3(kRsBlock), 0, st, data->y, N, 1, nullptr, sc->sp_k0, sc->sp_v0, sc->sp_nan);
-    GP_HIP(hipGetLastError());
-    if ((rc = radix_sort_segments(sc, N, 1, st)) != GP_OK) return rc;
+    if ((rc = radix_sort_segments(sc, data->y, nullptr, N, 1, st)) != GP_OK) return rc;
     hipLaunchKernelGGL(k_spear_rank_target, dim3(1), dim3(1024), 0, st, sc->sp_k0, sc->sp_v0, N, data->w,
                        sc->sp_rs, sc->sp_r2y, sc->sp_ty);
     GP_HIP(hipGetLastError());
@@ -2346,13 +2354,13 @@ gp_status spearman_impl(DeviceScratch* sc, const gp_population_dev* pop, const g
         LaunchCfg cfg;
         rc = prepare(sc, &view, data, 0, GP_METRIC_MSE, st, nullptr, &pv, &cvw, &dv, &sch, &cfg);
         if (rc != GP_OK) return rc;
-        rc = launch_eval(0, GP_METRIC_MSE, cfg, sc->n_cu, pv, cvw, dv, sch, sc->sp_out, nullptr, st, 0, Timing{});
+        // the outputs go to the first key buffer, which the sort's first pass
+        // reads before anything writes it again
+        float* out = reinterpret_cast<float*>(sc->sp_k0);
+        rc = launch_eval(0, GP_METRIC_MSE, cfg, sc->n_cu, pv, cvw, dv, sch, out, nullptr, st, 0, Timing{});
         if (rc != GP_OK) return rc;
         if ((rc = fill_nan_flags(b)) != GP_OK) return rc;
-        hipLaunchKernelGGL(k_spear_keys, dim3(key_blocks), dim3(kRsBlock), 0, st, sc->sp_out, N, b,
-                           data->w ? nullptr : sc->sp_r2y, sc->sp_k0, sc->sp_v0, sc->sp_nan);
-        GP_HIP(hipGetLastError());
-        if ((rc = radix_sort_segments(sc, N, b, st)) != GP_OK) return rc;
+        if ((rc = radix_sort_segments(sc, out, data->w ? nullptr : sc->sp_r2y, N, b, st)) != GP_OK) return rc;
         if (data->w)
             hipLaunchKernelGGL(k_spear_corr<true>, dim3(b), dim3(1024), 0, st, sc->sp_k0, sc->sp_v0, N, sc->sp_r2y,
                                data->w, sc->sp_ty, sc->sp_nan, fitness, p0);

@@ -104,8 +104,8 @@ def test_spearman_nan_and_constant_programs(gp):
                                        (1_500_000, 700 << 20)])
 def test_spearman_sizes_and_batches(gp, N, workset):
     """Ragged tiles, tiny inputs, 1.5M rows in one batch and, with the working
-    set limited to 700 MiB (20 bytes per row per program: 24 programs a
-    batch), in seven batches, the last one short."""
+    set limited to 700 MiB (16 bytes per row per program: 30 programs a
+    batch), in six batches, the last one short."""
     X, y = synth.pagie(N, seed=N)
     fmask = sum(1 << o for o in (oracle.ADD, oracle.SUB, oracle.MUL, oracle.DIV, oracle.NEG, oracle.SQRT))
     P = 160 if N > 100_000 else 48
