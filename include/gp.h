@@ -340,10 +340,13 @@ gp_status gp_tournament(const float* fitness, const int32_t* len, int32_t n_prog
  * 1/(1+a^2), cbrt 1/(3 cbrt(a)^2) (0 at 0).  Metrics MAE, MSE, RMSE,
  * LOGLOSS, PEARSON.  fitness_out [n_programs] (nullable) receives the
  * fitness as gp_fitness would.  All pointers DEVICE memory.  The population
- * view must carry max_len and total_consts.  A program's constants in slots
- * below 16 are summed in a fixed order (bit-reproducible); further slots are
- * summed with float64 atomics.  Scratch grows with 2*max_len tape entries per
- * wavefront (64 floats each). */
+ * view must carry max_len (at most 2^25, else GP_ERR_INVALID_ARG) and
+ * total_consts.  A program's constants in slots below 16 are summed in a
+ * fixed order (bit-reproducible); further slots are summed with float64
+ * atomics.  Rows per lane: a forced launch configuration's, else 2 or 4,
+ * whichever keeps more rows in flight per CU at the kernel's occupancy.
+ * Scratch grows with 2*max_len tape entries per wavefront (64 floats per
+ * row per lane each). */
 gp_status gp_fitness_backward(const gp_population_dev* pop, const gp_dataset_dev* data,
                               gp_metric metric, const float* grad_fitness,
                               float* fitness_out, float* grad_consts, void* stream);
