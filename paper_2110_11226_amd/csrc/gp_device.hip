@@ -847,7 +847,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
 // adjoint over the wavefront into a per-program float64 sum.  Only
 // instructions whose subtree holds a constant (kActive) record partials, and
 // the reverse pass jumps over every subtree without one.  The first
-// kTapeLdsBytes of each wavefront's tape live in LDS, the rest (long
+// tape_lds_bytes<R>() of each wavefront's tape live in LDS, the rest (long
 // programs) in a per-wavefront global area; the forward values are
 // recomputed per tile, never kept.  Local derivatives (reading): add (1,1),
 // sub (1,-1), mul (b,a), div (1/b, -a/b^2) if |b| > 0.001 else (0,0),
@@ -855,7 +855,10 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
 // sin cos a, cos -sin a, tan 1 + tan^2 a, neg -1.
 // ---------------------------------------------------------------------------
 constexpr int kGradLds = 16;            // constants per program summed in a fixed order
-constexpr int kTapeLdsBytes = 12288;    // per-wavefront tape held in LDS
+// per-wavefront tape held in LDS: 12 KB, 18 KB at 4 rows per lane (two
+// waves per SIMD there, so eight per CU still fit in LDS)
+template <int R>
+constexpr int tape_lds_bytes() { return R == 4 ? 18432 : 12288; }
 
 // tape entries an instruction records (0, 1 or 2)
 __device__ __forceinline__ int tape_entries(uint32_t cls, uint32_t fn) {
@@ -868,7 +871,7 @@ __device__ __forceinline__ int tape_entries(uint32_t cls, uint32_t fn) {
 // the tape entries beyond those in LDS
 template <int R>
 constexpr int64_t adjoint_wave_floats(int64_t tape_entries_max) {
-    const int64_t lds_entries = kTapeLdsBytes / (R * kWave * 4);
+    const int64_t lds_entries = tape_lds_bytes<R>() / (R * kWave * 4);
     const int64_t beyond = tape_entries_max > lds_entries ? tape_entries_max - lds_entries : 0;
     return (2 * kStackLds + beyond) * R * kWave;
 }
@@ -909,7 +912,7 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                                                     float* __restrict__ gmem,
                                                     int64_t wave_floats) {
     constexpr int FA = FREG > 0 ? FREG : 1;
-    constexpr int kTapeLds = kTapeLdsBytes / (R * kWave * 4);
+    constexpr int kTapeLds = tape_lds_bytes<R>() / (R * kWave * 4);
     const int lane = threadIdx.x;
     const int64_t N = d.N;
     const int64_t ld = d.ld;
