@@ -520,7 +520,8 @@ void orc_evaluate_pairs(const uint32_t *nodes, const int64_t *prog_off,
 /* Readings: rank 1 is the smallest value; tied values share the mean of the  */
 /* ranks they span (the standard definition); ranks ignore the weights, and   */
 /* the correlation of the ranks is the weighted Pearson of metric 4 (|r|,     */
-/* 0 for a constant rank vector); a NaN value makes the fitness NaN.          */
+/* 0 for a constant rank vector); NaN has no rank, so a NaN value, or a NaN   */
+/* in the target, makes the fitness NaN.                                      */
 static void merge_sort_idx(const double *v, int64_t *idx, int64_t *tmp, int64_t n)
 {
     /* bottom-up merge sort of the indices by value (stable) */
@@ -596,7 +597,7 @@ static double spearman_abs(const float *yh32, const double *yh64, const float *y
     for (int64_t r = 0; r < n; ++r) {
         a[r] = yh32 ? (double)yh32[r] : yh64[r];
         b[r] = (double)y[r];
-        if (isnan(a[r])) has_nan = 1;
+        if (isnan(a[r]) || isnan(b[r])) has_nan = 1;
     }
     double out = NAN;
     if (!has_nan) {
@@ -691,9 +692,15 @@ static double spearman_bound(const float *yh, const double *E, const float *y, c
     double *rb = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     double *d = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int y_nan = 0;
     for (int64_t r = 0; r < n; ++r) {
         v[r] = (double)yh[r];
         lo[r] = v[r] - E[r];
+        if (isnan(y[r])) y_nan = 1;
+    }
+    if (y_nan) {                            /* NaN on both sides, whatever the values */
+        free(v); free(lo); free(ra); free(rb); free(d); free(idx);
+        return 0.0;
     }
     average_ranks(lo, n, ra, idx);          /* idx: rows by ascending lower end */
     int64_t i = 0;

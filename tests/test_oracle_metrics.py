@@ -212,3 +212,21 @@ def test_spearman_nan_is_nan():
     pop = oracle.from_programs([([node(VAR, 0)], [])])
     f32p, f64 = oracle.fitness(pop, X, y, None, "spearman")
     assert np.isnan(f32p[0]) and np.isnan(f64[0])
+
+
+def test_spearman_nan_target_is_nan():
+    # NaN has no rank: a NaN in the target makes every program's fitness NaN
+    # (either sign of NaN, anywhere in the column), with a zero bound
+    X = np.array([[1.0, 2.0, 3.0, 4.0]], dtype=np.float32)
+    pop = oracle.from_programs([([node(VAR, 0)], []), ([node(CONST, 0)], [2.0])])
+    for k in range(4):
+        for nan in (np.float32(np.nan), -np.float32(np.nan)):
+            y = np.array([1.0, 3.0, 2.0, 4.0], dtype=np.float32)
+            y[k] = nan
+            f32p, f64, fb, fn = oracle.fitness(pop, X, y, None, "spearman", with_bound=True)
+            assert np.isnan(f32p).all() and np.isnan(f64).all(), (k, nan)
+            assert (fb == 0.0).all()
+    # without the NaN the same column is an ordinary rank correlation
+    y = np.array([1.0, 3.0, 2.0, 4.0], dtype=np.float32)
+    f32p, _ = oracle.fitness(pop, X, y, None, "spearman")
+    assert abs(f32p[0] - 0.8) <= 1e-6 and f32p[1] == 0.0
