@@ -116,7 +116,7 @@ void gp_shutdown(void);
 /*   SPEARMAN: |weighted correlation of the ranks of yh and of y|:     */
 /*            rank 1 the smallest, tied values the mean of their       */
 /*            ranks, ranks unweighted, the weights in the correlation; */
-/*            0 for a constant rank vector, NaN if any yh is NaN       */
+/*            0 for a constant rank vector, NaN if any yh or y is NaN  */
 /*            (larger is better).  gp_fitness, the generation graphs   */
 /*            and the evolution loop compute it (batched sort on the   */
 /*            device, n_rows below 2^31); gp_fitness_backward,         */

@@ -1697,9 +1697,9 @@ __global__ __launch_bounds__(1024) void k_spear_rank_target(const uint32_t* __re
 // the carry of the earlier blocks).  With a = rank - (N+1)/2 for the program
 // and b likewise for the target, the weighted sums of a, a^2 and a b and the
 // target's shared sums (tsum) give |r|: 0 for a constant rank vector, NaN if
-// the outputs held a NaN.  Two blocks' loads go out together.  Unweighted,
-// the sorted values are the target ranks themselves; weighted, they are rows,
-// whose target ranks and weights are gathered.
+// the outputs or the target held a NaN.  Two blocks' loads go out together.
+// Unweighted, the sorted values are the target ranks themselves; weighted,
+// they are rows, whose target ranks and weights are gathered.
 template <bool WEIGHTED>
 __global__ __launch_bounds__(1024) void k_spear_corr(const uint32_t* __restrict__ keys,
                                                       const uint32_t* __restrict__ vals, int64_t N,
@@ -1707,6 +1707,7 @@ __global__ __launch_bounds__(1024) void k_spear_corr(const uint32_t* __restrict_
                                                       const float* __restrict__ w,
                                                       const double* __restrict__ tsum,
                                                       const int32_t* __restrict__ nan_flag,
+                                                      const int32_t* __restrict__ target_nan,
                                                       float* __restrict__ fitness, int32_t prog0) {
     constexpr int kW = 1024 / kWave, kE = 2;
     constexpr uint32_t kNone = 0xffffffffu;
@@ -1825,7 +1826,7 @@ __global__ __launch_bounds__(1024) void k_spear_corr(const uint32_t* __restrict_
         const double cab = tot[2] - tot[0] * tsum[1] / W;
         const bool constant = k[0] == k[n - 1];    // one run of equal values
         float f;
-        if (nan_flag[seg]) f = __builtin_nanf("");
+        if (nan_flag[seg] || *target_nan) f = __builtin_nanf("");
         else if (constant || !(va > 0.0) || !(vb > 0.0) || !isfinite(va) || !isfinite(vb)) f = 0.0f;
         else f = static_cast<float>(fabs(cab / sqrt(va * vb)));
         fitness[prog0 + seg] = f;
@@ -2256,13 +2257,14 @@ __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t* __restrict__ p, in
 
 // Sorts the B segments of N float values at src (keys formed in the first
 // pass, each carrying its row's target rank, or its row when rank2_y is
-// NULL): the sorted keys and values end in k0 / v0.  src may be k0 itself
-// (the first pass writes k1 / v1 only).
+// NULL): the sorted keys and values end in k0 / v0, and nan_flag[s] is
+// raised for a segment holding a NaN.  src may be k0 itself (the first pass
+// writes k1 / v1 only).
 gp_status radix_sort_segments(DeviceScratch* sc, const float* src, const uint32_t* rank2_y, int64_t N, int32_t B,
-                              hipStream_t st) {
+                              int32_t* nan_flag, hipStream_t st) {
     const int32_t T = static_cast<int32_t>((N + kRsTile - 1) / kRsTile);
     const uint32_t* in0 = reinterpret_cast<const uint32_t*>(src);
-    hipLaunchKernelGGL(k_rs_count<true>, dim3(T, B), dim3(kRsBlock), 0, st, in0, N, T, 0, sc->sp_cnt, sc->sp_nan);
+    hipLaunchKernelGGL(k_rs_count<true>, dim3(T, B), dim3(kRsBlock), 0, st, in0, N, T, 0, sc->sp_cnt, nan_flag);
     GP_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_rs_scan, dim3(B), dim3(1024), 0, st, sc->sp_cnt, T);
     GP_HIP(hipGetLastError());
@@ -2328,18 +2330,20 @@ gp_status spearman_impl(DeviceScratch* sc, const gp_population_dev* pop, const g
     need(reinterpret_cast<void**>(&sc->sp_cnt), &sc->sp_cnt_cap, static_cast<size_t>(B) * kRsRadix * T,
          sizeof(uint32_t));
     need(reinterpret_cast<void**>(&sc->sp_r2y), &sc->sp_r2y_cap, static_cast<size_t>(N), sizeof(uint32_t));
-    need(reinterpret_cast<void**>(&sc->sp_nan), &sc->sp_nan_cap, static_cast<size_t>(B), sizeof(int32_t));
+    need(reinterpret_cast<void**>(&sc->sp_nan), &sc->sp_nan_cap, static_cast<size_t>(B) + 1, sizeof(int32_t));
     need(reinterpret_cast<void**>(&sc->sp_ty), &sc->sp_ty_cap, 3, sizeof(double));
     if (rc != GP_OK) return rc;
-    auto fill_nan_flags = [&](int32_t n) -> gp_status {
-        hipLaunchKernelGGL(k_fill_i32, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, sc->sp_nan,
+    auto fill_nan_flags = [&](int32_t* flags, int32_t n) -> gp_status {
+        hipLaunchKernelGGL(k_fill_i32, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, flags,
                            static_cast<int64_t>(n), 0);
         GP_HIP(hipGetLastError());
         return GP_OK;
     };
-    // the target's ranks (twice the mean rank of each row)
-    if ((rc = fill_nan_flags(1)) != GP_OK) return rc;
-    if ((rc = radix_sort_segments(sc, data->y, nullptr, N, 1, st)) != GP_OK) return rc;
+    // the target's ranks (twice the mean rank of each row); a NaN in the
+    // target (flag B) makes every program's fitness NaN
+    int32_t* target_nan = sc->sp_nan + B;
+    if ((rc = fill_nan_flags(target_nan, 1)) != GP_OK) return rc;
+    if ((rc = radix_sort_segments(sc, data->y, nullptr, N, 1, target_nan, st)) != GP_OK) return rc;
     hipLaunchKernelGGL(k_spear_rank_target, dim3(1), dim3(1024), 0, st, sc->sp_k0, sc->sp_v0, N, data->w,
                        sc->sp_rs, sc->sp_r2y, sc->sp_ty);
     GP_HIP(hipGetLastError());
@@ -2362,14 +2366,15 @@ gp_status spearman_impl(DeviceScratch* sc, const gp_population_dev* pop, const g
         float* out = reinterpret_cast<float*>(sc->sp_k0);
         rc = launch_eval(0, GP_METRIC_MSE, cfg, sc->n_cu, pv, cvw, dv, sch, out, nullptr, st, 0, Timing{});
         if (rc != GP_OK) return rc;
-        if ((rc = fill_nan_flags(b)) != GP_OK) return rc;
-        if ((rc = radix_sort_segments(sc, out, data->w ? nullptr : sc->sp_r2y, N, b, st)) != GP_OK) return rc;
+        if ((rc = fill_nan_flags(sc->sp_nan, b)) != GP_OK) return rc;
+        if ((rc = radix_sort_segments(sc, out, data->w ? nullptr : sc->sp_r2y, N, b, sc->sp_nan, st)) != GP_OK)
+            return rc;
         if (data->w)
             hipLaunchKernelGGL(k_spear_corr<true>, dim3(b), dim3(1024), 0, st, sc->sp_k0, sc->sp_v0, N, sc->sp_r2y,
-                               data->w, sc->sp_ty, sc->sp_nan, fitness, p0);
+                               data->w, sc->sp_ty, sc->sp_nan, target_nan, fitness, p0);
         else
             hipLaunchKernelGGL(k_spear_corr<false>, dim3(b), dim3(1024), 0, st, sc->sp_k0, sc->sp_v0, N, sc->sp_r2y,
-                               nullptr, sc->sp_ty, sc->sp_nan, fitness, p0);
+                               nullptr, sc->sp_ty, sc->sp_nan, target_nan, fitness, p0);
         GP_HIP(hipGetLastError());
     }
     return GP_OK;

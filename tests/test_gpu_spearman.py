@@ -100,6 +100,29 @@ def test_spearman_nan_and_constant_programs(gp):
     assert np.allclose(got[[1, 3]], f32p[[1, 3]], rtol=1e-6)
 
 
+def test_spearman_nan_target_is_nan_for_every_program(gp):
+    """A NaN in the target (either sign, first, last or inside a tile) makes
+    every program's Spearman fitness NaN, in every batch, as in the oracle."""
+    N = 9000
+    X, y0 = synth.pagie(N, seed=8)
+    host = gp.build_population(40, 2, "rhh", min_depth=1, max_depth=4, seed=3)
+    for k in (0, N - 1, 4500):
+        for nan in (np.float32(np.nan), -np.float32(np.nan)):
+            y = y0.copy()
+            y[k] = nan
+            gp.set_spearman_workset(16 * N * 7)          # batches of 7 programs
+            try:
+                got = gpu_spearman(gp, host, X, y, None, 2)
+            finally:
+                gp.set_spearman_workset(0)
+            f32p, _ = oracle.fitness(to_oracle(host), X, y, None, "spearman")
+            assert np.isnan(got).all() and np.isnan(f32p).all(), (k, nan)
+    # and the next call, without the NaN, is ordinary again
+    got = gpu_spearman(gp, host, X, y0, None, 2)
+    f32p, f64, fb, fn = oracle.fitness(to_oracle(host), X, y0, None, "spearman", n_threads=NT, with_bound=True)
+    check(got, f32p, fb, fn, "after NaN target")
+
+
 @pytest.mark.parametrize("N,workset", [(1, 0), (2, 0), (63, 0), (4097, 0), (1_500_000, 0),
                                        (1_500_000, 700 << 20)])
 def test_spearman_sizes_and_batches(gp, N, workset):
