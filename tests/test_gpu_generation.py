@@ -84,6 +84,35 @@ def test_graph_replays_match_plain_calls(gp, metric):
         gen.close()
 
 
+def test_graph_spearman_in_several_batches(gp):
+    """Spearman fitness captured with a working-set limit that splits the
+    programs into six batches (the last one short): every replay equals the
+    plain call under the same limit, bit for bit."""
+    P, N, F = 256, 20_001, 2
+    X, y = synth.pagie(N, seed=11227)
+    data = gp.DeviceDataset(X, y)
+    pops = populations(gp, P, F, 3)
+    cap_nodes = max(int(p.nodes.shape[0]) for p in pops)
+    cap_consts = max(int(p.consts.shape[0]) for p in pops)
+    gp.set_spearman_workset(16 * N * 50)          # 50 programs a batch
+    try:
+        gen = gp.Generation(data, P, cap_nodes, cap_consts, "spearman", parsimony=0.0, tournament_size=7,
+                            n_tournaments=P, seed=5)
+        try:
+            for g, host in enumerate(pops):
+                fit_g, win_g = gen.run(host, g)
+                fit_e, win_e = eager(gp, host, data, "spearman", 0.0, 7, P, 5, g, F)
+                assert np.array_equal(fit_g.view(np.uint32), fit_e.view(np.uint32)), g
+                assert np.array_equal(win_g, win_e), g
+        finally:
+            gen.close()
+    finally:
+        gp.set_spearman_workset(0)
+    # and the batched result is the one-batch result
+    fit_one, _ = eager(gp, pops[2], data, "spearman", 0.0, 7, P, 5, 2, F)
+    assert np.array_equal(fit_g.view(np.uint32), fit_one.view(np.uint32))
+
+
 def test_graph_fitness_matches_oracle(gp):
     P, N, F = 128, 20_000, 2
     X, y = synth.pagie(N, seed=11227)
