@@ -146,6 +146,17 @@ def test_device_entry_points_reject_bad_arguments_before_launch(gp):
     with pytest.raises(gp.GPError, match="INVALID_ARG"):
         gp.set_spearman_workset(-1)
     gp.set_spearman_workset(0)
+    # the adjoint: programs beyond its reverse-walk links, and Spearman (no
+    # derivative), are refused before any device work (the pointers are
+    # placeholders, never read)
+    fake = ctypes.c_void_p(256)
+    pv = B.PopulationDev(fake, fake, None, fake, fake, 4, 40, (1 << 25) + 1, 0)
+    dv = B.DatasetDev(fake, 100, 2, 100, fake, None)
+    assert B._backward(ctypes.byref(pv), ctypes.byref(dv), 1, None, None, None, None) == -1
+    assert "2^25" in B._last_error().decode()
+    pv.max_len = 50
+    assert B._backward(ctypes.byref(pv), ctypes.byref(dv), 5, None, None, None, None) == -6
+    assert "Spearman" in B._last_error().decode()
 
 
 def test_metric_direction(gp):
