@@ -302,6 +302,8 @@ def main():
     ap.add_argument("--no-spearman", action="store_true", help="skip the Spearman fitness timing")
     ap.add_argument("--only-spearman", action="store_true",
                     help="time only the Spearman fitness (for a kernel trace of it)")
+    ap.add_argument("--only-adjoint", action="store_true",
+                    help="only the adjoint / forward ratio on the differentiation workload (for profiling)")
     ap.add_argument("--configs", action="store_true",
                     help="instead of the step, measure gp_fitness on every workload configuration")
     ap.add_argument("--cpu-rows", type=int, default=196_608)
@@ -332,6 +334,12 @@ def main():
         del src, dst
     if args.configs:
         print(json.dumps({"configs": config_table(gp, torch)}), flush=True)
+        return 0
+    if args.only_adjoint:
+        adj = adjoint_ratio(gp, torch)
+        log(f"[bench] forward {adj['forward_ms']:.2f} ms, backward {adj['backward_ms']:.2f} ms, "
+            f"ratio {adj['ratio']:.2f}")
+        print(json.dumps({"adjoint": adj}), flush=True)
         return 0
     if args.only_spearman:
         spear = spearman_time(gp, torch)
