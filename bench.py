@@ -302,6 +302,8 @@ def main():
     ap.add_argument("--no-spearman", action="store_true", help="skip the Spearman fitness timing")
     ap.add_argument("--only-spearman", action="store_true",
                     help="time only the Spearman fitness (for a kernel trace of it)")
+    ap.add_argument("--only-loop", action="store_true",
+                    help="only the generation-loop timing (host vs device genetic operations; for profiling)")
     ap.add_argument("--only-adjoint", action="store_true",
                     help="only the adjoint / forward ratio on the differentiation workload (for profiling)")
     ap.add_argument("--configs", action="store_true",
@@ -334,6 +336,12 @@ def main():
         del src, dst
     if args.configs:
         print(json.dumps({"configs": config_table(gp, torch)}), flush=True)
+        return 0
+    if args.only_loop:
+        loop = loop_generation_time(gp, torch)
+        log(f"[bench] loop ms/generation: host mutation {loop['host_mutation_ms_per_generation']:.2f}, "
+            f"device loop {loop['device_loop_ms_per_generation']:.2f}")
+        print(json.dumps({"generation_loop": loop}), flush=True)
         return 0
     if args.only_adjoint:
         adj = adjoint_ratio(gp, torch)
