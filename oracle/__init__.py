@@ -74,9 +74,13 @@ def lib():
         L.orc_evaluate_f32.argtypes = [P, P, P, P, i32, P, i64, i64, P, ctypes.c_int]
         L.orc_evaluate_f64.argtypes = [P, P, P, P, i32, P, i64, i64, P, ctypes.c_int]
         L.orc_evaluate_pairs.argtypes = [P, P, P, P, P, i64, P, P, i64, ctypes.c_double, ctypes.c_double,
-                                         P, P, P, P, ctypes.c_int]
+                                         u32, P, P, P, P, ctypes.c_int]
         L.orc_fitness.argtypes = [P, P, P, P, i32, P, i64, i64, P, P, i32, P, P, ctypes.c_double,
-                                  ctypes.c_double, P, P, ctypes.c_int]
+                                  ctypes.c_double, u32, P, P, ctypes.c_int]
+        L.orc_cr_undecided.restype = ctypes.c_longlong
+        L.orc_cr_undecided.argtypes = []
+        L.orc_cr_reset.argtypes = []
+        L.orc_cr_set_margin.argtypes = [ctypes.c_double]
         L.orc_philox4x32_10.argtypes = [P, P, P]
         L.orc_philox_words.argtypes = [u64, u32, u32, u32, u32, u32, P]
         L.orc_tournament.argtypes = [P, P, i32, i32, f32, i32, i32, u64, u64, P]
@@ -95,6 +99,23 @@ def lib():
         L.orc_mutate.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def cr_undecided() -> int:
+    """Library-function roundings the float32 path could not decide since the
+    last cr_reset() (its result is then the x87 extended value's rounding)."""
+    return int(lib().orc_cr_undecided())
+
+
+def cr_reset():
+    lib().orc_cr_reset()
+
+
+def cr_set_margin(ulps=8.0):
+    """Distance (in double ulps) from a float32 rounding boundary below which
+    the float32 path consults the extended-precision result (tests widen it
+    to exercise that path; the default is 8)."""
+    lib().orc_cr_set_margin(float(ulps))
 
 
 def _p(a):
@@ -188,9 +209,11 @@ class RowAnalysis:
 
 
 def evaluate_pairs(pop: Population, X, prog, row, n_threads=None, u=ULP_ALLOWANCE,
-                   rf=ROUND_FLIP) -> RowAnalysis:
+                   rf=ROUND_FLIP, exact=0) -> RowAnalysis:
     """Float32 and float64 values and the conditioning analysis of each
-    (prog[i], row[i]) pair (see row_analysis in gp_oracle.c)."""
+    (prog[i], row[i]) pair (see row_analysis in gp_oracle.c).  `exact` is a
+    mask (bit per opcode) of the library functions the comparison takes as
+    correctly rounded on both sides: they get no allowance u of their own."""
     X, N = _ds(X)
     prog = np.ascontiguousarray(prog, dtype=np.int32)
     row = np.ascontiguousarray(row, dtype=np.int64)
@@ -201,18 +224,18 @@ def evaluate_pairs(pop: Population, X, prog, row, n_threads=None, u=ULP_ALLOWANC
     fl = np.empty(n, np.uint8)
     lib().orc_evaluate_pairs(_p(pop.nodes), _p(pop.prog_off), _p(pop.consts),
                              _p(pop.const_off), _p(X), N, _p(prog), _p(row), n, float(u), float(rf),
-                             _p(o32), _p(o64), _p(eb), _p(fl), _threads(n_threads))
+                             int(exact), _p(o32), _p(o64), _p(eb), _p(fl), _threads(n_threads))
     return RowAnalysis(o32, o64, eb, (fl & 1).astype(bool), (fl & 2).astype(bool))
 
 
 def fitness(pop: Population, X, y, w=None, metric="mse", n_threads=None, with_f64=True,
-            with_bound=False, u=ULP_ALLOWANCE, rf=ROUND_FLIP):
+            with_bound=False, u=ULP_ALLOWANCE, rf=ROUND_FLIP, exact=0):
     """(fitness from the float32 program values, fitness with every step in
     float64), as float64 arrays; the float32 result the library must match is
     the first one rounded to float32.  With with_bound=True also returns the
     first-order bound on the float32-path fitness's sensitivity and, per
     program, the number of rows with a protected predicate near its
-    threshold."""
+    threshold.  `exact` as in evaluate_pairs."""
     X, N = _ds(X)
     y = np.ascontiguousarray(y, dtype=np.float32)
     w = None if w is None else np.ascontiguousarray(w, dtype=np.float32)
@@ -223,7 +246,7 @@ def fitness(pop: Population, X, y, w=None, metric="mse", n_threads=None, with_f6
     fn = np.empty(pop.n_programs, np.int32) if with_bound else None
     lib().orc_fitness(_p(pop.nodes), _p(pop.prog_off), _p(pop.consts), _p(pop.const_off),
                       pop.n_programs, _p(X), N, N, _p(y), _p(w), m, _p(f32p), _p(f64), float(u),
-                      float(rf), _p(fb), _p(fn), _threads(n_threads))
+                      float(rf), int(exact), _p(fb), _p(fn), _threads(n_threads))
     if with_bound:
         return f32p, f64, fb, fn
     return f32p, f64

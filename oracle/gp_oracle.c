@@ -64,8 +64,9 @@ static int op_arity(int op)
 /* ---- protected operators (reading: the gplearn convention) ---- */
 static const float ORC_EPS = 0.001f;      /* float nearest 0.001 */
 
+static float cr_f32(int op, float a, float b);
 static float pdiv_f(float a, float b) { return fabsf(b) > ORC_EPS ? a / b : 1.0f; }
-static float plog_f(float a) { return fabsf(a) > ORC_EPS ? logf(fabsf(a)) : 0.0f; }
+static float plog_f(float a) { return fabsf(a) > ORC_EPS ? cr_f32(O_LOG, fabsf(a), 0.0f) : 0.0f; }
 static float psqrt_f(float a) { return sqrtf(fabsf(a)); }
 
 static double pdiv_d(double a, double b) { return fabs(b) > (double)ORC_EPS ? a / b : 1.0; }
@@ -118,6 +119,107 @@ static double min_d(double a, double b)
     return signbit(a) ? a : b;
 }
 
+/* ---- correctly rounded float32 values of the library functions ----
+ * Reading (float32 semantics): the float32 evaluation rounds the exact value
+ * of every function once, to nearest (ties to even), as IEEE arithmetic does
+ * for +, -, *, / and sqrt.  The paper names its functions but no library,
+ * and the float32 value of a program would otherwise depend on which
+ * library computed sin.  The C library's double result (within a few of its
+ * ulps of the exact value) decides the rounding unless it lies within
+ * 8 of its ulps (orc_cr_set_margin) of a float32 rounding boundary; then the x87
+ * extended-precision result decides, and if that too lies that close to the
+ * boundary the case is counted in orc_cr_undecided() (the extended result's
+ * rounding is returned). */
+static double g_cr_margin = 8.0;   /* tests widen it to exercise the fallback */
+static long long g_cr_undecided = 0;
+
+long long orc_cr_undecided(void) { return g_cr_undecided; }
+void orc_cr_reset(void) { g_cr_undecided = 0; }
+void orc_cr_set_margin(double m) { g_cr_margin = m > 0.0 ? m : 8.0; }
+
+/* the float32 rounding boundaries on either side of f = RN(v), as doubles
+ * (exact: a midpoint of two floats has 25 significant bits); the boundary
+ * beyond FLT_MAX is FLT_MAX + half its spacing */
+static void f32_boundaries(float f, double *lo, double *hi)
+{
+    const double top = 0x1.ffffffp127;
+    if (isinf(f)) {
+        *lo = f > 0 ? top : -INFINITY;
+        *hi = f > 0 ? INFINITY : -top;
+        return;
+    }
+    float fd = nextafterf(f, -INFINITY), fu = nextafterf(f, INFINITY);
+    *lo = isinf(fd) ? -top : ((double)f + (double)fd) * 0.5;
+    *hi = isinf(fu) ? top : ((double)f + (double)fu) * 0.5;
+}
+
+static int near_boundary_d(double v)
+{
+    if (isnan(v)) return 0;
+    double lo, hi;
+    f32_boundaries((float)v, &lo, &hi);
+    double d = fmin(v - lo, hi - v);
+    double a = fabs(v);
+    double ulp = isinf(a) ? 0.0 : nextafter(a, INFINITY) - a;
+    return d <= g_cr_margin * ulp;
+}
+
+static int near_boundary_ld(long double v)
+{
+    if (isnan(v)) return 0;
+    double lo, hi;
+    f32_boundaries((float)v, &lo, &hi);
+    long double d = fminl(v - (long double)lo, (long double)hi - v);
+    long double a = fabsl(v);
+    long double ulp = isinf(a) ? 0.0L : nextafterl(a, INFINITY) - a;
+    return d <= 8.0L * ulp;
+}
+
+static double lib_d(int op, double a, double b)
+{
+    switch (op) {
+    case O_SIN: return sin(a);
+    case O_COS: return cos(a);
+    case O_TAN: return tan(a);
+    case O_LOG: return log(a);
+    case O_EXP: return exp(a);
+    case O_TANH: return tanh(a);
+    case O_ATAN: return atan(a);
+    case O_CBRT: return cbrt(a);
+    case O_ATAN2: return atan2(a, b);
+    default: return NAN;
+    }
+}
+
+static long double lib_ld(int op, long double a, long double b)
+{
+    switch (op) {
+    case O_SIN: return sinl(a);
+    case O_COS: return cosl(a);
+    case O_TAN: return tanl(a);
+    case O_LOG: return logl(a);
+    case O_EXP: return expl(a);
+    case O_TANH: return tanhl(a);
+    case O_ATAN: return atanl(a);
+    case O_CBRT: return cbrtl(a);
+    case O_ATAN2: return atan2l(a, b);
+    default: return NAN;
+    }
+}
+
+/* RN(f(a[, b])) for the library function op */
+static float cr_f32(int op, float a, float b)
+{
+    double v = lib_d(op, (double)a, (double)b);
+    if (!near_boundary_d(v)) return (float)v;
+    long double w = lib_ld(op, (long double)a, (long double)b);
+    if (near_boundary_ld(w)) {
+#pragma omp atomic
+        g_cr_undecided++;
+    }
+    return (float)w;
+}
+
 static float op_f32(int op, float a, float b)
 {
     switch (op) {
@@ -127,21 +229,16 @@ static float op_f32(int op, float a, float b)
     case O_DIV: return pdiv_f(a, b);
     case O_MAX: return max_f(a, b);
     case O_MIN: return min_f(a, b);
-    case O_ATAN2: return atan2f(a, b);
+    case O_ATAN2: return cr_f32(O_ATAN2, a, b);
     case O_NEG: return -a;
     case O_LOG: return plog_f(a);
     case O_SQRT: return psqrt_f(a);
-    case O_SIN: return sinf(a);
-    case O_COS: return cosf(a);
-    case O_TAN: return tanf(a);
+    case O_SIN: case O_COS: case O_TAN: case O_EXP: case O_TANH: case O_ATAN: case O_CBRT:
+        return cr_f32(op, a, 0.0f);
     case O_ABS: return fabsf(a);
-    case O_EXP: return expf(a);
     case O_INV: return pinv_f(a);
     case O_SQ: return a * a;
     case O_CUBE: { float q = a * a; return q * a; }
-    case O_TANH: return tanhf(a);
-    case O_ATAN: return atanf(a);
-    case O_CBRT: return cbrtf(a);
     default: return NAN;
     }
 }
@@ -251,13 +348,13 @@ static double eval_row_f64(const uint32_t *nodes, int64_t len, const float *c,
 
 /* Conditioning analysis of one row (test infrastructure for the tolerance
  * policy).  Evaluates the program in float32 and float64 in lock-step and
- * carries, in float64, a bound E on how far a float32 evaluation can move
- * when every library-function result (sin, cos, tan, log, exp, tanh, atan,
- * cbrt, atan2) is allowed to differ from the correctly rounded one by `u`
- * relative: two correct library implementations of these functions are a
- * few ulp apart, while add, sub, mul, div, neg, abs, sqrt, max, min, inv, sq
- * and cube are correctly rounded everywhere and contribute nothing of their
- * own.  Operands carry bounds Ea, Eb; each node's bound is the largest
+ * carries, in float64, a bound E on how far another float32 evaluation can
+ * move when every library-function result (sin, cos, tan, log, exp, tanh,
+ * atan, cbrt, atan2) that it does not round correctly is allowed to differ
+ * from the correctly rounded one by `u` relative (an implementation within a
+ * few ulp); the functions in exact_mask (bit per opcode, argument xm), and
+ * add, sub, mul, div, neg, abs, sqrt, max, min, inv, sq and cube, are
+ * correctly rounded on both sides and contribute nothing of their own.  Operands carry bounds Ea, Eb; each node's bound is the largest
  * change of its value over the whole box [a - Ea, a + Ea] x [b - Eb, b + Eb]
  * (mean value theorem with the supremum of |f'| over the interval, or the
  * exact remainder of a polynomial), not the first-order |f'(a)| Ea, so that
@@ -330,8 +427,17 @@ static int neg_bit(double x) { return signbit(x) ? 1 : 0; }
 /* bound of a library function's result: D (1 + u) + u |v| */
 static double lib_bound(double D, double v, double u) { return D * (1.0 + u) + u * fabs(v); }
 
+/* bound of a library function's result when both sides round it correctly
+ * (bit `op` of exact_mask): only the operand's movement D and, where the
+ * operand moves, a flip to the neighbouring float */
+static double fn_bound(int op, uint32_t exact_mask, double D, double v, double u, double rf)
+{
+    if (exact_mask & (1u << op)) return D + round_flip(v, D, 1, rf);
+    return lib_bound(D, v, u);
+}
+
 static void row_analysis(const uint32_t *nodes, int64_t len, const float *c,
-                         const float *X, int64_t ld, int64_t row, double u, double rf,
+                         const float *X, int64_t ld, int64_t row, double u, double rf, uint32_t xm,
                          float *v32, double *v64, double *Eout, int *flip_out, int *near_out)
 {
     float sf[ORC_STACK];
@@ -362,13 +468,13 @@ static void row_analysis(const uint32_t *nodes, int64_t len, const float *c,
                 if (af == 0.0f && ad == 0.0 && neg_bit(bf) != neg_bit(bd)) flip = 1;
                 if (bd < 0.0 && fabs(ad) <= ea) near = 1;
                 if (ea == 0.0 && eb == 0.0) {
-                    se[h] = u * fabs(sd[h]);
+                    se[h] = fn_bound(O_ATAN2, xm, 0.0, sd[h], u, rf);
                 } else {
                     double ra = fmax(fabs(ad) - ea, 0.0), rb = fmax(fabs(bd) - eb, 0.0);
                     double r2 = ra * ra + rb * rb;
                     if (!(r2 > 0.0)) { near = 1; se[h] = INFINITY; }
-                    else se[h] = lib_bound((mul0(fabs(bd) + eb, ea) + mul0(fabs(ad) + ea, eb)) / r2,
-                                           sd[h], u);
+                    else se[h] = fn_bound(O_ATAN2, xm, (mul0(fabs(bd) + eb, ea) + mul0(fabs(ad) + ea, eb)) / r2,
+                                          sd[h], u, rf);
                 }
             } else if (op == O_ADD || op == O_SUB) {
                 se[h] = ea + eb;
@@ -403,7 +509,7 @@ static void row_analysis(const uint32_t *nodes, int64_t len, const float *c,
                     se[h] = ea == 0.0 ? 0.0 : (m > 0.0 ? ea / (m * m) : INFINITY);
                     se[h] += round_flip(sd[h], se[h], 1, rf);
                 } else {
-                    se[h] = lib_bound(ea == 0.0 ? 0.0 : ea * sup_deriv(O_LOG, ad, ea), sd[h], u);
+                    se[h] = fn_bound(O_LOG, xm, ea == 0.0 ? 0.0 : ea * sup_deriv(O_LOG, ad, ea), sd[h], u, rf);
                 }
                 break;
             case O_SQRT: {
@@ -422,11 +528,11 @@ static void row_analysis(const uint32_t *nodes, int64_t len, const float *c,
                 break;
             case O_CBRT: {
                 double D = ea == 0.0 ? 0.0 : fmin(ea * sup_deriv(O_CBRT, ad, ea), 1.5874010519681994 * cbrt(ea));
-                se[h] = lib_bound(D, sd[h], u);
+                se[h] = fn_bound(O_CBRT, xm, D, sd[h], u, rf);
                 break;
             }
             default:   /* sin, cos, tan, exp, tanh, atan */
-                se[h] = lib_bound(ea == 0.0 ? 0.0 : ea * sup_deriv(op, ad, ea), sd[h], u);
+                se[h] = fn_bound(op, xm, ea == 0.0 ? 0.0 : ea * sup_deriv(op, ad, ea), sd[h], u, rf);
                 break;
             }
             h++;
@@ -482,7 +588,7 @@ void orc_evaluate_pairs(const uint32_t *nodes, const int64_t *prog_off,
                         const float *consts, const int64_t *const_off,
                         const float *X, int64_t ld,
                         const int32_t *prog, const int64_t *row, int64_t n_pairs, double u, double rf,
-                        float *out32, double *out64, double *ebound, uint8_t *flags, int n_threads)
+                        uint32_t exact_mask, float *out32, double *out64, double *ebound, uint8_t *flags, int n_threads)
 {
     (void)n_threads;
 #pragma omp parallel for schedule(static) num_threads(n_threads > 0 ? n_threads : 1)
@@ -492,7 +598,8 @@ void orc_evaluate_pairs(const uint32_t *nodes, const int64_t *prog_off,
         int64_t len = prog_off[p + 1] - prog_off[p];
         const float *pc = consts + const_off[p];
         int flip, near;
-        row_analysis(pn, len, pc, X, ld, row[i], u, rf, &out32[i], &out64[i], &ebound[i], &flip, &near);
+        row_analysis(pn, len, pc, X, ld, row[i], u, rf, exact_mask, &out32[i], &out64[i], &ebound[i], &flip,
+                     &near);
         flags[i] = (uint8_t)(flip | (near << 1));
     }
 }
@@ -811,8 +918,8 @@ void orc_fitness(const uint32_t *nodes, const int64_t *prog_off,
                  const float *consts, const int64_t *const_off, int32_t n_programs,
                  const float *X, int64_t ld, int64_t n_rows,
                  const float *y, const float *w, int32_t metric,
-                 double *fit_f32path, double *fit_f64, double u, double rf, double *fbound,
-                 int32_t *fnear, int n_threads)
+                 double *fit_f32path, double *fit_f64, double u, double rf, uint32_t exact_mask,
+                 double *fbound, int32_t *fnear, int n_threads)
 {
     (void)n_threads;
 #pragma omp parallel num_threads(n_threads > 0 ? n_threads : 1)
@@ -830,7 +937,8 @@ void orc_fitness(const uint32_t *nodes, const int64_t *prog_off,
             if (fbound) {
                 for (int64_t r = 0; r < n_rows; ++r) {
                     int flip, near;
-                    row_analysis(pn, len, pc, X, ld, r, u, rf, &yh32[r], &yh64[r], &E[r], &flip, &near);
+                    row_analysis(pn, len, pc, X, ld, r, u, rf, exact_mask, &yh32[r], &yh64[r], &E[r], &flip,
+                                 &near);
                     nnear += near;
                 }
             } else {
