@@ -89,7 +89,7 @@ def lib():
                                            i32, u64, P, i64, P, P, i64, P, P, P, P]
         L.orc_build_population.restype = ctypes.c_int
         L.orc_grad_consts.argtypes = [P, P, P, P, i32, P, i64, i64, P, P, i32, P, P, P,
-                                      ctypes.c_double, u64, ctypes.c_int]
+                                      ctypes.c_double, u64, ctypes.c_int, ctypes.c_int]
         L.orc_plan_generation.argtypes = [f32, f32, f32, f32, u64, i32, u64, P, P, P]
         L.orc_plan_generation.restype = ctypes.c_int
         L.orc_mutate.argtypes = [f32, f32, f32, f32, f32, i32, u64,
@@ -308,12 +308,15 @@ def build_population(n_programs, n_features, method="rhh", min_depth=2, max_dept
 
 
 def grad_consts(pop: Population, X, y, w=None, metric="mse", gscale=None, n_threads=None,
-                mc_u=0.0, mc_seed=0):
+                mc_u=0.0, mc_seed=0, f32_tape=False):
     """(d fitness / d consts for every constant, fitness) in float64.
 
     mc_u > 0 perturbs every operation's result by a relative +-mc_u (Monte
     Carlo arithmetic, signs from SplitMix64 keyed by mc_seed): the spread of
-    the results over a few seeds estimates their float32 conditioning."""
+    the results over a few seeds estimates their float32 conditioning.
+    f32_tape=True takes the derivative at the float32 evaluation (its
+    values and protected branches), the partials still in float64; with
+    mc_u > 0 only the reverse sweep is then perturbed."""
     X, N = _ds(X)
     y = np.ascontiguousarray(y, dtype=np.float32)
     w = None if w is None else np.ascontiguousarray(w, dtype=np.float32)
@@ -323,7 +326,7 @@ def grad_consts(pop: Population, X, y, w=None, metric="mse", gscale=None, n_thre
     fit = np.zeros(pop.n_programs, np.float64)
     lib().orc_grad_consts(_p(pop.nodes), _p(pop.prog_off), _p(pop.consts), _p(pop.const_off),
                           pop.n_programs, _p(X), N, N, _p(y), _p(w), m, _p(gs), _p(g), _p(fit),
-                          float(mc_u), int(mc_seed), _threads(n_threads))
+                          float(mc_u), int(mc_seed), 1 if f32_tape else 0, _threads(n_threads))
     return g[:pop.consts.shape[0]], fit
 
 

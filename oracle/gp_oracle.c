@@ -1309,6 +1309,11 @@ int orc_build_population(int32_t n_programs, int32_t n_features, int32_t method,
 /* Seeds: MSE 2w(yh-y)/W; MAE w sign(yh-y)/W; RMSE dMSE/(2 RMSE) (0 if RMSE   */
 /* is 0); logistic w(sigmoid(yh)-y)/W; Pearson d|r|/dyh.                      */
 /* grad[const_off[p] + s] receives gscale[p] * d fitness_p / d c_s.           */
+/* With f32_tape the forward pass is the float32 evaluation and the sweep     */
+/* takes its partials, in float64, at those float32 values: the derivative    */
+/* of the float32 program, whose protected branches and values are the ones   */
+/* a float32 evaluation takes (reading; with mc_u > 0 only the sweep's        */
+/* partials and seed are perturbed then).                                     */
 /* Programs longer than 4096 nodes get NaN fitness and derivatives.          */
 /* ------------------------------------------------------------------------ */
 static double local_partial(int op, int which, double a, double b, double out)
@@ -1370,10 +1375,13 @@ static double mc_factor(double u, uint64_t seed, int64_t r, int64_t i, int role)
     return (z >> 63) ? 1.0 - u : 1.0 + u;
 }
 
-/* float64 forward pass of one row keeping every node's value val[i] and the  */
-/* end (one past) of its subtree endi[i]; returns the program value.          */
+/* Forward pass of one row keeping every node's value val[i] and the end     */
+/* (one past) of its subtree endi[i]; returns the program value.  In float64, */
+/* or, with f32 set, the float32 evaluation (each node's float32 value,       */
+/* widened: the point at which a float32 program's derivative is taken);      */
+/* Monte Carlo perturbation applies to the float64 pass only.                 */
 static double forward_row(const uint32_t *pn, int64_t L, const float *pc, const float *X,
-                          int64_t ld, int64_t r, double u, uint64_t seed,
+                          int64_t ld, int64_t r, double u, uint64_t seed, int f32,
                           double *val, int64_t *endi)
 {
     double st[ORC_STACK];
@@ -1388,12 +1396,12 @@ static double forward_row(const uint32_t *pn, int64_t L, const float *pc, const 
             endi[i] = i + 1;
         } else if (ar == 1) {
             double a = st[--h];
-            v = op_f64(op, a, 0.0) * mc_factor(u, seed, r, i, 0);
+            v = f32 ? (double)op_f32(op, (float)a, 0.0f) : op_f64(op, a, 0.0) * mc_factor(u, seed, r, i, 0);
             endi[i] = endi[i + 1];
         } else {
             double a = st[--h];
             double b = st[--h];
-            v = op_f64(op, a, b) * mc_factor(u, seed, r, i, 0);
+            v = f32 ? (double)op_f32(op, (float)a, (float)b) : op_f64(op, a, b) * mc_factor(u, seed, r, i, 0);
             endi[i] = endi[endi[i + 1]];
         }
         val[i] = v;
@@ -1409,7 +1417,7 @@ void orc_grad_consts(const uint32_t *nodes, const int64_t *prog_off,
                      const float *X, int64_t ld, int64_t n_rows,
                      const float *y, const float *w, int32_t metric,
                      const double *gscale, double *grad, double *fit_out,
-                     double mc_u, uint64_t mc_seed, int n_threads)
+                     double mc_u, uint64_t mc_seed, int f32_tape, int n_threads)
 {
 #pragma omp parallel num_threads(n_threads > 0 ? n_threads : 1)
     {
@@ -1433,8 +1441,9 @@ void orc_grad_consts(const uint32_t *nodes, const int64_t *prog_off,
             /* forward pass for the metric's global statistics */
             double W = 0.0, S = 0.0;
             for (int64_t r = 0; r < n_rows; ++r)
-                yh[r] = mc_u == 0.0 ? eval_row_f64(pn, L, pc, X, ld, r)
-                                    : forward_row(pn, L, pc, X, ld, r, mc_u, mc_seed, val, endi);
+                yh[r] = f32_tape ? (double)eval_row_f32(pn, L, pc, X, ld, r)
+                        : mc_u == 0.0 ? eval_row_f64(pn, L, pc, X, ld, r)
+                                      : forward_row(pn, L, pc, X, ld, r, mc_u, mc_seed, 0, val, endi);
             double ma = 0.0, mb = 0.0, va = 0.0, vb = 0.0, cab = 0.0, rr = 0.0;
             for (int64_t r = 0; r < n_rows; ++r) {
                 double wr = w ? (double)w[r] : 1.0;
@@ -1483,7 +1492,7 @@ void orc_grad_consts(const uint32_t *nodes, const int64_t *prog_off,
                 }
                 }
                 seed *= gs * mc_factor(mc_u, mc_seed, r, 0, 3);
-                forward_row(pn, L, pc, X, ld, r, mc_u, mc_seed, val, endi);
+                forward_row(pn, L, pc, X, ld, r, mc_u, mc_seed, f32_tape, val, endi);
                 for (int64_t i = 0; i < L; ++i) adj[i] = 0.0;
                 adj[0] = seed;
                 for (int64_t i = 0; i < L; ++i) {

@@ -192,3 +192,82 @@ def test_reverse_mode_matches_central_differences_wider_set(fmask, seed):
     assert checked >= 12
     print(f"checked {checked}, agree {agree}")
     assert agree >= 0.8 * checked, (agree, checked)
+
+
+# ---- the float32-tape mode: derivatives taken at the float32 evaluation ----
+
+def test_f32_tape_equals_float64_when_float32_is_exact():
+    """Small-integer data and constants keep every float32 sum and product
+    exact, so the float32 and float64 evaluations coincide and the two modes
+    must give the same derivatives bit for bit."""
+    rng = np.random.default_rng(7)
+    n = 500
+    X = rng.integers(-3, 4, size=(3, n)).astype(np.float32)
+    y = rng.integers(-20, 21, size=n).astype(np.float32)
+    progs = []
+    for _ in range(60):
+        # a random expression tree over add/sub/mul with <= 6 leaves
+        def tree(d):
+            if d == 0 or rng.random() < 0.3:
+                if rng.random() < 0.5:
+                    return [node(VAR, int(rng.integers(0, 3)))]
+                return [node(CONST, -1)]
+            op = [oracle.ADD, oracle.SUB, oracle.MUL][int(rng.integers(0, 3))]
+            return [node(op)] + tree(d - 1) + tree(d - 1)
+        nodes = tree(3)
+        k = 0
+        consts = []
+        for i, w in enumerate(nodes):
+            if (w & 0xFF) == CONST:
+                nodes[i] = node(CONST, k)
+                consts.append(float(rng.integers(-2, 3)))
+                k += 1
+        progs.append((nodes, consts))
+    pop = oracle.from_programs(progs)
+    for metric in ("mse", "mae", "pearson"):
+        g64, f64 = oracle.grad_consts(pop, X, y, None, metric)
+        g32, f32 = oracle.grad_consts(pop, X, y, None, metric, f32_tape=True)
+        assert np.array_equal(g64, g32), metric
+        assert np.array_equal(f64, f32), metric
+
+
+def test_f32_tape_closed_form_with_rounding():
+    """mul(c, x0) against y = 2 x0: the derivative at the float32 evaluation
+    is 2 mean((fl32(c x0) - y) x0), with the rounded products."""
+    rng = np.random.default_rng(8)
+    n = 5000
+    x = rng.uniform(-3, 3, size=n).astype(np.float32)
+    y = (2.0 * x).astype(np.float32)
+    c = np.float32(0.7)
+    pop = oracle.from_programs([([node(MUL), node(CONST, 0), node(VAR, 0)], [c])])
+    g, f = oracle.grad_consts(pop, x[None, :], y, None, "mse", f32_tape=True)
+    yh = (c * x).astype(np.float64)          # float32 products
+    d = yh - y.astype(np.float64)
+    assert abs(f[0] - np.mean(d * d)) <= 1e-12 * np.mean(d * d)
+    expect = np.mean(2.0 * d * x.astype(np.float64))
+    assert abs(g[0] - expect) <= 1e-12 * abs(expect)
+
+
+def test_f32_tape_follows_float32_protected_branch():
+    """x0 / (x1 * c): rows where the float32 product rounds to |p| <= 0.001
+    while the exact product exceeds it take the protected arm (value 1,
+    derivative 0) in the float32 evaluation, the division in float64."""
+    thr = np.float32(0.001)
+    # c one float above 1: for x1 just below 0.001 the exact product x1 c
+    # can exceed 0.001 while its float32 rounding does not
+    c = np.nextafter(np.float32(1.0), np.float32(2.0))
+    cand = np.nextafter(thr, np.float32(0.0)) - np.arange(0, 64, dtype=np.float32) * np.float32(1e-12)
+    cand = cand.astype(np.float32)
+    prod32 = (cand * c).astype(np.float32)
+    prod64 = cand.astype(np.float64) * np.float64(c)
+    hit = np.nonzero((np.abs(prod32) <= thr) & (np.abs(prod64) > np.float64(thr)))[0]
+    assert hit.size > 0
+    x1 = cand[hit[:1]]
+    X = np.ascontiguousarray(np.stack([np.float32([2.0]), x1]))
+    y = np.float32([0.0])
+    pop = oracle.from_programs([([node(oracle.DIV), node(VAR, 0), node(MUL), node(VAR, 1), node(CONST, 0)],
+                                 [c])])
+    g32, f32 = oracle.grad_consts(pop, X, y, None, "mse", f32_tape=True)
+    g64, f64 = oracle.grad_consts(pop, X, y, None, "mse")
+    assert g32[0] == 0.0 and f32[0] == 1.0      # protected arm: value 1, no dependence on c
+    assert g64[0] != 0.0                        # the float64 evaluation divides
