@@ -1,0 +1,149 @@
+// crmath_check.cpp -- runs every float through gp_crmath.h's sin, cos and
+// log (compiled for the host) and compares each result with the correctly
+// rounded value decided from the C library: the double result of sin / cos /
+// log (error below one double ulp) decides the rounding unless it lies within
+// 8 double ulps of a float rounding boundary; then the extended-precision
+// (long double) result decides, unless it too lies within 8 of its ulps of
+// the boundary, and the input is printed as "undecided" for a
+// higher-precision check.
+//
+// Output, one line per finding:
+//   <op> <bits of x> <bits of the correctly rounded result>   an input the
+//        double evaluation rounds wrongly (an exception-table entry)
+//   unflagged <op> <bits>   such an input whose double result did not lie
+//        near a rounding boundary: the error bound is wrong (never expected)
+//   undecided <op> <bits>   the reference could not decide
+// and a summary per function.
+//
+// Build and run (host only):
+//   g++ -O2 -std=c++17 -ffp-contract=off -fopenmp -o crmath_check crmath_check.cpp
+//   ./crmath_check [sin|cos|log|all [stride]] > findings.txt
+// Entries of the form "<op> <bits> <bits>" are the exception tables that
+// gen_crmath_tables.py writes into gp_crmath_tables.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+#include "gp_crmath.h"
+
+namespace {
+
+// Correctly rounded float of the exact value, decided from double v (error
+// below 1 ulp) or long double w; returns false when neither can decide.
+bool decide(double v, long double w, float* out) {
+    float f = static_cast<float>(v);
+    // distance of v from the nearest float rounding boundary in double ulps
+    uint64_t b;
+    std::memcpy(&b, &v, 8);
+    const long long lo = static_cast<long long>(b & 0x1FFFFFFFull) - 0x10000000ll;
+    if (lo > 8 || lo < -8) {
+        *out = f;
+        return true;
+    }
+    // the extended result: 64-bit significand, boundary at bit 39 below the top
+    const float g = static_cast<float>(w);
+    const long double gd = static_cast<long double>(g);
+    // neighbouring floats of g and the two boundaries around it
+    const float up = std::nextafter(g, INFINITY), dn = std::nextafter(g, -INFINITY);
+    const long double mu = (gd + static_cast<long double>(up)) / 2, md = (gd + static_cast<long double>(dn)) / 2;
+    const long double ulp = std::fabs(w) * 0x1p-63L;
+    if (std::fabs(w - mu) <= 8 * ulp || std::fabs(w - md) <= 8 * ulp) return false;
+    *out = g;
+    return true;
+}
+
+struct Count {
+    long long n = 0, flagged = 0, wrong = 0, unflagged = 0, undecided = 0;
+};
+
+long long g_stride = 1;   // every g_stride-th input (1: all of them)
+
+template <typename Dev, typename Ref, typename RefL>
+Count run(const char* name, uint32_t lo, uint32_t hi, Dev dev, Ref ref, RefL refl, bool (*flag)(float)) {
+    Count total;
+#pragma omp parallel
+    {
+        Count c;
+#pragma omp for schedule(dynamic, 1 << 16)
+        for (long long ub = lo; ub <= static_cast<long long>(hi); ub += g_stride) {
+            float x;
+            const uint32_t u = static_cast<uint32_t>(ub);
+            std::memcpy(&x, &u, 4);
+            ++c.n;
+            const float got = dev(x);
+            const bool fl = flag(x);
+            if (fl) ++c.flagged;
+            float want;
+            if (!decide(ref(static_cast<double>(x)), refl(static_cast<long double>(x)), &want)) {
+                ++c.undecided;
+#pragma omp critical
+                std::printf("undecided %s 0x%08x\n", name, u);
+                continue;
+            }
+            uint32_t gb, wb;
+            std::memcpy(&gb, &got, 4);
+            std::memcpy(&wb, &want, 4);
+            if (gb != wb) {
+                ++c.wrong;
+                if (!fl) ++c.unflagged;
+#pragma omp critical
+                {
+                    if (fl)
+                        std::printf("%s 0x%08x 0x%08x\n", name, u, wb);
+                    else
+                        std::printf("unflagged %s 0x%08x got 0x%08x want 0x%08x\n", name, u, gb, wb);
+                }
+            }
+        }
+#pragma omp critical
+        {
+            total.n += c.n;
+            total.flagged += c.flagged;
+            total.wrong += c.wrong;
+            total.unflagged += c.unflagged;
+            total.undecided += c.undecided;
+        }
+    }
+    std::fprintf(stderr, "%s: %lld inputs, %lld near a boundary, %lld differ from the reference (%lld unflagged), "
+                 "%lld undecided\n", name, total.n, total.flagged, total.wrong, total.unflagged, total.undecided);
+    std::printf("summary %s %lld %lld %lld %lld %lld\n", name, total.n, total.flagged, total.wrong, total.unflagged,
+                total.undecided);
+    return total;
+}
+
+// whether the double result of an input lies near a rounding boundary
+bool flag_sincos(float x, bool is_cos) {
+    const float ax = std::fabs(x);
+    if (ax < 0x1p-12f) return false;
+    uint32_t ub;
+    std::memcpy(&ub, &ax, 4);
+    const double y = ax < 0x1p+20f ? gp::crm::sincos_small(ax, is_cos, gp::crm::kSinCosTab)
+                                   : gp::crm::sincos_large(ub, is_cos, gp::crm::kSinCosTab);
+    return gp::crm::near_boundary(y);
+}
+bool flag_sin(float x) { return flag_sincos(x, false); }
+bool flag_cos(float x) { return flag_sincos(x, true); }
+bool flag_log(float x) { return gp::crm::near_boundary(gp::crm::log_double(x)); }
+
+}  // namespace
+
+int main(int argc, char** argv) {
+    const char* which = argc > 1 ? argv[1] : "all";
+    if (argc > 2) g_stride = std::max(1LL, std::atoll(argv[2]));
+    const uint32_t fin = 0x7F7FFFFFu;   // largest finite float
+    float t = 0.001f;
+    uint32_t logs;
+    std::memcpy(&logs, &t, 4);
+    if (!std::strcmp(which, "all") || !std::strcmp(which, "sin"))
+        run("sin", 0u, fin, [](float x) { return gp::crm::sin_cr(x); }, [](double x) { return std::sin(x); },
+            [](long double x) { return sinl(x); }, flag_sin);
+    if (!std::strcmp(which, "all") || !std::strcmp(which, "cos"))
+        run("cos", 0u, fin, [](float x) { return gp::crm::cos_cr(x); }, [](double x) { return std::cos(x); },
+            [](long double x) { return cosl(x); }, flag_cos);
+    if (!std::strcmp(which, "all") || !std::strcmp(which, "log"))
+        run("log", logs + 1, fin, [](float x) { return gp::crm::log_cr(x); }, [](double x) { return std::log(x); },
+            [](long double x) { return logl(x); }, flag_log);
+    return 0;
+}

@@ -1,0 +1,253 @@
+// gp_crmath.h -- correctly rounded float32 sin, cos and log for the
+// evaluation kernels.
+//
+// The function set of Sec. III-D1 names sin, cos and log but no library; a
+// float32 evaluation that rounds each function's exact value once, to
+// nearest (ties to even), as IEEE arithmetic does for +, -, *, / and sqrt,
+// makes a program's float32 value independent of which library computed it.
+// With these three, every function of the benchmark set {add, sub, mul,
+// protected div, neg, protected log, protected sqrt, sin, cos} is correctly
+// rounded, so a program's output is one fixed float32 number per row.
+//
+// Method (each function): the float argument is widened to double (exact),
+// the function is evaluated in double with a relative error below 2^-50,
+// and the result is rounded to float.  That rounding is the correctly
+// rounded one unless the double result lies within the error bound of a
+// float rounding boundary (the midpoint of two neighbouring floats); there,
+// and only there, an exception table holds the inputs whose double result
+// falls on the wrong side (found by running every float through these
+// functions against an independent reference, crmath_check.cpp).
+//
+//   sin, cos: |x| = k (pi/32) + r, |r| <= pi/64: for |x| < 2^20 by a
+//     three-part Cody-Waite reduction whose first two products are exact;
+//     beyond, by Payne-Hanek: the 24-bit mantissa times a 160-bit window of
+//     the binary digits of 2/pi, in 32-bit integer limbs.  Then sin x =
+//     S cos r + C sin r with S, C the sine and cosine of (k mod 64) pi/32
+//     from a table (cos x takes k + 16), sin r and cos r by short Taylor
+//     polynomials.
+//   log: a = 2^e m, m in [1, 2); c = 1/(bucket centre of m) from a 128-entry
+//     table (c has 24 bits, so m c - 1 is exact); log a = E ln 2 - log c' +
+//     log1p(m c - 1) with log1p to r^9 (|m c - 1| <= 2^-7) and the table's
+//     -log c' and ln 2 carried as double + remainder.
+// The code is host- and device-compilable so that the exhaustive checker can
+// run the very same functions on the CPU.  The tables are taken by pointer:
+// the evaluation kernels stage them in LDS.
+#pragma once
+
+#include <cstdint>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define GP_CRF __host__ __device__ __forceinline__
+#define GP_CRTAB __device__ static constexpr
+#else
+#include <cmath>
+#define GP_CRF inline
+#define GP_CRTAB static constexpr
+#endif
+
+#include "gp_crmath_tables.h"
+
+namespace gp {
+namespace crm {
+
+// A constant handed to a double FMA through a scalar register pair: it is
+// then an operand of v_fma_f64 itself, instead of a vector register pair
+// the compiler would fill with two moves per use or keep occupied for the
+// whole kernel.
+#if defined(__HIP_DEVICE_COMPILE__)
+__device__ __forceinline__ double kreg(double c) {
+    asm volatile("" : "+s"(c));
+    return c;
+}
+#else
+inline double kreg(double c) { return c; }
+#endif
+
+GP_CRF uint64_t dbits(double v) {
+    uint64_t u;
+    __builtin_memcpy(&u, &v, sizeof u);
+    return u;
+}
+GP_CRF uint32_t fbits(float v) {
+    uint32_t u;
+    __builtin_memcpy(&u, &v, sizeof u);
+    return u;
+}
+GP_CRF float bitsf(uint32_t u) {
+    float v;
+    __builtin_memcpy(&v, &u, sizeof v);
+    return v;
+}
+
+// Rounding the double y to float can differ from rounding the exact value
+// only if y lies within its error bound of a float rounding boundary: the
+// 29 bits below float precision within kHardUlps double ulps of one half.
+// (The error bound 2^-50 |y| is at most 2^3 double ulps of y; 16 doubles it.)
+constexpr uint32_t kHardUlps = 16;
+GP_CRF bool near_boundary(double y) {
+    const uint32_t lo = static_cast<uint32_t>(dbits(y)) & 0x1FFFFFFFu;
+    return lo - (0x10000000u - kHardUlps) <= 2u * kHardUlps;
+}
+
+// The correctly rounded result of an input the exception table lists, else
+// the rounding f of the double result.
+template <int N>
+GP_CRF float exception(const uint32_t (&tab)[N][2], int n, uint32_t key, float f) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("");   // keeps the search behind its (rarely taken) branch
+#endif
+    for (int i = 0; i < n; ++i)
+        if (tab[i][0] == key) return bitsf(tab[i][1]);
+    return f;
+}
+
+// ---- sin, cos ----
+// |x| = k (pi/32) + r, |r| <= pi/64; with j = k mod 64 (plus 16 for cos,
+// cos x = sin(x + pi/2)), sin x = S_j cos r + C_j sin r for S_j, C_j the
+// sine and cosine of j pi/32 from a table, cos r and sin r by their Taylor
+// polynomials through r^8 and r^9 (truncation below 2^-64 relative).
+constexpr double kInvPi32 = 0x1.45f306dc9c883p+3;   // 32/pi
+// pi/32 = kPi32a + kPi32b + kPi32c + O(2^-118): a and b carry 29 bits each,
+// so k * a and k * b are exact for k < 2^24 (|x| < 2^20)
+constexpr double kPi32a = 0x1.921fb54000000p-4;
+constexpr double kPi32b = 0x1.10b4611000000p-34;
+constexpr double kPi32c = 0x1.4c4c6628b80dcp-63;
+constexpr double kPi32 = 0x1.921fb54442d18p-4;
+// (-1)^n / (2n+1)! and (-1)^n / (2n)!
+constexpr double kS3 = -0x1.5555555555555p-3, kS5 = 0x1.1111111111111p-7, kS7 = -0x1.a01a01a01a01ap-13,
+                 kS9 = 0x1.71de3a556c734p-19;
+constexpr double kC4 = 0x1.5555555555555p-5, kC6 = -0x1.6c16c16c16c17p-10, kC8 = 0x1.a01a01a01a01ap-16;
+
+// sin(j pi/32 + r) for |r| <= pi/64 (slightly more after rounding of k)
+GP_CRF double sin_from_table(const SinCosEntry& e, double r) {
+    const double r2 = r * r;
+    const double sp = fma(fma(fma(kreg(kS9), r2, kreg(kS7)), r2, kreg(kS5)), r2, kreg(kS3));
+    const double cp = fma(fma(fma(kreg(kC8), r2, kreg(kC6)), r2, kreg(kC4)), r2, -0.5);
+    const double cm1 = r2 * cp;                  // cos r - 1
+    const double sr = fma(r * r2, sp, r);        // sin r
+    return fma(e.s, cm1, fma(e.c, sr, e.s));
+}
+
+// |x| < 2^20: k and r by a three-part Cody-Waite reduction
+GP_CRF double sincos_small(double ax, bool is_cos, const SinCosEntry* tab) {
+    const double k = rint(ax * kreg(kInvPi32));
+    double r = fma(-k, kreg(kPi32a), ax);
+    r = fma(-k, kreg(kPi32b), r);
+    r = fma(-k, kreg(kPi32c), r);
+    const int j = (static_cast<int>(k) + (is_cos ? 16 : 0)) & 63;   // 0 <= k < 2^24
+    return sin_from_table(tab[j], r);
+}
+
+// The binary digits of 2/pi in 32-bit words, after one word of zeros (the
+// word index of digit p >= 1, weight 2^-p, is (p + 31) / 32).
+GP_CRTAB uint32_t kTwoOverPi[13] = {0u,          0xa2f9836eu, 0x4e441529u, 0xfc2757d1u, 0xf534ddc0u,
+                                   0xdb629599u, 0x3c439041u, 0xfe5163abu, 0xdebbc561u, 0xb7246e3au,
+                                   0x424dd2e0u, 0x06492eeau, 0x09d1921cu};
+
+// Payne-Hanek for |x| = M 2^E >= 2^20 (ub: the float bits of |x|).  Digits
+// of 2/pi of weight 2^(E-p) >= 4 multiply the integer M into multiples of 4
+// and are dropped: the window is digits p = E-1 .. E+158 (160 bits), so
+// Z = M * window * 2^-158 = |x| 2/pi mod 4 carries 158 fraction bits and an
+// error below 2^-134.  16 Z = |x| 32/pi mod 64: k is its nearest integer
+// (bits 154 up, after adding 2^153) and r = (16 Z - k) pi/32.
+GP_CRF double sincos_large(uint32_t ub, bool is_cos, const SinCosEntry* tab) {
+    const uint32_t M = (ub & 0x7FFFFFu) | 0x800000u;
+    const int E = static_cast<int>(ub >> 23) - 150;
+    const int p0 = E - 1;
+    const int k0 = (p0 + 31) >> 5;
+    const int s = (p0 + 31) & 31;
+    uint32_t z[5];
+    uint64_t c = 0;
+    for (int j = 4; j >= 0; --j) {
+        const uint32_t w = s ? (kTwoOverPi[k0 + j] << s) | (kTwoOverPi[k0 + j + 1] >> (32 - s))
+                             : kTwoOverPi[k0 + j];
+        const uint64_t t = static_cast<uint64_t>(M) * w + c;
+        z[j] = static_cast<uint32_t>(t);
+        c = t >> 32;
+    }
+    // bit 153 of Z is bit 25 of z[0]; k = bits 154..159
+    z[0] += 0x2000000u;
+    const int k = static_cast<int>(z[0] >> 26);
+    const int j = (k + (is_cos ? 16 : 0)) & 63;
+    // D = (bits 0..153) - 2^153: signed, 154 fraction bits of 16 Z
+    const int64_t top = static_cast<int64_t>(z[0] & 0x3FFFFFFu) - 0x2000000ll;
+    const bool dneg = top < 0;
+    uint32_t d[5] = {static_cast<uint32_t>(top), z[1], z[2], z[3], z[4]};
+    if (dneg) {   // |D|: two's complement negation across the limbs
+        uint64_t b = 1;
+        for (int i = 4; i >= 0; --i) {
+            const uint64_t t = static_cast<uint64_t>(~d[i]) + b;
+            d[i] = static_cast<uint32_t>(t);
+            b = t >> 32;
+        }
+    }
+    // normalise |D| to 64 significant bits
+    int j0 = 0;
+    while (j0 < 2 && d[j0] == 0u) ++j0;
+    const int l = __builtin_clz(d[j0] | 1u);   // (d[j0] != 0 for every float input)
+    uint64_t hi = (static_cast<uint64_t>(d[j0]) << 32) | d[j0 + 1];
+    if (l) hi = (hi << l) | (d[j0 + 2] >> (32 - l));
+    double D = ldexp(static_cast<double>(hi), 160 - 64 - 154 - 32 * j0 - l);
+    if (dneg) D = -D;
+    return sin_from_table(tab[j], D * kPi32);
+}
+
+// Correctly rounded sin (is_cos false) or cos of a float.
+GP_CRF float sincos_cr(float x, bool is_cos, const SinCosEntry* tab) {
+    const float ax = fabsf(x);
+    if (!(ax <= 0x1.fffffep+127f)) return x - x;   // NaN for +-inf and NaN
+    if (ax < 0x1p-12f) return is_cos ? 1.0f : x;   // sin x rounds to x, cos x to 1
+    const uint32_t ub = fbits(ax);
+    const double y = ax < 0x1p+20f ? sincos_small(static_cast<double>(ax), is_cos, tab)
+                                   : sincos_large(ub, is_cos, tab);
+    float f = static_cast<float>(y);   // the result for |x|
+    if (near_boundary(y)) f = is_cos ? exception(kCosExc, kCosExcN, ub, f) : exception(kSinExc, kSinExcN, ub, f);
+    return (!is_cos && x < 0.0f) ? -f : f;
+}
+
+GP_CRF float sin_cr(float x, const SinCosEntry* tab = kSinCosTab) { return sincos_cr(x, false, tab); }
+GP_CRF float cos_cr(float x, const SinCosEntry* tab = kSinCosTab) { return sincos_cr(x, true, tab); }
+
+// ---- log ----
+constexpr double kLn2hi = 0x1.62e42fefa3900p-1;   // 45 bits: E * kLn2hi is exact
+constexpr double kLn2lo = 0x1.de6af278ece60p-46;
+// (-1)^(k+1) / k, k = 2..9
+constexpr double kL3 = 0x1.5555555555555p-2, kL4 = -0x1.0000000000000p-2,
+                 kL5 = 0x1.999999999999ap-3, kL6 = -0x1.5555555555555p-3, kL7 = 0x1.2492492492492p-3,
+                 kL8 = -0x1.0000000000000p-3, kL9 = 0x1.c71c71c71c71cp-4;
+
+// log a for a normal positive finite float, in double.
+GP_CRF double log_double(float a, const LogEntry* tab = kLogTab) {
+    const uint32_t u = fbits(a);
+    const int i = static_cast<int>((u >> 16) & 0x7Fu);
+    const int E = static_cast<int>(u >> 23) - 127 + (i >= 53 ? 1 : 0);
+    const double m = static_cast<double>(bitsf((u & 0x7FFFFFu) | 0x3F800000u));
+    const LogEntry& t = tab[i];
+    const double r = fma(m, static_cast<double>(t.c), -1.0);   // exact
+    double p = fma(kreg(kL9), r, kreg(kL8));
+    p = fma(p, r, kreg(kL7));
+    p = fma(p, r, kreg(kL6));
+    p = fma(p, r, kreg(kL5));
+    p = fma(p, r, kreg(kL4));
+    p = fma(p, r, kreg(kL3));
+    p = fma(p, r, -0.5);
+    const double l1p = fma(r * r, p, r);
+    const double Ed = static_cast<double>(E);
+    const double hi = fma(Ed, kreg(kLn2hi), t.hi);
+    const double lo = fma(Ed, kreg(kLn2lo), static_cast<double>(t.lo) + l1p);
+    return hi + lo;
+}
+
+// Correctly rounded log of a float a > 0 that is normal or +inf (the
+// protected log only takes |a| > 0.001).
+GP_CRF float log_cr(float a, const LogEntry* tab = kLogTab) {
+    if (!(a <= 0x1.fffffep+127f)) return a;   // +inf (and NaN)
+    const double y = log_double(a, tab);
+    float f = static_cast<float>(y);
+    if (near_boundary(y)) f = exception(kLogExc, kLogExcN, fbits(a), f);
+    return f;
+}
+
+}  // namespace crm
+}  // namespace gp

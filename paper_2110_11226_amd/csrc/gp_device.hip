@@ -31,6 +31,7 @@
 #include <string>
 #include <vector>
 
+#include "gp_crmath.h"
 #include "gp_internal.h"
 
 using namespace gp;
@@ -65,8 +66,10 @@ struct DataView {
 // Compiled programs: program p's instructions are code[prog_off[p] ..
 // prog_off[p] + clen[p]) (clen[p] <= len[p]), in execution order.
 struct CodeView {
-    const uint4* code;
+    const uint4* code;     // the adjoint's format (k_compile)
     const int32_t* clen;
+    const uint4* ecode;    // the evaluation kernel's format (k_compile_eval)
+    const int32_t* eclen;
 };
 
 // Work decomposition: rows are split into n_chunks chunks of `chunk` rows
@@ -79,6 +82,7 @@ struct Sched {
     int64_t n_items;
     const int32_t* order;
     uint32_t* counter;
+    int32_t batch;     // work items claimed per atomic by the evaluation kernel
 };
 
 // ---------------------------------------------------------------------------
@@ -150,13 +154,34 @@ __device__ __forceinline__ T ldu(const T* p) {
 constexpr int kStackRegs = 15;
 constexpr int kStackLds = GP_MAX_STACK - kStackRegs;
 
+// Tables of the correctly rounded sin, cos and log (gp_crmath.h): staged in
+// LDS by the evaluation and adjoint kernels, read from global memory
+// elsewhere.
+struct MathTabs {
+    const crm::SinCosEntry* sc;
+    const crm::LogEntry* lg;
+};
+__device__ __forceinline__ MathTabs global_tabs() { return MathTabs{crm::kSinCosTab, crm::kLogTab}; }
+
+// The kernel-resident copies (one per block, filled before its first use).
+struct MathTabsLds {
+    crm::SinCosEntry sc[64];
+    crm::LogEntry lg[128];
+};
+__device__ __forceinline__ MathTabs stage_tabs(MathTabsLds& lds) {
+    for (int i = threadIdx.x; i < 64; i += blockDim.x) lds.sc[i] = crm::kSinCosTab[i];
+    for (int i = threadIdx.x; i < 128; i += blockDim.x) lds.lg[i] = crm::kLogTab[i];
+    __syncthreads();
+    return MathTabs{lds.sc, lds.lg};
+}
+
 // Protected operators (reading of Sec. III-C3's function set: the gplearn
 // convention).  Comparisons are written so that NaN takes the protected arm.
 __device__ __forceinline__ float op_div(float a, float b) {
     return fabsf(b) > GP_PROTECT_EPS ? a / b : 1.0f;
 }
-__device__ __forceinline__ float op_log(float a) {
-    return fabsf(a) > GP_PROTECT_EPS ? logf(fabsf(a)) : 0.0f;
+__device__ __forceinline__ float op_log(float a, const MathTabs& mt) {
+    return fabsf(a) > GP_PROTECT_EPS ? crm::log_cr(fabsf(a), mt.lg) : 0.0f;
 }
 __device__ __forceinline__ float op_sqrt(float a) { return sqrtf(fabsf(a)); }
 __device__ __forceinline__ float op_inv(float a) {
@@ -256,7 +281,7 @@ __device__ __forceinline__ void apply_binary(uint32_t fn, float (&a)[R], const f
 // t = f(t) for the unary function index fn (NEG, LOG, SQRT, SIN, COS, TAN
 // first, then the wider set)
 template <int R>
-__device__ __forceinline__ void apply_unary(uint32_t fn, float (&t)[R]) {
+__device__ __forceinline__ void apply_unary(uint32_t fn, float (&t)[R], const MathTabs& mt) {
     if (fn >= 6) {
         apply_unary_wide<R>(fn, t);
     } else if (fn < 3) {
@@ -265,7 +290,7 @@ __device__ __forceinline__ void apply_unary(uint32_t fn, float (&t)[R]) {
             for (int j = 0; j < R; ++j) t[j] = -t[j];
         } else if (fn == 1) {
 #pragma unroll
-            for (int j = 0; j < R; ++j) t[j] = op_log(t[j]);
+            for (int j = 0; j < R; ++j) t[j] = op_log(t[j], mt);
         } else {
 #pragma unroll
             for (int j = 0; j < R; ++j) t[j] = op_sqrt(t[j]);
@@ -273,10 +298,10 @@ __device__ __forceinline__ void apply_unary(uint32_t fn, float (&t)[R]) {
     } else {
         if (fn == 3) {
 #pragma unroll
-            for (int j = 0; j < R; ++j) t[j] = sinf(t[j]);
+            for (int j = 0; j < R; ++j) t[j] = crm::sin_cr(t[j], mt.sc);
         } else if (fn == 4) {
 #pragma unroll
-            for (int j = 0; j < R; ++j) t[j] = cosf(t[j]);
+            for (int j = 0; j < R; ++j) t[j] = crm::cos_cr(t[j], mt.sc);
         } else {
 #pragma unroll
             for (int j = 0; j < R; ++j) t[j] = tanf(t[j]);
@@ -326,7 +351,7 @@ __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint4* __restri
         if (ar == 1 && fold && h >= 1 && ((sh[top_i * kBlock] >> 30) & 1u)) {
             // unary of a constant: the pending instruction is that constant's push
             float t[1] = {shv[top_i * kBlock]};
-            apply_unary<1>(unary_index(op), t);
+            apply_unary<1>(unary_index(op), t, global_tabs());
             shv[top_i * kBlock] = t[0];
             pend.y = __float_as_uint(t[0]);
             continue;
@@ -444,6 +469,160 @@ __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint4* __restri
 }
 
 // ---------------------------------------------------------------------------
+// The evaluation kernel's instruction stream (k_compile_eval): one uint4 per
+// instruction, in execution order, each instruction's stack slots fixed by
+// the pre-pass, so the kernel keeps no stack pointer.
+//   x bits 0-7    opcode (below)
+//   x bits 8-15   slot the kernel stores the current top into before the
+//                 instruction: for a push, the slot of the entry it covers;
+//                 for every other instruction the sink slot kEvalRegs, which
+//                 is never read (one store per instruction keeps the
+//                 register array in place)
+//   x bits 16-23  slot of a binary function's second operand (kIBin)
+//   y             a constant's float bits (kIPushC, kIFoldC) or a feature
+//                 index (kIPushX, kIFoldX)
+//   z             up to 8 unary functions applied, in order, to the
+//                 instruction's result (4 bits each from the lowest: unary
+//                 index + 1; 0 ends the chain), so that a unary function
+//                 costs no dispatch of its own
+// Stack entries are numbered from the bottom; the top entry lives in
+// registers and entry e below it in slot e.  Slots from kEvalRegs on live in
+// LDS; the instructions that reach them carry kIDeep.
+// ---------------------------------------------------------------------------
+enum : uint32_t {
+    kIPushX = 0,    // push feature
+    kIPushC = 1,    // push constant
+    kIBin = 2,      // + binary index: top = top (op) slot
+    kIFoldX = 9,    // + binary index: top = feature (op) top
+    kIFoldC = 16,   // + binary index: top = constant (op) top
+    kIUn = 23,      // + unary index: top = f(top)
+    kIDeep = 64     // with kIPushX, kIPushC, kIBin: the slot lives in LDS
+};
+constexpr int kEvalSlots = GP_MAX_STACK - 1;   // entries below the top
+constexpr int kEvalRegs = 15;                  // slots held in VGPRs (plus the sink)
+constexpr int kEvalLds = kEvalSlots - kEvalRegs;
+
+__device__ __forceinline__ uint32_t ins_x(uint32_t op, uint32_t wslot, uint32_t rslot) {
+    return op | (wslot << 8) | (rslot << 16);
+}
+
+// k_compile_eval: one lane per program; the same right-to-left scan as
+// k_compile, emitting the stream above.  A terminal that is a binary
+// function's first operand is fused with it; a unary function is chained
+// onto the instruction before it; a subtree of constants only is evaluated
+// here, once, by the same float32 functions the kernel applies per row, and
+// replaced by one push of its value.
+__global__ __launch_bounds__(kBlock) void k_compile_eval(PopView pop, uint4* __restrict__ code,
+                                                          int32_t* __restrict__ clen) {
+    __shared__ uint32_t shadow[GP_MAX_STACK][kBlock];   // start | const-only << 31
+    __shared__ float shadow_v[GP_MAX_STACK][kBlock];    // value of a const-only entry
+    const int32_t p = static_cast<int32_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (p >= pop.P) return;
+    const int64_t off = pop.prog_off[p];
+    const int32_t L = pop.len[p];
+    const uint32_t* pn = pop.nodes + off;
+    const float* pc = pop.consts + pop.const_off[p];
+    uint4* out = code + off;
+    uint32_t* sh = &shadow[0][threadIdx.x];   // entry h at sh[h * kBlock]
+    float* shv = &shadow_v[0][threadIdx.x];
+    int h = 0;                                // entries on the stack
+    int32_t k = 0;                            // instructions emitted
+    int chain = 0;                            // unary functions chained on out[k-1]
+    const uint32_t sink = static_cast<uint32_t>(kEvalRegs);
+    auto clampe = [](int e) { return min(max(e, 0), GP_MAX_STACK - 1); };
+    // a push of constant v as entry e
+    auto push_c = [&](int e, float v) {
+        const uint32_t slot = static_cast<uint32_t>(max(e - 1, 0));
+        return slot >= sink ? make_uint4(ins_x(kIPushC | kIDeep, sink, slot), __float_as_uint(v), 0u, 0u)
+                            : make_uint4(ins_x(kIPushC, slot, 0u), __float_as_uint(v), 0u, 0u);
+    };
+    auto emit = [&](uint4 ins) {
+        out[k++] = ins;
+        chain = 0;
+    };
+    for (int32_t i = L - 1; i >= 0; --i) {
+        const uint32_t w = pn[i];
+        const uint32_t op = w & 0xffu;
+        const uint32_t arg = w >> 8;
+        const int ar = arity(op);
+        const int top = clampe(h - 1);
+        if (ar == 1) {
+            if (h >= 1 && (sh[top * kBlock] >> 31)) {
+                // a unary function of a constant: its push (the last
+                // instruction) takes the value
+                float t[1] = {shv[top * kBlock]};
+                apply_unary<1>(unary_index(op), t, global_tabs());
+                shv[top * kBlock] = t[0];
+                if (k >= 1) out[k - 1].y = __float_as_uint(t[0]);
+            } else if (k >= 1 && chain < 8) {
+                out[k - 1].z |= (unary_index(op) + 1u) << (4 * chain);
+                ++chain;
+            } else {
+                emit(make_uint4(ins_x(kIUn + unary_index(op), sink, 0u), 0u, 0u, 0u));
+            }
+            continue;
+        }
+        if (ar == 0) {
+            const uint32_t is_c = op == GP_OP_CONST ? 1u : 0u;
+            const uint32_t prev = i >= 1 ? (pn[i - 1] & 0xffu) : 0u;
+            if (i >= 1 && i != L - 1 && arity(prev) == 2 && h >= 1) {
+                // first operand of the binary function at i-1; the top is the second
+                const uint32_t fn = binary_index(prev);
+                const uint32_t e2 = sh[top * kBlock];
+                if (is_c && (e2 >> 31)) {
+                    float a[1] = {pc[arg]};
+                    const float b[1] = {shv[top * kBlock]};
+                    apply_binary<1>(fn, a, b);
+                    k = static_cast<int32_t>(e2 & 0x7fffffffu);   // drop the operand's instructions
+                    emit(push_c(top, a[0]));
+                    sh[top * kBlock] = static_cast<uint32_t>(k - 1) | (1u << 31);
+                    shv[top * kBlock] = a[0];
+                } else {
+                    emit(is_c ? make_uint4(ins_x(kIFoldC + fn, sink, 0u), __float_as_uint(pc[arg]), 0u, 0u)
+                              : make_uint4(ins_x(kIFoldX + fn, sink, 0u), arg, 0u, 0u));
+                    sh[top * kBlock] = e2 & 0x7fffffffu;
+                }
+                --i;
+                continue;
+            }
+            const int e = clampe(h);
+            if (is_c) {
+                emit(push_c(e, pc[arg]));
+                sh[e * kBlock] = static_cast<uint32_t>(k - 1) | (1u << 31);
+                shv[e * kBlock] = pc[arg];
+            } else {
+                const uint32_t slot = static_cast<uint32_t>(max(e - 1, 0));
+                emit(slot >= sink ? make_uint4(ins_x(kIPushX | kIDeep, sink, slot), arg, 0u, 0u)
+                                  : make_uint4(ins_x(kIPushX, slot, 0u), arg, 0u, 0u));
+                sh[e * kBlock] = static_cast<uint32_t>(k - 1);
+            }
+            ++h;
+            continue;
+        }
+        // binary, operands not fused: the first is the top (entry h-1), the
+        // second the entry below it (slot h-2)
+        const int e1 = clampe(h - 1), e2 = clampe(h - 2);
+        const uint32_t first = sh[e1 * kBlock], second = sh[e2 * kBlock];
+        const uint32_t fn = binary_index(op);
+        if ((first >> 31) && (second >> 31)) {
+            float a[1] = {shv[e1 * kBlock]};
+            const float b[1] = {shv[e2 * kBlock]};
+            apply_binary<1>(fn, a, b);
+            k = static_cast<int32_t>(second & 0x7fffffffu);
+            emit(push_c(e2, a[0]));
+            sh[e2 * kBlock] = static_cast<uint32_t>(k - 1) | (1u << 31);
+            shv[e2 * kBlock] = a[0];
+        } else {
+            const uint32_t slot = static_cast<uint32_t>(e2);
+            emit(make_uint4(ins_x(kIBin + fn | (slot >= sink ? kIDeep : 0u), sink, slot), 0u, 0u, 0u));
+            sh[e2 * kBlock] = second & 0x7fffffffu;
+        }
+        h = max(h - 1, 0);
+    }
+    clen[p] = k;
+}
+
+// ---------------------------------------------------------------------------
 // k_prepare: order programs by length (longest first) and reset the work
 // counter.  One block; counting sort over min(len, kBins-1).
 // ---------------------------------------------------------------------------
@@ -530,6 +709,12 @@ struct MetricTraits {
     static constexpr int KK = (METRIC == GP_METRIC_PEARSON) ? 4 : 1;  // doubles per partial
 };
 
+// Row-slot helpers of the evaluation kernel: the R per-row copies of a
+// register array are separate plain locals (GP_ARRAYS), indexed by a
+// wave-uniform slot.
+#define GP_ROWS(stmt)                  \
+    _Pragma("unroll") for (int j = 0; j < R; ++j) { stmt; }
+
 template <int R, int FREG, int MODE, int METRIC>
 __global__ __launch_bounds__(kBlock) void k_eval(PopView pop, CodeView cv, DataView d, Sched s,
                                                   float* __restrict__ out,
@@ -541,22 +726,30 @@ __global__ __launch_bounds__(kBlock) void k_eval(PopView pop, CodeView cv, DataV
     const int64_t N = d.N;
     const int64_t ld = d.ld;
     const float* __restrict__ X = d.X;
-    // stack entries beyond the registers: kStackLds * R * 64 floats per wavefront
-    // of the block (dynamic LDS, sized at launch for the block's wavefronts)
+    // stack slots beyond the registers: kEvalLds * R * 64 floats per
+    // wavefront of the block (dynamic LDS, sized at launch)
     extern __shared__ float ovf_all[];
-    float* ovf = ovf_all + (threadIdx.x >> 6) * (kStackLds * R * kWave);
+    float* ovf = ovf_all + (threadIdx.x >> 6) * (kEvalLds * R * kWave) + lane;
+    __shared__ MathTabsLds tabs_lds;
+    const MathTabs mt = stage_tabs(tabs_lds);
 
     for (;;) {
+        // work items: s.batch consecutive items per claim; item it covers
+        // program order[it / n_chunks] on chunk it % n_chunks (longest
+        // programs first, so the last items are the shortest)
         uint32_t it32 = 0;
-        if (lane == 0) it32 = atomicAdd(s.counter, 1u);
-        const int64_t it = static_cast<int64_t>(__builtin_amdgcn_readlane(static_cast<int>(it32), 0));
-        if (it >= s.n_items) break;   // every wavefront leaves here once the items run out
-        const int32_t c = static_cast<int32_t>(it / pop.P);
-        const int32_t k = static_cast<int32_t>(it - static_cast<int64_t>(c) * pop.P);
+        if (lane == 0) it32 = atomicAdd(s.counter, static_cast<uint32_t>(s.batch));
+        const int64_t it0 = static_cast<int64_t>(
+            static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(it32))));
+        if (it0 >= s.n_items) break;   // every wavefront leaves here once the items run out
+        const int64_t it1 = min(it0 + static_cast<int64_t>(s.batch), s.n_items);
+        for (int64_t it = it0; it < it1; ++it) {
+        const int32_t k = static_cast<int32_t>(it / s.n_chunks);
+        const int32_t c = static_cast<int32_t>(it - static_cast<int64_t>(k) * s.n_chunks);
         const int32_t p = ldu(s.order + k);
         const int64_t off = ldu(pop.prog_off + p);
-        const int32_t CL = ldu(cv.clen + p);
-        const uint4* __restrict__ pcode = cv.code + off;
+        const int32_t CL = ldu(cv.eclen + p);
+        const uint4* __restrict__ pcode = cv.ecode + off;
         const int64_t r0 = static_cast<int64_t>(c) * s.chunk;
         const int64_t r1 = min(r0 + s.chunk, N);
 
@@ -588,88 +781,87 @@ __global__ __launch_bounds__(kBlock) void k_eval(PopView pop, CodeView cv, DataV
                 }
             }
 
-            // ---- the stack machine (Sec. III-A order, compiled by k_compile) ----
-            // t[] is the top of the stack; slot `dp` (VGPRs below kStackRegs,
-            // LDS from there on) is the entry just below it.  Every instruction
-            // first writes the top into the slot above dp -- kept only when the
-            // instruction is a push, which then just advances dp -- so the
-            // register array sees exactly one indexed write per instruction and
-            // is never copied.  The first push parks the empty top in slot 0,
-            // which is never read back.  The next instruction is fetched one
-            // step ahead as a vector register and made scalar where it is used.
+            // ---- the stack machine (Sec. III-A order, compiled by k_compile_eval) ----
+            // t[] is the top entry; entry e below it is slot e (VGPRs below
+            // kEvalRegs, LDS from there on).  Each instruction first stores the
+            // top into its store slot (the sink unless it pushes), so the
+            // register array has one indexed write per instruction and is
+            // never copied; every case then updates t[] in place.  The next
+            // instruction is fetched one ahead by a vector load (in order
+            // with the others, so its wait covers only the older loads; a
+            // scalar load is waited for with every other one) and made
+            // scalar where it is used.
             float t[R];
-#pragma unroll
-            for (int j = 0; j < R; ++j) t[j] = 0.0f;
-            GP_ARRAYS(st, kStackRegs + 1);
-            int dp = -1;
+            GP_ROWS(t[j] = 0.0f);
+            GP_ARRAYS(st, kEvalRegs + 1);
             uint4 nxt = pcode[0];
             for (int q = 0; q < CL; ++q) {
                 const uint4 cur = nxt;
-                nxt = pcode[min(q + 1, CL - 1)];
-                const uint32_t w = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(cur.x)));
-                const uint32_t cls = w & 3u;
-                const uint32_t fn = (w >> 2) & 15u;
-                const int up = min(dp + 1, kStackRegs);
-                GP_PUT(st, up, t);
-                float a[R], b[R];
-                bool binary = false;
-                if (cls == kUn) {
-                    apply_unary<R>(fn, t);
-                } else if (cls == kBin) {
-                    if (dp < kStackRegs) {
-                        GP_GET(st, dp, b);
-                    } else {
-#pragma unroll
-                        for (int j = 0; j < R; ++j) b[j] = ovf[((dp - kStackRegs) * R + j) * kWave + lane];
-                    }
-                    --dp;
-#pragma unroll
-                    for (int j = 0; j < R; ++j) a[j] = t[j];
-                    binary = true;
-                } else {
-                    float v[R];
-                    if (w & kConstBit) {
-                        const float cval = __uint_as_float(cur.y);
-#pragma unroll
-                        for (int j = 0; j < R; ++j) v[j] = cval;
-                    } else if constexpr (FREG > 0) {
-                        const uint32_t arg = w >> 8;
-                        v[0] = xa0[arg];
-                        if constexpr (R > 1) v[1] = xa1[arg];
-                        if constexpr (R > 2) v[2] = xa2[arg];
-                        if constexpr (R > 3) v[3] = xa3[arg];
-                    } else {
-                        const float* __restrict__ col = X + static_cast<int64_t>(w >> 8) * ld;
-#pragma unroll
-                        for (int j = 0; j < R; ++j) v[j] = col[row[j]];
-                    }
-                    if (cls == kPush) {
-                        ++dp;
-                        if (dp >= kStackRegs) {
-#pragma unroll
-                            for (int j = 0; j < R; ++j) ovf[((dp - kStackRegs) * R + j) * kWave + lane] = t[j];
-                        }
-#pragma unroll
-                        for (int j = 0; j < R; ++j) t[j] = v[j];
-                    } else {
-                        // kFold: the terminal is the first operand, the top the second
-#pragma unroll
-                        for (int j = 0; j < R; ++j) {
-                            a[j] = v[j];
-                            b[j] = t[j];
-                        }
-                        binary = true;
-                    }
-                }
-                if (binary) {
-                    apply_binary<R>(fn, a, b);
-#pragma unroll
-                    for (int j = 0; j < R; ++j) t[j] = a[j];
+                nxt = pcode[q + 1];
+                const uint32_t cx = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(cur.x)));
+                const uint32_t cy = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(cur.y)));
+                const uint32_t cz = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(cur.z)));
+                const uint32_t op = cx & 0xffu;
+                const uint32_t wslot = (cx >> 8) & 0xffu;
+                const uint32_t rslot = cx >> 16;
+                GP_PUT(st, wslot, t);
+                float v[R];   // a terminal's value
+                // the feature cy (for kIPushX / kIFoldX)
+#define GP_FEATURE()                                                          \
+    do {                                                                      \
+        if constexpr (FREG > 0) {                                             \
+            v[0] = xa0[cy];                                                   \
+            if constexpr (R > 1) v[1] = xa1[cy];                              \
+            if constexpr (R > 2) v[2] = xa2[cy];                              \
+            if constexpr (R > 3) v[3] = xa3[cy];                              \
+        } else {                                                              \
+            const float* __restrict__ col = X + static_cast<int64_t>(cy) * ld; \
+            GP_ROWS(v[j] = col[row[j]]);                                      \
+        }                                                                     \
+    } while (0)
+#define GP_BIN_CASES(BASE, LOAD)                                                        \
+    case (BASE) + 0: { LOAD; GP_ROWS(t[j] = A0 + B0); } break;                          \
+    case (BASE) + 1: { LOAD; GP_ROWS(t[j] = A0 - B0); } break;                          \
+    case (BASE) + 2: { LOAD; GP_ROWS(t[j] = A0 * B0); } break;                          \
+    case (BASE) + 3: { LOAD; GP_ROWS(t[j] = op_div(A0, B0)); } break;                   \
+    case (BASE) + 4: case (BASE) + 5: case (BASE) + 6: {                                    \
+        LOAD; float a_[R], b_[R]; GP_ROWS(a_[j] = A0; b_[j] = B0);                    \
+        apply_binary_wide<R>(op - (BASE), a_, b_); GP_ROWS(t[j] = a_[j]);             \
+    } break;
+                switch (op) {
+                case kIPushX: GP_FEATURE(); GP_ROWS(t[j] = v[j]); break;
+                case kIPushC: {
+                    const float cval = __uint_as_float(cy);
+                    GP_ROWS(t[j] = cval);
+                } break;
+                case kIPushX | kIDeep: {
+                    GP_FEATURE();
+                    GP_ROWS(ovf[((rslot - kEvalRegs) * R + j) * kWave] = t[j]);
+                    GP_ROWS(t[j] = v[j]);
+                } break;
+                case kIPushC | kIDeep: {
+                    const float cval = __uint_as_float(cy);
+                    GP_ROWS(ovf[((rslot - kEvalRegs) * R + j) * kWave] = t[j]);
+                    GP_ROWS(t[j] = cval);
+                } break;
+#define A0 t[j]
+#define B0 v[j]
+                GP_BIN_CASES(kIBin, GP_GET(st, rslot, v))
+                GP_BIN_CASES(kIBin | kIDeep, GP_ROWS(v[j] = ovf[((rslot - kEvalRegs) * R + j) * kWave]))
+#undef A0
+#undef B0
+#define A0 v[j]
+#define B0 t[j]
+                GP_BIN_CASES(kIFoldX, GP_FEATURE())
+                GP_BIN_CASES(kIFoldC, const float cval = __uint_as_float(cy); GP_ROWS(v[j] = cval))
+#undef A0
+#undef B0
+                default: apply_unary<R>(op - kIUn, t, mt); break;
                 }
                 // the unary functions chained on this instruction
-                for (uint32_t ch = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(cur.z)));
-                     ch != 0u; ch >>= 4)
-                    apply_unary<R>((ch & 15u) - 1u, t);
+                for (uint32_t ch = cz; ch != 0u; ch >>= 4) apply_unary<R>((ch & 15u) - 1u, t, mt);
+#undef GP_BIN_CASES
+#undef GP_FEATURE
             }
 
             if constexpr (MODE == 0) {
@@ -730,8 +922,10 @@ __global__ __launch_bounds__(kBlock) void k_eval(PopView pop, CodeView cv, DataV
                 }
             }
         }
+        }
     }
 }
+#undef GP_ROWS
 
 // ---------------------------------------------------------------------------
 // k_finalize: merge each program's chunk partials in a fixed order (float64)
@@ -924,6 +1118,9 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
     float* __restrict__ aovf = wmem + kStackLds * R * kWave;        // adjoint stack beyond registers
     float* __restrict__ gtape = wmem + 2 * kStackLds * R * kWave;   // tape entries beyond LDS
     const double W = *wsum;
+    // (the function tables stay in global memory here: their LDS copy would
+    // cost the tape a wavefront per CU)
+    const MathTabs mt = global_tabs();
 
     // entry e of row slot j: LDS for e < kTapeLds, the global area beyond
     auto tape_put = [&](int e, const float (&v)[R]) {
@@ -1018,7 +1215,7 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                     float x[R];
 #pragma unroll
                     for (int j = 0; j < R; ++j) x[j] = t[j];
-                    apply_unary<R>(fn, t);
+                    apply_unary<R>(fn, t, mt);
                     if (fn != 0 && act) {
                         float dv[R];
                         unary_derivative<R>(fn, x, t, dv);
@@ -1113,7 +1310,7 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                     float x[R];
 #pragma unroll
                     for (int j = 0; j < R; ++j) x[j] = t[j];
-                    apply_unary<R>(u, t);
+                    apply_unary<R>(u, t, mt);
                     if (u != 0 && act) {
                         float dv[R];
                         unary_derivative<R>(u, x, t, dv);
@@ -1851,10 +2048,14 @@ struct DeviceScratch {
     size_t part_cap = 0;         // doubles
     double* ystat = nullptr;
     size_t ystat_cap = 0;        // doubles
-    uint4* code = nullptr;
+    uint4* code = nullptr;       // the adjoint's instruction stream
     size_t code_cap = 0;         // instructions
     int32_t* clen = nullptr;
     size_t clen_cap = 0;
+    uint4* ecode = nullptr;      // the evaluation kernel's instruction stream
+    size_t ecode_cap = 0;
+    int32_t* eclen = nullptr;
+    size_t eclen_cap = 0;
     double* stats = nullptr;     // per-program statistics (kStats doubles each)
     size_t stats_cap = 0;
     double* gpart = nullptr;     // gradient partials
@@ -1937,7 +2138,8 @@ gp_status scratch_init(DeviceScratch& s, int dev) {
 }
 
 bool scratch_empty(const DeviceScratch& s) {
-    return !s.counter && !s.order && !s.part && !s.ystat && !s.code && !s.clen && !s.stats && !s.gpart &&
+    return !s.counter && !s.order && !s.part && !s.ystat && !s.code && !s.clen && !s.ecode && !s.eclen &&
+           !s.stats && !s.gpart &&
            !s.gextra && !s.tape && !s.fit_tmp && !s.sp_k0 && !s.sp_k1 && !s.sp_v0 && !s.sp_v1 &&
            !s.sp_rs && !s.sp_cnt && !s.sp_r2y && !s.sp_nan && !s.sp_ty;
 }
@@ -1946,6 +2148,7 @@ bool scratch_empty(const DeviceScratch& s) {
 void scratch_free(DeviceScratch& s) {
     for (void* q : {s.counter, static_cast<void*>(s.order), static_cast<void*>(s.part),
                     static_cast<void*>(s.ystat), static_cast<void*>(s.code), static_cast<void*>(s.clen),
+                    static_cast<void*>(s.ecode), static_cast<void*>(s.eclen),
                     static_cast<void*>(s.stats), static_cast<void*>(s.gpart), static_cast<void*>(s.gextra),
                     static_cast<void*>(s.tape), static_cast<void*>(s.fit_tmp),
                     static_cast<void*>(s.sp_k0), static_cast<void*>(s.sp_k1), static_cast<void*>(s.sp_v0),
@@ -2083,12 +2286,12 @@ gp_status launch_eval_m(const LaunchCfg& cfg, int n_cu, const PopView& pv, const
                         const DataView& dv, const Sched& s, float* out, double* part, hipStream_t st,
                         int64_t node_rows, const Timing& tm) {
     const int block = cfg.wpb * kWave;
-    const size_t lds = static_cast<size_t>(cfg.wpb) * kStackLds * cfg.R * kWave * sizeof(float);
+    const size_t lds = static_cast<size_t>(cfg.wpb) * kEvalLds * cfg.R * kWave * sizeof(float);
     auto go = [&](auto kernel) -> gp_status {
         int per_cu = 0;
         GP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds));
         per_cu = std::max(per_cu, 1);
-        const int64_t waves_needed = s.n_items;
+        const int64_t waves_needed = (s.n_items + s.batch - 1) / s.batch;
         int64_t blocks = static_cast<int64_t>(per_cu) * n_cu;
         blocks = std::min<int64_t>(blocks, (waves_needed + cfg.wpb - 1) / cfg.wpb);
         blocks = std::max<int64_t>(blocks, 1);
@@ -2151,6 +2354,12 @@ gp_status reserve(DeviceScratch* sc, int32_t P, int64_t total_nodes, int64_t n_c
     if (rc != GP_OK) return rc;
     rc = grow(reinterpret_cast<void**>(&sc->clen), &sc->clen_cap, P, sizeof(int32_t));
     if (rc != GP_OK) return rc;
+    // (+1: the evaluation kernel fetches one instruction past a program's end)
+    rc = grow(reinterpret_cast<void**>(&sc->ecode), &sc->ecode_cap, static_cast<size_t>(total_nodes) + 1,
+              sizeof(uint4));
+    if (rc != GP_OK) return rc;
+    rc = grow(reinterpret_cast<void**>(&sc->eclen), &sc->eclen_cap, P, sizeof(int32_t));
+    if (rc != GP_OK) return rc;
     if (mode == 1) {
         const size_t kk = metric == GP_METRIC_PEARSON ? 4 : 1;
         rc = grow(reinterpret_cast<void**>(&sc->part), &sc->part_cap, static_cast<size_t>(P) * n_chunks * kk,
@@ -2177,11 +2386,14 @@ gp_status chunking(const gp_population_dev* pop, const gp_dataset_dev* data, con
 }
 
 // Shared front half of the evaluation paths: configuration, scratch, the
-// length ordering and the instruction stream.  `force` (nullable) overrides
-// the configuration choice.
+// length ordering and the instruction streams.  `force` (nullable) overrides
+// the configuration choice.  The evaluation kernel's stream (constant
+// subtrees folded) is compiled unless `adjoint` asks for the adjoint's
+// stream instead; `both` compiles the two (a backward pass that runs a
+// forward pass first).
 gp_status prepare(DeviceScratch* sc, const gp_population_dev* pop, const gp_dataset_dev* data, int mode,
                   int metric, hipStream_t st, const LaunchCfg* force, PopView* pv, CodeView* cvw, DataView* dv,
-                  Sched* sch, LaunchCfg* cfg, bool fold = true) {
+                  Sched* sch, LaunchCfg* cfg, bool adjoint = false, bool both = false) {
     *pv = PopView{pop->nodes, pop->prog_off, pop->consts, pop->const_off, pop->len, pop->n_programs};
     *dv = DataView{data->X, data->ld, data->n_features, data->n_rows, data->y, data->w};
     *cfg = force ? *force
@@ -2191,15 +2403,27 @@ gp_status prepare(DeviceScratch* sc, const gp_population_dev* pop, const gp_data
     if (rc != GP_OK) return rc;
     rc = reserve(sc, pop->n_programs, pop->total_nodes, n_chunks, mode, metric);
     if (rc != GP_OK) return rc;
-    *sch = Sched{chunk, static_cast<int32_t>(n_chunks), n_chunks * pop->n_programs, sc->order,
-                 static_cast<uint32_t*>(sc->counter)};
+    // items claimed per atomic: enough that a launch issues about 32 claims
+    // per resident wavefront (16 per CU), at most 8
+    const int64_t n_items = n_chunks * pop->n_programs;
+    const int64_t claims = static_cast<int64_t>(sc->n_cu) * 16 * 32;
+    const int32_t batch = static_cast<int32_t>(std::min<int64_t>(8, std::max<int64_t>(1, n_items / claims)));
+    *sch = Sched{chunk, static_cast<int32_t>(n_chunks), n_items, sc->order, static_cast<uint32_t*>(sc->counter),
+                 batch};
     hipLaunchKernelGGL(k_prepare, dim3(1), dim3(1024), 0, st, pop->len, pop->n_programs, sc->order,
                        static_cast<uint32_t*>(sc->counter));
     GP_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_compile, dim3((pop->n_programs + kBlock - 1) / kBlock), dim3(kBlock), 0, st, *pv,
-                       sc->code, sc->clen, fold ? 1 : 0);
-    GP_HIP(hipGetLastError());
-    *cvw = CodeView{sc->code, sc->clen};
+    const dim3 cgrid((pop->n_programs + kBlock - 1) / kBlock);
+    if (!adjoint || both) {
+        hipLaunchKernelGGL(k_compile_eval, cgrid, dim3(kBlock), 0, st, *pv, sc->ecode, sc->eclen);
+        GP_HIP(hipGetLastError());
+    }
+    if (adjoint) {
+        hipLaunchKernelGGL(k_compile, cgrid, dim3(kBlock), 0, st, *pv, sc->code, sc->clen, 0);
+        GP_HIP(hipGetLastError());
+    }
+    *cvw = CodeView{adjoint ? sc->code : nullptr, adjoint ? sc->clen : nullptr,
+                    (!adjoint || both) ? sc->ecode : nullptr, (!adjoint || both) ? sc->eclen : nullptr};
     return GP_OK;
 }
 
@@ -3477,8 +3701,10 @@ gp_status gp_fitness_backward(const gp_population_dev* pop, const gp_dataset_dev
     DataView dv;
     Sched sch;
     LaunchCfg cfg;
-    // no constant folding: every constant carries its own derivative
-    rc = prepare(sc, pop, data, 1, metric, st, nullptr, &pv, &cvw, &dv, &sch, &cfg, false);
+    // the adjoint's stream (no constant folding: every constant carries its
+    // own derivative); RMSE and Pearson also run the evaluation kernel first
+    const bool needs_forward = metric == GP_METRIC_RMSE || metric == GP_METRIC_PEARSON;
+    rc = prepare(sc, pop, data, 1, metric, st, nullptr, &pv, &cvw, &dv, &sch, &cfg, true, needs_forward);
     if (rc != GP_OK) return rc;
     const int32_t P = pop->n_programs;
     const int64_t nc = std::max<int64_t>(pop->total_consts, 1);
@@ -3505,7 +3731,6 @@ gp_status gp_fitness_backward(const gp_population_dev* pop, const gp_dataset_dev
     GP_HIP(hipGetLastError());
     const int fblocks = (P + (kBlock / kWave) - 1) / (kBlock / kWave);
     float* fit = fitness_out ? fitness_out : sc->fit_tmp;
-    const bool needs_forward = metric == GP_METRIC_RMSE || metric == GP_METRIC_PEARSON;
     if (needs_forward) {
         rc = launch_eval(1, metric, cfg, sc->n_cu, pv, cvw, dv, sch, nullptr, sc->part, st,
                          pop->total_nodes * data->n_rows, Timing{});
