@@ -2,21 +2,30 @@
 the paper) against the oracle's float64 reverse mode, whose own pins are a
 closed form and central finite differences (tests/test_oracle_grad.py).
 
-The GPU runs forward values, tape and adjoints in float32, so near a
-singularity of the program (a zero of cos under a division, say) its
-derivative can differ from the float64 one by far more than the forward
-value does.  The oracle estimates that float32 conditioning by Monte Carlo
-arithmetic: the spread of its derivatives when every operation is perturbed
-by a relative +-2^-22 (about the error of a float32 transcendental), over
+The GPU runs forward values, tape and adjoints in float32.  Over functions
+that both sides round correctly (the nine-function set: sin, cos and log by
+gp_crmath.h on the device) its forward values are the oracle's float32 ones
+bit for bit, so the reference is the oracle's reverse mode taken at the
+float32 evaluation (its values and protected branches, the partials in
+float64): only the float32 rounding of the reverse sweep separates the two.
+The oracle estimates that rounding by Monte Carlo arithmetic: the spread of
+its derivatives when every partial is perturbed by a relative +-2^-22, over
 three seeds.
 
-Tolerance, per program, with scale = max_k |g_64[k]|:
-  * well-conditioned programs (no protected predicate near its threshold,
-    derivative spread at most 2.5e-5 * scale):
-        max_k |g_gpu[k] - g_64[k]| <= 1e-4 * scale;
-  * every program whose fitness is well-conditioned (no protected predicate
-    near its threshold, fitness bound within the fitness tolerance):
-        max_k |g_gpu[k] - g_64[k]| <= 1e-4 * scale + 10 * max_k spread[k].
+Tolerance, per constant k of a program, with scale = max_k |g_64[k]|:
+    |g_gpu[k] - g_64[k]| <= 1e-4 |g_64[k]| + 10 spread[k] + 1e-6 scale,
+where spread[k] is that constant's own Monte Carlo spread.  A constant whose
+spread is below 2.5e-5 |g_64[k]| is thereby held to about 1e-4 relative on
+its own derivative, however small it is next to its siblings'; the 1e-6
+scale floor only absorbs the float32 rounding of the per-row terms in a sum
+that cancels.  No program is excluded, except one whose derivative lies
+beyond the float32 range.
+
+With the wider set's tan, exp, tanh, atan, cbrt and atan2 (the device
+library's, a few ulp from the oracle's) the reference is the float64
+evaluation, and a program escapes (counted, reported) where that cannot
+stand for float32: a protected predicate within its bound of the threshold,
+or a chaotic fitness (its conditioning bound beyond the fitness tolerance).
 """
 import os
 
@@ -25,7 +34,7 @@ import pytest
 
 import oracle
 import synth
-from _parity import to_oracle
+from _parity import CR_MASK, ParityStats, to_oracle
 
 pytestmark = pytest.mark.gpu
 NT = min(16, os.cpu_count() or 1)
@@ -63,56 +72,64 @@ def well_conditioned(f32p, f64, fbound, fnear):
                 & (fbound <= 1e-5 * np.abs(f32p)))
 
 
-def oracle_reference(opop, X, y, w, metric, gscale=None):
+def oracle_reference(opop, X, y, w, metric, gscale=None, f32_tape=True):
     """float64 derivatives, their Monte Carlo spread, and the fitness
-    conditioning of every program."""
-    ref, _ = oracle.grad_consts(opop, X, y, w, metric, gscale=gscale, n_threads=NT)
+    conditioning of every program.  With f32_tape (programs whose functions
+    are all correctly rounded on both sides, so the device's float32 forward
+    values are the oracle's) the derivatives are taken at the float32
+    evaluation, and the spread measures the float32 rounding of the reverse
+    sweep alone."""
+    ref, _ = oracle.grad_consts(opop, X, y, w, metric, gscale=gscale, n_threads=NT, f32_tape=f32_tape)
     spread = np.zeros_like(ref)
     with np.errstate(invalid="ignore"):
         for seed in MC_SEEDS:
             gm, _ = oracle.grad_consts(opop, X, y, w, metric, gscale=gscale, n_threads=NT,
-                                       mc_u=MC_U, mc_seed=seed)
+                                       mc_u=MC_U, mc_seed=seed, f32_tape=f32_tape)
             spread = np.fmax(spread, np.abs(gm - ref))
-    cond = oracle.fitness(opop, X, y, w, metric, n_threads=NT, with_bound=True)
+    cond = None if f32_tape else oracle.fitness(opop, X, y, w, metric, n_threads=NT, with_bound=True,
+                                                exact=CR_MASK)
     return ref, spread, cond
 
 
 def check_grads(host, g, ref, spread, cond, label):
-    f32p, _, fbound, fnear = cond
-    # a fitness whose own conditioning bound exceeds the fitness tolerance is
-    # chaotic in float32 (e.g. sin of a cube that reaches 1e10 on some rows):
-    # a few Monte Carlo samples of such a heavy-tailed sum do not bound its
-    # derivative, so only the tight bar's exclusion applies there
-    with np.errstate(invalid="ignore"):
-        fit_ok = (np.asarray(fnear) == 0) & ((np.asarray(fbound) <= 1e-4 * np.abs(f32p))
-                                              | (np.asarray(fbound) == 0))
-    checked = ill = 0
+    """Per-constant check; returns (programs checked, programs escaped) and
+    records the constant counts (tight: spread within 2.5e-5 |g_64|).  cond
+    (the oracle's fitness conditioning) is None for a float32-tape
+    reference, which shares the device's forward values and branches."""
+    if cond is None:
+        fit_ok = np.ones(host.n_programs, bool)
+    else:
+        f32p, _, fbound, fnear = cond
+        with np.errstate(invalid="ignore"):
+            fit_ok = (np.asarray(fnear) == 0) & ((np.asarray(fbound) <= 1e-4 * np.abs(f32p))
+                                                  | (np.asarray(fbound) == 0))
+    big = np.finfo(np.float32).max
+    checked = escaped = c_tight = c_spread = c_escaped = 0
     for p in range(host.n_programs):
         a, b = int(host.const_off[p]), int(host.const_off[p + 1])
         if a == b:
             continue
         r, sp = ref[a:b], spread[a:b]
-        # a fitness or derivative beyond the float32 range (nested cubes
-        # reaching 1e49, say) has no float32 value to compare with
-        big = np.finfo(np.float32).max
-        if not (np.all(np.isfinite(r)) and np.all(np.isfinite(sp)) and abs(f32p[p]) <= big
-                and np.all(np.abs(r) <= big)):
-            ill += 1
+        if not (fit_ok[p] and np.all(np.isfinite(r)) and np.all(np.isfinite(sp)) and np.all(np.abs(r) <= big)):
+            escaped += 1
+            c_escaped += b - a
             continue
         scale = np.max(np.abs(r))
-        err = np.max(np.abs(g[a:b] - r))
-        if fit_ok[p]:
-            assert err <= GRAD_TOL * scale + 10.0 * np.max(sp), \
-                (label, p, "beyond the conditioning estimate", err, np.max(sp), g[a:b], r)
-        if not (fnear[p] == 0 and np.max(sp) <= SPREAD_TOL * scale):
-            ill += 1
-            continue
-        if scale == 0.0:
-            assert err == 0.0, (label, p)
-        else:
-            assert err <= GRAD_TOL * scale, (label, p, err / scale, g[a:b], r)
+        err = np.abs(g[a:b] - r)
+        tol = GRAD_TOL * np.abs(r) + 10.0 * sp + 1e-6 * scale
+        bad = ~(err <= tol)
+        if bad.any():
+            k = int(np.nonzero(bad)[0][0])
+            raise AssertionError(f"{label}: program {p} constant {k}: gpu {g[a + k]!r} float64 {r[k]!r} "
+                                 f"(spread {sp[k]:.3g}, scale {scale:.3g}); all: {g[a:b]} vs {r}")
+        tight = sp <= SPREAD_TOL * np.abs(r)
+        c_tight += int(tight.sum())
+        c_spread += int((~tight).sum())
         checked += 1
-    return checked, ill
+    ParityStats(label, "gradients", checked, c_tight, c_spread, escaped).record()
+    print(f"{label}: {checked} programs checked ({c_tight} constants held to 1e-4 of their own derivative, "
+          f"{c_spread} to their Monte Carlo spread), {escaped} programs ({c_escaped} constants) escaped")
+    return checked, escaped
 
 
 def test_closed_form_mul_c_x0(gp):
@@ -149,10 +166,8 @@ def test_matches_float64_reverse_mode(gp, metric, weighted):
     gscale = rng.uniform(0.5, 2.0, size=P)
     g, fit_out, fwd = run_backward(gp, host, X, y, w, metric, 8, gscale)
     ref, spread, cond = oracle_reference(to_oracle(host), X, y, w, metric, gscale)
-    checked, ill = check_grads(host, g, ref, spread, cond, f"{metric} w={weighted}")
-    print(f"{metric} weighted={weighted}: {checked} programs checked, {ill} ill-conditioned")
-    # near-uncorrelated programs (|r| << 1) dominate the ill-conditioned Pearson set
-    assert checked >= (15 if metric == "pearson" else 40)
+    checked, escaped = check_grads(host, g, ref, spread, cond, f"{metric} w={weighted}")
+    assert escaped == 0
     # fitness_out agrees with gp_fitness (different summation order only)
     fin = np.isfinite(fwd)
     assert np.array_equal(fin, np.isfinite(fit_out))
@@ -175,37 +190,35 @@ def test_forced_rows_per_lane(gp, cfg):
     finally:
         gp.set_launch_config(None)
     ref, spread, cond = oracle_reference(to_oracle(host), X, y, None, "mse")
-    checked, ill = check_grads(host, g, ref, spread, cond, f"forced {cfg}")
-    assert checked >= 40
+    checked, escaped = check_grads(host, g, ref, spread, cond, f"forced {cfg}")
+    assert escaped == 0
     fin = np.isfinite(fwd)
     assert np.allclose(fit_out[fin], fwd[fin], rtol=1e-6, atol=0)
 
 
 def test_long_programs_float64_reverse_mode(gp):
     """Programs of 1-200 nodes over the nine-function set (the shape of the
-    differentiation workload): many are chaotic in float32; the
-    well-conditioned ones must meet the bar."""
+    differentiation workload): every constant of every program."""
     N = 30_000
     X, y = synth.diff_target(N, seed=12)
     host = gp.build_population(160, 8, "exact_len", min_len=1, max_len=200, max_consts=16, seed=2115)
     g, _, _ = run_backward(gp, host, X, y, None, "mse", 8)
     ref, spread, cond = oracle_reference(to_oracle(host), X, y, None, "mse")
-    checked, ill = check_grads(host, g, ref, spread, cond, "long")
-    print(f"long programs: {checked} checked, {ill} ill-conditioned")
-    assert checked >= 20
+    checked, escaped = check_grads(host, g, ref, spread, cond, "long")
+    assert escaped == 0
 
 
 def test_correctly_rounded_function_set_all_programs(gp):
-    # no transcendental: every program is well-conditioned, all are checked
+    # add, sub, mul, neg: every program is checked
     fmask = sum(1 << o for o in (oracle.ADD, oracle.SUB, oracle.MUL, oracle.NEG))
     N = 20_000
     X, y = synth.diff_target(N, seed=7)
     host = gp.build_population(128, 8, "exact_len", min_len=1, max_len=120, max_consts=16,
                                function_mask=fmask, seed=8)
     g, _, _ = run_backward(gp, host, X, y, None, "mse", 8)
-    ref, spread, (f32p, f64, fb, fn) = oracle_reference(to_oracle(host), X, y, None, "mse")
-    checked, ill = check_grads(host, g, ref, spread, (f32p, f32p, fb, fn), "add/sub/mul/neg")
-    assert ill == 0 and checked == sum(int(host.const_off[p + 1] > host.const_off[p]) for p in range(128))
+    ref, spread, cond = oracle_reference(to_oracle(host), X, y, None, "mse")
+    checked, escaped = check_grads(host, g, ref, spread, cond, "add/sub/mul/neg")
+    assert escaped == 0 and checked == sum(int(host.const_off[p + 1] > host.const_off[p]) for p in range(128))
 
 
 @pytest.mark.parametrize("metric", ["mse", "pearson"])
@@ -220,9 +233,10 @@ def test_wider_function_set_float64_reverse_mode(gp, metric):
     host = gp.build_population(P, 8, "rhh", min_depth=2, max_depth=6, max_consts=16,
                                function_mask=oracle.ALL_FMASK, seed=2119)
     g, fit_out, fwd = run_backward(gp, host, X, y, None, metric, 8)
-    ref, spread, cond = oracle_reference(to_oracle(host), X, y, None, metric)
-    checked, ill = check_grads(host, g, ref, spread, cond, f"wide {metric}")
-    print(f"wide {metric}: {checked} programs checked, {ill} ill-conditioned")
+    # tan, exp, tanh, atan, cbrt and atan2 are the device library's: the
+    # float64 reference with the fitness conditioning decides the escapes
+    ref, spread, cond = oracle_reference(to_oracle(host), X, y, None, metric, f32_tape=False)
+    checked, escaped = check_grads(host, g, ref, spread, cond, f"wide {metric}")
     assert checked >= (15 if metric == "pearson" else 40)
     fin = np.isfinite(fwd)
     assert np.array_equal(fin, np.isfinite(fit_out))
@@ -230,8 +244,7 @@ def test_wider_function_set_float64_reverse_mode(gp, metric):
 
 
 def test_wider_correctly_rounded_set_all_programs(gp):
-    # max, min, abs, square, cube with add / sub / mul / neg: no library
-    # function, so every program is well-conditioned and all are checked
+    # max, min, abs, square, cube with add / sub / mul / neg
     fmask = sum(1 << o for o in (oracle.ADD, oracle.SUB, oracle.MUL, oracle.NEG, oracle.MAX,
                                  oracle.MIN, oracle.ABS, oracle.SQ, oracle.CUBE))
     N = 20_000
@@ -239,11 +252,12 @@ def test_wider_correctly_rounded_set_all_programs(gp):
     host = gp.build_population(128, 8, "exact_len", min_len=1, max_len=60, max_consts=16,
                                function_mask=fmask, seed=18)
     g, _, _ = run_backward(gp, host, X, y, None, "mse", 8)
-    ref, spread, (f32p, f64, fb, fn) = oracle_reference(to_oracle(host), X, y, None, "mse")
-    checked, ill = check_grads(host, g, ref, spread, (f32p, f32p, fb, fn), "wide correctly rounded")
-    print(f"wide correctly rounded: {checked} checked, {ill} ill")
+    ref, spread, cond = oracle_reference(to_oracle(host), X, y, None, "mse")
+    checked, escaped = check_grads(host, g, ref, spread, cond, "wide correctly rounded")
     n_const = sum(int(host.const_off[p + 1] > host.const_off[p]) for p in range(128))
-    assert checked >= 0.9 * n_const
+    # with a float32-tape reference a program escapes only when a derivative
+    # lies beyond the float32 range (nested cubes and squares overflow)
+    assert checked + escaped == n_const and escaped <= 0.05 * n_const
 
 
 def test_more_than_sixteen_constants_and_edge_rows(gp):
@@ -299,10 +313,14 @@ def test_autograd_function_and_refinement(gp):
     assert np.array_equal(new_c.cpu().numpy()[keep], host.consts[keep])
 
 
-def test_full_size_differentiation_workload_sampled(gp):
+def test_full_size_differentiation_workload(gp):
     """1,048,576 rows x 8 features, 2048 programs with up to 16 constants:
-    one backward launch for the whole population; sampled programs checked
-    against float64 reverse mode over every row."""
+    one backward launch for the whole population; 32 programs with
+    constants drawn at random (8 of them with 150 nodes or more, no
+    conditioning filter) checked constant by constant against float64
+    reverse mode at the float32 evaluation over every row.  The Monte Carlo spread is taken on an
+    evenly spaced eighth of the rows (a derivative is a mean over rows, so
+    its float32 sensitivity has the same scale on a large sample)."""
     import torch
     N = 1_048_576
     X, y = synth.diff_target(N, seed=11231)
@@ -313,28 +331,25 @@ def test_full_size_differentiation_workload_sampled(gp):
     torch.cuda.synchronize()
     g = g.cpu().numpy().astype(np.float64)
     rng = np.random.default_rng(3)
-    cand = rng.choice(np.nonzero(np.diff(host.const_off) > 0)[0], size=96, replace=False)
-    sub = oracle.from_programs([(host.nodes[host.prog_off[p]:host.prog_off[p + 1]],
-                                 host.consts[host.const_off[p]:host.const_off[p + 1]]) for p in cand])
-    idx = np.linspace(0, N - 1, 16384).astype(np.int64)
-    f32p, f64, fb, fn = oracle.fitness(sub, np.ascontiguousarray(X[:, idx]), y[idx], None, "mse",
-                                       n_threads=NT, with_bound=True)
-    ok = well_conditioned(f32p, f64, fb, fn) & (fb <= 1e-6 * np.abs(f32p))
-    ref_s, spread_s, _ = oracle_reference(sub, np.ascontiguousarray(X[:, idx]), y[idx], None, "mse")
-    for i in range(len(cand)):
-        a, b = int(sub.const_off[i]), int(sub.const_off[i + 1])
-        ok[i] &= bool(np.max(spread_s[a:b]) <= 0.1 * SPREAD_TOL * np.max(np.abs(ref_s[a:b])))
-    good = list(np.nonzero(ok)[0][:6])
-    assert len(good) >= 3
-    pick = cand[good]
+    withc = np.nonzero(np.diff(host.const_off) > 0)[0]
+    pick = rng.choice(withc, size=24, replace=False)
+    longs = np.setdiff1d(withc[host.length[withc] >= 150], pick)
+    pick = np.sort(np.concatenate([pick, rng.choice(longs, size=8, replace=False)]))
     sub = oracle.from_programs([(host.nodes[host.prog_off[p]:host.prog_off[p + 1]],
                                  host.consts[host.const_off[p]:host.const_off[p + 1]]) for p in pick])
-    ref, _ = oracle.grad_consts(sub, X, y, None, "mse", n_threads=NT)
-    k = 0
-    for i, p in enumerate(pick):
-        a, b = int(host.const_off[p]), int(host.const_off[p + 1])
-        r = ref[k:k + (b - a)]
-        k += b - a
-        assert np.max(np.abs(g[a:b] - r)) <= GRAD_TOL * max(np.max(np.abs(r)), 1e-30), (p, g[a:b], r)
-    print(f"differentiation workload: {len(pick)} sampled programs checked, lengths "
-          f"{host.length[pick].tolist()}")
+    ref, _ = oracle.grad_consts(sub, X, y, None, "mse", n_threads=NT, f32_tape=True)
+    idx = np.arange(0, N, 8)
+    Xs, ys = np.ascontiguousarray(X[:, idx]), np.ascontiguousarray(y[idx])
+    ref_s, _ = oracle.grad_consts(sub, Xs, ys, None, "mse", n_threads=NT, f32_tape=True)
+    spread = np.zeros_like(ref)
+    with np.errstate(invalid="ignore"):
+        for seed in MC_SEEDS:
+            gm, _ = oracle.grad_consts(sub, Xs, ys, None, "mse", n_threads=NT, mc_u=MC_U, mc_seed=seed,
+                                       f32_tape=True)
+            spread = np.fmax(spread, np.abs(gm - ref_s))
+    gsub = np.concatenate([g[host.const_off[p]:host.const_off[p + 1]] for p in pick])
+    hsub = gp.HostPopulation(sub.nodes, sub.prog_off, sub.consts, sub.const_off, sub.length)
+    checked, escaped = check_grads(hsub, gsub, ref, spread, None, "diff-1M")
+    print(f"differentiation workload: {checked} of {len(pick)} sampled programs checked, lengths "
+          f"{sorted(host.length[pick].tolist())}")
+    assert escaped == 0

@@ -125,7 +125,8 @@ def test_graph_fitness_matches_oracle(gp):
     finally:
         gen.close()
     f32p, f64 = oracle.fitness(to_oracle(host), X, y, None, "mse", n_threads=8)
-    ok = np.isfinite(f64)
+    ok = np.isfinite(f32p)
+    assert np.array_equal(np.isfinite(fit), ok)
     assert np.allclose(fit[ok], f32p[ok], rtol=1e-4, atol=0)
 
 

@@ -71,7 +71,8 @@ def test_loop_against_oracle_each_generation(gp):
         _, pop, fit = steps[g]
         opop = to_oracle(pop)
         f32p, f64 = oracle.fitness(opop, X, y, None, "mse", n_threads=8)
-        ok = np.isfinite(f64) & (np.abs(f32p - f64) <= 1e-6 * np.abs(f64))
+        # every function is correctly rounded on both sides: every program
+        ok = np.isfinite(f32p)
         assert np.allclose(fit[ok], f32p[ok], rtol=1e-4, atol=0), g
         assert np.array_equal(np.isfinite(fit), np.isfinite(f32p))
         ops, ft, T = oracle.plan_generation(ev, P, g)

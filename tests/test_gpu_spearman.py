@@ -15,7 +15,7 @@ import pytest
 
 import oracle
 import synth
-from _parity import to_oracle
+from _parity import CR_MASK, to_oracle
 
 pytestmark = pytest.mark.gpu
 NT = min(16, os.cpu_count() or 1)
@@ -59,10 +59,12 @@ def test_spearman_rhh_population(gp, weighted):
     w = synth.weights(N, seed=3) if weighted else None
     host = gp.build_population(256, 2, "rhh", min_depth=2, max_depth=6, seed=2111)
     got = gpu_spearman(gp, host, X, y, w, 2)
-    f32p, f64, fb, fn = oracle.fitness(to_oracle(host), X, y, w, "spearman", n_threads=NT, with_bound=True)
+    f32p, f64, fb, fn = oracle.fitness(to_oracle(host), X, y, w, "spearman", n_threads=NT, with_bound=True,
+                                    exact=CR_MASK)
     tight = check(got, f32p, fb, fn, f"rhh w={weighted}")
-    print(f"spearman rhh weighted={weighted}: {tight} programs with a zero bound")
-    assert tight >= 40
+    # every function of the set is correctly rounded on both sides: every
+    # program's outputs are the oracle's, so every bound is zero
+    assert tight == 256
 
 
 @pytest.mark.parametrize("N", [3000, 70_000])
@@ -76,7 +78,8 @@ def test_spearman_ties_everywhere(gp, N):
     fmask = sum(1 << o for o in (oracle.ADD, oracle.SUB, oracle.MUL, oracle.NEG))
     host = gp.build_population(200, 2, "exact_len", min_len=1, max_len=40, function_mask=fmask, seed=9)
     got = gpu_spearman(gp, host, X, y, None, 2)
-    f32p, f64, fb, fn = oracle.fitness(to_oracle(host), X, y, None, "spearman", n_threads=NT, with_bound=True)
+    f32p, f64, fb, fn = oracle.fitness(to_oracle(host), X, y, None, "spearman", n_threads=NT, with_bound=True,
+                                    exact=CR_MASK)
     # exact arithmetic on small integers: identical values, ranks and ties on both sides
     assert np.all(fb == 0.0)
     assert np.allclose(got, f32p, rtol=1e-6, atol=1e-7)
@@ -119,7 +122,8 @@ def test_spearman_nan_target_is_nan_for_every_program(gp):
             assert np.isnan(got).all() and np.isnan(f32p).all(), (k, nan)
     # and the next call, without the NaN, is ordinary again
     got = gpu_spearman(gp, host, X, y0, None, 2)
-    f32p, f64, fb, fn = oracle.fitness(to_oracle(host), X, y0, None, "spearman", n_threads=NT, with_bound=True)
+    f32p, f64, fb, fn = oracle.fitness(to_oracle(host), X, y0, None, "spearman", n_threads=NT, with_bound=True,
+                                    exact=CR_MASK)
     check(got, f32p, fb, fn, "after NaN target")
 
 
@@ -138,5 +142,6 @@ def test_spearman_sizes_and_batches(gp, N, workset):
         got = gpu_spearman(gp, host, X, y, None, 2)
     finally:
         gp.set_spearman_workset(0)
-    f32p, f64, fb, fn = oracle.fitness(to_oracle(host), X, y, None, "spearman", n_threads=NT, with_bound=True)
+    f32p, f64, fb, fn = oracle.fitness(to_oracle(host), X, y, None, "spearman", n_threads=NT, with_bound=True,
+                                    exact=CR_MASK)
     check(got, f32p, fb, fn, f"N={N}")
