@@ -56,8 +56,9 @@ enum {
     GP_OP_COS = 10,  /* cos a                                                      */
     GP_OP_TAN = 11,  /* tan a                                                      */
     /* the wider set (the paper counts its functions without listing them) */
-    GP_OP_MAX = 12,   /* fmaxf(a, b): IEEE maxNum, a NaN operand yields the other */
-    GP_OP_MIN = 13,   /* fminf(a, b)                                              */
+    GP_OP_MAX = 12,   /* IEEE 754-2019 maximumNumber: a NaN operand yields the    */
+                      /* other; -0 orders below +0                                */
+    GP_OP_MIN = 13,   /* minimumNumber: a NaN operand yields the other; -0 < +0   */
     GP_OP_ATAN2 = 14, /* atan2f(a, b): a is y, b is x                             */
     GP_OP_ABS = 15,   /* |a|                                                      */
     GP_OP_EXP = 16,   /* exp a                                                    */

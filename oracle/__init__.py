@@ -21,6 +21,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gp_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# (tests/test_sanitizers.py points this at an AddressSanitizer build)
+_LIB = os.environ.get("GP_ORACLE_LIB", _LIB)
 
 # opcodes as the oracle reads them (op in bits 0-7, argument in bits 8-31)
 VAR, CONST, ADD, SUB, MUL, DIV, NEG, LOG, SQRT, SIN, COS, TAN = range(12)
