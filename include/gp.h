@@ -68,7 +68,12 @@ enum {
     GP_OP_TANH = 20,  /* tanh a                                                   */
     GP_OP_ATAN = 21,  /* atan a                                                   */
     GP_OP_CBRT = 22,  /* cube root of a                                           */
-    GP_OP_COUNT = 23
+    GP_OP_COUNT = 23,
+    /* user-defined functions (Sec. V: custom function sets), registered with
+     * gp_register_function: 24..27 take one argument, 28..31 two */
+    GP_OP_USER1 = 24,
+    GP_OP_USER2 = 28,
+    GP_OP_LIMIT = 32  /* every opcode is below this                             */
 };
 #define GP_NODE(op, arg) ((uint32_t)(op) | ((uint32_t)(arg) << 8))
 #define GP_NODE_OP(w) ((uint32_t)(w) & 0xffu)
@@ -127,14 +132,57 @@ void gp_shutdown(void);
 /* float32 program value; LOGLOSS's in float32; all row sums in        */
 /* float64; the result is rounded to float32.                          */
 /* ------------------------------------------------------------------ */
+/*   USER_0..USER_3 (Sec. V: custom loss functions): the row loss is the */
+/*            float32 value of the registered two-argument user function */
+/*            GP_OP_USER2 + i applied to (yh, y); fitness = sum w l /    */
+/*            sum w in float64 (smaller is better).  gp_fitness and the  */
+/*            generation graphs and evolution loop compute it;           */
+/*            gp_fitness_backward gives GP_ERR_UNSUPPORTED.              */
 typedef enum {
     GP_METRIC_MAE = 0,
     GP_METRIC_MSE = 1,
     GP_METRIC_RMSE = 2,
     GP_METRIC_LOGLOSS = 3,
     GP_METRIC_PEARSON = 4,
-    GP_METRIC_SPEARMAN = 5
+    GP_METRIC_SPEARMAN = 5,
+    GP_METRIC_USER_0 = 6,
+    GP_METRIC_USER_1 = 7,
+    GP_METRIC_USER_2 = 8,
+    GP_METRIC_USER_3 = 9
 } gp_metric;
+
+/* ------------------------------------------------------------------ */
+/* User-defined functions (Sec. V: custom function sets and loss      */
+/* functions during GP runs).                                          */
+/* ------------------------------------------------------------------ */
+/* Maximum size of a definition and the stack it may use on its own. */
+#define GP_USER_MAX_NODES 32
+#define GP_USER_MAX_CONSTS 16
+#define GP_USER_MAX_STACK 6
+
+/* Define user function `op` (GP_OP_USER1 .. GP_OP_USER1+3: one argument;
+ * GP_OP_USER2 .. GP_OP_USER2+3: two) as an expression over the built-in
+ * functions: def[def_len] is a prefix list (the program encoding above) in
+ * which GP_NODE(GP_OP_VAR, k) stands for argument k (k < the function's
+ * arity; argument 0 is the first) and GP_NODE(GP_OP_CONST, k) for
+ * consts[k].  A program node `op` then evaluates to the definition's value
+ * on its arguments, every operation rounded to float32 as when the
+ * definition is written out in the program.  The definition may not use
+ * user functions, must leave exactly one value and may hold at most
+ * GP_USER_MAX_STACK values on the right-to-left scan (this stack comes on
+ * top of the program's GP_MAX_STACK).  def_len == 0 removes the definition.
+ * Once defined, `op` may appear in programs (gp_validate_population accepts
+ * it), in function_mask (bit 1 << op) of the generators and mutation, and a
+ * two-argument function may serve as the row loss of GP_METRIC_USER_i
+ * (op = GP_OP_USER2 + i).  Process-wide; it applies to calls made after it
+ * and to generation graphs and evolution loops created after it (those
+ * created before keep what they captured).  Not thread-safe against
+ * concurrent evaluation calls.  gp_fitness_backward gives
+ * GP_ERR_UNSUPPORTED for populations that use user functions. */
+gp_status gp_register_function(uint32_t op, const uint32_t* def, int32_t def_len, const float* consts,
+                               int32_t n_consts);
+/* 1 if user function op is defined, else 0. */
+int gp_function_defined(uint32_t op);
 
 /* 1 if a larger value of the metric is better (Sec. III-C1: the criterion
  * may favour smaller or larger values), 0 if smaller is better, -1 if the
@@ -313,6 +361,7 @@ gp_status gp_evaluate(const gp_population_dev* pop, const gp_dataset_dev* data,
  * outputs never reach memory.  fitness is DEVICE memory [n_programs]. */
 gp_status gp_fitness(const gp_population_dev* pop, const gp_dataset_dev* data,
                      gp_metric metric, float* fitness, void* stream);
+
 
 /* Tournament selection (Sec. III-C1): tournament t draws tournament_size
  * program indices with replacement, draw d being floor(word * n / 2^32) for

@@ -34,8 +34,11 @@ ARITY = {VAR: 0, CONST: 0, ADD: 2, SUB: 2, MUL: 2, DIV: 2,
          ABS: 1, EXP: 1, INV: 1, SQ: 1, CUBE: 1, TANH: 1, ATAN: 1, CBRT: 1}
 # every function: the nine of the benchmark configurations, tan, and the wider set
 ALL_FMASK = sum(1 << op for op, a in ARITY.items() if a > 0)
-METRICS = {"mae": 0, "mse": 1, "rmse": 2, "logloss": 3, "pearson": 4, "spearman": 5}
-LARGER_IS_BETTER = {0: 0, 1: 0, 2: 0, 3: 0, 4: 1}
+METRICS = {"mae": 0, "mse": 1, "rmse": 2, "logloss": 3, "pearson": 4, "spearman": 5,
+           "user0": 6, "user1": 7, "user2": 8, "user3": 9}
+LARGER_IS_BETTER = {0: 0, 1: 0, 2: 0, 3: 0, 4: 1, 5: 1, 6: 0, 7: 0, 8: 0, 9: 0}
+# user-defined functions (Sec. V): 24..27 of one argument, 28..31 of two
+USER1, USER2 = 24, 28
 INIT = {"rhh": 0, "full": 1, "grow": 2, "exact_len": 3}
 # the nine-function set used by the Pagie / classification workloads
 DEFAULT_FMASK = sum(1 << op for op in (ADD, SUB, MUL, DIV, NEG, LOG, SQRT, SIN, COS))
@@ -71,6 +74,8 @@ def lib():
         P = ctypes.c_void_p
         i32, i64, u32, u64, f32 = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
                                    ctypes.c_uint64, ctypes.c_float)
+        L.orc_set_user_function.argtypes = [ctypes.c_int, P, ctypes.c_int, P, ctypes.c_int]
+        L.orc_set_user_function.restype = ctypes.c_int
         L.orc_check_program.argtypes = [P, i64, i32, i64, P]
         L.orc_check_program.restype = ctypes.c_int
         L.orc_evaluate_f32.argtypes = [P, P, P, P, i32, P, i64, i64, P, ctypes.c_int]
@@ -169,6 +174,17 @@ def from_programs(programs) -> Population:
 
 def node(op, arg=0):
     return (int(op) & 0xFF) | (int(arg) << 8)
+
+
+def set_user_function(op, nodes=None, consts=()):
+    """Define user function `op` (USER1..USER1+3: one argument, USER2..USER2+3:
+    two) as the prefix list `nodes` over the built-in functions, VAR k being
+    argument k and CONST k consts[k]; no nodes removes it."""
+    nd = np.ascontiguousarray(np.asarray(nodes if nodes else [0], np.uint32))
+    cs = np.ascontiguousarray(np.asarray(consts if len(consts) else [0.0], np.float32))
+    rc = lib().orc_set_user_function(int(op), _p(nd), len(nodes) if nodes else 0, _p(cs), len(consts))
+    if rc != 0:
+        raise ValueError("orc_set_user_function: bad arguments")
 
 
 def check_program(nodes, n_features, n_consts):

@@ -45,7 +45,10 @@ enum {
     O_NEG = 6, O_LOG = 7, O_SQRT = 8, O_SIN = 9, O_COS = 10, O_TAN = 11,
     O_MAX = 12, O_MIN = 13, O_ATAN2 = 14,
     O_ABS = 15, O_EXP = 16, O_INV = 17, O_SQ = 18, O_CUBE = 19, O_TANH = 20, O_ATAN = 21, O_CBRT = 22,
-    O_NUM = 23
+    O_NUM = 23,
+    /* user-defined functions (Sec. V, custom function sets): 24..27 take one
+     * argument, 28..31 two; each is defined by orc_set_user_function */
+    O_USER1 = 24, O_USER2 = 28, O_LIMIT = 32
 };
 #define ORC_STACK 20          /* fixed evaluation stack, Sec. III-B */
 
@@ -57,8 +60,80 @@ static int op_arity(int op)
     case O_NEG: case O_LOG: case O_SQRT: case O_SIN: case O_COS: case O_TAN:
     case O_ABS: case O_EXP: case O_INV: case O_SQ: case O_CUBE: case O_TANH: case O_ATAN: case O_CBRT:
         return 1;
-    default: return -1;
+    default:
+        if (op >= O_USER1 && op < O_USER2) return 1;
+        if (op >= O_USER2 && op < O_LIMIT) return 2;
+        return -1;
     }
+}
+
+/* ---- user-defined functions (Sec. V: custom function sets and losses) ----
+ * Function u (opcode O_USER1 + u) is a prefix list over the built-in
+ * functions in which VAR k stands for its argument k and CONST k for its
+ * constant k.  Its value on arguments (a, b) is the value of that list with
+ * the arguments put in: evaluated here by the same right-to-left stack
+ * rule as a program, every built-in operation rounded to float32 (float32
+ * path) or carried in float64.  Definitions are not checked here (the
+ * library's gp_register_function checks them). */
+#define ORC_USER_NODES 32
+#define ORC_USER_CONSTS 16
+static struct {
+    int len;
+    uint32_t nodes[ORC_USER_NODES];
+    float consts[ORC_USER_CONSTS];
+} orc_user[O_LIMIT - O_USER1];
+
+int orc_set_user_function(int op, const uint32_t *nodes, int len, const float *consts, int n_consts)
+{
+    if (op < O_USER1 || op >= O_LIMIT || len < 0 || len > ORC_USER_NODES || n_consts < 0 ||
+        n_consts > ORC_USER_CONSTS)
+        return -1;
+    int u = op - O_USER1;
+    orc_user[u].len = len;
+    for (int i = 0; i < ORC_USER_NODES; ++i) orc_user[u].nodes[i] = i < len ? nodes[i] : 0u;
+    for (int i = 0; i < ORC_USER_CONSTS; ++i) orc_user[u].consts[i] = i < n_consts ? consts[i] : 0.0f;
+    return 0;
+}
+
+static float op_f32(int op, float a, float b);
+static double op_f64(int op, double a, double b);
+
+static float user_f32(int op, float a, float b)
+{
+    int u = op - O_USER1;
+    float st[ORC_USER_NODES];
+    int h = 0;
+    for (int i = orc_user[u].len - 1; i >= 0; --i) {
+        int dop = (int)(orc_user[u].nodes[i] & 0xffu);
+        uint32_t arg = orc_user[u].nodes[i] >> 8;
+        if (dop == O_VAR) { st[h++] = arg == 0 ? a : b; continue; }
+        if (dop == O_CONST) { st[h++] = orc_user[u].consts[arg % ORC_USER_CONSTS]; continue; }
+        int ar = op_arity(dop);
+        if (ar < 1 || dop >= O_NUM || h < ar) return NAN;
+        float x = st[--h];
+        float y = ar == 2 ? st[--h] : 0.0f;
+        st[h++] = op_f32(dop, x, y);
+    }
+    return h == 1 ? st[0] : NAN;
+}
+
+static double user_f64(int op, double a, double b)
+{
+    int u = op - O_USER1;
+    double st[ORC_USER_NODES];
+    int h = 0;
+    for (int i = orc_user[u].len - 1; i >= 0; --i) {
+        int dop = (int)(orc_user[u].nodes[i] & 0xffu);
+        uint32_t arg = orc_user[u].nodes[i] >> 8;
+        if (dop == O_VAR) { st[h++] = arg == 0 ? a : b; continue; }
+        if (dop == O_CONST) { st[h++] = (double)orc_user[u].consts[arg % ORC_USER_CONSTS]; continue; }
+        int ar = op_arity(dop);
+        if (ar < 1 || dop >= O_NUM || h < ar) return NAN;
+        double x = st[--h];
+        double y = ar == 2 ? st[--h] : 0.0;
+        st[h++] = op_f64(dop, x, y);
+    }
+    return h == 1 ? st[0] : NAN;
 }
 
 /* ---- protected operators (reading: the gplearn convention) ---- */
@@ -239,7 +314,7 @@ static float op_f32(int op, float a, float b)
     case O_INV: return pinv_f(a);
     case O_SQ: return a * a;
     case O_CUBE: { float q = a * a; return q * a; }
-    default: return NAN;
+    default: return (op >= O_USER1 && op < O_LIMIT) ? user_f32(op, a, b) : NAN;
     }
 }
 
@@ -267,7 +342,7 @@ static double op_f64(int op, double a, double b)
     case O_TANH: return tanh(a);
     case O_ATAN: return atan(a);
     case O_CBRT: return cbrt(a);
-    default: return NAN;
+    default: return (op >= O_USER1 && op < O_LIMIT) ? user_f64(op, a, b) : NAN;
     }
 }
 
@@ -766,6 +841,11 @@ static double metric_from_values(int metric, const float *yh32, const double *yh
                 double z = yh64[r], yr = (double)y[r];
                 l = fmax(z, 0.0) - yr * z + log1p(exp(-fabs(z)));
             }
+        } else if (metric >= 6 && metric <= 9) {
+            /* user loss i: U_i(yhat, y), U_i the two-argument user function
+             * O_USER2 + i, in float32 (float32 path) or float64 */
+            int uop = O_USER2 + (metric - 6);
+            l = yh32 ? (double)user_f32(uop, yh32[r], y[r]) : user_f64(uop, yh64[r], (double)y[r]);
         } else {
             double d = (yh32 ? (double)yh32[r] : yh64[r]) - (double)y[r];
             l = (metric == 0) ? fabs(d) : d * d;
@@ -1085,7 +1165,7 @@ void orc_tournament_draws(int32_t n_programs, int32_t k, int32_t t, uint64_t see
 /*       binary if h >= 2 and h-2 <= i; (plus a parity rule when there is no  */
 /*       unary function).  One word picks uniformly among the allowed items,  */
 /*       listed as features, constant, unary ops, binary ops.                 */
-/* Function set: bit (1 << opcode) of fmask for opcodes 2..11.                */
+/* Function set: bit (1 << opcode) of fmask for opcodes 2..22 and 24..31.     */
 /* Constant slots are numbered 0,1,.. in prefix order.                        */
 /* ------------------------------------------------------------------------ */
 typedef struct {
@@ -1107,9 +1187,9 @@ static void put_const(orc_buf *b, float v)
 
 typedef struct {
     int n_features;
-    int funcs[O_NUM]; int n_funcs;      /* enabled functions in opcode order */
-    int un[O_NUM]; int n_un;
-    int bin[O_NUM]; int n_bin;
+    int funcs[O_LIMIT]; int n_funcs;    /* enabled functions in opcode order */
+    int un[O_LIMIT]; int n_un;
+    int bin[O_LIMIT]; int n_bin;
     float lo, hi; int consts_on; int max_consts;
 } orc_gen_cfg;
 
@@ -1225,10 +1305,10 @@ static int fill_cfg(orc_gen_cfg *cfg, int32_t n_features, uint32_t fmask, float 
 {
     memset(cfg, 0, sizeof *cfg);
     if (n_features < 1) return -1;
-    if (fmask & ~(((1u << O_NUM) - 1u) & ~3u)) return -1;
+    if (fmask & (1u << 23 | 3u)) return -1;
     cfg->n_features = n_features;
-    for (int op = O_ADD; op < O_NUM; ++op) {
-        if (fmask & (1u << op)) {
+    for (int op = O_ADD; op < O_LIMIT; ++op) {
+        if (op_arity(op) > 0 && (fmask & (1u << op))) {
             cfg->funcs[cfg->n_funcs++] = op;
             if (op_arity(op) == 1) cfg->un[cfg->n_un++] = op; else cfg->bin[cfg->n_bin++] = op;
         }
@@ -1254,13 +1334,13 @@ int orc_build_population(int32_t n_programs, int32_t n_features, int32_t method,
     memset(&cfg, 0, sizeof cfg);
     if (n_programs < 0 || n_features < 1) return -1;
     cfg.n_features = n_features;
-    for (int op = O_ADD; op < O_NUM; ++op) {
-        if (fmask & (1u << op)) {
+    for (int op = O_ADD; op < O_LIMIT; ++op) {
+        if (op_arity(op) > 0 && (fmask & (1u << op))) {
             cfg.funcs[cfg.n_funcs++] = op;
             if (op_arity(op) == 1) cfg.un[cfg.n_un++] = op; else cfg.bin[cfg.n_bin++] = op;
         }
     }
-    if (fmask & ~(((1u << O_NUM) - 1u) & ~3u)) return -1;
+    if (fmask & (1u << 23 | 3u)) return -1;
     if (cfg.n_funcs == 0) return -1;
     cfg.lo = const_lo; cfg.hi = const_hi;
     cfg.consts_on = !(const_lo > const_hi);

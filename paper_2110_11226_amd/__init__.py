@@ -11,7 +11,7 @@ from ._binding import (  # noqa: F401
     validate_population, version, get_launch_config, set_launch_config, set_spearman_workset,
     profile_enable, profile_read, autotune, autotune_save, autotune_load, autotune_clear, Generation,
     plan_generation, mutate, GENOPS, plan_generation_device, mutate_device, DeviceOffspring, FUNCS_ALL, Evolution,
-    FUNCS_DEFAULT, MAX_STACK, METRICS, LIB_PATH,
+    FUNCS_DEFAULT, MAX_STACK, METRICS, LIB_PATH, register_function, function_defined, OP_USER1, OP_USER2,
 )
 from .autograd import GPFitness, refine_constants  # noqa: F401,E402
 from .loop import (run_generations, RunResult, GenerationLog, save_checkpoint,  # noqa: F401,E402

@@ -28,9 +28,12 @@ OP_VAR, OP_CONST, OP_ADD, OP_SUB, OP_MUL, OP_DIV, OP_NEG, OP_LOG, OP_SQRT, OP_SI
 OP_MAX, OP_MIN, OP_ATAN2 = 12, 13, 14
 OP_ABS, OP_EXP, OP_INV, OP_SQ, OP_CUBE, OP_TANH, OP_ATAN, OP_CBRT = range(15, 23)
 FUNCS_ALL = sum(1 << op for op in range(OP_ADD, OP_CBRT + 1))
+OP_USER1, OP_USER2 = 24, 28   # user functions: 24..27 of one argument, 28..31 of two
 MAX_STACK = 20
+USER_MAX_NODES, USER_MAX_CONSTS, USER_MAX_STACK = 32, 16, 6
 FUNCS_DEFAULT = 0x7FC
-METRICS = {"mae": 0, "mse": 1, "rmse": 2, "logloss": 3, "pearson": 4, "spearman": 5}
+METRICS = {"mae": 0, "mse": 1, "rmse": 2, "logloss": 3, "pearson": 4, "spearman": 5,
+           "user0": 6, "user1": 7, "user2": 8, "user3": 9}
 INIT = {"rhh": 0, "full": 1, "grow": 2, "exact_len": 3}
 STATUS = {0: "GP_OK", -1: "GP_ERR_INVALID_ARG", -2: "GP_ERR_INVALID_PROGRAM",
           -3: "GP_ERR_STACK_OVERFLOW", -4: "GP_ERR_OUT_OF_MEMORY", -5: "GP_ERR_DEVICE",
@@ -75,6 +78,8 @@ _validate = _sig("gp_validate_population", [_vp, _vp, _vp, _i32, _i32, _vp, _vp]
 _evaluate = _sig("gp_evaluate", [ctypes.POINTER(PopulationDev), ctypes.POINTER(DatasetDev), _vp, _vp])
 _fitness = _sig("gp_fitness", [ctypes.POINTER(PopulationDev), ctypes.POINTER(DatasetDev), ctypes.c_int,
                                _vp, _vp])
+_register_fn = _sig("gp_register_function", [_u32, _vp, _i32, _vp, _i32])
+_fn_defined = _sig("gp_function_defined", [_u32])
 _tournament = _sig("gp_tournament", [_vp, _vp, _i32, ctypes.c_int, _f32, _i32, _i32, _u64, _u64, _vp, _vp])
 class LaunchConfig(ctypes.Structure):
     _fields_ = [("rows_per_lane", _i32), ("feature_regs", _i32), ("tiles_per_chunk", _i32),
@@ -136,6 +141,7 @@ _backward = _sig("gp_fitness_backward", [ctypes.POINTER(PopulationDev), ctypes.P
 
 EXPORTED = ["gp_last_error", "gp_version", "gp_shutdown", "gp_metric_larger_is_better",
             "gp_build_population", "gp_validate_population", "gp_evaluate", "gp_fitness",
+            "gp_register_function", "gp_function_defined",
             "gp_tournament", "gp_fitness_backward", "gp_get_launch_config", "gp_set_launch_config",
             "gp_profile_enable", "gp_profile_read", "gp_autotune", "gp_autotune_save", "gp_autotune_load",
             "gp_autotune_clear", "gp_generation_create", "gp_generation_run", "gp_generation_info",
@@ -385,6 +391,24 @@ def fitness(pop: DevicePopulation, data: DeviceDataset, metric="mse", out=None, 
     _check(_fitness(ctypes.byref(view), ctypes.byref(data.view), metric_id(metric), _tptr(out),
                     _stream(stream)), "gp_fitness")
     return out
+
+
+def register_function(op, nodes=None, consts=()):
+    """gp_register_function: define user function `op` (24..27: one
+    argument, 28..31: two) as the prefix list `nodes` (node words over the
+    built-in functions, OP_VAR k = argument k, OP_CONST k = consts[k]);
+    nodes None or empty removes the definition."""
+    if not nodes:
+        _check(_register_fn(int(op), None, 0, None, 0), "gp_register_function")
+        return
+    nd = np.ascontiguousarray(np.asarray(nodes, np.uint32))
+    cs = np.ascontiguousarray(np.asarray(consts, np.float32))
+    _check(_register_fn(int(op), _np_ptr(nd), int(nd.shape[0]), _np_ptr(cs) if cs.size else None, int(cs.size)),
+           "gp_register_function")
+
+
+def function_defined(op) -> bool:
+    return bool(_fn_defined(int(op)))
 
 
 def tournament(fit, length, metric="mse", parsimony=0.0, tournament_size=20, n_tournaments=None,

@@ -119,13 +119,14 @@ bool flag_sincos(float x, bool is_cos) {
     if (ax < 0x1p-12f) return false;
     uint32_t ub;
     std::memcpy(&ub, &ax, 4);
-    const double y = ax < 0x1p+20f ? gp::crm::sincos_small(ax, is_cos, gp::crm::kSinCosTab)
-                                   : gp::crm::sincos_large(ub, is_cos, gp::crm::kSinCosTab);
+    const gp::crm::SinCosK K = gp::crm::sincos_k();
+    const double y = ax < 0x1p+20f ? gp::crm::sincos_small(ax, is_cos, gp::crm::kSinCosTab, K)
+                                   : gp::crm::sincos_large(ub, is_cos, gp::crm::kSinCosTab, K);
     return gp::crm::near_boundary(y);
 }
 bool flag_sin(float x) { return flag_sincos(x, false); }
 bool flag_cos(float x) { return flag_sincos(x, true); }
-bool flag_log(float x) { return gp::crm::near_boundary(gp::crm::log_double(x)); }
+bool flag_log(float x) { return gp::crm::near_boundary(gp::crm::log_double(x, gp::crm::kLogTab, gp::crm::log_k())); }
 
 }  // namespace
 
@@ -137,13 +138,40 @@ int main(int argc, char** argv) {
     uint32_t logs;
     std::memcpy(&logs, &t, 4);
     if (!std::strcmp(which, "all") || !std::strcmp(which, "sin"))
-        run("sin", 0u, fin, [](float x) { return gp::crm::sin_cr(x); }, [](double x) { return std::sin(x); },
+        run("sin", 0u, fin, [](float x) { return gp::crm::sin_cr(x, gp::crm::kSinCosTab, gp::crm::sincos_k()); }, [](double x) { return std::sin(x); },
             [](long double x) { return sinl(x); }, flag_sin);
     if (!std::strcmp(which, "all") || !std::strcmp(which, "cos"))
-        run("cos", 0u, fin, [](float x) { return gp::crm::cos_cr(x); }, [](double x) { return std::cos(x); },
+        run("cos", 0u, fin, [](float x) { return gp::crm::cos_cr(x, gp::crm::kSinCosTab, gp::crm::sincos_k()); }, [](double x) { return std::cos(x); },
             [](long double x) { return cosl(x); }, flag_cos);
+    if (!std::strcmp(which, "all") || !std::strcmp(which, "sin") || !std::strcmp(which, "cos")) {
+        // negative inputs: sin(-x) = -sin x and cos(-x) = cos x bit for bit
+        // (both zeros, infinities and NaN included), on every g_stride-th float
+        long long bad = 0, n = 0;
+        const gp::crm::SinCosK K = gp::crm::sincos_k();
+        for (long long ub = 0; ub <= 0x7FFFFFFFll; ub += g_stride) {
+            float x, nx;
+            const uint32_t u = static_cast<uint32_t>(ub), nu = u | 0x80000000u;
+            std::memcpy(&x, &u, 4);
+            std::memcpy(&nx, &nu, 4);
+            const float sp = gp::crm::sin_cr(x, gp::crm::kSinCosTab, K), sn = gp::crm::sin_cr(nx, gp::crm::kSinCosTab, K);
+            const float cp = gp::crm::cos_cr(x, gp::crm::kSinCosTab, K), cn = gp::crm::cos_cr(nx, gp::crm::kSinCosTab, K);
+            const float msp = -sp;
+            uint32_t a, b, c, d;
+            std::memcpy(&a, &msp, 4);
+            std::memcpy(&b, &sn, 4);
+            std::memcpy(&c, &cp, 4);
+            std::memcpy(&d, &cn, 4);
+            const bool nan = std::isnan(sp) && std::isnan(sn) && std::isnan(cp) && std::isnan(cn);
+            ++n;
+            if (!nan && (a != b || c != d)) {
+                ++bad;
+                if (bad <= 8) std::printf("sign 0x%08x sin %08x/%08x cos %08x/%08x\n", nu, b, a, d, c);
+            }
+        }
+        std::printf("summary sign %lld 0 %lld %lld 0\n", n, bad, bad);
+    }
     if (!std::strcmp(which, "all") || !std::strcmp(which, "log"))
-        run("log", logs + 1, fin, [](float x) { return gp::crm::log_cr(x); }, [](double x) { return std::log(x); },
+        run("log", logs + 1, fin, [](float x) { return gp::crm::log_cr(x, gp::crm::kLogTab, gp::crm::log_k()); }, [](double x) { return std::log(x); },
             [](long double x) { return logl(x); }, flag_log);
     return 0;
 }

@@ -18,20 +18,22 @@
 // falls on the wrong side (found by running every float through these
 // functions against an independent reference, crmath_check.cpp).
 //
-//   sin, cos: |x| = k (pi/32) + r, |r| <= pi/64: for |x| < 2^20 by a
+//   sin, cos: |x| = k (pi/64) + r, |r| <= pi/128: for |x| < 2^20 by a
 //     three-part Cody-Waite reduction whose first two products are exact;
 //     beyond, by Payne-Hanek: the 24-bit mantissa times a 160-bit window of
 //     the binary digits of 2/pi, in 32-bit integer limbs.  Then sin x =
-//     S cos r + C sin r with S, C the sine and cosine of (k mod 64) pi/32
-//     from a table (cos x takes k + 16), sin r and cos r by short Taylor
+//     S cos r + C sin r with S, C the sine and cosine of (k mod 128) pi/64
+//     from a table (cos x takes k + 32), sin r and cos r by short Taylor
 //     polynomials.
 //   log: a = 2^e m, m in [1, 2); c = 1/(bucket centre of m) from a 128-entry
 //     table (c has 24 bits, so m c - 1 is exact); log a = E ln 2 - log c' +
-//     log1p(m c - 1) with log1p to r^9 (|m c - 1| <= 2^-7) and the table's
+//     log1p(m c - 1) with log1p to r^7 (|m c - 1| <= 2^-7) and the table's
 //     -log c' and ln 2 carried as double + remainder.
 // The code is host- and device-compilable so that the exhaustive checker can
-// run the very same functions on the CPU.  The tables are taken by pointer:
-// the evaluation kernels stage them in LDS.
+// run the very same functions on the CPU.  The tables are taken by pointer
+// (the evaluation kernels stage them in LDS) and the double constants as a
+// struct (sincos_k, log_k: built once per instruction, shared by the rows a
+// lane evaluates).
 #pragma once
 
 #include <cstdint>
@@ -103,40 +105,49 @@ GP_CRF float exception(const uint32_t (&tab)[N][2], int n, uint32_t key, float f
 }
 
 // ---- sin, cos ----
-// |x| = k (pi/32) + r, |r| <= pi/64; with j = k mod 64 (plus 16 for cos,
+// |x| = k (pi/64) + r, |r| <= pi/128; with j = k mod 128 (plus 32 for cos,
 // cos x = sin(x + pi/2)), sin x = S_j cos r + C_j sin r for S_j, C_j the
-// sine and cosine of j pi/32 from a table, cos r and sin r by their Taylor
-// polynomials through r^8 and r^9 (truncation below 2^-64 relative).
-constexpr double kInvPi32 = 0x1.45f306dc9c883p+3;   // 32/pi
-// pi/32 = kPi32a + kPi32b + kPi32c + O(2^-118): a and b carry 29 bits each,
-// so k * a and k * b are exact for k < 2^24 (|x| < 2^20)
-constexpr double kPi32a = 0x1.921fb54000000p-4;
-constexpr double kPi32b = 0x1.10b4611000000p-34;
-constexpr double kPi32c = 0x1.4c4c6628b80dcp-63;
-constexpr double kPi32 = 0x1.921fb54442d18p-4;
+// sine and cosine of j pi/64 from a table, cos r - 1 and sin r by their
+// Taylor polynomials through r^6 and r^7 (truncation below 2^-57 relative).
+constexpr double kInvPi64 = 0x1.45f306dc9c883p+4;   // 64/pi
+// pi/64 = kPi64a + kPi64b + kPi64c + O(2^-119): a and b carry at most 28
+// bits, so k * a and k * b are exact for k < 2^25 (|x| < 2^20)
+constexpr double kPi64a = 0x1.921fb54000000p-5;
+constexpr double kPi64b = 0x1.10b4610000000p-35;
+constexpr double kPi64c = 0x1.a62633145c06ep-63;
+constexpr double kPi64 = 0x1.921fb54442d18p-5;
 // (-1)^n / (2n+1)! and (-1)^n / (2n)!
-constexpr double kS3 = -0x1.5555555555555p-3, kS5 = 0x1.1111111111111p-7, kS7 = -0x1.a01a01a01a01ap-13,
-                 kS9 = 0x1.71de3a556c734p-19;
-constexpr double kC4 = 0x1.5555555555555p-5, kC6 = -0x1.6c16c16c16c17p-10, kC8 = 0x1.a01a01a01a01ap-16;
+constexpr double kS3 = -0x1.5555555555555p-3, kS5 = 0x1.1111111111111p-7, kS7 = -0x1.a01a01a01a01ap-13;
+constexpr double kC4 = 0x1.5555555555555p-5, kC6 = -0x1.6c16c16c16c17p-10;
 
-// sin(j pi/32 + r) for |r| <= pi/64 (slightly more after rounding of k)
-GP_CRF double sin_from_table(const SinCosEntry& e, double r) {
+// The double constants of sin and cos as operands.  The evaluation kernels
+// build this once per instruction and share it among the rows a lane holds.
+struct SinCosK {
+    double inv, pa, pb, pc, s3, s5, s7, c4, c6;
+};
+GP_CRF SinCosK sincos_k() {
+    return SinCosK{kreg(kInvPi64), kreg(kPi64a), kreg(kPi64b), kreg(kPi64c), kreg(kS3),
+                   kreg(kS5),      kreg(kS7),    kreg(kC4),    kreg(kC6)};
+}
+
+// sin(j pi/64 + r) for |r| <= pi/128 (slightly more after rounding of k)
+GP_CRF double sin_from_table(const SinCosEntry& e, double r, const SinCosK& K) {
     const double r2 = r * r;
-    const double sp = fma(fma(fma(kreg(kS9), r2, kreg(kS7)), r2, kreg(kS5)), r2, kreg(kS3));
-    const double cp = fma(fma(fma(kreg(kC8), r2, kreg(kC6)), r2, kreg(kC4)), r2, -0.5);
+    const double sp = fma(fma(K.s7, r2, K.s5), r2, K.s3);
+    const double cp = fma(fma(K.c6, r2, K.c4), r2, -0.5);
     const double cm1 = r2 * cp;                  // cos r - 1
     const double sr = fma(r * r2, sp, r);        // sin r
     return fma(e.s, cm1, fma(e.c, sr, e.s));
 }
 
-// |x| < 2^20: k and r by a three-part Cody-Waite reduction
-GP_CRF double sincos_small(double ax, bool is_cos, const SinCosEntry* tab) {
-    const double k = rint(ax * kreg(kInvPi32));
-    double r = fma(-k, kreg(kPi32a), ax);
-    r = fma(-k, kreg(kPi32b), r);
-    r = fma(-k, kreg(kPi32c), r);
-    const int j = (static_cast<int>(k) + (is_cos ? 16 : 0)) & 63;   // 0 <= k < 2^24
-    return sin_from_table(tab[j], r);
+// 0 <= ax <= 2^20: k and r by a three-part Cody-Waite reduction
+GP_CRF double sincos_small(double ax, bool is_cos, const SinCosEntry* tab, const SinCosK& K) {
+    const double k = rint(ax * K.inv);
+    double r = fma(-k, K.pa, ax);
+    r = fma(-k, K.pb, r);
+    r = fma(-k, K.pc, r);
+    const int j = (static_cast<int>(k) + (is_cos ? 32 : 0)) & 127;   // 0 <= k < 2^25
+    return sin_from_table(tab[j], r, K);
 }
 
 // The binary digits of 2/pi in 32-bit words, after one word of zeros (the
@@ -145,13 +156,13 @@ GP_CRTAB uint32_t kTwoOverPi[13] = {0u,          0xa2f9836eu, 0x4e441529u, 0xfc2
                                    0xdb629599u, 0x3c439041u, 0xfe5163abu, 0xdebbc561u, 0xb7246e3au,
                                    0x424dd2e0u, 0x06492eeau, 0x09d1921cu};
 
-// Payne-Hanek for |x| = M 2^E >= 2^20 (ub: the float bits of |x|).  Digits
-// of 2/pi of weight 2^(E-p) >= 4 multiply the integer M into multiples of 4
-// and are dropped: the window is digits p = E-1 .. E+158 (160 bits), so
-// Z = M * window * 2^-158 = |x| 2/pi mod 4 carries 158 fraction bits and an
-// error below 2^-134.  16 Z = |x| 32/pi mod 64: k is its nearest integer
-// (bits 154 up, after adding 2^153) and r = (16 Z - k) pi/32.
-GP_CRF double sincos_large(uint32_t ub, bool is_cos, const SinCosEntry* tab) {
+// Payne-Hanek for finite |x| = M 2^E >= 2^20 (ub: the float bits of |x|).
+// Digits of 2/pi of weight 2^(E-p) >= 4 multiply the integer M into
+// multiples of 4 and are dropped: the window is digits p = E-1 .. E+158 (160
+// bits), so Z = M * window * 2^-158 = |x| 2/pi mod 4 carries 158 fraction
+// bits and an error below 2^-134.  32 Z = |x| 64/pi mod 128: k is its
+// nearest integer (bits 153 up, after adding 2^152) and r = (32 Z - k) pi/64.
+GP_CRF double sincos_large(uint32_t ub, bool is_cos, const SinCosEntry* tab, const SinCosK& K) {
     const uint32_t M = (ub & 0x7FFFFFu) | 0x800000u;
     const int E = static_cast<int>(ub >> 23) - 150;
     const int p0 = E - 1;
@@ -166,12 +177,12 @@ GP_CRF double sincos_large(uint32_t ub, bool is_cos, const SinCosEntry* tab) {
         z[j] = static_cast<uint32_t>(t);
         c = t >> 32;
     }
-    // bit 153 of Z is bit 25 of z[0]; k = bits 154..159
-    z[0] += 0x2000000u;
-    const int k = static_cast<int>(z[0] >> 26);
-    const int j = (k + (is_cos ? 16 : 0)) & 63;
-    // D = (bits 0..153) - 2^153: signed, 154 fraction bits of 16 Z
-    const int64_t top = static_cast<int64_t>(z[0] & 0x3FFFFFFu) - 0x2000000ll;
+    // bit 152 of Z is bit 24 of z[0]; k = bits 153..159
+    z[0] += 0x1000000u;
+    const int k = static_cast<int>(z[0] >> 25);
+    const int j = (k + (is_cos ? 32 : 0)) & 127;
+    // D = (bits 0..152) - 2^152: signed, 153 fraction bits of 32 Z
+    const int64_t top = static_cast<int64_t>(z[0] & 0x1FFFFFFu) - 0x1000000ll;
     const bool dneg = top < 0;
     uint32_t d[5] = {static_cast<uint32_t>(top), z[1], z[2], z[3], z[4]};
     if (dneg) {   // |D|: two's complement negation across the limbs
@@ -188,65 +199,90 @@ GP_CRF double sincos_large(uint32_t ub, bool is_cos, const SinCosEntry* tab) {
     const int l = __builtin_clz(d[j0] | 1u);   // (d[j0] != 0 for every float input)
     uint64_t hi = (static_cast<uint64_t>(d[j0]) << 32) | d[j0 + 1];
     if (l) hi = (hi << l) | (d[j0 + 2] >> (32 - l));
-    double D = ldexp(static_cast<double>(hi), 160 - 64 - 154 - 32 * j0 - l);
+    double D = ldexp(static_cast<double>(hi), 160 - 64 - 153 - 32 * j0 - l);
     if (dneg) D = -D;
-    return sin_from_table(tab[j], D * kPi32);
+    return sin_from_table(tab[j], D * kPi64, K);
 }
 
-// Correctly rounded sin (is_cos false) or cos of a float.
-GP_CRF float sincos_cr(float x, bool is_cos, const SinCosEntry* tab) {
+// Exception-table entries [B, E) (sorted by key) applied to f without a branch
+template <int N>
+GP_CRF float exceptions_select(const uint32_t (&tab)[N][2], int b, int e, uint32_t key, float f) {
+    for (int i = b; i < e; ++i) f = key == tab[i][0] ? bitsf(tab[i][1]) : f;
+    return f;
+}
+
+// Correctly rounded sin (is_cos false) or cos of a float.  The common case
+// (|x| < 2^20) runs without a branch; Payne-Hanek reduction, infinities and
+// NaN take one that is rarely entered.  Exception entries below 2^20 are
+// matched by selects, the others in that branch.
+GP_CRF float sincos_cr(float x, bool is_cos, const SinCosEntry* tab, const SinCosK& K) {
     const float ax = fabsf(x);
-    if (!(ax <= 0x1.fffffep+127f)) return x - x;   // NaN for +-inf and NaN
-    if (ax < 0x1p-12f) return is_cos ? 1.0f : x;   // sin x rounds to x, cos x to 1
     const uint32_t ub = fbits(ax);
-    const double y = ax < 0x1p+20f ? sincos_small(static_cast<double>(ax), is_cos, tab)
-                                   : sincos_large(ub, is_cos, tab);
-    float f = static_cast<float>(y);   // the result for |x|
-    if (near_boundary(y)) f = is_cos ? exception(kCosExc, kCosExcN, ub, f) : exception(kSinExc, kSinExcN, ub, f);
-    return (!is_cos && x < 0.0f) ? -f : f;
+    // (clamped so that NaN and large inputs keep k in range; their result
+    // is replaced below)
+    const double y = sincos_small(static_cast<double>(fminf(ax, 0x1p+20f)), is_cos, tab, K);
+    float f = static_cast<float>(y);
+    f = is_cos ? exceptions_select(kCosExc, 0, kCosExcSmallN, ub, f)
+               : exceptions_select(kSinExc, 0, kSinExcSmallN, ub, f);
+    f = ax < 0x1p-12f ? (is_cos ? 1.0f : ax) : f;   // sin x rounds to x, cos x to 1
+    if (ub >= 0x49800000u) {                           // |x| >= 2^20, inf, NaN
+        if (ub < 0x7F800000u) {
+            const double yl = sincos_large(ub, is_cos, tab, K);
+            f = static_cast<float>(yl);
+            if (near_boundary(yl))
+                f = is_cos ? exception(kCosExc, kCosExcN, ub, f) : exception(kSinExc, kSinExcN, ub, f);
+        } else {
+            f = x - x;   // NaN
+        }
+    }
+    return (!is_cos && (fbits(x) >> 31)) ? -f : f;   // sin(-x) = -sin x, -0 included
 }
 
-GP_CRF float sin_cr(float x, const SinCosEntry* tab = kSinCosTab) { return sincos_cr(x, false, tab); }
-GP_CRF float cos_cr(float x, const SinCosEntry* tab = kSinCosTab) { return sincos_cr(x, true, tab); }
+GP_CRF float sin_cr(float x, const SinCosEntry* tab, const SinCosK& K) { return sincos_cr(x, false, tab, K); }
+GP_CRF float cos_cr(float x, const SinCosEntry* tab, const SinCosK& K) { return sincos_cr(x, true, tab, K); }
 
 // ---- log ----
 constexpr double kLn2hi = 0x1.62e42fefa3900p-1;   // 45 bits: E * kLn2hi is exact
 constexpr double kLn2lo = 0x1.de6af278ece60p-46;
-// (-1)^(k+1) / k, k = 2..9
-constexpr double kL3 = 0x1.5555555555555p-2, kL4 = -0x1.0000000000000p-2,
-                 kL5 = 0x1.999999999999ap-3, kL6 = -0x1.5555555555555p-3, kL7 = 0x1.2492492492492p-3,
-                 kL8 = -0x1.0000000000000p-3, kL9 = 0x1.c71c71c71c71cp-4;
+// (-1)^(k+1) / k, k = 3..7 (log1p to r^7: |r| <= 2^-7, truncation below
+// 2^-52 relative)
+constexpr double kL3 = 0x1.5555555555555p-2, kL4 = -0x1.0000000000000p-2, kL5 = 0x1.999999999999ap-3,
+                 kL6 = -0x1.5555555555555p-3, kL7 = 0x1.2492492492492p-3;
+
+struct LogK {
+    double l3, l4, l5, l6, l7, ln2hi, ln2lo;
+};
+GP_CRF LogK log_k() {
+    return LogK{kreg(kL3), kreg(kL4), kreg(kL5), kreg(kL6), kreg(kL7), kreg(kLn2hi), kreg(kLn2lo)};
+}
 
 // log a for a normal positive finite float, in double.
-GP_CRF double log_double(float a, const LogEntry* tab = kLogTab) {
+GP_CRF double log_double(float a, const LogEntry* tab, const LogK& K) {
     const uint32_t u = fbits(a);
     const int i = static_cast<int>((u >> 16) & 0x7Fu);
     const int E = static_cast<int>(u >> 23) - 127 + (i >= 53 ? 1 : 0);
     const double m = static_cast<double>(bitsf((u & 0x7FFFFFu) | 0x3F800000u));
     const LogEntry& t = tab[i];
     const double r = fma(m, static_cast<double>(t.c), -1.0);   // exact
-    double p = fma(kreg(kL9), r, kreg(kL8));
-    p = fma(p, r, kreg(kL7));
-    p = fma(p, r, kreg(kL6));
-    p = fma(p, r, kreg(kL5));
-    p = fma(p, r, kreg(kL4));
-    p = fma(p, r, kreg(kL3));
+    double p = fma(K.l7, r, K.l6);
+    p = fma(p, r, K.l5);
+    p = fma(p, r, K.l4);
+    p = fma(p, r, K.l3);
     p = fma(p, r, -0.5);
     const double l1p = fma(r * r, p, r);
     const double Ed = static_cast<double>(E);
-    const double hi = fma(Ed, kreg(kLn2hi), t.hi);
-    const double lo = fma(Ed, kreg(kLn2lo), static_cast<double>(t.lo) + l1p);
+    const double hi = fma(Ed, K.ln2hi, t.hi);
+    const double lo = fma(Ed, K.ln2lo, static_cast<double>(t.lo) + l1p);
     return hi + lo;
 }
 
-// Correctly rounded log of a float a > 0 that is normal or +inf (the
+// Correctly rounded log of a float a > 0 that is normal, +inf or NaN (the
 // protected log only takes |a| > 0.001).
-GP_CRF float log_cr(float a, const LogEntry* tab = kLogTab) {
-    if (!(a <= 0x1.fffffep+127f)) return a;   // +inf (and NaN)
-    const double y = log_double(a, tab);
+GP_CRF float log_cr(float a, const LogEntry* tab, const LogK& K) {
+    const double y = log_double(a, tab, K);   // (finite for +inf and NaN; replaced below)
     float f = static_cast<float>(y);
     if (near_boundary(y)) f = exception(kLogExc, kLogExcN, fbits(a), f);
-    return f;
+    return a <= 0x1.fffffep+127f ? f : a;     // +inf (and NaN) unchanged
 }
 
 }  // namespace crm

@@ -68,8 +68,10 @@ struct DataView {
 struct CodeView {
     const uint4* code;     // the adjoint's format (k_compile)
     const int32_t* clen;
-    const uint4* ecode;    // the evaluation kernel's format (k_compile_eval)
-    const int32_t* eclen;
+    const uint4* ecode;    // the evaluation kernel's format (k_compile_eval):
+    const int32_t* eclen;  // program p from ecode[prog_off[p] * ex_mul + p * ex_add]
+    int32_t ex_mul;        // instructions per node at most (1, or the longest user definition)
+    int32_t ex_add;        // instructions per program added by a user loss
 };
 
 // Work decomposition: rows are split into n_chunks chunks of `chunk` rows
@@ -83,6 +85,7 @@ struct Sched {
     const int32_t* order;
     uint32_t* counter;
     int32_t batch;     // work items claimed per atomic by the evaluation kernel
+    int32_t lds_slots; // stack slots per row in LDS (kEvalLds or kEvalLdsUser)
 };
 
 // ---------------------------------------------------------------------------
@@ -165,11 +168,11 @@ __device__ __forceinline__ MathTabs global_tabs() { return MathTabs{crm::kSinCos
 
 // The kernel-resident copies (one per block, filled before its first use).
 struct MathTabsLds {
-    crm::SinCosEntry sc[64];
+    crm::SinCosEntry sc[128];
     crm::LogEntry lg[128];
 };
 __device__ __forceinline__ MathTabs stage_tabs(MathTabsLds& lds) {
-    for (int i = threadIdx.x; i < 64; i += blockDim.x) lds.sc[i] = crm::kSinCosTab[i];
+    for (int i = threadIdx.x; i < 128; i += blockDim.x) lds.sc[i] = crm::kSinCosTab[i];
     for (int i = threadIdx.x; i < 128; i += blockDim.x) lds.lg[i] = crm::kLogTab[i];
     __syncthreads();
     return MathTabs{lds.sc, lds.lg};
@@ -180,8 +183,8 @@ __device__ __forceinline__ MathTabs stage_tabs(MathTabsLds& lds) {
 __device__ __forceinline__ float op_div(float a, float b) {
     return fabsf(b) > GP_PROTECT_EPS ? a / b : 1.0f;
 }
-__device__ __forceinline__ float op_log(float a, const MathTabs& mt) {
-    return fabsf(a) > GP_PROTECT_EPS ? crm::log_cr(fabsf(a), mt.lg) : 0.0f;
+__device__ __forceinline__ float op_log(float a, const MathTabs& mt, const crm::LogK& K) {
+    return fabsf(a) > GP_PROTECT_EPS ? crm::log_cr(fabsf(a), mt.lg, K) : 0.0f;
 }
 __device__ __forceinline__ float op_sqrt(float a) { return sqrtf(fabsf(a)); }
 __device__ __forceinline__ float op_inv(float a) {
@@ -289,19 +292,22 @@ __device__ __forceinline__ void apply_unary(uint32_t fn, float (&t)[R], const Ma
 #pragma unroll
             for (int j = 0; j < R; ++j) t[j] = -t[j];
         } else if (fn == 1) {
+            const crm::LogK K = crm::log_k();   // (once for the R rows)
 #pragma unroll
-            for (int j = 0; j < R; ++j) t[j] = op_log(t[j], mt);
+            for (int j = 0; j < R; ++j) t[j] = op_log(t[j], mt, K);
         } else {
 #pragma unroll
             for (int j = 0; j < R; ++j) t[j] = op_sqrt(t[j]);
         }
     } else {
         if (fn == 3) {
+            const crm::SinCosK K = crm::sincos_k();
 #pragma unroll
-            for (int j = 0; j < R; ++j) t[j] = crm::sin_cr(t[j], mt.sc);
+            for (int j = 0; j < R; ++j) t[j] = crm::sin_cr(t[j], mt.sc, K);
         } else if (fn == 4) {
+            const crm::SinCosK K = crm::sincos_k();
 #pragma unroll
-            for (int j = 0; j < R; ++j) t[j] = crm::cos_cr(t[j], mt.sc);
+            for (int j = 0; j < R; ++j) t[j] = crm::cos_cr(t[j], mt.sc, K);
         } else {
 #pragma unroll
             for (int j = 0; j < R; ++j) t[j] = tanf(t[j]);
@@ -478,9 +484,10 @@ __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint4* __restri
 //                 for every other instruction the sink slot kEvalRegs, which
 //                 is never read (one store per instruction keeps the
 //                 register array in place)
-//   x bits 16-23  slot of a binary function's second operand (kIBin)
-//   y             a constant's float bits (kIPushC, kIFoldC) or a feature
-//                 index (kIPushX, kIFoldX)
+//   x bits 16-23  slot of a binary function's second operand (kIBin); the
+//                 LDS slot a deep push covers (kIDeep)
+//   y             a constant's float bits (kIPushC, kIFoldC), a feature
+//                 index (kIPushX, kIFoldX) or the slot a copy reads (kIPushS)
 //   z             up to 8 unary functions applied, in order, to the
 //                 instruction's result (4 bits each from the lowest: unary
 //                 index + 1; 0 ends the chain), so that a unary function
@@ -488,6 +495,16 @@ __global__ __launch_bounds__(kBlock) void k_compile(PopView pop, uint4* __restri
 // Stack entries are numbered from the bottom; the top entry lives in
 // registers and entry e below it in slot e.  Slots from kEvalRegs on live in
 // LDS; the instructions that reach them carry kIDeep.
+//
+// A user function (Sec. V: custom function sets) is expanded in place: its
+// arguments are evaluated as usual, its definition's argument references
+// become kIPushS copies of the argument entries, and once the definition has
+// left its value on top, the arguments below it are simply forgotten (the
+// next push overwrites their slots).  A user loss (GP_METRIC_USER_i) is the
+// same expansion around the whole program: kIPushY pushes the row's target
+// first, and the loss function's definition runs on (output, target) last.
+// These stacks reach past the program's own GP_MAX_STACK, into LDS slots
+// kEvalLds .. kEvalLdsUser-1, which launches that may meet them provide.
 // ---------------------------------------------------------------------------
 enum : uint32_t {
     kIPushX = 0,    // push feature
@@ -496,11 +513,19 @@ enum : uint32_t {
     kIFoldX = 9,    // + binary index: top = feature (op) top
     kIFoldC = 16,   // + binary index: top = constant (op) top
     kIUn = 23,      // + unary index: top = f(top)
-    kIDeep = 64     // with kIPushX, kIPushC, kIBin: the slot lives in LDS
+    kIPushS = 40,   // push a copy of the entry in slot y (register or LDS)
+    kIPushY = 41,   // push the row's target
+    kIDeep = 64     // with kIPushX, kIPushC, kIPushS, kIBin: the slot x
+                    // bits 16-23 names lives in LDS
 };
 constexpr int kEvalSlots = GP_MAX_STACK - 1;   // entries below the top
 constexpr int kEvalRegs = 15;                  // slots held in VGPRs (plus the sink)
 constexpr int kEvalLds = kEvalSlots - kEvalRegs;
+// with user functions or a user loss: the target below the program, and a
+// definition's own GP_USER_MAX_STACK values above its arguments
+constexpr int kEvalSlotsUser = GP_MAX_STACK + GP_USER_MAX_STACK;
+constexpr int kEvalLdsUser = kEvalSlotsUser - kEvalRegs;
+constexpr int kCompileDepth = kEvalSlotsUser + 1;   // entries the compiler tracks
 
 __device__ __forceinline__ uint32_t ins_x(uint32_t op, uint32_t wslot, uint32_t rslot) {
     return op | (wslot << 8) | (rslot << 16);
@@ -511,39 +536,115 @@ __device__ __forceinline__ uint32_t ins_x(uint32_t op, uint32_t wslot, uint32_t 
 // function's first operand is fused with it; a unary function is chained
 // onto the instruction before it; a subtree of constants only is evaluated
 // here, once, by the same float32 functions the kernel applies per row, and
-// replaced by one push of its value.
+// replaced by one push of its value.  User functions are expanded from
+// `ud`; loss_fn >= 0 wraps the program in the user loss (GP_OP_USER2 +
+// loss_fn) of (output, target).
 __global__ __launch_bounds__(kBlock) void k_compile_eval(PopView pop, uint4* __restrict__ code,
-                                                          int32_t* __restrict__ clen) {
-    __shared__ uint32_t shadow[GP_MAX_STACK][kBlock];   // start | const-only << 31
-    __shared__ float shadow_v[GP_MAX_STACK][kBlock];    // value of a const-only entry
+                                                          int32_t* __restrict__ clen, UserDefs ud,
+                                                          int32_t loss_fn, int32_t ex_mul, int32_t ex_add) {
+    __shared__ uint32_t shadow[kCompileDepth][kBlock];   // start | const-only << 31
+    __shared__ float shadow_v[kCompileDepth][kBlock];    // value of a const-only entry
     const int32_t p = static_cast<int32_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (p >= pop.P) return;
     const int64_t off = pop.prog_off[p];
     const int32_t L = pop.len[p];
     const uint32_t* pn = pop.nodes + off;
     const float* pc = pop.consts + pop.const_off[p];
-    uint4* out = code + off;
+    uint4* out = code + off * ex_mul + static_cast<int64_t>(p) * ex_add;
     uint32_t* sh = &shadow[0][threadIdx.x];   // entry h at sh[h * kBlock]
     float* shv = &shadow_v[0][threadIdx.x];
     int h = 0;                                // entries on the stack
     int32_t k = 0;                            // instructions emitted
     int chain = 0;                            // unary functions chained on out[k-1]
     const uint32_t sink = static_cast<uint32_t>(kEvalRegs);
-    auto clampe = [](int e) { return min(max(e, 0), GP_MAX_STACK - 1); };
+    auto clampe = [](int e) { return min(max(e, 0), kCompileDepth - 1); };
     // a push of constant v as entry e
     auto push_c = [&](int e, float v) {
         const uint32_t slot = static_cast<uint32_t>(max(e - 1, 0));
         return slot >= sink ? make_uint4(ins_x(kIPushC | kIDeep, sink, slot), __float_as_uint(v), 0u, 0u)
                             : make_uint4(ins_x(kIPushC, slot, 0u), __float_as_uint(v), 0u, 0u);
     };
+    // a push of the value of entry src as entry e
+    auto push_s = [&](int e, int src) {
+        const uint32_t slot = static_cast<uint32_t>(max(e - 1, 0));
+        const uint32_t rs = static_cast<uint32_t>(clampe(src));
+        return slot >= sink ? make_uint4(ins_x(kIPushS | kIDeep, sink, slot), rs, 0u, 0u)
+                            : make_uint4(ins_x(kIPushS, slot, 0u), rs, 0u, 0u);
+    };
     auto emit = [&](uint4 ins) {
         out[k++] = ins;
         chain = 0;
     };
-    for (int32_t i = L - 1; i >= 0; --i) {
-        const uint32_t w = pn[i];
+    // The item source: the program right to left; while a user function is
+    // expanded, its definition right to left.  (i: next program position;
+    // uf: the function being expanded or -1, di its next position, call_h
+    // the stack height when it began, call_ar its arity.)
+    int32_t i = L - 1;
+    int uf = -1, di = 0, call_h = 0, call_ar = 0;
+    bool loss_pending = loss_fn >= 0;
+    if (loss_pending) {
+        // entry 0: the target, under the program's value
+        emit(make_uint4(ins_x(kIPushY, 0u, 0u), 0u, 0u, 0u));
+        sh[0] = 0u;
+        h = 1;
+    }
+    for (;;) {
+        uint32_t w;
+        bool in_def;
+        if (uf >= 0) {
+            if (di < 0) {
+                // end of the expansion: the value replaces the arguments
+                const int base = max(call_h - call_ar, 0);
+                sh[clampe(base) * kBlock] = sh[clampe(base) * kBlock] & 0x7fffffffu;   // the deepest argument's start
+                h = base + 1;
+                uf = -1;
+                continue;
+            }
+            w = ud.nodes[uf][di];
+            in_def = true;
+        } else {
+            if (i < 0) {
+                if (!loss_pending) break;
+                loss_pending = false;
+                uf = kUserFns / 2 + loss_fn;   // the two-argument user functions follow the one-argument ones
+                di = ud.len[uf] - 1;
+                call_h = h;
+                call_ar = 2;
+                continue;
+            }
+            w = pn[i];
+            in_def = false;
+        }
         const uint32_t op = w & 0xffu;
         const uint32_t arg = w >> 8;
+        if (!in_def && is_user_op(op)) {
+            uf = static_cast<int>(op - GP_OP_USER1);
+            di = ud.len[uf] - 1;
+            call_h = h;
+            call_ar = arity(op);
+            --i;
+            continue;
+        }
+        if (in_def && op == GP_OP_VAR) {
+            // argument `arg` of the function: entry call_h - 1 - arg
+            const int e = clampe(h);
+            emit(push_s(e, call_h - 1 - static_cast<int>(arg)));
+            sh[e * kBlock] = static_cast<uint32_t>(k - 1);
+            ++h;
+            --di;
+            continue;
+        }
+        // position and the item before it in the same source (a terminal
+        // fuses only with a built-in binary function of its own source)
+        const int32_t pos = in_def ? di : i;
+        const int32_t last = in_def ? ud.len[uf] - 1 : L - 1;
+        const uint32_t prev = pos >= 1 ? ((in_def ? ud.nodes[uf][pos - 1] : pn[pos - 1]) & 0xffu) : 0u;
+        const float cval = op == GP_OP_CONST ? (in_def ? ud.consts[uf][arg & (GP_USER_MAX_CONSTS - 1)] : pc[arg])
+                                             : 0.0f;
+        auto advance = [&](int n) {
+            if (in_def) di -= n;
+            else i -= n;
+        };
         const int ar = arity(op);
         const int top = clampe(h - 1);
         if (ar == 1) {
@@ -560,17 +661,17 @@ __global__ __launch_bounds__(kBlock) void k_compile_eval(PopView pop, uint4* __r
             } else {
                 emit(make_uint4(ins_x(kIUn + unary_index(op), sink, 0u), 0u, 0u, 0u));
             }
+            advance(1);
             continue;
         }
         if (ar == 0) {
             const uint32_t is_c = op == GP_OP_CONST ? 1u : 0u;
-            const uint32_t prev = i >= 1 ? (pn[i - 1] & 0xffu) : 0u;
-            if (i >= 1 && i != L - 1 && arity(prev) == 2 && h >= 1) {
-                // first operand of the binary function at i-1; the top is the second
+            if (pos >= 1 && pos != last && is_builtin_binary(prev) && h >= 1) {
+                // first operand of the binary function before it; the top is the second
                 const uint32_t fn = binary_index(prev);
                 const uint32_t e2 = sh[top * kBlock];
                 if (is_c && (e2 >> 31)) {
-                    float a[1] = {pc[arg]};
+                    float a[1] = {cval};
                     const float b[1] = {shv[top * kBlock]};
                     apply_binary<1>(fn, a, b);
                     k = static_cast<int32_t>(e2 & 0x7fffffffu);   // drop the operand's instructions
@@ -578,18 +679,18 @@ __global__ __launch_bounds__(kBlock) void k_compile_eval(PopView pop, uint4* __r
                     sh[top * kBlock] = static_cast<uint32_t>(k - 1) | (1u << 31);
                     shv[top * kBlock] = a[0];
                 } else {
-                    emit(is_c ? make_uint4(ins_x(kIFoldC + fn, sink, 0u), __float_as_uint(pc[arg]), 0u, 0u)
+                    emit(is_c ? make_uint4(ins_x(kIFoldC + fn, sink, 0u), __float_as_uint(cval), 0u, 0u)
                               : make_uint4(ins_x(kIFoldX + fn, sink, 0u), arg, 0u, 0u));
                     sh[top * kBlock] = e2 & 0x7fffffffu;
                 }
-                --i;
+                advance(2);
                 continue;
             }
             const int e = clampe(h);
             if (is_c) {
-                emit(push_c(e, pc[arg]));
+                emit(push_c(e, cval));
                 sh[e * kBlock] = static_cast<uint32_t>(k - 1) | (1u << 31);
-                shv[e * kBlock] = pc[arg];
+                shv[e * kBlock] = cval;
             } else {
                 const uint32_t slot = static_cast<uint32_t>(max(e - 1, 0));
                 emit(slot >= sink ? make_uint4(ins_x(kIPushX | kIDeep, sink, slot), arg, 0u, 0u)
@@ -597,6 +698,7 @@ __global__ __launch_bounds__(kBlock) void k_compile_eval(PopView pop, uint4* __r
                 sh[e * kBlock] = static_cast<uint32_t>(k - 1);
             }
             ++h;
+            advance(1);
             continue;
         }
         // binary, operands not fused: the first is the top (entry h-1), the
@@ -618,9 +720,23 @@ __global__ __launch_bounds__(kBlock) void k_compile_eval(PopView pop, uint4* __r
             sh[e2 * kBlock] = second & 0x7fffffffu;
         }
         h = max(h - 1, 0);
+        advance(1);
     }
     clen[p] = k;
 }
+
+// ---------------------------------------------------------------------------
+// k_find_user: raises flag[0] (which the caller zeroes, k_zero_u32) if any
+// of the n nodes is a user function.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_find_user(const uint32_t* __restrict__ nodes, int64_t n,
+                                                       uint32_t* __restrict__ flag) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * kBlock)
+        if (is_user_op(nodes[i] & 0xffu)) flag[0] = 1u;
+}
+
+__global__ void k_zero_u32(uint32_t* __restrict__ p) { p[0] = 0u; }
 
 // ---------------------------------------------------------------------------
 // k_prepare: order programs by length (longest first) and reset the work
@@ -726,10 +842,11 @@ __global__ __launch_bounds__(kBlock) void k_eval(PopView pop, CodeView cv, DataV
     const int64_t N = d.N;
     const int64_t ld = d.ld;
     const float* __restrict__ X = d.X;
-    // stack slots beyond the registers: kEvalLds * R * 64 floats per
-    // wavefront of the block (dynamic LDS, sized at launch)
+    // stack slots beyond the registers: s.lds_slots * R * 64 floats per
+    // wavefront of the block (dynamic LDS, sized at launch: kEvalLds, or
+    // kEvalLdsUser when user functions may be expanded)
     extern __shared__ float ovf_all[];
-    float* ovf = ovf_all + (threadIdx.x >> 6) * (kEvalLds * R * kWave) + lane;
+    float* ovf = ovf_all + (threadIdx.x >> 6) * (s.lds_slots * R * kWave) + lane;
     __shared__ MathTabsLds tabs_lds;
     const MathTabs mt = stage_tabs(tabs_lds);
 
@@ -749,7 +866,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(PopView pop, CodeView cv, DataV
         const int32_t p = ldu(s.order + k);
         const int64_t off = ldu(pop.prog_off + p);
         const int32_t CL = ldu(cv.eclen + p);
-        const uint4* __restrict__ pcode = cv.ecode + off;
+        const uint4* __restrict__ pcode = cv.ecode + off * cv.ex_mul + static_cast<int64_t>(p) * cv.ex_add;
         const int64_t r0 = static_cast<int64_t>(c) * s.chunk;
         const int64_t r1 = min(r0 + s.chunk, N);
 
@@ -844,6 +961,19 @@ __global__ __launch_bounds__(kBlock) void k_eval(PopView pop, CodeView cv, DataV
                     GP_ROWS(ovf[((rslot - kEvalRegs) * R + j) * kWave] = t[j]);
                     GP_ROWS(t[j] = cval);
                 } break;
+                case kIPushS:
+                case kIPushS | kIDeep: {
+                    // (the covered entry is stored first: a copy of the
+                    // entry just covered reads it back)
+                    if (op & kIDeep) GP_ROWS(ovf[((rslot - kEvalRegs) * R + j) * kWave] = t[j]);
+                    if (cy < static_cast<uint32_t>(kEvalRegs)) {
+                        GP_GET(st, cy, v);
+                    } else {
+                        GP_ROWS(v[j] = ovf[((cy - kEvalRegs) * R + j) * kWave]);
+                    }
+                    GP_ROWS(t[j] = v[j]);
+                } break;
+                case kIPushY: GP_ROWS(t[j] = d.y[row[j]]); break;
 #define A0 t[j]
 #define B0 v[j]
                 GP_BIN_CASES(kIBin, GP_GET(st, rslot, v))
@@ -886,6 +1016,11 @@ __global__ __launch_bounds__(kBlock) void k_eval(PopView pop, CodeView cv, DataV
                     } else if constexpr (METRIC == GP_METRIC_MAE) {
                         const double e = static_cast<double>(t[j]) - static_cast<double>(yv);
                         const double term = wv * fabs(e);
+                        acc0 += valid[j] ? term : 0.0;
+                    } else if constexpr (METRIC == GP_METRIC_USER_0) {
+                        // a user loss: the stream already ends in the row loss
+                        (void)yv;
+                        const double term = wv * static_cast<double>(t[j]);
                         acc0 += valid[j] ? term : 0.0;
                     } else if constexpr (METRIC == GP_METRIC_LOGLOSS) {
                         const float z = t[j];
@@ -2090,6 +2225,7 @@ struct DeviceScratch {
     int n_cu = 0;
     int dev = -1;
     std::string arch;
+    bool fixed = false;          // carved from preallocated memory: never grown
 };
 
 std::mutex g_mu;
@@ -2192,6 +2328,10 @@ gp_status check_data(const gp_dataset_dev* d, const char* who, bool need_y) {
 gp_status check_fitness_metric(int metric, const char* who, bool spearman_ok = false) {
     if (gp_metric_larger_is_better(static_cast<gp_metric>(metric)) < 0)
         return fail(GP_ERR_INVALID_ARG, std::string(who) + ": unknown metric");
+    if (metric >= GP_METRIC_USER_0 && metric <= GP_METRIC_USER_3 &&
+        !((user_defined_mask() >> (GP_OP_USER2 + metric - GP_METRIC_USER_0)) & 1u))
+        return fail(GP_ERR_INVALID_ARG, std::string(who) + ": a user loss needs its two-argument user function "
+                                                            "(GP_OP_USER2 + i) defined");
     if (metric == GP_METRIC_SPEARMAN && !spearman_ok)
         return fail(GP_ERR_UNSUPPORTED, std::string(who) + ": Spearman has no derivative or launch configuration "
                                                             "(gp_fitness, generations and evolution compute it)");
@@ -2225,7 +2365,8 @@ int kernel_class(int mode, int metric) {
     case GP_METRIC_RMSE: return 1;
     case GP_METRIC_MAE: return 2;
     case GP_METRIC_LOGLOSS: return 3;
-    default: return 4;
+    case GP_METRIC_PEARSON: return 4;
+    default: return 5;   // user losses
     }
 }
 
@@ -2286,7 +2427,7 @@ gp_status launch_eval_m(const LaunchCfg& cfg, int n_cu, const PopView& pv, const
                         const DataView& dv, const Sched& s, float* out, double* part, hipStream_t st,
                         int64_t node_rows, const Timing& tm) {
     const int block = cfg.wpb * kWave;
-    const size_t lds = static_cast<size_t>(cfg.wpb) * kEvalLds * cfg.R * kWave * sizeof(float);
+    const size_t lds = static_cast<size_t>(cfg.wpb) * s.lds_slots * cfg.R * kWave * sizeof(float);
     auto go = [&](auto kernel) -> gp_status {
         int per_cu = 0;
         GP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds));
@@ -2341,32 +2482,73 @@ gp_status launch_eval(int mode, int metric, const LaunchCfg& cfg, int n_cu, cons
         return launch_eval_m<1, GP_METRIC_LOGLOSS>(cfg, n_cu, pv, cv, dv, s, out, part, st, node_rows, tm);
     case GP_METRIC_PEARSON:
         return launch_eval_m<1, GP_METRIC_PEARSON>(cfg, n_cu, pv, cv, dv, s, out, part, st, node_rows, tm);
+    case GP_METRIC_USER_0:
+    case GP_METRIC_USER_1:
+    case GP_METRIC_USER_2:
+    case GP_METRIC_USER_3:
+        return launch_eval_m<1, GP_METRIC_USER_0>(cfg, n_cu, pv, cv, dv, s, out, part, st, node_rows, tm);
     default: return fail(GP_ERR_UNSUPPORTED, "metric not supported by the fused fitness kernel");
     }
 }
 
-// Scratch sizes one evaluation needs; grows sc's buffers to them.  Called
-// outside any stream capture (it may allocate).
-gp_status reserve(DeviceScratch* sc, int32_t P, int64_t total_nodes, int64_t n_chunks, int mode, int metric) {
-    gp_status rc = grow(reinterpret_cast<void**>(&sc->order), &sc->order_cap, P, sizeof(int32_t));
+// How the evaluation stream expands user functions (Sec. V): the
+// definitions, the loss wrapped around every program (GP_METRIC_USER_i), and
+// the room this takes: program p's stream starts at prog_off[p] * mul +
+// p * add, and the kernel's LDS holds lds_slots stack slots per row.
+struct ExpandPlan {
+    UserDefs defs;
+    int32_t loss_fn = -1;
+    int32_t mul = 1, add = 0;
+    int32_t lds_slots = kEvalLds;
+};
+
+bool is_user_metric(int metric) { return metric >= GP_METRIC_USER_0 && metric <= GP_METRIC_USER_3; }
+
+ExpandPlan expand_plan(int mode, int metric) {
+    ExpandPlan x;
+    user_defs(&x.defs);
+    const uint32_t mask = user_defined_mask();
+    if (mask == 0u) return x;
+    for (int u = 0; u < kUserFns; ++u)
+        if ((mask >> (GP_OP_USER1 + u)) & 1u) x.mul = std::max(x.mul, x.defs.len[u]);
+    if (mode == 1 && is_user_metric(metric)) {
+        x.loss_fn = metric - GP_METRIC_USER_0;
+        x.add = 1 + x.defs.len[kUserFns / 2 + x.loss_fn];
+    }
+    x.lds_slots = kEvalLdsUser;
+    return x;
+}
+
+// Scratch sizes one evaluation needs; grows sc's buffers to them (a fixed
+// scratch must already hold them).  Called outside any stream capture (it may
+// allocate).  The adjoint's instruction stream is reserved unless
+// `adjoint_stream` is false.
+gp_status reserve(DeviceScratch* sc, int32_t P, int64_t total_nodes, int64_t n_chunks, int mode, int metric,
+                  bool adjoint_stream = true, int32_t ex_mul = 1, int32_t ex_add = 0) {
+    auto need = [sc](auto** ptr, size_t* cap, size_t n, size_t elem) -> gp_status {
+        if (!sc->fixed) return grow(reinterpret_cast<void**>(ptr), cap, n, elem);
+        if (*ptr && *cap >= n) return GP_OK;
+        return fail(GP_ERR_BUFFER_TOO_SMALL, "fixed scratch smaller than the evaluation needs");
+    };
+    gp_status rc = need(&sc->order, &sc->order_cap, P, sizeof(int32_t));
     if (rc != GP_OK) return rc;
-    rc = grow(reinterpret_cast<void**>(&sc->code), &sc->code_cap, static_cast<size_t>(total_nodes), sizeof(uint4));
-    if (rc != GP_OK) return rc;
-    rc = grow(reinterpret_cast<void**>(&sc->clen), &sc->clen_cap, P, sizeof(int32_t));
-    if (rc != GP_OK) return rc;
+    if (adjoint_stream) {
+        rc = need(&sc->code, &sc->code_cap, static_cast<size_t>(total_nodes), sizeof(uint4));
+        if (rc != GP_OK) return rc;
+        rc = need(&sc->clen, &sc->clen_cap, P, sizeof(int32_t));
+        if (rc != GP_OK) return rc;
+    }
     // (+1: the evaluation kernel fetches one instruction past a program's end)
-    rc = grow(reinterpret_cast<void**>(&sc->ecode), &sc->ecode_cap, static_cast<size_t>(total_nodes) + 1,
-              sizeof(uint4));
+    rc = need(&sc->ecode, &sc->ecode_cap,
+              static_cast<size_t>(total_nodes) * ex_mul + static_cast<size_t>(P) * ex_add + 1, sizeof(uint4));
     if (rc != GP_OK) return rc;
-    rc = grow(reinterpret_cast<void**>(&sc->eclen), &sc->eclen_cap, P, sizeof(int32_t));
+    rc = need(&sc->eclen, &sc->eclen_cap, P, sizeof(int32_t));
     if (rc != GP_OK) return rc;
     if (mode == 1) {
         const size_t kk = metric == GP_METRIC_PEARSON ? 4 : 1;
-        rc = grow(reinterpret_cast<void**>(&sc->part), &sc->part_cap, static_cast<size_t>(P) * n_chunks * kk,
-                  sizeof(double));
+        rc = need(&sc->part, &sc->part_cap, static_cast<size_t>(P) * n_chunks * kk, sizeof(double));
         if (rc != GP_OK) return rc;
-        rc = grow(reinterpret_cast<void**>(&sc->ystat), &sc->ystat_cap, static_cast<size_t>(n_chunks) * 4,
-                  sizeof(double));
+        rc = need(&sc->ystat, &sc->ystat_cap, static_cast<size_t>(n_chunks) * 4, sizeof(double));
         if (rc != GP_OK) return rc;
     }
     return GP_OK;
@@ -2401,7 +2583,8 @@ gp_status prepare(DeviceScratch* sc, const gp_population_dev* pop, const gp_data
     int64_t chunk = 0, n_chunks = 0;
     gp_status rc = chunking(pop, data, *cfg, &chunk, &n_chunks);
     if (rc != GP_OK) return rc;
-    rc = reserve(sc, pop->n_programs, pop->total_nodes, n_chunks, mode, metric);
+    const ExpandPlan xp = expand_plan(mode, metric);
+    rc = reserve(sc, pop->n_programs, pop->total_nodes, n_chunks, mode, metric, adjoint, xp.mul, xp.add);
     if (rc != GP_OK) return rc;
     // items claimed per atomic: enough that a launch issues about 32 claims
     // per resident wavefront (16 per CU), at most 8
@@ -2409,13 +2592,14 @@ gp_status prepare(DeviceScratch* sc, const gp_population_dev* pop, const gp_data
     const int64_t claims = static_cast<int64_t>(sc->n_cu) * 16 * 32;
     const int32_t batch = static_cast<int32_t>(std::min<int64_t>(8, std::max<int64_t>(1, n_items / claims)));
     *sch = Sched{chunk, static_cast<int32_t>(n_chunks), n_items, sc->order, static_cast<uint32_t*>(sc->counter),
-                 batch};
+                 batch, xp.lds_slots};
     hipLaunchKernelGGL(k_prepare, dim3(1), dim3(1024), 0, st, pop->len, pop->n_programs, sc->order,
                        static_cast<uint32_t*>(sc->counter));
     GP_HIP(hipGetLastError());
     const dim3 cgrid((pop->n_programs + kBlock - 1) / kBlock);
     if (!adjoint || both) {
-        hipLaunchKernelGGL(k_compile_eval, cgrid, dim3(kBlock), 0, st, *pv, sc->ecode, sc->eclen);
+        hipLaunchKernelGGL(k_compile_eval, cgrid, dim3(kBlock), 0, st, *pv, sc->ecode, sc->eclen, xp.defs,
+                           xp.loss_fn, xp.mul, xp.add);
         GP_HIP(hipGetLastError());
     }
     if (adjoint) {
@@ -2423,7 +2607,8 @@ gp_status prepare(DeviceScratch* sc, const gp_population_dev* pop, const gp_data
         GP_HIP(hipGetLastError());
     }
     *cvw = CodeView{adjoint ? sc->code : nullptr, adjoint ? sc->clen : nullptr,
-                    (!adjoint || both) ? sc->ecode : nullptr, (!adjoint || both) ? sc->eclen : nullptr};
+                    (!adjoint || both) ? sc->ecode : nullptr, (!adjoint || both) ? sc->eclen : nullptr, xp.mul,
+                    xp.add};
     return GP_OK;
 }
 
@@ -2453,6 +2638,9 @@ gp_status fitness_impl(DeviceScratch* sc, const gp_population_dev* pop, const gp
                        sch.n_chunks, pop->n_programs, data->n_rows, has_w, fitness, nullptr)
     switch (metric) {
     case GP_METRIC_MAE: GP_FIN(GP_METRIC_MAE); break;
+    case GP_METRIC_USER_0: case GP_METRIC_USER_1: case GP_METRIC_USER_2: case GP_METRIC_USER_3:
+        GP_FIN(GP_METRIC_MAE);   // the weighted mean of the row losses
+        break;
     case GP_METRIC_MSE: GP_FIN(GP_METRIC_MSE); break;
     case GP_METRIC_RMSE: GP_FIN(GP_METRIC_RMSE); break;
     case GP_METRIC_LOGLOSS: GP_FIN(GP_METRIC_LOGLOSS); break;
@@ -3351,7 +3539,8 @@ gp_status gp_generation_run(gp_generation* g, const uint32_t* nodes, const int64
         const gp_population_dev cap_view = stage_view(g, p.node_capacity, p.const_capacity);
         rc = chunking(&cap_view, &g->data, g->cfg, &chunk, &n_chunks);
         if (rc != GP_OK) return rc;
-        rc = reserve(&g->sc, P, p.node_capacity, n_chunks, 1, p.metric);
+        const ExpandPlan xp = expand_plan(1, p.metric);
+        rc = reserve(&g->sc, P, p.node_capacity, n_chunks, 1, p.metric, true, xp.mul, xp.add);
         if (rc != GP_OK) return rc;
         if (spear) {
             // grow the Spearman buffers outside the capture (on this population)
@@ -3549,7 +3738,8 @@ gp_status evo_prepare(gp_evolution_s* e) {
     const gp_population_dev v = evo_view(e, 0);
     gp_status rc = chunking(&v, &e->data, e->cfg, &chunk, &n_chunks);
     if (rc != GP_OK) return rc;
-    rc = reserve(&e->sc, P, e->node_cap, n_chunks, 1, p.metric);
+    const ExpandPlan xp = expand_plan(1, p.metric);
+    rc = reserve(&e->sc, P, e->node_cap, n_chunks, 1, p.metric, true, xp.mul, xp.add);
     if (rc != GP_OK) return rc;
     if (spear) {
         // grow the Spearman buffers outside the capture (on the current population)
@@ -3685,6 +3875,8 @@ gp_status gp_fitness_backward(const gp_population_dev* pop, const gp_dataset_dev
     if (rc != GP_OK) return rc;
     rc = check_fitness_metric(metric, "gp_fitness_backward");
     if (rc != GP_OK) return rc;
+    if (is_user_metric(metric))
+        return fail(GP_ERR_UNSUPPORTED, "gp_fitness_backward: user losses have no derivative here");
     if (pop->n_programs == 0) return GP_OK;
     if (pop->total_consts < 0 || (pop->total_consts > 0 && (!grad_consts || !pop->consts)))
         return fail(GP_ERR_INVALID_ARG, "gp_fitness_backward: grad_consts and consts are needed");
@@ -3696,6 +3888,23 @@ gp_status gp_fitness_backward(const gp_population_dev* pop, const gp_dataset_dev
     DeviceScratch* sc;
     rc = arena(&sc);
     if (rc != GP_OK) return rc;
+    if (user_defined_mask() != 0u) {
+        // user functions have no derivative here: look for them (this
+        // waits for the stream)
+        uint32_t* flag = static_cast<uint32_t*>(sc->counter) + 32;   // (the counter's spare half)
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, flag);
+        GP_HIP(hipGetLastError());
+        const int64_t nb = std::min<int64_t>((pop->total_nodes + kBlock - 1) / kBlock, 4096);
+        hipLaunchKernelGGL(k_find_user, dim3(static_cast<unsigned>(std::max<int64_t>(nb, 1))), dim3(kBlock), 0, st,
+                           pop->nodes, pop->total_nodes, flag);
+        GP_HIP(hipGetLastError());
+        uint32_t found = 0u;
+        GP_HIP(hipMemcpyAsync(&found, flag, sizeof found, hipMemcpyDeviceToHost, st));
+        GP_HIP(hipStreamSynchronize(st));
+        if (found)
+            return fail(GP_ERR_UNSUPPORTED, "gp_fitness_backward: the population uses user functions, which have "
+                                            "no derivative here");
+    }
     PopView pv;
     CodeView cvw;
     DataView dv;

@@ -1,8 +1,10 @@
 // gp_host.cpp -- host side of the library: status text, population
 // generation (Sec. II-A, Sec. III-A) and population validation.
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,6 +19,17 @@ gp_status fail(gp_status st, const std::string& msg) {
     return st;
 }
 gp_status ok() { return GP_OK; }
+
+// ---- user function registry (Sec. V: custom function sets) ----
+static std::mutex g_user_mu;
+static UserDefs g_user{};
+static std::atomic<uint32_t> g_user_mask{0u};
+
+void user_defs(UserDefs* out) {
+    std::lock_guard<std::mutex> lk(g_user_mu);
+    *out = g_user;
+}
+uint32_t user_defined_mask() { return g_user_mask.load(); }
 
 namespace {
 
@@ -51,8 +64,8 @@ struct Gen {
     std::vector<float> consts;
 
     explicit Gen(const gp_init_params& p) : prm(p) {
-        for (uint32_t op = GP_OP_ADD; op < GP_OP_COUNT; ++op) {
-            if (!(p.function_mask & (1u << op))) continue;
+        for (uint32_t op = GP_OP_ADD; op < GP_OP_LIMIT; ++op) {
+            if (!(p.function_mask & (1u << op)) || arity(op) < 1) continue;
             fs.all.push_back(op);
             (arity(op) == 1 ? fs.unary : fs.binary).push_back(op);
         }
@@ -184,14 +197,14 @@ struct Gen {
 gp_status check_init(const gp_init_params& p, const char* who) {
     if (p.n_programs < 0 || p.n_features < 1)
         return fail(GP_ERR_INVALID_ARG, std::string(who) + ": need n_programs >= 0 and n_features >= 1");
-    const uint32_t allowed = ((1u << GP_OP_COUNT) - 1u) & ~3u;
-    if (p.function_mask == 0 || (p.function_mask & ~allowed))
-        return fail(GP_ERR_INVALID_ARG, std::string(who) + ": function_mask must select functions (bits 2..22) only");
+    if (p.function_mask == 0 || (p.function_mask & ~allowed_function_mask()))
+        return fail(GP_ERR_INVALID_ARG, std::string(who) + ": function_mask must select functions (bits 2..22, "
+                                                           "or 24..31 once defined) only");
     if (p.method == GP_INIT_EXACT_LEN) {
         if (p.min_len < 1 || p.max_len < p.min_len || p.max_len > (1 << 20))
             return fail(GP_ERR_INVALID_ARG, std::string(who) + ": need 1 <= min_len <= max_len <= 2^20");
         bool has_binary = false;
-        for (uint32_t op = GP_OP_ADD; op < GP_OP_COUNT; ++op) has_binary |= arity(op) == 2 && ((p.function_mask >> op) & 1u);
+        for (uint32_t op = GP_OP_ADD; op < GP_OP_LIMIT; ++op) has_binary |= arity(op) == 2 && ((p.function_mask >> op) & 1u);
         if (!has_binary && p.max_len > 1)
             return fail(GP_ERR_INVALID_ARG, std::string(who) + ": exact lengths above 1 need a binary function");
     } else if (p.method >= GP_INIT_RHH && p.method <= GP_INIT_GROW) {
@@ -376,6 +389,7 @@ const char* gp_version(void) { return "gp-mi355x 0.1 (gfx950)"; }
 int gp_metric_larger_is_better(gp_metric metric) {
     switch (metric) {
     case GP_METRIC_MAE: case GP_METRIC_MSE: case GP_METRIC_RMSE: case GP_METRIC_LOGLOSS:
+    case GP_METRIC_USER_0: case GP_METRIC_USER_1: case GP_METRIC_USER_2: case GP_METRIC_USER_3:
         return 0;
     case GP_METRIC_PEARSON: case GP_METRIC_SPEARMAN:
         return 1;
@@ -383,6 +397,50 @@ int gp_metric_larger_is_better(gp_metric metric) {
         return -1;
     }
 }
+
+gp_status gp_register_function(uint32_t op, const uint32_t* def, int32_t def_len, const float* consts,
+                               int32_t n_consts) {
+    if (!is_user_op(op))
+        return fail(GP_ERR_INVALID_ARG, "gp_register_function: op must be a user opcode (24..31)");
+    const int ar = arity(op);
+    const int u = static_cast<int>(op - GP_OP_USER1);
+    if (def_len == 0) {
+        std::lock_guard<std::mutex> lk(g_user_mu);
+        g_user.len[u] = 0;
+        g_user_mask.fetch_and(~(1u << op));
+        return ok();
+    }
+    if (!def || def_len < 0 || def_len > GP_USER_MAX_NODES)
+        return fail(GP_ERR_INVALID_ARG, "gp_register_function: need 1 <= def_len <= 32 and a definition");
+    if (n_consts < 0 || n_consts > GP_USER_MAX_CONSTS || (n_consts > 0 && !consts))
+        return fail(GP_ERR_INVALID_ARG, "gp_register_function: need 0 <= n_consts <= 16 and the constants");
+    // a valid prefix list over built-in functions, its arguments and its
+    // constants, on a stack of at most GP_USER_MAX_STACK values
+    int h = 0;
+    for (int32_t i = def_len - 1; i >= 0; --i) {
+        const uint32_t w = def[i], dop = GP_NODE_OP(w), arg = GP_NODE_ARG(w);
+        const int a = dop < GP_OP_COUNT ? arity(dop) : -1;
+        if (a < 0)
+            return fail(GP_ERR_INVALID_PROGRAM, "gp_register_function: a definition uses built-in functions only");
+        if (dop == GP_OP_VAR && arg >= static_cast<uint32_t>(ar))
+            return fail(GP_ERR_INVALID_PROGRAM, "gp_register_function: argument index above the arity");
+        if (dop == GP_OP_CONST && arg >= static_cast<uint32_t>(n_consts))
+            return fail(GP_ERR_INVALID_PROGRAM, "gp_register_function: constant index out of range");
+        if (h < a) return fail(GP_ERR_INVALID_PROGRAM, "gp_register_function: a function lacks operands");
+        h += 1 - a;
+        if (h > GP_USER_MAX_STACK)
+            return fail(GP_ERR_STACK_OVERFLOW, "gp_register_function: the definition needs more than 6 stack values");
+    }
+    if (h != 1) return fail(GP_ERR_INVALID_PROGRAM, "gp_register_function: the definition leaves more than one value");
+    std::lock_guard<std::mutex> lk(g_user_mu);
+    g_user.len[u] = def_len;
+    for (int32_t i = 0; i < GP_USER_MAX_NODES; ++i) g_user.nodes[u][i] = i < def_len ? def[i] : 0u;
+    for (int32_t i = 0; i < GP_USER_MAX_CONSTS; ++i) g_user.consts[u][i] = i < n_consts ? consts[i] : 0.0f;
+    g_user_mask.fetch_or(1u << op);
+    return ok();
+}
+
+int gp_function_defined(uint32_t op) { return is_user_op(op) && ((user_defined_mask() >> op) & 1u) ? 1 : 0; }
 
 gp_status gp_build_population(const gp_init_params* prm, uint32_t* nodes, int64_t nodes_cap,
                               int64_t* prog_off, float* consts, int64_t consts_cap,
@@ -433,6 +491,7 @@ gp_status gp_validate_population(const uint32_t* nodes, const int64_t* prog_off,
                                  int32_t* max_height, int32_t* bad_program) {
     if (n_programs < 0 || n_features < 1 || !prog_off || !const_off || (n_programs > 0 && !nodes))
         return fail(GP_ERR_INVALID_ARG, "gp_validate_population: bad arguments");
+    const uint32_t user_mask = user_defined_mask();
     for (int32_t p = 0; p < n_programs; ++p) {
         const int64_t a = prog_off[p], b = prog_off[p + 1];
         const int64_t nc = const_off[p + 1] - const_off[p];
@@ -450,6 +509,8 @@ gp_status gp_validate_population(const uint32_t* nodes, const int64_t* prog_off,
             const uint32_t op = GP_NODE_OP(w);
             const int ar = arity(op);
             if (ar < 0) return bad(GP_ERR_INVALID_PROGRAM, "unknown opcode");
+            if (is_user_op(op) && !((user_mask >> op) & 1u))
+                return bad(GP_ERR_INVALID_PROGRAM, "user function not defined");
             if (op == GP_OP_VAR && GP_NODE_ARG(w) >= static_cast<uint32_t>(n_features))
                 return bad(GP_ERR_INVALID_PROGRAM, "feature index out of range");
             if (op == GP_OP_CONST && static_cast<int64_t>(GP_NODE_ARG(w)) >= nc)

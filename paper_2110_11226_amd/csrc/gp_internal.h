@@ -21,8 +21,26 @@ namespace gp {
 GP_HD int arity(uint32_t op) {
     if (op <= GP_OP_CONST) return 0;
     if (op <= GP_OP_DIV || (op >= GP_OP_MAX && op <= GP_OP_ATAN2)) return 2;
-    return op < GP_OP_COUNT ? 1 : -1;
+    if (op < GP_OP_COUNT) return 1;
+    // user functions (Sec. V): the arity is fixed by the opcode, whether or
+    // not the function is defined (gp_validate_population checks that)
+    if (op >= GP_OP_USER1 && op < GP_OP_USER2) return 1;
+    if (op >= GP_OP_USER2 && op < GP_OP_LIMIT) return 2;
+    return -1;
 }
+GP_HD bool is_user_op(uint32_t op) { return op >= GP_OP_USER1 && op < GP_OP_LIMIT; }
+// built-in binary functions (the ones with a binary index)
+GP_HD bool is_builtin_binary(uint32_t op) { return op < GP_OP_COUNT && arity(op) == 2; }
+
+// User function definitions as the kernels take them (by value, a kernel
+// argument): definition u (opcode GP_OP_USER1 + u) is nodes[u][0 .. len[u])
+// with constants consts[u][..]; len[u] == 0 when undefined.
+constexpr int kUserFns = GP_OP_LIMIT - GP_OP_USER1;
+struct UserDefs {
+    int32_t len[kUserFns];
+    uint32_t nodes[kUserFns][GP_USER_MAX_NODES];
+    float consts[kUserFns][GP_USER_MAX_CONSTS];
+};
 
 // Index of a binary function among the binary ones (ADD..DIV, MAX..ATAN2 ->
 // 0..6) and of a unary one among the unary ones (NEG..TAN, ABS..CBRT -> 0..13).
@@ -69,6 +87,15 @@ GP_HD float unit(uint32_t word) {
 // Thread-local error text behind gp_last_error().
 gp_status fail(gp_status st, const std::string& msg);
 gp_status ok();
+
+// The process-wide user function registry (gp_register_function): a copy
+// of the definitions, and the bit (1 << op) of every defined opcode.
+void user_defs(UserDefs* out);
+uint32_t user_defined_mask();
+// The built-in functions' bits of function_mask, and every bit a mask may
+// hold now (built-ins plus defined user functions).
+constexpr uint32_t kBuiltinMask = ((1u << GP_OP_COUNT) - 1u) & ~3u;
+inline uint32_t allowed_function_mask() { return kBuiltinMask | user_defined_mask(); }
 
 #if defined(__HIPCC__)
 // Returns GP_ERR_DEVICE with the runtime's message when a HIP call fails.

@@ -62,7 +62,7 @@ struct InitDev {
     int32_t consts_enabled;
     float const_lo, const_hi;
     int32_t n_all, n_un, n_bin;
-    uint8_t all[GP_OP_COUNT], un[GP_OP_COUNT], bin[GP_OP_COUNT];
+    uint8_t all[GP_OP_LIMIT], un[GP_OP_LIMIT], bin[GP_OP_LIMIT];
 };
 
 struct EvolveDev {
@@ -89,11 +89,11 @@ __device__ __forceinline__ uint32_t resolve_gen(uint32_t gen, const uint32_t* d_
 // The function tables, copied to LDS once per block so that a drawn index
 // reads them without local-memory indexing.
 struct FnLds {
-    uint8_t all[GP_OP_COUNT], un[GP_OP_COUNT], bin[GP_OP_COUNT];
+    uint8_t all[GP_OP_LIMIT], un[GP_OP_LIMIT], bin[GP_OP_LIMIT];
 };
 
 __device__ __forceinline__ void load_fns(FnLds& f, const InitDev& in) {
-    for (int i = threadIdx.x; i < GP_OP_COUNT; i += blockDim.x) {
+    for (int i = threadIdx.x; i < GP_OP_LIMIT; i += blockDim.x) {
         f.all[i] = in.all[i];
         f.un[i] = in.un[i];
         f.bin[i] = in.bin[i];
@@ -617,7 +617,7 @@ __global__ __launch_bounds__(kMutBlock) void k_child(
 int64_t donor_bound(const gp_init_params& in) {
     if (in.method == GP_INIT_EXACT_LEN) return static_cast<int64_t>(in.max_len) + 1;
     bool has_binary = false;
-    for (uint32_t op = GP_OP_ADD; op < GP_OP_COUNT; ++op)
+    for (uint32_t op = GP_OP_ADD; op < GP_OP_LIMIT; ++op)
         has_binary |= arity(op) == 2 && ((in.function_mask >> op) & 1u);
     return has_binary ? (int64_t{1} << (in.max_depth + 1)) - 1 : in.max_depth + 1;
 }
@@ -634,8 +634,8 @@ InitDev to_dev(const gp_init_params& p) {
     d.consts_enabled = !(p.const_lo > p.const_hi);
     d.const_lo = p.const_lo;
     d.const_hi = p.const_hi;
-    for (uint32_t op = GP_OP_ADD; op < GP_OP_COUNT; ++op) {
-        if (!(p.function_mask & (1u << op))) continue;
+    for (uint32_t op = GP_OP_ADD; op < GP_OP_LIMIT; ++op) {
+        if (!(p.function_mask & (1u << op)) || arity(op) < 1) continue;
         d.all[d.n_all++] = static_cast<uint8_t>(op);
         if (arity(op) == 1) d.un[d.n_un++] = static_cast<uint8_t>(op);
         else d.bin[d.n_bin++] = static_cast<uint8_t>(op);
@@ -686,15 +686,15 @@ gp_status mutate_check(const gp_evolve_params* ev, const gp_init_params* in, int
     if (ev->max_len < 1) return fail(GP_ERR_INVALID_ARG, std::string(who) + ": max_len must be >= 1");
     if (n_offspring < 0) return fail(GP_ERR_INVALID_ARG, std::string(who) + ": n_offspring < 0");
     if (in->n_features < 1) return fail(GP_ERR_INVALID_ARG, std::string(who) + ": n_features >= 1");
-    const uint32_t allowed = ((1u << GP_OP_COUNT) - 1u) & ~3u;
-    if (in->function_mask == 0 || (in->function_mask & ~allowed))
-        return fail(GP_ERR_INVALID_ARG, std::string(who) + ": function_mask must select functions (bits 2..22) only");
+    if (in->function_mask == 0 || (in->function_mask & ~allowed_function_mask()))
+        return fail(GP_ERR_INVALID_ARG, std::string(who) + ": function_mask must select functions (bits 2..22, "
+                                                           "or 24..31 once defined) only");
     if (in->method == GP_INIT_EXACT_LEN) {
         if (in->min_len < 1 || in->max_len < in->min_len || in->max_len > (1 << 20))
             return fail(GP_ERR_INVALID_ARG, std::string(who) + ": need 1 <= min_len <= max_len <= 2^20");
         if (donor_bound(*in) > 1 && in->max_len > 1) {
             bool has_binary = false;
-            for (uint32_t op = GP_OP_ADD; op < GP_OP_COUNT; ++op)
+            for (uint32_t op = GP_OP_ADD; op < GP_OP_LIMIT; ++op)
                 has_binary |= arity(op) == 2 && ((in->function_mask >> op) & 1u);
             if (!has_binary)
                 return fail(GP_ERR_INVALID_ARG, std::string(who) + ": exact lengths above 1 need a binary function");
