@@ -88,24 +88,76 @@ def committed_traffic():
     return float(val.group(1))
 
 
-def cpu_baseline(host, X, y, metric, budget_rows):
+def host_threads():
+    """(threads the oracle runs on, the host's core count as nproc reports
+    it): every core this process may use, unless OMP_NUM_THREADS caps it."""
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cap = os.environ.get("OMP_NUM_THREADS")
+    threads = min(nproc, int(cap)) if cap and cap.isdigit() and int(cap) > 0 else nproc
+    return threads, nproc
+
+
+def cpu_baseline(host, X, y, metric, budget_rows, single_rows=2048):
     """The oracle as it stands, timed on this host's cores over every program
-    and an evenly spaced row subsample."""
+    and an evenly spaced row subsample; and on one core over a smaller one."""
     import oracle
     N = X.shape[1]
-    stride = max(1, N // budget_rows)
-    idx = np.arange(0, N, stride)[:budget_rows]
-    Xs = np.ascontiguousarray(X[:, idx])
-    ys = np.ascontiguousarray(y[idx])
     opop = oracle.Population(host.nodes, host.prog_off, host.consts, host.const_off, host.length)
-    cores = min(16, os.cpu_count() or 1)
-    t0 = time.perf_counter()
-    oracle.fitness(opop, Xs, ys, None, metric, n_threads=cores, with_f64=False)
-    dt = time.perf_counter() - t0
-    gops = float(host.length.astype(np.int64).sum()) * len(idx) / dt
-    return {"value": gops, "unit": "GPops/s", "cores": cores, "kind": "oracle",
-            "sample": f"all {host.n_programs} programs x {len(idx)} rows (every {stride}th row), "
-                      f"float32 path, {dt:.1f} s on {cores} threads"}
+    sum_len = float(host.length.astype(np.int64).sum())
+    threads, nproc = host_threads()
+
+    def timed(rows, n_threads):
+        stride = max(1, N // rows)
+        idx = np.arange(0, N, stride)[:rows]
+        Xs, ys = np.ascontiguousarray(X[:, idx]), np.ascontiguousarray(y[idx])
+        t0 = time.perf_counter()
+        oracle.fitness(opop, Xs, ys, None, metric, n_threads=n_threads, with_f64=False)
+        dt = time.perf_counter() - t0
+        return sum_len * len(idx) / dt, len(idx), stride, dt
+
+    gops, n, stride, dt = timed(budget_rows, threads)
+    g1, n1, s1, dt1 = timed(single_rows, 1)
+    return {"value": gops, "unit": "GPops/s", "cores": threads, "nproc": nproc, "kind": "oracle",
+            "sample": f"all {host.n_programs} programs x {n} rows (every {stride}th row), float32 path, "
+                      f"{dt:.1f} s on {threads} threads (nproc {nproc})",
+            "single_core": {"value": g1, "unit": "GPops/s", "cores": 1,
+                            "sample": f"all {host.n_programs} programs x {n1} rows (every {s1}th row), "
+                                      f"{dt1:.1f} s"}}
+
+
+def parity_sample(gp, torch, host, X, y, metric, rows=4096):
+    """The step's population on an evenly spaced row sample of its dataset:
+    every program's outputs against the oracle's float32 evaluation (bit for
+    bit), and every program's fitness on those rows against the oracle's
+    float32-path and float64 fitness."""
+    import oracle
+    N = X.shape[1]
+    idx = np.linspace(0, N - 1, rows).astype(np.int64)
+    Xs, ys = np.ascontiguousarray(X[:, idx]), np.ascontiguousarray(y[idx])
+    pop = gp.DevicePopulation(host, n_features=X.shape[0])
+    data = gp.DeviceDataset(Xs, ys)
+    out = gp.evaluate(pop, data)
+    fit = gp.fitness(pop, data, metric)
+    torch.cuda.synchronize()
+    got, gfit = out.cpu().numpy(), fit.cpu().numpy().astype(np.float64)
+    threads, _ = host_threads()
+    opop = oracle.Population(host.nodes, host.prog_off, host.consts, host.const_off, host.length)
+    ref = oracle.evaluate_f32(opop, Xs, n_threads=threads)
+    same = (got.view(np.uint32) == ref.view(np.uint32)) | (np.isnan(got) & np.isnan(ref))
+    f32p, f64 = oracle.fitness(opop, Xs, ys, None, metric, n_threads=threads)
+    ref32 = f32p.astype(np.float32).astype(np.float64)
+    fin = np.isfinite(ref32)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        e32 = np.abs(gfit - ref32) / np.abs(ref32)
+        e64 = np.abs(gfit - f64) / np.abs(f64)
+    m32, m64 = fin & np.isfinite(e32), fin & np.isfinite(e64)
+    return {"rows": int(rows), "programs": int(host.n_programs), "outputs_checked": int(got.size),
+            "outputs_bit_exact": int(same.sum()), "outputs_excluded": 0,
+            "fitness_checked": int(fin.sum()), "fitness_excluded": 0,
+            "fitness_nonfinite_class_match": bool(np.array_equal(np.isfinite(gfit), fin)),
+            "max_rel_err_vs_oracle_f32": float(e32[m32].max()) if m32.any() else 0.0,
+            "max_rel_err_vs_f64": float(e64[m64].max()) if m64.any() else 0.0,
+            "tolerance": "outputs bit-exact; fitness 1e-4 relative"}
 
 
 def op_mix(host, gops):
@@ -133,7 +185,7 @@ CONFIGS = [
 ]
 
 
-def config_table(gp, torch, oracle_rows=65_536):
+def config_table(gp, torch, oracle_rows=16_384):
     """gp_fitness throughput on each workload configuration: autotuned, 3
     warm-up calls, then the median of `runs` event-timed calls; the literal
     and op-mix fractions; the oracle on every program over an evenly spaced
@@ -169,8 +221,13 @@ def config_table(gp, torch, oracle_rows=65_536):
             row["adjoint"] = adjoint_ratio(gp, torch)
         log(f"[bench] {c['name']}: {t:.3f} ms, {gops:.3g} GPops/s ({100 * gops / PEAK_FP32_VALU:.2f}% of 157.3 T, "
             f"{100 * row['op_mix']['frac']:.1f}% of the op-mix ceiling)")
-        row["oracle"] = cpu_baseline(host, X, y, c["metric"], min(oracle_rows, c["rows"]))
+        row["oracle"] = cpu_baseline(host, X, y, c["metric"], min(oracle_rows, c["rows"]),
+                                     single_rows=min(1024, c["rows"]))
         log(f"[bench] {c['name']} oracle: {row['oracle']['value']:.3g} GPops/s on {row['oracle']['cores']} threads")
+        row["parity"] = parity_sample(gp, torch, host, X, y, c["metric"], rows=min(4096, c["rows"]))
+        log(f"[bench] {c['name']} parity: {row['parity']['outputs_bit_exact']} of "
+            f"{row['parity']['outputs_checked']} outputs bit-exact, max fitness rel err vs f64 "
+            f"{row['parity']['max_rel_err_vs_f64']:.2e}")
         out.append(row)
         del pop, data, fit, X, y
     return out
@@ -295,6 +352,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="pagie-16M", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true", help="skip the oracle parity sample")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-arith", action="store_true", help="skip the add/sub/mul-only population")
@@ -308,7 +366,7 @@ def main():
                     help="only the adjoint / forward ratio on the differentiation workload (for profiling)")
     ap.add_argument("--configs", action="store_true",
                     help="instead of the step, measure gp_fitness on every workload configuration")
-    ap.add_argument("--cpu-rows", type=int, default=196_608)
+    ap.add_argument("--cpu-rows", type=int, default=32_768)
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache (JSON lines): loaded if present, written after tuning")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -426,6 +484,16 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a row subsample")
         base = cpu_baseline(host, X, y, metric, args.cpu_rows)
+        log(f"[bench] oracle {base['value']:.3g} GPops/s on {base['cores']} threads, "
+            f"{base['single_core']['value']:.3g} on one")
+
+    par = None
+    if not args.no_parity:
+        log("[bench] parity on a row sample")
+        par = parity_sample(gp, torch, host, X, y, metric)
+        log(f"[bench] parity: {par['outputs_bit_exact']} of {par['outputs_checked']} outputs bit-exact, "
+            f"max fitness rel err {par['max_rel_err_vs_oracle_f32']:.2e} (oracle f32), "
+            f"{par['max_rel_err_vs_f64']:.2e} (f64)")
 
     traffic = committed_traffic() if args.workload == "pagie-16M" else None
     line = {
@@ -463,6 +531,7 @@ def main():
         "spearman": spear,
         "adjoint": adj,
         "cpu_baseline": base,
+        "parity": par,
     }
     print(json.dumps(line), flush=True)
 
