@@ -362,6 +362,28 @@ gp_status gp_evaluate(const gp_population_dev* pop, const gp_dataset_dev* data,
 gp_status gp_fitness(const gp_population_dev* pop, const gp_dataset_dev* data,
                      gp_metric metric, float* fitness, void* stream);
 
+/* gp_fitness for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels, launch configuration and result as gp_fitness, with the
+ * scratch (work counter, length order, instruction stream, per-chunk
+ * partial sums) taken from a static 64 MiB device array that the library
+ * holds on every device it runs on until the process ends.  It allocates
+ * nothing on the device (no hipMalloc, hipFree or allocating library call)
+ * and needs
+ *   256 + 2 a(4 P) + a(16 (total_nodes m + P u + 1)) + a(8 P C k) + a(32 C)
+ * bytes, a(n) = n rounded up to 256, C = the launch's row chunks
+ * (ceil(n_rows / (tiles_per_chunk * 64 * rows_per_lane)), gp_get_launch_config),
+ * k = 4 for PEARSON else 1, m = 1 (or, while user functions are defined,
+ * the longest definition's length), u = 0 (for a user loss, 1 + its
+ * definition's length); above 64 MiB it returns GP_ERR_INVALID_ARG and
+ * launches nothing.  Metrics: MAE, MSE, RMSE, LOGLOSS, PEARSON (SPEARMAN:
+ * GP_ERR_UNSUPPORTED).  Every call on a device shares that device's array
+ * and overwrites it: calls that overlap on one device (other streams, other
+ * threads' work in flight) race; a call ordered after another on the same
+ * stream is safe.  The first call on a device looks up its array's address
+ * (hipGetSymbolAddress) and its properties. */
+gp_status gp_fitness_noalloc(const gp_population_dev* pop, const gp_dataset_dev* data,
+                             gp_metric metric, float* fitness, void* stream);
 
 /* Tournament selection (Sec. III-C1): tournament t draws tournament_size
  * program indices with replacement, draw d being floor(word * n / 2^32) for

@@ -7,7 +7,7 @@ library raises ImportError.
 """
 from ._binding import (  # noqa: F401
     DeviceDataset, DevicePopulation, GPError, HostPopulation, build_population, evaluate,
-    fitness, fitness_backward, larger_is_better, metric_id, shutdown, tournament,
+    fitness, fitness_backward, fitness_noalloc, larger_is_better, metric_id, shutdown, tournament,
     validate_population, version, get_launch_config, set_launch_config, set_spearman_workset,
     profile_enable, profile_read, autotune, autotune_save, autotune_load, autotune_clear, Generation,
     plan_generation, mutate, GENOPS, plan_generation_device, mutate_device, DeviceOffspring, FUNCS_ALL, Evolution,

@@ -78,6 +78,8 @@ _validate = _sig("gp_validate_population", [_vp, _vp, _vp, _i32, _i32, _vp, _vp]
 _evaluate = _sig("gp_evaluate", [ctypes.POINTER(PopulationDev), ctypes.POINTER(DatasetDev), _vp, _vp])
 _fitness = _sig("gp_fitness", [ctypes.POINTER(PopulationDev), ctypes.POINTER(DatasetDev), ctypes.c_int,
                                _vp, _vp])
+_fitness_noalloc = _sig("gp_fitness_noalloc", [ctypes.POINTER(PopulationDev), ctypes.POINTER(DatasetDev),
+                                                ctypes.c_int, _vp, _vp])
 _register_fn = _sig("gp_register_function", [_u32, _vp, _i32, _vp, _i32])
 _fn_defined = _sig("gp_function_defined", [_u32])
 _tournament = _sig("gp_tournament", [_vp, _vp, _i32, ctypes.c_int, _f32, _i32, _i32, _u64, _u64, _vp, _vp])
@@ -140,7 +142,7 @@ _backward = _sig("gp_fitness_backward", [ctypes.POINTER(PopulationDev), ctypes.P
                                          ctypes.c_int, _vp, _vp, _vp, _vp])
 
 EXPORTED = ["gp_last_error", "gp_version", "gp_shutdown", "gp_metric_larger_is_better",
-            "gp_build_population", "gp_validate_population", "gp_evaluate", "gp_fitness",
+            "gp_build_population", "gp_validate_population", "gp_evaluate", "gp_fitness", "gp_fitness_noalloc",
             "gp_register_function", "gp_function_defined",
             "gp_tournament", "gp_fitness_backward", "gp_get_launch_config", "gp_set_launch_config",
             "gp_profile_enable", "gp_profile_read", "gp_autotune", "gp_autotune_save", "gp_autotune_load",
@@ -409,6 +411,17 @@ def register_function(op, nodes=None, consts=()):
 
 def function_defined(op) -> bool:
     return bool(_fn_defined(int(op)))
+
+
+def fitness_noalloc(pop: DevicePopulation, data: DeviceDataset, metric="mse", out=None, stream=None):
+    """gp_fitness_noalloc: fitness with the library's static device scratch
+    (no device allocation inside the call; `out` may be preallocated)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(pop.n_programs, dtype=torch.float32, device=data.X.device)
+    _check(_fitness_noalloc(ctypes.byref(pop.view), ctypes.byref(data.view), metric_id(metric), _tptr(out),
+                            _stream(stream)), "gp_fitness_noalloc")
+    return out
 
 
 def tournament(fit, length, metric="mse", parsimony=0.0, tournament_size=20, n_tournaments=None,

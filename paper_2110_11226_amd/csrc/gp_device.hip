@@ -2651,6 +2651,61 @@ gp_status fitness_impl(DeviceScratch* sc, const gp_population_dev* pop, const gp
     return GP_OK;
 }
 
+// ---- fitness without allocation ----
+// One static array per device serves every gp_fitness_noalloc call on it.
+// In host code `scratch` names a host-side stand-in: the device address comes
+// from hipGetSymbolAddress, once per device, and only that address reaches
+// kernels.
+constexpr size_t kNoAllocBytes = size_t{64} << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+constexpr int kNoAllocMaxDevices = 64;
+struct NoAllocDevice {
+    unsigned char* ptr = nullptr;   // this device's copy of `scratch`
+    int n_cu = 0;
+    char arch[64] = {};
+};
+NoAllocDevice g_noalloc[kNoAllocMaxDevices];
+
+size_t align256(size_t n) { return (n + 255) & ~size_t{255}; }
+
+// Carves the scratch of one fitness evaluation out of the device's array into
+// sc (caps exact, fixed: reserve() checks instead of growing).  Fails if the
+// evaluation needs more than kNoAllocBytes.
+gp_status noalloc_carve(unsigned char* base, DeviceScratch* sc, int32_t P, int64_t total_nodes, int64_t n_chunks,
+                        int metric) {
+    const size_t kk = metric == GP_METRIC_PEARSON ? 4 : 1;
+    const ExpandPlan xp = expand_plan(1, metric);
+    const size_t n_code = static_cast<size_t>(total_nodes) * xp.mul + static_cast<size_t>(P) * xp.add + 1;
+    const size_t n_part = static_cast<size_t>(P) * static_cast<size_t>(n_chunks) * kk;
+    const size_t n_ystat = static_cast<size_t>(n_chunks) * 4;
+    const size_t bytes = 256 + align256(static_cast<size_t>(P) * sizeof(int32_t)) * 2 +
+                         align256(n_code * sizeof(uint4)) + align256(n_part * sizeof(double)) +
+                         align256(n_ystat * sizeof(double));
+    if (bytes > kNoAllocBytes)
+        return fail(GP_ERR_INVALID_ARG, "gp_fitness_noalloc: this evaluation needs " + std::to_string(bytes) +
+                                            " bytes of scratch, above the limit of " +
+                                            std::to_string(kNoAllocBytes) + " (use gp_fitness)");
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        unsigned char* q = base + off;
+        off += align256(n);
+        return q;
+    };
+    sc->counter = take(256);
+    sc->order = reinterpret_cast<int32_t*>(take(static_cast<size_t>(P) * sizeof(int32_t)));
+    sc->order_cap = static_cast<size_t>(P);
+    sc->eclen = reinterpret_cast<int32_t*>(take(static_cast<size_t>(P) * sizeof(int32_t)));
+    sc->eclen_cap = static_cast<size_t>(P);
+    sc->ecode = reinterpret_cast<uint4*>(take(n_code * sizeof(uint4)));
+    sc->ecode_cap = n_code;
+    sc->part = reinterpret_cast<double*>(take(n_part * sizeof(double)));
+    sc->part_cap = n_part;
+    sc->ystat = reinterpret_cast<double*>(take(n_ystat * sizeof(double)));
+    sc->ystat_cap = n_ystat;
+    sc->fixed = true;
+    return GP_OK;
+}
+
 gp_status tournament_impl(const float* fitness, const int32_t* len, int32_t P, int larger, float parsimony,
                           int32_t k, int32_t T, uint64_t seed, uint32_t gen, const uint32_t* gen_dev,
                           int32_t* winners, hipStream_t st) {
@@ -3406,6 +3461,47 @@ gp_status gp_fitness(const gp_population_dev* pop, const gp_dataset_dev* data, g
     Timing tm;
     tm.profile = true;
     return fitness_impl(sc, pop, data, metric, fitness, static_cast<hipStream_t>(stream), nullptr, tm);
+}
+
+gp_status gp_fitness_noalloc(const gp_population_dev* pop, const gp_dataset_dev* data, gp_metric metric,
+                             float* fitness, void* stream) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    gp_status rc = check_pop(pop, "gp_fitness_noalloc");
+    if (rc != GP_OK) return rc;
+    rc = check_data(data, "gp_fitness_noalloc", true);
+    if (rc != GP_OK) return rc;
+    if (!fitness) return fail(GP_ERR_INVALID_ARG, "gp_fitness_noalloc: fitness is NULL");
+    rc = check_fitness_metric(metric, "gp_fitness_noalloc");
+    if (rc != GP_OK) return rc;
+    if (pop->n_programs == 0) return GP_OK;
+    int dev = 0;
+    GP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocMaxDevices)
+        return fail(GP_ERR_UNSUPPORTED, "gp_fitness_noalloc: device index above the supported 64");
+    NoAllocDevice& nd = g_noalloc[dev];
+    if (!nd.ptr) {   // first call on this device (which is current)
+        void* p = nullptr;
+        GP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(GP_ERR_DEVICE, "gp_fitness_noalloc: no device address for the scratch array");
+        hipDeviceProp_t prop;
+        GP_HIP(hipGetDeviceProperties(&prop, dev));
+        nd.n_cu = prop.multiProcessorCount;
+        size_t i = 0;
+        for (; i + 1 < sizeof nd.arch && prop.gcnArchName[i] && prop.gcnArchName[i] != ':'; ++i)
+            nd.arch[i] = prop.gcnArchName[i];
+        nd.arch[i] = 0;
+        nd.ptr = static_cast<unsigned char*>(p);
+    }
+    DeviceScratch sc;
+    sc.n_cu = nd.n_cu;
+    sc.dev = dev;
+    sc.arch = nd.arch;
+    const LaunchCfg cfg = pick_cfg(sc, data->n_features, data->n_rows, pop->n_programs, kernel_class(1, metric));
+    int64_t chunk = 0, n_chunks = 0;
+    if ((rc = chunking(pop, data, cfg, &chunk, &n_chunks)) != GP_OK) return rc;
+    if ((rc = noalloc_carve(nd.ptr, &sc, pop->n_programs, pop->total_nodes, n_chunks, metric)) != GP_OK)
+        return rc;
+    return fitness_impl(&sc, pop, data, metric, fitness, static_cast<hipStream_t>(stream), &cfg, Timing{});
 }
 
 gp_status gp_tournament(const float* fitness, const int32_t* len, int32_t n_programs, gp_metric metric,
