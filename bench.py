@@ -44,7 +44,21 @@ ISSUE_RATE = 39.3e12          # VALU lane-instruction slots per second: 256 CUs 
 # SQ CUBE TANH ATAN CBRT.
 OP_COST = (0.0, 0.0, 0.5, 0.5, 0.5, 10.0, 0.5, 5.0, 8.0, 5.0, 5.0, 14.0, 1.0, 1.0, 20.0, 0.5, 5.0, 10.0,
            0.5, 1.0, 10.0, 12.0, 10.0)
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2110_11226_amd", "csrc", "gp_device.hip")
+# The same table measured on this kernel (`--op-costs` under rocprofv3
+# SQ_INSTS_VALU): VALU lane-instructions per row for each function itself,
+# without dispatch.  A unary function's cost is its chain population's VALU
+# per node-row less the negation chain's plus 1 (one instruction for neg); a
+# binary function's is twice its fold population's excess over add's plus 1
+# (a fold instruction covers two nodes).  add, sub and mul are one
+# instruction per row (no packed FP32); sin, cos and log carry the double
+# evaluation of their correctly rounded form.
+OP_COST_MEASURED = (0.0, 0.0, 1.0, 1.0, 1.0, 12.9, 1.0, 32.9, 15.9, 29.7, 28.9, 28.7, 5.9, 5.9, 38.6, 1.2,
+                    13.1, 13.1, 1.2, 2.2, 9.8, 16.1, 15.1)
+# what the evaluation kernel is built from: its source, the headers it
+# includes and the build flags
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2110_11226_amd", *f) for f in
+                  (("csrc", "gp_device.hip"), ("csrc", "gp_crmath.h"), ("csrc", "gp_crmath_tables.h"),
+                   ("csrc", "gp_internal.h"), ("build.py",))] + [os.path.join(ROOT, "include", "gp.h")]
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_eval_pagie-16M_traffic.md")
 
 WORKLOADS = {
@@ -71,8 +85,11 @@ def make_data(wl):
 
 
 def source_sha():
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def committed_traffic():
@@ -161,13 +178,21 @@ def parity_sample(gp, torch, host, X, y, metric, rows=4096):
 
 
 def op_mix(host, gops):
-    """The population's op-mix ceiling (ISSUE_RATE / mean cost per node-row
-    from OP_COST) and the fraction of it that `gops` reaches."""
+    """The population's op-mix ceiling (ISSUE_RATE / mean cost per node-row)
+    and the fraction of it that `gops` reaches, from the measured cost table
+    (OP_COST_MEASURED); the frozen table's figures (OP_COST) beside them."""
     ops = np.asarray(host.nodes, np.uint32) & 0xFF
     hist = np.bincount(ops, minlength=len(OP_COST))
-    per = float((hist[:len(OP_COST)] * np.asarray(OP_COST)).sum() / hist.sum())
-    ceiling = ISSUE_RATE / per
-    return {"lane_slots_per_node_row": per, "ceiling": ceiling, "unit": "GPops/s", "frac": gops / ceiling}
+
+    def ceil(table):
+        per = float((hist[:len(table)] * np.asarray(table)).sum() / hist.sum())
+        return per, ISSUE_RATE / per
+
+    per, ceiling = ceil(OP_COST_MEASURED)
+    per0, ceiling0 = ceil(OP_COST)
+    return {"lane_slots_per_node_row": per, "ceiling": ceiling, "unit": "GPops/s", "frac": gops / ceiling,
+            "table": "measured (VALU per row of each function, no dispatch)",
+            "frozen": {"lane_slots_per_node_row": per0, "ceiling": ceiling0, "frac": gops / ceiling0}}
 
 
 CONFIGS = [
@@ -256,6 +281,64 @@ def arith_only(gp, data, wl, steps):
     return {"population": "exact_len 1-200 over {add, sub, mul}, seed 2113", "sum_len": sum_len,
             "kernel_avg_ms": k, "value": gops, "unit": "GPops/s", "frac": gops / PEAK_FP32_VALU,
             "op_mix": op_mix(host, gops), "launch": list(launch)}
+
+
+OPCOST_UNARY = ("neg", "log", "sqrt", "sin", "cos", "tan", "exp", "tanh", "atan", "cbrt", "abs", "inv", "sq", "cube")
+OPCOST_BINARY = ("add", "sub", "mul", "div", "max", "min", "atan2")
+OPCODE = {"add": 2, "sub": 3, "mul": 4, "div": 5, "neg": 6, "log": 7, "sqrt": 8, "sin": 9, "cos": 10, "tan": 11,
+          "max": 12, "min": 13, "atan2": 14, "abs": 15, "exp": 16, "inv": 17, "sq": 18, "cube": 19, "tanh": 20,
+          "atan": 21, "cbrt": 22}
+
+
+def op_cost_populations():
+    """Single-function populations for the per-function cost breakdown:
+    'unary_f': x0 under a chain of 100 f (8 chained per instruction);
+    'fold_f': f(x0, f(x1, f(x0, ... x1))), every terminal fused with its
+    binary function (one instruction per two nodes); 'bin_f': f(f(x0, x1),
+    f(f(x0, x1), ...)), the outer f of each level reading its second
+    operand from the stack.  256 copies of one program each."""
+    V0, V1 = 0, 1 << 8   # GP_NODE(VAR, 0), GP_NODE(VAR, 1)
+    out = []
+    for f in OPCOST_UNARY:
+        out.append(("unary_" + f, [OPCODE[f]] * 100 + [V0]))
+    for f in OPCOST_BINARY:
+        fold = []
+        for i in range(50):
+            fold += [OPCODE[f], V0 if i % 2 == 0 else V1]
+        out.append(("fold_" + f, fold + [V1]))
+        out.append(("bin_" + f, [OPCODE[f], OPCODE[f], V0, V1] * 25 + [V0]))
+    return out
+
+
+def op_costs(gp, torch, rows=1 << 20):
+    """One MSE fitness dispatch per single-function population on Pagie
+    rows (launch configuration 4 rows per lane, 2 feature registers, 16
+    tiles, 4 waves), in the order of op_cost_populations: the kernel time
+    and node-rows of each (run under rocprofv3 --pmc to read the
+    instruction counters of each dispatch)."""
+    import synth
+    X, y = synth.pagie(rows, seed=11229)
+    data = gp.DeviceDataset(X, y)
+    gp.set_launch_config((4, 2, 16, 4))
+    gp.profile_enable(True)
+    res = []
+    try:
+        for name, prog in op_cost_populations():
+            L, P = len(prog), 256
+            nodes = np.tile(np.asarray(prog, np.uint32), P)
+            host = gp.HostPopulation(nodes, np.arange(P + 1, dtype=np.int64) * L, np.zeros(1, np.float32),
+                                     np.zeros(P + 1, np.int64), np.full(P, L, np.int32))
+            pop = gp.DevicePopulation(host, n_features=2)
+            _, ms0, _ = gp.profile_read()
+            gp.fitness(pop, data, "mse")
+            torch.cuda.synchronize()
+            _, ms1, _ = gp.profile_read()
+            res.append({"case": name, "nodes": L, "kernel_ms": ms1 - ms0, "node_rows": P * L * rows})
+            log(f"[bench] {name}: {ms1 - ms0:.3f} ms")
+    finally:
+        gp.set_launch_config(None)
+        gp.profile_enable(False)
+    return res
 
 
 def loop_generation_time(gp, torch, n_gen=10):
@@ -364,6 +447,8 @@ def main():
                     help="only the generation-loop timing (host vs device genetic operations; for profiling)")
     ap.add_argument("--only-adjoint", action="store_true",
                     help="only the adjoint / forward ratio on the differentiation workload (for profiling)")
+    ap.add_argument("--op-costs", action="store_true",
+                    help="only the single-function populations of the per-function cost breakdown")
     ap.add_argument("--configs", action="store_true",
                     help="instead of the step, measure gp_fitness on every workload configuration")
     ap.add_argument("--cpu-rows", type=int, default=32_768)
@@ -394,6 +479,9 @@ def main():
         del src, dst
     if args.configs:
         print(json.dumps({"configs": config_table(gp, torch)}), flush=True)
+        return 0
+    if args.op_costs:
+        print(json.dumps({"op_costs": op_costs(gp, torch)}), flush=True)
         return 0
     if args.only_loop:
         loop = loop_generation_time(gp, torch)
@@ -524,7 +612,8 @@ def main():
                      "traffic": traffic,
                      "kernel": "k_eval (persistent fused evaluation + MSE row loss + wave reduction)",
                      "kernel_avg_ms": kern_avg_ms, "kernel_timed_by": tm["timed_by"],
-                     "ops_per_launch": ops_launch, "op": "one program node evaluated on one row"},
+                     "ops_per_launch": ops_launch, "op": "one program node evaluated on one row",
+                     "kernel_source_sha256": source_sha()},
         "op_mix": op_mix(host, achieved),
         "arith_only": arith,
         "generation_loop": loop,

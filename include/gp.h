@@ -370,7 +370,7 @@ gp_status gp_fitness(const gp_population_dev* pop, const gp_dataset_dev* data,
  * holds on every device it runs on until the process ends.  It allocates
  * nothing on the device (no hipMalloc, hipFree or allocating library call)
  * and needs
- *   256 + 2 a(4 P) + a(16 (total_nodes m + P u + 1)) + a(8 P C k) + a(32 C)
+ *   1024 + 2 a(4 P) + a(16 (total_nodes m + P u + 1)) + a(8 P C k) + a(32 C)
  * bytes, a(n) = n rounded up to 256, C = the launch's row chunks
  * (ceil(n_rows / (tiles_per_chunk * 64 * rows_per_lane)), gp_get_launch_config),
  * k = 4 for PEARSON else 1, m = 1 (or, while user functions are defined,

@@ -1394,7 +1394,7 @@ int orc_build_population(int32_t n_programs, int32_t n_features, int32_t method,
 /* of the float32 program, whose protected branches and values are the ones   */
 /* a float32 evaluation takes (reading; with mc_u > 0 only the sweep's        */
 /* partials and seed are perturbed then).                                     */
-/* Programs longer than 4096 nodes get NaN fitness and derivatives.          */
+/* Any program length: the per-thread buffers take the longest program.      */
 /* ------------------------------------------------------------------------ */
 static double local_partial(int op, int which, double a, double b, double out)
 {
@@ -1490,7 +1490,6 @@ static double forward_row(const uint32_t *pn, int64_t L, const float *pc, const 
     return val[0];
 }
 
-#define ORC_GRAD_MAX_LEN 4096
 
 void orc_grad_consts(const uint32_t *nodes, const int64_t *prog_off,
                      const float *consts, const int64_t *const_off, int32_t n_programs,
@@ -1499,12 +1498,16 @@ void orc_grad_consts(const uint32_t *nodes, const int64_t *prog_off,
                      const double *gscale, double *grad, double *fit_out,
                      double mc_u, uint64_t mc_seed, int f32_tape, int n_threads)
 {
+    /* per-thread buffers for the longest program (any length) */
+    int64_t max_len = 1;
+    for (int32_t p = 0; p < n_programs; ++p)
+        if (prog_off[p + 1] - prog_off[p] > max_len) max_len = prog_off[p + 1] - prog_off[p];
 #pragma omp parallel num_threads(n_threads > 0 ? n_threads : 1)
     {
         double *yh = (double *)malloc(sizeof(double) * (size_t)(n_rows > 0 ? n_rows : 1));
-        double *val = (double *)malloc(sizeof(double) * ORC_GRAD_MAX_LEN);
-        double *adj = (double *)malloc(sizeof(double) * ORC_GRAD_MAX_LEN);
-        int64_t *endi = (int64_t *)malloc(sizeof(int64_t) * ORC_GRAD_MAX_LEN);
+        double *val = (double *)malloc(sizeof(double) * (size_t)(max_len + 1));
+        double *adj = (double *)malloc(sizeof(double) * (size_t)(max_len + 1));
+        int64_t *endi = (int64_t *)malloc(sizeof(int64_t) * (size_t)(max_len + 1));
 #pragma omp for schedule(dynamic, 1)
         for (int32_t p = 0; p < n_programs; ++p) {
             const uint32_t *pn = nodes + prog_off[p];
@@ -1513,11 +1516,6 @@ void orc_grad_consts(const uint32_t *nodes, const int64_t *prog_off,
             int64_t nc = const_off[p + 1] - const_off[p];
             double *gp = grad + const_off[p];
             for (int64_t s = 0; s < nc; ++s) gp[s] = 0.0;
-            if (L > ORC_GRAD_MAX_LEN) {      /* longer programs are not supported here */
-                if (fit_out) fit_out[p] = NAN;
-                for (int64_t s = 0; s < nc; ++s) gp[s] = NAN;
-                continue;
-            }
             /* forward pass for the metric's global statistics */
             double W = 0.0, S = 0.0;
             for (int64_t r = 0; r < n_rows; ++r)

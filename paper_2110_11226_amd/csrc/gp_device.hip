@@ -78,6 +78,13 @@ struct CodeView {
 // (a multiple of the 64*R rows one wavefront covers per tile).  Work item
 // it = chunk_index * P + k covers program order[k] on that chunk; programs are
 // ordered longest first so each chunk's long programs start early.
+// The work counters: one per XCD queue, 64 bytes apart, in a 1 KiB block
+// whose word kFlagWord serves the backward pass's user-function check.
+constexpr int kQueues = 8;
+constexpr int kQueueStride = 16;
+constexpr size_t kCounterBytes = 1024;
+constexpr int kFlagWord = 128;
+
 struct Sched {
     int64_t chunk;
     int32_t n_chunks;
@@ -764,7 +771,7 @@ __global__ __launch_bounds__(1024) void k_prepare(const int32_t* __restrict__ le
             start[b] = run;
             run += c;
         }
-        counter[0] = 0u;
+        for (int q = 0; q < kQueues; ++q) counter[q * kQueueStride] = 0u;
     }
     __syncthreads();
     for (int p = tid; p < P; p += blockDim.x) {
@@ -850,19 +857,30 @@ __global__ __launch_bounds__(kBlock) void k_eval(PopView pop, CodeView cv, DataV
     __shared__ MathTabsLds tabs_lds;
     const MathTabs mt = stage_tabs(tabs_lds);
 
-    for (;;) {
-        // work items: s.batch consecutive items per claim; item it covers
-        // program order[it / n_chunks] on chunk it % n_chunks (longest
-        // programs first, so the last items are the shortest)
+    // Work items: one queue per XCD.  Queue x holds the chunks c with
+    // c % kQueues == x, chunk-major, each chunk's programs in LPT order
+    // (longest first), so that a chunk's rows are read into one L2 while
+    // every program walks them.  Blocks are dealt to the XCDs in turn, so
+    // a block starts on queue blockIdx.x % kQueues; a wavefront whose queue
+    // has run dry takes items from the next ones, and leaves once all are
+    // dry.  A claim takes s.batch consecutive items.
+    const int q0 = static_cast<int>(blockIdx.x % kQueues);
+    for (int qi = 0; qi < kQueues;) {
+        const int qx = (q0 + qi) % kQueues;
+        const int64_t q_items = (static_cast<int64_t>(s.n_chunks) - qx + kQueues - 1) / kQueues * pop.P;
         uint32_t it32 = 0;
-        if (lane == 0) it32 = atomicAdd(s.counter, static_cast<uint32_t>(s.batch));
+        if (lane == 0) it32 = atomicAdd(s.counter + qx * kQueueStride, static_cast<uint32_t>(s.batch));
         const int64_t it0 = static_cast<int64_t>(
             static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(it32))));
-        if (it0 >= s.n_items) break;   // every wavefront leaves here once the items run out
-        const int64_t it1 = min(it0 + static_cast<int64_t>(s.batch), s.n_items);
+        if (it0 >= q_items) {   // this queue is dry: the next one
+            ++qi;
+            continue;
+        }
+        const int64_t it1 = min(it0 + static_cast<int64_t>(s.batch), q_items);
         for (int64_t it = it0; it < it1; ++it) {
-        const int32_t k = static_cast<int32_t>(it / s.n_chunks);
-        const int32_t c = static_cast<int32_t>(it - static_cast<int64_t>(k) * s.n_chunks);
+        const int32_t cq = static_cast<int32_t>(it / pop.P);
+        const int32_t k = static_cast<int32_t>(it - static_cast<int64_t>(cq) * pop.P);
+        const int32_t c = cq * kQueues + qx;
         const int32_t p = ldu(s.order + k);
         const int64_t off = ldu(pop.prog_off + p);
         const int32_t CL = ldu(cv.eclen + p);
@@ -1184,10 +1202,11 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
 // sin cos a, cos -sin a, tan 1 + tan^2 a, neg -1.
 // ---------------------------------------------------------------------------
 constexpr int kGradLds = 16;            // constants per program summed in a fixed order
-// per-wavefront tape held in LDS: 12 KB, 18 KB at 4 rows per lane (two
-// waves per SIMD there, so eight per CU still fit in LDS)
+// per-wavefront tape held in LDS: 12 KB, 15 KB at 4 rows per lane (two
+// waves per SIMD there, so eight per CU still fit in LDS beside the 4 KB of
+// function tables each holds)
 template <int R>
-constexpr int tape_lds_bytes() { return R == 4 ? 18432 : 12288; }
+constexpr int tape_lds_bytes() { return R == 4 ? 15360 : 12288; }
 
 // tape entries an instruction records (0, 1 or 2)
 __device__ __forceinline__ int tape_entries(uint32_t cls, uint32_t fn) {
@@ -1253,9 +1272,10 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
     float* __restrict__ aovf = wmem + kStackLds * R * kWave;        // adjoint stack beyond registers
     float* __restrict__ gtape = wmem + 2 * kStackLds * R * kWave;   // tape entries beyond LDS
     const double W = *wsum;
-    // (the function tables stay in global memory here: their LDS copy would
-    // cost the tape a wavefront per CU)
-    const MathTabs mt = global_tabs();
+    // (the function tables' LDS copy takes the 4 KB the tape gives up at
+    // four rows per lane: eight wavefronts per CU still fit)
+    __shared__ MathTabsLds tabs_lds;
+    const MathTabs mt = stage_tabs(tabs_lds);
 
     // entry e of row slot j: LDS for e < kTapeLds, the global area beyond
     auto tape_put = [&](int e, const float (&v)[R]) {
@@ -1277,13 +1297,29 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
         }
     };
 
+    // work items: the evaluation kernel's per-XCD queues, one item per claim
+    const int q0 = static_cast<int>(blockIdx.x % kQueues);
+    int qi = 0;
     for (;;) {
-        uint32_t it32 = 0;
-        if (lane == 0) it32 = atomicAdd(s.counter, 1u);
-        const int64_t it = static_cast<int64_t>(__builtin_amdgcn_readlane(static_cast<int>(it32), 0));
-        if (it >= s.n_items) break;
-        const int32_t c = static_cast<int32_t>(it / pop.P);
-        const int32_t k = static_cast<int32_t>(it - static_cast<int64_t>(c) * pop.P);
+        int64_t it = -1;
+        int qx = q0;
+        while (qi < kQueues) {
+            qx = (q0 + qi) % kQueues;
+            const int64_t q_items = (static_cast<int64_t>(s.n_chunks) - qx + kQueues - 1) / kQueues * pop.P;
+            uint32_t it32 = 0;
+            if (lane == 0) it32 = atomicAdd(s.counter + qx * kQueueStride, 1u);
+            const int64_t cand = static_cast<int64_t>(
+                static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(it32), 0)));
+            if (cand < q_items) {
+                it = cand;
+                break;
+            }
+            ++qi;   // this queue is dry
+        }
+        if (it < 0) break;   // every queue is dry
+        const int32_t cq = static_cast<int32_t>(it / pop.P);
+        const int32_t k = static_cast<int32_t>(it - static_cast<int64_t>(cq) * pop.P);
+        const int32_t c = cq * kQueues + qx;
         const int32_t p = ldu(s.order + k);
         const int64_t off = ldu(pop.prog_off + p);
         const int32_t CL = ldu(cv.clen + p);
@@ -2261,8 +2297,8 @@ gp_status grow(void** ptr, size_t* cap, size_t need_elems, size_t elem) {
 
 gp_status scratch_init(DeviceScratch& s, int dev) {
     if (s.counter) return GP_OK;
-    GP_HIP(hipMalloc(&s.counter, 256));
-    GP_HIP(hipMemset(s.counter, 0, 256));
+    GP_HIP(hipMalloc(&s.counter, kCounterBytes));
+    GP_HIP(hipMemset(s.counter, 0, kCounterBytes));
     hipDeviceProp_t prop;
     GP_HIP(hipGetDeviceProperties(&prop, dev));
     s.n_cu = prop.multiProcessorCount;
@@ -2394,6 +2430,11 @@ LaunchCfg heuristic_cfg(int F, int64_t N, int32_t P, int n_cu) {
     // features in registers only for F <= 2: eight of them cost a wavefront of
     // occupancy at 4 rows per lane, which measures slower than reading them
     c.freg = F <= 2 ? 2 : 0;
+    // a small job (fewer single-tile items than 8 per SIMD at 4 rows per
+    // lane) takes one row per lane: four times the items, each a quarter as
+    // long, so that the chip fills
+    const int64_t tiles4 = (N + kWave * 4 - 1) / (kWave * 4);
+    if (tiles4 * static_cast<int64_t>(P) < static_cast<int64_t>(n_cu) * 4 * 8) c.R = 1;
     const int64_t tile_rows = static_cast<int64_t>(kWave) * c.R;
     const int64_t n_tiles = (N + tile_rows - 1) / tile_rows;
     // aim for >= 32 work items per resident wavefront, chunks of <= 64 tiles
@@ -2678,7 +2719,7 @@ gp_status noalloc_carve(unsigned char* base, DeviceScratch* sc, int32_t P, int64
     const size_t n_code = static_cast<size_t>(total_nodes) * xp.mul + static_cast<size_t>(P) * xp.add + 1;
     const size_t n_part = static_cast<size_t>(P) * static_cast<size_t>(n_chunks) * kk;
     const size_t n_ystat = static_cast<size_t>(n_chunks) * 4;
-    const size_t bytes = 256 + align256(static_cast<size_t>(P) * sizeof(int32_t)) * 2 +
+    const size_t bytes = kCounterBytes + align256(static_cast<size_t>(P) * sizeof(int32_t)) * 2 +
                          align256(n_code * sizeof(uint4)) + align256(n_part * sizeof(double)) +
                          align256(n_ystat * sizeof(double));
     if (bytes > kNoAllocBytes)
@@ -2691,7 +2732,7 @@ gp_status noalloc_carve(unsigned char* base, DeviceScratch* sc, int32_t P, int64
         off += align256(n);
         return q;
     };
-    sc->counter = take(256);
+    sc->counter = take(kCounterBytes);
     sc->order = reinterpret_cast<int32_t*>(take(static_cast<size_t>(P) * sizeof(int32_t)));
     sc->order_cap = static_cast<size_t>(P);
     sc->eclen = reinterpret_cast<int32_t*>(take(static_cast<size_t>(P) * sizeof(int32_t)));
@@ -3987,7 +4028,7 @@ gp_status gp_fitness_backward(const gp_population_dev* pop, const gp_dataset_dev
     if (user_defined_mask() != 0u) {
         // user functions have no derivative here: look for them (this
         // waits for the stream)
-        uint32_t* flag = static_cast<uint32_t*>(sc->counter) + 32;   // (the counter's spare half)
+        uint32_t* flag = static_cast<uint32_t*>(sc->counter) + kFlagWord;
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, flag);
         GP_HIP(hipGetLastError());
         const int64_t nb = std::min<int64_t>((pop->total_nodes + kBlock - 1) / kBlock, 4096);

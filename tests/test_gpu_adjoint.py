@@ -208,6 +208,33 @@ def test_long_programs_float64_reverse_mode(gp):
     assert escaped == 0
 
 
+def test_programs_longer_than_4096_nodes(gp):
+    """Programs of 4,500-8,401 nodes, beyond the adjoint's LDS tape and any
+    fixed buffer: a sum chain of 4,200 constants (every derivative
+    2 mean(yhat - y)) and random long programs over the correctly rounded
+    set, every constant against the oracle's float32-tape reverse mode."""
+    rng = np.random.default_rng(12)
+    chain = []
+    for k in range(4200):
+        chain += [oracle.node(oracle.ADD), oracle.node(oracle.CONST, k)]
+    chain.append(oracle.node(oracle.VAR, 0))
+    rand = gp.build_population(6, 8, "exact_len", min_len=4500, max_len=6000, max_consts=16, seed=77)
+    progs = [(chain, rng.uniform(-1e-3, 1e-3, size=4200).astype(np.float32))]
+    for p in range(rand.n_programs):
+        a, b = int(rand.prog_off[p]), int(rand.prog_off[p + 1])
+        c, d = int(rand.const_off[p]), int(rand.const_off[p + 1])
+        progs.append((rand.nodes[a:b], rand.consts[c:d]))
+    op = oracle.from_programs(progs)
+    host = gp.HostPopulation(op.nodes, op.prog_off, op.consts, op.const_off, op.length)
+    gp.validate_population(host, 8)
+    X, y = synth.diff_target(9_000, seed=14)
+    print("adjoint: programs of 4,500-8,401 nodes", flush=True)
+    g, _, _ = run_backward(gp, host, X, y, None, "mse", 8)
+    ref, spread, cond = oracle_reference(op, X, y, None, "mse")
+    checked, escaped = check_grads(host, g, ref, spread, cond, "longer than 4096")
+    assert escaped == 0 and checked == host.n_programs
+
+
 def test_correctly_rounded_function_set_all_programs(gp):
     # add, sub, mul, neg: every program is checked
     fmask = sum(1 << o for o in (oracle.ADD, oracle.SUB, oracle.MUL, oracle.NEG))

@@ -271,3 +271,25 @@ def test_f32_tape_follows_float32_protected_branch():
     g64, f64 = oracle.grad_consts(pop, X, y, None, "mse")
     assert g32[0] == 0.0 and f32[0] == 1.0      # protected arm: value 1, no dependence on c
     assert g64[0] != 0.0                        # the float64 evaluation divides
+
+
+def test_long_program_closed_form():
+    """A program of 8,401 nodes (beyond any fixed buffer): c0 + (c1 + (... +
+    (c4199 + x0))), whose MSE gradient is 2 mean(yhat - y) for every
+    constant."""
+    rng = np.random.default_rng(12)
+    n_c = 4200
+    c = rng.uniform(-1e-3, 1e-3, size=n_c).astype(np.float32)
+    prog = []
+    for k in range(n_c):
+        prog += [node(ADD), node(CONST, k)]
+    prog.append(node(VAR, 0))
+    assert len(prog) == 8401
+    pop = oracle.from_programs([(prog, c)])
+    X = rng.normal(size=(1, 300)).astype(np.float32)
+    y = rng.normal(size=300).astype(np.float32)
+    g, f = oracle.grad_consts(pop, X, y, None, "mse")
+    yh = oracle.evaluate_f64(pop, X)[0]
+    want = 2.0 * np.mean(yh - y.astype(np.float64))
+    assert np.all(np.isfinite(g)) and np.allclose(g, want, rtol=1e-12, atol=1e-15)
+    assert np.isclose(f[0], np.mean((yh - y) ** 2), rtol=1e-12)
