@@ -174,6 +174,8 @@ def parity_sample(gp, torch, host, X, y, metric, rows=4096):
             "fitness_nonfinite_class_match": bool(np.array_equal(np.isfinite(gfit), fin)),
             "max_rel_err_vs_oracle_f32": float(e32[m32].max()) if m32.any() else 0.0,
             "max_rel_err_vs_f64": float(e64[m64].max()) if m64.any() else 0.0,
+            "median_rel_err_vs_f64": float(np.median(e64[m64])) if m64.any() else 0.0,
+            "programs_within_1e-4_of_f64": int((e64[m64] <= 1e-4).sum()),
             "tolerance": "outputs bit-exact; fitness 1e-4 relative"}
 
 

@@ -62,8 +62,17 @@ __device__ __forceinline__ double kreg(double c) {
     asm volatile("" : "+s"(c));
     return c;
 }
+// The same constant in a vector register pair: the operand of an FMA whose
+// other two operands already include a scalar one (one scalar operand per
+// vector instruction), set once and shared by the rows of a lane.
+__device__ __forceinline__ double kvreg(double c) {
+    double v;
+    asm volatile("v_mov_b64 %0, %1" : "=v"(v) : "s"(c));
+    return v;
+}
 #else
 inline double kreg(double c) { return c; }
+inline double kvreg(double c) { return c; }
 #endif
 
 GP_CRF uint64_t dbits(double v) {
@@ -127,7 +136,7 @@ struct SinCosK {
 };
 GP_CRF SinCosK sincos_k() {
     return SinCosK{kreg(kInvPi64), kreg(kPi64a), kreg(kPi64b), kreg(kPi64c), kreg(kS3),
-                   kreg(kS5),      kreg(kS7),    kreg(kC4),    kreg(kC6)};
+                   kvreg(kS5),     kreg(kS7),    kvreg(kC4),   kreg(kC6)};
 }
 
 // sin(j pi/64 + r) for |r| <= pi/128 (slightly more after rounding of k)
@@ -146,8 +155,19 @@ GP_CRF double sincos_small(double ax, bool is_cos, const SinCosEntry* tab, const
     double r = fma(-k, K.pa, ax);
     r = fma(-k, K.pb, r);
     r = fma(-k, K.pc, r);
-    const int j = (static_cast<int>(k) + (is_cos ? 32 : 0)) & 127;   // 0 <= k < 2^25
-    return sin_from_table(tab[j], r, K);
+    // byte offset of entry (k + 32 for cos) mod 128, 0 <= k < 2^25
+    const uint32_t off = ((static_cast<uint32_t>(static_cast<int>(k)) << 4) + (is_cos ? 512u : 0u)) & 0x7F0u;
+    return sin_from_table(*reinterpret_cast<const SinCosEntry*>(reinterpret_cast<const char*>(tab) + off), r, K);
+}
+
+// |x| clamped to [0, 2^20] (NaN to any value in it: such inputs take the
+// Payne-Hanek branch's special case)
+GP_CRF float abs_clamp20(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_fmed3f(fabsf(x), 0.0f, 0x1p+20f);
+#else
+    return fminf(fabsf(x), 0x1p+20f);
+#endif
 }
 
 // The binary digits of 2/pi in 32-bit words, after one word of zeros (the
@@ -214,17 +234,19 @@ GP_CRF float exceptions_select(const uint32_t (&tab)[N][2], int b, int e, uint32
 // Correctly rounded sin (is_cos false) or cos of a float.  The common case
 // (|x| < 2^20) runs without a branch; Payne-Hanek reduction, infinities and
 // NaN take one that is rarely entered.  Exception entries below 2^20 are
-// matched by selects, the others in that branch.
+// matched by selects, the others in that branch.  Tiny arguments need no
+// case of their own: for |x| < 2^-12 the double result lies within
+// x^2 / 6 < 2^-26.6 (relative) of x, or x^2 / 2 < 2^-25 of 1, so it rounds
+// to x (sin) or 1 (cos), as the exact value does.
 GP_CRF float sincos_cr(float x, bool is_cos, const SinCosEntry* tab, const SinCosK& K) {
     const float ax = fabsf(x);
     const uint32_t ub = fbits(ax);
     // (clamped so that NaN and large inputs keep k in range; their result
     // is replaced below)
-    const double y = sincos_small(static_cast<double>(fminf(ax, 0x1p+20f)), is_cos, tab, K);
+    const double y = sincos_small(static_cast<double>(abs_clamp20(x)), is_cos, tab, K);
     float f = static_cast<float>(y);
     f = is_cos ? exceptions_select(kCosExc, 0, kCosExcSmallN, ub, f)
                : exceptions_select(kSinExc, 0, kSinExcSmallN, ub, f);
-    f = ax < 0x1p-12f ? (is_cos ? 1.0f : ax) : f;   // sin x rounds to x, cos x to 1
     if (ub >= 0x49800000u) {                           // |x| >= 2^20, inf, NaN
         if (ub < 0x7F800000u) {
             const double yl = sincos_large(ub, is_cos, tab, K);
@@ -253,7 +275,7 @@ struct LogK {
     double l3, l4, l5, l6, l7, ln2hi, ln2lo;
 };
 GP_CRF LogK log_k() {
-    return LogK{kreg(kL3), kreg(kL4), kreg(kL5), kreg(kL6), kreg(kL7), kreg(kLn2hi), kreg(kLn2lo)};
+    return LogK{kreg(kL3), kreg(kL4), kreg(kL5), kvreg(kL6), kreg(kL7), kreg(kLn2hi), kreg(kLn2lo)};
 }
 
 // log a for a normal positive finite float, in double.

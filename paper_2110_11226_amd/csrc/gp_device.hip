@@ -175,8 +175,8 @@ __device__ __forceinline__ MathTabs global_tabs() { return MathTabs{crm::kSinCos
 
 // The kernel-resident copies (one per block, filled before its first use).
 struct MathTabsLds {
-    crm::SinCosEntry sc[128];
-    crm::LogEntry lg[128];
+    crm::LogEntry lg[128];       // (at offset 0: its entries' address is the index alone)
+    crm::SinCosEntry sc[128];    // (at 2 KB: the offset merges into the index's mask)
 };
 __device__ __forceinline__ MathTabs stage_tabs(MathTabsLds& lds) {
     for (int i = threadIdx.x; i < 128; i += blockDim.x) lds.sc[i] = crm::kSinCosTab[i];
@@ -191,7 +191,10 @@ __device__ __forceinline__ float op_div(float a, float b) {
     return fabsf(b) > GP_PROTECT_EPS ? a / b : 1.0f;
 }
 __device__ __forceinline__ float op_log(float a, const MathTabs& mt, const crm::LogK& K) {
-    return fabsf(a) > GP_PROTECT_EPS ? crm::log_cr(fabsf(a), mt.lg, K) : 0.0f;
+    // (evaluated on every lane, the protected ones included, so that the
+    // protection is a select rather than a branch)
+    const float l = crm::log_cr(fabsf(a), mt.lg, K);
+    return fabsf(a) > GP_PROTECT_EPS ? l : 0.0f;
 }
 __device__ __forceinline__ float op_sqrt(float a) { return sqrtf(fabsf(a)); }
 __device__ __forceinline__ float op_inv(float a) {
