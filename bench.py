@@ -52,7 +52,7 @@ OP_COST = (0.0, 0.0, 0.5, 0.5, 0.5, 10.0, 0.5, 5.0, 8.0, 5.0, 5.0, 14.0, 1.0, 1.
 # (a fold instruction covers two nodes).  add, sub and mul are one
 # instruction per row (no packed FP32); sin, cos and log carry the double
 # evaluation of their correctly rounded form.
-OP_COST_MEASURED = (0.0, 0.0, 1.0, 1.0, 1.0, 12.9, 1.0, 32.9, 15.9, 29.7, 28.9, 28.7, 5.9, 5.9, 38.6, 1.2,
+OP_COST_MEASURED = (0.0, 0.0, 1.0, 1.0, 1.0, 12.9, 1.0, 30.9, 15.9, 25.3, 23.5, 28.7, 6.0, 6.0, 38.6, 1.2,
                     13.1, 13.1, 1.2, 2.2, 9.8, 16.1, 15.1)
 # what the evaluation kernel is built from: its source, the headers it
 # includes and the build flags
