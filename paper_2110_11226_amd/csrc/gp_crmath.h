@@ -18,17 +18,17 @@
 // falls on the wrong side (found by running every float through these
 // functions against an independent reference, crmath_check.cpp).
 //
-//   sin, cos: |x| = k (pi/64) + r, |r| <= pi/128: for |x| < 2^20 by a
+//   sin, cos: x = k (pi/64) + r, |r| <= pi/128: for |x| < 2^20 by a
 //     three-part Cody-Waite reduction whose first two products are exact;
-//     beyond, by Payne-Hanek: the 24-bit mantissa times a 160-bit window of
-//     the binary digits of 2/pi, in 32-bit integer limbs.  Then sin x =
-//     S cos r + C sin r with S, C the sine and cosine of (k mod 128) pi/64
-//     from a table (cos x takes k + 32), sin r and cos r by short Taylor
-//     polynomials.
+//     beyond, by Payne-Hanek on |x|: the 24-bit mantissa times a 160-bit
+//     window of the binary digits of 2/pi, in 32-bit integer limbs.  Then
+//     sin x = S cos r + C sin r with S, C the sine and cosine of
+//     (k mod 128) pi/64 from a table (cos x takes k + 32), sin r and cos r by
+//     short Taylor polynomials.
 //   log: a = 2^e m, m in [1, 2); c = 1/(bucket centre of m) from a 128-entry
 //     table (c has 24 bits, so m c - 1 is exact); log a = E ln 2 - log c' +
-//     log1p(m c - 1) with log1p to r^7 (|m c - 1| <= 2^-7) and the table's
-//     -log c' and ln 2 carried as double + remainder.
+//     log1p(m c - 1) with log1p to r^7 (|m c - 1| <= 2^-7), the table's
+//     -log c' and ln 2 each rounded to double.
 // The code is host- and device-compilable so that the exhaustive checker can
 // run the very same functions on the CPU.  The tables are taken by pointer
 // (the evaluation kernels stage them in LDS) and the double constants as a
@@ -129,14 +129,21 @@ constexpr double kPi64 = 0x1.921fb54442d18p-5;
 constexpr double kS3 = -0x1.5555555555555p-3, kS5 = 0x1.1111111111111p-7, kS7 = -0x1.a01a01a01a01ap-13;
 constexpr double kC4 = 0x1.5555555555555p-5, kC6 = -0x1.6c16c16c16c17p-10;
 
-// The double constants of sin and cos as operands.  The evaluation kernels
-// build this once per instruction and share it among the rows a lane holds.
+// 1.5 * 2^52: x + kRound is x rounded to an integer, held in the low bits of
+// the double's significand (|x| < 2^51); cos adds its quarter turn, 32
+// table steps, in the same operation
+constexpr double kRound = 0x1.8p+52;
+constexpr double kRoundCos = 0x1.8p+52 + 32.0;
+
+// The double constants of sin (is_cos false) or cos as operands.  The
+// evaluation kernels build this once per instruction and share it among the
+// rows a lane holds.
 struct SinCosK {
-    double inv, pa, pb, pc, s3, s5, s7, c4, c6;
+    double inv, rnd, pa, pb, pc, s3, s5, s7, c4, c6;
 };
-GP_CRF SinCosK sincos_k() {
-    return SinCosK{kreg(kInvPi64), kreg(kPi64a), kreg(kPi64b), kreg(kPi64c), kreg(kS3),
-                   kvreg(kS5),     kreg(kS7),    kvreg(kC4),   kreg(kC6)};
+GP_CRF SinCosK sincos_k(bool is_cos) {
+    return SinCosK{kreg(kInvPi64), kreg(is_cos ? kRoundCos : kRound), kreg(kPi64a), kreg(kPi64b),
+                   kreg(kPi64c),   kreg(kS3), kvreg(kS5), kreg(kS7), kvreg(kC4), kreg(kC6)};
 }
 
 // sin(j pi/64 + r) for |r| <= pi/128 (slightly more after rounding of k)
@@ -149,24 +156,32 @@ GP_CRF double sin_from_table(const SinCosEntry& e, double r, const SinCosK& K) {
     return fma(e.s, cm1, fma(e.c, sr, e.s));
 }
 
-// 0 <= ax <= 2^20: k and r by a three-part Cody-Waite reduction
-GP_CRF double sincos_small(double ax, bool is_cos, const SinCosEntry* tab, const SinCosK& K) {
-    const double k = rint(ax * K.inv);
-    double r = fma(-k, K.pa, ax);
+// |x| <= 2^20: k and r by a three-part Cody-Waite reduction.  k is the
+// integer nearest x * 64/pi (from the exact product: a tie or a
+// neighbouring integer only moves r within the polynomials' range), and
+// the low word of x * 64/pi + K.rnd is k (k + 32 for cos) modulo 2^32, so
+// that a negative k indexes the table as k mod 128 does.  Every step is odd
+// in x (k, r and the table's sines change sign, its cosines do not), so
+// sin(-x) = -sin x and cos(-x) = cos x hold bit for bit, zeros aside (see
+// sincos_common).
+GP_CRF double sincos_small(double x, const SinCosEntry* tab, const SinCosK& K) {
+    const double kr = fma(x, K.inv, K.rnd);
+    const double k = kr - K.rnd;
+    double r = fma(-k, K.pa, x);
     r = fma(-k, K.pb, r);
     r = fma(-k, K.pc, r);
-    // byte offset of entry (k + 32 for cos) mod 128, 0 <= k < 2^25
-    const uint32_t off = ((static_cast<uint32_t>(static_cast<int>(k)) << 4) + (is_cos ? 512u : 0u)) & 0x7F0u;
+    // byte offset of entry (k or k + 32) mod 128
+    const uint32_t off = (static_cast<uint32_t>(dbits(kr)) << 4) & 0x7F0u;
     return sin_from_table(*reinterpret_cast<const SinCosEntry*>(reinterpret_cast<const char*>(tab) + off), r, K);
 }
 
-// |x| clamped to [0, 2^20] (NaN to any value in it: such inputs take the
+// x clamped to [-2^20, 2^20] (NaN to any value in it: such inputs take the
 // Payne-Hanek branch's special case)
-GP_CRF float abs_clamp20(float x) {
+GP_CRF float clamp20(float x) {
 #if defined(__HIP_DEVICE_COMPILE__)
-    return __builtin_amdgcn_fmed3f(fabsf(x), 0.0f, 0x1p+20f);
+    return __builtin_amdgcn_fmed3f(x, -0x1p+20f, 0x1p+20f);
 #else
-    return fminf(fabsf(x), 0x1p+20f);
+    return fmaxf(fminf(x, 0x1p+20f), -0x1p+20f);
 #endif
 }
 
@@ -224,78 +239,98 @@ GP_CRF double sincos_large(uint32_t ub, bool is_cos, const SinCosEntry* tab, con
     return sin_from_table(tab[j], D * kPi64, K);
 }
 
-// Exception-table entries [B, E) (sorted by key) applied to f without a branch
+// Exception-table entries [B, E) (sorted by key) applied to f without a
+// branch; an entry's result is negated where neg holds
 template <int N>
-GP_CRF float exceptions_select(const uint32_t (&tab)[N][2], int b, int e, uint32_t key, float f) {
-    for (int i = b; i < e; ++i) f = key == tab[i][0] ? bitsf(tab[i][1]) : f;
+GP_CRF float exceptions_select(const uint32_t (&tab)[N][2], int b, int e, uint32_t key, float f, bool neg) {
+    for (int i = b; i < e; ++i) f = key == tab[i][0] ? (neg ? -bitsf(tab[i][1]) : bitsf(tab[i][1])) : f;
     return f;
 }
 
-// Correctly rounded sin (is_cos false) or cos of a float.  The common case
-// (|x| < 2^20) runs without a branch; Payne-Hanek reduction, infinities and
-// NaN take one that is rarely entered.  Exception entries below 2^20 are
-// matched by selects, the others in that branch.  Tiny arguments need no
+// Correctly rounded sin (is_cos false) or cos of a float, in two parts so
+// that a lane holding several rows can test them all before one branch:
+// sincos_common is the result for |x| < 2^20, without a branch (exception
+// entries below 2^20 are matched by selects); an input for which
+// sincos_rare_input holds (|x| >= 2^20, inf, NaN) takes sincos_rare's
+// result instead: Payne-Hanek reduction, or NaN.  Tiny arguments need no
 // case of their own: for |x| < 2^-12 the double result lies within
 // x^2 / 6 < 2^-26.6 (relative) of x, or x^2 / 2 < 2^-25 of 1, so it rounds
 // to x (sin) or 1 (cos), as the exact value does.
-GP_CRF float sincos_cr(float x, bool is_cos, const SinCosEntry* tab, const SinCosK& K) {
-    const float ax = fabsf(x);
-    const uint32_t ub = fbits(ax);
+GP_CRF float sincos_common(float x, bool is_cos, const SinCosEntry* tab, const SinCosK& K) {
     // (clamped so that NaN and large inputs keep k in range; their result
-    // is replaced below)
-    const double y = sincos_small(static_cast<double>(abs_clamp20(x)), is_cos, tab, K);
+    // is replaced by sincos_rare's)
+    const double y = sincos_small(static_cast<double>(clamp20(x)), tab, K);
     float f = static_cast<float>(y);
-    f = is_cos ? exceptions_select(kCosExc, 0, kCosExcSmallN, ub, f)
-               : exceptions_select(kSinExc, 0, kSinExcSmallN, ub, f);
-    if (ub >= 0x49800000u) {                           // |x| >= 2^20, inf, NaN
-        if (ub < 0x7F800000u) {
-            const double yl = sincos_large(ub, is_cos, tab, K);
-            f = static_cast<float>(yl);
-            if (near_boundary(yl))
-                f = is_cos ? exception(kCosExc, kCosExcN, ub, f) : exception(kSinExc, kSinExcN, ub, f);
-        } else {
-            f = x - x;   // NaN
-        }
+    // (the entries list |x|; sin's result takes the sign of x)
+    const uint32_t ub = fbits(x) & 0x7FFFFFFFu;
+    if (is_cos) return exceptions_select(kCosExc, 0, kCosExcSmallN, ub, f, false);
+    f = exceptions_select(kSinExc, 0, kSinExcSmallN, ub, f, (fbits(x) >> 31) != 0u);
+    // sin(-0) = -0: the polynomial's additions of +0 give +0 there
+    return x == 0.0f ? x : f;
+}
+
+GP_CRF bool sincos_rare_input(float x) { return !(fabsf(x) < 0x1p+20f); }   // (NaN included)
+
+GP_CRF float sincos_rare(float x, bool is_cos, const SinCosEntry* tab, const SinCosK& K) {
+    const uint32_t ub = fbits(x) & 0x7FFFFFFFu;
+    float f;
+    if (ub < 0x7F800000u) {
+        const double yl = sincos_large(ub, is_cos, tab, K);
+        f = static_cast<float>(yl);
+        if (near_boundary(yl))
+            f = is_cos ? exception(kCosExc, kCosExcN, ub, f) : exception(kSinExc, kSinExcN, ub, f);
+    } else {
+        f = x - x;   // NaN
     }
-    return (!is_cos && (fbits(x) >> 31)) ? -f : f;   // sin(-x) = -sin x, -0 included
+    return (!is_cos && (fbits(x) >> 31)) ? -f : f;
+}
+
+GP_CRF float sincos_cr(float x, bool is_cos, const SinCosEntry* tab, const SinCosK& K) {
+    float f = sincos_common(x, is_cos, tab, K);
+    if (sincos_rare_input(x)) f = sincos_rare(x, is_cos, tab, K);
+    return f;
 }
 
 GP_CRF float sin_cr(float x, const SinCosEntry* tab, const SinCosK& K) { return sincos_cr(x, false, tab, K); }
 GP_CRF float cos_cr(float x, const SinCosEntry* tab, const SinCosK& K) { return sincos_cr(x, true, tab, K); }
 
 // ---- log ----
-constexpr double kLn2hi = 0x1.62e42fefa3900p-1;   // 45 bits: E * kLn2hi is exact
-constexpr double kLn2lo = 0x1.de6af278ece60p-46;
-// (-1)^(k+1) / k, k = 3..7 (log1p to r^7: |r| <= 2^-7, truncation below
-// 2^-52 relative)
+// ln 2 rounded to double: E ln 2 is then off by |E| 2^-55.3 at most, which
+// is below 2^-53.8 of the result for every E != 0 (|log a| >= |E| ln 2 -
+// ln(2)/2 there)
+constexpr double kLn2 = 0x1.62e42fefa39efp-1;
+// (-1)^(k+1) / k, k = 3..7 (log1p to r^7: |r| <= 2^-8, 2^-7 in the first
+// bucket, whose c = 1; truncation below 2^-52 relative)
 constexpr double kL3 = 0x1.5555555555555p-2, kL4 = -0x1.0000000000000p-2, kL5 = 0x1.999999999999ap-3,
                  kL6 = -0x1.5555555555555p-3, kL7 = 0x1.2492492492492p-3;
 
 struct LogK {
-    double l3, l4, l5, l6, l7, ln2hi, ln2lo;
+    double l3, l4, l5, l6, l7, ln2;
 };
 GP_CRF LogK log_k() {
-    return LogK{kreg(kL3), kreg(kL4), kreg(kL5), kvreg(kL6), kreg(kL7), kreg(kLn2hi), kreg(kLn2lo)};
+    return LogK{kreg(kL3), kreg(kL4), kreg(kL5), kvreg(kL6), kreg(kL7), kreg(kLn2)};
 }
 
-// log a for a normal positive finite float, in double.
+// log a for a normal positive finite float, in double: E ln 2 + L + log1p(r)
+// with r = m c - 1 exact (24-bit m times the 24-bit c).  The table's L
+// carries its double rounding, below 2^-53 |L|.  Where E = 0 and L != 0,
+// |r| <= 0.34 |L|, so the result is at least 0.66 |L| and that rounding is
+// below 2^-52.4 of it; with the rounding of log1p and of the final addition
+// the relative error stays below 2^-51 (E ln 2 + L is exact when E = 0).
 GP_CRF double log_double(float a, const LogEntry* tab, const LogK& K) {
     const uint32_t u = fbits(a);
     const int i = static_cast<int>((u >> 16) & 0x7Fu);
     const int E = static_cast<int>(u >> 23) - 127 + (i >= 53 ? 1 : 0);
     const double m = static_cast<double>(bitsf((u & 0x7FFFFFu) | 0x3F800000u));
     const LogEntry& t = tab[i];
-    const double r = fma(m, static_cast<double>(t.c), -1.0);   // exact
+    const double r = fma(m, t.c, -1.0);   // exact
     double p = fma(K.l7, r, K.l6);
     p = fma(p, r, K.l5);
     p = fma(p, r, K.l4);
     p = fma(p, r, K.l3);
     p = fma(p, r, -0.5);
     const double l1p = fma(r * r, p, r);
-    const double Ed = static_cast<double>(E);
-    const double hi = fma(Ed, K.ln2hi, t.hi);
-    const double lo = fma(Ed, K.ln2lo, static_cast<double>(t.lo) + l1p);
-    return hi + lo;
+    return fma(static_cast<double>(E), K.ln2, t.hi) + l1p;
 }
 
 // Correctly rounded log of a float a > 0 that is normal, +inf or NaN (the

@@ -190,15 +190,78 @@ __device__ __forceinline__ MathTabs stage_tabs(MathTabsLds& lds) {
 __device__ __forceinline__ float op_div(float a, float b) {
     return fabsf(b) > GP_PROTECT_EPS ? a / b : 1.0f;
 }
-__device__ __forceinline__ float op_log(float a, const MathTabs& mt, const crm::LogK& K) {
-    // (evaluated on every lane, the protected ones included, so that the
-    // protection is a select rather than a branch)
-    const float l = crm::log_cr(fabsf(a), mt.lg, K);
-    return fabsf(a) > GP_PROTECT_EPS ? l : 0.0f;
+// The protected log of the R rows of a lane: log|t| correctly rounded
+// (crm::log_cr) where |t| > 0.001, else 0.  Evaluated on every row, the
+// protected ones included, so that the protection is a select; the
+// exception-table lookup, for rows whose double result lies near a rounding
+// boundary, is one branch for all the rows, rarely taken.
+template <int R>
+__device__ __forceinline__ void log_rows(float (&t)[R], const MathTabs& mt) {
+    const crm::LogK K = crm::log_k();   // (once for the R rows)
+    float f[R];
+    bool near[R];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const double y = crm::log_double(fabsf(t[j]), mt.lg, K);   // (finite for inf and NaN)
+        f[j] = static_cast<float>(y);
+        near[j] = crm::near_boundary(y);
+        any |= near[j];
+    }
+    if (any) {
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            if (near[j]) f[j] = crm::exception(crm::kLogExc, crm::kLogExcN, crm::fbits(fabsf(t[j])), f[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const float a = fabsf(t[j]);
+        const float l = a <= 0x1.fffffep+127f ? f[j] : a;   // +inf (and NaN) unchanged
+        t[j] = a > GP_PROTECT_EPS ? l : 0.0f;
+    }
 }
-__device__ __forceinline__ float op_sqrt(float a) { return sqrtf(fabsf(a)); }
+// sqrt|a|, correctly rounded: in double from the hardware reciprocal square
+// root y (relative error e below 2^-22) by two Newton steps on s = d y with
+// h = y / 2 held fixed (the error goes e -> 1.5 e^2 -> about 1.5 e^3), then
+// rounded to float.  A float's square root lies at least 2^-51 (relative)
+// from every float rounding boundary (a - m^2 is a nonzero multiple of the
+// least bit of m^2 for a midpoint m), so the double result, within 2^-53,
+// rounds as the exact one does.  Zeros and infinity are passed through (the
+// steps would give NaN there); NaN stays NaN.
+__device__ __forceinline__ float op_sqrt(float a) {
+    const double d = static_cast<double>(fabsf(a));
+    const double y = __builtin_amdgcn_rsq(d);
+    const double h = 0.5 * y;
+    double s = d * y;
+    s = fma(fma(-s, s, d), h, s);
+    s = fma(fma(-s, s, d), h, s);
+    // class mask: +0 (bit 6) or +inf (bit 9)
+    return __builtin_amdgcn_class(d, 0x240) ? fabsf(a) : static_cast<float>(s);
+}
 __device__ __forceinline__ float op_inv(float a) {
     return fabsf(a) > GP_PROTECT_EPS ? 1.0f / a : 0.0f;
+}
+
+// t = sin t (is_cos false) or cos t on the R rows of a lane: the common
+// path on every row, then one branch, rarely taken, for the rows with
+// |t| >= 2^20, inf or NaN
+template <int R>
+__device__ __forceinline__ void sincos_rows(bool is_cos, float (&t)[R], const MathTabs& mt) {
+    const crm::SinCosK K = crm::sincos_k(is_cos);   // (once for the R rows)
+    float f[R];
+    bool rare = false;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        f[j] = crm::sincos_common(t[j], is_cos, mt.sc, K);
+        rare |= crm::sincos_rare_input(t[j]);
+    }
+    if (rare) {
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            if (crm::sincos_rare_input(t[j])) f[j] = crm::sincos_rare(t[j], is_cos, mt.sc, K);
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) t[j] = f[j];
 }
 
 // a = a (op) b for the wider binary functions (MAX, MIN, ATAN2 as 4..6)
@@ -302,22 +365,16 @@ __device__ __forceinline__ void apply_unary(uint32_t fn, float (&t)[R], const Ma
 #pragma unroll
             for (int j = 0; j < R; ++j) t[j] = -t[j];
         } else if (fn == 1) {
-            const crm::LogK K = crm::log_k();   // (once for the R rows)
-#pragma unroll
-            for (int j = 0; j < R; ++j) t[j] = op_log(t[j], mt, K);
+            log_rows<R>(t, mt);
         } else {
 #pragma unroll
             for (int j = 0; j < R; ++j) t[j] = op_sqrt(t[j]);
         }
     } else {
         if (fn == 3) {
-            const crm::SinCosK K = crm::sincos_k();
-#pragma unroll
-            for (int j = 0; j < R; ++j) t[j] = crm::sin_cr(t[j], mt.sc, K);
+            sincos_rows<R>(false, t, mt);
         } else if (fn == 4) {
-            const crm::SinCosK K = crm::sincos_k();
-#pragma unroll
-            for (int j = 0; j < R; ++j) t[j] = crm::cos_cr(t[j], mt.sc, K);
+            sincos_rows<R>(true, t, mt);
         } else {
 #pragma unroll
             for (int j = 0; j < R; ++j) t[j] = tanf(t[j]);

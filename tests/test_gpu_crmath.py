@@ -1,12 +1,13 @@
-"""The device's correctly rounded sin, cos and log (gp_crmath.h) against the
-oracle's float32 functions, on every float.
+"""The device's correctly rounded sin, cos, log (gp_crmath.h) and protected
+square root against the oracle's float32 functions, on every float.
 
 The function set of Sec. III-D1 names its functions but no library; both
 sides round each function's exact value once, to nearest, so the two must
 agree bit for bit on all 2^32 inputs.  The values go through the evaluation
-kernel itself: programs [SIN x0], [COS x0] and [LOG x0] (the protected log
-of |x0|, 0 where |x0| <= 0.001 or x0 is NaN) over a dataset whose rows are
-every float bit pattern, 2^28 rows at a time.
+kernel itself: programs [SIN x0], [COS x0], [LOG x0] (the protected log
+of |x0|, 0 where |x0| <= 0.001 or x0 is NaN) and [SQRT x0] (sqrt|x0|, IEEE
+correctly rounded on the oracle's side) over a dataset whose rows are every
+float bit pattern, 2^28 rows at a time.
 """
 import os
 
@@ -31,7 +32,7 @@ def gp():
 def programs(gp):
     n = oracle.node
     op = oracle.from_programs([([n(oracle.SIN), n(oracle.VAR, 0)], []), ([n(oracle.COS), n(oracle.VAR, 0)], []),
-                               ([n(oracle.LOG), n(oracle.VAR, 0)], [])])
+                               ([n(oracle.LOG), n(oracle.VAR, 0)], []), ([n(oracle.SQRT), n(oracle.VAR, 0)], [])])
     return op, gp.HostPopulation(op.nodes, op.prog_off, op.consts, op.const_off, op.length)
 
 
@@ -46,12 +47,12 @@ def compare(gp, op, pop, bits):
     same = (got.view(np.uint32) == ref.view(np.uint32)) | (np.isnan(got) & np.isnan(ref))
     if not same.all():
         p, i = np.argwhere(~same)[0]
-        raise AssertionError(f"{int((~same).sum())} results differ; first: function {['sin', 'cos', 'log'][p]} "
+        raise AssertionError(f"{int((~same).sum())} results differ; first: function {['sin', 'cos', 'log', 'sqrt'][p]} "
                              f"x = {x[i]!r} ({bits[i]:#010x}): gpu {got[p, i]!r} oracle {ref[p, i]!r}")
     return got.size
 
 
-def test_sin_cos_log_every_float(gp):
+def test_sin_cos_log_sqrt_every_float(gp):
     op, host = programs(gp)
     pop = gp.DevicePopulation(host, n_features=1)
     oracle.cr_reset()
