@@ -190,35 +190,13 @@ __device__ __forceinline__ MathTabs stage_tabs(MathTabsLds& lds) {
 __device__ __forceinline__ float op_div(float a, float b) {
     return fabsf(b) > GP_PROTECT_EPS ? a / b : 1.0f;
 }
-// The protected log of the R rows of a lane: log|t| correctly rounded
-// (crm::log_cr) where |t| > 0.001, else 0.  Evaluated on every row, the
-// protected ones included, so that the protection is a select; the
-// exception-table lookup, for rows whose double result lies near a rounding
-// boundary, is one branch for all the rows, rarely taken.
-template <int R>
-__device__ __forceinline__ void log_rows(float (&t)[R], const MathTabs& mt) {
-    const crm::LogK K = crm::log_k();   // (once for the R rows)
-    float f[R];
-    bool near[R];
-    bool any = false;
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        const double y = crm::log_double(fabsf(t[j]), mt.lg, K);   // (finite for inf and NaN)
-        f[j] = static_cast<float>(y);
-        near[j] = crm::near_boundary(y);
-        any |= near[j];
-    }
-    if (any) {
-#pragma unroll
-        for (int j = 0; j < R; ++j)
-            if (near[j]) f[j] = crm::exception(crm::kLogExc, crm::kLogExcN, crm::fbits(fabsf(t[j])), f[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        const float a = fabsf(t[j]);
-        const float l = a <= 0x1.fffffep+127f ? f[j] : a;   // +inf (and NaN) unchanged
-        t[j] = a > GP_PROTECT_EPS ? l : 0.0f;
-    }
+__device__ __forceinline__ float op_log(float a, const MathTabs& mt, const crm::LogK& K) {
+    // (evaluated on every lane, the protected ones included, so that the
+    // protection is a select rather than a branch; row by row, unlike sin
+    // and cos below: the rows' table entries and double temporaries held
+    // together cost the kernel an occupancy step)
+    const float l = crm::log_cr(fabsf(a), mt.lg, K);
+    return fabsf(a) > GP_PROTECT_EPS ? l : 0.0f;
 }
 // sqrt|a|, correctly rounded: in double from the hardware reciprocal square
 // root y (relative error e below 2^-22) by two Newton steps on s = d y with
@@ -365,7 +343,9 @@ __device__ __forceinline__ void apply_unary(uint32_t fn, float (&t)[R], const Ma
 #pragma unroll
             for (int j = 0; j < R; ++j) t[j] = -t[j];
         } else if (fn == 1) {
-            log_rows<R>(t, mt);
+            const crm::LogK K = crm::log_k();   // (once for the R rows)
+#pragma unroll
+            for (int j = 0; j < R; ++j) t[j] = op_log(t[j], mt, K);
         } else {
 #pragma unroll
             for (int j = 0; j < R; ++j) t[j] = op_sqrt(t[j]);
