@@ -192,12 +192,43 @@ __device__ __forceinline__ float op_div(float a, float b) {
 }
 __device__ __forceinline__ float op_log(float a, const MathTabs& mt, const crm::LogK& K) {
     // (evaluated on every lane, the protected ones included, so that the
-    // protection is a select rather than a branch; row by row, unlike sin
-    // and cos below: the rows' table entries and double temporaries held
-    // together cost the kernel an occupancy step)
+    // protection is a select rather than a branch)
     const float l = crm::log_cr(fabsf(a), mt.lg, K);
     return fabsf(a) > GP_PROTECT_EPS ? l : 0.0f;
 }
+
+// The same on the R rows of a lane, with one branch, rarely taken, for the
+// exception-table lookups of all the rows instead of one per row: fewer
+// scalar instructions, but the rows' results and inputs are held together.
+// The evaluation kernel goes row by row (the extra registers cost it an
+// occupancy step); the adjoint kernel, with registers to spare at its
+// occupancy, takes this form.
+template <int R>
+__device__ __forceinline__ void log_rows(float (&t)[R], const MathTabs& mt) {
+    const crm::LogK K = crm::log_k();   // (once for the R rows)
+    float f[R];
+    bool near[R];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const double y = crm::log_double(fabsf(t[j]), mt.lg, K);   // (finite for inf and NaN)
+        f[j] = static_cast<float>(y);
+        near[j] = crm::near_boundary(y);
+        any |= near[j];
+    }
+    if (any) {
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            if (near[j]) f[j] = crm::exception(crm::kLogExc, crm::kLogExcN, crm::fbits(fabsf(t[j])), f[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const float a = fabsf(t[j]);
+        const float l = a <= 0x1.fffffep+127f ? f[j] : a;   // +inf (and NaN) unchanged
+        t[j] = a > GP_PROTECT_EPS ? l : 0.0f;
+    }
+}
+
 // sqrt|a|, correctly rounded: in double from the hardware reciprocal square
 // root y (relative error e below 2^-22) by two Newton steps on s = d y with
 // h = y / 2 held fixed (the error goes e -> 1.5 e^2 -> about 1.5 e^3), then
@@ -334,7 +365,8 @@ __device__ __forceinline__ void apply_binary(uint32_t fn, float (&a)[R], const f
 
 // t = f(t) for the unary function index fn (NEG, LOG, SQRT, SIN, COS, TAN
 // first, then the wider set)
-template <int R>
+// (LOG_ROWS: the protected log by log_rows rather than row by row)
+template <int R, bool LOG_ROWS = false>
 __device__ __forceinline__ void apply_unary(uint32_t fn, float (&t)[R], const MathTabs& mt) {
     if (fn >= 6) {
         apply_unary_wide<R>(fn, t);
@@ -343,9 +375,13 @@ __device__ __forceinline__ void apply_unary(uint32_t fn, float (&t)[R], const Ma
 #pragma unroll
             for (int j = 0; j < R; ++j) t[j] = -t[j];
         } else if (fn == 1) {
-            const crm::LogK K = crm::log_k();   // (once for the R rows)
+            if constexpr (LOG_ROWS) {
+                log_rows<R>(t, mt);
+            } else {
+                const crm::LogK K = crm::log_k();   // (once for the R rows)
 #pragma unroll
-            for (int j = 0; j < R; ++j) t[j] = op_log(t[j], mt, K);
+                for (int j = 0; j < R; ++j) t[j] = op_log(t[j], mt, K);
+            }
         } else {
 #pragma unroll
             for (int j = 0; j < R; ++j) t[j] = op_sqrt(t[j]);
@@ -1426,7 +1462,7 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                     float x[R];
 #pragma unroll
                     for (int j = 0; j < R; ++j) x[j] = t[j];
-                    apply_unary<R>(fn, t, mt);
+                    apply_unary<R, true>(fn, t, mt);
                     if (fn != 0 && act) {
                         float dv[R];
                         unary_derivative<R>(fn, x, t, dv);
@@ -1521,7 +1557,7 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                     float x[R];
 #pragma unroll
                     for (int j = 0; j < R; ++j) x[j] = t[j];
-                    apply_unary<R>(u, t, mt);
+                    apply_unary<R, true>(u, t, mt);
                     if (u != 0 && act) {
                         float dv[R];
                         unary_derivative<R>(u, x, t, dv);
