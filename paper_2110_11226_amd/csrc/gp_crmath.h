@@ -175,16 +175,6 @@ GP_CRF double sincos_small(double x, const SinCosEntry* tab, const SinCosK& K) {
     return sin_from_table(*reinterpret_cast<const SinCosEntry*>(reinterpret_cast<const char*>(tab) + off), r, K);
 }
 
-// x clamped to [-2^20, 2^20] (NaN to any value in it: such inputs take the
-// Payne-Hanek branch's special case)
-GP_CRF float clamp20(float x) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    return __builtin_amdgcn_fmed3f(x, -0x1p+20f, 0x1p+20f);
-#else
-    return fmaxf(fminf(x, 0x1p+20f), -0x1p+20f);
-#endif
-}
-
 // The binary digits of 2/pi in 32-bit words, after one word of zeros (the
 // word index of digit p >= 1, weight 2^-p, is (p + 31) / 32).
 GP_CRTAB uint32_t kTwoOverPi[13] = {0u,          0xa2f9836eu, 0x4e441529u, 0xfc2757d1u, 0xf534ddc0u,
@@ -257,9 +247,10 @@ GP_CRF float exceptions_select(const uint32_t (&tab)[N][2], int b, int e, uint32
 // x^2 / 6 < 2^-26.6 (relative) of x, or x^2 / 2 < 2^-25 of 1, so it rounds
 // to x (sin) or 1 (cos), as the exact value does.
 GP_CRF float sincos_common(float x, bool is_cos, const SinCosEntry* tab, const SinCosK& K) {
-    // (clamped so that NaN and large inputs keep k in range; their result
-    // is replaced by sincos_rare's)
-    const double y = sincos_small(static_cast<double>(clamp20(x)), tab, K);
+    // (an input sincos_rare_input flags gets a meaningless value here, read
+    // from within the table since its offset is masked, and replaced by
+    // sincos_rare's)
+    const double y = sincos_small(static_cast<double>(x), tab, K);
     float f = static_cast<float>(y);
     // (the entries list |x|; sin's result takes the sign of x)
     const uint32_t ub = fbits(x) & 0x7FFFFFFFu;
