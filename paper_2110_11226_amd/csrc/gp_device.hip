@@ -1301,15 +1301,20 @@ constexpr int64_t adjoint_wave_floats(int64_t tape_entries_max) {
 }
 
 // derivative of unary function fn (1..5: log, sqrt, sin, cos, tan; 6..13:
-// abs, exp, inv, sq, cube, tanh, atan, cbrt) at input x, whose result is y
+// abs, exp, inv, sq, cube, tanh, atan, cbrt) at input x, whose result is y.
+// Reciprocals here (and in the quotient's partials) come from the hardware
+// reciprocal, within 1 ulp: a partial's own rounding, well inside the
+// derivative tolerance, at a tenth of a correctly rounded division's cost.
+// Every argument is normal: |x| > 0.001, 2 sqrt|x| >= 2^-73.5, 1 + x^2 >= 1,
+// 3 cbrt(x)^2 >= 2^-99 for nonzero float x.
 template <int R>
 __device__ __forceinline__ void unary_derivative(uint32_t fn, const float (&x)[R], const float (&y)[R],
                                                  float (&dv)[R]) {
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         switch (fn) {
-        case 1: dv[j] = fabsf(x[j]) > GP_PROTECT_EPS ? 1.0f / x[j] : 0.0f; break;
-        case 2: dv[j] = x[j] == 0.0f ? 0.0f : copysignf(1.0f, x[j]) / (2.0f * y[j]); break;
+        case 1: dv[j] = fabsf(x[j]) > GP_PROTECT_EPS ? __builtin_amdgcn_rcpf(x[j]) : 0.0f; break;
+        case 2: dv[j] = x[j] == 0.0f ? 0.0f : copysignf(__builtin_amdgcn_rcpf(2.0f * y[j]), x[j]); break;
         case 3: dv[j] = cosf(x[j]); break;
         case 4: dv[j] = -sinf(x[j]); break;
         case 5: dv[j] = 1.0f + y[j] * y[j]; break;
@@ -1319,8 +1324,8 @@ __device__ __forceinline__ void unary_derivative(uint32_t fn, const float (&x)[R
         case 9: dv[j] = 2.0f * x[j]; break;
         case 10: dv[j] = 3.0f * (x[j] * x[j]); break;
         case 11: dv[j] = 1.0f - y[j] * y[j]; break;
-        case 12: dv[j] = 1.0f / (1.0f + x[j] * x[j]); break;
-        default: dv[j] = y[j] != 0.0f ? 1.0f / (3.0f * (y[j] * y[j])) : 0.0f; break;
+        case 12: dv[j] = __builtin_amdgcn_rcpf(1.0f + x[j] * x[j]); break;
+        default: dv[j] = y[j] != 0.0f ? __builtin_amdgcn_rcpf(3.0f * (y[j] * y[j])) : 0.0f; break;
         }
     }
 }
@@ -1524,7 +1529,7 @@ __global__ __launch_bounds__(kWave) void k_adjoint(PopView pop, CodeView cv, Dat
                                 db[j] = a[j];
                             } else if (fn == 3) {
                                 if (fabsf(b[j]) > GP_PROTECT_EPS) {
-                                    const float inv = 1.0f / b[j];
+                                    const float inv = __builtin_amdgcn_rcpf(b[j]);
                                     da[j] = inv;
                                     db[j] = -a[j] * inv * inv;
                                 } else {
